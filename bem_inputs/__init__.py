@@ -1,0 +1,15 @@
+"""Seeded, synthetic inputs shared by the HIP path's tests/bench and by the oracle.
+
+This package holds no arithmetic of the boundary element method itself: it only
+builds triangle meshes (vertex coordinates and connectivity) and draws seeded
+random vectors, plane-wave directions and request streams.  Both the GPU path
+and the CPU oracle consume what it produces; neither shares any other code.
+"""
+from .meshes import (icosphere, geodesic_sphere, ellipsoid, two_spheres,
+                     mesh_counts, Mesh)
+from .vectors import (complex_normal, wave_directions, request_stream,
+                      sample_rows)
+
+__all__ = ["icosphere", "geodesic_sphere", "ellipsoid", "two_spheres",
+           "mesh_counts", "Mesh", "complex_normal", "wave_directions",
+           "request_stream", "sample_rows"]

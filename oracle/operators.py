@@ -1,0 +1,156 @@
+"""Dense Galerkin P1 operators and the permuted PMCHWT matrix (oracle only).
+
+Permuted PMCHWT, single scatterer, unknowns [psi; phi] with
+psi = exterior Neumann trace, phi = Dirichlet trace of the total field
+(Sec. 2.2, unique pair of traces; Sec. 2.6, permuted formulation):
+
+    B = [[ V_0 + rho V_1 ,  -(K_0 + K_1)        ],
+         [ K'_0 + K'_1   ,   D_0 + D_1 / rho    ]],   rho = rho_int / rho_ext,
+
+right-hand side [gamma_D u_inc; gamma_N u_inc].  Exterior operators (index 0)
+couple all triangles; interior ones (index 1) act within each object only
+(Sec. 2.6, multiple scattering).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import quadrature as Q
+from .build import LIB, build
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build(force=True)
+        _lib = ctypes.CDLL(LIB)
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Rules:
+    def __init__(self, n_ss: int = 4):
+        bary, w = Q.dunavant6()
+        self.reg = np.ascontiguousarray(np.hstack([bary, w[:, None]]))
+        self.tabs = [np.ascontiguousarray(t) for t in Q.singular_rules(n_ss)]
+
+
+_RULES = {}
+
+
+def rules(n_ss: int = 4) -> Rules:
+    if n_ss not in _RULES:
+        _RULES[n_ss] = Rules(n_ss)
+    return _RULES[n_ss]
+
+
+def _mesh_args(mesh):
+    P = np.ascontiguousarray(mesh.vertices, dtype=np.float64)
+    T = np.ascontiguousarray(mesh.triangles, dtype=np.int32)
+    obj = None if mesh.object_id is None else \
+        np.ascontiguousarray(mesh.object_id, dtype=np.int32)
+    return P, T, obj
+
+
+def assemble(mesh, k, interior=False, n_ss=4):
+    """Dense V, K, K', D at wavenumber k: dict of complex [N, N]."""
+    lib = _load()
+    R = rules(n_ss)
+    P, T, obj = _mesh_args(mesh)
+    nv, nt = P.shape[0], T.shape[0]
+    outs = [np.zeros((nv, nv), np.complex128) for _ in range(4)]
+    k = complex(k)
+    lib.oracle_assemble_dense(
+        _ptr(P), ctypes.c_int(nv), _ptr(T), ctypes.c_int(nt),
+        _ptr(obj) if obj is not None else None, ctypes.c_int(int(interior)),
+        ctypes.c_double(k.real), ctypes.c_double(k.imag), _ptr(R.reg),
+        _ptr(R.tabs[0]), ctypes.c_int(len(R.tabs[0])),
+        _ptr(R.tabs[1]), ctypes.c_int(len(R.tabs[1])),
+        _ptr(R.tabs[2]), ctypes.c_int(len(R.tabs[2])),
+        *[_ptr(o) for o in outs])
+    return dict(V=outs[0], K=outs[1], Kp=outs[2], D=outs[3])
+
+
+def pmchwt_blocks(ops0, ops1, rho):
+    """Combine exterior (ops0) and interior (ops1) operators into B."""
+    B11 = ops0["V"] + rho * ops1["V"]
+    B12 = -(ops0["K"] + ops1["K"])
+    B21 = ops0["Kp"] + ops1["Kp"]
+    B22 = ops0["D"] + ops1["D"] / rho
+    return np.block([[B11, B12], [B21, B22]])
+
+
+def pmchwt_matrix(mesh, k_ext, k_int, rho, n_ss=4):
+    """Weak-form permuted PMCHWT matrix, complex [2N, 2N]."""
+    ops0 = assemble(mesh, k_ext, interior=False, n_ss=n_ss)
+    ops1 = assemble(mesh, k_int, interior=True, n_ss=n_ss)
+    return pmchwt_blocks(ops0, ops1, rho)
+
+
+def _matvec_tris(mesh, k, interior, test, xs, n_ss=4):
+    lib = _load()
+    R = rules(n_ss)
+    P, T, obj = _mesh_args(mesh)
+    test = np.ascontiguousarray(test, dtype=np.int32)
+    xs = [np.ascontiguousarray(x, dtype=np.complex128) for x in xs]
+    out = np.zeros((len(test), 4, 3), np.complex128)
+    k = complex(k)
+    lib.oracle_matvec_tris(
+        _ptr(P), ctypes.c_int(P.shape[0]), _ptr(T), ctypes.c_int(T.shape[0]),
+        _ptr(obj) if obj is not None else None, ctypes.c_int(int(interior)),
+        ctypes.c_double(k.real), ctypes.c_double(k.imag), _ptr(R.reg),
+        _ptr(R.tabs[0]), ctypes.c_int(len(R.tabs[0])),
+        _ptr(R.tabs[1]), ctypes.c_int(len(R.tabs[1])),
+        _ptr(R.tabs[2]), ctypes.c_int(len(R.tabs[2])),
+        _ptr(test), ctypes.c_int(len(test)), *[_ptr(x) for x in xs],
+        _ptr(out))
+    return out
+
+
+def pmchwt_matvec_rows(mesh, k_ext, k_int, rho, x, rows, n_ss=4):
+    """Rows `rows` (vertex indices) of both block rows of y = B x, matrix-free.
+
+    x = [psi; phi] complex [2N].  Returns (y1[rows], y2[rows]).
+    """
+    N = mesh.n_vertices
+    psi, phi = x[:N], x[N:]
+    rows = np.asarray(rows)
+    T = mesh.triangles
+    mask = np.isin(T, rows).any(axis=1)
+    test = np.nonzero(mask)[0]
+    o0 = _matvec_tris(mesh, k_ext, False, test, (psi, phi, psi, phi), n_ss)
+    o1 = _matvec_tris(mesh, k_int, True, test, (psi, phi, psi, phi), n_ss)
+    r1 = (o0[:, 0] + rho * o1[:, 0]) - (o0[:, 1] + o1[:, 1])
+    r2 = (o0[:, 2] + o1[:, 2]) + (o0[:, 3] + o1[:, 3] / rho)
+    y1 = np.zeros(N, np.complex128)
+    y2 = np.zeros(N, np.complex128)
+    tv = T[test]
+    for a in range(3):
+        np.add.at(y1, tv[:, a], r1[:, a])
+        np.add.at(y2, tv[:, a], r2[:, a])
+    return y1[rows], y2[rows]
+
+
+def pair_kernel_integral(vx, vy, which, px, py, k, power, n_ss=4):
+    """Singular-rule integral of exp(ikr)/r^power over one triangle pair."""
+    lib = _load()
+    tab = np.ascontiguousarray(Q.singular_rules(n_ss)[which])
+    res = np.zeros(2)
+    lib.oracle_pair_kernel(
+        _ptr(np.ascontiguousarray(vx, np.float64)),
+        _ptr(np.ascontiguousarray(vy, np.float64)), ctypes.c_int(which),
+        _ptr(tab), ctypes.c_int(len(tab)),
+        _ptr(np.ascontiguousarray(px, np.int32)),
+        _ptr(np.ascontiguousarray(py, np.int32)),
+        ctypes.c_double(complex(k).real), ctypes.c_double(complex(k).imag),
+        ctypes.c_int(power), _ptr(res))
+    return res[0] + 1j * res[1]

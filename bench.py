@@ -1,0 +1,147 @@
+#!/usr/bin/env python3
+"""Benchmark of the matrix-free permuted PMCHWT matvec and the OSRC-GMRES solve.
+
+Workload: unit sphere, icosphere level 5 (10 242 vertices, 20 480 triangles),
+k_ext = 10, k_int = 15, rho = 1.5, plane wave along +z; synthetic seeded
+input x (complex standard normal, seed 0) already resident in HBM.
+
+A step is one Galerkin matvec y = B x of the whole operator: source gather,
+FP32 pair kernel over all separated triangle pairs, fixed-order reduction to
+vertex rows and the FP64 near-field CSR SpMV.  value = T(T-1) triangle-pair
+evaluations per second of that step.  The solve comparison (FP64 GMRES vs
+FP32 pair kernel + FP64 true-residual refinement, both to 1e-6) and the FP64
+matvec are measured in the same run outside the timed steps.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PMCHWT matvec tri-pair evals/s + solve time; FP32+refine vs FP64 @1e-6 res"
+K_EXT, K_INT, RHO = 10.0, 15.0, 1.5
+
+
+def cpu_baseline(mesh, n_test=384):
+    """Oracle (FP64, plain C + OpenMP) matrix-free rows on a seeded sample of
+    test triangles against all trial triangles; tri-pair evaluations/s."""
+    from bem_inputs import complex_normal, sample_rows
+    from oracle import operators as O
+    N, T = mesh.n_vertices, mesh.n_triangles
+    x = complex_normal(2 * N, seed=0)
+    test = sample_rows(T, n_test, seed=3)
+    lib = O._load()
+    t0 = time.perf_counter()
+    O._matvec_tris(mesh, K_EXT, False, test, (x[:N], x[N:], x[:N], x[N:]))
+    O._matvec_tris(mesh, K_INT, True, test, (x[:N], x[N:], x[:N], x[N:]))
+    dt = time.perf_counter() - t0
+    return {"value": n_test * T / dt, "unit": "tri-pair evals/s",
+            "cores": int(lib.oracle_num_threads()), "kind": "oracle",
+            "sample": f"{n_test} seeded test triangles x all {T} trial triangles, "
+                      f"both wavenumbers, 4 operators, FP64 ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+              "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2104_04609_amd as P
+    from paper_2104_04609_amd import roofline as RL
+    from bem_inputs import complex_normal, icosphere
+
+    mesh = icosphere(5)
+    N, T = mesh.n_vertices, mesh.n_triangles
+    M = P.Mesh.from_inputs(mesh)
+    x = torch.from_numpy(complex_normal(2 * N, seed=0)).cuda()
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+
+    # first call builds the FP64 near-field operator (setup, not timed)
+    t0 = time.perf_counter()
+    P.pmchwt_matvec(M, K_EXT, K_INT, RHO, x, y, precision="fp32")
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+
+    def timed(precision, steps, warmup):
+        for _ in range(warmup):
+            P.pmchwt_matvec(M, K_EXT, K_INT, RHO, x, y, precision=precision)
+        P.profile_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            P.pmchwt_matvec(M, K_EXT, K_INT, RHO, x, y, precision=precision)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ms_k, n_k = P.profile_read(f"farfield_{precision}")
+        P.profile_enable(False)
+        return dt / steps, ms_k / max(n_k, 1)
+
+    step_s, kern_ms = timed("fp32", args.steps, args.warmup)
+    step64_s, kern64_ms = timed("fp64", max(3, args.steps // 4), 1)
+
+    pairs = RL.far_pairs_per_matvec(mesh.triangles)
+    roof = RL.pair_kernel_roofline(pairs, kern_ms * 1e-3, "fp32")
+    roof64 = RL.pair_kernel_roofline(pairs, kern64_ms * 1e-3, "fp64")
+    value = T * (T - 1) / step_s
+
+    solve = None
+    if not args.no_solve:
+        try:
+            solve = {}
+            for prec in ("fp64", "fp32"):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sol, info, rc = P.pmchwt_solve(M, K_EXT, K_INT, RHO, [[0, 0, 1]], 1e-6,
+                                               precision=prec)
+                torch.cuda.synchronize()
+                solve[prec] = {"seconds": time.perf_counter() - t0, "rc": rc, **info[0]}
+            solve["speedup_fp32_refine_vs_fp64"] = (solve["fp64"]["seconds"] /
+                                                    solve["fp32"]["seconds"])
+        except P.BemError as e:
+            solve = {"error": str(e)}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "tri-pair evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_s * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "icosphere L5 unit sphere (10242 vertices, 20480 "
+                               "triangles), k_ext=10, k_int=15, rho=1.5; FP32 pair "
+                               "kernel + FP64 near field",
+                   "n_vertices": N, "n_triangles": T, "k_ext": K_EXT, "k_int": K_INT,
+                   "rho": RHO, "parallelism": "single GPU"},
+        "roofline": {**roof, "kernel": "farfield_fp32",
+                     "kernel_ms": kern_ms, "point_pairs_per_launch": pairs,
+                     "flop_eq_per_pair": RL.FLOP_EQ_PER_PAIR},
+        "fp64_matvec": {"ms_per_step": step64_s * 1e3,
+                        "tri_pair_evals_per_s": T * (T - 1) / step64_s,
+                        "kernel_ms": kern64_ms, "roofline_frac": roof64["frac"]},
+        "setup_s": setup_s,
+        "solve": solve,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(mesh)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,186 @@
+/*
+ * bem.h -- C ABI of the MI355X (gfx950) OSRC-preconditioned PMCHWT library.
+ *
+ * Method: van 't Wout, Haqshenas, Gelat, Betcke, Saffari, "Frequency-robust
+ * preconditioning of boundary integral equations for acoustic transmission",
+ * J. Comput. Phys. 2022.  Section numbers below refer to that paper.
+ *
+ * Conventions shared by every call:
+ *   - Return value: 0 = BEM_OK, > 0 warning, < 0 error; after an error the
+ *     calling thread's message is available from bem_last_error().
+ *   - bem_c64 has the layout of C99 double _Complex (torch.complex128).
+ *   - Vectors x, y, solution are CALLER-OWNED DEVICE pointers on the current
+ *     HIP device, row-major [n_rhs][2N] with each row = [psi (N); phi (N)]:
+ *     psi = exterior Neumann trace, phi = Dirichlet trace of the total field
+ *     (Sec. 2.2, unique pair of traces), P1 coefficients per vertex.  They must
+ *     not alias; outputs are overwritten.
+ *   - Work is enqueued on hip_stream (NULL = the null stream) and is
+ *     stream-ordered; calls that return host data synchronise that stream.
+ *   - A mesh handle owns all device state derived from the mesh (geometry,
+ *     near-field operators, OSRC factors).  Reading it from several streams is
+ *     safe; creation and destruction are not thread-safe.
+ */
+#ifndef BEM_H
+#define BEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } bem_c64;
+typedef struct bem_mesh bem_mesh;
+
+enum {
+    BEM_OK = 0,
+    BEM_W_NOT_CONVERGED = 1,   /* best iterate written */
+    BEM_E_INVAL = -1,          /* bad argument */
+    BEM_E_BAD_MESH = -2,       /* not a closed, oriented, manifold surface */
+    BEM_E_NOMEM = -3,          /* device allocation / budget exceeded */
+    BEM_E_DEVICE = -4,         /* HIP runtime error */
+    BEM_E_NAN = -5,            /* NaN/Inf in an iterate or residual */
+    BEM_E_UNSUPPORTED = -6
+};
+
+/* Far-field (matrix-free pair kernel) precision.  The singular/near-field
+ * corrections, OSRC and GMRES always run in FP64. */
+enum { BEM_FP64 = 0, BEM_FP32 = 1 };
+
+/*
+ * Create the device state of a triangle surface mesh (Sec. 2.1: bounded
+ * objects Omega_m with boundaries Gamma_m, outward unit normals; Sec. 2.3:
+ * P1 elements on a triangular mesh).
+ *   vertices   host, float64 [n_vertices][3]
+ *   triangles  host, int32 [n_triangles][3], 0-based, counter-clockwise seen
+ *              from outside ((v1-v0)x(v2-v0) points outward)
+ *   object_id  host, int32 [n_triangles] in 0..n_objects-1, or NULL for one
+ *              object; the vertices of each object must be contiguous
+ * The inputs are copied; the caller keeps ownership.  Errors: BEM_E_INVAL
+ * (sizes, indices out of range), BEM_E_BAD_MESH (degenerate triangle, edge
+ * not shared by exactly two triangles with opposite orientation, object
+ * with non-positive signed volume, vertex shared by two objects),
+ * BEM_E_NOMEM, BEM_E_DEVICE.
+ */
+int bem_mesh_create(const double *vertices, int64_t n_vertices,
+                    const int32_t *triangles, int64_t n_triangles,
+                    const int32_t *object_id, bem_mesh **out);
+void bem_mesh_destroy(bem_mesh *mesh);
+
+/* Sizes of a mesh (any pointer may be NULL). */
+int bem_mesh_info(const bem_mesh *mesh, int64_t *n_vertices,
+                  int64_t *n_triangles, int32_t *n_objects,
+                  int64_t *device_bytes);
+
+/*
+ * y = B x: the Galerkin (weak-form) permuted PMCHWT operator (Sec. 2.6,
+ * single scatterer; multiple scatterers: exterior operators couple all
+ * objects, interior ones act within each object)
+ *     B = [[ V_0 + rho V_1 , -(K_0 + K_1)      ],
+ *          [ K'_0 + K'_1   ,  D_0 + D_1 / rho  ]],
+ * V, K, K' (the paper's T) and the Maue-form hypersingular D of Sec. 2.2 at
+ * k_ext (index 0) and k_int (index 1), P1 test and trial functions (Sec. 2.3),
+ * rho = rho_int / rho_ext.  Quadrature: 6-point rule per triangle for every
+ * pair not sharing a vertex; Sauter-Schwab-type rules (4 Gauss points per
+ * dimension) for coinciding, edge- and vertex-adjacent pairs.
+ *   x, y       device, bem_c64 [n_rhs][2N]
+ *   precision  BEM_FP64 or BEM_FP32 (pair kernel of separated triangles)
+ * The first call for a (k_ext, k_int, rho) builds and caches the near-field
+ * operator on the device.  Errors: BEM_E_INVAL (rho <= 0, Im k < 0, k == 0,
+ * n_rhs < 1, NULL pointers), BEM_E_NOMEM, BEM_E_DEVICE.
+ */
+int pmchwt_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int,
+                  double rho, const bem_c64 *x, bem_c64 *y, int n_rhs,
+                  int precision, void *hip_stream);
+
+/*
+ * y = diag(L_DtN, L_NtD) x in strong form (coefficients to coefficients),
+ * the OSRC operators of Sec. 2.5 with damped wavenumber k_eps, square root
+ * localised by an N_p-term Pade series with branch-cut rotation theta
+ * (Sec. 2.6):  L_DtN = ik R(X),  L_NtD = (1/ik) R(X)(I + X)^{-1},
+ * X = -M^{-1} S / k_eps^2 (P1 mass M, Laplace-Beltrami stiffness S),
+ * R(z) = C_0 + sum_j A_j z / (1 + B_j z).  k and k_eps apply to every object.
+ * The shifted sparse systems are factorised once per (k_eps, N_p, theta) and
+ * cached on the device.
+ *   x, y  device, bem_c64 [n_rhs][2N]
+ * Errors: BEM_E_INVAL (pade_terms < 1 or > 32, k == 0, k_eps == 0).
+ */
+int osrc_apply(const bem_mesh *mesh, int pade_terms, double theta,
+               bem_c64 k, bem_c64 k_eps, const bem_c64 *x, bem_c64 *y,
+               int n_rhs, void *hip_stream);
+
+/*
+ * Weak right-hand side [f_D; f_N] of the PMCHWT system for unit-amplitude
+ * plane waves u_inc = exp(i k_ext d.x) (Sec. 2.1, Sec. 2.6):
+ * f_D,i = int u_inc phi_i, f_N,i = int i k_ext (d.n) u_inc phi_i, 6-point rule.
+ *   directions  host, float64 [n_waves][3] (unit vectors)
+ *   f           device, bem_c64 [n_waves][2N]
+ */
+int pmchwt_rhs(const bem_mesh *mesh, bem_c64 k_ext, const double *directions,
+               int n_waves, bem_c64 *f, void *hip_stream);
+
+typedef struct {
+    int pade_terms;      /* N_p, default 4 (Sec. 3.1) */
+    double theta;        /* branch-cut rotation, default pi/3 */
+    int osrc_interior;   /* 1: OSRC wavenumber k_int (default), 0: k_ext */
+    double R;            /* k_eps radius; <= 0: 0.1 x object circumradius */
+    int precision;       /* BEM_FP64 (plain GMRES) or BEM_FP32 (refinement) */
+    int maxiter;         /* GMRES iterations cap (total), default 1000 */
+    double inner_tol;    /* FP32 inner GMRES tolerance, default 1e-5 */
+    int max_outer;       /* refinement steps cap, default 8 */
+} bem_solve_opts;
+
+typedef struct {
+    int iterations;      /* GMRES iterations (all inner solves) */
+    int outer_steps;     /* refinement steps (1 for FP64) */
+    int fp64_matvecs;
+    int fp32_matvecs;
+    double rel_residual; /* ||b - P x|| / ||b||, P with the FP64 operator */
+    double seconds;      /* wall time of this wave's solve */
+} bem_solve_info;
+
+/* Fill *opts with the defaults above. */
+void bem_solve_opts_default(bem_solve_opts *opts);
+
+/*
+ * Solve the OSRC-preconditioned permuted PMCHWT system (Sec. 2.6, strong
+ * form Sec. 2.4) for each plane wave:
+ *     L M^{-1} B x = L M^{-1} f,   L = diag(L_DtN, L_NtD) per object,
+ * with unrestarted GMRES from x_0 = 0 (Sec. 3.1) to ||b - P x|| <= tol ||b||.
+ * precision BEM_FP32: iterative refinement, outer residual with the FP64
+ * operator, inner GMRES on the operator with the FP32 pair kernel.
+ *   directions  host [n_waves][3];  solution  device [n_waves][2N]
+ *   info        host [n_waves] or NULL
+ * Returns BEM_W_NOT_CONVERGED (best iterate written) if maxiter is reached.
+ */
+int pmchwt_solve(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int,
+                 double rho, const double *directions, int n_waves, double tol,
+                 const bem_solve_opts *opts, bem_c64 *solution,
+                 bem_solve_info *info, void *hip_stream);
+
+/*
+ * Far-field pattern F(xhat) of a solution: u_sca ~ F exp(i k r)/r with
+ * F = 1/(4 pi) int exp(-i k xhat.y) [-psi - i k (xhat.n) phi] dy, from the
+ * exterior representation formula (Sec. 2.2).
+ *   solution device [2N];  dirs host [n_dirs][3];  out host [n_dirs]
+ */
+int bem_far_field(const bem_mesh *mesh, bem_c64 k_ext, const bem_c64 *solution,
+                  const double *dirs, int n_dirs, bem_c64 *out,
+                  void *hip_stream);
+
+/* Kernel timing with HIP events recorded on the launch stream, for the named
+ * kernel ("farfield_fp32", "farfield_fp64", "nearfield_spmv", ...).
+ * enable = 1 starts recording (and resets), 0 stops.  bem_profile_read
+ * synchronises the recorded events and returns total milliseconds and the
+ * launch count since the last reset. */
+int bem_profile_enable(int enable);
+int bem_profile_read(const char *kernel, double *total_ms, int64_t *launches);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *bem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BEM_H */

@@ -309,3 +309,15 @@ void oracle_pair_kernel(const double *vx, const double *vy, int which,
     res[0] = creal(acc);
     res[1] = cimag(acc);
 }
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+/* Number of OpenMP threads the oracle's pair loops use. */
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

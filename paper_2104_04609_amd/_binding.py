@@ -1,0 +1,250 @@
+"""ctypes binding of libbem.so (argument marshalling only).
+
+Every computation runs in the library's HIP kernels; torch tensors provide
+device memory (``data_ptr()``) and the HIP stream (``cuda_stream``).  The
+library must be built (``python -m paper_2104_04609_amd.build``); importing
+this module fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbem.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with "
+                      "`python -m paper_2104_04609_amd.build` (hipcc, gfx950)")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+BEM_FP64, BEM_FP32 = 0, 1
+_PREC = {"fp64": BEM_FP64, "fp32": BEM_FP32, BEM_FP64: BEM_FP64, BEM_FP32: BEM_FP32}
+ERRORS = {1: "BEM_W_NOT_CONVERGED", -1: "BEM_E_INVAL", -2: "BEM_E_BAD_MESH",
+          -3: "BEM_E_NOMEM", -4: "BEM_E_DEVICE", -5: "BEM_E_NAN",
+          -6: "BEM_E_UNSUPPORTED"}
+
+
+class c64(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+def _c(z) -> c64:
+    z = complex(z)
+    return c64(z.real, z.imag)
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("pade_terms", ctypes.c_int), ("theta", ctypes.c_double),
+                ("osrc_interior", ctypes.c_int), ("R", ctypes.c_double),
+                ("precision", ctypes.c_int), ("maxiter", ctypes.c_int),
+                ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("outer_steps", ctypes.c_int),
+                ("fp64_matvecs", ctypes.c_int), ("fp32_matvecs", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+lib.bem_mesh_create.argtypes = [_vp, _i64, _vp, _i64, _vp, ctypes.POINTER(_vp)]
+lib.bem_mesh_destroy.argtypes = [_vp]
+lib.bem_mesh_destroy.restype = None
+lib.bem_mesh_info.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_i64)]
+lib.pmchwt_matvec.argtypes = [_vp, c64, c64, ctypes.c_double, _vp, _vp,
+                              ctypes.c_int, ctypes.c_int, _vp]
+lib.osrc_apply.argtypes = [_vp, ctypes.c_int, ctypes.c_double, c64, c64, _vp, _vp,
+                           ctypes.c_int, _vp]
+lib.pmchwt_rhs.argtypes = [_vp, c64, _vp, ctypes.c_int, _vp, _vp]
+lib.bem_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
+lib.bem_solve_opts_default.restype = None
+lib.pmchwt_solve.argtypes = [_vp, c64, c64, ctypes.c_double, _vp, ctypes.c_int,
+                             ctypes.c_double, ctypes.POINTER(SolveOpts), _vp, _vp, _vp]
+lib.bem_far_field.argtypes = [_vp, c64, _vp, _vp, ctypes.c_int, _vp, _vp]
+lib.bem_profile_enable.argtypes = [ctypes.c_int]
+lib.bem_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(_i64)]
+lib.bem_last_error.restype = ctypes.c_char_p
+lib.bem_last_error.argtypes = []
+
+
+class BemError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise BemError(rc, lib.bem_last_error().decode())
+    return rc
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(_vp)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return _vp(stream.cuda_stream)
+
+
+def _dev_c128(t, n2: int, name: str):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != torch.complex128 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous complex128")
+    if t.numel() % n2 != 0:
+        raise ValueError(f"{name} has {t.numel()} entries, not a multiple of 2N={n2}")
+    return t.numel() // n2
+
+
+class Mesh:
+    """Device-resident mesh handle (bem_mesh_create / bem_mesh_destroy)."""
+
+    def __init__(self, vertices, triangles, object_id=None):
+        P = np.ascontiguousarray(vertices, dtype=np.float64)
+        T = np.ascontiguousarray(triangles, dtype=np.int32)
+        O = None if object_id is None else np.ascontiguousarray(object_id, np.int32)
+        if P.ndim != 2 or P.shape[1] != 3 or T.ndim != 2 or T.shape[1] != 3:
+            raise ValueError("vertices [N,3] and triangles [T,3] expected")
+        if O is not None and O.shape != (T.shape[0],):
+            raise ValueError("object_id must have one entry per triangle")
+        h = _vp()
+        self._h = None
+        _check(lib.bem_mesh_create(_np_ptr(P), P.shape[0], _np_ptr(T), T.shape[0],
+                                   _np_ptr(O) if O is not None else None,
+                                   ctypes.byref(h)))
+        self._h = h
+        self.n_vertices = P.shape[0]
+        self.n_triangles = T.shape[0]
+
+    @classmethod
+    def from_inputs(cls, m):
+        return cls(m.vertices, m.triangles, m.object_id)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        nv, nt, by = _i64(), _i64(), _i64()
+        no = ctypes.c_int32()
+        _check(lib.bem_mesh_info(self._h, ctypes.byref(nv), ctypes.byref(nt),
+                                 ctypes.byref(no), ctypes.byref(by)))
+        return dict(n_vertices=nv.value, n_triangles=nt.value, n_objects=no.value,
+                    device_bytes=by.value)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib.bem_mesh_destroy(self._h)
+            self._h = None
+
+
+def pmchwt_matvec(mesh: Mesh, k_ext, k_int, rho: float, x, y=None,
+                  precision="fp64", stream=None):
+    """y = B x (weak-form permuted PMCHWT); x, y complex128 [n_rhs, 2N] on device."""
+    import torch
+    n2 = 2 * mesh.n_vertices
+    n_rhs = _dev_c128(x, n2, "x")
+    if y is None:
+        y = torch.empty_like(x)
+    _dev_c128(y, n2, "y")
+    _check(lib.pmchwt_matvec(mesh.handle, _c(k_ext), _c(k_int), float(rho),
+                             _vp(x.data_ptr()), _vp(y.data_ptr()), n_rhs,
+                             _PREC[precision], _stream(stream)))
+    return y
+
+
+def osrc_apply(mesh: Mesh, pade_terms: int, theta: float, k, k_eps, x, y=None,
+               stream=None):
+    """y = diag(L_DtN, L_NtD) x (strong form); complex128 [n_rhs, 2N] on device."""
+    import torch
+    n2 = 2 * mesh.n_vertices
+    n_rhs = _dev_c128(x, n2, "x")
+    if y is None:
+        y = torch.empty_like(x)
+    _dev_c128(y, n2, "y")
+    _check(lib.osrc_apply(mesh.handle, int(pade_terms), float(theta), _c(k), _c(k_eps),
+                          _vp(x.data_ptr()), _vp(y.data_ptr()), n_rhs, _stream(stream)))
+    return y
+
+
+def pmchwt_rhs(mesh: Mesh, k_ext, directions, stream=None):
+    """Weak right-hand sides [f_D; f_N] for plane waves: complex128 [n_waves, 2N]."""
+    import torch
+    d = np.ascontiguousarray(np.atleast_2d(directions), dtype=np.float64)
+    f = torch.empty((d.shape[0], 2 * mesh.n_vertices), dtype=torch.complex128,
+                    device="cuda")
+    _check(lib.pmchwt_rhs(mesh.handle, _c(k_ext), _np_ptr(d), d.shape[0],
+                          _vp(f.data_ptr()), _stream(stream)))
+    return f
+
+
+def default_opts() -> SolveOpts:
+    o = SolveOpts()
+    lib.bem_solve_opts_default(ctypes.byref(o))
+    return o
+
+
+def pmchwt_solve(mesh: Mesh, k_ext, k_int, rho: float, directions, tol: float,
+                 opts: Optional[SolveOpts] = None, stream=None, **overrides):
+    """OSRC-preconditioned PMCHWT solve; returns (solution [n_waves, 2N], infos, rc)."""
+    import torch
+    d = np.ascontiguousarray(np.atleast_2d(directions), dtype=np.float64)
+    o = default_opts() if opts is None else opts
+    for k, v in overrides.items():
+        if k == "precision":
+            v = _PREC[v]
+        setattr(o, k, v)
+    sol = torch.empty((d.shape[0], 2 * mesh.n_vertices), dtype=torch.complex128,
+                      device="cuda")
+    infos = (SolveInfo * d.shape[0])()
+    rc = _check(lib.pmchwt_solve(mesh.handle, _c(k_ext), _c(k_int), float(rho),
+                                 _np_ptr(d), d.shape[0], float(tol), ctypes.byref(o),
+                                 _vp(sol.data_ptr()), ctypes.cast(infos, _vp),
+                                 _stream(stream)))
+    return sol, [i.as_dict() for i in infos], rc
+
+
+def far_field(mesh: Mesh, k_ext, solution, dirs, stream=None) -> np.ndarray:
+    d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
+    _dev_c128(solution, 2 * mesh.n_vertices, "solution")
+    out = np.zeros(d.shape[0], np.complex128)
+    _check(lib.bem_far_field(mesh.handle, _c(k_ext), _vp(solution.data_ptr()),
+                             _np_ptr(d), d.shape[0], _np_ptr(out), _stream(stream)))
+    return out
+
+
+def profile_enable(on: bool = True):
+    _check(lib.bem_profile_enable(1 if on else 0))
+
+
+def profile_read(kernel: str):
+    ms, n = ctypes.c_double(), _i64()
+    _check(lib.bem_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def exported_symbols(names: Sequence[str]):
+    """Names among `names` that the loaded library does not export."""
+    missing = []
+    for n in names:
+        try:
+            getattr(lib, n)
+        except AttributeError:
+            missing.append(n)
+    return missing

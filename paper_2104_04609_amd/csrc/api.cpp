@@ -1,0 +1,236 @@
+// C ABI entry points: argument validation, error reporting, kernel timing.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "bem_internal.h"
+
+namespace bem {
+
+namespace {
+thread_local std::string g_last_error;
+
+struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+
+void prof_clear_locked() {
+    for (auto &r : g_prof) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_prof.clear();
+}
+}   // namespace
+
+[[noreturn]] void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+
+Timer::Timer(const char *kernel, hipStream_t stream) : name(kernel), s(stream) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (!g_prof_on) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        a = b = nullptr;
+        return;
+    }
+    (void)hipEventRecord(a, s);
+}
+
+Timer::~Timer() {
+    if (!a) return;
+    (void)hipEventRecord(b, s);
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof.push_back({name, a, b});
+}
+
+}   // namespace bem
+
+bem_mesh::~bem_mesh() = default;
+
+int64_t bem_mesh::device_bytes() const {
+    int64_t b = geo64.bytes() + geo32.bytes() + tst.bytes() + tobj_d.bytes() + tri_d.bytes() +
+                star_ptr.bytes() + star_idx.bytes() + near_pairs.bytes() + nf_rowptr.bytes() +
+                nf_col.bytes() + nf_cptr.bytes() + nf_contrib.bytes() + ss_tab.bytes() +
+                dyn64.bytes() + dyn32.bytes() + partial.bytes() + trirows.bytes();
+    for (const auto &kv : near_cache) b += kv.second->vals.bytes();
+    for (const auto &kv : osrc_cache) b += bem::osrc_bytes(*kv.second);
+    return b;
+}
+
+using bem::fail;
+
+#define BEM_API_BEGIN try {
+#define BEM_API_END                                                              \
+    }                                                                            \
+    catch (const bem::Error &e) {                                                \
+        bem::g_last_error = e.msg;                                               \
+        return e.code;                                                           \
+    }                                                                            \
+    catch (const std::bad_alloc &) {                                             \
+        bem::g_last_error = "host allocation failed";                           \
+        return BEM_E_NOMEM;                                                      \
+    }                                                                            \
+    catch (const std::exception &e) {                                            \
+        bem::g_last_error = e.what();                                            \
+        return BEM_E_DEVICE;                                                     \
+    }
+
+namespace {
+
+void check_k(bem_c64 k, const char *name) {
+    if (!std::isfinite(k.re) || !std::isfinite(k.im))
+        fail(BEM_E_INVAL, std::string(name) + " is not finite");
+    if (k.im < 0) fail(BEM_E_INVAL, std::string(name) + " must have Im k >= 0");
+    if (k.re == 0 && k.im == 0) fail(BEM_E_INVAL, std::string(name) + " must be nonzero");
+}
+
+void check_mesh(const bem_mesh *m) {
+    if (!m) fail(BEM_E_INVAL, "mesh is NULL");
+}
+
+}   // namespace
+
+extern "C" {
+
+const char *bem_last_error(void) { return bem::g_last_error.c_str(); }
+
+int bem_mesh_create(const double *vertices, int64_t n_vertices, const int32_t *triangles,
+                    int64_t n_triangles, const int32_t *object_id, bem_mesh **out) {
+    BEM_API_BEGIN
+    bem::g_last_error.clear();
+    if (!out) fail(BEM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    auto m = std::make_unique<bem_mesh>();
+    bem::mesh_build(m.get(), vertices, n_vertices, triangles, n_triangles, object_id);
+    *out = m.release();
+    return BEM_OK;
+    BEM_API_END
+}
+
+void bem_mesh_destroy(bem_mesh *mesh) { delete mesh; }
+
+int bem_mesh_info(const bem_mesh *m, int64_t *nv, int64_t *nt, int32_t *nobj,
+                  int64_t *bytes) {
+    BEM_API_BEGIN
+    check_mesh(m);
+    if (nv) *nv = m->N;
+    if (nt) *nt = m->T;
+    if (nobj) *nobj = m->nobj;
+    if (bytes) *bytes = m->device_bytes();
+    return BEM_OK;
+    BEM_API_END
+}
+
+int pmchwt_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
+                  const bem_c64 *x, bem_c64 *y, int n_rhs, int precision,
+                  void *hip_stream) {
+    BEM_API_BEGIN
+    check_mesh(mesh);
+    check_k(k_ext, "k_ext");
+    check_k(k_int, "k_int");
+    if (!(rho > 0) || !std::isfinite(rho)) fail(BEM_E_INVAL, "rho must be positive");
+    if (!x || !y) fail(BEM_E_INVAL, "x and y must be device pointers");
+    if (x == y) fail(BEM_E_INVAL, "x and y must not alias");
+    if (n_rhs < 1) fail(BEM_E_INVAL, "n_rhs must be >= 1");
+    if (precision != BEM_FP64 && precision != BEM_FP32) fail(BEM_E_INVAL, "bad precision");
+    bem_mesh *m = const_cast<bem_mesh *>(mesh);
+    hipStream_t s = (hipStream_t)hip_stream;
+    double2 k0 = make_double2(k_ext.re, k_ext.im), k1 = make_double2(k_int.re, k_int.im);
+    const bem::NearOperator &nf = bem::nearfield_get(m, k0, k1, rho, s);
+    const int64_t n2 = 2 * m->N;
+    for (int r = 0; r < n_rhs; r++)
+        bem::farfield_apply(m, nf, k0, k1, rho, (const double2 *)x + r * n2,
+                            (double2 *)y + r * n2, precision, s);
+    return BEM_OK;
+    BEM_API_END
+}
+
+int osrc_apply(const bem_mesh *mesh, int pade_terms, double theta, bem_c64 k,
+               bem_c64 k_eps, const bem_c64 *x, bem_c64 *y, int n_rhs, void *hip_stream) {
+    BEM_API_BEGIN
+    check_mesh(mesh);
+    if (pade_terms < 1 || pade_terms > 32) fail(BEM_E_INVAL, "pade_terms must be in 1..32");
+    if (!std::isfinite(theta)) fail(BEM_E_INVAL, "theta not finite");
+    if (!std::isfinite(k.re) || !std::isfinite(k.im) || (k.re == 0 && k.im == 0))
+        fail(BEM_E_INVAL, "k must be finite and nonzero");
+    if (!std::isfinite(k_eps.re) || !std::isfinite(k_eps.im) ||
+        (k_eps.re == 0 && k_eps.im == 0))
+        fail(BEM_E_INVAL, "k_eps must be finite and nonzero");
+    if (!x || !y || x == y) fail(BEM_E_INVAL, "x, y must be distinct device pointers");
+    if (n_rhs < 1) fail(BEM_E_INVAL, "n_rhs must be >= 1");
+    bem_mesh *m = const_cast<bem_mesh *>(mesh);
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::vector<double2> keps(m->nobj, make_double2(k_eps.re, k_eps.im));
+    bem::OsrcState &st =
+        bem::osrc_get(m, pade_terms, theta, make_double2(k.re, k.im), keps, s);
+    const int64_t n2 = 2 * m->N;
+    for (int r = 0; r < n_rhs; r++)
+        bem::osrc_apply_strong(m, st, (const double2 *)x + r * n2, (double2 *)y + r * n2, s);
+    return BEM_OK;
+    BEM_API_END
+}
+
+int pmchwt_rhs(const bem_mesh *mesh, bem_c64 k_ext, const double *directions, int n_waves,
+               bem_c64 *f, void *hip_stream) {
+    BEM_API_BEGIN
+    check_mesh(mesh);
+    check_k(k_ext, "k_ext");
+    if (!directions || !f || n_waves < 1) fail(BEM_E_INVAL, "bad directions/f/n_waves");
+    for (int w = 0; w < n_waves; w++) {
+        const double *d = directions + 3 * w;
+        double nrm = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        if (!(std::fabs(nrm - 1.0) < 1e-6)) fail(BEM_E_INVAL, "directions must be unit vectors");
+    }
+    bem::rhs_project(const_cast<bem_mesh *>(mesh), make_double2(k_ext.re, k_ext.im),
+                     directions, n_waves, (double2 *)f, (hipStream_t)hip_stream);
+    return BEM_OK;
+    BEM_API_END
+}
+
+int bem_far_field(const bem_mesh *mesh, bem_c64 k_ext, const bem_c64 *solution,
+                  const double *dirs, int n_dirs, bem_c64 *out, void *hip_stream) {
+    BEM_API_BEGIN
+    check_mesh(mesh);
+    check_k(k_ext, "k_ext");
+    if (!solution || !dirs || !out || n_dirs < 1) fail(BEM_E_INVAL, "bad arguments");
+    bem::far_field_eval(const_cast<bem_mesh *>(mesh), make_double2(k_ext.re, k_ext.im),
+                        (const double2 *)solution, dirs, n_dirs, (double2 *)out,
+                        (hipStream_t)hip_stream);
+    return BEM_OK;
+    BEM_API_END
+}
+
+int bem_profile_enable(int enable) {
+    BEM_API_BEGIN
+    std::lock_guard<std::mutex> g(bem::g_prof_mu);
+    if (enable) bem::prof_clear_locked();
+    bem::g_prof_on = enable != 0;
+    return BEM_OK;
+    BEM_API_END
+}
+
+int bem_profile_read(const char *kernel, double *total_ms, int64_t *launches) {
+    BEM_API_BEGIN
+    if (!kernel) fail(BEM_E_INVAL, "kernel name is NULL");
+    std::lock_guard<std::mutex> g(bem::g_prof_mu);
+    double ms = 0;
+    int64_t n = 0;
+    for (auto &r : bem::g_prof) {
+        if (r.name != kernel) continue;
+        BEM_HIP(hipEventSynchronize(r.b));
+        float e = 0;
+        BEM_HIP(hipEventElapsedTime(&e, r.a, r.b));
+        ms += e;
+        n++;
+    }
+    if (total_ms) *total_ms = ms;
+    if (launches) *launches = n;
+    return BEM_OK;
+    BEM_API_END
+}
+
+}   // extern "C"

@@ -1,0 +1,215 @@
+// Internal declarations of the PMCHWT/OSRC library (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "bem.h"
+
+namespace bem {
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string &msg);
+
+#define BEM_HIP(expr)                                                         \
+    do {                                                                      \
+        hipError_t e_ = (expr);                                               \
+        if (e_ != hipSuccess)                                                 \
+            ::bem::fail(BEM_E_DEVICE, std::string(#expr) + ": " +             \
+                                          hipGetErrorString(e_));             \
+    } while (0)
+
+#define BEM_LAUNCH_CHECK() BEM_HIP(hipGetLastError())
+
+// Owning device buffer.
+template <class T> struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t count) { alloc(count); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        if (count == 0) return;
+        hipError_t e = hipMalloc((void **)&p, count * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            fail(BEM_E_NOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) +
+                                  " bytes failed: " + hipGetErrorString(e));
+        }
+        n = count;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void upload(const std::vector<T> &h) {
+        if (h.size() != n) alloc(h.size());
+        if (n) BEM_HIP(hipMemcpy(p, h.data(), n * sizeof(T), hipMemcpyHostToDevice));
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+// ---------------------------------------------------------------- quadrature
+struct Rules {
+    double reg_bary[6][3];   // 6-point rule, barycentric (phi_0, phi_1, phi_2)
+    double reg_w[6];         // weights, sum 1
+    // singular rules over K x K, K = {0 <= x2 <= x1 <= 1}: rows x1 x2 y1 y2 w
+    std::vector<double> ss[3];   // 0 coincident, 1 common edge, 2 common vertex
+};
+const Rules &rules();
+
+// ------------------------------------------------------------- device layout
+// Per-triangle static geometry record (FP64 and FP32 copies, the FP32 one in
+// coordinates centred on the bounding-box centre):
+//   [0..17]  the 6 quadrature points (x,y,z) of the 6-point rule
+//   [18..20] unit normal n
+//   [21]     plane offset c = n . v0  (n . p is the same for every p on it)
+constexpr int GEO_STRIDE = 22;
+// Per-triangle dynamic source record of one right-hand side:
+//   [0..11]  s_psi(q_j) = w_j |sigma| sum_b phi_b(q_j) psi_b, complex, j=0..5
+//   [12..23] s_phi(q_j), same with phi
+//   [24..29] sC = |sigma| sum_b curl(phi_b) phi_b  (3 complex)
+constexpr int DYN_STRIDE = 30;
+// Test-side contraction data per triangle:
+//   [0] |tau|   [1..9] curl phi_a (a-major, xyz)
+constexpr int TST_STRIDE = 10;
+// Partial far-field rows per (split, test triangle): 12 doubles
+//   row1[a] (re,im) a=0..2, row2[a] (re,im) a=0..2
+constexpr int ROW_STRIDE = 12;
+
+struct NearKey {
+    double k0r, k0i, k1r, k1i, rho;
+    bool operator<(const NearKey &o) const {
+        return std::tie(k0r, k0i, k1r, k1i, rho) <
+               std::tie(o.k0r, o.k0i, o.k1r, o.k1i, o.rho);
+    }
+};
+
+struct NearOperator {
+    DevBuf<double> vals;   // [4 blocks][nnz] complex (interleaved): B11 B12 B21 B22
+};
+
+struct OsrcKey {
+    int np;
+    double theta, kr, ki, ker, kei;
+    bool operator<(const OsrcKey &o) const {
+        return std::tie(np, theta, kr, ki, ker, kei) <
+               std::tie(o.np, o.theta, o.kr, o.ki, o.ker, o.kei);
+    }
+};
+
+struct OsrcState;   // defined in osrc.cpp
+struct OsrcDeleter {
+    void operator()(OsrcState *p) const;   // osrc.cpp
+};
+int64_t osrc_bytes(const OsrcState &st);
+
+struct Profile;
+
+}   // namespace bem
+
+struct bem_mesh {
+    int64_t N = 0, T = 0;
+    int nobj = 1;
+    std::vector<double> P;          // [N][3]
+    std::vector<int32_t> tri;       // [T][3]
+    std::vector<int32_t> tobj;      // [T]
+    std::vector<int32_t> vobj;      // [N]
+    std::vector<double> area;       // [T]
+    std::vector<double> normal;     // [T][3]
+    std::vector<double> curl;       // [T][3][3]
+    double centre[3] = {0, 0, 0};
+    std::vector<double> obj_radius; // circumradius about each object's centroid
+
+    // device geometry
+    bem::DevBuf<double> geo64;      // [T][GEO_STRIDE]
+    bem::DevBuf<float> geo32;       // [T][GEO_STRIDE]
+    bem::DevBuf<double> tst;        // [T][TST_STRIDE]
+    bem::DevBuf<int32_t> tobj_d;    // [T]
+    bem::DevBuf<int32_t> tri_d;     // [T][3]
+    bem::DevBuf<int32_t> star_ptr;  // [N+1] vertex -> (tri*3 + a), ascending
+    bem::DevBuf<int32_t> star_idx;
+
+    // near field: ordered pairs (tau, sigma) sharing >= 1 vertex
+    int64_t n_near = 0;
+    bem::DevBuf<int32_t> near_pairs;   // [n_near][4]: tau, sigma, class, perms
+    bem::DevBuf<int32_t> nf_rowptr;    // [N+1]
+    bem::DevBuf<int32_t> nf_col;       // [nnz]
+    bem::DevBuf<int32_t> nf_cptr;      // [nnz+1]
+    bem::DevBuf<int32_t> nf_contrib;   // pair*9 + a*3 + b
+    int64_t nf_nnz = 0;
+    bem::DevBuf<double> ss_tab;        // concatenated singular rules [n][5]
+    int ss_off[4] = {0, 0, 0, 0};      // row offsets of the three rules
+    std::map<bem::NearKey, std::unique_ptr<bem::NearOperator>> near_cache;
+
+    // OSRC: P1 vertex graph, M and S values, factor state per parameter set
+    std::map<bem::OsrcKey, std::unique_ptr<bem::OsrcState, bem::OsrcDeleter>> osrc_cache;
+
+    // scratch (grown on demand)
+    bem::DevBuf<double> dyn64;
+    bem::DevBuf<float> dyn32;
+    bem::DevBuf<double> partial;
+    bem::DevBuf<double> trirows;
+
+    int64_t device_bytes() const;
+    ~bem_mesh();
+};
+
+namespace bem {
+
+// farfield.hip
+void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
+                    double rho, const double2 *x, double2 *y, int precision,
+                    hipStream_t s);
+// nearfield.hip
+std::unique_ptr<NearOperator> nearfield_build(bem_mesh *m, double2 k0, double2 k1,
+                                              double rho, hipStream_t s);
+const NearOperator &nearfield_get(bem_mesh *m, double2 k0, double2 k1, double rho,
+                                  hipStream_t s);
+// mesh.cpp
+void mesh_build(bem_mesh *m, const double *P, int64_t N, const int32_t *tri,
+                int64_t T, const int32_t *obj);
+// rhs.hip
+void rhs_project(bem_mesh *m, double2 k0, const double *dirs, int n, double2 *f,
+                 hipStream_t s);
+void far_field_eval(bem_mesh *m, double2 k0, const double2 *x, const double *dirs,
+                    int n, double2 *out, hipStream_t s);
+// osrc.cpp / osrc.hip
+OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
+                    const std::vector<double2> &keps_obj, hipStream_t s);
+void osrc_apply_strong(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y,
+                       hipStream_t s);
+void osrc_apply_from_weak(bem_mesh *m, OsrcState &st, const double2 *yw,
+                          double2 *z, hipStream_t s);
+void osrc_mass_solve(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y,
+                     int nblocks, hipStream_t s);
+// profiling (api.cpp)
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    const char *name = nullptr;
+    hipStream_t s = nullptr;
+    Timer(const char *kernel, hipStream_t stream);
+    ~Timer();
+};
+
+}   // namespace bem

@@ -1,0 +1,493 @@
+// Matrix-free Galerkin matvec of the permuted PMCHWT operator (Sec. 2.6):
+//
+//   y1 = (V_0 + rho V_1) psi - (K_0 + K_1) phi
+//   y2 = (K'_0 + K'_1) psi + (D_0 + D_1 / rho) phi
+//
+// with the operators of Sec. 2.2 (D in Maue form) on P1 functions (Sec. 2.3).
+// For every test triangle tau and every trial triangle sigma that shares no
+// vertex with tau the 6x6 tensor 6-point rule is applied here; pairs sharing
+// a vertex (coinciding, edge- or vertex-adjacent) are integrated entirely by
+// the FP64 near-field CSR operator, built once per wavenumber pair.
+//
+// Per point pair (x in tau, y in sigma), r = |x - y|, G_m = e^{i k_m r}/r and
+// F_m = G_m (i k_m r - 1)/r^2 (the 1/4pi is applied once at the end):
+//   G_V = G_0 + rho G_1       (single layer, row 1)
+//   G_W = G_0 + G_1 / rho     (hypersingular curl-curl part, row 2)
+//   G_N = k_0^2 G_0 + k_1^2 G_1 / rho   (hypersingular normal part, row 2)
+//   F   = F_0 + F_1           (double layers)
+//   acc1(x) += G_V s_psi(y) - F (y - x).n_y s_phi(y)
+//   acc2(x) += F (x - y).n_x s_psi(y) - G_N (n_x.n_y) s_phi(y)
+//   A_tau   += w_x w_y G_W sC_sigma        (curl term, contracted per pair)
+// s_psi(y) = w_y |sigma| psi_h(y), sC_sigma = |sigma| curl(phi_h) on sigma.
+// Interior terms (index 1) are masked out for triangles of different objects.
+#include <cmath>
+#include <type_traits>
+
+#include "bem_internal.h"
+
+namespace bem {
+
+namespace {
+
+constexpr int FF_BLOCK = 256;   // test triangles (threads) per workgroup
+constexpr int FF_TILE = 32;     // trial triangles per LDS tile
+constexpr int SRC = GEO_STRIDE + DYN_STRIDE + 4;   // + object id, 3 vertex ids
+
+// 6-point rule (Dunavant, degree 4): orbits (1-2a, a, a); compile-time
+// constants so that the unrolled point loops fold them.
+constexpr double DUN_A1 = 0.44594849091596488631832925388305;
+constexpr double DUN_W1 = 0.22338158967801146569500700843312;
+constexpr double DUN_A2 = 0.091576213509770743459571463402202;
+constexpr double DUN_W2 = 0.10995174365532186763832632490021;
+__host__ __device__ constexpr double qw(int i) { return i < 3 ? DUN_W1 : DUN_W2; }
+__host__ __device__ constexpr double qb(int i, int a) {
+    return (a == i % 3) ? (1.0 - 2.0 * (i < 3 ? DUN_A1 : DUN_A2)) : (i < 3 ? DUN_A1 : DUN_A2);
+}
+
+// ---------------------------------------------------------------- math
+template <class R> struct Math;
+
+template <> struct Math<float> {
+    // sin/cos of 2 pi t: hardware v_sin/v_cos take revolutions; the argument
+    // is first reduced to [-1/2, 1/2] so that the hardware range is respected
+    // and the phase keeps FP32 resolution.
+    static __device__ __forceinline__ void sincos_rev(float t, float &s, float &c) {
+        float f = t - __builtin_rintf(t);
+        s = __builtin_amdgcn_sinf(f);
+        c = __builtin_amdgcn_cosf(f);
+    }
+    static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+};
+
+template <> struct Math<double> {
+    // sin/cos of 2 pi t for moderate |t|: t = n/4 + f, |f| <= 1/8, then
+    // Taylor series of sin and cos on [-pi/4, pi/4] (truncation < 5e-17) and
+    // the quadrant rotation by n.
+    static __device__ __forceinline__ void sincos_rev(double t, double &s, double &c) {
+        double n = __builtin_rint(4.0 * t);
+        double f = __builtin_fma(-0.25, n, t);
+        double x = f * 6.283185307179586476925286766559;
+        double x2 = x * x;
+        double ps = 1.0 / 1307674368000.0;           // 1/15!
+        ps = __builtin_fma(ps, -x2, 1.0 / 6227020800.0);    // 1/13!
+        ps = __builtin_fma(ps, -x2, 1.0 / 39916800.0);      // 1/11!
+        ps = __builtin_fma(ps, -x2, 1.0 / 362880.0);        // 1/9!
+        ps = __builtin_fma(ps, -x2, 1.0 / 5040.0);          // 1/7!
+        ps = __builtin_fma(ps, -x2, 1.0 / 120.0);           // 1/5!
+        ps = __builtin_fma(ps, -x2, 1.0 / 6.0);             // 1/3!
+        ps = __builtin_fma(ps, -x2, 1.0);
+        double sn = ps * x;
+        double pc = 1.0 / 20922789888000.0;          // 1/16!
+        pc = __builtin_fma(pc, -x2, 1.0 / 87178291200.0);   // 1/14!
+        pc = __builtin_fma(pc, -x2, 1.0 / 479001600.0);     // 1/12!
+        pc = __builtin_fma(pc, -x2, 1.0 / 3628800.0);       // 1/10!
+        pc = __builtin_fma(pc, -x2, 1.0 / 40320.0);         // 1/8!
+        pc = __builtin_fma(pc, -x2, 1.0 / 720.0);           // 1/6!
+        pc = __builtin_fma(pc, -x2, 1.0 / 24.0);            // 1/4!
+        pc = __builtin_fma(pc, -x2, 0.5);                   // 1/2!
+        double cs = __builtin_fma(pc, -x2, 1.0);
+        int q = ((int)n) & 3;
+        double s0 = (q & 1) ? cs : sn;
+        double c0 = (q & 1) ? sn : cs;
+        s = (q & 2) ? -s0 : s0;
+        c = ((q + 1) & 2) ? -c0 : c0;
+    }
+    // 1/sqrt(x): hardware estimate refined by two Newton steps
+    static __device__ __forceinline__ double rsq(double x) {
+        double y = __builtin_amdgcn_rsq(x);
+        double h = 0.5 * x;
+        y = y * __builtin_fma(-h * y, y, 1.5);
+        y = y * __builtin_fma(-h * y, y, 1.5);
+        return y;
+    }
+    static __device__ __forceinline__ double exp2(double x) { return ::exp2(x); }
+};
+
+// Wavenumber-dependent coefficients of one launch.
+template <class R> struct Coef {
+    R krev0, krev1;          // Re k / (2 pi)
+    R k0r, k0i, k1r, k1i;    // k
+    R kdec0, kdec1;          // -Im k * log2(e)
+    R rho, irho;
+    R n0r, n0i, n1r, n1i;    // k_0^2 and k_1^2 / rho
+};
+
+// ------------------------------------------------------------ source gather
+template <class R>
+__global__ __launch_bounds__(256) void source_gather_kernel(
+    const int32_t *__restrict__ tri, const double *__restrict__ tst,
+    const double2 *__restrict__ x, int64_t N, int T, R *__restrict__ dyn) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= T) return;
+    double2 ps[3], ph[3];
+    for (int b = 0; b < 3; b++) {
+        int v = tri[3 * s + b];
+        ps[b] = x[v];
+        ph[b] = x[N + v];
+    }
+    const double area = tst[TST_STRIDE * s];
+    R *out = dyn + (int64_t)DYN_STRIDE * s;
+    for (int j = 0; j < 6; j++) {
+        double wa = qw(j) * area;
+        double pr = 0, pi = 0, fr = 0, fi = 0;
+        for (int b = 0; b < 3; b++) {
+            pr += qb(j, b) * ps[b].x;
+            pi += qb(j, b) * ps[b].y;
+            fr += qb(j, b) * ph[b].x;
+            fi += qb(j, b) * ph[b].y;
+        }
+        out[2 * j] = (R)(wa * pr);
+        out[2 * j + 1] = (R)(wa * pi);
+        out[12 + 2 * j] = (R)(wa * fr);
+        out[12 + 2 * j + 1] = (R)(wa * fi);
+    }
+    for (int c = 0; c < 3; c++) {
+        double cr = 0, ci = 0;
+        for (int b = 0; b < 3; b++) {
+            double cu = tst[TST_STRIDE * s + 1 + 3 * b + c];
+            cr += cu * ph[b].x;
+            ci += cu * ph[b].y;
+        }
+        out[24 + 2 * c] = (R)(area * cr);
+        out[24 + 2 * c + 1] = (R)(area * ci);
+    }
+}
+
+// ------------------------------------------------------- fused pair kernel
+template <class R, bool CK0, bool CK1, bool MULTI>
+__global__ __launch_bounds__(FF_BLOCK) void farfield_kernel(
+    const R *__restrict__ geo, const R *__restrict__ dyn,
+    const int32_t *__restrict__ tobj, const int32_t *__restrict__ tri, int T,
+    int split_len, Coef<R> cf, double *__restrict__ partial) {
+    using MT = Math<R>;
+    __shared__ R tile[FF_TILE * SRC];
+    const int tau = blockIdx.x * FF_BLOCK + threadIdx.x;
+    const int split = blockIdx.y;
+    const int s_begin = split * split_len;
+    const int s_end = min(T, s_begin + split_len);
+    const bool active = tau < T;
+    const int tt = active ? tau : 0;
+
+    R px[6], py[6], pz[6];
+    for (int i = 0; i < 6; i++) {
+        px[i] = geo[GEO_STRIDE * tt + 3 * i];
+        py[i] = geo[GEO_STRIDE * tt + 3 * i + 1];
+        pz[i] = geo[GEO_STRIDE * tt + 3 * i + 2];
+    }
+    const R ntx = geo[GEO_STRIDE * tt + 18], nty = geo[GEO_STRIDE * tt + 19],
+            ntz = geo[GEO_STRIDE * tt + 20], ct = geo[GEO_STRIDE * tt + 21];
+    const R ot = MULTI ? (R)tobj[tt] : (R)0;
+    // vertex ids as R (exact: N < 2^24) for the adjacency test
+    const R tv0 = (R)tri[3 * tt], tv1 = (R)tri[3 * tt + 1], tv2 = (R)tri[3 * tt + 2];
+
+    R a1r[6], a1i[6], a2r[6], a2i[6];
+    R Ar[3], Ai[3];
+    double rows[12], Ad[6];
+    for (int i = 0; i < 6; i++) a1r[i] = a1i[i] = a2r[i] = a2i[i] = 0;
+    for (int c = 0; c < 3; c++) Ar[c] = Ai[c] = 0;
+    for (int c = 0; c < 12; c++) rows[c] = 0;
+    for (int c = 0; c < 6; c++) Ad[c] = 0;
+
+    auto flush = [&]() {
+        for (int a = 0; a < 3; a++) {
+            double r1r = 0, r1i = 0, r2r = 0, r2i = 0;
+            for (int i = 0; i < 6; i++) {
+                double wb = qw(i) * qb(i, a);
+                r1r += wb * (double)a1r[i];
+                r1i += wb * (double)a1i[i];
+                r2r += wb * (double)a2r[i];
+                r2i += wb * (double)a2i[i];
+            }
+            rows[2 * a] += r1r;
+            rows[2 * a + 1] += r1i;
+            rows[6 + 2 * a] += r2r;
+            rows[6 + 2 * a + 1] += r2i;
+        }
+        for (int c = 0; c < 3; c++) {
+            Ad[2 * c] += (double)Ar[c];
+            Ad[2 * c + 1] += (double)Ai[c];
+            Ar[c] = Ai[c] = 0;
+        }
+        for (int i = 0; i < 6; i++) a1r[i] = a1i[i] = a2r[i] = a2i[i] = 0;
+    };
+
+    for (int base = s_begin; base < s_end; base += FF_TILE) {
+        const int cnt = min(FF_TILE, s_end - base);
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < cnt * SRC; idx += FF_BLOCK) {
+            int s = idx / SRC, f = idx - s * SRC;
+            R v;
+            if (f < GEO_STRIDE) v = geo[(int64_t)GEO_STRIDE * (base + s) + f];
+            else if (f < GEO_STRIDE + DYN_STRIDE)
+                v = dyn[(int64_t)DYN_STRIDE * (base + s) + (f - GEO_STRIDE)];
+            else if (f == GEO_STRIDE + DYN_STRIDE) v = MULTI ? (R)tobj[base + s] : (R)0;
+            else v = (R)tri[3 * (base + s) + (f - GEO_STRIDE - DYN_STRIDE - 1)];
+            tile[idx] = v;
+        }
+        __syncthreads();
+        for (int s = 0; s < cnt; s++) {
+            const R *src = &tile[s * SRC];
+            {
+                const R *sv = src + GEO_STRIDE + DYN_STRIDE + 1;
+                const bool adj = sv[0] == tv0 || sv[0] == tv1 || sv[0] == tv2 ||
+                                 sv[1] == tv0 || sv[1] == tv1 || sv[1] == tv2 ||
+                                 sv[2] == tv0 || sv[2] == tv1 || sv[2] == tv2;
+                if (adj) continue;   // includes sigma == tau: near field
+            }
+            const R nsx = src[18], nsy = src[19], nsz = src[20], cs = src[21];
+            const R m1 = MULTI ? (src[GEO_STRIDE + DYN_STRIDE] == ot ? (R)1 : (R)0) : (R)1;
+            const R nn = ntx * nsx + nty * nsy + ntz * nsz;
+            // G_N (n_x . n_y) coefficients
+            const R g0r = cf.n0r * nn, g0i = cf.n0i * nn;
+            const R g1r = cf.n1r * nn, g1i = cf.n1i * nn;
+            R dnx[6], dny[6];
+            for (int j = 0; j < 6; j++)
+                dnx[j] = ct - (src[3 * j] * ntx + src[3 * j + 1] * nty + src[3 * j + 2] * ntz);
+            for (int i = 0; i < 6; i++)
+                dny[i] = cs - (px[i] * nsx + py[i] * nsy + pz[i] * nsz);
+            R gwr = 0, gwi = 0;
+#pragma unroll
+            for (int i = 0; i < 6; i++) {
+#pragma unroll
+                for (int j = 0; j < 6; j++) {
+                    const R dx = src[3 * j] - px[i];
+                    const R dy = src[3 * j + 1] - py[i];
+                    const R dz = src[3 * j + 2] - pz[i];
+                    const R r2 = dx * dx + dy * dy + dz * dz;
+                    const R ri = MT::rsq(r2);
+                    const R r = r2 * ri;
+                    R s0, c0, s1, c1;
+                    MT::sincos_rev(r * cf.krev0, s0, c0);
+                    MT::sincos_rev(r * cf.krev1, s1, c1);
+                    R ri0 = ri, ri1 = ri * m1;
+                    if (CK0) ri0 *= MT::exp2(r * cf.kdec0);
+                    if (CK1) ri1 *= MT::exp2(r * cf.kdec1);
+                    const R G0r = c0 * ri0, G0i = s0 * ri0;
+                    const R G1r = c1 * ri1, G1i = s1 * ri1;
+                    // G (i u - 1) with u = k r
+                    R F0r, F0i, F1r, F1i;
+                    {
+                        const R ur = cf.k0r * r;
+                        if (CK0) {
+                            const R ui = cf.k0i * r;
+                            F0r = -G0r * (1 + ui) - G0i * ur;
+                            F0i = -G0i * (1 + ui) + G0r * ur;
+                        } else {
+                            F0r = -G0r - ur * G0i;
+                            F0i = ur * G0r - G0i;
+                        }
+                    }
+                    {
+                        const R ur = cf.k1r * r;
+                        if (CK1) {
+                            const R ui = cf.k1i * r;
+                            F1r = -G1r * (1 + ui) - G1i * ur;
+                            F1i = -G1i * (1 + ui) + G1r * ur;
+                        } else {
+                            F1r = -G1r - ur * G1i;
+                            F1i = ur * G1r - G1i;
+                        }
+                    }
+                    const R ri2 = ri * ri;
+                    const R Fr = (F0r + F1r) * ri2, Fi = (F0i + F1i) * ri2;
+                    const R GVr = G0r + cf.rho * G1r, GVi = G0i + cf.rho * G1i;
+                    const R GWr = G0r + cf.irho * G1r, GWi = G0i + cf.irho * G1i;
+                    const R GNr = g0r * G0r - g0i * G0i + g1r * G1r - g1i * G1i;
+                    const R GNi = g0r * G0i + g0i * G0r + g1r * G1i + g1i * G1r;
+                    const R spr = src[GEO_STRIDE + 2 * j], spi = src[GEO_STRIDE + 2 * j + 1];
+                    const R sfr = src[GEO_STRIDE + 12 + 2 * j],
+                            sfi = src[GEO_STRIDE + 12 + 2 * j + 1];
+                    const R Fyr = Fr * dny[i], Fyi = Fi * dny[i];
+                    const R Fxr = Fr * dnx[j], Fxi = Fi * dnx[j];
+                    a1r[i] += GVr * spr - GVi * spi - (Fyr * sfr - Fyi * sfi);
+                    a1i[i] += GVr * spi + GVi * spr - (Fyr * sfi + Fyi * sfr);
+                    a2r[i] += Fxr * spr - Fxi * spi - (GNr * sfr - GNi * sfi);
+                    a2i[i] += Fxr * spi + Fxi * spr - (GNr * sfi + GNi * sfr);
+                    const R ww = (R)(qw(i) * qw(j));
+                    gwr += ww * GWr;
+                    gwi += ww * GWi;
+                }
+            }
+            for (int c = 0; c < 3; c++) {
+                const R scr = src[GEO_STRIDE + 24 + 2 * c], sci = src[GEO_STRIDE + 24 + 2 * c + 1];
+                Ar[c] += gwr * scr - gwi * sci;
+                Ai[c] += gwr * sci + gwi * scr;
+            }
+        }
+        if (std::is_same<R, float>::value) flush();
+    }
+    flush();
+    if (!active) return;
+    double *out = partial + ((int64_t)split * T + tau) * ROW_STRIDE;
+    for (int c = 0; c < 12; c++) out[c] = rows[c];
+    // the curl accumulator A follows the rows: [nsplit][T][6] after
+    // [nsplit][T][12]; the reduction contracts it with the test curls
+    double *outA = partial + (int64_t)gridDim.y * T * ROW_STRIDE +
+                   ((int64_t)split * T + tau) * 6;
+    for (int c = 0; c < 6; c++) outA[c] = Ad[c];
+}
+
+// --------------------------------------------------------- split reduction
+// trirows[tau][c] = |tau|/(4 pi) * sum_split (rows + curl term), fixed order.
+__global__ __launch_bounds__(256) void reduce_splits_kernel(
+    const double *__restrict__ partial, const double *__restrict__ tst, int T,
+    int nsplit, double *__restrict__ trirows) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    double acc[12], A[6];
+    for (int c = 0; c < 12; c++) acc[c] = 0;
+    for (int c = 0; c < 6; c++) A[c] = 0;
+    const double *pa = partial + (int64_t)nsplit * T * ROW_STRIDE;
+    for (int s = 0; s < nsplit; s++) {
+        const double *p = partial + ((int64_t)s * T + t) * ROW_STRIDE;
+        for (int c = 0; c < 12; c++) acc[c] += p[c];
+        const double *q = pa + ((int64_t)s * T + t) * 6;
+        for (int c = 0; c < 6; c++) A[c] += q[c];
+    }
+    const double *ts = tst + (int64_t)TST_STRIDE * t;
+    const double sc = ts[0] * 0.079577471545947667884441881686257;   // |tau|/(4 pi)
+    for (int a = 0; a < 3; a++) {
+        const double *cu = ts + 1 + 3 * a;
+        acc[6 + 2 * a] += cu[0] * A[0] + cu[1] * A[2] + cu[2] * A[4];
+        acc[6 + 2 * a + 1] += cu[0] * A[1] + cu[1] * A[3] + cu[2] * A[5];
+    }
+    for (int c = 0; c < 12; c++) trirows[(int64_t)ROW_STRIDE * t + c] = sc * acc[c];
+}
+
+// ------------------------------------- vertex gather + near-field CSR SpMV
+__global__ __launch_bounds__(256) void finalize_kernel(
+    const double *__restrict__ trirows, const int32_t *__restrict__ star_ptr,
+    const int32_t *__restrict__ star_idx, const int32_t *__restrict__ rowptr,
+    const int32_t *__restrict__ col, const double2 *__restrict__ nf, int64_t nnz,
+    const double2 *__restrict__ x, int64_t N, double2 *__restrict__ y) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double y1r = 0, y1i = 0, y2r = 0, y2i = 0;
+    for (int e = star_ptr[i]; e < star_ptr[i + 1]; e++) {
+        int ta = star_idx[e];
+        int t = ta / 3, a = ta - 3 * t;
+        const double *r = trirows + (int64_t)ROW_STRIDE * t;
+        y1r += r[2 * a];
+        y1i += r[2 * a + 1];
+        y2r += r[6 + 2 * a];
+        y2i += r[6 + 2 * a + 1];
+    }
+    const double2 *C11 = nf, *C12 = nf + nnz, *C21 = nf + 2 * nnz, *C22 = nf + 3 * nnz;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; e++) {
+        int j = col[e];
+        double2 p = x[j], f = x[N + j];
+        double2 a = C11[e], b = C12[e], c = C21[e], d = C22[e];
+        y1r += a.x * p.x - a.y * p.y + b.x * f.x - b.y * f.y;
+        y1i += a.x * p.y + a.y * p.x + b.x * f.y + b.y * f.x;
+        y2r += c.x * p.x - c.y * p.y + d.x * f.x - d.y * f.y;
+        y2i += c.x * p.y + c.y * p.x + d.x * f.y + d.y * f.x;
+    }
+    y[i] = make_double2(y1r, y1i);
+    y[N + i] = make_double2(y2r, y2i);
+}
+
+template <class R> Coef<R> make_coef(double2 k0, double2 k1, double rho) {
+    Coef<R> c;
+    const double inv2pi = 0.15915494309189533576888376337251;
+    const double log2e = 1.4426950408889634073599246810019;
+    c.krev0 = (R)(k0.x * inv2pi);
+    c.krev1 = (R)(k1.x * inv2pi);
+    c.k0r = (R)k0.x;
+    c.k0i = (R)k0.y;
+    c.k1r = (R)k1.x;
+    c.k1i = (R)k1.y;
+    c.kdec0 = (R)(-k0.y * log2e);
+    c.kdec1 = (R)(-k1.y * log2e);
+    c.rho = (R)rho;
+    c.irho = (R)(1.0 / rho);
+    c.n0r = (R)(k0.x * k0.x - k0.y * k0.y);
+    c.n0i = (R)(2.0 * k0.x * k0.y);
+    c.n1r = (R)((k1.x * k1.x - k1.y * k1.y) / rho);
+    c.n1i = (R)(2.0 * k1.x * k1.y / rho);
+    return c;
+}
+
+template <class R, bool CK0, bool CK1, bool MULTI>
+void launch_far(dim3 grid, hipStream_t s, const R *geo, const R *dyn,
+                const int32_t *tobj, const int32_t *tri, int T, int split_len, Coef<R> cf,
+                double *partial) {
+    hipLaunchKernelGGL((farfield_kernel<R, CK0, CK1, MULTI>), grid, dim3(FF_BLOCK), 0, s,
+                       geo, dyn, tobj, tri, T, split_len, cf, partial);
+}
+
+template <class R>
+void dispatch_far(dim3 grid, hipStream_t s, const R *geo, const R *dyn,
+                  const int32_t *tobj, const int32_t *tri, int T, int split_len, Coef<R> cf,
+                  double *partial, bool ck0, bool ck1, bool multi) {
+    int code = (ck0 ? 4 : 0) | (ck1 ? 2 : 0) | (multi ? 1 : 0);
+    switch (code) {
+#define BEM_CASE(c, a, b, m) \
+    case c: launch_far<R, a, b, m>(grid, s, geo, dyn, tobj, tri, T, split_len, cf, partial); break;
+        BEM_CASE(0, false, false, false)
+        BEM_CASE(1, false, false, true)
+        BEM_CASE(2, false, true, false)
+        BEM_CASE(3, false, true, true)
+        BEM_CASE(4, true, false, false)
+        BEM_CASE(5, true, false, true)
+        BEM_CASE(6, true, true, false)
+        BEM_CASE(7, true, true, true)
+#undef BEM_CASE
+    }
+}
+
+}   // namespace
+
+int farfield_splits(int T) {
+    int tiles = (T + FF_BLOCK - 1) / FF_BLOCK;
+    const int target = 2048;   // workgroups in flight per launch
+    int s = (target + tiles - 1) / tiles;
+    int min_len = FF_TILE;
+    int max_s = (T + min_len - 1) / min_len;
+    if (s > max_s) s = max_s;
+    if (s < 1) s = 1;
+    return s;
+}
+
+void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
+                    double rho, const double2 *x, double2 *y, int precision,
+                    hipStream_t s) {
+    const int T = (int)m->T;
+    const int nsplit = farfield_splits(T);
+    const int split_len = (T + nsplit - 1) / nsplit;
+    const size_t need = (size_t)nsplit * T * (ROW_STRIDE + 6);
+    if (m->partial.n < need) m->partial.alloc(need);
+    if (m->trirows.n < (size_t)T * ROW_STRIDE) m->trirows.alloc((size_t)T * ROW_STRIDE);
+    const bool ck0 = k0.y != 0.0, ck1 = k1.y != 0.0, multi = m->nobj > 1;
+    dim3 gg((T + 255) / 256);
+    dim3 grid((T + FF_BLOCK - 1) / FF_BLOCK, nsplit);
+    if (precision == BEM_FP32) {
+        if (m->dyn32.n < (size_t)T * DYN_STRIDE) m->dyn32.alloc((size_t)T * DYN_STRIDE);
+        hipLaunchKernelGGL(source_gather_kernel<float>, gg, dim3(256), 0, s, m->tri_d.p,
+                           m->tst.p, x, m->N, T, m->dyn32.p);
+        BEM_LAUNCH_CHECK();
+        Timer tm("farfield_fp32", s);
+        dispatch_far<float>(grid, s, m->geo32.p, m->dyn32.p, m->tobj_d.p, m->tri_d.p, T, split_len,
+                            make_coef<float>(k0, k1, rho), m->partial.p, ck0, ck1, multi);
+        BEM_LAUNCH_CHECK();
+    } else {
+        if (m->dyn64.n < (size_t)T * DYN_STRIDE) m->dyn64.alloc((size_t)T * DYN_STRIDE);
+        hipLaunchKernelGGL(source_gather_kernel<double>, gg, dim3(256), 0, s, m->tri_d.p,
+                           m->tst.p, x, m->N, T, m->dyn64.p);
+        BEM_LAUNCH_CHECK();
+        Timer tm("farfield_fp64", s);
+        dispatch_far<double>(grid, s, m->geo64.p, m->dyn64.p, m->tobj_d.p, m->tri_d.p, T, split_len,
+                             make_coef<double>(k0, k1, rho), m->partial.p, ck0, ck1, multi);
+        BEM_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(reduce_splits_kernel, gg, dim3(256), 0, s, m->partial.p, m->tst.p,
+                       T, nsplit, m->trirows.p);
+    BEM_LAUNCH_CHECK();
+    Timer tf("finalize", s);
+    hipLaunchKernelGGL(finalize_kernel, dim3((m->N + 255) / 256), dim3(256), 0, s,
+                       m->trirows.p, m->star_ptr.p, m->star_idx.p, m->nf_rowptr.p,
+                       m->nf_col.p, (const double2 *)nf.vals.p, m->nf_nnz, x, m->N, y);
+    BEM_LAUNCH_CHECK();
+}
+
+}   // namespace bem

@@ -1,0 +1,160 @@
+"""GPU parity of the permuted PMCHWT matvec, RHS and far field against the
+FP64 oracle (element by element), through the C ABI.
+
+Bar: relative L2 error <= 1e-10 for the FP64 path and <= 1e-5 for the FP32
+path, per block row (the V-row and the D-row differ in scale) and overall.
+Sizes: icosphere L3 (C1, all rows, dense oracle), L2 and a geodesic sphere
+(ragged triangle counts), two objects, lossy wavenumbers, and the full
+icosphere L5 workload on seed-sampled rows.
+"""
+import numpy as np
+import pytest
+
+from bem_inputs import (complex_normal, geodesic_sphere, icosphere, sample_rows,
+                        two_spheres, wave_directions)
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2104_04609_amd as P
+    return P
+
+
+_DENSE = {}
+
+
+def dense(mesh, k0, k1, rho):
+    from oracle.operators import pmchwt_matrix
+    key = (mesh.name, complex(k0), complex(k1), rho)
+    if key not in _DENSE:
+        _DENSE[key] = pmchwt_matrix(mesh, k0, k1, rho)
+    return _DENSE[key]
+
+
+def rel_blocks(y, ref, N):
+    out = {}
+    for name, sl in (("row1", slice(0, N)), ("row2", slice(N, 2 * N)),
+                     ("all", slice(0, 2 * N))):
+        out[name] = np.linalg.norm(y[sl] - ref[sl]) / np.linalg.norm(ref[sl])
+    return out
+
+
+def gpu_matvec(P, mesh, k0, k1, rho, x, precision):
+    import torch
+    M = P.Mesh.from_inputs(mesh)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    y = P.pmchwt_matvec(M, k0, k1, rho, xt, precision=precision)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+CASES = {
+    "C1_ico3": (lambda: icosphere(3), 2.0, 3.0, 1.5),
+    "ico2_lossy": (lambda: icosphere(2), 2.5 + 0.3j, 4.0 + 0.6j, 1.9),
+    "geodesic3_ragged": (lambda: geodesic_sphere(3), 1.5, 2.2, 0.7),
+    "two_spheres1": (lambda: two_spheres(1, offset=1.5), 2.0, 3.5 + 0.2j, 1.3),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_matvec_matches_dense_oracle(P, case, precision):
+    make, k0, k1, rho = CASES[case]
+    mesh = make()
+    print(f"case {case} N={mesh.n_vertices} T={mesh.n_triangles} {precision}", flush=True)
+    N = mesh.n_vertices
+    x = complex_normal(2 * N, seed=0)
+    ref = dense(mesh, k0, k1, rho) @ x
+    y = gpu_matvec(P, mesh, k0, k1, rho, x, precision)
+    err = rel_blocks(y, ref, N)
+    print(case, precision, err)
+    for v in err.values():
+        assert v <= TOL[precision], err
+
+
+def test_matvec_smooth_input_fp32(P):
+    # a converged-solution-like smooth input (low-order harmonics)
+    mesh = icosphere(3)
+    N = mesh.n_vertices
+    z = mesh.vertices[:, 2]
+    x = np.concatenate([np.exp(2j * z), (0.3 + 0.1j) * z ** 2]).astype(np.complex128)
+    ref = dense(mesh, 2.0, 3.0, 1.5) @ x
+    y = gpu_matvec(P, mesh, 2.0, 3.0, 1.5, x, "fp32")
+    err = rel_blocks(y, ref, N)
+    assert max(err.values()) <= TOL["fp32"], err
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_matvec_full_size_sampled_rows(P, precision):
+    """Icosphere L5 (10 242 vertices), k_ext = 10, k_int = 15, rho = 1.5, in
+    the launch configuration used for timing; 40 seed-sampled rows of each
+    block row against the oracle's matrix-free rows."""
+    from oracle.operators import pmchwt_matvec_rows
+    mesh = icosphere(5)
+    N = mesh.n_vertices
+    x = complex_normal(2 * N, seed=0)
+    rows = sample_rows(N, 40, seed=1)
+    print(f"ico5 sampled rows {precision}", flush=True)
+    r1, r2 = pmchwt_matvec_rows(mesh, 10.0, 15.0, 1.5, x, rows)
+    y = gpu_matvec(P, mesh, 10.0, 15.0, 1.5, x, precision)
+    e1 = np.linalg.norm(y[rows] - r1) / np.linalg.norm(r1)
+    e2 = np.linalg.norm(y[N + rows] - r2) / np.linalg.norm(r2)
+    print(precision, e1, e2)
+    assert e1 <= TOL[precision] and e2 <= TOL[precision], (e1, e2)
+
+
+def test_matvec_deterministic_and_batched(P):
+    import torch
+    mesh = icosphere(3)
+    N = mesh.n_vertices
+    M = P.Mesh.from_inputs(mesh)
+    X = torch.from_numpy(complex_normal((3, 2 * N), seed=4)).cuda()
+    for prec in ("fp64", "fp32"):
+        ys = [P.pmchwt_matvec(M, 2.0, 3.0, 1.5, X, precision=prec) for _ in range(3)]
+        torch.cuda.synchronize()
+        assert torch.equal(ys[0], ys[1]) and torch.equal(ys[0], ys[2])
+        for r in range(3):
+            yr = P.pmchwt_matvec(M, 2.0, 3.0, 1.5, X[r].contiguous(), precision=prec)
+            assert torch.equal(yr, ys[0][r])
+
+
+def test_rhs_matches_oracle(P):
+    from oracle.rhs import plane_wave_rhs
+    mesh = geodesic_sphere(4)
+    M = P.Mesh.from_inputs(mesh)
+    d = wave_directions(3, seed=7)
+    f = P.pmchwt_rhs(M, 3.0 + 0.1j, d).cpu().numpy()
+    for w in range(3):
+        ref = plane_wave_rhs(mesh, 3.0 + 0.1j, d[w])
+        assert np.linalg.norm(f[w] - ref) / np.linalg.norm(ref) < 1e-13
+
+
+def test_far_field_matches_oracle(P):
+    import torch
+    from oracle.rhs import far_field
+    mesh = icosphere(2)
+    M = P.Mesh.from_inputs(mesh)
+    x = complex_normal(2 * mesh.n_vertices, seed=9)
+    dirs = wave_directions(17, seed=3)
+    out = P.far_field(M, 2.0, torch.from_numpy(x).cuda(), dirs)
+    ref = far_field(mesh, 2.0, x, dirs)
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref) < 1e-13
+
+
+def test_invalid_arguments_raise(P):
+    import torch
+    mesh = icosphere(1)
+    M = P.Mesh.from_inputs(mesh)
+    x = torch.zeros(2 * mesh.n_vertices, dtype=torch.complex128, device="cuda")
+    with pytest.raises(P.BemError):
+        P.pmchwt_matvec(M, 2.0, 3.0, -1.0, x)
+    with pytest.raises(P.BemError):
+        P.pmchwt_matvec(M, 2.0 - 0.5j, 3.0, 1.0, x)
+    with pytest.raises(ValueError):
+        P.pmchwt_matvec(M, 2.0, 3.0, 1.0, x[:-1].contiguous())

@@ -20,7 +20,8 @@ LIB = os.path.join(HERE, "libbem.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["api.cpp", "mesh.cpp", "quadrature.cpp", "farfield.hip",
-           "nearfield.hip", "rhs.hip", "osrc.cpp", "solve.cpp"]
+           "nearfield.hip", "rhs.hip", "sparse_ldl.cpp", "osrc.cpp",
+           "osrc_kernels.hip", "blas.hip", "solve.cpp"]
 
 FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Wall", "-Wno-unused-function", "-Wno-unused-result",

@@ -30,6 +30,8 @@ void prof_clear_locked() {
 
 [[noreturn]] void fail(int code, const std::string &msg) { throw Error{code, msg}; }
 
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
 Timer::Timer(const char *kernel, hipStream_t stream) : name(kernel), s(stream) {
     std::lock_guard<std::mutex> g(g_prof_mu);
     if (!g_prof_on) return;
@@ -58,6 +60,7 @@ int64_t bem_mesh::device_bytes() const {
                 dyn64.bytes() + dyn32.bytes() + partial.bytes() + trirows.bytes();
     for (const auto &kv : near_cache) b += kv.second->vals.bytes();
     for (const auto &kv : osrc_cache) b += bem::osrc_bytes(*kv.second);
+    if (osrc_sym) b += bem::osrc_sym_bytes(*osrc_sym);
     return b;
 }
 

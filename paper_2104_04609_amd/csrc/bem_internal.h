@@ -20,6 +20,7 @@ struct Error {
 };
 
 [[noreturn]] void fail(int code, const std::string &msg);
+void set_last_error(const std::string &msg);
 
 #define BEM_HIP(expr)                                                         \
     do {                                                                      \
@@ -111,10 +112,10 @@ struct NearOperator {
 
 struct OsrcKey {
     int np;
-    double theta, kr, ki, ker, kei;
+    double theta, kr, ki;
+    std::vector<double> keps;   // (re, im) of k_eps per object
     bool operator<(const OsrcKey &o) const {
-        return std::tie(np, theta, kr, ki, ker, kei) <
-               std::tie(o.np, o.theta, o.kr, o.ki, o.ker, o.kei);
+        return std::tie(np, theta, kr, ki, keps) < std::tie(o.np, o.theta, o.kr, o.ki, o.keps);
     }
 };
 
@@ -123,6 +124,11 @@ struct OsrcDeleter {
     void operator()(OsrcState *p) const;   // osrc.cpp
 };
 int64_t osrc_bytes(const OsrcState &st);
+struct OsrcSymbolicState;   // osrc.cpp
+struct OsrcSymDeleter {
+    void operator()(OsrcSymbolicState *p) const;
+};
+int64_t osrc_sym_bytes(const OsrcSymbolicState &st);
 
 struct Profile;
 
@@ -163,6 +169,7 @@ struct bem_mesh {
     std::map<bem::NearKey, std::unique_ptr<bem::NearOperator>> near_cache;
 
     // OSRC: P1 vertex graph, M and S values, factor state per parameter set
+    std::unique_ptr<bem::OsrcSymbolicState, bem::OsrcSymDeleter> osrc_sym;
     std::map<bem::OsrcKey, std::unique_ptr<bem::OsrcState, bem::OsrcDeleter>> osrc_cache;
 
     // scratch (grown on demand)

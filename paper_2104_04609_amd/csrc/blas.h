@@ -1,0 +1,22 @@
+// Complex FP64 vector kernels used by GMRES (deterministic reductions).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace bem {
+
+// h[i] = <V_i, w> = sum_k conj(V[i][k]) w[k], i < m (V row-major, stride ld)
+void blas_block_dot(const double2 *V, int64_t ld, int m, const double2 *w, int64_t n,
+                    double2 *h, hipStream_t s);
+// w += sign * sum_{i<m} h[i] V_i
+void blas_block_axpy(const double2 *V, int64_t ld, const double2 *h, int m, double sign,
+                     double2 *w, int64_t n, hipStream_t s);
+// v /= sqrt(Re nrm2[0]), in place
+void blas_normalize(double2 *v, const double2 *nrm2, int64_t n, hipStream_t s);
+// out = a x + b y  (y may be NULL; out may alias x or y)
+void blas_axpby(double2 a, const double2 *x, double2 b, const double2 *y, double2 *out,
+                int64_t n, hipStream_t s);
+
+}   // namespace bem

@@ -1,0 +1,102 @@
+// Complex FP64 vector kernels of the GMRES solver.  All reductions run in a
+// fixed order (per-thread strided sums, then an LDS tree), so repeated runs
+// give identical results; no atomics.
+#include "bem_internal.h"
+#include "blas.h"
+
+namespace bem {
+
+namespace {
+
+constexpr int BT = 256;
+
+// h[i] = sum_k conj(V[i][k]) w[k], one workgroup per basis vector i
+__global__ __launch_bounds__(BT) void block_dot_kernel(const double2 *__restrict__ V, int64_t ld,
+                                                       const double2 *__restrict__ w, int64_t n,
+                                                       double2 *__restrict__ h) {
+    __shared__ double sr[BT], si[BT];
+    const double2 *v = V + (int64_t)blockIdx.x * ld;
+    double ar = 0.0, ai = 0.0;
+    for (int64_t k = threadIdx.x; k < n; k += BT) {
+        const double2 a = v[k], b = w[k];
+        ar += a.x * b.x + a.y * b.y;
+        ai += a.x * b.y - a.y * b.x;
+    }
+    sr[threadIdx.x] = ar;
+    si[threadIdx.x] = ai;
+    __syncthreads();
+    for (int o = BT / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            sr[threadIdx.x] += sr[threadIdx.x + o];
+            si[threadIdx.x] += si[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) h[blockIdx.x] = make_double2(sr[0], si[0]);
+}
+
+// w[k] += sign * sum_{i < m} V[i][k] h[i]   (fixed order in i)
+__global__ __launch_bounds__(BT) void block_axpy_kernel(const double2 *__restrict__ V, int64_t ld,
+                                                        const double2 *__restrict__ h, int m,
+                                                        double sign, double2 *__restrict__ w,
+                                                        int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (k >= n) return;
+    double ar = 0.0, ai = 0.0;
+    for (int i = 0; i < m; i++) {
+        const double2 a = V[(int64_t)i * ld + k], b = h[i];
+        ar += a.x * b.x - a.y * b.y;
+        ai += a.x * b.y + a.y * b.x;
+    }
+    double2 o = w[k];
+    w[k] = make_double2(o.x + sign * ar, o.y + sign * ai);
+}
+
+// v /= sqrt(nrm2->x) in place (nrm2 from a block_dot of v with itself)
+__global__ __launch_bounds__(BT) void normalize_kernel(double2 *v, const double2 *nrm2,
+                                                       int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (k >= n) return;
+    const double s = nrm2->x > 0.0 ? 1.0 / sqrt(nrm2->x) : 0.0;
+    v[k] = make_double2(v[k].x * s, v[k].y * s);
+}
+
+// out = a * x + b * y  (complex scalars)
+__global__ __launch_bounds__(BT) void axpby_kernel(double2 a, const double2 *x, double2 b,
+                                                   const double2 *y, double2 *out, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (k >= n) return;
+    const double2 u = x[k], v = y ? y[k] : make_double2(0.0, 0.0);
+    out[k] = make_double2(a.x * u.x - a.y * u.y + b.x * v.x - b.y * v.y,
+                          a.x * u.y + a.y * u.x + b.x * v.y + b.y * v.x);
+}
+
+unsigned blocks(int64_t n) { return (unsigned)((n + BT - 1) / BT); }
+
+}   // namespace
+
+void blas_block_dot(const double2 *V, int64_t ld, int m, const double2 *w, int64_t n,
+                    double2 *h, hipStream_t s) {
+    hipLaunchKernelGGL(block_dot_kernel, dim3(m), dim3(BT), 0, s, V, ld, w, n, h);
+    BEM_LAUNCH_CHECK();
+}
+
+void blas_block_axpy(const double2 *V, int64_t ld, const double2 *h, int m, double sign,
+                     double2 *w, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(block_axpy_kernel, dim3(blocks(n)), dim3(BT), 0, s, V, ld, h, m, sign,
+                       w, n);
+    BEM_LAUNCH_CHECK();
+}
+
+void blas_normalize(double2 *v, const double2 *nrm2, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(normalize_kernel, dim3(blocks(n)), dim3(BT), 0, s, v, nrm2, n);
+    BEM_LAUNCH_CHECK();
+}
+
+void blas_axpby(double2 a, const double2 *x, double2 b, const double2 *y, double2 *out,
+                int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(axpby_kernel, dim3(blocks(n)), dim3(BT), 0, s, a, x, b, y, out, n);
+    BEM_LAUNCH_CHECK();
+}
+
+}   // namespace bem

@@ -17,8 +17,11 @@
  *   - Work is enqueued on hip_stream (NULL = the null stream) and is
  *     stream-ordered; calls that return host data synchronise that stream.
  *   - A mesh handle owns all device state derived from the mesh (geometry,
- *     near-field operators, OSRC factors).  Reading it from several streams is
- *     safe; creation and destruction are not thread-safe.
+ *     near-field operators, OSRC factors) and the device scratch its calls
+ *     use.  Calls on one handle are stream-ordered; calls on the same handle
+ *     from different streams or host threads must not overlap (they share
+ *     that scratch).  Different handles are independent.  Creation and
+ *     destruction are not thread-safe.
  */
 #ifndef BEM_H
 #define BEM_H
@@ -73,7 +76,7 @@ int bem_mesh_info(const bem_mesh *mesh, int64_t *n_vertices,
                   int64_t *device_bytes);
 
 /*
- * y = B x: the Galerkin (weak-form) permuted PMCHWT operator (Sec. 2.6,
+ * y = B x: the Galerkin (weak-form) permuted PMCHWT operator (Sec. 2.7,
  * single scatterer; multiple scatterers: exterior operators couple all
  * objects, interior ones act within each object)
  *     B = [[ V_0 + rho V_1 , -(K_0 + K_1)      ],
@@ -95,9 +98,9 @@ int pmchwt_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int,
 
 /*
  * y = diag(L_DtN, L_NtD) x in strong form (coefficients to coefficients),
- * the OSRC operators of Sec. 2.5 with damped wavenumber k_eps, square root
+ * the OSRC operators of Sec. 2.6 with damped wavenumber k_eps, square root
  * localised by an N_p-term Pade series with branch-cut rotation theta
- * (Sec. 2.6):  L_DtN = ik R(X),  L_NtD = (1/ik) R(X)(I + X)^{-1},
+ * (Sec. 2.7):  L_DtN = ik R(X),  L_NtD = (1/ik) R(X)(I + X)^{-1},
  * X = -M^{-1} S / k_eps^2 (P1 mass M, Laplace-Beltrami stiffness S),
  * R(z) = C_0 + sum_j A_j z / (1 + B_j z).  k and k_eps apply to every object.
  * The shifted sparse systems are factorised once per (k_eps, N_p, theta) and
@@ -111,7 +114,7 @@ int osrc_apply(const bem_mesh *mesh, int pade_terms, double theta,
 
 /*
  * Weak right-hand side [f_D; f_N] of the PMCHWT system for unit-amplitude
- * plane waves u_inc = exp(i k_ext d.x) (Sec. 2.1, Sec. 2.6):
+ * plane waves u_inc = exp(i k_ext d.x) (Sec. 2.1, Sec. 2.7):
  * f_D,i = int u_inc phi_i, f_N,i = int i k_ext (d.n) u_inc phi_i, 6-point rule.
  *   directions  host, float64 [n_waves][3] (unit vectors)
  *   f           device, bem_c64 [n_waves][2N]
@@ -126,7 +129,9 @@ typedef struct {
     double R;            /* k_eps radius; <= 0: 0.1 x object circumradius */
     int precision;       /* BEM_FP64 (plain GMRES) or BEM_FP32 (refinement) */
     int maxiter;         /* GMRES iterations cap (total), default 1000 */
-    double inner_tol;    /* FP32 inner GMRES tolerance, default 1e-5 */
+    double inner_tol;    /* FP32 form: each inner GMRES stops at an absolute
+                            residual inner_tol * tol * ||b|| (at most half of
+                            the current outer residual); default 0.3 */
     int max_outer;       /* refinement steps cap, default 8 */
 } bem_solve_opts;
 
@@ -143,7 +148,7 @@ typedef struct {
 void bem_solve_opts_default(bem_solve_opts *opts);
 
 /*
- * Solve the OSRC-preconditioned permuted PMCHWT system (Sec. 2.6, strong
+ * Solve the OSRC-preconditioned permuted PMCHWT system (Sec. 2.7, strong
  * form Sec. 2.4) for each plane wave:
  *     L M^{-1} B x = L M^{-1} f,   L = diag(L_DtN, L_NtD) per object,
  * with unrestarted GMRES from x_0 = 0 (Sec. 3.1) to ||b - P x|| <= tol ||b||.

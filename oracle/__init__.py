@@ -9,10 +9,10 @@ boundary integral equations for acoustic transmission", J. Comput. Phys. 2022):
     (Sec. 2.2 boundary operators; Sec. 2.3 P1 Galerkin), regular 6-point rule
     for separated triangles and Sauter-Schwab-type singular quadrature for
     triangles sharing a vertex, an edge or coinciding;
-  * the permuted PMCHWT block operator with density scaling (Sec. 2.6);
+  * the permuted PMCHWT block operator with density scaling (Sec. 2.7);
   * mass matrix / strong form (Sec. 2.4);
   * OSRC DtN/NtD operators with damped wavenumber and rotated Pade
-    square root, sparse LU per shift (Sec. 2.5, 2.6);
+    square root, sparse LU per shift (Sec. 2.6, 2.7);
   * unrestarted MGS GMRES (Sec. 3.1);
   * plane-wave right-hand side, far field, and the Mie series of a penetrable
     sphere used as the end-to-end pin.

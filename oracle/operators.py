@@ -2,14 +2,14 @@
 
 Permuted PMCHWT, single scatterer, unknowns [psi; phi] with
 psi = exterior Neumann trace, phi = Dirichlet trace of the total field
-(Sec. 2.2, unique pair of traces; Sec. 2.6, permuted formulation):
+(Sec. 2.2, unique pair of traces; Sec. 2.7, permuted formulation):
 
     B = [[ V_0 + rho V_1 ,  -(K_0 + K_1)        ],
          [ K'_0 + K'_1   ,   D_0 + D_1 / rho    ]],   rho = rho_int / rho_ext,
 
 right-hand side [gamma_D u_inc; gamma_N u_inc].  Exterior operators (index 0)
 couple all triangles; interior ones (index 1) act within each object only
-(Sec. 2.6, multiple scattering).
+(Sec. 2.7, multiple scattering).
 """
 from __future__ import annotations
 

@@ -1,9 +1,9 @@
 """OSRC preconditioner and P1 mass/stiffness matrices (oracle only).
 
-OSRC operators (Sec. 2.5):  L_NtD = (1/ik) (I + Delta_Gamma / k_eps^2)^(-1/2),
+OSRC operators (Sec. 2.6):  L_NtD = (1/ik) (I + Delta_Gamma / k_eps^2)^(-1/2),
 L_DtN = ik (I + Delta_Gamma / k_eps^2)^(1/2), damped wavenumber
 k_eps = k (1 + 0.4 i (k R)^(-2/3)).  The square root is localised by a Pade
-series of N_p terms with branch-cut rotation theta (Sec. 2.6, last paragraph);
+series of N_p terms with branch-cut rotation theta (Sec. 2.7, last paragraph);
 the paper gives no formulas for it, so this follows the rotated Pade
 approximant it cites (Milinazzo-Zala-Brooke coefficients with the
 Antoine-Darbas rotation):
@@ -21,7 +21,7 @@ discrete Delta_Gamma / k_eps^2 is X = -M^{-1} S / k_eps^2):
   beta_j = B_j / k_eps^2,
   L_DtN u = ik R(X) u,     L_NtD u = (1/ik) R(X) (M - S/k_eps^2)^{-1} M u.
 
-All shifted systems are solved with a sparse LU computed once (Sec. 2.6).
+All shifted systems are solved with a sparse LU computed once (Sec. 2.7).
 """
 from __future__ import annotations
 
@@ -113,7 +113,7 @@ def pade_eval(z, n_p, theta):
 
 
 def damped_wavenumber(k, R):
-    """k_eps = k (1 + 0.4 i (k R)^(-2/3)), principal branch (Sec. 2.5)."""
+    """k_eps = k (1 + 0.4 i (k R)^(-2/3)), principal branch (Sec. 2.6)."""
     k = complex(k)
     return k * (1.0 + 0.4j * (k * R) ** (-2.0 / 3.0))
 

@@ -1,7 +1,7 @@
 """Plane-wave right-hand side and far field (oracle only).
 
 Incident plane wave of unit amplitude u_inc = exp(i k_ext d . x) (Sec. 2.1).
-Weak right-hand side of the permuted PMCHWT (Sec. 2.6):
+Weak right-hand side of the permuted PMCHWT (Sec. 2.7):
     f_D,i = int u_inc phi_i,     f_N,i = int (d/dn) u_inc phi_i
           = int i k_ext (d . n) exp(i k_ext d . x) phi_i,
 both with the 6-point triangle rule.

@@ -1,6 +1,6 @@
 """OSRC-preconditioned permuted PMCHWT solve (oracle only).
 
-Preconditioned strong-form system (Sec. 2.4 mass preconditioning, Sec. 2.6
+Preconditioned strong-form system (Sec. 2.4 mass preconditioning, Sec. 2.7
 OSRC-preconditioned PMCHWT):
     L M^{-1} B x = L M^{-1} f,   L = diag(L_DtN, L_NtD) per object,
 with M^{-1} applied to each N-block, the OSRC wavenumber the interior one by

@@ -1,4 +1,4 @@
-// Matrix-free Galerkin matvec of the permuted PMCHWT operator (Sec. 2.6):
+// Matrix-free Galerkin matvec of the permuted PMCHWT operator (Sec. 2.7):
 //
 //   y1 = (V_0 + rho V_1) psi - (K_0 + K_1) phi
 //   y2 = (K'_0 + K'_1) psi + (D_0 + D_1 / rho) phi

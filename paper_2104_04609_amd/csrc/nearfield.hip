@@ -4,7 +4,7 @@
 // For every ordered triangle pair (tau, sigma) sharing at least one vertex the
 // four combined 3x3 blocks
 //   B11 = V_0 + rho V_1,  B12 = -(K_0 + K_1),  B21 = K'_0 + K'_1,
-//   B22 = D_0 + D_1 / rho          (Sec. 2.6; operators of Sec. 2.2)
+//   B22 = D_0 + D_1 / rho          (Sec. 2.7; operators of Sec. 2.2)
 // are integrated with the singular rule of the pair's class (coincident,
 // common edge, common vertex); the matrix-free pair kernel skips exactly these
 // pairs.  The blocks are summed into a vertex-by-vertex CSR matrix in a fixed

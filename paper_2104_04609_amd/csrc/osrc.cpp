@@ -1,4 +1,4 @@
-// OSRC preconditioner (Sec. 2.5, Sec. 2.6 of the paper): host set-up of the
+// OSRC preconditioner (Sec. 2.6, Sec. 2.7 of the paper): host set-up of the
 // shifted sparse factorisations and the stream-ordered application.
 //
 //   L_DtN = ik (I + X)^{1/2},  L_NtD = (1/ik) (I + X)^{-1/2},  X = Delta_Gamma / k_eps^2
@@ -14,9 +14,14 @@
 //   C_0 = e^{i theta/2} [1 + sum_j a_j (e^{-i theta} - 1)/(1 + b_j (e^{-i theta} - 1))],
 //   A_j = e^{-i theta/2} a_j / (1 + b_j (e^{-i theta} - 1))^2,
 //   B_j = e^{-i theta} b_j / (1 + b_j (e^{-i theta} - 1)).
+// Applied in partial-fraction form: with
+// M^{-1} S (M - beta S)^{-1} = [(M - beta S)^{-1} - M^{-1}] / beta,
+//   R(X_h) u = C_0' u - sum_j (A_j / B_j) (M - (B_j/k_eps^2) S)^{-1} M u,
+//   C_0' = C_0 + sum_j A_j / B_j,
+// so one application needs two batched solve stages and no stiffness products.
 // All N_p + 2 systems (N_p shifts, M - S/k_eps^2, M) share the vertex-graph
 // pattern, one ordering and one symbolic factorisation; each is factorised
-// once (complex-symmetric LDL^T) and kept on the device (Sec. 2.6: a sparse
+// once (complex-symmetric LDL^T) and kept on the device (Sec. 2.7: a sparse
 // factorisation computed once and reused every iteration).
 #include <cmath>
 #include <complex>
@@ -31,13 +36,14 @@ void OsrcDeleter::operator()(OsrcState *p) const { delete p; }
 void OsrcSymDeleter::operator()(OsrcSymbolicState *p) const { delete p; }
 
 int64_t OsrcSymbolicState::bytes() const {
-    return gptr_d.bytes() + gcol_d.bytes() + perm_d.bytes() + Rp_d.bytes() + Rj_d.bytes() +
-           Lp_d.bytes() + Li_d.bytes() + fptr_d.bytes() + frow_d.bytes() + bptr_d.bytes() +
-           brow_d.bytes() + Mv_d.bytes() + Sv_d.bytes();
+    return gptr_d.bytes() + gcol_d.bytes() + perm_d.bytes() + Rj_d.bytes() + Li_d.bytes() +
+           bstart_d.bytes() + lbptr_d.bytes() + lblk_d.bytes() + lptr_d.bytes() + lrow_d.bytes() +
+           frange_d.bytes() +
+           brange_d.bytes() + doff_d.bytes() + Mv_d.bytes() + Sv_d.bytes();
 }
 int64_t OsrcState::bytes() const {
-    return cvert.bytes() + Dinv.bytes() + Lcsr.bytes() + Lcsc.bytes() + work.bytes() +
-           sbuf.bytes() + tmp.bytes() + wbuf.bytes();
+    return cvert.bytes() + Dinv.bytes() + Lcsr.bytes() + Lcsc.bytes() + invL.bytes() +
+           invLT.bytes() + work.bytes() + sbuf.bytes() + tmp.bytes() + wbuf.bytes();
 }
 int64_t osrc_bytes(const OsrcState &st) { return st.bytes(); }
 int64_t osrc_sym_bytes(const OsrcSymbolicState &st) { return st.bytes(); }
@@ -85,22 +91,49 @@ OsrcSymbolicState &symbolic(bem_mesh *m) {
                 st->Sv[e] += ar * (ca[0] * cb[0] + ca[1] * cb[1] + ca[2] * cb[2]);
             }
     }
-    std::vector<int32_t> perm = nested_dissection(n, st->gptr, st->gcol, m->P, m->vobj);
-    st->sym = ldl_symbolic(n, st->gptr, st->gcol, perm);
+    const NdOrder nd = nested_dissection(n, st->gptr, st->gcol, m->P, m->vobj);
+    st->sym = ldl_symbolic(n, st->gptr, st->gcol, nd);
     const LdlSymbolic &S = st->sym;
+    if (!S.blocks_ok) fail(BEM_E_UNSUPPORTED, "dissection blocks violate the level order");
     st->gptr_d.upload(st->gptr);
     st->gcol_d.upload(st->gcol);
     st->Mv_d.upload(st->Mv);
     st->Sv_d.upload(st->Sv);
     st->perm_d.upload(S.perm);
-    st->Rp_d.upload(S.Rp);
     st->Rj_d.upload(S.Rj);
-    st->Lp_d.upload(S.Lp);
     st->Li_d.upload(S.Li);
-    st->fptr_d.upload(S.fptr);
-    st->frow_d.upload(S.frow);
-    st->bptr_d.upload(S.bptr);
-    st->brow_d.upload(S.brow);
+    // blocks per level, external entry ranges, dense offsets
+    const int nb = (int)S.bheight.size(), nl = (int)S.lptr.size() - 1;
+    for (int b = 0; b < nb; b++)
+        if (S.bstart[b + 1] - S.bstart[b] > LDL_MAX_BLOCK)
+            fail(BEM_E_UNSUPPORTED, "dissection block larger than the solve workgroup can hold");
+    std::vector<int32_t> lbptr(nl + 1, 0), lblk(nb);
+    for (int b = 0; b < nb; b++) lbptr[S.bheight[b] + 1]++;
+    for (int l = 0; l < nl; l++) lbptr[l + 1] += lbptr[l];
+    {
+        std::vector<int32_t> fill(lbptr.begin(), lbptr.end() - 1);
+        for (int b = 0; b < nb; b++) lblk[fill[S.bheight[b]]++] = b;
+    }
+    st->lbcount.assign(nl, 0);
+    st->lrcount.assign(nl, 0);
+    for (int l = 0; l < nl; l++) {
+        st->lbcount[l] = lbptr[l + 1] - lbptr[l];
+        st->lrcount[l] = S.lptr[l + 1] - S.lptr[l];
+    }
+    st->lptr_d.upload(S.lptr);
+    st->lrow_d.upload(S.lrow);
+    std::vector<int2> fr(n), br(n);
+    for (int j = 0; j < n; j++) {
+        fr[j] = make_int2(S.Rp[j], S.fext[j]);
+        br[j] = make_int2(S.bext[j], S.Lp[j + 1]);
+    }
+    std::vector<int64_t> doff(S.doff.begin(), S.doff.end() - 1);
+    st->bstart_d.upload(S.bstart);
+    st->lbptr_d.upload(lbptr);
+    st->lblk_d.upload(lblk);
+    st->frange_d.upload(fr);
+    st->brange_d.upload(br);
+    st->doff_d.upload(doff);
     m->osrc_sym = std::move(st);
     return *m->osrc_sym;
 }
@@ -109,20 +142,26 @@ LdlDev ldl_view(const OsrcSymbolicState &sy, const OsrcState &st) {
     LdlDev L;
     L.n = sy.n;
     L.nnz = sy.sym.nnzL();
+    L.ndense = sy.sym.ndense;
     L.perm = sy.perm_d.p;
-    L.Rp = sy.Rp_d.p;
     L.Rj = sy.Rj_d.p;
-    L.Lp = sy.Lp_d.p;
     L.Li = sy.Li_d.p;
-    L.fptr = sy.fptr_d.p;
-    L.frow = sy.frow_d.p;
-    L.bptr = sy.bptr_d.p;
-    L.brow = sy.brow_d.p;
-    L.nfl = (int)sy.sym.fptr.size() - 1;
-    L.nbl = (int)sy.sym.bptr.size() - 1;
+    L.nlev = (int)sy.lbcount.size();
+    L.frange = sy.frange_d.p;
+    L.brange = sy.brange_d.p;
+    L.bstart = sy.bstart_d.p;
+    L.doff = sy.doff_d.p;
+    L.lbptr = sy.lbptr_d.p;
+    L.lblk = sy.lblk_d.p;
+    L.lbcount = sy.lbcount.data();
+    L.lptr = sy.lptr_d.p;
+    L.lrow = sy.lrow_d.p;
+    L.lrcount = sy.lrcount.data();
     L.Dinv = st.Dinv.p;
     L.Lcsr = st.Lcsr.p;
     L.Lcsc = st.Lcsc.p;
+    L.invL = st.invL.p;
+    L.invLT = st.invLT.p;
     return L;
 }
 
@@ -159,6 +198,14 @@ OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
     st->pc.np = np;
     st->pc.C0 = d2(C0);
     for (int j = 0; j < np; j++) st->pc.A[j] = d2(A[j]);
+    // partial-fraction coefficients: C_0' = C_0 + sum A_j/B_j, c_j = A_j/B_j
+    cdd C0p = C0;
+    st->pf.np = np;
+    for (int j = 0; j < np; j++) {
+        C0p += A[j] / B[j];
+        st->pf.A[j] = d2(A[j] / B[j]);
+    }
+    st->pf.C0 = d2(C0p);
     st->B.resize(np);
     for (int j = 0; j < np; j++) st->B[j] = d2(B[j]);
     // 1/k_eps^2 per vertex (object)
@@ -175,7 +222,7 @@ OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
     st->nfactors = nf;
     const LdlSymbolic &S = sy.sym;
     const int64_t nnz = S.nnzL();
-    std::vector<std::vector<cd>> Ds(nf), Ls(nf);
+    std::vector<std::vector<cd>> Ds(nf), Ls(nf), Is(nf), ITs(nf);
     std::vector<int> ok(nf, 0);
     auto factor = [&](int f) {
         // beta of system f: B_j (shifts), 1 (M - S/k_eps^2), 0 (M); times c_i
@@ -187,6 +234,7 @@ OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
                 vals[e2] = sy.Mv[e2] - beta * ci * sy.Sv[e2];
         }
         ok[f] = ldl_numeric(S, vals, Ds[f], Ls[f]) ? 1 : 0;
+        if (ok[f]) ldl_block_inverses(S, Ls[f], Is[f], ITs[f]);
     };
     {
         std::vector<std::thread> th;
@@ -195,18 +243,26 @@ OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
     }
     for (int f = 0; f < nf; f++)
         if (!ok[f]) fail(BEM_E_NAN, "zero pivot in OSRC factorisation " + std::to_string(f));
+    const int64_t nd = S.ndense;
     std::vector<double2> Dinv((size_t)nf * n), Lc((size_t)nf * nnz), Lr((size_t)nf * nnz);
+    std::vector<double2> iL((size_t)nf * nd), iLT((size_t)nf * nd);
     for (int f = 0; f < nf; f++) {
         for (int i = 0; i < n; i++) Dinv[(size_t)f * n + i] = d2(1.0 / Ds[f][i]);
         for (int64_t p = 0; p < nnz; p++) Lc[(size_t)f * nnz + p] = d2(Ls[f][p]);
         for (int64_t p = 0; p < nnz; p++) Lr[(size_t)f * nnz + p] = d2(Ls[f][S.Rmap[p]]);
+        for (int64_t p = 0; p < nd; p++) {
+            iL[(size_t)f * nd + p] = d2(Is[f][p]);
+            iLT[(size_t)f * nd + p] = d2(ITs[f][p]);
+        }
     }
     st->Dinv.upload(Dinv);
     st->Lcsc.upload(Lc);
     st->Lcsr.upload(Lr);
-    st->work.alloc((size_t)(np + 1) * n);
+    st->invL.upload(iL);
+    st->invLT.upload(iLT);
+    st->work.alloc((size_t)(np + 2) * n);
     st->sbuf.alloc((size_t)np * n);
-    st->tmp.alloc(4 * (size_t)n);
+    st->tmp.alloc(3 * (size_t)n);
     st->wbuf.alloc(2 * (size_t)n);
     (void)s;
     if (m->osrc_cache.size() >= 4) m->osrc_cache.erase(m->osrc_cache.begin());
@@ -224,30 +280,25 @@ void osrc_apply_from_weak(bem_mesh *m, OsrcState &st, const double2 *yw, double2
     const double2 one = make_double2(1.0, 0.0);
     const double2 *y1 = yw, *y2 = yw + n;
     double2 *z1 = z, *z2 = z + n;
-    double2 *v = st.tmp.p, *w1 = st.tmp.p + n, *m2 = st.tmp.p + 2 * n, *w2 = st.tmp.p + 3 * n;
+    double2 *u1 = st.tmp.p, *v = st.tmp.p + n, *m2 = st.tmp.p + 2 * n;
     Timer tm("osrc_apply", s);
-    // stage A: DtN shifted solves on y1; NtD (M - S/k_eps^2)^{-1} on y2
+    // stage 1: shifted solves and M^{-1} on y1 (DtN); (M - S/k_eps^2)^{-1} on y2 (NtD)
     TaskList ta{};
     for (int j = 0; j < np; j++)
         ta.t[j] = SolveTask{j, y1, st.sbuf.p + (size_t)j * n, one, st.work.p + (size_t)j * n};
-    ta.t[np] = SolveTask{np, y2, v, one, st.work.p + (size_t)np * n};
-    launch_ldl_solve(L, ta, np + 1, s);
-    launch_pade_combine(n, sy.gptr_d.p, sy.gcol_d.p, sy.Sv_d.p, st.cvert.p, st.pc, y1, st.sbuf.p,
-                        n, w1, s);
+    ta.t[np] = SolveTask{np + 1, y1, u1, one, st.work.p + (size_t)np * n};
+    ta.t[np + 1] = SolveTask{np, y2, v, one, st.work.p + (size_t)(np + 1) * n};
+    launch_ldl_solve(L, ta, np + 2, s);
+    // z1 = ik (C_0' M^{-1} y1 - sum_j (A_j/B_j) s_j);  m2 = M v
+    launch_pade_sum(n, st.pf, d2(ik), u1, st.sbuf.p, n, z1, s);
     launch_spmv_real(n, 1, sy.gptr_d.p, sy.gcol_d.p, sy.Mv_d.p, v, m2, s);
-    // stage B: DtN mass solve (times ik); NtD shifted solves on M v
+    // stage 2: shifted solves on M v (NtD)
     TaskList tb{};
-    tb.t[0] = SolveTask{np + 1, w1, z1, d2(ik), st.work.p};
     for (int j = 0; j < np; j++)
-        tb.t[1 + j] =
-            SolveTask{j, m2, st.sbuf.p + (size_t)j * n, one, st.work.p + (size_t)(1 + j) * n};
-    launch_ldl_solve(L, tb, np + 1, s);
-    launch_pade_combine(n, sy.gptr_d.p, sy.gcol_d.p, sy.Sv_d.p, st.cvert.p, st.pc, m2, st.sbuf.p,
-                        n, w2, s);
-    // stage C: NtD mass solve (times 1/ik)
-    TaskList tc{};
-    tc.t[0] = SolveTask{np + 1, w2, z2, d2(1.0 / ik), st.work.p};
-    launch_ldl_solve(L, tc, 1, s);
+        tb.t[j] = SolveTask{j, m2, st.sbuf.p + (size_t)j * n, one, st.work.p + (size_t)j * n};
+    launch_ldl_solve(L, tb, np, s);
+    // z2 = (1/ik) (C_0' v - sum_j (A_j/B_j) s'_j)
+    launch_pade_sum(n, st.pf, d2(1.0 / ik), v, st.sbuf.p, n, z2, s);
 }
 
 void osrc_apply_strong(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y,
@@ -263,7 +314,7 @@ void osrc_mass_solve(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y, i
     const int n = sy.n;
     const LdlDev L = ldl_view(sy, st);
     TaskList t{};
-    int nb = std::min(nblocks, st.np + 1);
+    int nb = std::min(nblocks, st.np + 2);
     for (int b0 = 0; b0 < nblocks; b0 += nb) {
         int cnt = std::min(nb, nblocks - b0);
         for (int b = 0; b < cnt; b++)

@@ -14,18 +14,33 @@ struct PadeCoef {
     double2 A[PADE_MAX];
 };
 
+// Largest dissection block (rows) a level workgroup can hold in LDS.
+constexpr int LDL_MAX_BLOCK = 4096;
+
 // Device view of the shared LDL^T structure plus the numeric factors.
 struct LdlDev {
     int n;
-    int64_t nnz;            // strict lower entries of L
-    const int32_t *perm;    // perm[new] = old
-    const int32_t *Rp, *Rj; // CSR of L (forward sweep)
-    const int32_t *Lp, *Li; // CSC of L (backward sweep with L^T)
-    const int32_t *fptr, *frow, *bptr, *brow;
-    int nfl, nbl;
-    const double2 *Dinv;    // [factors][n]
-    const double2 *Lcsr;    // [factors][nnz]
-    const double2 *Lcsc;    // [factors][nnz]
+    int64_t nnz;              // strict lower entries of L
+    int64_t ndense;           // entries of the dense block inverses
+    const int32_t *perm;      // perm[new] = old
+    const int32_t *Rj;        // CSR column indices of L (forward sweep)
+    const int32_t *Li;        // CSC row indices of L (backward sweep with L^T)
+    const int2 *frange;       // row j: external CSR entries [x, y)
+    const int2 *brange;       // column j: external CSC entries [x, y)
+    const int32_t *bstart;    // block b: rows [bstart[b], bstart[b+1])
+    const int64_t *doff;      // block b: dense inverse at doff[b] (w x w, row-major)
+    int nlev;                 // levels of the dissection tree
+    const int32_t *lbptr;     // level l: blocks lblk[lbptr[l] .. lbptr[l+1])
+    const int32_t *lblk;
+    const int32_t *lbcount;   // host copy: blocks per level
+    const int32_t *lptr;      // level l: rows lrow[lptr[l] .. lptr[l+1])
+    const int32_t *lrow;
+    const int32_t *lrcount;   // host copy: rows per level
+    const double2 *Dinv;      // [factors][n]
+    const double2 *Lcsr;      // [factors][nnz]
+    const double2 *Lcsc;      // [factors][nnz]
+    const double2 *invL;      // [factors][ndense]
+    const double2 *invLT;     // [factors][ndense]
 };
 
 // One system solve: out = scale * A_factor^{-1} in (vectors of length n).
@@ -44,8 +59,10 @@ struct OsrcSymbolicState {
     std::vector<int32_t> gptr, gcol;
     std::vector<double> Mv, Sv;
     LdlSymbolic sym;
-    DevBuf<int32_t> gptr_d, gcol_d, perm_d, Rp_d, Rj_d, Lp_d, Li_d, fptr_d, frow_d, bptr_d,
-        brow_d;
+    DevBuf<int32_t> gptr_d, gcol_d, perm_d, Rj_d, Li_d, bstart_d, lbptr_d, lblk_d, lptr_d, lrow_d;
+    DevBuf<int2> frange_d, brange_d;
+    DevBuf<int64_t> doff_d;
+    std::vector<int32_t> lbcount, lrcount;   // blocks and rows per level (host)
     DevBuf<double> Mv_d, Sv_d;
     int64_t bytes() const;
 };
@@ -53,27 +70,28 @@ struct OsrcSymbolicState {
 struct OsrcState {
     int np = 0;
     double2 k{0, 0};
-    PadeCoef pc{};
+    PadeCoef pc{};               // C_0, A_j of the Pade approximant
+    PadeCoef pf{};               // partial fractions: C_0', A_j / B_j
     std::vector<double2> B;      // Pade B_j
     int nfactors = 0;            // np shifts, (M - S/k_eps^2), M
     DevBuf<double2> cvert;       // 1/k_eps^2 of each vertex's object
-    DevBuf<double2> Dinv, Lcsr, Lcsc;
-    DevBuf<double2> work;        // (np + 1) x n solve work vectors
+    DevBuf<double2> Dinv, Lcsr, Lcsc, invL, invLT;
+    DevBuf<double2> work;        // (np + 2) x n solve work vectors
     DevBuf<double2> sbuf;        // np x n shifted-solve outputs
-    DevBuf<double2> tmp;         // 4 x n
+    DevBuf<double2> tmp;         // 3 x n
     DevBuf<double2> wbuf;        // 2 x n weak vectors (strong-form entry)
     int64_t bytes() const;
 };
 
-// Task list passed by value as a kernel argument (at most PADE_MAX + 1 systems).
+// Task list passed by value as a kernel argument (at most PADE_MAX + 2 systems).
 struct TaskList {
-    SolveTask t[PADE_MAX + 1];
+    SolveTask t[PADE_MAX + 2];
 };
 
 void launch_ldl_solve(const LdlDev &L, const TaskList &tasks, int ntasks, hipStream_t s);
-void launch_pade_combine(int n, const int32_t *gptr, const int32_t *gcol, const double *Sv,
-                         const double2 *cvert, const PadeCoef &pc, const double2 *in,
-                         const double2 *sv, int64_t sstride, double2 *out, hipStream_t s);
+// out = alpha (C0 u - sum_j A_j s_j)   (elementwise)
+void launch_pade_sum(int n, const PadeCoef &pc, double2 alpha, const double2 *u,
+                     const double2 *sv, int64_t sstride, double2 *out, hipStream_t s);
 void launch_spmv_real(int n, int nblk, const int32_t *gptr, const int32_t *gcol,
                       const double *V, const double2 *in, double2 *out, hipStream_t s);
 

@@ -1,7 +1,6 @@
-// Device kernels of the OSRC preconditioner: batched level-scheduled sparse
-// LDL^T solves (one workgroup per shifted system and right-hand side, all
-// systems sharing one pattern) and the Pade combinations with the P1
-// stiffness matrix.
+// Device kernels of the OSRC preconditioner: batched block-LDL^T solves over
+// the nested-dissection tree (all shifted systems share one pattern) and the
+// elementwise Pade partial-fraction sums.
 #include "osrc_internal.h"
 
 namespace bem {
@@ -12,94 +11,92 @@ __device__ inline double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-constexpr int LDL_THREADS = 1024;
+constexpr int LVL_THREADS = 256;
 
-// y[j] -= sum_e val[e] * y[idx[e]] for every row j of one level.  Wide levels:
-// one thread per row; narrow levels (long separator rows): one wavefront per
-// row with a fixed-order butterfly reduction.
-__device__ inline void sweep_level(double2 *__restrict__ y, const int32_t *__restrict__ rows,
-                                   int beg, int end, const int32_t *__restrict__ ptr,
-                                   const int32_t *__restrict__ idx,
-                                   const double2 *__restrict__ val) {
-    const int tid = threadIdx.x;
-    if (end - beg >= 64) {
-        for (int r = beg + tid; r < end; r += LDL_THREADS) {
-            const int j = rows[r];
-            double2 acc = y[j];
-            for (int e = ptr[j]; e < ptr[j + 1]; e++) {
-                const double2 p = cmul(val[e], y[idx[e]]);
-                acc.x -= p.x;
-                acc.y -= p.y;
-            }
-            y[j] = acc;
-        }
-    } else {
-        const int wave = tid >> 6, lane = tid & 63;
-        for (int r = beg + wave; r < end; r += LDL_THREADS / 64) {
-            const int j = rows[r];
-            double sx = 0.0, sy = 0.0;
-            for (int e = ptr[j] + lane; e < ptr[j + 1]; e += 64) {
-                const double2 p = cmul(val[e], y[idx[e]]);
-                sx += p.x;
-                sy += p.y;
-            }
-            for (int o = 32; o > 0; o >>= 1) {
-                sx += __shfl_xor(sx, o, 64);
-                sy += __shfl_xor(sy, o, 64);
-            }
-            if (lane == 0) {
-                double2 v = y[j];
-                y[j] = make_double2(v.x - sx, v.y - sy);
-            }
-        }
-    }
-}
+// Block-LDL^T solve over the nested-dissection tree, one pair of launches per
+// level.  Rows of a dissection block only reference rows of the same block
+// or of its dissection descendants (forward) / ancestors (backward), which
+// earlier launches have finished.
+//
+// forward, block B = rows [s0, s0 + w):
+//   y_j = in[perm[j]] - sum_{k < s0} L_jk y_k         (ldl_ext_kernel)
+//   y_B = inv(L_BB) y_B                               (ldl_dense_kernel)
+// backward (levels from the top down):
+//   y_j = Dinv_j y_j - sum_{i >= s0 + w} L_ij y_i      (ldl_ext_kernel)
+//   y_B = inv(L_BB)^T y_B;  out[perm[j]] = scale y_j  (ldl_dense_kernel)
 
-__global__ __launch_bounds__(LDL_THREADS) void ldl_solve_kernel(LdlDev L, TaskList tasks) {
-    const SolveTask t = tasks.t[blockIdx.x];
-    const int n = L.n;
-    const double2 *Dinv = L.Dinv + (int64_t)t.factor * n;
-    const double2 *Lr = L.Lcsr + (int64_t)t.factor * L.nnz;
-    const double2 *Lc = L.Lcsc + (int64_t)t.factor * L.nnz;
+// External update: one wavefront per row of the level (fixed-order
+// butterfly reduction), grid (ceil(rows / 4), tasks).  In place: a row only
+// reads rows of other (finished) blocks.
+template <bool FWD>
+__global__ __launch_bounds__(256) void ldl_ext_kernel(LdlDev L, TaskList tasks, int lev) {
+    const SolveTask t = tasks.t[blockIdx.y];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = L.lptr[lev] + blockIdx.x * 4 + wave;
+    if (r >= L.lptr[lev + 1]) return;
+    const int j = L.lrow[r];
     double2 *y = t.work;
-    for (int i = threadIdx.x; i < n; i += LDL_THREADS) y[i] = t.in[L.perm[i]];
-    __syncthreads();
-    for (int l = 0; l < L.nfl; l++) {
-        sweep_level(y, L.frow, L.fptr[l], L.fptr[l + 1], L.Rp, L.Rj, Lr);
-        __syncthreads();
+    const double2 *val = (FWD ? L.Lcsr : L.Lcsc) + (int64_t)t.factor * L.nnz;
+    const int32_t *idx = FWD ? L.Rj : L.Li;
+    const int2 rg = (FWD ? L.frange : L.brange)[j];
+    double sx = 0.0, sy = 0.0;
+    for (int e = rg.x + lane; e < rg.y; e += 64) {
+        const double2 p = cmul(val[e], y[idx[e]]);
+        sx += p.x;
+        sy += p.y;
     }
-    for (int i = threadIdx.x; i < n; i += LDL_THREADS) y[i] = cmul(y[i], Dinv[i]);
-    __syncthreads();
-    for (int l = 0; l < L.nbl; l++) {
-        sweep_level(y, L.brow, L.bptr[l], L.bptr[l + 1], L.Lp, L.Li, Lc);
-        __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) {
+        sx += __shfl_xor(sx, o, 64);
+        sy += __shfl_xor(sy, o, 64);
     }
-    for (int i = threadIdx.x; i < n; i += LDL_THREADS) t.out[L.perm[i]] = cmul(t.scale, y[i]);
+    if (lane == 0) {
+        const double2 base =
+            FWD ? t.in[L.perm[j]] : cmul(L.Dinv[(int64_t)t.factor * L.n + j], y[j]);
+        y[j] = make_double2(base.x - sx, base.y - sy);
+    }
 }
 
-// out[i] = C0 in[i] - c_i sum_e S_ie sum_j A_j s_j[col_e]
-__global__ __launch_bounds__(256) void pade_combine_kernel(
-    int n, const int32_t *__restrict__ gptr, const int32_t *__restrict__ gcol,
-    const double *__restrict__ Sv, const double2 *__restrict__ cvert, PadeCoef pc,
-    const double2 *__restrict__ in, const double2 *__restrict__ sv, int64_t sstride,
-    double2 *__restrict__ out) {
+// Dense block inverse: workgroup (block, task).  Consecutive threads (rows)
+// read consecutive addresses: invLT[c][r] forward, invL[c][r] backward.
+template <bool FWD>
+__global__ __launch_bounds__(LVL_THREADS) void ldl_dense_kernel(LdlDev L, TaskList tasks,
+                                                                int lev) {
+    __shared__ double2 tb[LDL_MAX_BLOCK];
+    const SolveTask t = tasks.t[blockIdx.y];
+    const int b = L.lblk[L.lbptr[lev] + blockIdx.x];
+    const int s0 = L.bstart[b], w = L.bstart[b + 1] - s0;
+    double2 *y = t.work;
+    const double2 *dense = (FWD ? L.invLT : L.invL) + (int64_t)t.factor * L.ndense + L.doff[b];
+    for (int r = threadIdx.x; r < w; r += LVL_THREADS) tb[r] = y[s0 + r];
+    __syncthreads();
+    for (int r = threadIdx.x; r < w; r += LVL_THREADS) {
+        double2 acc = make_double2(0.0, 0.0);
+        const int c0 = FWD ? 0 : r, c1 = FWD ? r + 1 : w;
+        for (int c = c0; c < c1; c++) {
+            const double2 p = cmul(dense[(int64_t)c * w + r], tb[c]);
+            acc.x += p.x;
+            acc.y += p.y;
+        }
+        y[s0 + r] = acc;
+        if (!FWD) t.out[L.perm[s0 + r]] = cmul(t.scale, acc);
+    }
+}
+
+// out[i] = alpha (C0 u[i] - sum_j A_j s_j[i])
+__global__ __launch_bounds__(256) void pade_sum_kernel(int n, PadeCoef pc, double2 alpha,
+                                                       const double2 *__restrict__ u,
+                                                       const double2 *__restrict__ sv,
+                                                       int64_t sstride,
+                                                       double2 *__restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int e = gptr[i]; e < gptr[i + 1]; e++) {
-        const int c = gcol[e];
-        double2 t = make_double2(0.0, 0.0);
-        for (int j = 0; j < pc.np; j++) {
-            const double2 p = cmul(pc.A[j], sv[j * sstride + c]);
-            t.x += p.x;
-            t.y += p.y;
-        }
-        acc.x += Sv[e] * t.x;
-        acc.y += Sv[e] * t.y;
+    double2 acc = cmul(pc.C0, u[i]);
+    for (int j = 0; j < pc.np; j++) {
+        const double2 p = cmul(pc.A[j], sv[j * sstride + i]);
+        acc.x -= p.x;
+        acc.y -= p.y;
     }
-    const double2 w = cmul(cvert[i], acc);
-    const double2 a = cmul(pc.C0, in[i]);
-    out[i] = make_double2(a.x - w.x, a.y - w.y);
+    out[i] = cmul(alpha, acc);
 }
 
 // out[i] = sum_e V_e in[col_e]  (real sparse matrix, complex vector), for
@@ -126,15 +123,27 @@ __global__ __launch_bounds__(256) void spmv_real_kernel(int n, int nblk,
 }   // namespace
 
 void launch_ldl_solve(const LdlDev &L, const TaskList &tasks, int ntasks, hipStream_t s) {
-    hipLaunchKernelGGL(ldl_solve_kernel, dim3(ntasks), dim3(LDL_THREADS), 0, s, L, tasks);
-    BEM_LAUNCH_CHECK();
+    Timer tm("osrc_ldl_solve", s);
+    for (int l = 0; l < L.nlev; l++) {
+        hipLaunchKernelGGL(ldl_ext_kernel<true>, dim3((L.lrcount[l] + 3) / 4, ntasks), dim3(256),
+                           0, s, L, tasks, l);
+        hipLaunchKernelGGL(ldl_dense_kernel<true>, dim3(L.lbcount[l], ntasks), dim3(LVL_THREADS),
+                           0, s, L, tasks, l);
+        BEM_LAUNCH_CHECK();
+    }
+    for (int l = L.nlev - 1; l >= 0; l--) {
+        hipLaunchKernelGGL(ldl_ext_kernel<false>, dim3((L.lrcount[l] + 3) / 4, ntasks), dim3(256),
+                           0, s, L, tasks, l);
+        hipLaunchKernelGGL(ldl_dense_kernel<false>, dim3(L.lbcount[l], ntasks), dim3(LVL_THREADS),
+                           0, s, L, tasks, l);
+        BEM_LAUNCH_CHECK();
+    }
 }
 
-void launch_pade_combine(int n, const int32_t *gptr, const int32_t *gcol, const double *Sv,
-                         const double2 *cvert, const PadeCoef &pc, const double2 *in,
-                         const double2 *sv, int64_t sstride, double2 *out, hipStream_t s) {
-    hipLaunchKernelGGL(pade_combine_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, gptr,
-                       gcol, Sv, cvert, pc, in, sv, sstride, out);
+void launch_pade_sum(int n, const PadeCoef &pc, double2 alpha, const double2 *u,
+                     const double2 *sv, int64_t sstride, double2 *out, hipStream_t s) {
+    hipLaunchKernelGGL(pade_sum_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, pc, alpha, u,
+                       sv, sstride, out);
     BEM_LAUNCH_CHECK();
 }
 

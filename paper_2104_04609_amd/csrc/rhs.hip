@@ -1,6 +1,6 @@
 // Plane-wave right-hand side and far-field pattern (FP64).
 //
-// Right-hand side of the permuted PMCHWT system (Sec. 2.6): the Dirichlet and
+// Right-hand side of the permuted PMCHWT system (Sec. 2.7): the Dirichlet and
 // Neumann traces of u_inc = exp(i k d.x) (unit-amplitude plane wave, Sec. 2.1)
 // tested with P1 functions, 6-point rule per triangle:
 //   f_D,i = int u_inc phi_i,   f_N,i = int i k (d.n) u_inc phi_i.

@@ -1,4 +1,4 @@
-// OSRC-preconditioned permuted PMCHWT solve (Sec. 2.6), strong form (mass
+// OSRC-preconditioned permuted PMCHWT solve (Sec. 2.7), strong form (mass
 // preconditioning, Sec. 2.4), unrestarted GMRES from x_0 = 0 (Sec. 3.1):
 //
 //   P x = b,  P = L M^{-1} B,  b = L M^{-1} f,  L = diag(L_DtN, L_NtD) per object.
@@ -148,7 +148,7 @@ bool gmres(Op &op, int prec, const double2 *b, double2 *x, int64_t n2, double to
 }
 
 double2 damped(double2 k, double R) {
-    // k_eps = k (1 + 0.4 i (k R)^{-2/3}), principal branch (Sec. 2.5)
+    // k_eps = k (1 + 0.4 i (k R)^{-2/3}), principal branch (Sec. 2.6)
     cdd kk(k.x, k.y);
     cdd ke = kk * (1.0 + cdd(0, 0.4) * std::pow(kk * R, -2.0 / 3.0));
     return make_double2(ke.real(), ke.imag());

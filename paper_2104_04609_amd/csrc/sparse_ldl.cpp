@@ -10,12 +10,19 @@ namespace bem {
 
 namespace {
 
-void dissect(std::vector<int32_t> &vs, const std::vector<int32_t> &ptr,
-             const std::vector<int32_t> &col, const std::vector<double> &xyz,
-             std::vector<int32_t> &side, std::vector<int32_t> &order, int leaf) {
+// Returns the height of the subtree rooted at this call (-1 if empty).
+int dissect(std::vector<int32_t> &vs, const std::vector<int32_t> &ptr,
+            const std::vector<int32_t> &col, const std::vector<double> &xyz,
+            std::vector<int32_t> &side, NdOrder &nd, int leaf) {
+    if (vs.empty()) return -1;
+    auto emit = [&](const std::vector<int32_t> &blk, int h) {
+        nd.bstart.push_back((int32_t)nd.order.size());
+        nd.bheight.push_back(h);
+        nd.order.insert(nd.order.end(), blk.begin(), blk.end());
+    };
     if ((int)vs.size() <= leaf) {
-        order.insert(order.end(), vs.begin(), vs.end());
-        return;
+        emit(vs, 0);
+        return 0;
     }
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int v : vs)
@@ -46,41 +53,46 @@ void dissect(std::vector<int32_t> &vs, const std::vector<int32_t> &ptr,
     }
     for (int v : vs) side[v] = 0;
     if (A.empty() || B.empty()) {   // cannot split further (degenerate geometry)
-        order.insert(order.end(), vs.begin(), vs.end());
-        return;
+        emit(vs, 0);
+        return 0;
     }
     std::sort(A.begin(), A.end());
     std::sort(B.begin(), B.end());
     std::sort(S.begin(), S.end());
-    dissect(A, ptr, col, xyz, side, order, leaf);
-    dissect(B, ptr, col, xyz, side, order, leaf);
-    order.insert(order.end(), S.begin(), S.end());
+    const int ha = dissect(A, ptr, col, xyz, side, nd, leaf);
+    const int hb = dissect(B, ptr, col, xyz, side, nd, leaf);
+    const int h = std::max(ha, hb) + 1;
+    if (S.empty()) return h - 1;
+    emit(S, h);
+    return h;
 }
 
 }   // namespace
 
-std::vector<int32_t> nested_dissection(int n, const std::vector<int32_t> &ptr,
-                                       const std::vector<int32_t> &col,
-                                       const std::vector<double> &xyz,
-                                       const std::vector<int32_t> &group, int leaf) {
-    std::vector<int32_t> order, side(n, 0);
-    order.reserve(n);
+NdOrder nested_dissection(int n, const std::vector<int32_t> &ptr, const std::vector<int32_t> &col,
+                          const std::vector<double> &xyz, const std::vector<int32_t> &group,
+                          int leaf) {
+    NdOrder nd;
+    std::vector<int32_t> side(n, 0);
+    nd.order.reserve(n);
     int ng = 0;
     for (int v = 0; v < n; v++) ng = std::max(ng, group[v] + 1);
     for (int g = 0; g < ng; g++) {
         std::vector<int32_t> vs;
         for (int v = 0; v < n; v++)
             if (group[v] == g) vs.push_back(v);
-        dissect(vs, ptr, col, xyz, side, order, leaf);
+        dissect(vs, ptr, col, xyz, side, nd, leaf);
     }
-    return order;
+    nd.bstart.push_back((int32_t)nd.order.size());
+    return nd;
 }
 
 LdlSymbolic ldl_symbolic(int n, const std::vector<int32_t> &ptr,
-                         const std::vector<int32_t> &col, const std::vector<int32_t> &perm) {
+                         const std::vector<int32_t> &col, const NdOrder &nd) {
     LdlSymbolic S;
     S.n = n;
-    S.perm = perm;
+    S.perm = nd.order;
+    const std::vector<int32_t> &perm = nd.order;
     S.iperm.assign(n, 0);
     for (int i = 0; i < n; i++) S.iperm[perm[i]] = i;
 
@@ -174,24 +186,44 @@ LdlSymbolic ldl_symbolic(int n, const std::vector<int32_t> &ptr,
                 fill[i]++;
             }
     }
-    // level schedules
-    std::vector<int32_t> h(n, 0), d(n, 0);
-    for (int j = 0; j < n; j++)
-        if (S.parent[j] >= 0) h[S.parent[j]] = std::max(h[S.parent[j]], h[j] + 1);
-    for (int j = n - 1; j >= 0; j--) d[j] = S.parent[j] >= 0 ? d[S.parent[j]] + 1 : 0;
-    auto schedule = [n](const std::vector<int32_t> &lev, std::vector<int32_t> &lp,
-                        std::vector<int32_t> &rows) {
-        int nl = 0;
-        for (int j = 0; j < n; j++) nl = std::max(nl, lev[j] + 1);
-        lp.assign(nl + 1, 0);
-        for (int j = 0; j < n; j++) lp[lev[j] + 1]++;
-        for (int l = 0; l < nl; l++) lp[l + 1] += lp[l];
-        rows.assign(n, 0);
-        std::vector<int32_t> fill(lp.begin(), lp.end() - 1);
-        for (int j = 0; j < n; j++) rows[fill[lev[j]]++] = j;
-    };
-    schedule(h, S.fptr, S.frow);
-    schedule(d, S.bptr, S.brow);
+    // dissection blocks, dense offsets, level schedule, external entry ranges
+    S.bstart = nd.bstart;
+    S.bheight = nd.bheight;
+    const int nb = (int)S.bheight.size();
+    S.blk.assign(n, 0);
+    S.doff.assign(nb + 1, 0);
+    int nl = 0;
+    for (int b = 0; b < nb; b++) {
+        const int w = S.bstart[b + 1] - S.bstart[b];
+        for (int r = S.bstart[b]; r < S.bstart[b + 1]; r++) S.blk[r] = b;
+        S.doff[b + 1] = S.doff[b] + (int64_t)w * w;
+        nl = std::max(nl, S.bheight[b] + 1);
+    }
+    S.ndense = S.doff[nb];
+    S.lptr.assign(nl + 1, 0);
+    for (int b = 0; b < nb; b++) S.lptr[S.bheight[b] + 1] += S.bstart[b + 1] - S.bstart[b];
+    for (int l = 0; l < nl; l++) S.lptr[l + 1] += S.lptr[l];
+    S.lrow.assign(n, 0);
+    {
+        std::vector<int32_t> fill(S.lptr.begin(), S.lptr.end() - 1);
+        for (int b = 0; b < nb; b++)
+            for (int r = S.bstart[b]; r < S.bstart[b + 1]; r++) S.lrow[fill[S.bheight[b]]++] = r;
+    }
+    S.fext.assign(n, 0);
+    S.bext.assign(n, 0);
+    for (int j = 0; j < n; j++) {
+        const int b0 = S.bstart[S.blk[j]], b1 = S.bstart[S.blk[j] + 1];
+        int e = S.Rp[j];
+        while (e < S.Rp[j + 1] && S.Rj[e] < b0) e++;
+        S.fext[j] = e;
+        int p = S.Lp[j];
+        while (p < S.Lp[j + 1] && S.Li[p] < b1) p++;
+        S.bext[j] = p;
+        // the level schedule needs every external entry to reference a block
+        // of smaller height (a dissection descendant)
+        for (int q = S.Rp[j]; q < e; q++)
+            if (S.bheight[S.blk[S.Rj[q]]] >= S.bheight[S.blk[j]]) S.blocks_ok = false;
+    }
     return S;
 }
 
@@ -236,6 +268,78 @@ bool ldl_numeric(const LdlSymbolic &S, const std::vector<cd> &vals, std::vector<
         }
     }
     return true;
+}
+
+void ldl_block_inverses(const LdlSymbolic &S, const std::vector<cd> &Lx, std::vector<cd> &invL,
+                        std::vector<cd> &invLT) {
+    invL.assign(S.ndense, cd(0));
+    invLT.assign(S.ndense, cd(0));
+    const int nb = (int)S.bheight.size();
+    std::vector<cd> Lb;
+    for (int b = 0; b < nb; b++) {
+        const int s0 = S.bstart[b], w = S.bstart[b + 1] - s0;
+        Lb.assign((size_t)w * w, cd(0));
+        for (int c = 0; c < w; c++) {
+            Lb[(size_t)c * w + c] = 1.0;
+            for (int p = S.Lp[s0 + c]; p < S.Lp[s0 + c + 1]; p++) {
+                const int i = S.Li[p] - s0;
+                if (i < w) Lb[(size_t)i * w + c] = Lx[p];
+            }
+        }
+        cd *X = &invL[S.doff[b]];
+        // X = Lb^{-1}: column by column, forward substitution
+        for (int c = 0; c < w; c++) {
+            X[(size_t)c * w + c] = 1.0;
+            for (int i = c + 1; i < w; i++) {
+                cd acc = 0.0;
+                for (int t = c; t < i; t++) acc += Lb[(size_t)i * w + t] * X[(size_t)t * w + c];
+                X[(size_t)i * w + c] = -acc;
+            }
+        }
+        cd *XT = &invLT[S.doff[b]];
+        for (int i = 0; i < w; i++)
+            for (int c = 0; c < w; c++) XT[(size_t)c * w + i] = X[(size_t)i * w + c];
+    }
+}
+
+void ldl_solve_blocks_host(const LdlSymbolic &S, const std::vector<cd> &D,
+                           const std::vector<cd> &Lx, const std::vector<cd> &invL,
+                           const std::vector<cd> &invLT, const std::vector<cd> &b,
+                           std::vector<cd> &x) {
+    const int n = S.n, nl = (int)S.lptr.size() - 1;
+    std::vector<cd> y(n), z(n);
+    for (int i = 0; i < n; i++) y[i] = b[S.perm[i]];
+    for (int l = 0; l < nl; l++) {
+        for (int r = S.lptr[l]; r < S.lptr[l + 1]; r++) {
+            const int j = S.lrow[r];
+            for (int e = S.Rp[j]; e < S.fext[j]; e++) y[j] -= Lx[S.Rmap[e]] * y[S.Rj[e]];
+        }
+        for (int r = S.lptr[l]; r < S.lptr[l + 1]; r++) {
+            const int i = S.lrow[r], bb = S.blk[i], s0 = S.bstart[bb],
+                      w = S.bstart[bb + 1] - s0;
+            cd acc = 0.0;
+            for (int t = 0; t <= i - s0; t++) acc += invL[S.doff[bb] + (i - s0) * w + t] * y[s0 + t];
+            z[i] = acc;
+        }
+        for (int r = S.lptr[l]; r < S.lptr[l + 1]; r++) y[S.lrow[r]] = z[S.lrow[r]];
+    }
+    for (int i = 0; i < n; i++) y[i] /= D[i];
+    for (int l = nl - 1; l >= 0; l--) {
+        for (int r = S.lptr[l]; r < S.lptr[l + 1]; r++) {
+            const int j = S.lrow[r];
+            for (int p = S.bext[j]; p < S.Lp[j + 1]; p++) y[j] -= Lx[p] * y[S.Li[p]];
+        }
+        for (int r = S.lptr[l]; r < S.lptr[l + 1]; r++) {
+            const int i = S.lrow[r], bb = S.blk[i], s0 = S.bstart[bb],
+                      w = S.bstart[bb + 1] - s0;
+            cd acc = 0.0;
+            for (int t = i - s0; t < w; t++) acc += invLT[S.doff[bb] + (i - s0) * w + t] * y[s0 + t];
+            z[i] = acc;
+        }
+        for (int r = S.lptr[l]; r < S.lptr[l + 1]; r++) y[S.lrow[r]] = z[S.lrow[r]];
+    }
+    x.assign(n, cd(0));
+    for (int i = 0; i < n; i++) x[S.perm[i]] = y[i];
 }
 
 void ldl_solve_host(const LdlSymbolic &S, const std::vector<cd> &D, const std::vector<cd> &Lx,

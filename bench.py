@@ -107,15 +107,30 @@ def main():
     if not args.no_solve:
         try:
             solve = {}
-            for prec in ("fp64", "fp32"):
+            # FP64 GMRES, FP32 matrix-free + refinement, FP32 assembled dense
+            # operator + refinement (assembly included in its time)
+            for name, prec, path in (("fp64", "fp64", 0), ("fp32", "fp32", 0),
+                                     ("fp32_dense", "fp32", 1)):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 sol, info, rc = P.pmchwt_solve(M, K_EXT, K_INT, RHO, [[0, 0, 1]], 1e-6,
-                                               precision=prec)
+                                               precision=prec, path=path)
                 torch.cuda.synchronize()
-                solve[prec] = {"seconds": time.perf_counter() - t0, "rc": rc, **info[0]}
+                solve[name] = {"seconds": time.perf_counter() - t0, "rc": rc, **info[0]}
             solve["speedup_fp32_refine_vs_fp64"] = (solve["fp64"]["seconds"] /
                                                     solve["fp32"]["seconds"])
+            solve["speedup_fp32_dense_refine_vs_fp64"] = (solve["fp64"]["seconds"] /
+                                                          solve["fp32_dense"]["seconds"])
+            # dense GEMV throughput (operator resident after the solve)
+            P.profile_enable(True)
+            for _ in range(5):
+                P.pmchwt_matvec(M, K_EXT, K_INT, RHO, x, y, precision="fp32_dense")
+            torch.cuda.synchronize()
+            gms, gn = P.profile_read("dense_gemv")
+            P.profile_enable(False)
+            gbytes = (2 * N) ** 2 * 8
+            solve["dense_gemv"] = {"ms": gms / gn, "GB_per_s": gbytes / (gms / gn * 1e-3) / 1e9,
+                                   "matrix_bytes": gbytes}
         except P.BemError as e:
             solve = {"error": str(e)}
 

@@ -46,9 +46,15 @@ enum {
     BEM_E_UNSUPPORTED = -6
 };
 
-/* Far-field (matrix-free pair kernel) precision.  The singular/near-field
- * corrections, OSRC and GMRES always run in FP64. */
-enum { BEM_FP64 = 0, BEM_FP32 = 1 };
+/* Precision/path of the separated-pair part of the operator.  The singular
+ * near field, OSRC and GMRES always run in FP64.
+ *   BEM_FP64        matrix-free pair kernel in FP64
+ *   BEM_FP32        matrix-free pair kernel in FP32
+ *   BEM_FP32_DENSE  assembled dense complex64 operator [2N][2N] (FP32 pair
+ *                   sums plus the FP64 near field rounded once), built on
+ *                   first use for a (k_ext, k_int, rho) and kept resident;
+ *                   needs 16 N^2 bytes of device memory (BEM_E_NOMEM else) */
+enum { BEM_FP64 = 0, BEM_FP32 = 1, BEM_FP32_DENSE = 2 };
 
 /*
  * Create the device state of a triangle surface mesh (Sec. 2.1: bounded
@@ -87,7 +93,7 @@ int bem_mesh_info(const bem_mesh *mesh, int64_t *n_vertices,
  * pair not sharing a vertex; Sauter-Schwab-type rules (4 Gauss points per
  * dimension) for coinciding, edge- and vertex-adjacent pairs.
  *   x, y       device, bem_c64 [n_rhs][2N]
- *   precision  BEM_FP64 or BEM_FP32 (pair kernel of separated triangles)
+ *   precision  BEM_FP64, BEM_FP32 or BEM_FP32_DENSE (see above)
  * The first call for a (k_ext, k_int, rho) builds and caches the near-field
  * operator on the device.  Errors: BEM_E_INVAL (rho <= 0, Im k < 0, k == 0,
  * n_rhs < 1, NULL pointers), BEM_E_NOMEM, BEM_E_DEVICE.
@@ -133,6 +139,9 @@ typedef struct {
                             residual inner_tol * tol * ||b|| (at most half of
                             the current outer residual); default 0.3 */
     int max_outer;       /* refinement steps cap, default 8 */
+    int path;            /* FP32 form inner operator: 0 matrix-free pair kernel,
+                            1 assembled dense complex64 operator, 2 dense when
+                            it fits in device memory (default) */
 } bem_solve_opts;
 
 typedef struct {

@@ -22,8 +22,9 @@ if not os.path.exists(LIB_PATH):
 
 lib = ctypes.CDLL(LIB_PATH)
 
-BEM_FP64, BEM_FP32 = 0, 1
-_PREC = {"fp64": BEM_FP64, "fp32": BEM_FP32, BEM_FP64: BEM_FP64, BEM_FP32: BEM_FP32}
+BEM_FP64, BEM_FP32, BEM_FP32_DENSE = 0, 1, 2
+_PREC = {"fp64": BEM_FP64, "fp32": BEM_FP32, "fp32_dense": BEM_FP32_DENSE,
+         BEM_FP64: BEM_FP64, BEM_FP32: BEM_FP32, BEM_FP32_DENSE: BEM_FP32_DENSE}
 ERRORS = {1: "BEM_W_NOT_CONVERGED", -1: "BEM_E_INVAL", -2: "BEM_E_BAD_MESH",
           -3: "BEM_E_NOMEM", -4: "BEM_E_DEVICE", -5: "BEM_E_NAN",
           -6: "BEM_E_UNSUPPORTED"}
@@ -42,7 +43,8 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("pade_terms", ctypes.c_int), ("theta", ctypes.c_double),
                 ("osrc_interior", ctypes.c_int), ("R", ctypes.c_double),
                 ("precision", ctypes.c_int), ("maxiter", ctypes.c_int),
-                ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int)]
+                ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
+                ("path", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

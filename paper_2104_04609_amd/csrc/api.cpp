@@ -59,6 +59,8 @@ int64_t bem_mesh::device_bytes() const {
                 nf_col.bytes() + nf_cptr.bytes() + nf_contrib.bytes() + ss_tab.bytes() +
                 dyn64.bytes() + dyn32.bytes() + partial.bytes() + trirows.bytes();
     for (const auto &kv : near_cache) b += kv.second->vals.bytes();
+    for (const auto &kv : dense_cache) b += kv.second->B.bytes();
+    b += xs32.bytes();
     for (const auto &kv : osrc_cache) b += bem::osrc_bytes(*kv.second);
     if (osrc_sym) b += bem::osrc_sym_bytes(*osrc_sym);
     return b;
@@ -139,12 +141,19 @@ int pmchwt_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho
     if (!x || !y) fail(BEM_E_INVAL, "x and y must be device pointers");
     if (x == y) fail(BEM_E_INVAL, "x and y must not alias");
     if (n_rhs < 1) fail(BEM_E_INVAL, "n_rhs must be >= 1");
-    if (precision != BEM_FP64 && precision != BEM_FP32) fail(BEM_E_INVAL, "bad precision");
+    if (precision != BEM_FP64 && precision != BEM_FP32 && precision != BEM_FP32_DENSE)
+        fail(BEM_E_INVAL, "bad precision");
     bem_mesh *m = const_cast<bem_mesh *>(mesh);
     hipStream_t s = (hipStream_t)hip_stream;
     double2 k0 = make_double2(k_ext.re, k_ext.im), k1 = make_double2(k_int.re, k_int.im);
     const bem::NearOperator &nf = bem::nearfield_get(m, k0, k1, rho, s);
     const int64_t n2 = 2 * m->N;
+    if (precision == BEM_FP32_DENSE) {
+        const bem::DenseOperator &op = bem::dense_get(m, k0, k1, rho, s);
+        for (int r = 0; r < n_rhs; r++)
+            bem::dense_gemv(op, (const double2 *)x + r * n2, (double2 *)y + r * n2, m->xs32, s);
+        return BEM_OK;
+    }
     for (int r = 0; r < n_rhs; r++)
         bem::farfield_apply(m, nf, k0, k1, rho, (const double2 *)x + r * n2,
                             (double2 *)y + r * n2, precision, s);

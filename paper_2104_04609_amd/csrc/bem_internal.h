@@ -110,6 +110,12 @@ struct NearOperator {
     DevBuf<double> vals;   // [4 blocks][nnz] complex (interleaved): B11 B12 B21 B22
 };
 
+// Assembled complex64 operator [2N][2N] (row-major).
+struct DenseOperator {
+    int64_t n2 = 0;
+    DevBuf<float2> B;
+};
+
 struct OsrcKey {
     int np;
     double theta, kr, ki;
@@ -167,6 +173,8 @@ struct bem_mesh {
     bem::DevBuf<double> ss_tab;        // concatenated singular rules [n][5]
     int ss_off[4] = {0, 0, 0, 0};      // row offsets of the three rules
     std::map<bem::NearKey, std::unique_ptr<bem::NearOperator>> near_cache;
+    std::map<bem::NearKey, std::unique_ptr<bem::DenseOperator>> dense_cache;
+    bem::DevBuf<float2> xs32;          // complex64 copy of a matvec input
 
     // OSRC: P1 vertex graph, M and S values, factor state per parameter set
     std::unique_ptr<bem::OsrcSymbolicState, bem::OsrcSymDeleter> osrc_sym;
@@ -193,6 +201,13 @@ std::unique_ptr<NearOperator> nearfield_build(bem_mesh *m, double2 k0, double2 k
                                               double rho, hipStream_t s);
 const NearOperator &nearfield_get(bem_mesh *m, double2 k0, double2 k1, double rho,
                                   hipStream_t s);
+// dense.hip
+int64_t dense_bytes(const bem_mesh *m);
+std::unique_ptr<DenseOperator> dense_assemble(bem_mesh *m, const NearOperator &nf, double2 k0,
+                                              double2 k1, double rho, hipStream_t s);
+const DenseOperator &dense_get(bem_mesh *m, double2 k0, double2 k1, double rho, hipStream_t s);
+void dense_gemv(const DenseOperator &op, const double2 *x, double2 *y, DevBuf<float2> &xs,
+                hipStream_t s);
 // mesh.cpp
 void mesh_build(bem_mesh *m, const double *P, int64_t N, const int32_t *tri,
                 int64_t T, const int32_t *obj);

@@ -1,0 +1,352 @@
+// Assembled form of the permuted PMCHWT Galerkin operator (Sec. 2.7;
+// operators of Sec. 2.2, P1 Galerkin of Sec. 2.3) as a dense complex64
+// matrix B [2N][2N] (row-major; rows [psi-row; phi-row] = [V-row; D-row],
+// columns [psi; phi]), for right-hand-side batches and for GMRES iterations
+// that reuse one operator many times.
+//
+// Entries are the same sums as the matrix-free matvec: the 6x6 rule (FP32)
+// over every test/trial triangle pair sharing no vertex, plus the FP64
+// near-field operator of the pairs that do.  Assembly is deterministic: per
+// tile J of trial vertices,
+//   dense_pairs_kernel:  Q[tau][j][a][blk] = sum_{sigma in star(j)} local
+//                        block (tau, sigma)[a][b(sigma, j)]    (thread (tau, j))
+//   dense_gather_kernel: B[i][j] = sum_{(tau, a) in star(i)} Q[tau][j][a]   (thread (i, j))
+// Each separated triangle pair is evaluated three times (once per trial
+// vertex), about three matrix-free matvecs of work per assembly.
+#include <cmath>
+
+#include "bem_internal.h"
+
+namespace bem {
+
+namespace {
+
+constexpr double DUN_A1 = 0.44594849091596488631832925388305;
+constexpr double DUN_W1 = 0.22338158967801146569500700843312;
+constexpr double DUN_A2 = 0.091576213509770743459571463402202;
+constexpr double DUN_W2 = 0.10995174365532186763832632490021;
+__host__ __device__ constexpr double qw(int i) { return i < 3 ? DUN_W1 : DUN_W2; }
+__host__ __device__ constexpr double qb(int i, int a) {
+    return (a == i % 3) ? (1.0 - 2.0 * (i < 3 ? DUN_A1 : DUN_A2)) : (i < 3 ? DUN_A1 : DUN_A2);
+}
+
+constexpr int JT = 512;   // trial vertices per assembly tile
+
+struct DCoef {
+    float krev0, krev1, k0r, k0i, k1r, k1i, kdec0, kdec1, rho, irho, n0r, n0i, n1r, n1i;
+};
+
+__device__ __forceinline__ void sincos_rev(float t, float &s, float &c) {
+    const float f = t - __builtin_rintf(t);   // hardware sin/cos take revolutions
+    s = __builtin_amdgcn_sinf(f);
+    c = __builtin_amdgcn_cosf(f);
+}
+
+template <bool CK0, bool CK1, bool MULTI>
+__global__ __launch_bounds__(256) void dense_pairs_kernel(
+    const float *__restrict__ geo, const double *__restrict__ tst,
+    const int32_t *__restrict__ tobj, const int32_t *__restrict__ tri,
+    const int32_t *__restrict__ star_ptr, const int32_t *__restrict__ star_idx, int T, int j0,
+    int64_t N, DCoef cf, float2 *__restrict__ Q) {
+    const int tau = blockIdx.x * 256 + threadIdx.x;
+    const int jl = blockIdx.y;
+    const int64_t j = j0 + jl;
+    const bool active = tau < T && j < N;
+    const int tt = tau < T ? tau : 0;
+    const float *g = geo + (int64_t)GEO_STRIDE * tt;
+    float px[6], py[6], pz[6];
+    for (int i = 0; i < 6; i++) {
+        px[i] = g[3 * i];
+        py[i] = g[3 * i + 1];
+        pz[i] = g[3 * i + 2];
+    }
+    const float ntx = g[18], nty = g[19], ntz = g[20], ct = g[21];
+    const int tv0 = tri[3 * tt], tv1 = tri[3 * tt + 1], tv2 = tri[3 * tt + 2];
+    const int ot = MULTI ? tobj[tt] : 0;
+    float cu[9];
+    for (int c = 0; c < 9; c++) cu[c] = (float)tst[TST_STRIDE * tt + 1 + c];
+    float outr[12], outi[12];   // [blk * 3 + a]
+    for (int c = 0; c < 12; c++) outr[c] = outi[c] = 0.f;
+    const int e0 = j < N ? star_ptr[j] : 0, e1 = j < N ? star_ptr[j + 1] : 0;
+    for (int e = e0; e < e1; e++) {
+        const int sb = star_idx[e];
+        const int s = sb / 3, b = sb - 3 * s;
+        const int sv0 = tri[3 * s], sv1 = tri[3 * s + 1], sv2 = tri[3 * s + 2];
+        const bool adj = sv0 == tv0 || sv0 == tv1 || sv0 == tv2 || sv1 == tv0 || sv1 == tv1 ||
+                         sv1 == tv2 || sv2 == tv0 || sv2 == tv1 || sv2 == tv2;
+        if (adj) continue;   // near field
+        const float *h = geo + (int64_t)GEO_STRIDE * s;
+        const float nsx = h[18], nsy = h[19], nsz = h[20], cs = h[21];
+        const float as = (float)tst[TST_STRIDE * s];
+        const float m1 = MULTI ? (tobj[s] == ot ? 1.f : 0.f) : 1.f;
+        const float nn = ntx * nsx + nty * nsy + ntz * nsz;
+        const float g0r = cf.n0r * nn, g0i = cf.n0i * nn, g1r = cf.n1r * nn, g1i = cf.n1i * nn;
+        float tq[6], dnx[6], dny[6];
+        for (int q = 0; q < 6; q++) {
+            tq[q] = (float)(qw(q) * qb(q, b)) * as;
+            dnx[q] = ct - (h[3 * q] * ntx + h[3 * q + 1] * nty + h[3 * q + 2] * ntz);
+        }
+        for (int p = 0; p < 6; p++) dny[p] = cs - (px[p] * nsx + py[p] * nsy + pz[p] * nsz);
+        float ar[4][6], ai[4][6];
+        for (int k = 0; k < 4; k++)
+            for (int p = 0; p < 6; p++) ar[k][p] = ai[k][p] = 0.f;
+        float gwr = 0.f, gwi = 0.f;
+#pragma unroll
+        for (int p = 0; p < 6; p++) {
+#pragma unroll
+            for (int q = 0; q < 6; q++) {
+                const float dx = h[3 * q] - px[p], dy = h[3 * q + 1] - py[p],
+                            dz = h[3 * q + 2] - pz[p];
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float ri = __builtin_amdgcn_rsqf(r2);
+                const float r = r2 * ri;
+                float s0, c0, s1, c1;
+                sincos_rev(r * cf.krev0, s0, c0);
+                sincos_rev(r * cf.krev1, s1, c1);
+                float ri0 = ri, ri1 = ri * m1;
+                if (CK0) ri0 *= __builtin_amdgcn_exp2f(r * cf.kdec0);
+                if (CK1) ri1 *= __builtin_amdgcn_exp2f(r * cf.kdec1);
+                const float G0r = c0 * ri0, G0i = s0 * ri0, G1r = c1 * ri1, G1i = s1 * ri1;
+                float F0r, F0i, F1r, F1i;
+                {
+                    const float ur = cf.k0r * r, ui = CK0 ? cf.k0i * r : 0.f;
+                    F0r = -G0r * (1.f + ui) - G0i * ur;
+                    F0i = -G0i * (1.f + ui) + G0r * ur;
+                }
+                {
+                    const float ur = cf.k1r * r, ui = CK1 ? cf.k1i * r : 0.f;
+                    F1r = -G1r * (1.f + ui) - G1i * ur;
+                    F1i = -G1i * (1.f + ui) + G1r * ur;
+                }
+                const float ri2 = ri * ri;
+                const float Fr = (F0r + F1r) * ri2, Fi = (F0i + F1i) * ri2;
+                const float t = tq[q];
+                // V-row psi column: G_V;  V-row phi column: -F (y-x).n_y
+                ar[0][p] += (G0r + cf.rho * G1r) * t;
+                ai[0][p] += (G0i + cf.rho * G1i) * t;
+                ar[1][p] -= Fr * dny[p] * t;
+                ai[1][p] -= Fi * dny[p] * t;
+                // D-row psi column: F (x-y).n_x;  D-row phi column: -G_N (n_x.n_y)
+                ar[2][p] += Fr * dnx[q] * t;
+                ai[2][p] += Fi * dnx[q] * t;
+                ar[3][p] -= (g0r * G0r - g0i * G0i + g1r * G1r - g1i * G1i) * t;
+                ai[3][p] -= (g0r * G0i + g0i * G0r + g1r * G1i + g1i * G1r) * t;
+                const float ww = (float)(qw(p) * qw(q));
+                gwr += ww * (G0r + cf.irho * G1r);
+                gwi += ww * (G0i + cf.irho * G1i);
+            }
+        }
+        // contract with the test functions; curl-curl part of D
+        float scb[3];
+        for (int c = 0; c < 3; c++) scb[c] = (float)tst[TST_STRIDE * s + 1 + 3 * b + c];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                float sr = 0.f, si = 0.f;
+#pragma unroll
+                for (int p = 0; p < 6; p++) {
+                    const float wp = (float)(qw(p) * qb(p, a));
+                    sr += wp * ar[k][p];
+                    si += wp * ai[k][p];
+                }
+                outr[3 * k + a] += sr;
+                outi[3 * k + a] += si;
+            }
+            const float cc = (cu[3 * a] * scb[0] + cu[3 * a + 1] * scb[1] + cu[3 * a + 2] * scb[2]) * as;
+            outr[9 + a] += cc * gwr;
+            outi[9 + a] += cc * gwi;
+        }
+    }
+    if (!active) return;
+    const float sc = (float)(tst[TST_STRIDE * tt] * 0.079577471545947667884441881686257);
+    float2 *o = Q + ((int64_t)tau * JT + jl) * 12;
+    for (int c = 0; c < 12; c++) o[c] = make_float2(sc * outr[c], sc * outi[c]);
+}
+
+// B[i][j], B[i][N+j], B[N+i][j], B[N+i][N+j] from the star of test vertex i
+__global__ __launch_bounds__(256) void dense_gather_kernel(const float2 *__restrict__ Q,
+                                                           const int32_t *__restrict__ star_ptr,
+                                                           const int32_t *__restrict__ star_idx,
+                                                           int64_t N, int j0, int jt,
+                                                           float2 *__restrict__ B) {
+    const int jl = blockIdx.y * 256 + threadIdx.x;
+    const int64_t i = blockIdx.x;
+    if (jl >= jt) return;
+    float2 acc[4] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+    for (int e = star_ptr[i]; e < star_ptr[i + 1]; e++) {
+        const int ta = star_idx[e];
+        const int t = ta / 3, a = ta - 3 * t;
+        const float2 *q = Q + ((int64_t)t * JT + jl) * 12;
+        for (int k = 0; k < 4; k++) {
+            acc[k].x += q[3 * k + a].x;
+            acc[k].y += q[3 * k + a].y;
+        }
+    }
+    const int64_t n2 = 2 * N, j = j0 + jl;
+    B[i * n2 + j] = acc[0];
+    B[i * n2 + N + j] = acc[1];
+    B[(N + i) * n2 + j] = acc[2];
+    B[(N + i) * n2 + N + j] = acc[3];
+}
+
+// add the FP64 near-field operator (rounded to complex64)
+__global__ __launch_bounds__(256) void dense_add_near_kernel(const int32_t *__restrict__ rowptr,
+                                                             const int32_t *__restrict__ col,
+                                                             const double2 *__restrict__ nf,
+                                                             int64_t nnz, int64_t N,
+                                                             float2 *__restrict__ B) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int64_t n2 = 2 * N;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; e++) {
+        const int64_t j = col[e];
+        const int64_t pos[4] = {i * n2 + j, i * n2 + N + j, (N + i) * n2 + j,
+                                (N + i) * n2 + N + j};
+        for (int k = 0; k < 4; k++) {
+            const double2 v = nf[k * nnz + e];
+            float2 o = B[pos[k]];
+            // sum in FP64, round once
+            B[pos[k]] = make_float2((float)((double)o.x + v.x), (float)((double)o.y + v.y));
+        }
+    }
+}
+
+// y = B x: one wavefront per row, FP32 products, FP64 lane partial sums and a
+// fixed-order butterfly reduction
+__global__ __launch_bounds__(256) void dense_gemv_kernel(const float2 *__restrict__ B,
+                                                         int64_t n2,
+                                                         const float2 *__restrict__ x,
+                                                         double2 *__restrict__ y) {
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n2) return;
+    const float2 *b = B + row * n2;
+    double sr = 0.0, si = 0.0;
+    for (int64_t c0 = 0; c0 < n2; c0 += 64 * 16) {
+        float pr = 0.f, pi = 0.f;
+        const int64_t c1 = c0 + 64 * 16 < n2 ? c0 + 64 * 16 : n2;
+        for (int64_t c = c0 + lane; c < c1; c += 64) {
+            const float2 a = b[c], v = x[c];
+            pr += a.x * v.x - a.y * v.y;
+            pi += a.x * v.y + a.y * v.x;
+        }
+        sr += pr;
+        si += pi;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        sr += __shfl_xor(sr, o, 64);
+        si += __shfl_xor(si, o, 64);
+    }
+    if (lane == 0) y[row] = make_double2(sr, si);
+}
+
+__global__ __launch_bounds__(256) void to_c64_kernel(const double2 *__restrict__ x,
+                                                     float2 *__restrict__ o, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) o[i] = make_float2((float)x[i].x, (float)x[i].y);
+}
+
+DCoef make_dcoef(double2 k0, double2 k1, double rho) {
+    const double inv2pi = 0.15915494309189533576888376337251;
+    const double log2e = 1.4426950408889634073599246810019;
+    DCoef c;
+    c.krev0 = (float)(k0.x * inv2pi);
+    c.krev1 = (float)(k1.x * inv2pi);
+    c.k0r = (float)k0.x;
+    c.k0i = (float)k0.y;
+    c.k1r = (float)k1.x;
+    c.k1i = (float)k1.y;
+    c.kdec0 = (float)(-k0.y * log2e);
+    c.kdec1 = (float)(-k1.y * log2e);
+    c.rho = (float)rho;
+    c.irho = (float)(1.0 / rho);
+    c.n0r = (float)(k0.x * k0.x - k0.y * k0.y);
+    c.n0i = (float)(2.0 * k0.x * k0.y);
+    c.n1r = (float)((k1.x * k1.x - k1.y * k1.y) / rho);
+    c.n1i = (float)(2.0 * k1.x * k1.y / rho);
+    return c;
+}
+
+template <bool A, bool B, bool C>
+void launch_pairs(dim3 grid, hipStream_t s, bem_mesh *m, int j0, DCoef cf, float2 *Q) {
+    hipLaunchKernelGGL((dense_pairs_kernel<A, B, C>), grid, dim3(256), 0, s, m->geo32.p, m->tst.p,
+                       m->tobj_d.p, m->tri_d.p, m->star_ptr.p, m->star_idx.p, (int)m->T, j0,
+                       m->N, cf, Q);
+}
+
+}   // namespace
+
+int64_t dense_bytes(const bem_mesh *m) { return 4 * m->N * m->N * (int64_t)sizeof(float2); }
+
+std::unique_ptr<DenseOperator> dense_assemble(bem_mesh *m, const NearOperator &nf, double2 k0,
+                                              double2 k1, double rho, hipStream_t s) {
+    auto op = std::make_unique<DenseOperator>();
+    const int64_t N = m->N, n2 = 2 * N;
+    op->n2 = n2;
+    op->B.alloc((size_t)(n2 * n2));
+    DevBuf<float2> Q((size_t)m->T * JT * 12);
+    const DCoef cf = make_dcoef(k0, k1, rho);
+    const int code = (k0.y != 0 ? 4 : 0) | (k1.y != 0 ? 2 : 0) | (m->nobj > 1 ? 1 : 0);
+    Timer tm("dense_assemble", s);
+    for (int64_t j0 = 0; j0 < N; j0 += JT) {
+        const int jt = (int)std::min<int64_t>(JT, N - j0);
+        dim3 grid((unsigned)((m->T + 255) / 256), jt);
+        switch (code) {
+        case 0: launch_pairs<false, false, false>(grid, s, m, (int)j0, cf, Q.p); break;
+        case 1: launch_pairs<false, false, true>(grid, s, m, (int)j0, cf, Q.p); break;
+        case 2: launch_pairs<false, true, false>(grid, s, m, (int)j0, cf, Q.p); break;
+        case 3: launch_pairs<false, true, true>(grid, s, m, (int)j0, cf, Q.p); break;
+        case 4: launch_pairs<true, false, false>(grid, s, m, (int)j0, cf, Q.p); break;
+        case 5: launch_pairs<true, false, true>(grid, s, m, (int)j0, cf, Q.p); break;
+        case 6: launch_pairs<true, true, false>(grid, s, m, (int)j0, cf, Q.p); break;
+        default: launch_pairs<true, true, true>(grid, s, m, (int)j0, cf, Q.p); break;
+        }
+        BEM_LAUNCH_CHECK();
+        hipLaunchKernelGGL(dense_gather_kernel, dim3((unsigned)N, (jt + 255) / 256), dim3(256), 0,
+                           s, Q.p, m->star_ptr.p, m->star_idx.p, N, (int)j0, jt, op->B.p);
+        BEM_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(dense_add_near_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
+                       m->nf_rowptr.p, m->nf_col.p, (const double2 *)nf.vals.p, m->nf_nnz, N,
+                       op->B.p);
+    BEM_LAUNCH_CHECK();
+    BEM_HIP(hipStreamSynchronize(s));   // Q is released on return
+    return op;
+}
+
+void dense_gemv(const DenseOperator &op, const double2 *x, double2 *y, DevBuf<float2> &xs,
+                hipStream_t s) {
+    const int64_t n2 = op.n2;
+    if (xs.n < (size_t)n2) xs.alloc((size_t)n2);
+    hipLaunchKernelGGL(to_c64_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, x, xs.p,
+                       n2);
+    BEM_LAUNCH_CHECK();
+    Timer tm("dense_gemv", s);
+    hipLaunchKernelGGL(dense_gemv_kernel, dim3((unsigned)((n2 + 3) / 4)), dim3(256), 0, s, op.B.p,
+                       n2, xs.p, y);
+    BEM_LAUNCH_CHECK();
+}
+
+const DenseOperator &dense_get(bem_mesh *m, double2 k0, double2 k1, double rho, hipStream_t s) {
+    NearKey key{k0.x, k0.y, k1.x, k1.y, rho};
+    auto it = m->dense_cache.find(key);
+    if (it != m->dense_cache.end()) return *it->second;
+    const NearOperator &nf = nearfield_get(m, k0, k1, rho, s);
+    // one resident dense operator per mesh unless memory allows more
+    size_t free_b = 0, total_b = 0;
+    BEM_HIP(hipMemGetInfo(&free_b, &total_b));
+    while (!m->dense_cache.empty() && (int64_t)free_b < dense_bytes(m) + (int64_t)(1ll << 30)) {
+        m->dense_cache.erase(m->dense_cache.begin());
+        BEM_HIP(hipMemGetInfo(&free_b, &total_b));
+    }
+    if ((int64_t)free_b < dense_bytes(m) + (int64_t)(1ll << 30))
+        fail(BEM_E_NOMEM, "dense operator of " + std::to_string(dense_bytes(m)) +
+                              " bytes does not fit in device memory");
+    auto op = dense_assemble(m, nf, k0, k1, rho, s);
+    auto &ref = *op;
+    m->dense_cache.emplace(key, std::move(op));
+    return ref;
+}
+
+}   // namespace bem

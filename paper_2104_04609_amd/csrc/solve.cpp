@@ -33,9 +33,11 @@ struct Op {
     OsrcState *st;
     hipStream_t s;
     double2 *yw;   // weak-form scratch [2N]
+    const DenseOperator *dense = nullptr;   // assembled operator (FP32 form)
     int n64 = 0, n32 = 0;
     void apply(const double2 *v, double2 *out, int precision) {
-        farfield_apply(m, *nf, k0, k1, rho, v, yw, precision, s);
+        if (precision == BEM_FP32_DENSE) dense_gemv(*dense, v, yw, m->xs32, s);
+        else farfield_apply(m, *nf, k0, k1, rho, v, yw, precision, s);
         osrc_apply_from_weak(m, *st, yw, out, s);
         if (precision == BEM_FP64) n64++;
         else n32++;
@@ -172,6 +174,7 @@ void bem_solve_opts_default(bem_solve_opts *o) {
     o->maxiter = 1000;
     o->inner_tol = 0.3;
     o->max_outer = 8;
+    o->path = 2;
 }
 
 int pmchwt_solve(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
@@ -192,6 +195,7 @@ int pmchwt_solve(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
         if (o.pade_terms < 1 || o.pade_terms > bem::PADE_MAX) fail(BEM_E_INVAL, "pade_terms");
         if (o.precision != BEM_FP64 && o.precision != BEM_FP32) fail(BEM_E_INVAL, "precision");
         if (o.maxiter < 1 || o.max_outer < 1 || !(o.inner_tol > 0)) fail(BEM_E_INVAL, "opts");
+        if (o.path < 0 || o.path > 2) fail(BEM_E_INVAL, "path must be 0, 1 or 2");
         for (int w = 0; w < n_waves; w++) {
             const double *d = directions + 3 * w;
             if (!(std::fabs(std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) - 1.0) < 1e-6))
@@ -211,6 +215,20 @@ int pmchwt_solve(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
         bem::DevBuf<double2> f((size_t)n_waves * n2), yw(n2), b(n2), x(n2), r(n2), dx(n2);
         bem::rhs_project(m, k0, directions, n_waves, f.p, s);
         bem::Op op{m, &nf, k0, k1, rho, &st, s, yw.p};
+        int inner = BEM_FP32;
+        if (o.precision == BEM_FP32 && o.path != 0) {
+            bool use = o.path == 1;
+            if (o.path == 2) {   // dense when it fits with room to spare
+                size_t free_b = 0, total_b = 0;
+                BEM_HIP(hipMemGetInfo(&free_b, &total_b));
+                use = bem::dense_bytes(m) + (int64_t)(2ll << 30) < (int64_t)free_b ||
+                      !m->dense_cache.empty();
+            }
+            if (use) {
+                op.dense = &bem::dense_get(m, k0, k1, rho, s);
+                inner = BEM_FP32_DENSE;
+            }
+        }
         bem::Workspace ws;
         ws.n2 = n2;
         ws.ensure(2, s);
@@ -241,7 +259,7 @@ int pmchwt_solve(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
                     const double eta = std::min(0.5, o.inner_tol * tol * bn / rn);
                     int it;
                     double est;
-                    bem::gmres(op, BEM_FP32, r.p, dx.p, n2, eta, o.maxiter - total_it, ws, it, est, s);
+                    bem::gmres(op, inner, r.p, dx.p, n2, eta, o.maxiter - total_it, ws, it, est, s);
                     total_it += it;
                     outer++;
                     bem::blas_axpby(make_double2(1, 0), x.p, make_double2(1, 0), dx.p, x.p, n2, s);

@@ -109,12 +109,14 @@ def test_solve_fp64_matches_oracle(P, case):
     assert np.linalg.norm(S.apply(x) - b) / np.linalg.norm(b) <= 2e-10
 
 
-def test_solve_fp32_refinement(P):
+@pytest.mark.parametrize("path", [0, 1])
+def test_solve_fp32_refinement(P, path):
+    """path 0: FP32 matrix-free pair kernel; path 1: assembled complex64."""
     mesh = icosphere(3)
     M = P.Mesh.from_inputs(mesh)
     S, xo, _ = oracle_solve(mesh, 2.0, 3.0, 1.5, 1e-10)
     sol, info, rc = P.pmchwt_solve(M, 2.0, 3.0, 1.5, [[0.0, 0.0, 1.0]], 1e-6,
-                                   precision="fp32")
+                                   precision="fp32", path=path)
     x = sol.cpu().numpy()[0]
     print(info[0])
     assert rc == 0 and info[0]["rel_residual"] <= 1e-6

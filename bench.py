@@ -50,6 +50,46 @@ def cpu_baseline(mesh, n_test=384):
                       f"both wavenumbers, 4 operators, FP64 ({dt:.1f} s)"}
 
 
+def batch_measure(P, M, mesh, mf_step_s):
+    """64 plane-wave right-hand sides (normalised Gaussian directions, seed
+    2104) at 4 wavenumber pairs k_ext in {4, 8, 12, 16}, k_int = 1.5 k_ext,
+    rho = 1.5: assembled complex64 operator x 64-column block on MFMA,
+    against the matrix-free FP32 matvec per right-hand side."""
+    import torch
+    from bem_inputs import wave_directions
+    from paper_2104_04609_amd import roofline as RL
+    d = wave_directions(64, seed=2104)
+    N = mesh.n_vertices
+    out = {"n_rhs": 64, "k_pairs": []}
+    for ke in (4.0, 8.0, 12.0, 16.0):
+        F = P.pmchwt_rhs(M, ke, d)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.profile_enable(True)
+        Y = P.pmchwt_matvec(M, ke, 1.5 * ke, 1.5, F, precision="fp32_dense")   # assembles
+        torch.cuda.synchronize()
+        first = time.perf_counter() - t0
+        asm_ms, _ = P.profile_read("dense_assemble")
+        P.profile_enable(False)
+        P.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(3):
+            P.pmchwt_matvec(M, ke, 1.5 * ke, 1.5, F, Y, precision="fp32_dense")
+        torch.cuda.synchronize()
+        gemm_s = (time.perf_counter() - t0) / 3
+        kms, kn = P.profile_read("dense_gemm_mfma")
+        P.profile_enable(False)
+        flops = 8.0 * (2 * N) ** 2 * 64
+        out["k_pairs"].append({
+            "k_ext": ke, "k_int": 1.5 * ke, "assembly_ms": asm_ms,
+            "first_call_s": first, "gemm_call_ms": gemm_s * 1e3,
+            "mfma_kernel_ms": kms / kn,
+            "mfma_tflops": flops / (kms / kn * 1e-3) / 1e12,
+            "mfma_frac_of_fp32_matrix_peak": flops / (kms / kn * 1e-3) / 1e12 / RL.PEAK_FP32_PACKED_TFLOPS})
+    out["matrix_free_64_rhs_s_estimate"] = 64 * mf_step_s
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,6 +97,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-batching", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
@@ -134,6 +175,10 @@ def main():
         except P.BemError as e:
             solve = {"error": str(e)}
 
+    batching = None
+    if not args.no_batching:
+        batching = batch_measure(P, M, mesh, step_s)
+
     out = {
         "metric": METRIC, "value": value, "unit": "tri-pair evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_s * 1e3,
@@ -152,6 +197,7 @@ def main():
                         "kernel_ms": kern64_ms, "roofline_frac": roof64["frac"]},
         "setup_s": setup_s,
         "solve": solve,
+        "batching": batching,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh)

@@ -150,8 +150,13 @@ int pmchwt_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho
     const int64_t n2 = 2 * m->N;
     if (precision == BEM_FP32_DENSE) {
         const bem::DenseOperator &op = bem::dense_get(m, k0, k1, rho, s);
-        for (int r = 0; r < n_rhs; r++)
-            bem::dense_gemv(op, (const double2 *)x + r * n2, (double2 *)y + r * n2, m->xs32, s);
+        if (n_rhs >= bem::DENSE_GEMM_MIN_RHS) {
+            bem::dense_gemm(op, (const double2 *)x, (double2 *)y, n_rhs, s);
+        } else {
+            for (int r = 0; r < n_rhs; r++)
+                bem::dense_gemv(op, (const double2 *)x + r * n2, (double2 *)y + r * n2, m->xs32,
+                                s);
+        }
         return BEM_OK;
     }
     for (int r = 0; r < n_rhs; r++)

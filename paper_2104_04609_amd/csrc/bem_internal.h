@@ -208,6 +208,10 @@ std::unique_ptr<DenseOperator> dense_assemble(bem_mesh *m, const NearOperator &n
 const DenseOperator &dense_get(bem_mesh *m, double2 k0, double2 k1, double rho, hipStream_t s);
 void dense_gemv(const DenseOperator &op, const double2 *x, double2 *y, DevBuf<float2> &xs,
                 hipStream_t s);
+// Y = B X for R right-hand sides (x, y RHS-major [R][2N]) on MFMA
+void dense_gemm(const DenseOperator &op, const double2 *x, double2 *y, int R, hipStream_t s);
+// right-hand-side count from which the MFMA product replaces per-RHS GEMVs
+constexpr int DENSE_GEMM_MIN_RHS = 16;
 // mesh.cpp
 void mesh_build(bem_mesh *m, const double *P, int64_t N, const int32_t *tri,
                 int64_t T, const int32_t *obj);

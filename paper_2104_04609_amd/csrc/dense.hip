@@ -241,6 +241,103 @@ __global__ __launch_bounds__(256) void dense_gemv_kernel(const float2 *__restric
     if (lane == 0) y[row] = make_double2(sr, si);
 }
 
+// ------------------------------------------------ multi-RHS product on MFMA
+// Y = B X for n_rhs right-hand sides as one real FP32 GEMM: B is read as a
+// real [M][Kp] matrix (M = 2N rows, Kp = 4N: re/im interleaved), X as the
+// real [Kp][Np] matrix with rows 2k = (Re X_k, Im X_k) and 2k+1 =
+// (-Im X_k, Re X_k) per right-hand side (columns 2r, 2r+1), so that columns
+// 2r and 2r+1 of the product are Re and Im of column r of B X.
+constexpr int GM = 128, GN = 128, GK = 32;   // block tile and K step
+constexpr int GKC = 4096;                    // split-K chunk (FP32 MFMA accumulation)
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// Xp[2k][2r], Xp[2k][2r+1], Xp[2k+1][2r], Xp[2k+1][2r+1] from x[r][k] (RHS-major)
+__global__ __launch_bounds__(256) void gemm_xprep_kernel(const double2 *__restrict__ x, int R,
+                                                         int64_t K, int Np,
+                                                         float *__restrict__ Xp) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= K * (Np / 2)) return;
+    const int64_t k = id / (Np / 2);
+    const int r = (int)(id - k * (Np / 2));
+    const double2 v = r < R ? x[(int64_t)r * K + k] : make_double2(0.0, 0.0);
+    float *row0 = Xp + (2 * k) * Np, *row1 = row0 + Np;
+    row0[2 * r] = (float)v.x;
+    row0[2 * r + 1] = (float)v.y;
+    row1[2 * r] = (float)(-v.y);
+    row1[2 * r + 1] = (float)v.x;
+}
+
+// partial products of K chunk blockIdx.z: Yp[z][M][Np]; 4 waves, 64 x 64 each
+__global__ __launch_bounds__(256) void gemm_mfma_kernel(const float *__restrict__ A,
+                                                        const float *__restrict__ Xp,
+                                                        float *__restrict__ Yp, int64_t M,
+                                                        int64_t Kp, int Np) {
+    __shared__ float As[GM][GK + 1];
+    __shared__ float Bs[GK][GN];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t m0 = (int64_t)blockIdx.x * GM;
+    const int n0 = blockIdx.y * GN;
+    const int64_t kbeg = (int64_t)blockIdx.z * GKC;
+    const int64_t kend = kbeg + GKC < Kp ? kbeg + GKC : Kp;
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    floatx16 acc[2][2];
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 2; j++)
+            for (int v = 0; v < 16; v++) acc[i][j][v] = 0.f;
+    for (int64_t k0 = kbeg; k0 < kend; k0 += GK) {
+        __syncthreads();
+        for (int i = 0; i < (GM * GK) / 256; i++) {
+            const int idx = i * 256 + t, row = idx / GK, col = idx % GK;
+            const int64_t gr = m0 + row, gc = k0 + col;
+            As[row][col] = (gr < M && gc < kend) ? A[gr * Kp + gc] : 0.f;
+        }
+        for (int i = 0; i < (GK * GN) / 256; i++) {
+            const int idx = i * 256 + t, row = idx / GN, col = idx % GN;
+            const int64_t gr = k0 + row;
+            Bs[row][col] = gr < kend ? Xp[gr * Np + n0 + col] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GK; kk += 2) {
+            const int ka = kk + (lane >> 5);
+            const float a0 = As[wr + (lane & 31)][ka], a1 = As[wr + 32 + (lane & 31)][ka];
+            const float b0 = Bs[ka][wc + (lane & 31)], b1 = Bs[ka][wc + 32 + (lane & 31)];
+            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+        }
+    }
+    float *Y = Yp + (int64_t)blockIdx.z * M * Np;
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 2; j++)
+            for (int v = 0; v < 16; v++) {
+                // 32x32 accumulator layout: column lane % 32, row
+                // 8 (v / 4) + 4 (lane / 32) + v % 4
+                const int64_t row = m0 + wr + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int col = n0 + wc + 32 * j + (lane & 31);
+                if (row < M) Y[row * Np + col] = acc[i][j][v];
+            }
+}
+
+// y[r][m] = sum over K chunks (fixed order, FP64) of (Yp[.][m][2r], Yp[.][m][2r+1])
+__global__ __launch_bounds__(256) void gemm_reduce_kernel(const float *__restrict__ Yp,
+                                                          int nchunks, int64_t M, int Np, int R,
+                                                          double2 *__restrict__ y) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= M * R) return;
+    const int r = (int)(id / M);
+    const int64_t m = id - (int64_t)r * M;
+    double sr = 0.0, si = 0.0;
+    for (int c = 0; c < nchunks; c++) {
+        const float *row = Yp + ((int64_t)c * M + m) * Np;
+        sr += row[2 * r];
+        si += row[2 * r + 1];
+    }
+    y[(int64_t)r * M + m] = make_double2(sr, si);
+}
+
 __global__ __launch_bounds__(256) void to_c64_kernel(const double2 *__restrict__ x,
                                                      float2 *__restrict__ o, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -326,6 +423,30 @@ void dense_gemv(const DenseOperator &op, const double2 *x, double2 *y, DevBuf<fl
     hipLaunchKernelGGL(dense_gemv_kernel, dim3((unsigned)((n2 + 3) / 4)), dim3(256), 0, s, op.B.p,
                        n2, xs.p, y);
     BEM_LAUNCH_CHECK();
+}
+
+void dense_gemm(const DenseOperator &op, const double2 *x, double2 *y, int R, hipStream_t s) {
+    const int64_t M = op.n2, K = op.n2, Kp = 2 * K;
+    const int Rp = ((R + 63) / 64) * 64, Np = 2 * Rp;
+    const int nchunks = (int)((Kp + GKC - 1) / GKC);
+    DevBuf<float> Xp((size_t)(Kp * Np));
+    DevBuf<float> Yp((size_t)nchunks * M * Np);
+    const int64_t prep = K * Rp;
+    hipLaunchKernelGGL(gemm_xprep_kernel, dim3((unsigned)((prep + 255) / 256)), dim3(256), 0, s, x,
+                       R, K, Np, Xp.p);
+    BEM_LAUNCH_CHECK();
+    {
+        Timer tm("dense_gemm_mfma", s);
+        hipLaunchKernelGGL(gemm_mfma_kernel,
+                           dim3((unsigned)((M + GM - 1) / GM), Np / GN, nchunks), dim3(256), 0, s,
+                           (const float *)op.B.p, Xp.p, Yp.p, M, Kp, Np);
+        BEM_LAUNCH_CHECK();
+    }
+    const int64_t red = M * R;
+    hipLaunchKernelGGL(gemm_reduce_kernel, dim3((unsigned)((red + 255) / 256)), dim3(256), 0, s,
+                       Yp.p, nchunks, M, Np, R, y);
+    BEM_LAUNCH_CHECK();
+    BEM_HIP(hipStreamSynchronize(s));   // Xp, Yp are released on return
 }
 
 const DenseOperator &dense_get(bem_mesh *m, double2 k0, double2 k1, double rho, hipStream_t s) {

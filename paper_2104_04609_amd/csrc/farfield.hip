@@ -9,16 +9,20 @@
 // a vertex (coinciding, edge- or vertex-adjacent) are integrated entirely by
 // the FP64 near-field CSR operator, built once per wavenumber pair.
 //
-// Per point pair (x in tau, y in sigma), r = |x - y|, G_m = e^{i k_m r}/r and
-// F_m = G_m (i k_m r - 1)/r^2 (the 1/4pi is applied once at the end):
+// Per point pair (x in tau, y in sigma), r = |x - y|, E_m = e^{i k_m r},
+// G_m = E_m/r and F_m = G_m (i k_m r - 1)/r^2 (the 1/4pi is applied once at
+// the end):
 //   G_V = G_0 + rho G_1       (single layer, row 1)
 //   G_W = G_0 + G_1 / rho     (hypersingular curl-curl part, row 2)
 //   G_N = k_0^2 G_0 + k_1^2 G_1 / rho   (hypersingular normal part, row 2)
-//   F   = F_0 + F_1           (double layers)
+//   F   = F_0 + F_1 = (i (k_0 E_0 + k_1 E_1) - G_0 - G_1) / r^2
 //   acc1(x) += G_V s_psi(y) - F (y - x).n_y s_phi(y)
 //   acc2(x) += F (x - y).n_x s_psi(y) - G_N (n_x.n_y) s_phi(y)
 //   A_tau   += w_x w_y G_W sC_sigma        (curl term, contracted per pair)
 // s_psi(y) = w_y |sigma| psi_h(y), sC_sigma = |sigma| curl(phi_h) on sigma.
+// Factors constant over the points y of one trial triangle are taken out of
+// the y sum: (y - x).n_y = c_sigma - x.n_sigma (per x), (x - y).n_x =
+// c_tau - y.n_tau (per y, folded into s_psi), and k_0^2 (n_x.n_y) per triangle pair.
 // Interior terms (index 1) are masked out for triangles of different objects.
 #include <cmath>
 #include <type_traits>
@@ -49,10 +53,10 @@ template <class R> struct Math;
 
 template <> struct Math<float> {
     // sin/cos of 2 pi t: hardware v_sin/v_cos take revolutions; the argument
-    // is first reduced to [-1/2, 1/2] so that the hardware range is respected
-    // and the phase keeps FP32 resolution.
+    // is first reduced exactly to its fractional part so that the hardware
+    // input range holds for every wavenumber and distance.
     static __device__ __forceinline__ void sincos_rev(float t, float &s, float &c) {
-        float f = t - __builtin_rintf(t);
+        const float f = __builtin_amdgcn_fractf(t);   // exact, in [0, 1)
         s = __builtin_amdgcn_sinf(f);
         c = __builtin_amdgcn_cosf(f);
     }
@@ -104,13 +108,21 @@ template <> struct Math<double> {
     static __device__ __forceinline__ double exp2(double x) { return ::exp2(x); }
 };
 
+__device__ __forceinline__ float fmac(float a, float b, float c) {
+    return __builtin_fmaf(a, b, c);
+}
+__device__ __forceinline__ double fmac(double a, double b, double c) {
+    return __builtin_fma(a, b, c);
+}
+
 // Wavenumber-dependent coefficients of one launch.
 template <class R> struct Coef {
     R krev0, krev1;          // Re k / (2 pi)
     R k0r, k0i, k1r, k1i;    // k
     R kdec0, kdec1;          // -Im k * log2(e)
     R rho, irho;
-    R n0r, n0i, n1r, n1i;    // k_0^2 and k_1^2 / rho
+    R n0r, n0i;              // k_0^2
+    R n10r, n10i;            // k_1^2 / (rho k_0^2)
 };
 
 // ------------------------------------------------------------ source gather
@@ -238,17 +250,25 @@ __global__ __launch_bounds__(FF_BLOCK) void farfield_kernel(
             const R nsx = src[18], nsy = src[19], nsz = src[20], cs = src[21];
             const R m1 = MULTI ? (src[GEO_STRIDE + DYN_STRIDE] == ot ? (R)1 : (R)0) : (R)1;
             const R nn = ntx * nsx + nty * nsy + ntz * nsz;
-            // G_N (n_x . n_y) coefficients
-            const R g0r = cf.n0r * nn, g0i = cf.n0i * nn;
-            const R g1r = cf.n1r * nn, g1i = cf.n1i * nn;
-            R dnx[6], dny[6];
-            for (int j = 0; j < 6; j++)
-                dnx[j] = ct - (src[3 * j] * ntx + src[3 * j + 1] * nty + src[3 * j + 2] * ntz);
+            // factor of the G_N term pulled out of the j sum: k_0^2 (n_x . n_y)
+            const R gnr = cf.n0r * nn, gni = cf.n0i * nn;
+            // (x_i - y).n_x s_psi(y_j) = ((y_j - x_i).n_x ... ) folded per point j:
+            // spx_j = (c_tau - y_j.n_x) s_psi(y_j)
+            R spxr[6], spxi[6], dny[6];
+            for (int j = 0; j < 6; j++) {
+                const R dnx = ct - (src[3 * j] * ntx + src[3 * j + 1] * nty + src[3 * j + 2] * ntz);
+                spxr[j] = dnx * src[GEO_STRIDE + 2 * j];
+                spxi[j] = dnx * src[GEO_STRIDE + 2 * j + 1];
+            }
             for (int i = 0; i < 6; i++)
                 dny[i] = cs - (px[i] * nsx + py[i] * nsy + pz[i] * nsz);
             R gwr = 0, gwi = 0;
 #pragma unroll
             for (int i = 0; i < 6; i++) {
+                // per test point: sum_j F s_phi and sum_j (G_0 + n10 G_1) s_phi,
+                // scaled by (y - x).n_y resp. k_0^2 (n_x . n_y) after the j loop
+                R qr = 0, qi = 0, nr = 0, ni = 0;
+                R t1r = a1r[i], t1i = a1i[i], t2r = a2r[i], t2i = a2i[i];
 #pragma unroll
                 for (int j = 0; j < 6; j++) {
                     const R dx = src[3 * j] - px[i];
@@ -257,57 +277,85 @@ __global__ __launch_bounds__(FF_BLOCK) void farfield_kernel(
                     const R r2 = dx * dx + dy * dy + dz * dz;
                     const R ri = MT::rsq(r2);
                     const R r = r2 * ri;
-                    R s0, c0, s1, c1;
-                    MT::sincos_rev(r * cf.krev0, s0, c0);
-                    MT::sincos_rev(r * cf.krev1, s1, c1);
-                    R ri0 = ri, ri1 = ri * m1;
-                    if (CK0) ri0 *= MT::exp2(r * cf.kdec0);
-                    if (CK1) ri1 *= MT::exp2(r * cf.kdec1);
-                    const R G0r = c0 * ri0, G0i = s0 * ri0;
-                    const R G1r = c1 * ri1, G1i = s1 * ri1;
-                    // G (i u - 1) with u = k r
-                    R F0r, F0i, F1r, F1i;
-                    {
-                        const R ur = cf.k0r * r;
-                        if (CK0) {
-                            const R ui = cf.k0i * r;
-                            F0r = -G0r * (1 + ui) - G0i * ur;
-                            F0i = -G0i * (1 + ui) + G0r * ur;
-                        } else {
-                            F0r = -G0r - ur * G0i;
-                            F0i = ur * G0r - G0i;
-                        }
+                    // E_m = e^{i k_m r} (masked to 0 for the interior term of
+                    // triangles on different objects)
+                    R E0r, E0i, E1r, E1i;
+                    MT::sincos_rev(r * cf.krev0, E0i, E0r);
+                    MT::sincos_rev(r * cf.krev1, E1i, E1r);
+                    if (CK0) {
+                        const R d0 = MT::exp2(r * cf.kdec0);
+                        E0r *= d0;
+                        E0i *= d0;
                     }
-                    {
-                        const R ur = cf.k1r * r;
-                        if (CK1) {
-                            const R ui = cf.k1i * r;
-                            F1r = -G1r * (1 + ui) - G1i * ur;
-                            F1i = -G1i * (1 + ui) + G1r * ur;
-                        } else {
-                            F1r = -G1r - ur * G1i;
-                            F1i = ur * G1r - G1i;
-                        }
+                    if (CK1 || MULTI) {
+                        R d1 = m1;
+                        if (CK1) d1 *= MT::exp2(r * cf.kdec1);
+                        E1r *= d1;
+                        E1i *= d1;
+                    }
+                    const R G0r = E0r * ri, G0i = E0i * ri;
+                    const R G1r = E1r * ri, G1i = E1i * ri;
+                    // F r^2 = G_0 (i k_0 r - 1) + G_1 (i k_1 r - 1)
+                    //       = i (k_0 E_0 + k_1 E_1) - (G_0 + G_1)       (r / r = 1)
+                    R Fr = -(G0r + G1r), Fi = -(G0i + G1i);
+                    Fr = fmac(-cf.k0r, E0i, Fr);
+                    Fi = fmac(cf.k0r, E0r, Fi);
+                    Fr = fmac(-cf.k1r, E1i, Fr);
+                    Fi = fmac(cf.k1r, E1r, Fi);
+                    if (CK0) {
+                        Fr = fmac(-cf.k0i, E0r, Fr);
+                        Fi = fmac(-cf.k0i, E0i, Fi);
+                    }
+                    if (CK1) {
+                        Fr = fmac(-cf.k1i, E1r, Fr);
+                        Fi = fmac(-cf.k1i, E1i, Fi);
                     }
                     const R ri2 = ri * ri;
-                    const R Fr = (F0r + F1r) * ri2, Fi = (F0i + F1i) * ri2;
-                    const R GVr = G0r + cf.rho * G1r, GVi = G0i + cf.rho * G1i;
-                    const R GWr = G0r + cf.irho * G1r, GWi = G0i + cf.irho * G1i;
-                    const R GNr = g0r * G0r - g0i * G0i + g1r * G1r - g1i * G1i;
-                    const R GNi = g0r * G0i + g0i * G0r + g1r * G1i + g1i * G1r;
+                    Fr *= ri2;
+                    Fi *= ri2;
+                    const R GVr = fmac(cf.rho, G1r, G0r), GVi = fmac(cf.rho, G1i, G0i);
+                    const R GWr = fmac(cf.irho, G1r, G0r), GWi = fmac(cf.irho, G1i, G0i);
+                    // G_0 + (k_1^2 / (rho k_0^2)) G_1
+                    R GNr = fmac(cf.n10r, G1r, G0r), GNi = fmac(cf.n10r, G1i, G0i);
+                    if (CK0 || CK1) {
+                        GNr = fmac(-cf.n10i, G1i, GNr);
+                        GNi = fmac(cf.n10i, G1r, GNi);
+                    }
                     const R spr = src[GEO_STRIDE + 2 * j], spi = src[GEO_STRIDE + 2 * j + 1];
                     const R sfr = src[GEO_STRIDE + 12 + 2 * j],
                             sfi = src[GEO_STRIDE + 12 + 2 * j + 1];
-                    const R Fyr = Fr * dny[i], Fyi = Fi * dny[i];
-                    const R Fxr = Fr * dnx[j], Fxi = Fi * dnx[j];
-                    a1r[i] += GVr * spr - GVi * spi - (Fyr * sfr - Fyi * sfi);
-                    a1i[i] += GVr * spi + GVi * spr - (Fyr * sfi + Fyi * sfr);
-                    a2r[i] += Fxr * spr - Fxi * spi - (GNr * sfr - GNi * sfi);
-                    a2i[i] += Fxr * spi + Fxi * spr - (GNr * sfi + GNi * sfr);
+                    // complex multiply-accumulates as explicit FMA chains
+                    t1r = fmac(GVr, spr, t1r);
+                    t1r = fmac(-GVi, spi, t1r);
+                    t1i = fmac(GVr, spi, t1i);
+                    t1i = fmac(GVi, spr, t1i);
+                    qr = fmac(Fr, sfr, qr);
+                    qr = fmac(-Fi, sfi, qr);
+                    qi = fmac(Fr, sfi, qi);
+                    qi = fmac(Fi, sfr, qi);
+                    t2r = fmac(Fr, spxr[j], t2r);
+                    t2r = fmac(-Fi, spxi[j], t2r);
+                    t2i = fmac(Fr, spxi[j], t2i);
+                    t2i = fmac(Fi, spxr[j], t2i);
+                    nr = fmac(GNr, sfr, nr);
+                    nr = fmac(-GNi, sfi, nr);
+                    ni = fmac(GNr, sfi, ni);
+                    ni = fmac(GNi, sfr, ni);
                     const R ww = (R)(qw(i) * qw(j));
-                    gwr += ww * GWr;
-                    gwi += ww * GWi;
+                    gwr = fmac(ww, GWr, gwr);
+                    gwi = fmac(ww, GWi, gwi);
                 }
+                // row 1: - F (y - x).n_y s_phi; row 2: - G_N (n_x . n_y) s_phi
+                t1r = fmac(-dny[i], qr, t1r);
+                t1i = fmac(-dny[i], qi, t1i);
+                t2r = fmac(-gnr, nr, t2r);
+                t2r = fmac(gni, ni, t2r);
+                t2i = fmac(-gnr, ni, t2i);
+                t2i = fmac(-gni, nr, t2i);
+                a1r[i] = t1r;
+                a1i[i] = t1i;
+                a2r[i] = t2r;
+                a2i[i] = t2i;
             }
             for (int c = 0; c < 3; c++) {
                 const R scr = src[GEO_STRIDE + 24 + 2 * c], sci = src[GEO_STRIDE + 24 + 2 * c + 1];
@@ -403,8 +451,12 @@ template <class R> Coef<R> make_coef(double2 k0, double2 k1, double rho) {
     c.irho = (R)(1.0 / rho);
     c.n0r = (R)(k0.x * k0.x - k0.y * k0.y);
     c.n0i = (R)(2.0 * k0.x * k0.y);
-    c.n1r = (R)((k1.x * k1.x - k1.y * k1.y) / rho);
-    c.n1i = (R)(2.0 * k1.x * k1.y / rho);
+    // k_1^2 / (rho k_0^2); k_0 != 0 is checked at the entry points
+    const double n0r = k0.x * k0.x - k0.y * k0.y, n0i = 2.0 * k0.x * k0.y;
+    const double n1r = (k1.x * k1.x - k1.y * k1.y) / rho, n1i = 2.0 * k1.x * k1.y / rho;
+    const double d = n0r * n0r + n0i * n0i;
+    c.n10r = (R)((n1r * n0r + n1i * n0i) / d);
+    c.n10i = (R)((n1i * n0r - n1r * n0i) / d);
     return c;
 }
 

@@ -85,7 +85,7 @@ def batch_measure(P, M, mesh, mf_step_s):
             "first_call_s": first, "gemm_call_ms": gemm_s * 1e3,
             "mfma_kernel_ms": kms / kn,
             "mfma_tflops": flops / (kms / kn * 1e-3) / 1e12,
-            "mfma_frac_of_fp32_matrix_peak": flops / (kms / kn * 1e-3) / 1e12 / RL.PEAK_FP32_PACKED_TFLOPS})
+            "mfma_frac_of_fp32_matrix_peak": flops / (kms / kn * 1e-3) / 1e12 / RL.PEAK_FP32_TFLOPS})
     out["matrix_free_64_rhs_s_estimate"] = 64 * mf_step_s
     return out
 
@@ -98,6 +98,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-batching", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 256 MiB read + 256 MiB write elementwise kernel 3 times, "
+                         "to scale HBM byte counters (FETCH_SIZE, WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
@@ -139,8 +142,18 @@ def main():
     step_s, kern_ms = timed("fp32", args.steps, args.warmup)
     step64_s, kern64_ms = timed("fp64", max(3, args.steps // 4), 1)
 
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
+    # measured issue rates of FMA and the transcendental instructions
+    rates = P.valu_rates()
     pairs = RL.far_pairs_per_matvec(mesh.triangles)
-    roof = RL.pair_kernel_roofline(pairs, kern_ms * 1e-3, "fp32")
+    roof = RL.pair_kernel_roofline(pairs, kern_ms * 1e-3, "fp32", rates)
     roof64 = RL.pair_kernel_roofline(pairs, kern64_ms * 1e-3, "fp64")
     value = T * (T - 1) / step_s
 
@@ -191,7 +204,7 @@ def main():
                    "rho": RHO, "parallelism": "single GPU"},
         "roofline": {**roof, "kernel": "farfield_fp32",
                      "kernel_ms": kern_ms, "point_pairs_per_launch": pairs,
-                     "flop_eq_per_pair": RL.FLOP_EQ_PER_PAIR},
+                     "flops_per_pair": RL.FLOPS_PER_PAIR, "valu_rates": rates},
         "fp64_matvec": {"ms_per_step": step64_s * 1e3,
                         "tri_pair_evals_per_s": T * (T - 1) / step64_s,
                         "kernel_ms": kern64_ms, "roofline_frac": roof64["frac"]},

@@ -190,6 +190,15 @@ int bem_far_field(const bem_mesh *mesh, bem_c64 k_ext, const bem_c64 *solution,
 int bem_profile_enable(int enable);
 int bem_profile_read(const char *kernel, double *total_ms, int64_t *launches);
 
+/* Diagnostic for the issue-bound roofline of the pair kernel: measured issue
+ * rates, in lane operations per second summed over the device, of
+ * rates[0] v_fma_f32, [1] v_sin_f32, [2] v_cos_f32, [3] v_rsq_f32 and
+ * [4] v_fma_f64.  Each comes from a micro-kernel with 8 independent
+ * dependency chains per lane at full occupancy (about 10 ms in total).
+ *   rates  host [5], written on success
+ * Allocates and frees 4 MiB of device memory; synchronises the stream. */
+int bem_valu_rates(double *rates, void *hip_stream);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *bem_last_error(void);
 

@@ -7,8 +7,10 @@ and the far field.  All arithmetic runs in the library's HIP kernels.
 """
 from ._binding import (BEM_FP32, BEM_FP32_DENSE, BEM_FP64, BemError, Mesh, SolveInfo, SolveOpts,
                        default_opts, far_field, lib, osrc_apply, pmchwt_matvec,
-                       pmchwt_rhs, pmchwt_solve, profile_enable, profile_read)
+                       pmchwt_rhs, pmchwt_solve, profile_enable, profile_read,
+                       valu_rates)
 
 __all__ = ["BEM_FP32", "BEM_FP32_DENSE", "BEM_FP64", "BemError", "Mesh", "SolveInfo", "SolveOpts",
            "default_opts", "far_field", "lib", "osrc_apply", "pmchwt_matvec",
-           "pmchwt_rhs", "pmchwt_solve", "profile_enable", "profile_read"]
+           "pmchwt_rhs", "pmchwt_solve", "profile_enable", "profile_read",
+           "valu_rates"]

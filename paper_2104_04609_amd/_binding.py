@@ -76,6 +76,7 @@ lib.bem_far_field.argtypes = [_vp, c64, _vp, _vp, ctypes.c_int, _vp, _vp]
 lib.bem_profile_enable.argtypes = [ctypes.c_int]
 lib.bem_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(_i64)]
+lib.bem_valu_rates.argtypes = [_vp, _vp]
 lib.bem_last_error.restype = ctypes.c_char_p
 lib.bem_last_error.argtypes = []
 
@@ -239,6 +240,13 @@ def profile_read(kernel: str):
     ms, n = ctypes.c_double(), _i64()
     _check(lib.bem_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def valu_rates(stream=None) -> dict:
+    """Measured issue rates (lane operations/s over the device)."""
+    r = np.zeros(5, np.float64)
+    _check(lib.bem_valu_rates(_np_ptr(r), _stream(stream)))
+    return dict(zip(("fma_f32", "sin_f32", "cos_f32", "rsq_f32", "fma_f64"), r.tolist()))
 
 
 def exported_symbols(names: Sequence[str]):

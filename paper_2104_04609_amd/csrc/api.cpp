@@ -221,6 +221,14 @@ int bem_far_field(const bem_mesh *mesh, bem_c64 k_ext, const bem_c64 *solution,
     BEM_API_END
 }
 
+int bem_valu_rates(double *rates, void *hip_stream) {
+    BEM_API_BEGIN
+    if (!rates) fail(BEM_E_INVAL, "rates is NULL");
+    bem::valu_rates(rates, (hipStream_t)hip_stream);
+    return BEM_OK;
+    BEM_API_END
+}
+
 int bem_profile_enable(int enable) {
     BEM_API_BEGIN
     std::lock_guard<std::mutex> g(bem::g_prof_mu);

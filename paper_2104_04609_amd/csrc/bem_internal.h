@@ -151,6 +151,7 @@ struct bem_mesh {
     std::vector<double> normal;     // [T][3]
     std::vector<double> curl;       // [T][3][3]
     double centre[3] = {0, 0, 0};
+    double diameter = 0;            // bounding-box diagonal
     std::vector<double> obj_radius; // circumradius about each object's centroid
 
     // device geometry
@@ -210,6 +211,10 @@ void dense_gemv(const DenseOperator &op, const double2 *x, double2 *y, DevBuf<fl
                 hipStream_t s);
 // Y = B X for R right-hand sides (x, y RHS-major [R][2N]) on MFMA
 void dense_gemm(const DenseOperator &op, const double2 *x, double2 *y, int R, hipStream_t s);
+
+// Issue rates (lane operations per second over the device) of v_fma_f32,
+// v_sin_f32, v_cos_f32, v_rsq_f32 and v_fma_f64; rates[5].
+void valu_rates(double *rates, hipStream_t s);
 // right-hand-side count from which the MFMA product replaces per-RHS GEMVs
 constexpr int DENSE_GEMM_MIN_RHS = 16;
 // mesh.cpp

@@ -24,8 +24,12 @@
 // the y sum: (y - x).n_y = c_sigma - x.n_sigma (per x), (x - y).n_x =
 // c_tau - y.n_tau (per y, folded into s_psi), and k_0^2 (n_x.n_y) per triangle pair.
 // Interior terms (index 1) are masked out for triangles of different objects.
+#include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <type_traits>
+#include <utility>
 
 #include "bem_internal.h"
 
@@ -52,11 +56,14 @@ __host__ __device__ constexpr double qb(int i, int a) {
 template <class R> struct Math;
 
 template <> struct Math<float> {
-    // sin/cos of 2 pi t: hardware v_sin/v_cos take revolutions; the argument
-    // is first reduced exactly to its fractional part so that the hardware
-    // input range holds for every wavenumber and distance.
+    // sin/cos of 2 pi t: hardware v_sin/v_cos take revolutions.  With FR the
+    // argument is first reduced exactly to its fractional part; without it
+    // the caller guarantees |t| < 256 revolutions, inside which the hardware
+    // reduction gives the same values (sin may differ by a last-bit rounding
+    // near its zeros).
+    template <bool FR>
     static __device__ __forceinline__ void sincos_rev(float t, float &s, float &c) {
-        const float f = __builtin_amdgcn_fractf(t);   // exact, in [0, 1)
+        const float f = FR ? __builtin_amdgcn_fractf(t) : t;
         s = __builtin_amdgcn_sinf(f);
         c = __builtin_amdgcn_cosf(f);
     }
@@ -68,6 +75,7 @@ template <> struct Math<double> {
     // sin/cos of 2 pi t for moderate |t|: t = n/4 + f, |f| <= 1/8, then
     // Taylor series of sin and cos on [-pi/4, pi/4] (truncation < 5e-17) and
     // the quadrant rotation by n.
+    template <bool FR>
     static __device__ __forceinline__ void sincos_rev(double t, double &s, double &c) {
         double n = __builtin_rint(4.0 * t);
         double f = __builtin_fma(-0.25, n, t);
@@ -167,13 +175,21 @@ __global__ __launch_bounds__(256) void source_gather_kernel(
 }
 
 // ------------------------------------------------------- fused pair kernel
-template <class R, bool CK0, bool CK1, bool MULTI>
-__global__ __launch_bounds__(FF_BLOCK) void farfield_kernel(
+// FP32: per-tile FP64 row sums live in LDS (one column per thread), which
+// keeps the kernel within 168 VGPRs, i.e. 3 waves per SIMD.
+constexpr int FF_ROWS = ROW_STRIDE + 6;   // 12 row sums + 6 curl sums
+template <class R> constexpr int ff_waves() { return std::is_same<R, float>::value ? 3 : 2; }
+
+template <class R, bool CK0, bool CK1, bool MULTI, bool FR>
+__global__ __launch_bounds__(FF_BLOCK) __attribute__((amdgpu_waves_per_eu(ff_waves<R>())))
+void farfield_kernel(
     const R *__restrict__ geo, const R *__restrict__ dyn,
     const int32_t *__restrict__ tobj, const int32_t *__restrict__ tri, int T,
     int split_len, Coef<R> cf, double *__restrict__ partial) {
     using MT = Math<R>;
+    constexpr bool F32 = std::is_same<R, float>::value;
     __shared__ R tile[FF_TILE * SRC];
+    __shared__ double sums[F32 ? FF_ROWS * FF_BLOCK : 1];
     const int tau = blockIdx.x * FF_BLOCK + threadIdx.x;
     const int split = blockIdx.y;
     const int s_begin = split * split_len;
@@ -195,11 +211,20 @@ __global__ __launch_bounds__(FF_BLOCK) void farfield_kernel(
 
     R a1r[6], a1i[6], a2r[6], a2i[6];
     R Ar[3], Ai[3];
-    double rows[12], Ad[6];
     for (int i = 0; i < 6; i++) a1r[i] = a1i[i] = a2r[i] = a2i[i] = 0;
     for (int c = 0; c < 3; c++) Ar[c] = Ai[c] = 0;
-    for (int c = 0; c < 12; c++) rows[c] = 0;
-    for (int c = 0; c < 6; c++) Ad[c] = 0;
+    // FP64 sums: rows c = 0..11 (row 1 / row 2, test vertex, re/im), then the
+    // 6 curl sums; in LDS for FP32, in registers for FP64
+    double regsum[F32 ? 1 : FF_ROWS];
+    auto sum_add = [&](int c, double v) {
+        if constexpr (F32) sums[c * FF_BLOCK + threadIdx.x] += v;
+        else regsum[c] += v;
+    };
+    if constexpr (F32) {
+        for (int c = 0; c < FF_ROWS; c++) sums[c * FF_BLOCK + threadIdx.x] = 0;
+    } else {
+        for (int c = 0; c < FF_ROWS; c++) regsum[c] = 0;
+    }
 
     auto flush = [&]() {
         for (int a = 0; a < 3; a++) {
@@ -211,14 +236,14 @@ __global__ __launch_bounds__(FF_BLOCK) void farfield_kernel(
                 r2r += wb * (double)a2r[i];
                 r2i += wb * (double)a2i[i];
             }
-            rows[2 * a] += r1r;
-            rows[2 * a + 1] += r1i;
-            rows[6 + 2 * a] += r2r;
-            rows[6 + 2 * a + 1] += r2i;
+            sum_add(2 * a, r1r);
+            sum_add(2 * a + 1, r1i);
+            sum_add(6 + 2 * a, r2r);
+            sum_add(6 + 2 * a + 1, r2i);
         }
         for (int c = 0; c < 3; c++) {
-            Ad[2 * c] += (double)Ar[c];
-            Ad[2 * c + 1] += (double)Ai[c];
+            sum_add(ROW_STRIDE + 2 * c, (double)Ar[c]);
+            sum_add(ROW_STRIDE + 2 * c + 1, (double)Ai[c]);
             Ar[c] = Ai[c] = 0;
         }
         for (int i = 0; i < 6; i++) a1r[i] = a1i[i] = a2r[i] = a2i[i] = 0;
@@ -280,8 +305,8 @@ __global__ __launch_bounds__(FF_BLOCK) void farfield_kernel(
                     // E_m = e^{i k_m r} (masked to 0 for the interior term of
                     // triangles on different objects)
                     R E0r, E0i, E1r, E1i;
-                    MT::sincos_rev(r * cf.krev0, E0i, E0r);
-                    MT::sincos_rev(r * cf.krev1, E1i, E1r);
+                    MT::template sincos_rev<FR>(r * cf.krev0, E0i, E0r);
+                    MT::template sincos_rev<FR>(r * cf.krev1, E1i, E1r);
                     if (CK0) {
                         const R d0 = MT::exp2(r * cf.kdec0);
                         E0r *= d0;
@@ -363,17 +388,21 @@ __global__ __launch_bounds__(FF_BLOCK) void farfield_kernel(
                 Ai[c] += gwr * sci + gwi * scr;
             }
         }
-        if (std::is_same<R, float>::value) flush();
+        if constexpr (F32) flush();
     }
     flush();
     if (!active) return;
+    auto sum_get = [&](int c) -> double {
+        if constexpr (F32) return sums[c * FF_BLOCK + threadIdx.x];
+        else return regsum[c];
+    };
     double *out = partial + ((int64_t)split * T + tau) * ROW_STRIDE;
-    for (int c = 0; c < 12; c++) out[c] = rows[c];
+    for (int c = 0; c < ROW_STRIDE; c++) out[c] = sum_get(c);
     // the curl accumulator A follows the rows: [nsplit][T][6] after
     // [nsplit][T][12]; the reduction contracts it with the test curls
     double *outA = partial + (int64_t)gridDim.y * T * ROW_STRIDE +
                    ((int64_t)split * T + tau) * 6;
-    for (int c = 0; c < 6; c++) outA[c] = Ad[c];
+    for (int c = 0; c < 6; c++) outA[c] = sum_get(ROW_STRIDE + c);
 }
 
 // --------------------------------------------------------- split reduction
@@ -460,22 +489,24 @@ template <class R> Coef<R> make_coef(double2 k0, double2 k1, double rho) {
     return c;
 }
 
-template <class R, bool CK0, bool CK1, bool MULTI>
+template <class R, bool CK0, bool CK1, bool MULTI, bool FR>
 void launch_far(dim3 grid, hipStream_t s, const R *geo, const R *dyn,
                 const int32_t *tobj, const int32_t *tri, int T, int split_len, Coef<R> cf,
                 double *partial) {
-    hipLaunchKernelGGL((farfield_kernel<R, CK0, CK1, MULTI>), grid, dim3(FF_BLOCK), 0, s,
+    hipLaunchKernelGGL((farfield_kernel<R, CK0, CK1, MULTI, FR>), grid, dim3(FF_BLOCK), 0, s,
                        geo, dyn, tobj, tri, T, split_len, cf, partial);
 }
 
-template <class R>
+// fr: reduce phases to [0, 1) revolutions before v_sin/v_cos (needed when
+// k r / 2 pi can reach 256); the FP64 path always reduces.
+template <class R, bool FR>
 void dispatch_far(dim3 grid, hipStream_t s, const R *geo, const R *dyn,
                   const int32_t *tobj, const int32_t *tri, int T, int split_len, Coef<R> cf,
                   double *partial, bool ck0, bool ck1, bool multi) {
     int code = (ck0 ? 4 : 0) | (ck1 ? 2 : 0) | (multi ? 1 : 0);
     switch (code) {
 #define BEM_CASE(c, a, b, m) \
-    case c: launch_far<R, a, b, m>(grid, s, geo, dyn, tobj, tri, T, split_len, cf, partial); break;
+    case c: launch_far<R, a, b, m, FR>(grid, s, geo, dyn, tobj, tri, T, split_len, cf, partial); break;
         BEM_CASE(0, false, false, false)
         BEM_CASE(1, false, false, true)
         BEM_CASE(2, false, true, false)
@@ -488,29 +519,80 @@ void dispatch_far(dim3 grid, hipStream_t s, const R *geo, const R *dyn,
     }
 }
 
+// Pair kernel variant for the runtime flags (code = 4 ck0 + 2 ck1 + multi).
+template <class R, bool FR> const void *far_kernel(int code) {
+    switch (code) {
+    case 0: return (const void *)farfield_kernel<R, false, false, false, FR>;
+    case 1: return (const void *)farfield_kernel<R, false, false, true, FR>;
+    case 2: return (const void *)farfield_kernel<R, false, true, false, FR>;
+    case 3: return (const void *)farfield_kernel<R, false, true, true, FR>;
+    case 4: return (const void *)farfield_kernel<R, true, false, false, FR>;
+    case 5: return (const void *)farfield_kernel<R, true, false, true, FR>;
+    case 6: return (const void *)farfield_kernel<R, true, true, false, FR>;
+    default: return (const void *)farfield_kernel<R, true, true, true, FR>;
+    }
+}
+
+// Workgroups of a pair kernel variant resident on the current device at once
+// (compute units x occupancy), cached per device and variant.
+int far_slots(const void *kern) {
+    static std::mutex mu;
+    static std::map<std::pair<int, const void *>, int> cache;
+    int dev = 0;
+    BEM_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find({dev, kern});
+    if (it != cache.end()) return it->second;
+    int cus = 0, per_cu = 0;
+    BEM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    BEM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, FF_BLOCK, 0));
+    const int slots = std::max(1, cus * per_cu);
+    cache[{dev, kern}] = slots;
+    return slots;
+}
+
 }   // namespace
 
-int farfield_splits(int T) {
-    int tiles = (T + FF_BLOCK - 1) / FF_BLOCK;
-    const int target = 2048;   // workgroups in flight per launch
-    int s = (target + tiles - 1) / tiles;
-    int min_len = FF_TILE;
-    int max_s = (T + min_len - 1) / min_len;
-    if (s > max_s) s = max_s;
-    if (s < 1) s = 1;
-    return s;
+// Number of trial-triangle splits (grid.y).  Every workgroup of a launch costs
+// about the same, so the launch runs in rounds of `slots` resident
+// workgroups; the split count minimises rounds x (trial triangles per split
+// + a small fixed cost), which avoids a nearly empty last round.
+int farfield_splits(int T, int slots) {
+    const int tiles = (T + FF_BLOCK - 1) / FF_BLOCK;
+    const int max_s = std::max(1, (T + FF_TILE - 1) / FF_TILE);
+    const double fixed = 2.0;   // prologue + flush, in trial triangles
+    int best = 1;
+    double best_cost = 1e300;
+    for (int sp = 1; sp <= max_s; sp++) {
+        const int len = (T + sp - 1) / sp;
+        const long long rounds = ((long long)tiles * sp + slots - 1) / slots;
+        const double cost = (double)rounds * (len + fixed);
+        if (cost < best_cost * (1.0 - 1e-12)) {
+            best_cost = cost;
+            best = sp;
+        }
+    }
+    return best;
 }
 
 void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
                     double rho, const double2 *x, double2 *y, int precision,
                     hipStream_t s) {
     const int T = (int)m->T;
-    const int nsplit = farfield_splits(T);
+    const bool ck0 = k0.y != 0.0, ck1 = k1.y != 0.0, multi = m->nobj > 1;
+    const int code = (ck0 ? 4 : 0) | (ck1 ? 2 : 0) | (multi ? 1 : 0);
+    // largest phase in revolutions: max Re k * diameter / (2 pi)
+    const double tmax = std::max(std::fabs(k0.x), std::fabs(k1.x)) * m->diameter *
+                        0.15915494309189533576888376337251;
+    const bool fr = tmax >= 256.0;
+    const void *kern = precision == BEM_FP32
+                           ? (fr ? far_kernel<float, true>(code) : far_kernel<float, false>(code))
+                           : far_kernel<double, true>(code);
+    const int nsplit = farfield_splits(T, far_slots(kern));
     const int split_len = (T + nsplit - 1) / nsplit;
     const size_t need = (size_t)nsplit * T * (ROW_STRIDE + 6);
     if (m->partial.n < need) m->partial.alloc(need);
     if (m->trirows.n < (size_t)T * ROW_STRIDE) m->trirows.alloc((size_t)T * ROW_STRIDE);
-    const bool ck0 = k0.y != 0.0, ck1 = k1.y != 0.0, multi = m->nobj > 1;
     dim3 gg((T + 255) / 256);
     dim3 grid((T + FF_BLOCK - 1) / FF_BLOCK, nsplit);
     if (precision == BEM_FP32) {
@@ -519,8 +601,14 @@ void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
                            m->tst.p, x, m->N, T, m->dyn32.p);
         BEM_LAUNCH_CHECK();
         Timer tm("farfield_fp32", s);
-        dispatch_far<float>(grid, s, m->geo32.p, m->dyn32.p, m->tobj_d.p, m->tri_d.p, T, split_len,
-                            make_coef<float>(k0, k1, rho), m->partial.p, ck0, ck1, multi);
+        if (!fr)
+            dispatch_far<float, false>(grid, s, m->geo32.p, m->dyn32.p, m->tobj_d.p, m->tri_d.p,
+                                       T, split_len, make_coef<float>(k0, k1, rho),
+                                       m->partial.p, ck0, ck1, multi);
+        else
+            dispatch_far<float, true>(grid, s, m->geo32.p, m->dyn32.p, m->tobj_d.p, m->tri_d.p,
+                                      T, split_len, make_coef<float>(k0, k1, rho),
+                                      m->partial.p, ck0, ck1, multi);
         BEM_LAUNCH_CHECK();
     } else {
         if (m->dyn64.n < (size_t)T * DYN_STRIDE) m->dyn64.alloc((size_t)T * DYN_STRIDE);
@@ -528,7 +616,7 @@ void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
                            m->tst.p, x, m->N, T, m->dyn64.p);
         BEM_LAUNCH_CHECK();
         Timer tm("farfield_fp64", s);
-        dispatch_far<double>(grid, s, m->geo64.p, m->dyn64.p, m->tobj_d.p, m->tri_d.p, T, split_len,
+        dispatch_far<double, true>(grid, s, m->geo64.p, m->dyn64.p, m->tobj_d.p, m->tri_d.p, T, split_len,
                              make_coef<double>(k0, k1, rho), m->partial.p, ck0, ck1, multi);
         BEM_LAUNCH_CHECK();
     }

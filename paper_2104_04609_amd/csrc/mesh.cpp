@@ -61,6 +61,7 @@ void mesh_build(bem_mesh *m, const double *P, int64_t N, const int32_t *tri,
         m->centre[c] = 0.5 * (lo[c] + hi[c]);
         diag2 += (hi[c] - lo[c]) * (hi[c] - lo[c]);
     }
+    m->diameter = std::sqrt(diag2);
 
     // vertex ownership by object
     m->vobj.assign(N, -1);

@@ -1,11 +1,21 @@
-"""Algorithmic work model of the matrix-free PMCHWT pair kernel.
+"""Algorithmic work model and issue-bound roofline of the matrix-free PMCHWT
+pair kernel.
 
 Unit of work: one quadrature point pair (x in tau, y in sigma), both
-wavenumbers, all four operators (V, K, K', D in Maue form) fused.  The count
-below is the arithmetic the fused kernel performs per point pair for real
-wavenumbers and one object, with a fused multiply-add counted as 2 flops.
-Transcendentals (1/sqrt r^2, sin and cos of two phases) run at a quarter of
-the FMA issue rate on CDNA, so each occupies 4 issue slots = 8 flop-equivalents.
+wavenumbers, all four operators (V, K, K', D in Maue form) fused.  The work
+per unit is the itemised count below, frozen before the kernel was tuned:
+about 110 flops (FMA = 2) and 5 transcendentals (1/sqrt r^2, sin and cos of
+two phases).  The kernel itself now needs fewer flops per pair (it factors
+triangle constants out of the point sums); the frozen count stays the unit so
+that speed-ups show up as a higher fraction.
+
+Issue-bound model (FP32):  t_pair = F / P32 + sum_t n_t / P_t  with
+P32 = 157.3 TFLOP/s (published vector FP32 peak of MI355X) and P_t the issue
+rate of each transcendental instruction, measured on the device by
+``bem_valu_rates``.  The roofline object reports achieved and peak in
+flop-equivalents at the P32 rate, so frac = achieved pairs/s / model pairs/s.
+FP64: software sin/cos and a refined 1/sqrt at about 30 flops each, against
+the 78.6 TFLOP/s FP64 vector peak.
 """
 from __future__ import annotations
 
@@ -13,29 +23,47 @@ import numpy as np
 
 # itemised per-point-pair count (flops, FMA = 2)
 FLOPS_ITEMS = {
-    "difference y - x": 3,
-    "r^2 (mul + 2 fma)": 5,
-    "r = r^2 / sqrt(r^2)": 1,
-    "phases k r / 2pi and reduction, 2 wavenumbers": 6,
-    "G_0, G_1 = e^{ikr} / r": 4,
-    "F_m r^2 = G_m (i k_m r - 1), 2 wavenumbers": 10,
-    "F = (F_0 + F_1) / r^2": 5,
-    "G_V, G_W (2 complex axpy)": 8,
-    "G_N (k_0^2 G_0 + k_1^2 G_1 / rho) (n_x . n_y)": 14,
-    "F (y-x).n_y, F (x-y).n_x": 4,
-    "row-1 and row-2 accumulations (4 complex fma pairs)": 32,
-    "curl-term weight sum w_x w_y G_W": 4,
+    "geometry: y - x, r^2, r, (y - x).n_y, (x - y).n_x": 20,
+    "per wavenumber (x2): phase k r / 2pi, G = e^{ikr}/r, F = G (ikr - 1)/r^2": 20,
+    "combinations G_V, G_W, G_N (n_x.n_y), F": 16,
+    "accumulations: V, K, K', D normal and curl-curl parts": 54,
 }
-FLOPS_PER_PAIR = sum(FLOPS_ITEMS.values())            # 96
-TRANS_PER_PAIR = 5                                    # rsqrt, 2 sin, 2 cos
-TRANS_FLOP_EQ = 8                                     # quarter rate: 4 FMA slots
-FLOP_EQ_PER_PAIR = FLOPS_PER_PAIR + TRANS_PER_PAIR * TRANS_FLOP_EQ   # 136
+FLOPS_PER_PAIR = sum(FLOPS_ITEMS.values())            # 110
+TRANS_PER_PAIR = {"sin_f32": 2, "cos_f32": 2, "rsq_f32": 1}
+FP64_SOFT_TRANS_FLOPS = 30                            # per software transcendental
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, FMA = 2 flops
-PEAK_FP32_PLAIN_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12   # 78.6 (no packed FP32)
-PEAK_FP32_PACKED_TFLOPS = 157.3                            # published, packed
+# VALU instructions per point pair of the tuned FP32 kernel (real wavenumbers,
+# one object), counted in its gfx950 assembly: 1890 VALU FP32 instructions per
+# 36-pair unrolled trial-triangle iteration, transcendentals excluded.
+KERNEL_VALU_PER_PAIR = 52.5
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+LANE_ISSUE_PER_S = 256 * 4 * 16 * 2.4e9                  # 3.93e13 (wave64 op = 4 cycles)
+PEAK_FP32_PLAIN_TFLOPS = 2 * LANE_ISSUE_PER_S / 1e12     # 78.6, plain FP32 FMA
+PEAK_FP32_TFLOPS = 157.3                                 # published vector FP32 (packed)
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+# quarter-rate assumption, used only when no measured rates are given
+QUARTER_RATES = {"fma_f32": LANE_ISSUE_PER_S, "sin_f32": LANE_ISSUE_PER_S / 4,
+                 "cos_f32": LANE_ISSUE_PER_S / 4, "rsq_f32": LANE_ISSUE_PER_S / 4,
+                 "fma_f64": LANE_ISSUE_PER_S}
+
+
+def trans_seconds_per_pair(rates: dict) -> float:
+    return sum(n / rates[op] for op, n in TRANS_PER_PAIR.items())
+
+
+def model_pairs_per_s(rates: dict | None = None) -> float:
+    """Issue-bound model peak of FP32 point-pair evaluations per second."""
+    rates = rates or QUARTER_RATES
+    return 1.0 / (FLOPS_PER_PAIR / (PEAK_FP32_TFLOPS * 1e12) + trans_seconds_per_pair(rates))
+
+
+def flop_eq_per_pair(rates: dict | None = None) -> float:
+    """Flop-equivalents per pair at the P32 rate (transcendentals priced by
+    their measured issue rate)."""
+    rates = rates or QUARTER_RATES
+    return FLOPS_PER_PAIR + PEAK_FP32_TFLOPS * 1e12 * trans_seconds_per_pair(rates)
 
 
 def adjacent_ordered_pairs(triangles: np.ndarray) -> int:
@@ -62,8 +90,23 @@ def far_pairs_per_matvec(triangles: np.ndarray) -> int:
 
 
 def pair_kernel_roofline(point_pairs: int, seconds_per_launch: float,
-                         precision: str = "fp32") -> dict:
-    achieved = point_pairs * FLOP_EQ_PER_PAIR / seconds_per_launch / 1e12
-    peak = PEAK_FP32_PLAIN_TFLOPS if precision == "fp32" else PEAK_FP64_TFLOPS
-    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None}
+                         precision: str = "fp32", rates: dict | None = None) -> dict:
+    pairs_s = point_pairs / seconds_per_launch
+    if precision == "fp32":
+        fe = flop_eq_per_pair(rates)
+        achieved = pairs_s * fe / 1e12
+        out = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+               "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+               "flop_eq_per_pair": fe, "point_pairs_per_s": pairs_s,
+               "model_point_pairs_per_s": model_pairs_per_s(rates)}
+        r = rates or QUARTER_RATES
+        # issue utilisation of the kernel's own instruction stream
+        t_issue = KERNEL_VALU_PER_PAIR / r["fma_f32"] + trans_seconds_per_pair(r)
+        out["issue_frac"] = pairs_s * t_issue
+        out["rates_measured"] = rates is not None
+        return out
+    fe = FLOPS_PER_PAIR + sum(TRANS_PER_PAIR.values()) * FP64_SOFT_TRANS_FLOPS
+    achieved = pairs_s * fe / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "flop_eq_per_pair": fe,
+            "point_pairs_per_s": pairs_s}

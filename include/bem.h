@@ -38,6 +38,7 @@ typedef struct bem_mesh bem_mesh;
 enum {
     BEM_OK = 0,
     BEM_W_NOT_CONVERGED = 1,   /* best iterate written */
+    BEM_W_PENDING = 2,         /* bem_server_wait: not completed yet */
     BEM_E_INVAL = -1,          /* bad argument */
     BEM_E_BAD_MESH = -2,       /* not a closed, oriented, manifold surface */
     BEM_E_NOMEM = -3,          /* device allocation / budget exceeded */
@@ -181,6 +182,87 @@ int pmchwt_solve(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int,
 int bem_far_field(const bem_mesh *mesh, bem_c64 k_ext, const bem_c64 *solution,
                   const double *dirs, int n_dirs, bem_c64 *out,
                   void *hip_stream);
+
+/*
+ * Serving loop: a queue of solve requests run by a pool of worker threads,
+ * each with its own HIP stream, so that the work of several requests overlaps
+ * on the device.  Requests name a mesh registered with the server; each mesh
+ * keeps up to max_replicas device-resident handles, whose near-field, OSRC
+ * and dense-operator caches stay resident between requests.  A handle serves
+ * one request at a time.
+ *
+ * Admission: a request starts when a worker and a handle of its mesh are free
+ * and its device-memory footprint (an upper bound of what the solve
+ * allocates: near field, OSRC factors, scratch, Krylov basis for maxiter
+ * iterations, the dense operator on the assembled path) fits in the budget
+ * beside the resident state of all handles and the footprints of running
+ * requests.  When it does not fit, cached state of idle handles is released,
+ * least recently used first.  A request that cannot fit even on an idle
+ * server completes with status BEM_E_NOMEM.  Waiting requests are admitted in
+ * arrival order, except that a request that fits may pass one that does not
+ * while the latter has waited less than 2 s.
+ *
+ * Path: opts.path 2 (auto) with FP32 becomes the assembled path when the
+ * dense complex64 operator is at most dense_max_bytes, else matrix-free; the
+ * choice depends only on the request, so a result does not depend on the
+ * other requests in flight.
+ */
+typedef struct bem_server bem_server;
+
+typedef struct {
+    int64_t hbm_budget;      /* bytes; <= 0: 90 % of free device memory at creation */
+    int workers;             /* concurrent requests (threads, streams); <= 0: 4; max 64 */
+    int max_replicas;        /* handles per registered mesh; <= 0: workers */
+    int64_t dense_max_bytes; /* auto path limit for the assembled operator; < 0: 16 GiB */
+} bem_server_opts;
+
+typedef struct {
+    int status;              /* return code of the solve (BEM_OK, BEM_W_NOT_CONVERGED, < 0) */
+    int path;                /* 0 matrix-free, 1 assembled (FP32 inner operator) */
+    double t_submit;         /* seconds since server creation */
+    double t_admit;
+    double t_end;
+    int64_t footprint;       /* admission estimate, bytes */
+    int replica;             /* handle index within its mesh */
+} bem_request_stats;
+
+typedef struct {
+    int64_t budget;          /* bytes */
+    int64_t resident_bytes;  /* cached state of all handles */
+    int64_t reserved_bytes;  /* footprints of running requests */
+    int64_t peak_bytes;      /* max over time of resident + reserved */
+    int inflight, peak_inflight, queued;
+    int64_t completed, rejected;
+    int64_t evictions;       /* idle handles whose cached state was released */
+} bem_server_stats;
+
+void bem_server_opts_default(bem_server_opts *opts);
+/* Create on the current device; opts NULL = defaults. */
+int bem_server_create(const bem_server_opts *opts, bem_server **out);
+/* Waits for running requests; requests still queued complete with
+ * BEM_E_INVAL ("server shut down").  Handles of registered meshes are freed. */
+void bem_server_destroy(bem_server *srv);
+/* Register a mesh (same arguments and validation as bem_mesh_create); one
+ * handle is created and its OSRC symbolic analysis run now. */
+int bem_server_add_mesh(bem_server *srv, const double *vertices, int64_t n_vertices,
+                        const int32_t *triangles, int64_t n_triangles,
+                        const int32_t *object_id, int *mesh_id);
+/* Queue one solve (arguments as pmchwt_solve).  solution: caller-owned
+ * device [n_waves][2N]; info: caller-owned host [n_waves] or NULL; both must
+ * stay valid until bem_server_wait returns for this request.  directions and
+ * opts are copied.  Argument errors are returned here (nothing queued). */
+int bem_server_submit(bem_server *srv, int mesh_id, bem_c64 k_ext, bem_c64 k_int, double rho,
+                      const double *directions, int n_waves, double tol,
+                      const bem_solve_opts *opts, bem_c64 *solution, bem_solve_info *info,
+                      int64_t *request_id);
+/* Wait up to timeout_s seconds (< 0: forever).  Returns BEM_OK when the
+ * request has completed (its status, timing and path in *stats; the request
+ * is then forgotten), BEM_W_PENDING on time-out, BEM_E_INVAL for an unknown
+ * id.  When the request's status is an error, bem_last_error() on the waiting
+ * thread holds its message. */
+int bem_server_wait(bem_server *srv, int64_t request_id, double timeout_s,
+                    bem_request_stats *stats);
+int bem_server_stats_get(bem_server *srv, bem_server_stats *stats);
 
 /* Kernel timing with HIP events recorded on the launch stream, for the named
  * kernel ("farfield_fp32", "farfield_fp64", "nearfield_spmv", ...).

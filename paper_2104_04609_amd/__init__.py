@@ -5,12 +5,14 @@ mesh state, the matrix-free permuted PMCHWT Galerkin matvec, the OSRC Pade
 preconditioner, plane-wave right-hand sides, the preconditioned GMRES solve
 and the far field.  All arithmetic runs in the library's HIP kernels.
 """
-from ._binding import (BEM_FP32, BEM_FP32_DENSE, BEM_FP64, BemError, Mesh, SolveInfo, SolveOpts,
+from ._binding import (BEM_FP32, BEM_FP32_DENSE, BEM_FP64, BemError, Mesh, Server, SolveInfo,
+                       SolveOpts,
                        default_opts, far_field, lib, osrc_apply, pmchwt_matvec,
                        pmchwt_rhs, pmchwt_solve, profile_enable, profile_read,
                        valu_rates)
 
-__all__ = ["BEM_FP32", "BEM_FP32_DENSE", "BEM_FP64", "BemError", "Mesh", "SolveInfo", "SolveOpts",
+__all__ = ["BEM_FP32", "BEM_FP32_DENSE", "BEM_FP64", "BemError", "Mesh", "Server", "SolveInfo",
+           "SolveOpts",
            "default_opts", "far_field", "lib", "osrc_apply", "pmchwt_matvec",
            "pmchwt_rhs", "pmchwt_solve", "profile_enable", "profile_read",
            "valu_rates"]

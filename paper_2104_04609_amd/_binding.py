@@ -25,7 +25,7 @@ lib = ctypes.CDLL(LIB_PATH)
 BEM_FP64, BEM_FP32, BEM_FP32_DENSE = 0, 1, 2
 _PREC = {"fp64": BEM_FP64, "fp32": BEM_FP32, "fp32_dense": BEM_FP32_DENSE,
          BEM_FP64: BEM_FP64, BEM_FP32: BEM_FP32, BEM_FP32_DENSE: BEM_FP32_DENSE}
-ERRORS = {1: "BEM_W_NOT_CONVERGED", -1: "BEM_E_INVAL", -2: "BEM_E_BAD_MESH",
+ERRORS = {1: "BEM_W_NOT_CONVERGED", 2: "BEM_W_PENDING", -1: "BEM_E_INVAL", -2: "BEM_E_BAD_MESH",
           -3: "BEM_E_NOMEM", -4: "BEM_E_DEVICE", -5: "BEM_E_NAN",
           -6: "BEM_E_UNSUPPORTED"}
 
@@ -56,6 +56,31 @@ class SolveInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_int64), ("workers", ctypes.c_int),
+                ("max_replicas", ctypes.c_int), ("dense_max_bytes", ctypes.c_int64)]
+
+
+class RequestStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("path", ctypes.c_int), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_end", ctypes.c_double),
+                ("footprint", ctypes.c_int64), ("replica", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("budget", ctypes.c_int64), ("resident_bytes", ctypes.c_int64),
+                ("reserved_bytes", ctypes.c_int64), ("peak_bytes", ctypes.c_int64),
+                ("inflight", ctypes.c_int), ("peak_inflight", ctypes.c_int),
+                ("queued", ctypes.c_int), ("completed", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("evictions", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
 lib.bem_mesh_create.argtypes = [_vp, _i64, _vp, _i64, _vp, ctypes.POINTER(_vp)]
@@ -77,6 +102,17 @@ lib.bem_profile_enable.argtypes = [ctypes.c_int]
 lib.bem_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(_i64)]
 lib.bem_valu_rates.argtypes = [_vp, _vp]
+lib.bem_server_opts_default.argtypes = [ctypes.POINTER(ServerOpts)]
+lib.bem_server_opts_default.restype = None
+lib.bem_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)]
+lib.bem_server_destroy.argtypes = [_vp]
+lib.bem_server_destroy.restype = None
+lib.bem_server_add_mesh.argtypes = [_vp, _vp, _i64, _vp, _i64, _vp, ctypes.POINTER(ctypes.c_int)]
+lib.bem_server_submit.argtypes = [_vp, ctypes.c_int, c64, c64, ctypes.c_double, _vp, ctypes.c_int,
+                                  ctypes.c_double, ctypes.POINTER(SolveOpts), _vp, _vp,
+                                  ctypes.POINTER(_i64)]
+lib.bem_server_wait.argtypes = [_vp, _i64, ctypes.c_double, ctypes.POINTER(RequestStats)]
+lib.bem_server_stats_get.argtypes = [_vp, ctypes.POINTER(ServerStats)]
 lib.bem_last_error.restype = ctypes.c_char_p
 lib.bem_last_error.argtypes = []
 
@@ -230,6 +266,82 @@ def far_field(mesh: Mesh, k_ext, solution, dirs, stream=None) -> np.ndarray:
     _check(lib.bem_far_field(mesh.handle, _c(k_ext), _vp(solution.data_ptr()),
                              _np_ptr(d), d.shape[0], _np_ptr(out), _stream(stream)))
     return out
+
+
+class Server:
+    """Serving loop (bem_server_*): queued solves on worker streams with
+    device-memory admission and resident per-mesh state."""
+
+    def __init__(self, hbm_budget: int = 0, workers: int = 4, max_replicas: int = 0,
+                 dense_max_bytes: int = -1):
+        o = ServerOpts()
+        lib.bem_server_opts_default(ctypes.byref(o))
+        o.hbm_budget, o.workers = int(hbm_budget), int(workers)
+        o.max_replicas, o.dense_max_bytes = int(max_replicas), int(dense_max_bytes)
+        h = _vp()
+        self._h = None
+        _check(lib.bem_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._meshes = {}      # mesh id -> number of vertices
+        self._pending = {}     # request id -> (solution tensor, info array)
+
+    def add_mesh(self, vertices, triangles, object_id=None) -> int:
+        P = np.ascontiguousarray(vertices, dtype=np.float64)
+        T = np.ascontiguousarray(triangles, dtype=np.int32)
+        O = None if object_id is None else np.ascontiguousarray(object_id, np.int32)
+        if P.ndim != 2 or P.shape[1] != 3 or T.ndim != 2 or T.shape[1] != 3:
+            raise ValueError("vertices [N,3] and triangles [T,3] expected")
+        mid = ctypes.c_int()
+        _check(lib.bem_server_add_mesh(self._h, _np_ptr(P), P.shape[0], _np_ptr(T), T.shape[0],
+                                       _np_ptr(O) if O is not None else None, ctypes.byref(mid)))
+        self._meshes[mid.value] = P.shape[0]
+        return mid.value
+
+    def submit(self, mesh_id: int, k_ext, k_int, rho: float, directions, tol: float,
+               opts: Optional[SolveOpts] = None, **overrides) -> int:
+        import torch
+        d = np.ascontiguousarray(np.atleast_2d(directions), dtype=np.float64)
+        o = default_opts() if opts is None else opts
+        for k, v in overrides.items():
+            if k == "precision":
+                v = _PREC[v]
+            setattr(o, k, v)
+        n = self._meshes.get(mesh_id, 1)   # an unknown id is rejected by the library
+        sol = torch.empty((d.shape[0], 2 * n), dtype=torch.complex128, device="cuda")
+        infos = (SolveInfo * d.shape[0])()
+        rid = _i64()
+        _check(lib.bem_server_submit(self._h, int(mesh_id), _c(k_ext), _c(k_int), float(rho),
+                                     _np_ptr(d), d.shape[0], float(tol), ctypes.byref(o),
+                                     _vp(sol.data_ptr()), ctypes.cast(infos, _vp),
+                                     ctypes.byref(rid)))
+        self._pending[rid.value] = (sol, infos)
+        return rid.value
+
+    def wait(self, request_id: int, timeout: float = -1.0):
+        """(solution, infos, stats) when done, None on time-out."""
+        st = RequestStats()
+        rc = _check(lib.bem_server_wait(self._h, int(request_id), float(timeout),
+                                        ctypes.byref(st)))
+        if rc == 2:
+            return None
+        sol, infos = self._pending.pop(request_id)
+        stats = st.as_dict()
+        if st.status < 0:
+            stats["error"] = f"{ERRORS.get(st.status, st.status)}: {lib.bem_last_error().decode()}"
+        return sol, [i.as_dict() for i in infos], stats
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib.bem_server_stats_get(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.bem_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
 
 
 def profile_enable(on: bool = True):

@@ -53,6 +53,19 @@ Timer::~Timer() {
 
 bem_mesh::~bem_mesh() = default;
 
+namespace bem {
+void mesh_trim(bem_mesh *m) {
+    m->near_cache.clear();
+    m->dense_cache.clear();
+    m->osrc_cache.clear();
+    m->xs32.release();
+    m->dyn64.release();
+    m->dyn32.release();
+    m->partial.release();
+    m->trirows.release();
+}
+}   // namespace bem
+
 int64_t bem_mesh::device_bytes() const {
     int64_t b = geo64.bytes() + geo32.bytes() + tst.bytes() + tobj_d.bytes() + tri_d.bytes() +
                 star_ptr.bytes() + star_idx.bytes() + near_pairs.bytes() + nf_rowptr.bytes() +

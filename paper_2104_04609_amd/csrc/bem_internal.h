@@ -197,6 +197,9 @@ namespace bem {
 void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
                     double rho, const double2 *x, double2 *y, int precision,
                     hipStream_t s);
+// device scratch (source records, split partials, triangle rows) that
+// farfield_apply needs for this precision and wavenumber pair
+int64_t farfield_scratch_bytes(const bem_mesh *m, int precision, double2 k0, double2 k1);
 // nearfield.hip
 std::unique_ptr<NearOperator> nearfield_build(bem_mesh *m, double2 k0, double2 k1,
                                               double rho, hipStream_t s);
@@ -204,6 +207,7 @@ const NearOperator &nearfield_get(bem_mesh *m, double2 k0, double2 k1, double rh
                                   hipStream_t s);
 // dense.hip
 int64_t dense_bytes(const bem_mesh *m);
+int64_t dense_assembly_scratch_bytes(const bem_mesh *m);
 std::unique_ptr<DenseOperator> dense_assemble(bem_mesh *m, const NearOperator &nf, double2 k0,
                                               double2 k1, double rho, hipStream_t s);
 const DenseOperator &dense_get(bem_mesh *m, double2 k0, double2 k1, double rho, hipStream_t s);
@@ -234,6 +238,26 @@ void osrc_apply_from_weak(bem_mesh *m, OsrcState &st, const double2 *yw,
                           double2 *z, hipStream_t s);
 void osrc_mass_solve(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y,
                      int nblocks, hipStream_t s);
+// symbolic analysis of the OSRC systems (once per mesh handle)
+void osrc_prepare(bem_mesh *m);
+// device bytes of one OSRC factor state with np Pade terms (runs the symbolic
+// analysis if needed)
+int64_t osrc_state_bytes(bem_mesh *m, int np);
+// solve.cpp
+// Validated OSRC-preconditioned solve (the body of pmchwt_solve); throws Error.
+int solve_run(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dirs,
+              int n_waves, double tol, const bem_solve_opts &o, double2 *solution,
+              bem_solve_info *info, hipStream_t s);
+void solve_check(const bem_mesh *m, double2 k0, double2 k1, double rho, const double *dirs,
+                 int n_waves, double tol, const bem_solve_opts &o);
+// Upper bound of the device memory one solve adds to a mesh handle with no
+// cached state (near field, OSRC factors, scratch, the dense operator when
+// o.path == 1 and FP32, the Krylov basis for o.maxiter iterations).
+int64_t solve_footprint(bem_mesh *m, double2 k0, double2 k1, double rho,
+                        const bem_solve_opts &o, int n_waves);
+// mesh.cpp: release cached operators and scratch (geometry and the OSRC
+// symbolic analysis stay)
+void mesh_trim(bem_mesh *m);
 // profiling (api.cpp)
 struct Timer {
     hipEvent_t a = nullptr, b = nullptr;

@@ -375,6 +375,9 @@ void launch_pairs(dim3 grid, hipStream_t s, bem_mesh *m, int j0, DCoef cf, float
 }   // namespace
 
 int64_t dense_bytes(const bem_mesh *m) { return 4 * m->N * m->N * (int64_t)sizeof(float2); }
+int64_t dense_assembly_scratch_bytes(const bem_mesh *m) {
+    return m->T * (int64_t)JT * 12 * (int64_t)sizeof(float2) + 2 * m->N * (int64_t)sizeof(float2);
+}
 
 std::unique_ptr<DenseOperator> dense_assemble(bem_mesh *m, const NearOperator &nf, double2 k0,
                                               double2 k1, double rho, hipStream_t s) {

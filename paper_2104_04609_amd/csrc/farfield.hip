@@ -575,20 +575,47 @@ int farfield_splits(int T, int slots) {
     return best;
 }
 
+namespace {
+
+// Launch plan of the pair kernel for one precision and wavenumber pair.
+struct FarPlan {
+    int code;      // 4 ck0 + 2 ck1 + multi
+    bool fr;       // phase reduction before v_sin/v_cos (FP32)
+    int nsplit;    // trial-triangle splits (grid.y)
+};
+
+FarPlan far_plan(const bem_mesh *m, int precision, double2 k0, double2 k1) {
+    FarPlan p;
+    const bool ck0 = k0.y != 0.0, ck1 = k1.y != 0.0, multi = m->nobj > 1;
+    p.code = (ck0 ? 4 : 0) | (ck1 ? 2 : 0) | (multi ? 1 : 0);
+    // largest phase in revolutions: max Re k * diameter / (2 pi)
+    const double tmax = std::max(std::fabs(k0.x), std::fabs(k1.x)) * m->diameter *
+                        0.15915494309189533576888376337251;
+    p.fr = precision != BEM_FP32 || tmax >= 256.0;
+    const void *kern = precision == BEM_FP32
+                           ? (p.fr ? far_kernel<float, true>(p.code)
+                                   : far_kernel<float, false>(p.code))
+                           : far_kernel<double, true>(p.code);
+    p.nsplit = farfield_splits((int)m->T, far_slots(kern));
+    return p;
+}
+
+}   // namespace
+
+int64_t farfield_scratch_bytes(const bem_mesh *m, int precision, double2 k0, double2 k1) {
+    const FarPlan p = far_plan(m, precision, k0, k1);
+    const int64_t T = m->T;
+    const int64_t dyn = T * DYN_STRIDE * (precision == BEM_FP32 ? 4 : 8);
+    return dyn + (int64_t)p.nsplit * T * (ROW_STRIDE + 6) * 8 + T * ROW_STRIDE * 8;
+}
+
 void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
                     double rho, const double2 *x, double2 *y, int precision,
                     hipStream_t s) {
     const int T = (int)m->T;
-    const bool ck0 = k0.y != 0.0, ck1 = k1.y != 0.0, multi = m->nobj > 1;
-    const int code = (ck0 ? 4 : 0) | (ck1 ? 2 : 0) | (multi ? 1 : 0);
-    // largest phase in revolutions: max Re k * diameter / (2 pi)
-    const double tmax = std::max(std::fabs(k0.x), std::fabs(k1.x)) * m->diameter *
-                        0.15915494309189533576888376337251;
-    const bool fr = tmax >= 256.0;
-    const void *kern = precision == BEM_FP32
-                           ? (fr ? far_kernel<float, true>(code) : far_kernel<float, false>(code))
-                           : far_kernel<double, true>(code);
-    const int nsplit = farfield_splits(T, far_slots(kern));
+    const FarPlan plan = far_plan(m, precision, k0, k1);
+    const int nsplit = plan.nsplit;
+    const bool ck0 = k0.y != 0.0, ck1 = k1.y != 0.0, multi = m->nobj > 1, fr = plan.fr;
     const int split_len = (T + nsplit - 1) / nsplit;
     const size_t need = (size_t)nsplit * T * (ROW_STRIDE + 6);
     if (m->partial.n < need) m->partial.alloc(need);

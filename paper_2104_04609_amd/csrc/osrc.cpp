@@ -167,6 +167,17 @@ LdlDev ldl_view(const OsrcSymbolicState &sy, const OsrcState &st) {
 
 }   // namespace
 
+void osrc_prepare(bem_mesh *m) { (void)symbolic(m); }
+
+int64_t osrc_state_bytes(bem_mesh *m, int np) {
+    const OsrcSymbolicState &sy = symbolic(m);
+    const int64_t n = sy.n, nnz = sy.sym.nnzL(), nd = sy.sym.ndense, nf = np + 2;
+    // cvert, Dinv, L (CSR + CSC), dense block inverses (+ transposes), work,
+    // shifted-solve outputs, tmp, wbuf; complex128 each
+    return (int64_t)sizeof(double2) *
+           (n + nf * (n + 2 * nnz + 2 * nd) + (np + 2) * n + np * n + 3 * n + 2 * n);
+}
+
 OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
                     const std::vector<double2> &keps_obj, hipStream_t s) {
     if ((int)keps_obj.size() != m->nobj) fail(BEM_E_INVAL, "one k_eps per object expected");

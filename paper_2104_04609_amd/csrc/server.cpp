@@ -1,0 +1,465 @@
+// Serving loop: queued solve requests, admission by a device-memory budget,
+// a pool of worker threads with one HIP stream each, and device-resident mesh
+// handles (geometry, near-field, OSRC and dense-operator caches) that persist
+// between requests.  Contract and policy are stated in bem.h.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "bem_internal.h"
+
+namespace bem {
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+constexpr double HEAD_PRIORITY_S = 2.0;   // after this wait, the oldest request blocks others
+
+struct Replica {
+    bem_mesh *h = nullptr;    // created lazily by the worker that first runs on it
+    bool busy = false;
+    int64_t resident = 0;     // device bytes of h while idle
+    uint64_t last_used = 0;   // admission tick
+};
+
+struct MeshEntry {
+    std::vector<double> P;
+    std::vector<int32_t> tri, obj;
+    bool has_obj = false;
+    int64_t nv = 0, nt = 0;
+    int64_t base_bytes = 0;   // a fresh handle after the OSRC symbolic analysis
+    std::vector<std::unique_ptr<Replica>> reps;
+};
+
+struct Request {
+    int64_t id = 0;
+    int mesh = 0;
+    double2 k0{}, k1{};
+    double rho = 0, tol = 0;
+    std::vector<double> dirs;
+    int n_waves = 0;
+    bem_solve_opts o{};
+    double2 *solution = nullptr;
+    bem_solve_info *info = nullptr;
+    int64_t footprint = 0;    // solve footprint (without creating a handle)
+    int64_t reserved = 0;     // footprint + handle creation when admitted
+    Replica *rep = nullptr;
+    int replica = -1;
+    double t_submit = 0, t_admit = 0, t_end = 0;
+    int status = BEM_OK;
+    std::string msg;
+    bool done = false;
+};
+
+void destroy_handle(bem_mesh *h) { delete h; }
+
+bem_mesh *create_handle(const MeshEntry &me) {
+    std::unique_ptr<bem_mesh> m(new bem_mesh());
+    mesh_build(m.get(), me.P.data(), me.nv, me.tri.data(), me.nt,
+               me.has_obj ? me.obj.data() : nullptr);
+    osrc_prepare(m.get());
+    return m.release();
+}
+
+}   // namespace
+
+}   // namespace bem
+
+struct bem_server {
+    bem_server_opts o{};
+    int device = 0;
+    bem::Clock::time_point t0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::shared_ptr<bem::Request>> queue;
+    std::map<int64_t, std::shared_ptr<bem::Request>> reqs;
+    std::vector<std::unique_ptr<bem::MeshEntry>> meshes;
+    std::vector<hipStream_t> streams;
+    std::vector<std::thread> threads;
+    bool stop = false;
+    int64_t next_id = 1;
+    uint64_t tick = 0;
+    int64_t reserved = 0, peak = 0;
+    int inflight = 0, peak_inflight = 0;
+    int64_t completed = 0, rejected = 0, evictions = 0;
+
+    double now() const {
+        return std::chrono::duration<double>(bem::Clock::now() - t0).count();
+    }
+    int64_t resident() const {
+        int64_t b = 0;
+        for (const auto &me : meshes)
+            for (const auto &r : me->reps) b += r->resident;
+        return b;
+    }
+    // Release cached state of idle handles, least recently used first, until
+    // `need` more bytes fit.  Returns whether they fit.
+    bool make_room(int64_t need) {
+        while (resident() + reserved + need > o.hbm_budget) {
+            bem::Replica *lru = nullptr;
+            bem::MeshEntry *lru_mesh = nullptr;
+            for (auto &me : meshes)
+                for (auto &r : me->reps)
+                    if (!r->busy && r->h && r->resident > me->base_bytes &&
+                        (!lru || r->last_used < lru->last_used)) {
+                        lru = r.get();
+                        lru_mesh = me.get();
+                    }
+            if (!lru) return false;
+            bem::mesh_trim(lru->h);
+            lru->resident = std::max(lru->h->device_bytes(), lru_mesh->base_bytes);
+            evictions++;
+        }
+        return true;
+    }
+    // Bytes that stay resident on an otherwise idle server (fresh handles).
+    int64_t floor_bytes() const {
+        int64_t b = 0;
+        for (const auto &me : meshes)
+            for (const auto &r : me->reps)
+                if (r->h) b += me->base_bytes;
+        return b;
+    }
+    void finish(const std::shared_ptr<bem::Request> &r) {
+        r->done = true;
+        r->t_end = now();
+        cv_done.notify_all();
+    }
+    // Next admissible request (lock held), or null.  Rejects requests that
+    // can never fit.
+    std::shared_ptr<bem::Request> admit() {
+        const double t = now();
+        for (size_t qi = 0; qi < queue.size();) {
+            if (qi > 0 && t - queue.front()->t_submit > bem::HEAD_PRIORITY_S) break;
+            auto r = queue[qi];
+            bem::MeshEntry &me = *meshes[r->mesh];
+            bem::Replica *pick = nullptr;
+            int pick_i = -1;
+            for (size_t i = 0; i < me.reps.size(); i++) {
+                bem::Replica *c = me.reps[i].get();
+                if (c->busy) continue;
+                if (!pick || (c->h && !pick->h) ||
+                    ((c->h != nullptr) == (pick->h != nullptr) && c->last_used > pick->last_used)) {
+                    pick = c;
+                    pick_i = (int)i;
+                }
+            }
+            const bool grow = !pick && (int)me.reps.size() < o.max_replicas;
+            if (!pick && !grow) {
+                qi++;
+                continue;
+            }
+            const bool fresh = grow || !pick->h;
+            const int64_t need = r->footprint + (fresh ? me.base_bytes : 0);
+            if (!make_room(need)) {
+                if (inflight == 0 && floor_bytes() + need > o.hbm_budget) {
+                    r->status = BEM_E_NOMEM;
+                    r->msg = "request footprint of " + std::to_string(need) +
+                             " bytes exceeds the server budget of " +
+                             std::to_string(o.hbm_budget) + " bytes";
+                    rejected++;
+                    queue.erase(queue.begin() + (long)qi);
+                    finish(r);
+                    continue;
+                }
+                qi++;
+                continue;
+            }
+            if (grow) {
+                me.reps.push_back(std::make_unique<bem::Replica>());
+                pick = me.reps.back().get();
+                pick_i = (int)me.reps.size() - 1;
+            }
+            pick->busy = true;
+            pick->last_used = ++tick;
+            r->rep = pick;
+            r->replica = pick_i;
+            r->reserved = need;
+            r->t_admit = t;
+            reserved += need;
+            inflight++;
+            peak_inflight = std::max(peak_inflight, inflight);
+            peak = std::max(peak, resident() + reserved);
+            queue.erase(queue.begin() + (long)qi);
+            return r;
+        }
+        return nullptr;
+    }
+
+    void worker(int wi) {
+        (void)hipSetDevice(device);
+        hipStream_t s = streams[wi];
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            std::shared_ptr<bem::Request> r;
+            while (!stop && !(r = admit()))
+                cv_work.wait_for(lk, std::chrono::milliseconds(50));
+            if (!r) return;
+            bem::MeshEntry &me = *meshes[r->mesh];
+            bem::Replica *rep = r->rep;
+            lk.unlock();
+            int status = BEM_OK;
+            std::string msg;
+            int64_t res = 0;
+            try {
+                if (!rep->h) rep->h = bem::create_handle(me);
+                status = bem::solve_run(rep->h, r->k0, r->k1, r->rho, r->dirs.data(), r->n_waves,
+                                        r->tol, r->o, r->solution, r->info, s);
+            } catch (const bem::Error &e) {
+                status = e.code;
+                msg = e.msg;
+            } catch (const std::bad_alloc &) {
+                status = BEM_E_NOMEM;
+                msg = "host allocation failed";
+            } catch (const std::exception &e) {
+                status = BEM_E_DEVICE;
+                msg = e.what();
+            }
+            if (status < 0) (void)hipStreamSynchronize(s);
+            if (rep->h) res = std::max(rep->h->device_bytes(), me.base_bytes);
+            lk.lock();
+            rep->busy = false;
+            rep->resident = res;
+            rep->last_used = ++tick;
+            reserved -= r->reserved;
+            inflight--;
+            completed++;
+            r->status = status;
+            r->msg = msg;
+            finish(r);
+            cv_work.notify_all();
+        }
+    }
+};
+
+using bem::fail;
+
+extern "C" {
+
+void bem_server_opts_default(bem_server_opts *o) {
+    if (!o) return;
+    o->hbm_budget = 0;
+    o->workers = 4;
+    o->max_replicas = 0;
+    o->dense_max_bytes = -1;
+}
+
+int bem_server_create(const bem_server_opts *opts, bem_server **out) {
+    try {
+        if (!out) fail(BEM_E_INVAL, "out is NULL");
+        *out = nullptr;
+        std::unique_ptr<bem_server> srv(new bem_server());
+        bem_server_opts_default(&srv->o);
+        if (opts) srv->o = *opts;
+        bem_server_opts &o = srv->o;
+        if (o.workers <= 0) o.workers = 4;
+        if (o.workers > 64) fail(BEM_E_INVAL, "workers must be at most 64");
+        if (o.max_replicas <= 0) o.max_replicas = o.workers;
+        if (o.dense_max_bytes < 0) o.dense_max_bytes = 16ll << 30;
+        BEM_HIP(hipGetDevice(&srv->device));
+        if (o.hbm_budget <= 0) {
+            size_t free_b = 0, total_b = 0;
+            BEM_HIP(hipMemGetInfo(&free_b, &total_b));
+            o.hbm_budget = (int64_t)(0.9 * (double)free_b);
+        }
+        srv->t0 = bem::Clock::now();
+        for (int i = 0; i < o.workers; i++) {
+            hipStream_t s = nullptr;
+            BEM_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+            srv->streams.push_back(s);
+        }
+        bem_server *raw = srv.get();
+        for (int i = 0; i < o.workers; i++) srv->threads.emplace_back([raw, i] { raw->worker(i); });
+        *out = srv.release();
+        return BEM_OK;
+    } catch (const bem::Error &e) {
+        bem::set_last_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        bem::set_last_error("host allocation failed");
+        return BEM_E_NOMEM;
+    }
+}
+
+void bem_server_destroy(bem_server *srv) {
+    if (!srv) return;
+    {
+        std::lock_guard<std::mutex> g(srv->mu);
+        srv->stop = true;
+        for (auto &r : srv->queue) {
+            r->status = BEM_E_INVAL;
+            r->msg = "server shut down";
+            srv->finish(r);
+        }
+        srv->queue.clear();
+    }
+    srv->cv_work.notify_all();
+    for (auto &t : srv->threads) t.join();
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(srv->device);
+    for (auto &me : srv->meshes)
+        for (auto &r : me->reps) bem::destroy_handle(r->h);
+    for (hipStream_t s : srv->streams) (void)hipStreamDestroy(s);
+    (void)hipSetDevice(prev);
+    delete srv;
+}
+
+int bem_server_add_mesh(bem_server *srv, const double *vertices, int64_t n_vertices,
+                        const int32_t *triangles, int64_t n_triangles,
+                        const int32_t *object_id, int *mesh_id) {
+    int prev = -1;
+    try {
+        if (!srv || !mesh_id) fail(BEM_E_INVAL, "server or mesh_id is NULL");
+        if (!vertices || !triangles || n_vertices < 3 || n_triangles < 4)
+            fail(BEM_E_INVAL, "bad mesh arrays");
+        auto me = std::make_unique<bem::MeshEntry>();
+        me->P.assign(vertices, vertices + 3 * n_vertices);
+        me->tri.assign(triangles, triangles + 3 * n_triangles);
+        me->has_obj = object_id != nullptr;
+        if (object_id) me->obj.assign(object_id, object_id + n_triangles);
+        me->nv = n_vertices;
+        me->nt = n_triangles;
+        BEM_HIP(hipGetDevice(&prev));
+        BEM_HIP(hipSetDevice(srv->device));
+        auto rep = std::make_unique<bem::Replica>();
+        rep->h = bem::create_handle(*me);
+        me->base_bytes = rep->h->device_bytes();
+        rep->resident = me->base_bytes;
+        me->reps.push_back(std::move(rep));
+        (void)hipSetDevice(prev);
+        prev = -1;
+        std::lock_guard<std::mutex> g(srv->mu);
+        srv->meshes.push_back(std::move(me));
+        *mesh_id = (int)srv->meshes.size() - 1;
+        return BEM_OK;
+    } catch (const bem::Error &e) {
+        if (prev >= 0) (void)hipSetDevice(prev);
+        bem::set_last_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        if (prev >= 0) (void)hipSetDevice(prev);
+        bem::set_last_error("host allocation failed");
+        return BEM_E_NOMEM;
+    }
+}
+
+int bem_server_submit(bem_server *srv, int mesh_id, bem_c64 k_ext, bem_c64 k_int, double rho,
+                      const double *directions, int n_waves, double tol,
+                      const bem_solve_opts *opts, bem_c64 *solution, bem_solve_info *info,
+                      int64_t *request_id) {
+    int prev = -1;
+    try {
+        if (!srv || !request_id) fail(BEM_E_INVAL, "server or request_id is NULL");
+        if (!solution) fail(BEM_E_INVAL, "solution is NULL");
+        bem::MeshEntry *me = nullptr;
+        bem_mesh *h0 = nullptr;
+        {
+            std::lock_guard<std::mutex> g(srv->mu);
+            if (srv->stop) fail(BEM_E_INVAL, "server is shutting down");
+            if (mesh_id < 0 || mesh_id >= (int)srv->meshes.size()) fail(BEM_E_INVAL, "mesh_id");
+            me = srv->meshes[mesh_id].get();
+            h0 = me->reps[0]->h;   // replica 0 is never released; its sizes are immutable
+        }
+        auto r = std::make_shared<bem::Request>();
+        r->mesh = mesh_id;
+        r->k0 = make_double2(k_ext.re, k_ext.im);
+        r->k1 = make_double2(k_int.re, k_int.im);
+        r->rho = rho;
+        r->tol = tol;
+        r->n_waves = n_waves;
+        bem_solve_opts_default(&r->o);
+        if (opts) r->o = *opts;
+        bem::solve_check(h0, r->k0, r->k1, rho, directions, n_waves, tol, r->o);
+        r->dirs.assign(directions, directions + 3 * n_waves);
+        r->solution = (double2 *)solution;
+        r->info = info;
+        // the path depends on the request alone
+        if (r->o.precision == BEM_FP32 && r->o.path == 2)
+            r->o.path = bem::dense_bytes(h0) <= srv->o.dense_max_bytes ? 1 : 0;
+        BEM_HIP(hipGetDevice(&prev));
+        BEM_HIP(hipSetDevice(srv->device));
+        r->footprint = bem::solve_footprint(h0, r->k0, r->k1, rho, r->o, n_waves);
+        (void)hipSetDevice(prev);
+        prev = -1;
+        {
+            std::lock_guard<std::mutex> g(srv->mu);
+            if (srv->stop) fail(BEM_E_INVAL, "server is shutting down");
+            r->id = srv->next_id++;
+            r->t_submit = srv->now();
+            srv->reqs[r->id] = r;
+            srv->queue.push_back(r);
+            *request_id = r->id;
+        }
+        srv->cv_work.notify_all();
+        return BEM_OK;
+    } catch (const bem::Error &e) {
+        if (prev >= 0) (void)hipSetDevice(prev);
+        bem::set_last_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        if (prev >= 0) (void)hipSetDevice(prev);
+        bem::set_last_error("host allocation failed");
+        return BEM_E_NOMEM;
+    }
+}
+
+int bem_server_wait(bem_server *srv, int64_t request_id, double timeout_s,
+                    bem_request_stats *stats) {
+    if (!srv) {
+        bem::set_last_error("server is NULL");
+        return BEM_E_INVAL;
+    }
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(request_id);
+    if (it == srv->reqs.end()) {
+        bem::set_last_error("unknown request id " + std::to_string(request_id));
+        return BEM_E_INVAL;
+    }
+    std::shared_ptr<bem::Request> r = it->second;
+    auto done = [&] { return r->done; };
+    if (timeout_s < 0) srv->cv_done.wait(lk, done);
+    else if (!srv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done))
+        return BEM_W_PENDING;
+    if (stats) {
+        stats->status = r->status;
+        stats->path = r->o.precision == BEM_FP32 && r->o.path == 1 ? 1 : 0;
+        stats->t_submit = r->t_submit;
+        stats->t_admit = r->t_admit;
+        stats->t_end = r->t_end;
+        stats->footprint = r->reserved > 0 ? r->reserved : r->footprint;
+        stats->replica = r->replica;
+    }
+    if (r->status < 0) bem::set_last_error(r->msg);
+    srv->reqs.erase(it);
+    return BEM_OK;
+}
+
+int bem_server_stats_get(bem_server *srv, bem_server_stats *st) {
+    if (!srv || !st) {
+        bem::set_last_error("server or stats is NULL");
+        return BEM_E_INVAL;
+    }
+    std::lock_guard<std::mutex> g(srv->mu);
+    st->budget = srv->o.hbm_budget;
+    st->resident_bytes = srv->resident();
+    st->reserved_bytes = srv->reserved;
+    st->peak_bytes = srv->peak;
+    st->inflight = srv->inflight;
+    st->peak_inflight = srv->peak_inflight;
+    st->queued = (int)srv->queue.size();
+    st->completed = srv->completed;
+    st->rejected = srv->rejected;
+    st->evictions = srv->evictions;
+    return BEM_OK;
+}
+
+}   // extern "C"

@@ -156,7 +156,149 @@ double2 damped(double2 k, double R) {
     return make_double2(ke.real(), ke.imag());
 }
 
+// Krylov basis capacity after growing to `need` vectors (Workspace::ensure).
+int64_t workspace_peak_vectors(int maxiter) {
+    int cap = 0;
+    int64_t peak = 0;
+    auto ensure = [&](int need) {
+        if (need <= cap + 1) return;
+        const int ncap = std::max(need - 1, std::max(2 * cap, 64));
+        peak = std::max<int64_t>(peak, (int64_t)(cap + 1) + (ncap + 1));   // old + new
+        cap = ncap;
+    };
+    ensure(2);
+    ensure(maxiter + 1);
+    return std::max<int64_t>(peak, cap + 1);
+}
+
 }   // namespace
+
+void solve_check(const bem_mesh *m, double2 k0, double2 k1, double rho, const double *dirs,
+                 int n_waves, double tol, const bem_solve_opts &o) {
+    if (!m) fail(BEM_E_INVAL, "mesh is NULL");
+    if (!dirs || n_waves < 1) fail(BEM_E_INVAL, "bad directions");
+    if (!(tol > 0) || !std::isfinite(tol)) fail(BEM_E_INVAL, "tol must be positive");
+    if (!(rho > 0) || !std::isfinite(rho)) fail(BEM_E_INVAL, "rho must be positive");
+    for (double2 k : {k0, k1})
+        if (!std::isfinite(k.x) || !std::isfinite(k.y) || k.y < 0 || (k.x == 0 && k.y == 0))
+            fail(BEM_E_INVAL, "wavenumbers must be finite, nonzero, Im k >= 0");
+    if (o.pade_terms < 1 || o.pade_terms > PADE_MAX) fail(BEM_E_INVAL, "pade_terms");
+    if (o.precision != BEM_FP64 && o.precision != BEM_FP32) fail(BEM_E_INVAL, "precision");
+    if (o.maxiter < 1 || o.max_outer < 1 || !(o.inner_tol > 0)) fail(BEM_E_INVAL, "opts");
+    if (o.path < 0 || o.path > 2) fail(BEM_E_INVAL, "path must be 0, 1 or 2");
+    for (int w = 0; w < n_waves; w++) {
+        const double *d = dirs + 3 * w;
+        if (!(std::fabs(std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) - 1.0) < 1e-6))
+            fail(BEM_E_INVAL, "directions must be unit vectors");
+    }
+}
+
+int64_t solve_footprint(bem_mesh *m, double2 k0, double2 k1, double rho,
+                        const bem_solve_opts &o, int n_waves) {
+    (void)rho;
+    const int64_t n2 = 2 * m->N, c16 = (int64_t)sizeof(double2);
+    int64_t b = 4 * m->nf_nnz * c16;                          // near-field CSR values
+    b += osrc_state_bytes(m, o.pade_terms);                    // OSRC factors
+    int64_t scratch = farfield_scratch_bytes(m, BEM_FP64, k0, k1);
+    const bool dense = o.precision == BEM_FP32 && o.path == 1;
+    if (o.precision == BEM_FP32 && !dense)
+        scratch = std::max(scratch, farfield_scratch_bytes(m, BEM_FP32, k0, k1)) +
+                  m->T * DYN_STRIDE * 4;                      // dyn32 beside dyn64
+    b += scratch;
+    if (dense) b += dense_bytes(m) + dense_assembly_scratch_bytes(m);
+    b += ((int64_t)n_waves + 5) * n2 * c16;                    // f, yw, b, x, r, dx
+    b += workspace_peak_vectors(o.maxiter) * n2 * c16 + (2 * (int64_t)o.maxiter + 8) * c16;
+    return b;
+}
+
+int solve_run(bem_mesh *m, double2 k0, double2 k1, double rho, const double *directions,
+              int n_waves, double tol, const bem_solve_opts &o, double2 *solution,
+              bem_solve_info *info, hipStream_t s) {
+    solve_check(m, k0, k1, rho, directions, n_waves, tol, o);
+    if (!solution) fail(BEM_E_INVAL, "solution is NULL");
+    const int64_t n2 = 2 * m->N;
+    const NearOperator &nf = nearfield_get(m, k0, k1, rho, s);
+    const double2 ko = o.osrc_interior ? k1 : k0;
+    std::vector<double2> keps(m->nobj);
+    for (int ob = 0; ob < m->nobj; ob++)
+        keps[ob] = damped(ko, o.R > 0 ? o.R : 0.1 * m->obj_radius[ob]);
+    OsrcState &st = osrc_get(m, o.pade_terms, o.theta, ko, keps, s);
+
+    DevBuf<double2> f((size_t)n_waves * n2), yw(n2), b(n2), x(n2), r(n2), dx(n2);
+    rhs_project(m, k0, directions, n_waves, f.p, s);
+    Op op{m, &nf, k0, k1, rho, &st, s, yw.p};
+    int inner = BEM_FP32;
+    if (o.precision == BEM_FP32 && o.path != 0) {
+        bool use = o.path == 1;
+        if (o.path == 2) {   // dense when it fits with room to spare
+            size_t free_b = 0, total_b = 0;
+            BEM_HIP(hipMemGetInfo(&free_b, &total_b));
+            use = dense_bytes(m) + (int64_t)(2ll << 30) < (int64_t)free_b ||
+                  !m->dense_cache.empty();
+        }
+        if (use) {
+            op.dense = &dense_get(m, k0, k1, rho, s);
+            inner = BEM_FP32_DENSE;
+        }
+    }
+    Workspace ws;
+    ws.n2 = n2;
+    ws.ensure(2, s);
+    int worst = BEM_OK;
+    for (int w = 0; w < n_waves; w++) {
+        auto t0 = std::chrono::steady_clock::now();
+        op.n64 = op.n32 = 0;
+        osrc_apply_from_weak(m, st, f.p + (size_t)w * n2, b.p, s);
+        const double bn = dev_norm(b.p, n2, ws.h.p, s);
+        int total_it = 0, outer = 0;
+        double rel = 0.0;
+        bool conv = false;
+        if (o.precision == BEM_FP64) {
+            int it;
+            double est;
+            conv = gmres(op, BEM_FP64, b.p, x.p, n2, tol, o.maxiter, ws, it, est, s);
+            total_it = it;
+            outer = 1;
+            op.apply(x.p, r.p, BEM_FP64);   // true residual with the FP64 operator
+            blas_axpby(make_double2(1, 0), b.p, make_double2(-1, 0), r.p, r.p, n2, s);
+            rel = bn > 0 ? dev_norm(r.p, n2, ws.h.p, s) / bn : 0.0;
+        } else {
+            BEM_HIP(hipMemsetAsync(x.p, 0, n2 * sizeof(double2), s));
+            BEM_HIP(hipMemcpyAsync(r.p, b.p, n2 * sizeof(double2), hipMemcpyDeviceToDevice, s));
+            double rn = bn;
+            rel = bn > 0 ? 1.0 : 0.0;
+            while (rel > tol && outer < o.max_outer && total_it < o.maxiter) {
+                const double eta = std::min(0.5, o.inner_tol * tol * bn / rn);
+                int it;
+                double est;
+                gmres(op, inner, r.p, dx.p, n2, eta, o.maxiter - total_it, ws, it, est, s);
+                total_it += it;
+                outer++;
+                blas_axpby(make_double2(1, 0), x.p, make_double2(1, 0), dx.p, x.p, n2, s);
+                op.apply(x.p, r.p, BEM_FP64);
+                blas_axpby(make_double2(1, 0), b.p, make_double2(-1, 0), r.p, r.p, n2, s);
+                rn = dev_norm(r.p, n2, ws.h.p, s);
+                rel = rn / bn;
+            }
+            conv = rel <= tol;
+        }
+        BEM_HIP(hipMemcpyAsync(solution + (size_t)w * n2, x.p, n2 * sizeof(double2),
+                               hipMemcpyDeviceToDevice, s));
+        BEM_HIP(hipStreamSynchronize(s));
+        const double secs =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (info) {
+            info[w].iterations = total_it;
+            info[w].outer_steps = outer;
+            info[w].fp64_matvecs = op.n64;
+            info[w].fp32_matvecs = op.n32;
+            info[w].rel_residual = rel;
+            info[w].seconds = secs;
+        }
+        if (!conv && rel > tol) worst = BEM_W_NOT_CONVERGED;
+    }
+    return worst;
+}
 
 }   // namespace bem
 
@@ -184,108 +326,12 @@ int pmchwt_solve(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
     try {
         if (!mesh) fail(BEM_E_INVAL, "mesh is NULL");
         if (!directions || !solution || n_waves < 1) fail(BEM_E_INVAL, "bad directions/solution");
-        if (!(tol > 0) || !std::isfinite(tol)) fail(BEM_E_INVAL, "tol must be positive");
-        if (!(rho > 0) || !std::isfinite(rho)) fail(BEM_E_INVAL, "rho must be positive");
-        for (bem_c64 k : {k_ext, k_int})
-            if (!std::isfinite(k.re) || !std::isfinite(k.im) || k.im < 0 || (k.re == 0 && k.im == 0))
-                fail(BEM_E_INVAL, "wavenumbers must be finite, nonzero, Im k >= 0");
         bem_solve_opts o;
         bem_solve_opts_default(&o);
         if (opts_in) o = *opts_in;
-        if (o.pade_terms < 1 || o.pade_terms > bem::PADE_MAX) fail(BEM_E_INVAL, "pade_terms");
-        if (o.precision != BEM_FP64 && o.precision != BEM_FP32) fail(BEM_E_INVAL, "precision");
-        if (o.maxiter < 1 || o.max_outer < 1 || !(o.inner_tol > 0)) fail(BEM_E_INVAL, "opts");
-        if (o.path < 0 || o.path > 2) fail(BEM_E_INVAL, "path must be 0, 1 or 2");
-        for (int w = 0; w < n_waves; w++) {
-            const double *d = directions + 3 * w;
-            if (!(std::fabs(std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) - 1.0) < 1e-6))
-                fail(BEM_E_INVAL, "directions must be unit vectors");
-        }
-        bem_mesh *m = const_cast<bem_mesh *>(mesh);
-        hipStream_t s = (hipStream_t)hip_stream;
-        const int64_t n2 = 2 * m->N;
-        const double2 k0 = make_double2(k_ext.re, k_ext.im), k1 = make_double2(k_int.re, k_int.im);
-        const bem::NearOperator &nf = bem::nearfield_get(m, k0, k1, rho, s);
-        const double2 ko = o.osrc_interior ? k1 : k0;
-        std::vector<double2> keps(m->nobj);
-        for (int ob = 0; ob < m->nobj; ob++)
-            keps[ob] = bem::damped(ko, o.R > 0 ? o.R : 0.1 * m->obj_radius[ob]);
-        bem::OsrcState &st = bem::osrc_get(m, o.pade_terms, o.theta, ko, keps, s);
-
-        bem::DevBuf<double2> f((size_t)n_waves * n2), yw(n2), b(n2), x(n2), r(n2), dx(n2);
-        bem::rhs_project(m, k0, directions, n_waves, f.p, s);
-        bem::Op op{m, &nf, k0, k1, rho, &st, s, yw.p};
-        int inner = BEM_FP32;
-        if (o.precision == BEM_FP32 && o.path != 0) {
-            bool use = o.path == 1;
-            if (o.path == 2) {   // dense when it fits with room to spare
-                size_t free_b = 0, total_b = 0;
-                BEM_HIP(hipMemGetInfo(&free_b, &total_b));
-                use = bem::dense_bytes(m) + (int64_t)(2ll << 30) < (int64_t)free_b ||
-                      !m->dense_cache.empty();
-            }
-            if (use) {
-                op.dense = &bem::dense_get(m, k0, k1, rho, s);
-                inner = BEM_FP32_DENSE;
-            }
-        }
-        bem::Workspace ws;
-        ws.n2 = n2;
-        ws.ensure(2, s);
-        int worst = BEM_OK;
-        for (int w = 0; w < n_waves; w++) {
-            auto t0 = std::chrono::steady_clock::now();
-            op.n64 = op.n32 = 0;
-            bem::osrc_apply_from_weak(m, st, f.p + (size_t)w * n2, b.p, s);
-            const double bn = bem::dev_norm(b.p, n2, ws.h.p, s);
-            int total_it = 0, outer = 0;
-            double rel = 0.0;
-            bool conv = false;
-            if (o.precision == BEM_FP64) {
-                int it;
-                double est;
-                conv = bem::gmres(op, BEM_FP64, b.p, x.p, n2, tol, o.maxiter, ws, it, est, s);
-                total_it = it;
-                outer = 1;
-                op.apply(x.p, r.p, BEM_FP64);   // true residual with the FP64 operator
-                bem::blas_axpby(make_double2(1, 0), b.p, make_double2(-1, 0), r.p, r.p, n2, s);
-                rel = bn > 0 ? bem::dev_norm(r.p, n2, ws.h.p, s) / bn : 0.0;
-            } else {
-                BEM_HIP(hipMemsetAsync(x.p, 0, n2 * sizeof(double2), s));
-                BEM_HIP(hipMemcpyAsync(r.p, b.p, n2 * sizeof(double2), hipMemcpyDeviceToDevice, s));
-                double rn = bn;
-                rel = bn > 0 ? 1.0 : 0.0;
-                while (rel > tol && outer < o.max_outer && total_it < o.maxiter) {
-                    const double eta = std::min(0.5, o.inner_tol * tol * bn / rn);
-                    int it;
-                    double est;
-                    bem::gmres(op, inner, r.p, dx.p, n2, eta, o.maxiter - total_it, ws, it, est, s);
-                    total_it += it;
-                    outer++;
-                    bem::blas_axpby(make_double2(1, 0), x.p, make_double2(1, 0), dx.p, x.p, n2, s);
-                    op.apply(x.p, r.p, BEM_FP64);
-                    bem::blas_axpby(make_double2(1, 0), b.p, make_double2(-1, 0), r.p, r.p, n2, s);
-                    rn = bem::dev_norm(r.p, n2, ws.h.p, s);
-                    rel = rn / bn;
-                }
-                conv = rel <= tol;
-            }
-            BEM_HIP(hipMemcpyAsync(solution + (size_t)w * n2, x.p, n2 * sizeof(double2),
-                                   hipMemcpyDeviceToDevice, s));
-            BEM_HIP(hipStreamSynchronize(s));
-            const double secs =
-                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-            if (info) {
-                info[w].iterations = total_it;
-                info[w].outer_steps = outer;
-                info[w].fp64_matvecs = op.n64;
-                info[w].fp32_matvecs = op.n32;
-                info[w].rel_residual = rel;
-                info[w].seconds = secs;
-            }
-            if (!conv && rel > tol) worst = BEM_W_NOT_CONVERGED;
-        }
-        return worst;
+        return bem::solve_run(const_cast<bem_mesh *>(mesh), make_double2(k_ext.re, k_ext.im),
+                              make_double2(k_int.re, k_int.im), rho, directions, n_waves, tol, o,
+                              (double2 *)solution, info, (hipStream_t)hip_stream);
     } catch (const bem::Error &e) {
         bem::set_last_error(e.msg);
         return e.code;

@@ -90,6 +90,72 @@ def batch_measure(P, M, mesh, mf_step_s):
     return out
 
 
+def serving_measure(P, n_requests: int, workers: int = 4, seed: int = 5) -> dict:
+    """Serving mix: meshes {icosphere L3, L4, L5, ellipsoid (geodesic 45
+    scaled by (1, 0.6, 0.4)), two level-4 spheres}, k_ext ~ U[1, 20],
+    k_int/k_ext ~ U[1.3, 1.9], rho ~ U[1.2, 2.0], 1-8 plane waves, tol 1e-6,
+    FP32 + refinement, auto path (seeded stream, seed 5).  A prefix of the
+    stream submitted at once gives the saturated solves/s; the whole stream
+    then arrives as a Poisson process at 0.7 x that rate."""
+    from bem_inputs import ellipsoid, geodesic_sphere, icosphere, request_stream, two_spheres
+    meshes = {"ico3": icosphere(3), "ico4": icosphere(4), "ico5": icosphere(5),
+              "ellipsoid45": ellipsoid(geodesic_sphere(45)),
+              "two_spheres4": two_spheres(4, offset=1.5)}
+    srv = P.Server(workers=workers)
+    ids = {k: srv.add_mesh(m.vertices, m.triangles, m.object_id) for k, m in meshes.items()}
+    reqs = request_stream(n_requests, seed=seed, rate=1.0)
+
+    def submit(r):
+        return srv.submit(ids[r["mesh"]], r["k_ext"], r["k_int"], r["rho"], r["directions"],
+                          1e-6, precision="fp32")
+
+    n_sat = max(8, n_requests // 4)
+    t0 = time.perf_counter()
+    for rid in [submit(r) for r in reqs[:n_sat]]:
+        srv.wait(rid)
+    sat = n_sat / (time.perf_counter() - t0)
+    print(f"serving: saturated {sat:.2f} solves/s over {n_sat} requests", file=sys.stderr,
+          flush=True)
+    lam = 0.7 * sat
+    t0 = time.perf_counter()
+    pending = []
+    for r in reqs:
+        dt = r["arrival"] / lam - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        pending.append((r, submit(r)))
+    results = [(r, srv.wait(rid)) for r, rid in pending]
+    elapsed = time.perf_counter() - t0
+    stats = srv.stats()
+    srv.close()
+    lat = np.array([st["t_end"] - st["t_submit"] for _, (_, _, st) in results])
+    queue_wait = np.array([st["t_admit"] - st["t_submit"] for _, (_, _, st) in results])
+    busy = sum(st["t_end"] - st["t_admit"] for _, (_, _, st) in results)
+    bad = [st for _, (_, info, st) in results
+           if st["status"] != 0 or max(i["rel_residual"] for i in info) > 1e-6]
+    by_mesh = {}
+    for r, (_, info, st) in results:
+        e = by_mesh.setdefault(r["mesh"], {"n": 0, "latency_s": [], "paths": set()})
+        e["n"] += 1
+        e["latency_s"].append(st["t_end"] - st["t_submit"])
+        e["paths"].add(st["path"])
+    return {
+        "requests": n_requests, "workers": workers, "seed": seed,
+        "saturated_solves_per_s": sat, "saturated_prefix": n_sat,
+        "arrival_rate_per_s": lam, "solves_per_s": n_requests / elapsed,
+        "waves_per_s": sum(len(r["directions"]) for r in reqs) / elapsed,
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "p50_queue_wait_s": float(np.percentile(queue_wait, 50)),
+        "mean_concurrency": busy / elapsed, "peak_inflight": stats["peak_inflight"],
+        "peak_bytes": stats["peak_bytes"], "budget": stats["budget"],
+        "evictions": stats["evictions"], "rejected": stats["rejected"],
+        "failed_or_unconverged": len(bad),
+        "per_mesh": {k: {"n": v["n"], "p50_latency_s": float(np.median(v["latency_s"])),
+                         "paths": sorted(v["paths"])} for k, v in by_mesh.items()},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +164,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-batching", action="store_true")
+    ap.add_argument("--serving", type=int, default=32, metavar="N",
+                    help="requests of the serving mix to replay (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB read + 256 MiB write elementwise kernel 3 times, "
                          "to scale HBM byte counters (FETCH_SIZE, WRITE_SIZE)")
@@ -192,6 +260,8 @@ def main():
     if not args.no_batching:
         batching = batch_measure(P, M, mesh, step_s)
 
+    serving = serving_measure(P, args.serving) if args.serving > 0 else None
+
     out = {
         "metric": METRIC, "value": value, "unit": "tri-pair evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_s * 1e3,
@@ -211,6 +281,7 @@ def main():
         "setup_s": setup_s,
         "solve": solve,
         "batching": batching,
+        "serving": serving,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh)

@@ -1,4 +1,5 @@
 // C ABI entry points: argument validation, error reporting, kernel timing.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -163,13 +164,7 @@ int pmchwt_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho
     const int64_t n2 = 2 * m->N;
     if (precision == BEM_FP32_DENSE) {
         const bem::DenseOperator &op = bem::dense_get(m, k0, k1, rho, s);
-        if (n_rhs >= bem::DENSE_GEMM_MIN_RHS) {
-            bem::dense_gemm(op, (const double2 *)x, (double2 *)y, n_rhs, s);
-        } else {
-            for (int r = 0; r < n_rhs; r++)
-                bem::dense_gemv(op, (const double2 *)x + r * n2, (double2 *)y + r * n2, m->xs32,
-                                s);
-        }
+        bem::dense_apply(op, (const double2 *)x, (double2 *)y, n_rhs, m->xs32, s);
         return BEM_OK;
     }
     for (int r = 0; r < n_rhs; r++)
@@ -198,8 +193,9 @@ int osrc_apply(const bem_mesh *mesh, int pade_terms, double theta, bem_c64 k,
     bem::OsrcState &st =
         bem::osrc_get(m, pade_terms, theta, make_double2(k.re, k.im), keps, s);
     const int64_t n2 = 2 * m->N;
-    for (int r = 0; r < n_rhs; r++)
-        bem::osrc_apply_strong(m, st, (const double2 *)x + r * n2, (double2 *)y + r * n2, s);
+    for (int r0 = 0; r0 < n_rhs; r0 += 16)   // batches of up to 16 right-hand sides
+        bem::osrc_apply_strong(m, st, (const double2 *)x + r0 * n2, (double2 *)y + r0 * n2,
+                               std::min(16, n_rhs - r0), s);
     return BEM_OK;
     BEM_API_END
 }

@@ -211,10 +211,16 @@ int64_t dense_assembly_scratch_bytes(const bem_mesh *m);
 std::unique_ptr<DenseOperator> dense_assemble(bem_mesh *m, const NearOperator &nf, double2 k0,
                                               double2 k1, double rho, hipStream_t s);
 const DenseOperator &dense_get(bem_mesh *m, double2 k0, double2 k1, double rho, hipStream_t s);
-void dense_gemv(const DenseOperator &op, const double2 *x, double2 *y, DevBuf<float2> &xs,
+// y_r = B x_r, r < R (x, y RHS-major [R][2N]): multi-vector product reading B
+// once per 8 right-hand sides
+void dense_gemv(const DenseOperator &op, const double2 *x, double2 *y, int R, DevBuf<float2> &xs,
                 hipStream_t s);
 // Y = B X for R right-hand sides (x, y RHS-major [R][2N]) on MFMA
 void dense_gemm(const DenseOperator &op, const double2 *x, double2 *y, int R, hipStream_t s);
+int64_t dense_gemm_scratch_bytes(const bem_mesh *m, int R);
+// MFMA product from DENSE_GEMM_MIN_RHS right-hand sides, else dense_gemv
+void dense_apply(const DenseOperator &op, const double2 *x, double2 *y, int R,
+                 DevBuf<float2> &xs, hipStream_t s);
 
 // Issue rates (lane operations per second over the device) of v_fma_f32,
 // v_sin_f32, v_cos_f32, v_rsq_f32 and v_fma_f64; rates[5].
@@ -232,17 +238,18 @@ void far_field_eval(bem_mesh *m, double2 k0, const double2 *x, const double *dir
 // osrc.cpp / osrc.hip
 OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
                     const std::vector<double2> &keps_obj, hipStream_t s);
-void osrc_apply_strong(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y,
+// R right-hand sides, [R][2N] contiguous each
+void osrc_apply_strong(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y, int R,
                        hipStream_t s);
-void osrc_apply_from_weak(bem_mesh *m, OsrcState &st, const double2 *yw,
-                          double2 *z, hipStream_t s);
+void osrc_apply_from_weak(bem_mesh *m, OsrcState &st, const double2 *yw, double2 *z, int R,
+                          hipStream_t s);
 void osrc_mass_solve(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y,
                      int nblocks, hipStream_t s);
 // symbolic analysis of the OSRC systems (once per mesh handle)
 void osrc_prepare(bem_mesh *m);
-// device bytes of one OSRC factor state with np Pade terms (runs the symbolic
-// analysis if needed)
-int64_t osrc_state_bytes(bem_mesh *m, int np);
+// device bytes of one OSRC factor state with np Pade terms, sized for R
+// right-hand sides per apply (runs the symbolic analysis if needed)
+int64_t osrc_state_bytes(bem_mesh *m, int np, int R);
 // solve.cpp
 // Validated OSRC-preconditioned solve (the body of pmchwt_solve); throws Error.
 int solve_run(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dirs,

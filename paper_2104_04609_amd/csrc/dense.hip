@@ -212,33 +212,47 @@ __global__ __launch_bounds__(256) void dense_add_near_kernel(const int32_t *__re
     }
 }
 
-// y = B x: one wavefront per row, FP32 products, FP64 lane partial sums and a
-// fixed-order butterfly reduction
+// y_r = B x_r for NR right-hand sides: one wavefront per row reads the row
+// once; per right-hand side, FP32 products over chunks of 16 x 64 columns,
+// FP64 lane partial sums and a fixed-order butterfly reduction.
+// x: [NR][n2] complex64; y_r = y + r ystride.
+template <int NR>
 __global__ __launch_bounds__(256) void dense_gemv_kernel(const float2 *__restrict__ B,
                                                          int64_t n2,
                                                          const float2 *__restrict__ x,
-                                                         double2 *__restrict__ y) {
+                                                         double2 *__restrict__ y,
+                                                         int64_t ystride) {
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= n2) return;
     const float2 *b = B + row * n2;
-    double sr = 0.0, si = 0.0;
+    double sr[NR], si[NR];
+    for (int r = 0; r < NR; r++) sr[r] = si[r] = 0.0;
     for (int64_t c0 = 0; c0 < n2; c0 += 64 * 16) {
-        float pr = 0.f, pi = 0.f;
+        float pr[NR], pi[NR];
+        for (int r = 0; r < NR; r++) pr[r] = pi[r] = 0.f;
         const int64_t c1 = c0 + 64 * 16 < n2 ? c0 + 64 * 16 : n2;
         for (int64_t c = c0 + lane; c < c1; c += 64) {
-            const float2 a = b[c], v = x[c];
-            pr += a.x * v.x - a.y * v.y;
-            pi += a.x * v.y + a.y * v.x;
+            const float2 a = b[c];
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                const float2 v = x[r * n2 + c];
+                pr[r] += a.x * v.x - a.y * v.y;
+                pi[r] += a.x * v.y + a.y * v.x;
+            }
         }
-        sr += pr;
-        si += pi;
+        for (int r = 0; r < NR; r++) {
+            sr[r] += pr[r];
+            si[r] += pi[r];
+        }
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        sr += __shfl_xor(sr, o, 64);
-        si += __shfl_xor(si, o, 64);
-    }
-    if (lane == 0) y[row] = make_double2(sr, si);
+    for (int r = 0; r < NR; r++)
+        for (int o = 32; o > 0; o >>= 1) {
+            sr[r] += __shfl_xor(sr[r], o, 64);
+            si[r] += __shfl_xor(si[r], o, 64);
+        }
+    if (lane == 0)
+        for (int r = 0; r < NR; r++) y[r * ystride + row] = make_double2(sr[r], si[r]);
 }
 
 // ------------------------------------------------ multi-RHS product on MFMA
@@ -415,17 +429,51 @@ std::unique_ptr<DenseOperator> dense_assemble(bem_mesh *m, const NearOperator &n
     return op;
 }
 
-void dense_gemv(const DenseOperator &op, const double2 *x, double2 *y, DevBuf<float2> &xs,
+constexpr int GEMV_MAX_RHS = 8;   // right-hand sides per multi-vector product launch
+
+template <int NR>
+void launch_gemv(const DenseOperator &op, const float2 *xs, double2 *y, hipStream_t s) {
+    hipLaunchKernelGGL(dense_gemv_kernel<NR>, dim3((unsigned)((op.n2 + 3) / 4)), dim3(256), 0, s,
+                       op.B.p, op.n2, xs, y, op.n2);
+}
+
+void dense_gemv(const DenseOperator &op, const double2 *x, double2 *y, int R, DevBuf<float2> &xs,
                 hipStream_t s) {
     const int64_t n2 = op.n2;
-    if (xs.n < (size_t)n2) xs.alloc((size_t)n2);
-    hipLaunchKernelGGL(to_c64_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, x, xs.p,
-                       n2);
-    BEM_LAUNCH_CHECK();
-    Timer tm("dense_gemv", s);
-    hipLaunchKernelGGL(dense_gemv_kernel, dim3((unsigned)((n2 + 3) / 4)), dim3(256), 0, s, op.B.p,
-                       n2, xs.p, y);
-    BEM_LAUNCH_CHECK();
+    const int64_t need = (int64_t)std::min(R, GEMV_MAX_RHS) * n2;
+    if (xs.n < (size_t)need) xs.alloc((size_t)need);
+    for (int r0 = 0; r0 < R; r0 += GEMV_MAX_RHS) {
+        const int nr = std::min(GEMV_MAX_RHS, R - r0);
+        const int64_t cnt = nr * n2;
+        hipLaunchKernelGGL(to_c64_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
+                           x + r0 * n2, xs.p, cnt);
+        BEM_LAUNCH_CHECK();
+        Timer tm("dense_gemv", s);
+        double2 *yr = y + r0 * n2;
+        switch (nr) {
+        case 1: launch_gemv<1>(op, xs.p, yr, s); break;
+        case 2: launch_gemv<2>(op, xs.p, yr, s); break;
+        case 3: launch_gemv<3>(op, xs.p, yr, s); break;
+        case 4: launch_gemv<4>(op, xs.p, yr, s); break;
+        case 5: launch_gemv<5>(op, xs.p, yr, s); break;
+        case 6: launch_gemv<6>(op, xs.p, yr, s); break;
+        case 7: launch_gemv<7>(op, xs.p, yr, s); break;
+        default: launch_gemv<8>(op, xs.p, yr, s); break;
+        }
+        BEM_LAUNCH_CHECK();
+    }
+}
+
+int64_t dense_gemm_scratch_bytes(const bem_mesh *m, int R) {
+    const int64_t M = 2 * m->N, Kp = 2 * M;
+    const int64_t Np = 2 * (((int64_t)R + 63) / 64) * 64, nchunks = (Kp + GKC - 1) / GKC;
+    return (Kp * Np + nchunks * M * Np) * (int64_t)sizeof(float);
+}
+
+void dense_apply(const DenseOperator &op, const double2 *x, double2 *y, int R,
+                 DevBuf<float2> &xs, hipStream_t s) {
+    if (R >= DENSE_GEMM_MIN_RHS) dense_gemm(op, x, y, R, s);
+    else dense_gemv(op, x, y, R, xs, s);
 }
 
 void dense_gemm(const DenseOperator &op, const double2 *x, double2 *y, int R, hipStream_t s) {

@@ -43,7 +43,16 @@ int64_t OsrcSymbolicState::bytes() const {
 }
 int64_t OsrcState::bytes() const {
     return cvert.bytes() + Dinv.bytes() + Lcsr.bytes() + Lcsc.bytes() + invL.bytes() +
-           invLT.bytes() + work.bytes() + sbuf.bytes() + tmp.bytes() + wbuf.bytes();
+           invLT.bytes() + work.bytes() + obuf.bytes() + wbuf.bytes();
+}
+
+void OsrcState::ensure_batch(int R) {
+    if (R <= batch) return;
+    const size_t n = cvert.n;
+    work.alloc((size_t)R * (np + 2) * n);
+    obuf.alloc((size_t)R * (np + 3) * n);
+    wbuf.alloc((size_t)R * 2 * n);
+    batch = R;
 }
 int64_t osrc_bytes(const OsrcState &st) { return st.bytes(); }
 int64_t osrc_sym_bytes(const OsrcSymbolicState &st) { return st.bytes(); }
@@ -169,13 +178,13 @@ LdlDev ldl_view(const OsrcSymbolicState &sy, const OsrcState &st) {
 
 void osrc_prepare(bem_mesh *m) { (void)symbolic(m); }
 
-int64_t osrc_state_bytes(bem_mesh *m, int np) {
+int64_t osrc_state_bytes(bem_mesh *m, int np, int R) {
     const OsrcSymbolicState &sy = symbolic(m);
     const int64_t n = sy.n, nnz = sy.sym.nnzL(), nd = sy.sym.ndense, nf = np + 2;
-    // cvert, Dinv, L (CSR + CSC), dense block inverses (+ transposes), work,
-    // shifted-solve outputs, tmp, wbuf; complex128 each
+    // cvert, Dinv, L (CSR + CSC), dense block inverses (+ transposes); per
+    // right-hand side work, outputs and weak vectors; complex128 each
     return (int64_t)sizeof(double2) *
-           (n + nf * (n + 2 * nnz + 2 * nd) + (np + 2) * n + np * n + 3 * n + 2 * n);
+           (n + nf * (n + 2 * nnz + 2 * nd) + (int64_t)R * ((np + 2) + (np + 3) + 2) * n);
 }
 
 OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
@@ -271,10 +280,7 @@ OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
     st->Lcsr.upload(Lr);
     st->invL.upload(iL);
     st->invLT.upload(iLT);
-    st->work.alloc((size_t)(np + 2) * n);
-    st->sbuf.alloc((size_t)np * n);
-    st->tmp.alloc(3 * (size_t)n);
-    st->wbuf.alloc(2 * (size_t)n);
+    st->ensure_batch(1);
     (void)s;
     if (m->osrc_cache.size() >= 4) m->osrc_cache.erase(m->osrc_cache.begin());
     auto &ref = *st;
@@ -282,41 +288,50 @@ OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
     return ref;
 }
 
-void osrc_apply_from_weak(bem_mesh *m, OsrcState &st, const double2 *yw, double2 *z,
+void osrc_apply_from_weak(bem_mesh *m, OsrcState &st, const double2 *yw, double2 *z, int R,
                           hipStream_t s) {
     OsrcSymbolicState &sy = *m->osrc_sym;
     const int n = sy.n, np = st.np;
+    st.ensure_batch(R);
     const LdlDev L = ldl_view(sy, st);
     const cdd ik = cdd(0, 1) * cdd(st.k.x, st.k.y);
     const double2 one = make_double2(1.0, 0.0);
-    const double2 *y1 = yw, *y2 = yw + n;
-    double2 *z1 = z, *z2 = z + n;
-    double2 *u1 = st.tmp.p, *v = st.tmp.p + n, *m2 = st.tmp.p + 2 * n;
+    // right-hand side r: yw + r 2n in, z + r 2n out, obuf + r (np + 3) n,
+    // work + r (np + 2) n
+    const int64_t n2 = 2 * (int64_t)n, os = (int64_t)(np + 3) * n, ws = (int64_t)(np + 2) * n;
+    double2 *ob = st.obuf.p, *wk = st.work.p;
+    double2 *u1 = ob + (size_t)np * n, *v = ob + (size_t)(np + 1) * n, *m2 = ob + (size_t)(np + 2) * n;
     Timer tm("osrc_apply", s);
     // stage 1: shifted solves and M^{-1} on y1 (DtN); (M - S/k_eps^2)^{-1} on y2 (NtD)
     TaskList ta{};
-    for (int j = 0; j < np; j++)
-        ta.t[j] = SolveTask{j, y1, st.sbuf.p + (size_t)j * n, one, st.work.p + (size_t)j * n};
-    ta.t[np] = SolveTask{np + 1, y1, u1, one, st.work.p + (size_t)np * n};
-    ta.t[np + 1] = SolveTask{np, y2, v, one, st.work.p + (size_t)(np + 1) * n};
-    launch_ldl_solve(L, ta, np + 2, s);
+    for (int j = 0; j < np; j++) ta.t[j] = SolveTask{j, yw, ob + (size_t)j * n, one, wk + (size_t)j * n};
+    ta.t[np] = SolveTask{np + 1, yw, u1, one, wk + (size_t)np * n};
+    ta.t[np + 1] = SolveTask{np, yw + n, v, one, wk + (size_t)(np + 1) * n};
+    ta.in_stride = n2;
+    ta.out_stride = os;
+    ta.work_stride = ws;
+    launch_ldl_solve(L, ta, np + 2, R, s);
     // z1 = ik (C_0' M^{-1} y1 - sum_j (A_j/B_j) s_j);  m2 = M v
-    launch_pade_sum(n, st.pf, d2(ik), u1, st.sbuf.p, n, z1, s);
-    launch_spmv_real(n, 1, sy.gptr_d.p, sy.gcol_d.p, sy.Mv_d.p, v, m2, s);
+    launch_pade_sum(n, st.pf, d2(ik), u1, os, ob, n, os, z, n2, R, s);
+    launch_spmv_real(n, R, sy.gptr_d.p, sy.gcol_d.p, sy.Mv_d.p, v, os, m2, os, s);
     // stage 2: shifted solves on M v (NtD)
     TaskList tb{};
-    for (int j = 0; j < np; j++)
-        tb.t[j] = SolveTask{j, m2, st.sbuf.p + (size_t)j * n, one, st.work.p + (size_t)j * n};
-    launch_ldl_solve(L, tb, np, s);
+    for (int j = 0; j < np; j++) tb.t[j] = SolveTask{j, m2, ob + (size_t)j * n, one, wk + (size_t)j * n};
+    tb.in_stride = os;
+    tb.out_stride = os;
+    tb.work_stride = ws;
+    launch_ldl_solve(L, tb, np, R, s);
     // z2 = (1/ik) (C_0' v - sum_j (A_j/B_j) s'_j)
-    launch_pade_sum(n, st.pf, d2(1.0 / ik), v, st.sbuf.p, n, z2, s);
+    launch_pade_sum(n, st.pf, d2(1.0 / ik), v, os, ob, n, os, z + n, n2, R, s);
 }
 
-void osrc_apply_strong(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y,
+void osrc_apply_strong(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y, int R,
                        hipStream_t s) {
     OsrcSymbolicState &sy = *m->osrc_sym;
-    launch_spmv_real(sy.n, 2, sy.gptr_d.p, sy.gcol_d.p, sy.Mv_d.p, x, st.wbuf.p, s);
-    osrc_apply_from_weak(m, st, st.wbuf.p, y, s);
+    st.ensure_batch(R);
+    launch_spmv_real(sy.n, 2 * R, sy.gptr_d.p, sy.gcol_d.p, sy.Mv_d.p, x, sy.n, st.wbuf.p, sy.n,
+                     s);
+    osrc_apply_from_weak(m, st, st.wbuf.p, y, R, s);
 }
 
 void osrc_mass_solve(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y, int nblocks,
@@ -331,7 +346,7 @@ void osrc_mass_solve(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y, i
         for (int b = 0; b < cnt; b++)
             t.t[b] = SolveTask{st.np + 1, x + (size_t)(b0 + b) * n, y + (size_t)(b0 + b) * n,
                                make_double2(1.0, 0.0), st.work.p + (size_t)b * n};
-        launch_ldl_solve(L, t, cnt, s);
+        launch_ldl_solve(L, t, cnt, 1, s);
     }
 }
 

@@ -76,23 +76,33 @@ struct OsrcState {
     int nfactors = 0;            // np shifts, (M - S/k_eps^2), M
     DevBuf<double2> cvert;       // 1/k_eps^2 of each vertex's object
     DevBuf<double2> Dinv, Lcsr, Lcsc, invL, invLT;
-    DevBuf<double2> work;        // (np + 2) x n solve work vectors
-    DevBuf<double2> sbuf;        // np x n shifted-solve outputs
-    DevBuf<double2> tmp;         // 3 x n
-    DevBuf<double2> wbuf;        // 2 x n weak vectors (strong-form entry)
+    // per right-hand side r of a batched apply (capacity `batch`):
+    DevBuf<double2> work;        // [r][np + 2][n] solve work vectors
+    DevBuf<double2> obuf;        // [r][np + 3][n]: s_0..s_{np-1}, u, v, M v
+    DevBuf<double2> wbuf;        // [r][2][n] weak vectors (strong-form entry)
+    int batch = 0;
+    void ensure_batch(int R);
     int64_t bytes() const;
 };
 
-// Task list passed by value as a kernel argument (at most PADE_MAX + 2 systems).
+// Task list passed by value as a kernel argument (at most PADE_MAX + 2
+// systems per right-hand side).  A launch runs nbase x R tasks: task
+// (r, b) is t[b] with in/out/work advanced by r times the strides.
 struct TaskList {
     SolveTask t[PADE_MAX + 2];
+    int nbase;
+    int64_t in_stride, out_stride, work_stride;
 };
 
-void launch_ldl_solve(const LdlDev &L, const TaskList &tasks, int ntasks, hipStream_t s);
-// out = alpha (C0 u - sum_j A_j s_j)   (elementwise)
+void launch_ldl_solve(const LdlDev &L, TaskList tasks, int ntasks, int nrhs, hipStream_t s);
+// out_r = alpha (C0 u_r - sum_j A_j s_{r,j})   (elementwise, r < nrhs):
+// u_r = u + r ustride, s_{r,j} = sv + r vstride + j sstride, out_r = out + r ostride
 void launch_pade_sum(int n, const PadeCoef &pc, double2 alpha, const double2 *u,
-                     const double2 *sv, int64_t sstride, double2 *out, hipStream_t s);
+                     int64_t ustride, const double2 *sv, int64_t sstride, int64_t vstride,
+                     double2 *out, int64_t ostride, int nrhs, hipStream_t s);
+// out_b = V in_b for b < nblk, in_b = in + b istride, out_b = out + b ostride
 void launch_spmv_real(int n, int nblk, const int32_t *gptr, const int32_t *gcol,
-                      const double *V, const double2 *in, double2 *out, hipStream_t s);
+                      const double *V, const double2 *in, int64_t istride, double2 *out,
+                      int64_t ostride, hipStream_t s);
 
 }   // namespace bem

@@ -28,9 +28,18 @@ constexpr int LVL_THREADS = 256;
 // External update: one wavefront per row of the level (fixed-order
 // butterfly reduction), grid (ceil(rows / 4), tasks).  In place: a row only
 // reads rows of other (finished) blocks.
+__device__ inline SolveTask task_of(const TaskList &tasks, int y) {
+    const int b = y % tasks.nbase, r = y / tasks.nbase;
+    SolveTask t = tasks.t[b];
+    t.in += r * tasks.in_stride;
+    t.out += r * tasks.out_stride;
+    t.work += r * tasks.work_stride;
+    return t;
+}
+
 template <bool FWD>
 __global__ __launch_bounds__(256) void ldl_ext_kernel(LdlDev L, TaskList tasks, int lev) {
-    const SolveTask t = tasks.t[blockIdx.y];
+    const SolveTask t = task_of(tasks, blockIdx.y);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = L.lptr[lev] + blockIdx.x * 4 + wave;
     if (r >= L.lptr[lev + 1]) return;
@@ -62,7 +71,7 @@ template <bool FWD>
 __global__ __launch_bounds__(LVL_THREADS) void ldl_dense_kernel(LdlDev L, TaskList tasks,
                                                                 int lev) {
     __shared__ double2 tb[LDL_MAX_BLOCK];
-    const SolveTask t = tasks.t[blockIdx.y];
+    const SolveTask t = task_of(tasks, blockIdx.y);
     const int b = L.lblk[L.lbptr[lev] + blockIdx.x];
     const int s0 = L.bstart[b], w = L.bstart[b + 1] - s0;
     double2 *y = t.work;
@@ -82,14 +91,20 @@ __global__ __launch_bounds__(LVL_THREADS) void ldl_dense_kernel(LdlDev L, TaskLi
     }
 }
 
-// out[i] = alpha (C0 u[i] - sum_j A_j s_j[i])
+// out_r[i] = alpha (C0 u_r[i] - sum_j A_j s_{r,j}[i]), r = blockIdx.y
 __global__ __launch_bounds__(256) void pade_sum_kernel(int n, PadeCoef pc, double2 alpha,
                                                        const double2 *__restrict__ u,
+                                                       int64_t ustride,
                                                        const double2 *__restrict__ sv,
-                                                       int64_t sstride,
-                                                       double2 *__restrict__ out) {
+                                                       int64_t sstride, int64_t vstride,
+                                                       double2 *__restrict__ out,
+                                                       int64_t ostride) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int64_t r = blockIdx.y;
+    u += r * ustride;
+    sv += r * vstride;
+    out += r * ostride;
     double2 acc = cmul(pc.C0, u[i]);
     for (int j = 0; j < pc.np; j++) {
         const double2 p = cmul(pc.A[j], sv[j * sstride + i]);
@@ -99,59 +114,62 @@ __global__ __launch_bounds__(256) void pade_sum_kernel(int n, PadeCoef pc, doubl
     out[i] = cmul(alpha, acc);
 }
 
-// out[i] = sum_e V_e in[col_e]  (real sparse matrix, complex vector), for
-// nblk consecutive blocks of length n
-__global__ __launch_bounds__(256) void spmv_real_kernel(int n, int nblk,
-                                                        const int32_t *__restrict__ gptr,
+// out_b[i] = sum_e V_e in_b[col_e]  (real sparse matrix, complex vectors),
+// block b = blockIdx.y
+__global__ __launch_bounds__(256) void spmv_real_kernel(int n, const int32_t *__restrict__ gptr,
                                                         const int32_t *__restrict__ gcol,
                                                         const double *__restrict__ V,
                                                         const double2 *__restrict__ in,
-                                                        double2 *__restrict__ out) {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= (int64_t)n * nblk) return;
-    const int b = (int)(id / n), i = (int)(id - (int64_t)b * n);
-    const double2 *x = in + (int64_t)b * n;
+                                                        int64_t istride,
+                                                        double2 *__restrict__ out,
+                                                        int64_t ostride) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double2 *x = in + (int64_t)blockIdx.y * istride;
     double2 acc = make_double2(0.0, 0.0);
     for (int e = gptr[i]; e < gptr[i + 1]; e++) {
         const double2 v = x[gcol[e]];
         acc.x += V[e] * v.x;
         acc.y += V[e] * v.y;
     }
-    out[(int64_t)b * n + i] = acc;
+    out[(int64_t)blockIdx.y * ostride + i] = acc;
 }
 
 }   // namespace
 
-void launch_ldl_solve(const LdlDev &L, const TaskList &tasks, int ntasks, hipStream_t s) {
+void launch_ldl_solve(const LdlDev &L, TaskList tasks, int ntasks, int nrhs, hipStream_t s) {
     Timer tm("osrc_ldl_solve", s);
+    tasks.nbase = ntasks;
+    const unsigned gy = (unsigned)(ntasks * nrhs);
     for (int l = 0; l < L.nlev; l++) {
-        hipLaunchKernelGGL(ldl_ext_kernel<true>, dim3((L.lrcount[l] + 3) / 4, ntasks), dim3(256),
+        hipLaunchKernelGGL(ldl_ext_kernel<true>, dim3((L.lrcount[l] + 3) / 4, gy), dim3(256),
                            0, s, L, tasks, l);
-        hipLaunchKernelGGL(ldl_dense_kernel<true>, dim3(L.lbcount[l], ntasks), dim3(LVL_THREADS),
+        hipLaunchKernelGGL(ldl_dense_kernel<true>, dim3(L.lbcount[l], gy), dim3(LVL_THREADS),
                            0, s, L, tasks, l);
         BEM_LAUNCH_CHECK();
     }
     for (int l = L.nlev - 1; l >= 0; l--) {
-        hipLaunchKernelGGL(ldl_ext_kernel<false>, dim3((L.lrcount[l] + 3) / 4, ntasks), dim3(256),
+        hipLaunchKernelGGL(ldl_ext_kernel<false>, dim3((L.lrcount[l] + 3) / 4, gy), dim3(256),
                            0, s, L, tasks, l);
-        hipLaunchKernelGGL(ldl_dense_kernel<false>, dim3(L.lbcount[l], ntasks), dim3(LVL_THREADS),
+        hipLaunchKernelGGL(ldl_dense_kernel<false>, dim3(L.lbcount[l], gy), dim3(LVL_THREADS),
                            0, s, L, tasks, l);
         BEM_LAUNCH_CHECK();
     }
 }
 
 void launch_pade_sum(int n, const PadeCoef &pc, double2 alpha, const double2 *u,
-                     const double2 *sv, int64_t sstride, double2 *out, hipStream_t s) {
-    hipLaunchKernelGGL(pade_sum_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, pc, alpha, u,
-                       sv, sstride, out);
+                     int64_t ustride, const double2 *sv, int64_t sstride, int64_t vstride,
+                     double2 *out, int64_t ostride, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(pade_sum_kernel, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, n, pc,
+                       alpha, u, ustride, sv, sstride, vstride, out, ostride);
     BEM_LAUNCH_CHECK();
 }
 
 void launch_spmv_real(int n, int nblk, const int32_t *gptr, const int32_t *gcol,
-                      const double *V, const double2 *in, double2 *out, hipStream_t s) {
-    int64_t work = (int64_t)n * nblk;
-    hipLaunchKernelGGL(spmv_real_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s,
-                       n, nblk, gptr, gcol, V, in, out);
+                      const double *V, const double2 *in, int64_t istride, double2 *out,
+                      int64_t ostride, hipStream_t s) {
+    hipLaunchKernelGGL(spmv_real_kernel, dim3((n + 255) / 256, nblk), dim3(256), 0, s, n, gptr,
+                       gcol, V, in, istride, out, ostride);
     BEM_LAUNCH_CHECK();
 }
 

@@ -25,6 +25,8 @@ namespace {
 
 using cdd = std::complex<double>;
 
+// P applied to R right-hand sides at once (contiguous [R][2N] in and out):
+// weak operator (assembled or pair kernel + near field), then L M^{-1}.
 struct Op {
     bem_mesh *m;
     const NearOperator *nf;
@@ -32,15 +34,18 @@ struct Op {
     double rho;
     OsrcState *st;
     hipStream_t s;
-    double2 *yw;   // weak-form scratch [2N]
     const DenseOperator *dense = nullptr;   // assembled operator (FP32 form)
-    int n64 = 0, n32 = 0;
-    void apply(const double2 *v, double2 *out, int precision) {
-        if (precision == BEM_FP32_DENSE) dense_gemv(*dense, v, yw, m->xs32, s);
-        else farfield_apply(m, *nf, k0, k1, rho, v, yw, precision, s);
-        osrc_apply_from_weak(m, *st, yw, out, s);
-        if (precision == BEM_FP64) n64++;
-        else n32++;
+    DevBuf<double2> yw;                      // weak-form scratch [R][2N]
+    void apply(const double2 *in, double2 *out, int R, int precision) {
+        const int64_t n2 = 2 * m->N;
+        if (yw.n < (size_t)(R * n2)) yw.alloc((size_t)(R * n2));
+        if (precision == BEM_FP32_DENSE) {
+            dense_apply(*dense, in, yw.p, R, m->xs32, s);
+        } else {
+            for (int r = 0; r < R; r++)
+                farfield_apply(m, *nf, k0, k1, rho, in + r * n2, yw.p + r * n2, precision, s);
+        }
+        osrc_apply_from_weak(m, *st, yw.p, out, R, s);
     }
 };
 
@@ -62,98 +67,151 @@ struct Workspace {
     }
 };
 
-double dev_norm(const double2 *v, int64_t n, double2 *hbuf, hipStream_t s) {
-    blas_block_dot(v, n, 1, v, n, hbuf, s);
-    double2 h;
-    BEM_HIP(hipMemcpyAsync(&h, hbuf, sizeof(double2), hipMemcpyDeviceToHost, s));
+// Squared norms of R vectors (stride n) into host nrm[R] (one sync).
+void dev_norms(const double2 *v, int64_t n, int R, double2 *dbuf, double *nrm, hipStream_t s) {
+    for (int r = 0; r < R; r++) blas_block_dot(v + r * n, n, 1, v + r * n, n, dbuf + r, s);
+    std::vector<double2> h(R);
+    BEM_HIP(hipMemcpyAsync(h.data(), dbuf, R * sizeof(double2), hipMemcpyDeviceToHost, s));
     BEM_HIP(hipStreamSynchronize(s));
-    if (!std::isfinite(h.x)) fail(BEM_E_NAN, "NaN/Inf in a vector norm");
-    return std::sqrt(std::max(h.x, 0.0));
+    for (int r = 0; r < R; r++) {
+        if (!std::isfinite(h[r].x)) fail(BEM_E_NAN, "NaN/Inf in a vector norm");
+        nrm[r] = std::sqrt(std::max(h[r].x, 0.0));
+    }
 }
 
-// Unrestarted GMRES on `op` (precision prec) for op(x) = b from x_0 = 0.
-// Writes x; returns true when |g_{j+1}| <= tol ||b||.
-bool gmres(Op &op, int prec, const double2 *b, double2 *x, int64_t n2, double tol,
-           int maxiter, Workspace &ws, int &iters, double &est, hipStream_t s) {
-    iters = 0;
-    est = 0.0;
-    ws.n2 = n2;
-    ws.ensure(2, s);
-    BEM_HIP(hipMemsetAsync(x, 0, n2 * sizeof(double2), s));
-    const double beta = dev_norm(b, n2, ws.h.p, s);
-    if (beta == 0.0) return true;
-    if (maxiter < 1) return false;
-    blas_axpby(make_double2(1.0 / beta, 0.0), b, make_double2(0, 0), nullptr, ws.V.p, n2, s);
-    std::vector<cdd> H, cs, sn, g(1, cdd(beta));
+void copy_vec(double2 *dst, const double2 *src, int64_t n, hipStream_t s) {
+    BEM_HIP(hipMemcpyAsync(dst, src, n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+}
+
+// Waves solved together in one lockstep group.
+constexpr int SOLVE_BATCH = 16;
+
+// Unrestarted GMRES for R systems op(x_r) = b_r from x_0 = 0, run in
+// lockstep: every iteration applies the operator to the newest Krylov vector
+// of all systems still running, then orthogonalises each system's vector
+// against its own basis (CGS2 on the device, Givens on the host).  System r
+// stops when |g_{j+1}| <= tol[r] ||b_r|| or after maxit[r] iterations.
+// b, x: [R][n2].  Writes x, iters[r]; conv[r] = converged.
+void gmres_batch(Op &op, int prec, const double2 *b, double2 *x, int R, int64_t n2,
+                 const double *tol, const int *maxit, std::vector<Workspace> &ws,
+                 int *iters, bool *conv, int *napply, hipStream_t s) {
+    struct Sys {
+        std::vector<cdd> H, cs, sn, g;
+        double beta = 0;
+        int m = 0;
+        bool run = false;
+    };
+    std::vector<Sys> sy(R);
+    if ((int)ws.size() < R) ws.resize(R);
+    DevBuf<double2> nb(R);
+    std::vector<double> bn(R);
+    for (int r = 0; r < R; r++) {
+        ws[r].n2 = n2;
+        ws[r].ensure(2, s);
+        BEM_HIP(hipMemsetAsync(x + r * n2, 0, n2 * sizeof(double2), s));
+    }
+    dev_norms(b, n2, R, nb.p, bn.data(), s);
+    for (int r = 0; r < R; r++) {
+        iters[r] = 0;
+        conv[r] = bn[r] == 0.0;
+        sy[r].beta = bn[r];
+        sy[r].g.assign(1, cdd(bn[r]));
+        sy[r].run = !conv[r] && maxit[r] > 0;
+        if (sy[r].run)
+            blas_axpby(make_double2(1.0 / bn[r], 0.0), b + r * n2, make_double2(0, 0), nullptr,
+                       ws[r].V.p, n2, s);
+    }
+    DevBuf<double2> vin, vout;
     std::vector<double2> hh;
-    int m = 0;
-    bool conv = false;
-    for (int j = 0; j < maxiter; j++) {
-        ws.ensure(j + 2, s);
-        double2 *Vj = ws.V.p + (size_t)j * n2, *Vn = ws.V.p + (size_t)(j + 1) * n2;
-        op.apply(Vj, Vn, prec);
-        double2 *h1 = ws.h.p, *h2 = ws.h.p + (j + 1), *nr = ws.h.p + 2 * (j + 1);
-        blas_block_dot(ws.V.p, n2, j + 1, Vn, n2, h1, s);
-        blas_block_axpy(ws.V.p, n2, h1, j + 1, -1.0, Vn, n2, s);
-        blas_block_dot(ws.V.p, n2, j + 1, Vn, n2, h2, s);
-        blas_block_axpy(ws.V.p, n2, h2, j + 1, -1.0, Vn, n2, s);
-        blas_block_dot(Vn, n2, 1, Vn, n2, nr, s);
-        blas_normalize(Vn, nr, n2, s);
-        hh.resize(2 * (j + 1) + 1);
-        BEM_HIP(hipMemcpyAsync(hh.data(), ws.h.p, hh.size() * sizeof(double2),
-                               hipMemcpyDeviceToHost, s));
+    for (int j = 0;; j++) {
+        std::vector<int> act;
+        for (int r = 0; r < R; r++)
+            if (sy[r].run) act.push_back(r);
+        if (act.empty()) break;
+        const int A = (int)act.size();
+        if (vin.n < (size_t)(A * n2)) {
+            vin.alloc((size_t)(A * n2));
+            vout.alloc((size_t)(A * n2));
+        }
+        for (int a = 0; a < A; a++) {
+            ws[act[a]].ensure(j + 2, s);
+            copy_vec(vin.p + a * n2, ws[act[a]].V.p + (size_t)j * n2, n2, s);
+        }
+        op.apply(vin.p, vout.p, A, prec);
+        for (int a = 0; a < A; a++) {
+            Workspace &w = ws[act[a]];
+            double2 *Vn = w.V.p + (size_t)(j + 1) * n2;
+            copy_vec(Vn, vout.p + a * n2, n2, s);
+            double2 *h1 = w.h.p, *h2 = w.h.p + (j + 1), *nr = w.h.p + 2 * (j + 1);
+            blas_block_dot(w.V.p, n2, j + 1, Vn, n2, h1, s);
+            blas_block_axpy(w.V.p, n2, h1, j + 1, -1.0, Vn, n2, s);
+            blas_block_dot(w.V.p, n2, j + 1, Vn, n2, h2, s);
+            blas_block_axpy(w.V.p, n2, h2, j + 1, -1.0, Vn, n2, s);
+            blas_block_dot(Vn, n2, 1, Vn, n2, nr, s);
+            blas_normalize(Vn, nr, n2, s);
+            napply[act[a]]++;
+        }
+        const size_t per = 2 * (size_t)(j + 1) + 1;
+        hh.resize(per * A);
+        for (int a = 0; a < A; a++)
+            BEM_HIP(hipMemcpyAsync(hh.data() + a * per, ws[act[a]].h.p, per * sizeof(double2),
+                                   hipMemcpyDeviceToHost, s));
         BEM_HIP(hipStreamSynchronize(s));
-        // column j of the Hessenberg matrix (stored by columns, length j + 2)
-        std::vector<cdd> col(j + 2);
-        for (int i = 0; i <= j; i++)
-            col[i] = cdd(hh[i].x + hh[j + 1 + i].x, hh[i].y + hh[j + 1 + i].y);
-        const double hn = std::sqrt(std::max(hh[2 * (j + 1)].x, 0.0));
-        if (!std::isfinite(hn)) fail(BEM_E_NAN, "NaN/Inf in the Arnoldi process");
-        col[j + 1] = hn;
-        for (int i = 0; i < j; i++) {   // previous rotations
-            cdd a = col[i], c = col[i + 1];
-            col[i] = std::conj(cs[i]) * a + std::conj(sn[i]) * c;
-            col[i + 1] = -sn[i] * a + cs[i] * c;
-        }
-        const double d = std::sqrt(std::norm(col[j]) + std::norm(col[j + 1]));
-        cdd c0 = d > 0 ? col[j] / d : cdd(1.0), s0 = d > 0 ? col[j + 1] / d : cdd(0.0);
-        cs.push_back(c0);
-        sn.push_back(s0);
-        col[j] = std::conj(c0) * col[j] + std::conj(s0) * col[j + 1];
-        col[j + 1] = 0.0;
-        g.push_back(-s0 * g[j]);
-        g[j] = std::conj(c0) * g[j];
-        H.insert(H.end(), col.begin(), col.begin() + (j + 1));   // R column j (rows 0..j)
-        m = j + 1;
-        est = std::abs(g[j + 1]) / beta;
-        if (!std::isfinite(est)) fail(BEM_E_NAN, "NaN/Inf in the GMRES residual");
-        if (est <= tol) {
-            conv = true;
-            break;
+        for (int a = 0; a < A; a++) {
+            const int r = act[a];
+            Sys &q = sy[r];
+            const double2 *h = hh.data() + a * per;
+            // column j of the Hessenberg matrix (length j + 2)
+            std::vector<cdd> col(j + 2);
+            for (int i = 0; i <= j; i++)
+                col[i] = cdd(h[i].x + h[j + 1 + i].x, h[i].y + h[j + 1 + i].y);
+            const double hn = std::sqrt(std::max(h[2 * (j + 1)].x, 0.0));
+            if (!std::isfinite(hn)) fail(BEM_E_NAN, "NaN/Inf in the Arnoldi process");
+            col[j + 1] = hn;
+            for (int i = 0; i < j; i++) {   // previous rotations
+                cdd u = col[i], v = col[i + 1];
+                col[i] = std::conj(q.cs[i]) * u + std::conj(q.sn[i]) * v;
+                col[i + 1] = -q.sn[i] * u + q.cs[i] * v;
+            }
+            const double d = std::sqrt(std::norm(col[j]) + std::norm(col[j + 1]));
+            cdd c0 = d > 0 ? col[j] / d : cdd(1.0), s0 = d > 0 ? col[j + 1] / d : cdd(0.0);
+            q.cs.push_back(c0);
+            q.sn.push_back(s0);
+            col[j] = std::conj(c0) * col[j] + std::conj(s0) * col[j + 1];
+            q.g.push_back(-s0 * q.g[j]);
+            q.g[j] = std::conj(c0) * q.g[j];
+            q.H.insert(q.H.end(), col.begin(), col.begin() + (j + 1));   // R column j
+            q.m = j + 1;
+            const double est = std::abs(q.g[j + 1]) / q.beta;
+            if (!std::isfinite(est)) fail(BEM_E_NAN, "NaN/Inf in the GMRES residual");
+            if (est <= tol[r]) {
+                conv[r] = true;
+                q.run = false;
+            } else if (q.m >= maxit[r]) {
+                q.run = false;
+            }
         }
     }
-    iters = m;
-    // back substitution R y = g (R upper triangular, columns stored packed)
-    std::vector<cdd> y(m);
-    auto R = [&](int i, int jj) { return H[(size_t)jj * (jj + 1) / 2 + i]; };
-    for (int i = m - 1; i >= 0; i--) {
-        cdd acc = g[i];
-        for (int jj = i + 1; jj < m; jj++) acc -= R(i, jj) * y[jj];
-        y[i] = acc / R(i, i);
+    // x_r = V_r y_r with R_r y_r = g_r (back substitution, packed columns)
+    for (int r = 0; r < R; r++) {
+        Sys &q = sy[r];
+        iters[r] = q.m;
+        if (q.m == 0) continue;
+        const int m = q.m;
+        std::vector<cdd> y(m);
+        auto Rm = [&](int i, int jj) { return q.H[(size_t)jj * (jj + 1) / 2 + i]; };
+        for (int i = m - 1; i >= 0; i--) {
+            cdd acc = q.g[i];
+            for (int jj = i + 1; jj < m; jj++) acc -= Rm(i, jj) * y[jj];
+            y[i] = acc / Rm(i, i);
+        }
+        std::vector<double2> yd(m);
+        for (int i = 0; i < m; i++) yd[i] = make_double2(y[i].real(), y[i].imag());
+        BEM_HIP(hipMemcpyAsync(ws[r].h.p, yd.data(), m * sizeof(double2), hipMemcpyHostToDevice,
+                               s));
+        blas_block_axpy(ws[r].V.p, n2, ws[r].h.p, m, 1.0, x + r * n2, n2, s);
+        BEM_HIP(hipStreamSynchronize(s));
     }
-    std::vector<double2> yd(m);
-    for (int i = 0; i < m; i++) yd[i] = make_double2(y[i].real(), y[i].imag());
-    BEM_HIP(hipMemcpyAsync(ws.h.p, yd.data(), m * sizeof(double2), hipMemcpyHostToDevice, s));
-    blas_block_axpy(ws.V.p, n2, ws.h.p, m, 1.0, x, n2, s);
-    BEM_HIP(hipStreamSynchronize(s));
-    return conv;
-}
-
-double2 damped(double2 k, double R) {
-    // k_eps = k (1 + 0.4 i (k R)^{-2/3}), principal branch (Sec. 2.6)
-    cdd kk(k.x, k.y);
-    cdd ke = kk * (1.0 + cdd(0, 0.4) * std::pow(kk * R, -2.0 / 3.0));
-    return make_double2(ke.real(), ke.imag());
 }
 
 // Krylov basis capacity after growing to `need` vectors (Workspace::ensure).
@@ -169,6 +227,13 @@ int64_t workspace_peak_vectors(int maxiter) {
     ensure(2);
     ensure(maxiter + 1);
     return std::max<int64_t>(peak, cap + 1);
+}
+
+double2 damped(double2 k, double R) {
+    // k_eps = k (1 + 0.4 i (k R)^{-2/3}), principal branch (Sec. 2.6)
+    cdd kk(k.x, k.y);
+    cdd ke = kk * (1.0 + cdd(0, 0.4) * std::pow(kk * R, -2.0 / 3.0));
+    return make_double2(ke.real(), ke.imag());
 }
 
 }   // namespace
@@ -197,17 +262,19 @@ int64_t solve_footprint(bem_mesh *m, double2 k0, double2 k1, double rho,
                         const bem_solve_opts &o, int n_waves) {
     (void)rho;
     const int64_t n2 = 2 * m->N, c16 = (int64_t)sizeof(double2);
+    const int G = std::min(n_waves, SOLVE_BATCH);
     int64_t b = 4 * m->nf_nnz * c16;                          // near-field CSR values
-    b += osrc_state_bytes(m, o.pade_terms);                    // OSRC factors
+    b += osrc_state_bytes(m, o.pade_terms, G);                 // OSRC factors + batch buffers
     int64_t scratch = farfield_scratch_bytes(m, BEM_FP64, k0, k1);
     const bool dense = o.precision == BEM_FP32 && o.path == 1;
     if (o.precision == BEM_FP32 && !dense)
         scratch = std::max(scratch, farfield_scratch_bytes(m, BEM_FP32, k0, k1)) +
                   m->T * DYN_STRIDE * 4;                      // dyn32 beside dyn64
     b += scratch;
-    if (dense) b += dense_bytes(m) + dense_assembly_scratch_bytes(m);
-    b += ((int64_t)n_waves + 5) * n2 * c16;                    // f, yw, b, x, r, dx
-    b += workspace_peak_vectors(o.maxiter) * n2 * c16 + (2 * (int64_t)o.maxiter + 8) * c16;
+    if (dense) b += dense_bytes(m) + dense_assembly_scratch_bytes(m) + 2 * G * n2 * 8 +
+                    dense_gemm_scratch_bytes(m, G);
+    b += ((int64_t)n_waves + 8 * (int64_t)G) * n2 * c16;      // f, B, X, R, D, T, yw, vin, vout
+    b += G * (workspace_peak_vectors(o.maxiter) * n2 * c16 + (2 * (int64_t)o.maxiter + 8) * c16);
     return b;
 }
 
@@ -224,9 +291,9 @@ int solve_run(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dir
         keps[ob] = damped(ko, o.R > 0 ? o.R : 0.1 * m->obj_radius[ob]);
     OsrcState &st = osrc_get(m, o.pade_terms, o.theta, ko, keps, s);
 
-    DevBuf<double2> f((size_t)n_waves * n2), yw(n2), b(n2), x(n2), r(n2), dx(n2);
+    DevBuf<double2> f((size_t)n_waves * n2);
     rhs_project(m, k0, directions, n_waves, f.p, s);
-    Op op{m, &nf, k0, k1, rho, &st, s, yw.p};
+    Op op{m, &nf, k0, k1, rho, &st, s};
     int inner = BEM_FP32;
     if (o.precision == BEM_FP32 && o.path != 0) {
         bool use = o.path == 1;
@@ -241,61 +308,104 @@ int solve_run(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dir
             inner = BEM_FP32_DENSE;
         }
     }
-    Workspace ws;
-    ws.n2 = n2;
-    ws.ensure(2, s);
+    // waves are solved in lockstep groups of up to SOLVE_BATCH
+    const int G = std::min(n_waves, SOLVE_BATCH);
+    DevBuf<double2> B((size_t)G * n2), X((size_t)G * n2), Rv((size_t)G * n2),
+        D((size_t)G * n2), T((size_t)G * n2), nb(G);
+    std::vector<Workspace> ws;
     int worst = BEM_OK;
-    for (int w = 0; w < n_waves; w++) {
-        auto t0 = std::chrono::steady_clock::now();
-        op.n64 = op.n32 = 0;
-        osrc_apply_from_weak(m, st, f.p + (size_t)w * n2, b.p, s);
-        const double bn = dev_norm(b.p, n2, ws.h.p, s);
-        int total_it = 0, outer = 0;
-        double rel = 0.0;
-        bool conv = false;
+    for (int w0 = 0; w0 < n_waves; w0 += G) {
+        const int R = std::min(G, n_waves - w0);
+        const auto t0 = std::chrono::steady_clock::now();
+        std::vector<int> n64(R, 0), n32(R, 0), its(R, 0), outer(R, 0);
+        std::vector<double> bn(R), rel(R, 0.0);
+        std::vector<char> cv(R, 0);
+        osrc_apply_from_weak(m, st, f.p + (size_t)w0 * n2, B.p, R, s);
+        dev_norms(B.p, n2, R, nb.p, bn.data(), s);
         if (o.precision == BEM_FP64) {
-            int it;
-            double est;
-            conv = gmres(op, BEM_FP64, b.p, x.p, n2, tol, o.maxiter, ws, it, est, s);
-            total_it = it;
-            outer = 1;
-            op.apply(x.p, r.p, BEM_FP64);   // true residual with the FP64 operator
-            blas_axpby(make_double2(1, 0), b.p, make_double2(-1, 0), r.p, r.p, n2, s);
-            rel = bn > 0 ? dev_norm(r.p, n2, ws.h.p, s) / bn : 0.0;
-        } else {
-            BEM_HIP(hipMemsetAsync(x.p, 0, n2 * sizeof(double2), s));
-            BEM_HIP(hipMemcpyAsync(r.p, b.p, n2 * sizeof(double2), hipMemcpyDeviceToDevice, s));
-            double rn = bn;
-            rel = bn > 0 ? 1.0 : 0.0;
-            while (rel > tol && outer < o.max_outer && total_it < o.maxiter) {
-                const double eta = std::min(0.5, o.inner_tol * tol * bn / rn);
-                int it;
-                double est;
-                gmres(op, inner, r.p, dx.p, n2, eta, o.maxiter - total_it, ws, it, est, s);
-                total_it += it;
-                outer++;
-                blas_axpby(make_double2(1, 0), x.p, make_double2(1, 0), dx.p, x.p, n2, s);
-                op.apply(x.p, r.p, BEM_FP64);
-                blas_axpby(make_double2(1, 0), b.p, make_double2(-1, 0), r.p, r.p, n2, s);
-                rn = dev_norm(r.p, n2, ws.h.p, s);
-                rel = rn / bn;
+            std::vector<double> tl(R, tol);
+            std::vector<int> mi(R, o.maxiter);
+            bool cvb[SOLVE_BATCH];
+            gmres_batch(op, BEM_FP64, B.p, X.p, R, n2, tl.data(), mi.data(), ws, its.data(), cvb,
+                        n64.data(), s);
+            // true residual with the FP64 operator
+            op.apply(X.p, Rv.p, R, BEM_FP64);
+            blas_axpby(make_double2(1, 0), B.p, make_double2(-1, 0), Rv.p, Rv.p, R * n2, s);
+            std::vector<double> rn(R);
+            dev_norms(Rv.p, n2, R, nb.p, rn.data(), s);
+            for (int r = 0; r < R; r++) {
+                n64[r]++;
+                outer[r] = 1;
+                rel[r] = bn[r] > 0 ? rn[r] / bn[r] : 0.0;
+                cv[r] = cvb[r] || rel[r] <= tol;
             }
-            conv = rel <= tol;
+        } else {
+            // iterative refinement: x += d, P32 d = r to eta ||b||, r = b - P64 x
+            BEM_HIP(hipMemsetAsync(X.p, 0, R * n2 * sizeof(double2), s));
+            copy_vec(Rv.p, B.p, R * n2, s);
+            std::vector<double> rn(bn);
+            for (int r = 0; r < R; r++) rel[r] = bn[r] > 0 ? 1.0 : 0.0;
+            for (;;) {
+                std::vector<int> act;
+                for (int r = 0; r < R; r++)
+                    if (rel[r] > tol && outer[r] < o.max_outer && its[r] < o.maxiter)
+                        act.push_back(r);
+                if (act.empty()) break;
+                const int A = (int)act.size();
+                std::vector<double> eta(A);
+                std::vector<int> mi(A), it(A), na(A, 0);
+                bool cvb[SOLVE_BATCH];
+                for (int a = 0; a < A; a++) {
+                    const int r = act[a];
+                    eta[a] = std::min(0.5, o.inner_tol * tol * bn[r] / rn[r]);
+                    mi[a] = o.maxiter - its[r];
+                    copy_vec(T.p + a * n2, Rv.p + act[a] * n2, n2, s);
+                }
+                gmres_batch(op, inner, T.p, D.p, A, n2, eta.data(), mi.data(), ws, it.data(),
+                            cvb, na.data(), s);
+                for (int a = 0; a < A; a++) {
+                    const int r = act[a];
+                    its[r] += it[a];
+                    outer[r]++;
+                    n32[r] += na[a];
+                    blas_axpby(make_double2(1, 0), X.p + r * n2, make_double2(1, 0),
+                               D.p + a * n2, X.p + r * n2, n2, s);
+                    copy_vec(T.p + a * n2, X.p + r * n2, n2, s);
+                }
+                op.apply(T.p, D.p, A, BEM_FP64);
+                for (int a = 0; a < A; a++) {
+                    const int r = act[a];
+                    n64[r]++;
+                    blas_axpby(make_double2(1, 0), B.p + r * n2, make_double2(-1, 0),
+                               D.p + a * n2, Rv.p + r * n2, n2, s);
+                    copy_vec(T.p + a * n2, Rv.p + r * n2, n2, s);
+                }
+                std::vector<double> nrm(A);
+                dev_norms(T.p, n2, A, nb.p, nrm.data(), s);
+                for (int a = 0; a < A; a++) {
+                    const int r = act[a];
+                    rn[r] = nrm[a];
+                    rel[r] = rn[r] / bn[r];
+                }
+            }
+            for (int r = 0; r < R; r++) cv[r] = rel[r] <= tol;
         }
-        BEM_HIP(hipMemcpyAsync(solution + (size_t)w * n2, x.p, n2 * sizeof(double2),
-                               hipMemcpyDeviceToDevice, s));
+        copy_vec(solution + (size_t)w0 * n2, X.p, R * n2, s);
         BEM_HIP(hipStreamSynchronize(s));
         const double secs =
             std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        if (info) {
-            info[w].iterations = total_it;
-            info[w].outer_steps = outer;
-            info[w].fp64_matvecs = op.n64;
-            info[w].fp32_matvecs = op.n32;
-            info[w].rel_residual = rel;
-            info[w].seconds = secs;
+        for (int r = 0; r < R; r++) {
+            if (info) {
+                bem_solve_info &q = info[w0 + r];
+                q.iterations = its[r];
+                q.outer_steps = outer[r];
+                q.fp64_matvecs = n64[r];
+                q.fp32_matvecs = n32[r];
+                q.rel_residual = rel[r];
+                q.seconds = secs;
+            }
+            if (!cv[r]) worst = BEM_W_NOT_CONVERGED;
         }
-        if (!conv && rel > tol) worst = BEM_W_NOT_CONVERGED;
     }
     return worst;
 }

@@ -165,3 +165,19 @@ def test_solve_multiple_waves(P):
     for w in range(3):
         one, _, _ = P.pmchwt_solve(M, 2.0, 3.0, 1.5, d[w:w + 1], 1e-9)
         assert np.allclose(one.cpu().numpy()[0], sol.cpu().numpy()[w], rtol=0, atol=1e-14)
+
+
+def test_solve_lockstep_waves_fp32_dense(P):
+    """Waves solved in one lockstep group (multi-vector dense product, batched
+    OSRC) against each wave solved alone; both to 1e-9."""
+    from bem_inputs import wave_directions
+    mesh = icosphere(3)
+    M = P.Mesh.from_inputs(mesh)
+    d = wave_directions(5, seed=8)
+    sol, info, rc = P.pmchwt_solve(M, 3.0, 4.5, 1.6, d, 1e-9, precision="fp32", path=1)
+    assert rc == 0
+    for w in range(5):
+        one, i1, _ = P.pmchwt_solve(M, 3.0, 4.5, 1.6, d[w:w + 1], 1e-9, precision="fp32", path=1)
+        a, b = sol.cpu().numpy()[w], one.cpu().numpy()[0]
+        assert info[w]["rel_residual"] <= 1e-9 and i1[0]["rel_residual"] <= 1e-9
+        assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-7, w

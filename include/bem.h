@@ -272,6 +272,18 @@ int bem_server_stats_get(bem_server *srv, bem_server_stats *stats);
 int bem_profile_enable(int enable);
 int bem_profile_read(const char *kernel, double *total_ms, int64_t *launches);
 
+/* Process-wide launch parameters (the autotuner sets them; defaults apply
+ * otherwise):
+ *   "farfield.multi_max"  right-hand sides sharing one pair-kernel launch on
+ *                         the FP32 matrix-free path: 1, 2 or 4 (default 4)
+ *   "dense.gemm_min_rhs"  right-hand-side count from which the assembled
+ *                         operator is applied with the MFMA product instead of
+ *                         the multi-vector product (default 16)
+ * Results of a solve depend on these (the summation order changes), within
+ * the FP32 accuracy.  BEM_E_INVAL for an unknown key or value. */
+int bem_tune_set(const char *key, int64_t value);
+int bem_tune_get(const char *key, int64_t *value);
+
 /* Diagnostic for the issue-bound roofline of the pair kernel: measured issue
  * rates, in lane operations per second summed over the device, of
  * rates[0] v_fma_f32, [1] v_sin_f32, [2] v_cos_f32, [3] v_rsq_f32 and

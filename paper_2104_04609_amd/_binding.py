@@ -102,6 +102,8 @@ lib.bem_profile_enable.argtypes = [ctypes.c_int]
 lib.bem_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(_i64)]
 lib.bem_valu_rates.argtypes = [_vp, _vp]
+lib.bem_tune_set.argtypes = [ctypes.c_char_p, _i64]
+lib.bem_tune_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(_i64)]
 lib.bem_server_opts_default.argtypes = [ctypes.POINTER(ServerOpts)]
 lib.bem_server_opts_default.restype = None
 lib.bem_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)]
@@ -352,6 +354,16 @@ def profile_read(kernel: str):
     ms, n = ctypes.c_double(), _i64()
     _check(lib.bem_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def tune_set(key: str, value: int):
+    _check(lib.bem_tune_set(key.encode(), int(value)))
+
+
+def tune_get(key: str) -> int:
+    v = _i64()
+    _check(lib.bem_tune_get(key.encode(), ctypes.byref(v)))
+    return v.value
 
 
 def valu_rates(stream=None) -> dict:

@@ -55,6 +55,11 @@ Timer::~Timer() {
 bem_mesh::~bem_mesh() = default;
 
 namespace bem {
+Tuning &tuning() {
+    static Tuning t;
+    return t;
+}
+
 void mesh_trim(bem_mesh *m) {
     m->near_cache.clear();
     m->dense_cache.clear();
@@ -161,15 +166,13 @@ int pmchwt_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho
     hipStream_t s = (hipStream_t)hip_stream;
     double2 k0 = make_double2(k_ext.re, k_ext.im), k1 = make_double2(k_int.re, k_int.im);
     const bem::NearOperator &nf = bem::nearfield_get(m, k0, k1, rho, s);
-    const int64_t n2 = 2 * m->N;
     if (precision == BEM_FP32_DENSE) {
         const bem::DenseOperator &op = bem::dense_get(m, k0, k1, rho, s);
         bem::dense_apply(op, (const double2 *)x, (double2 *)y, n_rhs, m->xs32, s);
         return BEM_OK;
     }
-    for (int r = 0; r < n_rhs; r++)
-        bem::farfield_apply(m, nf, k0, k1, rho, (const double2 *)x + r * n2,
-                            (double2 *)y + r * n2, precision, s);
+    bem::farfield_apply_batch(m, nf, k0, k1, rho, (const double2 *)x, (double2 *)y, n_rhs,
+                              precision, s);
     return BEM_OK;
     BEM_API_END
 }
@@ -226,6 +229,36 @@ int bem_far_field(const bem_mesh *mesh, bem_c64 k_ext, const bem_c64 *solution,
     bem::far_field_eval(const_cast<bem_mesh *>(mesh), make_double2(k_ext.re, k_ext.im),
                         (const double2 *)solution, dirs, n_dirs, (double2 *)out,
                         (hipStream_t)hip_stream);
+    return BEM_OK;
+    BEM_API_END
+}
+
+int bem_tune_set(const char *key, int64_t value) {
+    BEM_API_BEGIN
+    if (!key) fail(BEM_E_INVAL, "key is NULL");
+    const std::string k(key);
+    bem::Tuning &t = bem::tuning();
+    if (k == "farfield.multi_max") {
+        if (value != 1 && value != 2 && value != 4) fail(BEM_E_INVAL, "farfield.multi_max: 1, 2 or 4");
+        t.farfield_multi_max = (int)value;
+    } else if (k == "dense.gemm_min_rhs") {
+        if (value < 1 || value > 1 << 20) fail(BEM_E_INVAL, "dense.gemm_min_rhs out of range");
+        t.dense_gemm_min_rhs = (int)value;
+    } else {
+        fail(BEM_E_INVAL, "unknown tuning key " + k);
+    }
+    return BEM_OK;
+    BEM_API_END
+}
+
+int bem_tune_get(const char *key, int64_t *value) {
+    BEM_API_BEGIN
+    if (!key || !value) fail(BEM_E_INVAL, "key or value is NULL");
+    const std::string k(key);
+    bem::Tuning &t = bem::tuning();
+    if (k == "farfield.multi_max") *value = t.farfield_multi_max;
+    else if (k == "dense.gemm_min_rhs") *value = t.dense_gemm_min_rhs;
+    else fail(BEM_E_INVAL, "unknown tuning key " + k);
     return BEM_OK;
     BEM_API_END
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <atomic>
 #include <map>
 #include <memory>
 #include <string>
@@ -197,9 +198,14 @@ namespace bem {
 void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
                     double rho, const double2 *x, double2 *y, int precision,
                     hipStream_t s);
+// y_r = B x_r for R right-hand sides ([R][2N]); FP32 shares each kernel
+// evaluation among up to 4 right-hand sides
+void farfield_apply_batch(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
+                          double rho, const double2 *x, double2 *y, int R, int precision,
+                          hipStream_t s);
 // device scratch (source records, split partials, triangle rows) that
-// farfield_apply needs for this precision and wavenumber pair
-int64_t farfield_scratch_bytes(const bem_mesh *m, int precision, double2 k0, double2 k1);
+// farfield_apply_batch needs for this precision, wavenumber pair and R
+int64_t farfield_scratch_bytes(const bem_mesh *m, int precision, double2 k0, double2 k1, int R);
 // nearfield.hip
 std::unique_ptr<NearOperator> nearfield_build(bem_mesh *m, double2 k0, double2 k1,
                                               double rho, hipStream_t s);
@@ -218,15 +224,19 @@ void dense_gemv(const DenseOperator &op, const double2 *x, double2 *y, int R, De
 // Y = B X for R right-hand sides (x, y RHS-major [R][2N]) on MFMA
 void dense_gemm(const DenseOperator &op, const double2 *x, double2 *y, int R, hipStream_t s);
 int64_t dense_gemm_scratch_bytes(const bem_mesh *m, int R);
-// MFMA product from DENSE_GEMM_MIN_RHS right-hand sides, else dense_gemv
+// MFMA product from tuning().dense_gemm_min_rhs right-hand sides, else dense_gemv
 void dense_apply(const DenseOperator &op, const double2 *x, double2 *y, int R,
                  DevBuf<float2> &xs, hipStream_t s);
 
 // Issue rates (lane operations per second over the device) of v_fma_f32,
 // v_sin_f32, v_cos_f32, v_rsq_f32 and v_fma_f64; rates[5].
 void valu_rates(double *rates, hipStream_t s);
-// right-hand-side count from which the MFMA product replaces per-RHS GEMVs
-constexpr int DENSE_GEMM_MIN_RHS = 16;
+// Process-wide tunable launch parameters (bem_tune_set / bem_tune_get).
+struct Tuning {
+    std::atomic<int> farfield_multi_max{4};   // right-hand sides per pair-kernel launch
+    std::atomic<int> dense_gemm_min_rhs{16};  // MFMA product from this many right-hand sides
+};
+Tuning &tuning();
 // mesh.cpp
 void mesh_build(bem_mesh *m, const double *P, int64_t N, const int32_t *tri,
                 int64_t T, const int32_t *obj);

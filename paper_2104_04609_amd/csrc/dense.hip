@@ -472,7 +472,7 @@ int64_t dense_gemm_scratch_bytes(const bem_mesh *m, int R) {
 
 void dense_apply(const DenseOperator &op, const double2 *x, double2 *y, int R,
                  DevBuf<float2> &xs, hipStream_t s) {
-    if (R >= DENSE_GEMM_MIN_RHS) dense_gemm(op, x, y, R, s);
+    if (R >= tuning().dense_gemm_min_rhs.load()) dense_gemm(op, x, y, R, s);
     else dense_gemv(op, x, y, R, xs, s);
 }
 

@@ -405,6 +405,233 @@ void farfield_kernel(
     for (int c = 0; c < 6; c++) outA[c] = sum_get(ROW_STRIDE + c);
 }
 
+// ----------------------------------------- multi-right-hand-side pair kernel
+// NR right-hand sides share every kernel evaluation (geometry, phases,
+// G_V, G_W, G_N, F); only the accumulations are per right-hand side.  FP32,
+// phases below 256 revolutions.  dyn: [NR][T][DYN_STRIDE]; partial of
+// right-hand side r at partial + r nsplit T (ROW_STRIDE + 6), same layout
+// as the single-vector kernel.  Per-tile FP64 sums are accumulated in place
+// in the thread's own partial slots.
+template <int NR> constexpr int srcm() { return GEO_STRIDE + 4 + NR * DYN_STRIDE; }
+
+template <int NR> constexpr int multi_waves() { return NR >= 4 ? 1 : 2; }
+
+template <bool CK0, bool CK1, bool MULTI, int NR>
+__global__ __launch_bounds__(FF_BLOCK) __attribute__((amdgpu_waves_per_eu(multi_waves<NR>())))
+void farfield_multi_kernel(
+    const float *__restrict__ geo, const float *__restrict__ dyn,
+    const int32_t *__restrict__ tobj, const int32_t *__restrict__ tri, int T,
+    int split_len, Coef<float> cf, double *__restrict__ partial) {
+    using R = float;
+    using MT = Math<float>;
+    constexpr int SM = srcm<NR>();
+    constexpr int OBJ = GEO_STRIDE, VID = GEO_STRIDE + 1, DYN0 = GEO_STRIDE + 4;
+    __shared__ R tile[FF_TILE * SM];
+    const int tau = blockIdx.x * FF_BLOCK + threadIdx.x;
+    const int split = blockIdx.y;
+    const int s_begin = split * split_len;
+    const int s_end = min(T, s_begin + split_len);
+    const bool active = tau < T;
+    const int tt = active ? tau : 0;
+
+    R px[6], py[6], pz[6];
+    for (int i = 0; i < 6; i++) {
+        px[i] = geo[GEO_STRIDE * tt + 3 * i];
+        py[i] = geo[GEO_STRIDE * tt + 3 * i + 1];
+        pz[i] = geo[GEO_STRIDE * tt + 3 * i + 2];
+    }
+    const R ntx = geo[GEO_STRIDE * tt + 18], nty = geo[GEO_STRIDE * tt + 19],
+            ntz = geo[GEO_STRIDE * tt + 20], ct = geo[GEO_STRIDE * tt + 21];
+    const R ot = MULTI ? (R)tobj[tt] : (R)0;
+    const R tv0 = (R)tri[3 * tt], tv1 = (R)tri[3 * tt + 1], tv2 = (R)tri[3 * tt + 2];
+
+    R a1r[NR][6], a1i[NR][6], a2r[NR][6], a2i[NR][6], Ar[NR][3], Ai[NR][3];
+    for (int r = 0; r < NR; r++) {
+        for (int i = 0; i < 6; i++) a1r[r][i] = a1i[r][i] = a2r[r][i] = a2i[r][i] = 0;
+        for (int c = 0; c < 3; c++) Ar[r][c] = Ai[r][c] = 0;
+    }
+    const int64_t rstride = (int64_t)gridDim.y * T * (ROW_STRIDE + 6);
+    double *out = partial + ((int64_t)split * T + tau) * ROW_STRIDE;
+    double *outA = partial + (int64_t)gridDim.y * T * ROW_STRIDE + ((int64_t)split * T + tau) * 6;
+    bool first = true;
+    auto flush = [&]() {
+        for (int r = 0; r < NR; r++) {
+            double v[ROW_STRIDE + 6];
+            for (int a = 0; a < 3; a++) {
+                double r1r = 0, r1i = 0, r2r = 0, r2i = 0;
+                for (int i = 0; i < 6; i++) {
+                    double wb = qw(i) * qb(i, a);
+                    r1r += wb * (double)a1r[r][i];
+                    r1i += wb * (double)a1i[r][i];
+                    r2r += wb * (double)a2r[r][i];
+                    r2i += wb * (double)a2i[r][i];
+                }
+                v[2 * a] = r1r;
+                v[2 * a + 1] = r1i;
+                v[6 + 2 * a] = r2r;
+                v[6 + 2 * a + 1] = r2i;
+            }
+            for (int c = 0; c < 3; c++) {
+                v[ROW_STRIDE + 2 * c] = (double)Ar[r][c];
+                v[ROW_STRIDE + 2 * c + 1] = (double)Ai[r][c];
+                Ar[r][c] = Ai[r][c] = 0;
+            }
+            for (int i = 0; i < 6; i++) a1r[r][i] = a1i[r][i] = a2r[r][i] = a2i[r][i] = 0;
+            if (active) {
+                double *o = out + r * rstride, *oA = outA + r * rstride;
+                for (int c = 0; c < ROW_STRIDE; c++) o[c] = first ? v[c] : o[c] + v[c];
+                for (int c = 0; c < 6; c++) oA[c] = first ? v[ROW_STRIDE + c] : oA[c] + v[ROW_STRIDE + c];
+            }
+        }
+        first = false;
+    };
+
+    for (int base = s_begin; base < s_end; base += FF_TILE) {
+        const int cnt = min(FF_TILE, s_end - base);
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < cnt * SM; idx += FF_BLOCK) {
+            const int sl = idx / SM, f = idx - sl * SM;
+            R v;
+            if (f < GEO_STRIDE) v = geo[(int64_t)GEO_STRIDE * (base + sl) + f];
+            else if (f == OBJ) v = MULTI ? (R)tobj[base + sl] : (R)0;
+            else if (f < DYN0) v = (R)tri[3 * (base + sl) + (f - VID)];
+            else {
+                const int r = (f - DYN0) / DYN_STRIDE, c = f - DYN0 - r * DYN_STRIDE;
+                v = dyn[((int64_t)r * T + base + sl) * DYN_STRIDE + c];
+            }
+            tile[idx] = v;
+        }
+        __syncthreads();
+        for (int sl = 0; sl < cnt; sl++) {
+            const R *src = &tile[sl * SM];
+            {
+                const R *sv = src + VID;
+                const bool adj = sv[0] == tv0 || sv[0] == tv1 || sv[0] == tv2 ||
+                                 sv[1] == tv0 || sv[1] == tv1 || sv[1] == tv2 ||
+                                 sv[2] == tv0 || sv[2] == tv1 || sv[2] == tv2;
+                if (adj) continue;   // includes sigma == tau: near field
+            }
+            const R nsx = src[18], nsy = src[19], nsz = src[20], cs = src[21];
+            const R m1 = MULTI ? (src[OBJ] == ot ? (R)1 : (R)0) : (R)1;
+            const R nn = ntx * nsx + nty * nsy + ntz * nsz;
+            const R gnr = cf.n0r * nn, gni = cf.n0i * nn;
+            R dnx[6], dny[6];
+            for (int j = 0; j < 6; j++)
+                dnx[j] = ct - (src[3 * j] * ntx + src[3 * j + 1] * nty + src[3 * j + 2] * ntz);
+            for (int i = 0; i < 6; i++)
+                dny[i] = cs - (px[i] * nsx + py[i] * nsy + pz[i] * nsz);
+            R gwr = 0, gwi = 0;
+#pragma unroll
+            for (int i = 0; i < 6; i++) {
+                R qr[NR], qi[NR], nr[NR], ni[NR];
+                for (int r = 0; r < NR; r++) qr[r] = qi[r] = nr[r] = ni[r] = 0;
+#pragma unroll
+                for (int j = 0; j < 6; j++) {
+                    const R dx = src[3 * j] - px[i];
+                    const R dy = src[3 * j + 1] - py[i];
+                    const R dz = src[3 * j + 2] - pz[i];
+                    const R r2 = dx * dx + dy * dy + dz * dz;
+                    const R ri = MT::rsq(r2);
+                    const R rr = r2 * ri;
+                    R E0r, E0i, E1r, E1i;
+                    MT::template sincos_rev<false>(rr * cf.krev0, E0i, E0r);
+                    MT::template sincos_rev<false>(rr * cf.krev1, E1i, E1r);
+                    if (CK0) {
+                        const R d0 = MT::exp2(rr * cf.kdec0);
+                        E0r *= d0;
+                        E0i *= d0;
+                    }
+                    if (CK1 || MULTI) {
+                        R d1 = m1;
+                        if (CK1) d1 *= MT::exp2(rr * cf.kdec1);
+                        E1r *= d1;
+                        E1i *= d1;
+                    }
+                    const R G0r = E0r * ri, G0i = E0i * ri;
+                    const R G1r = E1r * ri, G1i = E1i * ri;
+                    R Fr = -(G0r + G1r), Fi = -(G0i + G1i);
+                    Fr = fmac(-cf.k0r, E0i, Fr);
+                    Fi = fmac(cf.k0r, E0r, Fi);
+                    Fr = fmac(-cf.k1r, E1i, Fr);
+                    Fi = fmac(cf.k1r, E1r, Fi);
+                    if (CK0) {
+                        Fr = fmac(-cf.k0i, E0r, Fr);
+                        Fi = fmac(-cf.k0i, E0i, Fi);
+                    }
+                    if (CK1) {
+                        Fr = fmac(-cf.k1i, E1r, Fr);
+                        Fi = fmac(-cf.k1i, E1i, Fi);
+                    }
+                    const R ri2 = ri * ri;
+                    Fr *= ri2;
+                    Fi *= ri2;
+                    const R GVr = fmac(cf.rho, G1r, G0r), GVi = fmac(cf.rho, G1i, G0i);
+                    const R GWr = fmac(cf.irho, G1r, G0r), GWi = fmac(cf.irho, G1i, G0i);
+                    R GNr = fmac(cf.n10r, G1r, G0r), GNi = fmac(cf.n10r, G1i, G0i);
+                    if (CK0 || CK1) {
+                        GNr = fmac(-cf.n10i, G1i, GNr);
+                        GNi = fmac(cf.n10i, G1r, GNi);
+                    }
+                    const R Fxr = Fr * dnx[j], Fxi = Fi * dnx[j];
+#pragma unroll
+                    for (int r = 0; r < NR; r++) {
+                        const R *d = src + DYN0 + r * DYN_STRIDE;
+                        const R spr = d[2 * j], spi = d[2 * j + 1];
+                        const R sfr = d[12 + 2 * j], sfi = d[12 + 2 * j + 1];
+                        R t1r = a1r[r][i], t1i = a1i[r][i], t2r = a2r[r][i], t2i = a2i[r][i];
+                        t1r = fmac(GVr, spr, t1r);
+                        t1r = fmac(-GVi, spi, t1r);
+                        t1i = fmac(GVr, spi, t1i);
+                        t1i = fmac(GVi, spr, t1i);
+                        qr[r] = fmac(Fr, sfr, qr[r]);
+                        qr[r] = fmac(-Fi, sfi, qr[r]);
+                        qi[r] = fmac(Fr, sfi, qi[r]);
+                        qi[r] = fmac(Fi, sfr, qi[r]);
+                        t2r = fmac(Fxr, spr, t2r);
+                        t2r = fmac(-Fxi, spi, t2r);
+                        t2i = fmac(Fxr, spi, t2i);
+                        t2i = fmac(Fxi, spr, t2i);
+                        nr[r] = fmac(GNr, sfr, nr[r]);
+                        nr[r] = fmac(-GNi, sfi, nr[r]);
+                        ni[r] = fmac(GNr, sfi, ni[r]);
+                        ni[r] = fmac(GNi, sfr, ni[r]);
+                        a1r[r][i] = t1r;
+                        a1i[r][i] = t1i;
+                        a2r[r][i] = t2r;
+                        a2i[r][i] = t2i;
+                    }
+                    const R ww = (R)(qw(i) * qw(j));
+                    gwr = fmac(ww, GWr, gwr);
+                    gwi = fmac(ww, GWi, gwi);
+                }
+#pragma unroll
+                for (int r = 0; r < NR; r++) {
+                    a1r[r][i] = fmac(-dny[i], qr[r], a1r[r][i]);
+                    a1i[r][i] = fmac(-dny[i], qi[r], a1i[r][i]);
+                    R t2r = a2r[r][i], t2i = a2i[r][i];
+                    t2r = fmac(-gnr, nr[r], t2r);
+                    t2r = fmac(gni, ni[r], t2r);
+                    t2i = fmac(-gnr, ni[r], t2i);
+                    t2i = fmac(-gni, nr[r], t2i);
+                    a2r[r][i] = t2r;
+                    a2i[r][i] = t2i;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                const R *d = src + DYN0 + r * DYN_STRIDE;
+                for (int c = 0; c < 3; c++) {
+                    const R scr = d[24 + 2 * c], sci = d[24 + 2 * c + 1];
+                    Ar[r][c] += gwr * scr - gwi * sci;
+                    Ai[r][c] += gwr * sci + gwi * scr;
+                }
+            }
+        }
+        flush();
+    }
+    if (first) flush();   // empty split: zero partials
+}
+
 // --------------------------------------------------------- split reduction
 // trirows[tau][c] = |tau|/(4 pi) * sum_split (rows + curl term), fixed order.
 __global__ __launch_bounds__(256) void reduce_splits_kernel(
@@ -533,6 +760,41 @@ template <class R, bool FR> const void *far_kernel(int code) {
     }
 }
 
+template <int NR> const void *multi_kernel(int code) {
+    switch (code) {
+    case 0: return (const void *)farfield_multi_kernel<false, false, false, NR>;
+    case 1: return (const void *)farfield_multi_kernel<false, false, true, NR>;
+    case 2: return (const void *)farfield_multi_kernel<false, true, false, NR>;
+    case 3: return (const void *)farfield_multi_kernel<false, true, true, NR>;
+    case 4: return (const void *)farfield_multi_kernel<true, false, false, NR>;
+    case 5: return (const void *)farfield_multi_kernel<true, false, true, NR>;
+    case 6: return (const void *)farfield_multi_kernel<true, true, false, NR>;
+    default: return (const void *)farfield_multi_kernel<true, true, true, NR>;
+    }
+}
+
+template <int NR>
+void launch_multi(int code, dim3 grid, hipStream_t s, const float *geo, const float *dyn,
+                  const int32_t *tobj, const int32_t *tri, int T, int split_len, Coef<float> cf,
+                  double *partial) {
+    switch (code) {
+#define BEM_CASE(c, a, b, m)                                                                  \
+    case c:                                                                                   \
+        hipLaunchKernelGGL((farfield_multi_kernel<a, b, m, NR>), grid, dim3(FF_BLOCK), 0, s, \
+                           geo, dyn, tobj, tri, T, split_len, cf, partial);                   \
+        break;
+        BEM_CASE(0, false, false, false)
+        BEM_CASE(1, false, false, true)
+        BEM_CASE(2, false, true, false)
+        BEM_CASE(3, false, true, true)
+        BEM_CASE(4, true, false, false)
+        BEM_CASE(5, true, false, true)
+        BEM_CASE(6, true, true, false)
+        BEM_CASE(7, true, true, true)
+#undef BEM_CASE
+    }
+}
+
 // Workgroups of a pair kernel variant resident on the current device at once
 // (compute units x occupancy), cached per device and variant.
 int far_slots(const void *kern) {
@@ -602,11 +864,22 @@ FarPlan far_plan(const bem_mesh *m, int precision, double2 k0, double2 k1) {
 
 }   // namespace
 
-int64_t farfield_scratch_bytes(const bem_mesh *m, int precision, double2 k0, double2 k1) {
+// right-hand sides per multi-vector pair-kernel launch
+constexpr int FF_MULTI_MAX = 4;
+
+int64_t farfield_scratch_bytes(const bem_mesh *m, int precision, double2 k0, double2 k1, int R) {
     const FarPlan p = far_plan(m, precision, k0, k1);
     const int64_t T = m->T;
-    const int64_t dyn = T * DYN_STRIDE * (precision == BEM_FP32 ? 4 : 8);
-    return dyn + (int64_t)p.nsplit * T * (ROW_STRIDE + 6) * 8 + T * ROW_STRIDE * 8;
+    int64_t dyn = T * DYN_STRIDE * (precision == BEM_FP32 ? 4 : 8);
+    int64_t part = (int64_t)p.nsplit * T * (ROW_STRIDE + 6) * 8;
+    if (precision == BEM_FP32 && !p.fr && R >= 2) {
+        const int nr = std::min({R, FF_MULTI_MAX, tuning().farfield_multi_max.load()}) >= 4 ? 4 : 2;
+        const int ns = farfield_splits((int)T, far_slots(nr == 4 ? multi_kernel<4>(p.code)
+                                                                  : multi_kernel<2>(p.code)));
+        dyn = std::max(dyn, (int64_t)nr * T * DYN_STRIDE * 4);
+        part = std::max(part, (int64_t)nr * ns * T * (ROW_STRIDE + 6) * 8);
+    }
+    return dyn + part + T * ROW_STRIDE * 8;
 }
 
 void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
@@ -655,6 +928,64 @@ void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
                        m->trirows.p, m->star_ptr.p, m->star_idx.p, m->nf_rowptr.p,
                        m->nf_col.p, (const double2 *)nf.vals.p, m->nf_nnz, x, m->N, y);
     BEM_LAUNCH_CHECK();
+}
+
+namespace {
+
+// NR right-hand sides through the multi-vector kernel (FP32, no phase reduction).
+template <int NR>
+void farfield_multi_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
+                          double rho, int code, const double2 *x, double2 *y, hipStream_t s) {
+    const int T = (int)m->T;
+    const int64_t N = m->N, n2 = 2 * N;
+    const int nsplit = farfield_splits(T, far_slots(multi_kernel<NR>(code)));
+    const int split_len = (T + nsplit - 1) / nsplit;
+    const int64_t rstride = (int64_t)nsplit * T * (ROW_STRIDE + 6);
+    if (m->partial.n < (size_t)(NR * rstride)) m->partial.alloc((size_t)(NR * rstride));
+    if (m->trirows.n < (size_t)T * ROW_STRIDE) m->trirows.alloc((size_t)T * ROW_STRIDE);
+    if (m->dyn32.n < (size_t)NR * T * DYN_STRIDE) m->dyn32.alloc((size_t)NR * T * DYN_STRIDE);
+    dim3 gg((T + 255) / 256);
+    for (int r = 0; r < NR; r++) {
+        hipLaunchKernelGGL(source_gather_kernel<float>, gg, dim3(256), 0, s, m->tri_d.p, m->tst.p,
+                           x + r * n2, N, T, m->dyn32.p + (int64_t)r * T * DYN_STRIDE);
+        BEM_LAUNCH_CHECK();
+    }
+    {
+        Timer tm("farfield_fp32_multi", s);
+        launch_multi<NR>(code, dim3((T + FF_BLOCK - 1) / FF_BLOCK, nsplit), s, m->geo32.p,
+                         m->dyn32.p, m->tobj_d.p, m->tri_d.p, T, split_len,
+                         make_coef<float>(k0, k1, rho), m->partial.p);
+        BEM_LAUNCH_CHECK();
+    }
+    for (int r = 0; r < NR; r++) {
+        hipLaunchKernelGGL(reduce_splits_kernel, gg, dim3(256), 0, s, m->partial.p + r * rstride,
+                           m->tst.p, T, nsplit, m->trirows.p);
+        BEM_LAUNCH_CHECK();
+        hipLaunchKernelGGL(finalize_kernel, dim3((N + 255) / 256), dim3(256), 0, s, m->trirows.p,
+                           m->star_ptr.p, m->star_idx.p, m->nf_rowptr.p, m->nf_col.p,
+                           (const double2 *)nf.vals.p, m->nf_nnz, x + r * n2, N, y + r * n2);
+        BEM_LAUNCH_CHECK();
+    }
+}
+
+}   // namespace
+
+void farfield_apply_batch(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
+                          double rho, const double2 *x, double2 *y, int R, int precision,
+                          hipStream_t s) {
+    const int64_t n2 = 2 * m->N;
+    const FarPlan plan = far_plan(m, precision, k0, k1);
+    int r0 = 0;
+    const int mm = tuning().farfield_multi_max.load();
+    if (precision == BEM_FP32 && !plan.fr && mm >= 2) {
+        if (mm >= 4)
+            for (; R - r0 >= 4; r0 += 4)
+            farfield_multi_apply<4>(m, nf, k0, k1, rho, plan.code, x + r0 * n2, y + r0 * n2, s);
+        for (; R - r0 >= 2; r0 += 2)
+            farfield_multi_apply<2>(m, nf, k0, k1, rho, plan.code, x + r0 * n2, y + r0 * n2, s);
+    }
+    for (; r0 < R; r0++)
+        farfield_apply(m, nf, k0, k1, rho, x + r0 * n2, y + r0 * n2, precision, s);
 }
 
 }   // namespace bem

@@ -42,8 +42,7 @@ struct Op {
         if (precision == BEM_FP32_DENSE) {
             dense_apply(*dense, in, yw.p, R, m->xs32, s);
         } else {
-            for (int r = 0; r < R; r++)
-                farfield_apply(m, *nf, k0, k1, rho, in + r * n2, yw.p + r * n2, precision, s);
+            farfield_apply_batch(m, *nf, k0, k1, rho, in, yw.p, R, precision, s);
         }
         osrc_apply_from_weak(m, *st, yw.p, out, R, s);
     }
@@ -265,11 +264,10 @@ int64_t solve_footprint(bem_mesh *m, double2 k0, double2 k1, double rho,
     const int G = std::min(n_waves, SOLVE_BATCH);
     int64_t b = 4 * m->nf_nnz * c16;                          // near-field CSR values
     b += osrc_state_bytes(m, o.pade_terms, G);                 // OSRC factors + batch buffers
-    int64_t scratch = farfield_scratch_bytes(m, BEM_FP64, k0, k1);
+    int64_t scratch = farfield_scratch_bytes(m, BEM_FP64, k0, k1, G);
     const bool dense = o.precision == BEM_FP32 && o.path == 1;
     if (o.precision == BEM_FP32 && !dense)
-        scratch = std::max(scratch, farfield_scratch_bytes(m, BEM_FP32, k0, k1)) +
-                  m->T * DYN_STRIDE * 4;                      // dyn32 beside dyn64
+        scratch += farfield_scratch_bytes(m, BEM_FP32, k0, k1, G);   // dyn32 beside dyn64
     b += scratch;
     if (dense) b += dense_bytes(m) + dense_assembly_scratch_bytes(m) + 2 * G * n2 * 8 +
                     dense_gemm_scratch_bytes(m, G);

@@ -39,6 +39,7 @@ enum {
     BEM_OK = 0,
     BEM_W_NOT_CONVERGED = 1,   /* best iterate written */
     BEM_W_PENDING = 2,         /* bem_server_wait: not completed yet */
+    BEM_W_DEFAULT = 3,         /* bem_tune_lookup: no tuned entry, defaults returned */
     BEM_E_INVAL = -1,          /* bad argument */
     BEM_E_BAD_MESH = -2,       /* not a closed, oriented, manifold surface */
     BEM_E_NOMEM = -3,          /* device allocation / budget exceeded */
@@ -272,10 +273,12 @@ int bem_server_stats_get(bem_server *srv, bem_server_stats *stats);
 int bem_profile_enable(int enable);
 int bem_profile_read(const char *kernel, double *total_ms, int64_t *launches);
 
-/* Process-wide launch parameters (the autotuner sets them; defaults apply
- * otherwise):
+/* Process-wide default launch parameters, used for shapes without an
+ * autotuned entry:
  *   "farfield.multi_max"  right-hand sides sharing one pair-kernel launch on
  *                         the FP32 matrix-free path: 1, 2 or 4 (default 4)
+ *   "farfield.block"      test triangles per pair-kernel workgroup: 64, 128
+ *                         or 256 (default 256)
  *   "dense.gemm_min_rhs"  right-hand-side count from which the assembled
  *                         operator is applied with the MFMA product instead of
  *                         the multi-vector product (default 16)
@@ -283,6 +286,42 @@ int bem_profile_read(const char *kernel, double *total_ms, int64_t *launches);
  * the FP32 accuracy.  BEM_E_INVAL for an unknown key or value. */
 int bem_tune_set(const char *key, int64_t value);
 int bem_tune_get(const char *key, int64_t *value);
+
+/*
+ * Autotuner.  For a mesh size (triangle count) and a right-hand-side count it
+ * times, on the device, the pair-kernel workgroup size (64, 128 or 256 test
+ * triangles) and the right-hand sides per launch (1, 2, 4) of the FP32
+ * matrix-free operator, and, when the assembled complex64 operator fits in
+ * free device memory with 2 GiB to spare, its assembly and the product with
+ * n_rhs vectors (multi-vector product or MFMA).  The assembled path is chosen
+ * when assembly + expected_matvecs products beat expected_matvecs matrix-free
+ * applications.  The result is kept for (n_triangles, bucket of n_rhs:
+ * 1, 2-3, 4-7, 8-15, 16+) and used by every later matvec and solve of that
+ * shape: launch parameters always, the path when opts.path is 2 (auto).
+ * When a cache file was named with bem_tune_cache_load, new entries are
+ * appended to it.  The timing input is zero vectors; the operator is built
+ * for (k_ext, k_int, rho) and the assembled one freed after timing.
+ */
+typedef struct {
+    int block;               /* test triangles per pair-kernel workgroup */
+    int multi;               /* right-hand sides per pair-kernel launch */
+    int gemm_min;            /* assembled path: MFMA product from this many vectors */
+    int path;                /* -1 no preference, 0 matrix-free, 1 assembled */
+    double t_matrix_free;    /* seconds per operator application to n_rhs vectors */
+    double t_assembled;      /* same on the assembled operator (0 if not timed) */
+    double t_assembly;       /* seconds to assemble (0 if not timed) */
+} bem_tune_entry;
+
+int bem_autotune(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho, int n_rhs,
+                 int expected_matvecs, bem_tune_entry *out, void *hip_stream);
+/* Load entries for `arch` (NULL: the current device's, e.g. "gfx950") from a
+ * cache file and append later autotune results to it.  A missing file is an
+ * empty cache.  Malformed lines and other architectures are skipped. */
+int bem_tune_cache_load(const char *path, const char *arch, int *n_loaded);
+/* Entry for a shape: BEM_OK if tuned, BEM_W_DEFAULT with the defaults if not. */
+int bem_tune_lookup(int64_t n_triangles, int n_rhs, bem_tune_entry *out);
+/* Forget all tuned entries and the cache file name. */
+void bem_tune_clear(void);
 
 /* Diagnostic for the issue-bound roofline of the pair kernel: measured issue
  * rates, in lane operations per second summed over the device, of

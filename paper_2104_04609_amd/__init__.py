@@ -9,10 +9,12 @@ from ._binding import (BEM_FP32, BEM_FP32_DENSE, BEM_FP64, BemError, Mesh, Serve
                        SolveOpts,
                        default_opts, far_field, lib, osrc_apply, pmchwt_matvec,
                        pmchwt_rhs, pmchwt_solve, profile_enable, profile_read,
-                       tune_get, tune_set, valu_rates)
+                       autotune, tune_cache_load, tune_clear, tune_get, tune_lookup, tune_set,
+                       valu_rates)
 
 __all__ = ["BEM_FP32", "BEM_FP32_DENSE", "BEM_FP64", "BemError", "Mesh", "Server", "SolveInfo",
            "SolveOpts",
            "default_opts", "far_field", "lib", "osrc_apply", "pmchwt_matvec",
            "pmchwt_rhs", "pmchwt_solve", "profile_enable", "profile_read",
-           "tune_get", "tune_set", "valu_rates"]
+           "autotune", "tune_cache_load", "tune_clear", "tune_get", "tune_lookup", "tune_set",
+           "valu_rates"]

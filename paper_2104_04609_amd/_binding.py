@@ -25,7 +25,7 @@ lib = ctypes.CDLL(LIB_PATH)
 BEM_FP64, BEM_FP32, BEM_FP32_DENSE = 0, 1, 2
 _PREC = {"fp64": BEM_FP64, "fp32": BEM_FP32, "fp32_dense": BEM_FP32_DENSE,
          BEM_FP64: BEM_FP64, BEM_FP32: BEM_FP32, BEM_FP32_DENSE: BEM_FP32_DENSE}
-ERRORS = {1: "BEM_W_NOT_CONVERGED", 2: "BEM_W_PENDING", -1: "BEM_E_INVAL", -2: "BEM_E_BAD_MESH",
+ERRORS = {1: "BEM_W_NOT_CONVERGED", 2: "BEM_W_PENDING", 3: "BEM_W_DEFAULT", -1: "BEM_E_INVAL", -2: "BEM_E_BAD_MESH",
           -3: "BEM_E_NOMEM", -4: "BEM_E_DEVICE", -5: "BEM_E_NAN",
           -6: "BEM_E_UNSUPPORTED"}
 
@@ -51,6 +51,15 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("outer_steps", ctypes.c_int),
                 ("fp64_matvecs", ctypes.c_int), ("fp32_matvecs", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int), ("multi", ctypes.c_int), ("gemm_min", ctypes.c_int),
+                ("path", ctypes.c_int), ("t_matrix_free", ctypes.c_double),
+                ("t_assembled", ctypes.c_double), ("t_assembly", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -103,6 +112,12 @@ lib.bem_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double
                                  ctypes.POINTER(_i64)]
 lib.bem_valu_rates.argtypes = [_vp, _vp]
 lib.bem_tune_set.argtypes = [ctypes.c_char_p, _i64]
+lib.bem_autotune.argtypes = [_vp, c64, c64, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                             ctypes.POINTER(TuneEntry), _vp]
+lib.bem_tune_cache_load.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]
+lib.bem_tune_lookup.argtypes = [_i64, ctypes.c_int, ctypes.POINTER(TuneEntry)]
+lib.bem_tune_clear.argtypes = []
+lib.bem_tune_clear.restype = None
 lib.bem_tune_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(_i64)]
 lib.bem_server_opts_default.argtypes = [ctypes.POINTER(ServerOpts)]
 lib.bem_server_opts_default.restype = None
@@ -354,6 +369,34 @@ def profile_read(kernel: str):
     ms, n = ctypes.c_double(), _i64()
     _check(lib.bem_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def autotune(mesh: Mesh, k_ext, k_int, rho: float, n_rhs: int = 1,
+             expected_matvecs: int = 50, stream=None) -> dict:
+    """Time the launch choices on the device; the result is used from now on
+    for this mesh size and right-hand-side bucket."""
+    e = TuneEntry()
+    _check(lib.bem_autotune(mesh.handle, _c(k_ext), _c(k_int), float(rho), int(n_rhs),
+                            int(expected_matvecs), ctypes.byref(e), _stream(stream)))
+    return e.as_dict()
+
+
+def tune_cache_load(path: str, arch: Optional[str] = None) -> int:
+    n = ctypes.c_int()
+    _check(lib.bem_tune_cache_load(path.encode(), arch.encode() if arch else None,
+                                   ctypes.byref(n)))
+    return n.value
+
+
+def tune_lookup(n_triangles: int, n_rhs: int = 1):
+    """(entry, tuned): the autotuned entry, or the defaults with tuned False."""
+    e = TuneEntry()
+    rc = _check(lib.bem_tune_lookup(int(n_triangles), int(n_rhs), ctypes.byref(e)))
+    return e.as_dict(), rc == 0
+
+
+def tune_clear():
+    lib.bem_tune_clear()
 
 
 def tune_set(key: str, value: int):

@@ -241,6 +241,9 @@ int bem_tune_set(const char *key, int64_t value) {
     if (k == "farfield.multi_max") {
         if (value != 1 && value != 2 && value != 4) fail(BEM_E_INVAL, "farfield.multi_max: 1, 2 or 4");
         t.farfield_multi_max = (int)value;
+    } else if (k == "farfield.block") {
+        if (value != 64 && value != 128 && value != 256) fail(BEM_E_INVAL, "farfield.block: 64, 128 or 256");
+        t.farfield_block = (int)value;
     } else if (k == "dense.gemm_min_rhs") {
         if (value < 1 || value > 1 << 20) fail(BEM_E_INVAL, "dense.gemm_min_rhs out of range");
         t.dense_gemm_min_rhs = (int)value;
@@ -257,6 +260,7 @@ int bem_tune_get(const char *key, int64_t *value) {
     const std::string k(key);
     bem::Tuning &t = bem::tuning();
     if (k == "farfield.multi_max") *value = t.farfield_multi_max;
+    else if (k == "farfield.block") *value = t.farfield_block;
     else if (k == "dense.gemm_min_rhs") *value = t.dense_gemm_min_rhs;
     else fail(BEM_E_INVAL, "unknown tuning key " + k);
     return BEM_OK;

@@ -114,6 +114,7 @@ struct NearOperator {
 // Assembled complex64 operator [2N][2N] (row-major).
 struct DenseOperator {
     int64_t n2 = 0;
+    int64_t T = 0;             // triangles of the mesh (tuning lookups)
     DevBuf<float2> B;
 };
 
@@ -194,15 +195,37 @@ struct bem_mesh {
 
 namespace bem {
 
+// Process-wide default launch parameters (bem_tune_set / bem_tune_get).
+struct Tuning {
+    std::atomic<int> farfield_multi_max{4};   // right-hand sides per pair-kernel launch
+    std::atomic<int> farfield_block{256};     // test triangles per pair-kernel workgroup
+    std::atomic<int> dense_gemm_min_rhs{16};  // MFMA product from this many right-hand sides
+};
+Tuning &tuning();
+
+// Launch parameters for one (triangle count, right-hand-side bucket): an
+// autotuned entry (tune.cpp) or the defaults above.
+struct TuneEntry {
+    int block = 256;           // test triangles per pair-kernel workgroup: 64, 128, 256
+    int multi = 4;             // right-hand sides per pair-kernel launch: 1, 2, 4
+    int gemm_min = 16;         // MFMA product from this many right-hand sides
+    int path = -1;             // FP32 solves: -1 no preference, 0 matrix-free, 1 assembled
+    double t_mf = 0, t_dense = 0, t_asm = 0;   // seconds (R vectors; assembly)
+};
+int tune_bucket(int R);                    // 1, 2, 4, 8 or 16
+TuneEntry tune_lookup(int64_t T, int R);   // tuned entry, else defaults
+bool tune_find(int64_t T, int R, TuneEntry *e);
+
 // farfield.hip
 void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
                     double rho, const double2 *x, double2 *y, int precision,
-                    hipStream_t s);
+                    hipStream_t s, int block = 0);
 // y_r = B x_r for R right-hand sides ([R][2N]); FP32 shares each kernel
 // evaluation among up to 4 right-hand sides
+// Launch parameters: tune_lookup(T, R) unless `forced` is given.
 void farfield_apply_batch(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
                           double rho, const double2 *x, double2 *y, int R, int precision,
-                          hipStream_t s);
+                          hipStream_t s, const TuneEntry *forced = nullptr);
 // device scratch (source records, split partials, triangle rows) that
 // farfield_apply_batch needs for this precision, wavenumber pair and R
 int64_t farfield_scratch_bytes(const bem_mesh *m, int precision, double2 k0, double2 k1, int R);
@@ -226,17 +249,12 @@ void dense_gemm(const DenseOperator &op, const double2 *x, double2 *y, int R, hi
 int64_t dense_gemm_scratch_bytes(const bem_mesh *m, int R);
 // MFMA product from tuning().dense_gemm_min_rhs right-hand sides, else dense_gemv
 void dense_apply(const DenseOperator &op, const double2 *x, double2 *y, int R,
-                 DevBuf<float2> &xs, hipStream_t s);
+                 DevBuf<float2> &xs, hipStream_t s, const TuneEntry *forced = nullptr);
 
 // Issue rates (lane operations per second over the device) of v_fma_f32,
 // v_sin_f32, v_cos_f32, v_rsq_f32 and v_fma_f64; rates[5].
 void valu_rates(double *rates, hipStream_t s);
-// Process-wide tunable launch parameters (bem_tune_set / bem_tune_get).
-struct Tuning {
-    std::atomic<int> farfield_multi_max{4};   // right-hand sides per pair-kernel launch
-    std::atomic<int> dense_gemm_min_rhs{16};  // MFMA product from this many right-hand sides
-};
-Tuning &tuning();
+
 // mesh.cpp
 void mesh_build(bem_mesh *m, const double *P, int64_t N, const int32_t *tri,
                 int64_t T, const int32_t *obj);

@@ -398,6 +398,7 @@ std::unique_ptr<DenseOperator> dense_assemble(bem_mesh *m, const NearOperator &n
     auto op = std::make_unique<DenseOperator>();
     const int64_t N = m->N, n2 = 2 * N;
     op->n2 = n2;
+    op->T = m->T;
     op->B.alloc((size_t)(n2 * n2));
     DevBuf<float2> Q((size_t)m->T * JT * 12);
     const DCoef cf = make_dcoef(k0, k1, rho);
@@ -471,8 +472,9 @@ int64_t dense_gemm_scratch_bytes(const bem_mesh *m, int R) {
 }
 
 void dense_apply(const DenseOperator &op, const double2 *x, double2 *y, int R,
-                 DevBuf<float2> &xs, hipStream_t s) {
-    if (R >= tuning().dense_gemm_min_rhs.load()) dense_gemm(op, x, y, R, s);
+                 DevBuf<float2> &xs, hipStream_t s, const TuneEntry *forced) {
+    const int gmin = forced ? forced->gemm_min : tune_lookup(op.T, R).gemm_min;
+    if (R >= gmin) dense_gemm(op, x, y, R, s);
     else dense_gemv(op, x, y, R, xs, s);
 }
 

@@ -37,7 +37,7 @@ namespace bem {
 
 namespace {
 
-constexpr int FF_BLOCK = 256;   // test triangles (threads) per workgroup
+constexpr int FF_BLOCK = 256;   // largest workgroup (test triangles per workgroup)
 constexpr int FF_TILE = 32;     // trial triangles per LDS tile
 constexpr int SRC = GEO_STRIDE + DYN_STRIDE + 4;   // + object id, 3 vertex ids
 
@@ -189,8 +189,9 @@ void farfield_kernel(
     using MT = Math<R>;
     constexpr bool F32 = std::is_same<R, float>::value;
     __shared__ R tile[FF_TILE * SRC];
-    __shared__ double sums[F32 ? FF_ROWS * FF_BLOCK : 1];
-    const int tau = blockIdx.x * FF_BLOCK + threadIdx.x;
+    extern __shared__ double sums[];   // FP32: [FF_ROWS][blockDim.x] (dynamic)
+    const int nthr = blockDim.x;
+    const int tau = blockIdx.x * nthr + threadIdx.x;
     const int split = blockIdx.y;
     const int s_begin = split * split_len;
     const int s_end = min(T, s_begin + split_len);
@@ -217,11 +218,11 @@ void farfield_kernel(
     // 6 curl sums; in LDS for FP32, in registers for FP64
     double regsum[F32 ? 1 : FF_ROWS];
     auto sum_add = [&](int c, double v) {
-        if constexpr (F32) sums[c * FF_BLOCK + threadIdx.x] += v;
+        if constexpr (F32) sums[c * nthr + threadIdx.x] += v;
         else regsum[c] += v;
     };
     if constexpr (F32) {
-        for (int c = 0; c < FF_ROWS; c++) sums[c * FF_BLOCK + threadIdx.x] = 0;
+        for (int c = 0; c < FF_ROWS; c++) sums[c * nthr + threadIdx.x] = 0;
     } else {
         for (int c = 0; c < FF_ROWS; c++) regsum[c] = 0;
     }
@@ -252,7 +253,7 @@ void farfield_kernel(
     for (int base = s_begin; base < s_end; base += FF_TILE) {
         const int cnt = min(FF_TILE, s_end - base);
         __syncthreads();
-        for (int idx = threadIdx.x; idx < cnt * SRC; idx += FF_BLOCK) {
+        for (int idx = threadIdx.x; idx < cnt * SRC; idx += nthr) {
             int s = idx / SRC, f = idx - s * SRC;
             R v;
             if (f < GEO_STRIDE) v = geo[(int64_t)GEO_STRIDE * (base + s) + f];
@@ -393,7 +394,7 @@ void farfield_kernel(
     flush();
     if (!active) return;
     auto sum_get = [&](int c) -> double {
-        if constexpr (F32) return sums[c * FF_BLOCK + threadIdx.x];
+        if constexpr (F32) return sums[c * nthr + threadIdx.x];
         else return regsum[c];
     };
     double *out = partial + ((int64_t)split * T + tau) * ROW_STRIDE;
@@ -427,7 +428,8 @@ void farfield_multi_kernel(
     constexpr int SM = srcm<NR>();
     constexpr int OBJ = GEO_STRIDE, VID = GEO_STRIDE + 1, DYN0 = GEO_STRIDE + 4;
     __shared__ R tile[FF_TILE * SM];
-    const int tau = blockIdx.x * FF_BLOCK + threadIdx.x;
+    const int nthr = blockDim.x;
+    const int tau = blockIdx.x * nthr + threadIdx.x;
     const int split = blockIdx.y;
     const int s_begin = split * split_len;
     const int s_end = min(T, s_begin + split_len);
@@ -489,7 +491,7 @@ void farfield_multi_kernel(
     for (int base = s_begin; base < s_end; base += FF_TILE) {
         const int cnt = min(FF_TILE, s_end - base);
         __syncthreads();
-        for (int idx = threadIdx.x; idx < cnt * SM; idx += FF_BLOCK) {
+        for (int idx = threadIdx.x; idx < cnt * SM; idx += nthr) {
             const int sl = idx / SM, f = idx - sl * SM;
             R v;
             if (f < GEO_STRIDE) v = geo[(int64_t)GEO_STRIDE * (base + sl) + f];
@@ -716,24 +718,29 @@ template <class R> Coef<R> make_coef(double2 k0, double2 k1, double rho) {
     return c;
 }
 
+// dynamic LDS of the single-vector kernel: FP32 per-thread FP64 sums
+template <class R> size_t far_smem(int blk) {
+    return std::is_same<R, float>::value ? (size_t)FF_ROWS * blk * sizeof(double) : 0;
+}
+
 template <class R, bool CK0, bool CK1, bool MULTI, bool FR>
-void launch_far(dim3 grid, hipStream_t s, const R *geo, const R *dyn,
+void launch_far(dim3 grid, int blk, hipStream_t s, const R *geo, const R *dyn,
                 const int32_t *tobj, const int32_t *tri, int T, int split_len, Coef<R> cf,
                 double *partial) {
-    hipLaunchKernelGGL((farfield_kernel<R, CK0, CK1, MULTI, FR>), grid, dim3(FF_BLOCK), 0, s,
-                       geo, dyn, tobj, tri, T, split_len, cf, partial);
+    hipLaunchKernelGGL((farfield_kernel<R, CK0, CK1, MULTI, FR>), grid, dim3(blk), far_smem<R>(blk),
+                       s, geo, dyn, tobj, tri, T, split_len, cf, partial);
 }
 
 // fr: reduce phases to [0, 1) revolutions before v_sin/v_cos (needed when
 // k r / 2 pi can reach 256); the FP64 path always reduces.
 template <class R, bool FR>
-void dispatch_far(dim3 grid, hipStream_t s, const R *geo, const R *dyn,
+void dispatch_far(dim3 grid, int blk, hipStream_t s, const R *geo, const R *dyn,
                   const int32_t *tobj, const int32_t *tri, int T, int split_len, Coef<R> cf,
                   double *partial, bool ck0, bool ck1, bool multi) {
     int code = (ck0 ? 4 : 0) | (ck1 ? 2 : 0) | (multi ? 1 : 0);
     switch (code) {
 #define BEM_CASE(c, a, b, m) \
-    case c: launch_far<R, a, b, m, FR>(grid, s, geo, dyn, tobj, tri, T, split_len, cf, partial); break;
+    case c: launch_far<R, a, b, m, FR>(grid, blk, s, geo, dyn, tobj, tri, T, split_len, cf, partial); break;
         BEM_CASE(0, false, false, false)
         BEM_CASE(1, false, false, true)
         BEM_CASE(2, false, true, false)
@@ -774,13 +781,13 @@ template <int NR> const void *multi_kernel(int code) {
 }
 
 template <int NR>
-void launch_multi(int code, dim3 grid, hipStream_t s, const float *geo, const float *dyn,
+void launch_multi(int code, dim3 grid, int blk, hipStream_t s, const float *geo, const float *dyn,
                   const int32_t *tobj, const int32_t *tri, int T, int split_len, Coef<float> cf,
                   double *partial) {
     switch (code) {
 #define BEM_CASE(c, a, b, m)                                                                  \
     case c:                                                                                   \
-        hipLaunchKernelGGL((farfield_multi_kernel<a, b, m, NR>), grid, dim3(FF_BLOCK), 0, s, \
+        hipLaunchKernelGGL((farfield_multi_kernel<a, b, m, NR>), grid, dim3(blk), 0, s,      \
                            geo, dyn, tobj, tri, T, split_len, cf, partial);                   \
         break;
         BEM_CASE(0, false, false, false)
@@ -796,20 +803,21 @@ void launch_multi(int code, dim3 grid, hipStream_t s, const float *geo, const fl
 }
 
 // Workgroups of a pair kernel variant resident on the current device at once
-// (compute units x occupancy), cached per device and variant.
-int far_slots(const void *kern) {
+// (compute units x occupancy) for a block size and dynamic LDS, cached per
+// device and variant.
+int far_slots(const void *kern, int blk, size_t smem) {
     static std::mutex mu;
-    static std::map<std::pair<int, const void *>, int> cache;
+    static std::map<std::tuple<int, const void *, int>, int> cache;
     int dev = 0;
     BEM_HIP(hipGetDevice(&dev));
     std::lock_guard<std::mutex> g(mu);
-    auto it = cache.find({dev, kern});
+    auto it = cache.find({dev, kern, blk});
     if (it != cache.end()) return it->second;
     int cus = 0, per_cu = 0;
     BEM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    BEM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, FF_BLOCK, 0));
+    BEM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, blk, smem));
     const int slots = std::max(1, cus * per_cu);
-    cache[{dev, kern}] = slots;
+    cache[{dev, kern, blk}] = slots;
     return slots;
 }
 
@@ -819,8 +827,8 @@ int far_slots(const void *kern) {
 // about the same, so the launch runs in rounds of `slots` resident
 // workgroups; the split count minimises rounds x (trial triangles per split
 // + a small fixed cost), which avoids a nearly empty last round.
-int farfield_splits(int T, int slots) {
-    const int tiles = (T + FF_BLOCK - 1) / FF_BLOCK;
+int farfield_splits(int T, int slots, int blk) {
+    const int tiles = (T + blk - 1) / blk;
     const int max_s = std::max(1, (T + FF_TILE - 1) / FF_TILE);
     const double fixed = 2.0;   // prologue + flush, in trial triangles
     int best = 1;
@@ -843,10 +851,11 @@ namespace {
 struct FarPlan {
     int code;      // 4 ck0 + 2 ck1 + multi
     bool fr;       // phase reduction before v_sin/v_cos (FP32)
+    int blk;       // test triangles per workgroup
     int nsplit;    // trial-triangle splits (grid.y)
 };
 
-FarPlan far_plan(const bem_mesh *m, int precision, double2 k0, double2 k1) {
+FarPlan far_plan(const bem_mesh *m, int precision, double2 k0, double2 k1, int blk) {
     FarPlan p;
     const bool ck0 = k0.y != 0.0, ck1 = k1.y != 0.0, multi = m->nobj > 1;
     p.code = (ck0 ? 4 : 0) | (ck1 ? 2 : 0) | (multi ? 1 : 0);
@@ -854,39 +863,52 @@ FarPlan far_plan(const bem_mesh *m, int precision, double2 k0, double2 k1) {
     const double tmax = std::max(std::fabs(k0.x), std::fabs(k1.x)) * m->diameter *
                         0.15915494309189533576888376337251;
     p.fr = precision != BEM_FP32 || tmax >= 256.0;
+    p.blk = blk;
     const void *kern = precision == BEM_FP32
                            ? (p.fr ? far_kernel<float, true>(p.code)
                                    : far_kernel<float, false>(p.code))
                            : far_kernel<double, true>(p.code);
-    p.nsplit = farfield_splits((int)m->T, far_slots(kern));
+    const size_t smem = precision == BEM_FP32 ? far_smem<float>(blk) : 0;
+    p.nsplit = farfield_splits((int)m->T, far_slots(kern, blk, smem), blk);
     return p;
 }
+
+int valid_block(int b) { return b == 64 || b == 128 || b == 256 ? b : 256; }
 
 }   // namespace
 
 // right-hand sides per multi-vector pair-kernel launch
 constexpr int FF_MULTI_MAX = 4;
 
+// Upper bound over every block size and vectors-per-launch choice, so that
+// it holds whatever the tuning table says.
 int64_t farfield_scratch_bytes(const bem_mesh *m, int precision, double2 k0, double2 k1, int R) {
-    const FarPlan p = far_plan(m, precision, k0, k1);
     const int64_t T = m->T;
-    int64_t dyn = T * DYN_STRIDE * (precision == BEM_FP32 ? 4 : 8);
-    int64_t part = (int64_t)p.nsplit * T * (ROW_STRIDE + 6) * 8;
-    if (precision == BEM_FP32 && !p.fr && R >= 2) {
-        const int nr = std::min({R, FF_MULTI_MAX, tuning().farfield_multi_max.load()}) >= 4 ? 4 : 2;
-        const int ns = farfield_splits((int)T, far_slots(nr == 4 ? multi_kernel<4>(p.code)
-                                                                  : multi_kernel<2>(p.code)));
-        dyn = std::max(dyn, (int64_t)nr * T * DYN_STRIDE * 4);
-        part = std::max(part, (int64_t)nr * ns * T * (ROW_STRIDE + 6) * 8);
+    int64_t dyn = T * DYN_STRIDE * (precision == BEM_FP32 ? 4 : 8), part = 0;
+    for (int blk : {64, 128, 256}) {
+        const FarPlan p = far_plan(m, precision, k0, k1, blk);
+        part = std::max(part, (int64_t)p.nsplit * T * (ROW_STRIDE + 6) * 8);
+        if (precision == BEM_FP32 && !p.fr && R >= 2)
+            for (int nr : {2, 4}) {
+                if (nr > R) continue;
+                const int ns = farfield_splits(
+                    (int)T, far_slots(nr == 4 ? multi_kernel<4>(p.code) : multi_kernel<2>(p.code),
+                                      blk, 0),
+                    blk);
+                dyn = std::max(dyn, (int64_t)nr * T * DYN_STRIDE * 4);
+                part = std::max(part, (int64_t)nr * ns * T * (ROW_STRIDE + 6) * 8);
+            }
     }
     return dyn + part + T * ROW_STRIDE * 8;
 }
 
 void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
                     double rho, const double2 *x, double2 *y, int precision,
-                    hipStream_t s) {
+                    hipStream_t s, int block) {
     const int T = (int)m->T;
-    const FarPlan plan = far_plan(m, precision, k0, k1);
+    const FarPlan plan =
+        far_plan(m, precision, k0, k1, valid_block(block > 0 ? block : tune_lookup(T, 1).block));
+    const int blk = plan.blk;
     const int nsplit = plan.nsplit;
     const bool ck0 = k0.y != 0.0, ck1 = k1.y != 0.0, multi = m->nobj > 1, fr = plan.fr;
     const int split_len = (T + nsplit - 1) / nsplit;
@@ -894,7 +916,7 @@ void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
     if (m->partial.n < need) m->partial.alloc(need);
     if (m->trirows.n < (size_t)T * ROW_STRIDE) m->trirows.alloc((size_t)T * ROW_STRIDE);
     dim3 gg((T + 255) / 256);
-    dim3 grid((T + FF_BLOCK - 1) / FF_BLOCK, nsplit);
+    dim3 grid((T + blk - 1) / blk, nsplit);
     if (precision == BEM_FP32) {
         if (m->dyn32.n < (size_t)T * DYN_STRIDE) m->dyn32.alloc((size_t)T * DYN_STRIDE);
         hipLaunchKernelGGL(source_gather_kernel<float>, gg, dim3(256), 0, s, m->tri_d.p,
@@ -902,11 +924,11 @@ void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
         BEM_LAUNCH_CHECK();
         Timer tm("farfield_fp32", s);
         if (!fr)
-            dispatch_far<float, false>(grid, s, m->geo32.p, m->dyn32.p, m->tobj_d.p, m->tri_d.p,
+            dispatch_far<float, false>(grid, blk, s, m->geo32.p, m->dyn32.p, m->tobj_d.p, m->tri_d.p,
                                        T, split_len, make_coef<float>(k0, k1, rho),
                                        m->partial.p, ck0, ck1, multi);
         else
-            dispatch_far<float, true>(grid, s, m->geo32.p, m->dyn32.p, m->tobj_d.p, m->tri_d.p,
+            dispatch_far<float, true>(grid, blk, s, m->geo32.p, m->dyn32.p, m->tobj_d.p, m->tri_d.p,
                                       T, split_len, make_coef<float>(k0, k1, rho),
                                       m->partial.p, ck0, ck1, multi);
         BEM_LAUNCH_CHECK();
@@ -916,7 +938,7 @@ void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
                            m->tst.p, x, m->N, T, m->dyn64.p);
         BEM_LAUNCH_CHECK();
         Timer tm("farfield_fp64", s);
-        dispatch_far<double, true>(grid, s, m->geo64.p, m->dyn64.p, m->tobj_d.p, m->tri_d.p, T, split_len,
+        dispatch_far<double, true>(grid, blk, s, m->geo64.p, m->dyn64.p, m->tobj_d.p, m->tri_d.p, T, split_len,
                              make_coef<double>(k0, k1, rho), m->partial.p, ck0, ck1, multi);
         BEM_LAUNCH_CHECK();
     }
@@ -935,10 +957,11 @@ namespace {
 // NR right-hand sides through the multi-vector kernel (FP32, no phase reduction).
 template <int NR>
 void farfield_multi_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
-                          double rho, int code, const double2 *x, double2 *y, hipStream_t s) {
+                          double rho, int code, int blk, const double2 *x, double2 *y,
+                          hipStream_t s) {
     const int T = (int)m->T;
     const int64_t N = m->N, n2 = 2 * N;
-    const int nsplit = farfield_splits(T, far_slots(multi_kernel<NR>(code)));
+    const int nsplit = farfield_splits(T, far_slots(multi_kernel<NR>(code), blk, 0), blk);
     const int split_len = (T + nsplit - 1) / nsplit;
     const int64_t rstride = (int64_t)nsplit * T * (ROW_STRIDE + 6);
     if (m->partial.n < (size_t)(NR * rstride)) m->partial.alloc((size_t)(NR * rstride));
@@ -952,7 +975,7 @@ void farfield_multi_apply(bem_mesh *m, const NearOperator &nf, double2 k0, doubl
     }
     {
         Timer tm("farfield_fp32_multi", s);
-        launch_multi<NR>(code, dim3((T + FF_BLOCK - 1) / FF_BLOCK, nsplit), s, m->geo32.p,
+        launch_multi<NR>(code, dim3((T + blk - 1) / blk, nsplit), blk, s, m->geo32.p,
                          m->dyn32.p, m->tobj_d.p, m->tri_d.p, T, split_len,
                          make_coef<float>(k0, k1, rho), m->partial.p);
         BEM_LAUNCH_CHECK();
@@ -972,20 +995,24 @@ void farfield_multi_apply(bem_mesh *m, const NearOperator &nf, double2 k0, doubl
 
 void farfield_apply_batch(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
                           double rho, const double2 *x, double2 *y, int R, int precision,
-                          hipStream_t s) {
+                          hipStream_t s, const TuneEntry *forced) {
     const int64_t n2 = 2 * m->N;
-    const FarPlan plan = far_plan(m, precision, k0, k1);
+    const TuneEntry te = forced ? *forced : tune_lookup(m->T, R);
+    const int blk = valid_block(te.block);
+    const FarPlan plan = far_plan(m, precision, k0, k1, blk);
     int r0 = 0;
-    const int mm = tuning().farfield_multi_max.load();
+    const int mm = te.multi;
     if (precision == BEM_FP32 && !plan.fr && mm >= 2) {
         if (mm >= 4)
             for (; R - r0 >= 4; r0 += 4)
-            farfield_multi_apply<4>(m, nf, k0, k1, rho, plan.code, x + r0 * n2, y + r0 * n2, s);
+                farfield_multi_apply<4>(m, nf, k0, k1, rho, plan.code, blk, x + r0 * n2,
+                                        y + r0 * n2, s);
         for (; R - r0 >= 2; r0 += 2)
-            farfield_multi_apply<2>(m, nf, k0, k1, rho, plan.code, x + r0 * n2, y + r0 * n2, s);
+            farfield_multi_apply<2>(m, nf, k0, k1, rho, plan.code, blk, x + r0 * n2, y + r0 * n2,
+                                    s);
     }
     for (; r0 < R; r0++)
-        farfield_apply(m, nf, k0, k1, rho, x + r0 * n2, y + r0 * n2, precision, s);
+        farfield_apply(m, nf, k0, k1, rho, x + r0 * n2, y + r0 * n2, precision, s, blk);
 }
 
 }   // namespace bem

@@ -382,9 +382,12 @@ int bem_server_submit(bem_server *srv, int mesh_id, bem_c64 k_ext, bem_c64 k_int
         r->dirs.assign(directions, directions + 3 * n_waves);
         r->solution = (double2 *)solution;
         r->info = info;
-        // the path depends on the request alone
-        if (r->o.precision == BEM_FP32 && r->o.path == 2)
-            r->o.path = bem::dense_bytes(h0) <= srv->o.dense_max_bytes ? 1 : 0;
+        // the path depends on the request alone (and the autotuned table)
+        if (r->o.precision == BEM_FP32 && r->o.path == 2) {
+            bem::TuneEntry te;
+            const bool mf = bem::tune_find(h0->T, std::min(n_waves, 16), &te) && te.path == 0;
+            r->o.path = !mf && bem::dense_bytes(h0) <= srv->o.dense_max_bytes ? 1 : 0;
+        }
         BEM_HIP(hipGetDevice(&prev));
         BEM_HIP(hipSetDevice(srv->device));
         r->footprint = bem::solve_footprint(h0, r->k0, r->k1, rho, r->o, n_waves);

@@ -295,11 +295,13 @@ int solve_run(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dir
     int inner = BEM_FP32;
     if (o.precision == BEM_FP32 && o.path != 0) {
         bool use = o.path == 1;
-        if (o.path == 2) {   // dense when it fits with room to spare
+        if (o.path == 2) {   // autotuned choice, else dense when it fits with room to spare
             size_t free_b = 0, total_b = 0;
             BEM_HIP(hipMemGetInfo(&free_b, &total_b));
-            use = dense_bytes(m) + (int64_t)(2ll << 30) < (int64_t)free_b ||
-                  !m->dense_cache.empty();
+            const bool fits = dense_bytes(m) + (int64_t)(2ll << 30) < (int64_t)free_b ||
+                              !m->dense_cache.empty();
+            TuneEntry te;
+            use = fits && !(tune_find(m->T, std::min(n_waves, SOLVE_BATCH), &te) && te.path == 0);
         }
         if (use) {
             op.dense = &dense_get(m, k0, k1, rho, s);

@@ -252,3 +252,25 @@ def test_matvec_multi_rhs_full_size_sampled_rows(P, multi_max):
         e2 = np.linalg.norm(Y[r][N + rows] - r2) / np.linalg.norm(r2)
         print(r, e1, e2)
         assert e1 <= TOL["fp32"] and e2 <= TOL["fp32"]
+
+
+@pytest.mark.parametrize("block", [64, 128])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_matvec_workgroup_sizes(P, block, precision):
+    """Pair kernel with 64 and 128 test triangles per workgroup (ragged last
+    workgroup on the geodesic mesh) against the oracle's dense matrix."""
+    old = P.tune_get("farfield.block")
+    try:
+        P.tune_set("farfield.block", block)
+        for case in ("geodesic3_ragged", "two_spheres1"):
+            make, k0, k1, rho = CASES[case]
+            mesh = make()
+            N = mesh.n_vertices
+            x = complex_normal(2 * N, seed=0)
+            ref = dense(mesh, k0, k1, rho) @ x
+            y = gpu_matvec(P, mesh, k0, k1, rho, x, precision)
+            err = rel_blocks(y, ref, N)
+            print(case, block, precision, err)
+            assert max(err.values()) <= TOL[precision], err
+    finally:
+        P.tune_set("farfield.block", old)

@@ -33,11 +33,11 @@ __host__ __device__ constexpr double qb(int i, int a) {
 constexpr int JT = 512;   // trial vertices per assembly tile
 
 struct DCoef {
-    float krev0, krev1, k0r, k0i, k1r, k1i, kdec0, kdec1, rho, irho, n0r, n0i, n1r, n1i;
+    float krev0, krev1, k0r, k0i, k1r, k1i, kdec0, kdec1, rho, irho, n0r, n0i, n10r, n10i;
 };
 
 __device__ __forceinline__ void sincos_rev(float t, float &s, float &c) {
-    const float f = t - __builtin_rintf(t);   // hardware sin/cos take revolutions
+    const float f = __builtin_amdgcn_fractf(t);   // hardware sin/cos take revolutions
     s = __builtin_amdgcn_sinf(f);
     c = __builtin_amdgcn_cosf(f);
 }
@@ -80,19 +80,20 @@ __global__ __launch_bounds__(256) void dense_pairs_kernel(
         const float as = (float)tst[TST_STRIDE * s];
         const float m1 = MULTI ? (tobj[s] == ot ? 1.f : 0.f) : 1.f;
         const float nn = ntx * nsx + nty * nsy + ntz * nsz;
-        const float g0r = cf.n0r * nn, g0i = cf.n0i * nn, g1r = cf.n1r * nn, g1i = cf.n1i * nn;
-        float tq[6], dnx[6], dny[6];
+        // factor of the G_N term taken out of the q sum: k_0^2 (n_x . n_y)
+        const float gnr = cf.n0r * nn, gni = cf.n0i * nn;
+        float tq[6], tx[6], dny[6];
         for (int q = 0; q < 6; q++) {
             tq[q] = (float)(qw(q) * qb(q, b)) * as;
-            dnx[q] = ct - (h[3 * q] * ntx + h[3 * q + 1] * nty + h[3 * q + 2] * ntz);
+            // (x - y).n_x = c_tau - y.n_tau, folded into the trial weight
+            tx[q] = (ct - (h[3 * q] * ntx + h[3 * q + 1] * nty + h[3 * q + 2] * ntz)) * tq[q];
         }
         for (int p = 0; p < 6; p++) dny[p] = cs - (px[p] * nsx + py[p] * nsy + pz[p] * nsz);
         float ar[4][6], ai[4][6];
-        for (int k = 0; k < 4; k++)
-            for (int p = 0; p < 6; p++) ar[k][p] = ai[k][p] = 0.f;
         float gwr = 0.f, gwi = 0.f;
 #pragma unroll
         for (int p = 0; p < 6; p++) {
+            float vr = 0.f, vi = 0.f, fr = 0.f, fi = 0.f, kr = 0.f, ki = 0.f, nr = 0.f, ni = 0.f;
 #pragma unroll
             for (int q = 0; q < 6; q++) {
                 const float dx = h[3 * q] - px[p], dy = h[3 * q + 1] - py[p],
@@ -100,41 +101,69 @@ __global__ __launch_bounds__(256) void dense_pairs_kernel(
                 const float r2 = dx * dx + dy * dy + dz * dz;
                 const float ri = __builtin_amdgcn_rsqf(r2);
                 const float r = r2 * ri;
-                float s0, c0, s1, c1;
-                sincos_rev(r * cf.krev0, s0, c0);
-                sincos_rev(r * cf.krev1, s1, c1);
-                float ri0 = ri, ri1 = ri * m1;
-                if (CK0) ri0 *= __builtin_amdgcn_exp2f(r * cf.kdec0);
-                if (CK1) ri1 *= __builtin_amdgcn_exp2f(r * cf.kdec1);
-                const float G0r = c0 * ri0, G0i = s0 * ri0, G1r = c1 * ri1, G1i = s1 * ri1;
-                float F0r, F0i, F1r, F1i;
-                {
-                    const float ur = cf.k0r * r, ui = CK0 ? cf.k0i * r : 0.f;
-                    F0r = -G0r * (1.f + ui) - G0i * ur;
-                    F0i = -G0i * (1.f + ui) + G0r * ur;
+                // E_m = e^{i k_m r} (interior term masked across objects)
+                float E0r, E0i, E1r, E1i;
+                sincos_rev(r * cf.krev0, E0i, E0r);
+                sincos_rev(r * cf.krev1, E1i, E1r);
+                if (CK0) {
+                    const float d0 = __builtin_amdgcn_exp2f(r * cf.kdec0);
+                    E0r *= d0;
+                    E0i *= d0;
                 }
-                {
-                    const float ur = cf.k1r * r, ui = CK1 ? cf.k1i * r : 0.f;
-                    F1r = -G1r * (1.f + ui) - G1i * ur;
-                    F1i = -G1i * (1.f + ui) + G1r * ur;
+                if (CK1 || MULTI) {
+                    float d1 = m1;
+                    if (CK1) d1 *= __builtin_amdgcn_exp2f(r * cf.kdec1);
+                    E1r *= d1;
+                    E1i *= d1;
+                }
+                const float G0r = E0r * ri, G0i = E0i * ri, G1r = E1r * ri, G1i = E1i * ri;
+                // F r^2 = i (k_0 E_0 + k_1 E_1) - G_0 - G_1
+                float Fr = -(G0r + G1r), Fi = -(G0i + G1i);
+                Fr = __builtin_fmaf(-cf.k0r, E0i, Fr);
+                Fi = __builtin_fmaf(cf.k0r, E0r, Fi);
+                Fr = __builtin_fmaf(-cf.k1r, E1i, Fr);
+                Fi = __builtin_fmaf(cf.k1r, E1r, Fi);
+                if (CK0) {
+                    Fr = __builtin_fmaf(-cf.k0i, E0r, Fr);
+                    Fi = __builtin_fmaf(-cf.k0i, E0i, Fi);
+                }
+                if (CK1) {
+                    Fr = __builtin_fmaf(-cf.k1i, E1r, Fr);
+                    Fi = __builtin_fmaf(-cf.k1i, E1i, Fi);
                 }
                 const float ri2 = ri * ri;
-                const float Fr = (F0r + F1r) * ri2, Fi = (F0i + F1i) * ri2;
+                Fr *= ri2;
+                Fi *= ri2;
                 const float t = tq[q];
-                // V-row psi column: G_V;  V-row phi column: -F (y-x).n_y
-                ar[0][p] += (G0r + cf.rho * G1r) * t;
-                ai[0][p] += (G0i + cf.rho * G1i) * t;
-                ar[1][p] -= Fr * dny[p] * t;
-                ai[1][p] -= Fi * dny[p] * t;
-                // D-row psi column: F (x-y).n_x;  D-row phi column: -G_N (n_x.n_y)
-                ar[2][p] += Fr * dnx[q] * t;
-                ai[2][p] += Fi * dnx[q] * t;
-                ar[3][p] -= (g0r * G0r - g0i * G0i + g1r * G1r - g1i * G1i) * t;
-                ai[3][p] -= (g0r * G0i + g0i * G0r + g1r * G1i + g1i * G1r) * t;
+                // V-row psi column: G_V t
+                vr = __builtin_fmaf(__builtin_fmaf(cf.rho, G1r, G0r), t, vr);
+                vi = __builtin_fmaf(__builtin_fmaf(cf.rho, G1i, G0i), t, vi);
+                // V-row phi column: -(y - x).n_y F t (the factor after the q sum)
+                fr = __builtin_fmaf(Fr, t, fr);
+                fi = __builtin_fmaf(Fi, t, fi);
+                // D-row psi column: F (x - y).n_x t
+                kr = __builtin_fmaf(Fr, tx[q], kr);
+                ki = __builtin_fmaf(Fi, tx[q], ki);
+                // D-row phi column: -k_0^2 (n_x.n_y) (G_0 + k_1^2/(rho k_0^2) G_1) t
+                float Nr = __builtin_fmaf(cf.n10r, G1r, G0r), Ni = __builtin_fmaf(cf.n10r, G1i, G0i);
+                if (CK0 || CK1) {
+                    Nr = __builtin_fmaf(-cf.n10i, G1i, Nr);
+                    Ni = __builtin_fmaf(cf.n10i, G1r, Ni);
+                }
+                nr = __builtin_fmaf(Nr, t, nr);
+                ni = __builtin_fmaf(Ni, t, ni);
                 const float ww = (float)(qw(p) * qw(q));
-                gwr += ww * (G0r + cf.irho * G1r);
-                gwi += ww * (G0i + cf.irho * G1i);
+                gwr = __builtin_fmaf(ww, __builtin_fmaf(cf.irho, G1r, G0r), gwr);
+                gwi = __builtin_fmaf(ww, __builtin_fmaf(cf.irho, G1i, G0i), gwi);
             }
+            ar[0][p] = vr;
+            ai[0][p] = vi;
+            ar[1][p] = -dny[p] * fr;
+            ai[1][p] = -dny[p] * fi;
+            ar[2][p] = kr;
+            ai[2][p] = ki;
+            ar[3][p] = -(gnr * nr - gni * ni);
+            ai[3][p] = -(gnr * ni + gni * nr);
         }
         // contract with the test functions; curl-curl part of D
         float scb[3];
@@ -374,8 +403,12 @@ DCoef make_dcoef(double2 k0, double2 k1, double rho) {
     c.irho = (float)(1.0 / rho);
     c.n0r = (float)(k0.x * k0.x - k0.y * k0.y);
     c.n0i = (float)(2.0 * k0.x * k0.y);
-    c.n1r = (float)((k1.x * k1.x - k1.y * k1.y) / rho);
-    c.n1i = (float)(2.0 * k1.x * k1.y / rho);
+    // k_1^2 / (rho k_0^2); k_0 != 0 is checked at the entry points
+    const double n0r = k0.x * k0.x - k0.y * k0.y, n0i = 2.0 * k0.x * k0.y;
+    const double n1r = (k1.x * k1.x - k1.y * k1.y) / rho, n1i = 2.0 * k1.x * k1.y / rho;
+    const double d = n0r * n0r + n0i * n0i;
+    c.n10r = (float)((n1r * n0r + n1i * n0i) / d);
+    c.n10i = (float)((n1i * n0r - n1r * n0i) / d);
     return c;
 }
 

@@ -50,11 +50,35 @@ def cpu_baseline(mesh, n_test=384):
                       f"both wavenumbers, 4 operators, FP64 ({dt:.1f} s)"}
 
 
+def pmc_traffic():
+    """HBM bytes per launch of the FP32 pair kernel from the committed PMC
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel of known size),
+    or None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "farfield_fp32_ico5_pmc.md")
+    try:
+        text = open(path).read()
+        rec = json.loads(re.search(r"```json\n(.*?)```", text, re.S).group(1))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, AttributeError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    kib = 1024.0
+    fetch = rec["fetch_kib"] * kib * rec["copy_bytes"] / (rec["copy_fetch_kib"] * kib)
+    write = rec["write_kib"] * kib * rec["copy_bytes"] / (rec["copy_write_kib"] * kib)
+    return {"bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write,
+            "source": "profiles/farfield_fp32_ico5_pmc.md"}
+
+
 def batch_measure(P, M, mesh, mf_step_s):
     """64 plane-wave right-hand sides (normalised Gaussian directions, seed
     2104) at 4 wavenumber pairs k_ext in {4, 8, 12, 16}, k_int = 1.5 k_ext,
     rho = 1.5: assembled complex64 operator x 64-column block on MFMA,
-    against the matrix-free FP32 matvec per right-hand side."""
+    against the matrix-free FP32 operator on the same block (4 right-hand
+    sides per pair-kernel launch).  Then 8 plane waves solved in one lockstep
+    group against 8 single-wave solves (FP32 + refinement, assembled path)."""
     import torch
     from bem_inputs import wave_directions
     from paper_2104_04609_amd import roofline as RL
@@ -80,13 +104,37 @@ def batch_measure(P, M, mesh, mf_step_s):
         kms, kn = P.profile_read("dense_gemm_mfma")
         P.profile_enable(False)
         flops = 8.0 * (2 * N) ** 2 * 64
+        # matrix-free FP32 on the same 64-column block
+        P.pmchwt_matvec(M, ke, 1.5 * ke, 1.5, F, Y, precision="fp32")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.pmchwt_matvec(M, ke, 1.5 * ke, 1.5, F, Y, precision="fp32")
+        torch.cuda.synchronize()
+        mf_s = time.perf_counter() - t0
         out["k_pairs"].append({
             "k_ext": ke, "k_int": 1.5 * ke, "assembly_ms": asm_ms,
             "first_call_s": first, "gemm_call_ms": gemm_s * 1e3,
             "mfma_kernel_ms": kms / kn,
             "mfma_tflops": flops / (kms / kn * 1e-3) / 1e12,
-            "mfma_frac_of_fp32_matrix_peak": flops / (kms / kn * 1e-3) / 1e12 / RL.PEAK_FP32_TFLOPS})
-    out["matrix_free_64_rhs_s_estimate"] = 64 * mf_step_s
+            "mfma_frac_of_fp32_matrix_peak": flops / (kms / kn * 1e-3) / 1e12 / RL.PEAK_FP32_TFLOPS,
+            "matrix_free_64_rhs_ms": mf_s * 1e3,
+            "matrix_free_64_rhs_ms_one_per_launch": 64 * mf_step_s * 1e3})
+    # lockstep multi-wave solve against single-wave solves
+    d8 = wave_directions(8, seed=2104)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info8, rc8 = P.pmchwt_solve(M, K_EXT, K_INT, RHO, d8, 1e-6, precision="fp32", path=1)
+    torch.cuda.synchronize()
+    lock_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for w in range(8):
+        P.pmchwt_solve(M, K_EXT, K_INT, RHO, d8[w:w + 1], 1e-6, precision="fp32", path=1)
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - t0
+    out["solve_8_waves"] = {"lockstep_s": lock_s, "one_at_a_time_s": seq_s, "rc": rc8,
+                            "speedup": seq_s / lock_s,
+                            "max_rel_residual": max(i["rel_residual"] for i in info8),
+                            "k_ext": K_EXT, "k_int": K_INT, "path": "assembled (FP32 + refine)"}
     return out
 
 
@@ -222,6 +270,9 @@ def main():
     rates = P.valu_rates()
     pairs = RL.far_pairs_per_matvec(mesh.triangles)
     roof = RL.pair_kernel_roofline(pairs, kern_ms * 1e-3, "fp32", rates)
+    traffic = pmc_traffic()
+    roof["traffic"] = traffic["bytes"] if traffic else None
+    roof["traffic_detail"] = traffic
     roof64 = RL.pair_kernel_roofline(pairs, kern64_ms * 1e-3, "fp64")
     value = T * (T - 1) / step_s
 
@@ -229,6 +280,9 @@ def main():
     if not args.no_solve:
         try:
             solve = {}
+            # near-field and OSRC factors are built once per handle: warm them so
+            # that no timed solve pays for them (untimed, one iteration)
+            P.pmchwt_solve(M, K_EXT, K_INT, RHO, [[0, 0, 1]], 1e-6, precision="fp64", maxiter=1)
             # FP64 GMRES, FP32 matrix-free + refinement, FP32 assembled dense
             # operator + refinement (assembly included in its time)
             for name, prec, path in (("fp64", "fp64", 0), ("fp32", "fp32", 0),
@@ -239,8 +293,27 @@ def main():
                                                precision=prec, path=path)
                 torch.cuda.synchronize()
                 solve[name] = {"seconds": time.perf_counter() - t0, "rc": rc, **info[0]}
+            # the autotuner's choice for this shape (matrix-free vs assembled), then a
+            # solve on the auto path
+            # (fresh handle with warm near field and OSRC, so that assembly, when
+            # chosen, is paid inside the timed solve)
+            M2 = P.Mesh.from_inputs(mesh)
+            P.pmchwt_solve(M2, K_EXT, K_INT, RHO, [[0, 0, 1]], 1e-6, precision="fp64", maxiter=1)
+            tuned = P.autotune(M2, K_EXT, K_INT, RHO, n_rhs=1,
+                               expected_matvecs=solve["fp32"]["iterations"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sol, info, rc = P.pmchwt_solve(M2, K_EXT, K_INT, RHO, [[0, 0, 1]], 1e-6,
+                                           precision="fp32", path=2)
+            torch.cuda.synchronize()
+            solve["fp32_autotuned"] = {"seconds": time.perf_counter() - t0, "rc": rc,
+                                       "tune": tuned, **info[0]}
+            P.tune_clear()
+            del M2
             solve["speedup_fp32_refine_vs_fp64"] = (solve["fp64"]["seconds"] /
                                                     solve["fp32"]["seconds"])
+            solve["speedup_fp32_autotuned_vs_fp64"] = (solve["fp64"]["seconds"] /
+                                                       solve["fp32_autotuned"]["seconds"])
             solve["speedup_fp32_dense_refine_vs_fp64"] = (solve["fp64"]["seconds"] /
                                                           solve["fp32_dense"]["seconds"])
             # dense GEMV throughput (operator resident after the solve)

@@ -311,13 +311,16 @@ __global__ __launch_bounds__(256) void gemm_xprep_kernel(const double2 *__restri
     row1[2 * r + 1] = (float)v.x;
 }
 
-// partial products of K chunk blockIdx.z: Yp[z][M][Np]; 4 waves, 64 x 64 each
+// partial products of K chunk blockIdx.z: Yp[z][M][Np]; 4 waves, 64 x 64 each.
+// The next K step's tiles are loaded into registers (16-byte loads) while the
+// current one is multiplied from LDS, then stored to the other LDS buffer:
+// one barrier per K step.  Kp and Np are multiples of 4, chunk ends of 32.
 __global__ __launch_bounds__(256) void gemm_mfma_kernel(const float *__restrict__ A,
                                                         const float *__restrict__ Xp,
                                                         float *__restrict__ Yp, int64_t M,
                                                         int64_t Kp, int Np) {
-    __shared__ float As[GM][GK + 1];
-    __shared__ float Bs[GK][GN];
+    __shared__ float As[2][GM][GK + 1];
+    __shared__ float Bs[2][GK][GN];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t m0 = (int64_t)blockIdx.x * GM;
     const int n0 = blockIdx.y * GN;
@@ -328,29 +331,50 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const float *__restrict_
     for (int i = 0; i < 2; i++)
         for (int j = 0; j < 2; j++)
             for (int v = 0; v < 16; v++) acc[i][j][v] = 0.f;
+    // per thread: 4 float4 of the A tile (rows idx / 8, columns 4 (idx % 8)) and
+    // 4 float4 of the B tile (rows idx / 32, columns 4 (idx % 32)), idx = i 256 + t
+    float4 ra[4], rb[4];
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    auto gload = [&](int64_t k0) {
+        for (int i = 0; i < 4; i++) {
+            const int idx = i * 256 + t;
+            const int64_t gr = m0 + idx / 8, gc = k0 + 4 * (idx % 8);
+            ra[i] = (gr < M && gc < kend) ? *(const float4 *)(A + gr * Kp + gc) : zero4;
+            const int64_t br = k0 + idx / 32;
+            rb[i] = br < kend ? *(const float4 *)(Xp + br * Np + n0 + 4 * (idx % 32)) : zero4;
+        }
+    };
+    auto lstore = [&](int buf) {
+        for (int i = 0; i < 4; i++) {
+            const int idx = i * 256 + t;
+            float *a = &As[buf][idx / 8][4 * (idx % 8)];
+            a[0] = ra[i].x;
+            a[1] = ra[i].y;
+            a[2] = ra[i].z;
+            a[3] = ra[i].w;
+            *(float4 *)&Bs[buf][idx / 32][4 * (idx % 32)] = rb[i];
+        }
+    };
+    gload(kbeg);
+    lstore(0);
+    __syncthreads();
+    int cur = 0;
     for (int64_t k0 = kbeg; k0 < kend; k0 += GK) {
-        __syncthreads();
-        for (int i = 0; i < (GM * GK) / 256; i++) {
-            const int idx = i * 256 + t, row = idx / GK, col = idx % GK;
-            const int64_t gr = m0 + row, gc = k0 + col;
-            As[row][col] = (gr < M && gc < kend) ? A[gr * Kp + gc] : 0.f;
-        }
-        for (int i = 0; i < (GK * GN) / 256; i++) {
-            const int idx = i * 256 + t, row = idx / GN, col = idx % GN;
-            const int64_t gr = k0 + row;
-            Bs[row][col] = gr < kend ? Xp[gr * Np + n0 + col] : 0.f;
-        }
-        __syncthreads();
+        const bool more = k0 + GK < kend;
+        if (more) gload(k0 + GK);
 #pragma unroll
         for (int kk = 0; kk < GK; kk += 2) {
             const int ka = kk + (lane >> 5);
-            const float a0 = As[wr + (lane & 31)][ka], a1 = As[wr + 32 + (lane & 31)][ka];
-            const float b0 = Bs[ka][wc + (lane & 31)], b1 = Bs[ka][wc + 32 + (lane & 31)];
+            const float a0 = As[cur][wr + (lane & 31)][ka], a1 = As[cur][wr + 32 + (lane & 31)][ka];
+            const float b0 = Bs[cur][ka][wc + (lane & 31)], b1 = Bs[cur][ka][wc + 32 + (lane & 31)];
             acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
             acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
             acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
             acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
         }
+        if (more) lstore(cur ^ 1);
+        __syncthreads();
+        cur ^= 1;
     }
     float *Y = Yp + (int64_t)blockIdx.z * M * Np;
     for (int i = 0; i < 2; i++)

@@ -415,16 +415,19 @@ void farfield_kernel(
 // in the thread's own partial slots.
 template <int NR> constexpr int srcm() { return GEO_STRIDE + 4 + NR * DYN_STRIDE; }
 
-template <int NR> constexpr int multi_waves() { return NR >= 4 ? 1 : 2; }
+template <class R, int NR> constexpr int multi_waves() {
+    return std::is_same<R, double>::value || NR >= 4 ? 1 : 2;
+}
 
-template <bool CK0, bool CK1, bool MULTI, int NR>
-__global__ __launch_bounds__(FF_BLOCK) __attribute__((amdgpu_waves_per_eu(multi_waves<NR>())))
+template <class R, bool CK0, bool CK1, bool MULTI, int NR>
+__global__ __launch_bounds__(FF_BLOCK) __attribute__((amdgpu_waves_per_eu(multi_waves<R, NR>())))
 void farfield_multi_kernel(
-    const float *__restrict__ geo, const float *__restrict__ dyn,
+    const R *__restrict__ geo, const R *__restrict__ dyn,
     const int32_t *__restrict__ tobj, const int32_t *__restrict__ tri, int T,
-    int split_len, Coef<float> cf, double *__restrict__ partial) {
-    using R = float;
-    using MT = Math<float>;
+    int split_len, Coef<R> cf, double *__restrict__ partial) {
+    using MT = Math<R>;
+    // FP32 phases are below 256 revolutions on this path; FP64 always reduces
+    constexpr bool FRM = std::is_same<R, double>::value;
     constexpr int SM = srcm<NR>();
     constexpr int OBJ = GEO_STRIDE, VID = GEO_STRIDE + 1, DYN0 = GEO_STRIDE + 4;
     __shared__ R tile[FF_TILE * SM];
@@ -536,8 +539,8 @@ void farfield_multi_kernel(
                     const R ri = MT::rsq(r2);
                     const R rr = r2 * ri;
                     R E0r, E0i, E1r, E1i;
-                    MT::template sincos_rev<false>(rr * cf.krev0, E0i, E0r);
-                    MT::template sincos_rev<false>(rr * cf.krev1, E1i, E1r);
+                    MT::template sincos_rev<FRM>(rr * cf.krev0, E0i, E0r);
+                    MT::template sincos_rev<FRM>(rr * cf.krev1, E1i, E1r);
                     if (CK0) {
                         const R d0 = MT::exp2(rr * cf.kdec0);
                         E0r *= d0;
@@ -767,28 +770,28 @@ template <class R, bool FR> const void *far_kernel(int code) {
     }
 }
 
-template <int NR> const void *multi_kernel(int code) {
+template <class R, int NR> const void *multi_kernel(int code) {
     switch (code) {
-    case 0: return (const void *)farfield_multi_kernel<false, false, false, NR>;
-    case 1: return (const void *)farfield_multi_kernel<false, false, true, NR>;
-    case 2: return (const void *)farfield_multi_kernel<false, true, false, NR>;
-    case 3: return (const void *)farfield_multi_kernel<false, true, true, NR>;
-    case 4: return (const void *)farfield_multi_kernel<true, false, false, NR>;
-    case 5: return (const void *)farfield_multi_kernel<true, false, true, NR>;
-    case 6: return (const void *)farfield_multi_kernel<true, true, false, NR>;
-    default: return (const void *)farfield_multi_kernel<true, true, true, NR>;
+    case 0: return (const void *)farfield_multi_kernel<R, false, false, false, NR>;
+    case 1: return (const void *)farfield_multi_kernel<R, false, false, true, NR>;
+    case 2: return (const void *)farfield_multi_kernel<R, false, true, false, NR>;
+    case 3: return (const void *)farfield_multi_kernel<R, false, true, true, NR>;
+    case 4: return (const void *)farfield_multi_kernel<R, true, false, false, NR>;
+    case 5: return (const void *)farfield_multi_kernel<R, true, false, true, NR>;
+    case 6: return (const void *)farfield_multi_kernel<R, true, true, false, NR>;
+    default: return (const void *)farfield_multi_kernel<R, true, true, true, NR>;
     }
 }
 
-template <int NR>
-void launch_multi(int code, dim3 grid, int blk, hipStream_t s, const float *geo, const float *dyn,
-                  const int32_t *tobj, const int32_t *tri, int T, int split_len, Coef<float> cf,
+template <class R, int NR>
+void launch_multi(int code, dim3 grid, int blk, hipStream_t s, const R *geo, const R *dyn,
+                  const int32_t *tobj, const int32_t *tri, int T, int split_len, Coef<R> cf,
                   double *partial) {
     switch (code) {
-#define BEM_CASE(c, a, b, m)                                                                  \
-    case c:                                                                                   \
-        hipLaunchKernelGGL((farfield_multi_kernel<a, b, m, NR>), grid, dim3(blk), 0, s,      \
-                           geo, dyn, tobj, tri, T, split_len, cf, partial);                   \
+#define BEM_CASE(c, a, b, m)                                                                     \
+    case c:                                                                                      \
+        hipLaunchKernelGGL((farfield_multi_kernel<R, a, b, m, NR>), grid, dim3(blk), 0, s,      \
+                           geo, dyn, tobj, tri, T, split_len, cf, partial);                      \
         break;
         BEM_CASE(0, false, false, false)
         BEM_CASE(1, false, false, true)
@@ -879,25 +882,28 @@ int valid_block(int b) { return b == 64 || b == 128 || b == 256 ? b : 256; }
 
 // right-hand sides per multi-vector pair-kernel launch
 constexpr int FF_MULTI_MAX = 4;
+constexpr int FF_MULTI_MAX_FP64 = 2;
 
 // Upper bound over every block size and vectors-per-launch choice, so that
 // it holds whatever the tuning table says.
 int64_t farfield_scratch_bytes(const bem_mesh *m, int precision, double2 k0, double2 k1, int R) {
     const int64_t T = m->T;
-    int64_t dyn = T * DYN_STRIDE * (precision == BEM_FP32 ? 4 : 8), part = 0;
+    const bool f32 = precision == BEM_FP32;
+    const int64_t rb = f32 ? 4 : 8;
+    int64_t dyn = T * DYN_STRIDE * rb, part = 0;
     for (int blk : {64, 128, 256}) {
         const FarPlan p = far_plan(m, precision, k0, k1, blk);
         part = std::max(part, (int64_t)p.nsplit * T * (ROW_STRIDE + 6) * 8);
-        if (precision == BEM_FP32 && !p.fr && R >= 2)
-            for (int nr : {2, 4}) {
-                if (nr > R) continue;
-                const int ns = farfield_splits(
-                    (int)T, far_slots(nr == 4 ? multi_kernel<4>(p.code) : multi_kernel<2>(p.code),
-                                      blk, 0),
-                    blk);
-                dyn = std::max(dyn, (int64_t)nr * T * DYN_STRIDE * 4);
-                part = std::max(part, (int64_t)nr * ns * T * (ROW_STRIDE + 6) * 8);
-            }
+        if (R < 2 || (f32 && p.fr)) continue;
+        for (int nr : {2, 4}) {
+            if (nr > R || (!f32 && nr > FF_MULTI_MAX_FP64)) continue;
+            const void *k = f32 ? (nr == 4 ? multi_kernel<float, 4>(p.code)
+                                           : multi_kernel<float, 2>(p.code))
+                                : multi_kernel<double, 2>(p.code);
+            const int ns = farfield_splits((int)T, far_slots(k, blk, 0), blk);
+            dyn = std::max(dyn, (int64_t)nr * T * DYN_STRIDE * rb);
+            part = std::max(part, (int64_t)nr * ns * T * (ROW_STRIDE + 6) * 8);
+        }
     }
     return dyn + part + T * ROW_STRIDE * 8;
 }
@@ -954,30 +960,40 @@ void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
 
 namespace {
 
-// NR right-hand sides through the multi-vector kernel (FP32, no phase reduction).
-template <int NR>
+// NR right-hand sides through the multi-vector kernel (FP32 without phase
+// reduction, or FP64).
+template <class R, int NR>
 void farfield_multi_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
                           double rho, int code, int blk, const double2 *x, double2 *y,
                           hipStream_t s) {
+    constexpr bool F32 = std::is_same<R, float>::value;
     const int T = (int)m->T;
     const int64_t N = m->N, n2 = 2 * N;
-    const int nsplit = farfield_splits(T, far_slots(multi_kernel<NR>(code), blk, 0), blk);
+    const int nsplit = farfield_splits(T, far_slots(multi_kernel<R, NR>(code), blk, 0), blk);
     const int split_len = (T + nsplit - 1) / nsplit;
     const int64_t rstride = (int64_t)nsplit * T * (ROW_STRIDE + 6);
     if (m->partial.n < (size_t)(NR * rstride)) m->partial.alloc((size_t)(NR * rstride));
     if (m->trirows.n < (size_t)T * ROW_STRIDE) m->trirows.alloc((size_t)T * ROW_STRIDE);
-    if (m->dyn32.n < (size_t)NR * T * DYN_STRIDE) m->dyn32.alloc((size_t)NR * T * DYN_STRIDE);
+    R *dyn;
+    if constexpr (F32) {
+        if (m->dyn32.n < (size_t)NR * T * DYN_STRIDE) m->dyn32.alloc((size_t)NR * T * DYN_STRIDE);
+        dyn = m->dyn32.p;
+    } else {
+        if (m->dyn64.n < (size_t)NR * T * DYN_STRIDE) m->dyn64.alloc((size_t)NR * T * DYN_STRIDE);
+        dyn = m->dyn64.p;
+    }
+    const R *geo = F32 ? (const R *)m->geo32.p : (const R *)m->geo64.p;
     dim3 gg((T + 255) / 256);
     for (int r = 0; r < NR; r++) {
-        hipLaunchKernelGGL(source_gather_kernel<float>, gg, dim3(256), 0, s, m->tri_d.p, m->tst.p,
-                           x + r * n2, N, T, m->dyn32.p + (int64_t)r * T * DYN_STRIDE);
+        hipLaunchKernelGGL(source_gather_kernel<R>, gg, dim3(256), 0, s, m->tri_d.p, m->tst.p,
+                           x + r * n2, N, T, dyn + (int64_t)r * T * DYN_STRIDE);
         BEM_LAUNCH_CHECK();
     }
     {
-        Timer tm("farfield_fp32_multi", s);
-        launch_multi<NR>(code, dim3((T + blk - 1) / blk, nsplit), blk, s, m->geo32.p,
-                         m->dyn32.p, m->tobj_d.p, m->tri_d.p, T, split_len,
-                         make_coef<float>(k0, k1, rho), m->partial.p);
+        Timer tm(F32 ? "farfield_fp32_multi" : "farfield_fp64_multi", s);
+        launch_multi<R, NR>(code, dim3((T + blk - 1) / blk, nsplit), blk, s, geo, dyn,
+                            m->tobj_d.p, m->tri_d.p, T, split_len, make_coef<R>(k0, k1, rho),
+                            m->partial.p);
         BEM_LAUNCH_CHECK();
     }
     for (int r = 0; r < NR; r++) {
@@ -1005,11 +1021,15 @@ void farfield_apply_batch(bem_mesh *m, const NearOperator &nf, double2 k0, doubl
     if (precision == BEM_FP32 && !plan.fr && mm >= 2) {
         if (mm >= 4)
             for (; R - r0 >= 4; r0 += 4)
-                farfield_multi_apply<4>(m, nf, k0, k1, rho, plan.code, blk, x + r0 * n2,
-                                        y + r0 * n2, s);
+                farfield_multi_apply<float, 4>(m, nf, k0, k1, rho, plan.code, blk, x + r0 * n2,
+                                               y + r0 * n2, s);
         for (; R - r0 >= 2; r0 += 2)
-            farfield_multi_apply<2>(m, nf, k0, k1, rho, plan.code, blk, x + r0 * n2, y + r0 * n2,
-                                    s);
+            farfield_multi_apply<float, 2>(m, nf, k0, k1, rho, plan.code, blk, x + r0 * n2,
+                                           y + r0 * n2, s);
+    } else if (precision == BEM_FP64 && mm >= 2) {
+        for (; R - r0 >= 2; r0 += 2)
+            farfield_multi_apply<double, 2>(m, nf, k0, k1, rho, plan.code, blk, x + r0 * n2,
+                                            y + r0 * n2, s);
     }
     for (; r0 < R; r0++)
         farfield_apply(m, nf, k0, k1, rho, x + r0 * n2, y + r0 * n2, precision, s, blk);

@@ -156,6 +156,9 @@ def test_solve_not_converged_returns_best_iterate(P):
 
 
 def test_solve_multiple_waves(P):
+    """FP64: waves solved in one lockstep group (pair kernel shared by two
+    vectors, summed in another order) against each wave alone, both to 1e-9;
+    the discrete solution is unique, so they agree to the solve accuracy."""
     from bem_inputs import wave_directions
     mesh = icosphere(2)
     M = P.Mesh.from_inputs(mesh)
@@ -163,8 +166,10 @@ def test_solve_multiple_waves(P):
     sol, info, rc = P.pmchwt_solve(M, 2.0, 3.0, 1.5, d, 1e-9)
     assert rc == 0
     for w in range(3):
-        one, _, _ = P.pmchwt_solve(M, 2.0, 3.0, 1.5, d[w:w + 1], 1e-9)
-        assert np.allclose(one.cpu().numpy()[0], sol.cpu().numpy()[w], rtol=0, atol=1e-14)
+        one, i1, _ = P.pmchwt_solve(M, 2.0, 3.0, 1.5, d[w:w + 1], 1e-9)
+        a, b = sol.cpu().numpy()[w], one.cpu().numpy()[0]
+        assert info[w]["rel_residual"] <= 1e-9 and i1[0]["rel_residual"] <= 1e-9
+        assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-8, w
 
 
 def test_solve_lockstep_waves_fp32_dense(P):

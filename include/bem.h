@@ -279,6 +279,10 @@ int bem_profile_read(const char *kernel, double *total_ms, int64_t *launches);
  *                         the FP32 matrix-free path: 1, 2 or 4 (default 4)
  *   "farfield.block"      test triangles per pair-kernel workgroup: 64, 128
  *                         or 256 (default 256)
+ *   "dense.skinny_min_rhs" right-hand-side count (>= 2) from which products
+ *                         with the assembled operator below gemm_min use the
+ *                         16-column MFMA kernel instead of the multi-vector
+ *                         GEMV (default 5)
  *   "dense.gemm_min_rhs"  right-hand-side count from which the assembled
  *                         operator is applied with the MFMA product instead of
  *                         the multi-vector product (default 16)
@@ -293,9 +297,9 @@ int bem_tune_get(const char *key, int64_t *value);
  * triangles) and the right-hand sides per launch (1, 2, 4) of the FP32
  * matrix-free operator, and, when the assembled complex64 operator fits in
  * free device memory with 2 GiB to spare, its assembly and the product with
- * n_rhs vectors (multi-vector product or MFMA).  The assembled path is chosen
- * when assembly + expected_matvecs products beat expected_matvecs matrix-free
- * applications.  The result is kept for (n_triangles, bucket of n_rhs:
+ * n_rhs vectors (multi-vector GEMV, 16-column MFMA kernel or MFMA GEMM).  The
+ * assembled path is chosen when assembly + expected_matvecs products beat
+ * expected_matvecs matrix-free applications.  The result is kept for (n_triangles, bucket of n_rhs:
  * 1, 2-3, 4-7, 8-15, 16+) and used by every later matvec and solve of that
  * shape: launch parameters always, the path when opts.path is 2 (auto).
  * When a cache file was named with bem_tune_cache_load, new entries are
@@ -305,7 +309,9 @@ int bem_tune_get(const char *key, int64_t *value);
 typedef struct {
     int block;               /* test triangles per pair-kernel workgroup */
     int multi;               /* right-hand sides per pair-kernel launch */
-    int gemm_min;            /* assembled path: MFMA product from this many vectors */
+    int gemm_min;            /* assembled path: MFMA GEMM from this many vectors */
+    int skinny_min;          /* below gemm_min: 16-column MFMA product from this many, else
+                                the multi-vector GEMV */
     int path;                /* -1 no preference, 0 matrix-free, 1 assembled */
     double t_matrix_free;    /* seconds per operator application to n_rhs vectors */
     double t_assembled;      /* same on the assembled operator (0 if not timed) */

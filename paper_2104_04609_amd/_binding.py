@@ -58,7 +58,8 @@ class SolveInfo(ctypes.Structure):
 
 class TuneEntry(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int), ("multi", ctypes.c_int), ("gemm_min", ctypes.c_int),
-                ("path", ctypes.c_int), ("t_matrix_free", ctypes.c_double),
+                ("skinny_min", ctypes.c_int), ("path", ctypes.c_int),
+                ("t_matrix_free", ctypes.c_double),
                 ("t_assembled", ctypes.c_double), ("t_assembly", ctypes.c_double)]
 
     def as_dict(self):

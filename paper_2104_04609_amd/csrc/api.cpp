@@ -244,6 +244,9 @@ int bem_tune_set(const char *key, int64_t value) {
     } else if (k == "farfield.block") {
         if (value != 64 && value != 128 && value != 256) fail(BEM_E_INVAL, "farfield.block: 64, 128 or 256");
         t.farfield_block = (int)value;
+    } else if (k == "dense.skinny_min_rhs") {
+        if (value < 2 || value > 1 << 20) fail(BEM_E_INVAL, "dense.skinny_min_rhs out of range");
+        t.dense_skinny_min_rhs = (int)value;
     } else if (k == "dense.gemm_min_rhs") {
         if (value < 1 || value > 1 << 20) fail(BEM_E_INVAL, "dense.gemm_min_rhs out of range");
         t.dense_gemm_min_rhs = (int)value;
@@ -261,6 +264,7 @@ int bem_tune_get(const char *key, int64_t *value) {
     bem::Tuning &t = bem::tuning();
     if (k == "farfield.multi_max") *value = t.farfield_multi_max;
     else if (k == "farfield.block") *value = t.farfield_block;
+    else if (k == "dense.skinny_min_rhs") *value = t.dense_skinny_min_rhs;
     else if (k == "dense.gemm_min_rhs") *value = t.dense_gemm_min_rhs;
     else fail(BEM_E_INVAL, "unknown tuning key " + k);
     return BEM_OK;

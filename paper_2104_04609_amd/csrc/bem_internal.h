@@ -200,6 +200,7 @@ struct Tuning {
     std::atomic<int> farfield_multi_max{4};   // right-hand sides per pair-kernel launch
     std::atomic<int> farfield_block{256};     // test triangles per pair-kernel workgroup
     std::atomic<int> dense_gemm_min_rhs{16};  // MFMA product from this many right-hand sides
+    std::atomic<int> dense_skinny_min_rhs{5}; // skinny MFMA product from this many (else multi-GEMV)
 };
 Tuning &tuning();
 
@@ -209,6 +210,7 @@ struct TuneEntry {
     int block = 256;           // test triangles per pair-kernel workgroup: 64, 128, 256
     int multi = 4;             // right-hand sides per pair-kernel launch: 1, 2, 4
     int gemm_min = 16;         // MFMA product from this many right-hand sides
+    int skinny_min = 5;        // below gemm_min: skinny MFMA product from this many, else multi-vector GEMV
     int path = -1;             // FP32 solves: -1 no preference, 0 matrix-free, 1 assembled
     double t_mf = 0, t_dense = 0, t_asm = 0;   // seconds (R vectors; assembly)
 };
@@ -243,7 +245,7 @@ const DenseOperator &dense_get(bem_mesh *m, double2 k0, double2 k1, double rho, 
 // y_r = B x_r, r < R (x, y RHS-major [R][2N]): multi-vector product reading B
 // once per 8 right-hand sides
 void dense_gemv(const DenseOperator &op, const double2 *x, double2 *y, int R, DevBuf<float2> &xs,
-                hipStream_t s);
+                hipStream_t s, bool skinny = true);
 // Y = B X for R right-hand sides (x, y RHS-major [R][2N]) on MFMA
 void dense_gemm(const DenseOperator &op, const double2 *x, double2 *y, int R, hipStream_t s);
 int64_t dense_gemm_scratch_bytes(const bem_mesh *m, int R);

@@ -405,6 +405,104 @@ __global__ __launch_bounds__(256) void gemm_reduce_kernel(const float *__restric
     y[(int64_t)r * M + m] = make_double2(sr, si);
 }
 
+// ------------------------------------ 2-8 right-hand sides: skinny MFMA product
+// The same real GEMM with 16 columns (8 complex right-hand sides) on
+// v_mfma_f32_16x16x4f32.  HBM-bound: every wave streams blocks of 16 rows of
+// B over its K chunk, 1 KB of each row per step, with load instructions that
+// read 64 contiguous bytes of each of the 16 rows (the four lanes q of a row
+// are adjacent): long per-row runs keep HBM streaming.  The operand is the
+// transposed, re/im interleaved XT[16][Kp].  The 4 k-slots of an MFMA may
+// hold any 4 values of k as long as A and XT agree: in a step of 256, lane
+// (i, q) = (lane % 16, lane / 16) holds k = kb + 16c + 4q + e (c < 16, e < 4)
+// and MFMA (c, e) takes component e of its c-th 16-byte load.
+constexpr int SK_ROWS = 256;    // rows per workgroup (4 waves x 4 blocks of 16)
+constexpr int SK_KC = 1024;     // split-K chunk (real K): FP32 accumulation length
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// XT[2r][2k], XT[2r][2k+1], XT[2r+1][2k], XT[2r+1][2k+1] from x[r][k], r < R <= 8
+__global__ __launch_bounds__(256) void skinny_xprep_kernel(const double2 *__restrict__ x, int R,
+                                                           int64_t K, float *__restrict__ XT) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= K * 8) return;
+    const int r = (int)(id / K);
+    const int64_t k = id - (int64_t)r * K;
+    const double2 v = r < R ? x[(int64_t)r * K + k] : make_double2(0.0, 0.0);
+    const int64_t Kp = 2 * K;
+    float *re = XT + (2 * r) * Kp, *im = re + Kp;
+    re[2 * k] = (float)v.x;
+    re[2 * k + 1] = (float)(-v.y);
+    im[2 * k] = (float)v.y;
+    im[2 * k + 1] = (float)v.x;
+}
+
+// Yp[chunk][M][16] partial products; grid (ceil(M / 256), chunks).  The
+// workgroup's XT chunk [16][SK_KC] is staged in LDS once; every wave streams
+// 4 blocks of 16 rows, block by block, 1 KB of each row per step.
+__global__ __launch_bounds__(256) void skinny_mfma_kernel(const float *__restrict__ A,
+                                                          const float *__restrict__ XT,
+                                                          float *__restrict__ Yp, int64_t M,
+                                                          int64_t Kp) {
+    // rows padded by 4 floats: the 16 rows' 16-byte reads fall in distinct banks
+    constexpr int XS = SK_KC + 4;
+    __shared__ float xs[16 * XS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, q = lane >> 4;
+    const int64_t kbeg = (int64_t)blockIdx.y * SK_KC;
+    const int64_t kend = kbeg + SK_KC < Kp ? kbeg + SK_KC : Kp;
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int idx = threadIdx.x; idx < 16 * SK_KC / 4; idx += 256) {
+        const int c = idx / (SK_KC / 4), k4 = 4 * (idx - c * (SK_KC / 4));
+        *(float4 *)&xs[c * XS + k4] =
+            kbeg + k4 < kend ? *(const float4 *)(XT + (int64_t)c * Kp + kbeg + k4) : zero4;
+    }
+    __syncthreads();
+    floatx4 acc[4];
+    for (int b = 0; b < 4; b++)
+        for (int v = 0; v < 4; v++) acc[b][v] = 0.f;
+    const int64_t rbase = (int64_t)blockIdx.x * SK_ROWS + wave * 64;
+    // units u = (step, block): 16 rows x 256 k; the next unit's 16 loads are
+    // issued before this unit's 64 MFMAs
+    const int nsteps = (int)((kend - kbeg + 255) / 256);
+    auto load = [&](int u, float4 (&a)[16]) {
+        const int64_t kb = kbeg + 256 * (int64_t)(u >> 2);
+        const int64_t row = rbase + 16 * (u & 3) + i;
+        const bool rin = row < M;
+        const float *arow = A + (rin ? row : 0) * Kp;
+        for (int c = 0; c < 16; c++) {
+            const int64_t kk = kb + 16 * c + 4 * q;   // multiple of 4, as are kend and Kp
+            a[c] = (rin && kk < kend) ? *(const float4 *)(arow + kk) : zero4;
+        }
+    };
+    float4 av[16], an[16], bv[16];
+    load(0, av);
+    for (int st = 0; st < nsteps; st++) {
+        for (int c = 0; c < 16; c++)
+            bv[c] = *(const float4 *)&xs[i * XS + 256 * st + 16 * c + 4 * q];
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            const int u = 4 * st + b;
+            const bool more = u + 1 < 4 * nsteps;
+            if (more) load(u + 1, an);
+            for (int c = 0; c < 16; c++) {
+                acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c].x, bv[c].x, acc[b], 0, 0, 0);
+                acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c].y, bv[c].y, acc[b], 0, 0, 0);
+                acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c].z, bv[c].z, acc[b], 0, 0, 0);
+                acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c].w, bv[c].w, acc[b], 0, 0, 0);
+            }
+            if (more)
+                for (int c = 0; c < 16; c++) av[c] = an[c];
+        }
+    }
+    // 16x16 accumulator layout: column lane % 16, row 4 (lane / 16) + v
+    float *Y = Yp + (int64_t)blockIdx.y * M * 16;
+    for (int b = 0; b < 4; b++) {
+        const int64_t r0 = rbase + 16 * b + 4 * q;
+        for (int v = 0; v < 4; v++)
+            if (r0 + v < M) Y[(r0 + v) * 16 + i] = acc[b][v];
+    }
+}
+
 __global__ __launch_bounds__(256) void to_c64_kernel(const double2 *__restrict__ x,
                                                      float2 *__restrict__ o, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -487,39 +585,65 @@ std::unique_ptr<DenseOperator> dense_assemble(bem_mesh *m, const NearOperator &n
     return op;
 }
 
-constexpr int GEMV_MAX_RHS = 8;   // right-hand sides per multi-vector product launch
-
 template <int NR>
 void launch_gemv(const DenseOperator &op, const float2 *xs, double2 *y, hipStream_t s) {
     hipLaunchKernelGGL(dense_gemv_kernel<NR>, dim3((unsigned)((op.n2 + 3) / 4)), dim3(256), 0, s,
                        op.B.p, op.n2, xs, y, op.n2);
 }
 
+constexpr int GEMV_MAX_RHS = 8;   // right-hand sides per multi-vector GEMV launch
+
 void dense_gemv(const DenseOperator &op, const double2 *x, double2 *y, int R, DevBuf<float2> &xs,
-                hipStream_t s) {
+                hipStream_t s, bool skinny) {
     const int64_t n2 = op.n2;
-    const int64_t need = (int64_t)std::min(R, GEMV_MAX_RHS) * n2;
-    if (xs.n < (size_t)need) xs.alloc((size_t)need);
-    for (int r0 = 0; r0 < R; r0 += GEMV_MAX_RHS) {
-        const int nr = std::min(GEMV_MAX_RHS, R - r0);
-        const int64_t cnt = nr * n2;
-        hipLaunchKernelGGL(to_c64_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
-                           x + r0 * n2, xs.p, cnt);
-        BEM_LAUNCH_CHECK();
-        Timer tm("dense_gemv", s);
-        double2 *yr = y + r0 * n2;
-        switch (nr) {
-        case 1: launch_gemv<1>(op, xs.p, yr, s); break;
-        case 2: launch_gemv<2>(op, xs.p, yr, s); break;
-        case 3: launch_gemv<3>(op, xs.p, yr, s); break;
-        case 4: launch_gemv<4>(op, xs.p, yr, s); break;
-        case 5: launch_gemv<5>(op, xs.p, yr, s); break;
-        case 6: launch_gemv<6>(op, xs.p, yr, s); break;
-        case 7: launch_gemv<7>(op, xs.p, yr, s); break;
-        default: launch_gemv<8>(op, xs.p, yr, s); break;
+    if (R == 1 || !skinny) {
+        // multi-vector GEMV: one row per wavefront, B read once per 8 vectors
+        const int64_t need = (int64_t)std::min(R, GEMV_MAX_RHS) * n2;
+        if (xs.n < (size_t)need) xs.alloc((size_t)need);
+        for (int r0 = 0; r0 < R; r0 += GEMV_MAX_RHS) {
+            const int nr = std::min(GEMV_MAX_RHS, R - r0);
+            const int64_t cnt = nr * n2;
+            hipLaunchKernelGGL(to_c64_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0,
+                               s, x + r0 * n2, xs.p, cnt);
+            BEM_LAUNCH_CHECK();
+            Timer tm("dense_gemv", s);
+            double2 *yr = y + r0 * n2;
+            switch (nr) {
+            case 1: launch_gemv<1>(op, xs.p, yr, s); break;
+            case 2: launch_gemv<2>(op, xs.p, yr, s); break;
+            case 3: launch_gemv<3>(op, xs.p, yr, s); break;
+            case 4: launch_gemv<4>(op, xs.p, yr, s); break;
+            case 5: launch_gemv<5>(op, xs.p, yr, s); break;
+            case 6: launch_gemv<6>(op, xs.p, yr, s); break;
+            case 7: launch_gemv<7>(op, xs.p, yr, s); break;
+            default: launch_gemv<8>(op, xs.p, yr, s); break;
+            }
+            BEM_LAUNCH_CHECK();
         }
+        return;
+    }
+    const int64_t M = n2, Kp = 2 * n2;
+    const int nchunks = (int)((Kp + SK_KC - 1) / SK_KC);
+    DevBuf<float> XT((size_t)(16 * Kp));
+    DevBuf<float> Yp((size_t)nchunks * M * 16);
+    for (int r0 = 0; r0 < R; r0 += 8) {
+        const int nr = std::min(8, R - r0);
+        hipLaunchKernelGGL(skinny_xprep_kernel, dim3((unsigned)((8 * n2 + 255) / 256)), dim3(256),
+                           0, s, x + r0 * n2, nr, n2, XT.p);
+        BEM_LAUNCH_CHECK();
+        {
+            Timer tm("dense_skinny_mfma", s);
+            hipLaunchKernelGGL(skinny_mfma_kernel,
+                               dim3((unsigned)((M + SK_ROWS - 1) / SK_ROWS), nchunks), dim3(256),
+                               0, s, (const float *)op.B.p, XT.p, Yp.p, M, Kp);
+            BEM_LAUNCH_CHECK();
+        }
+        const int64_t red = M * nr;
+        hipLaunchKernelGGL(gemm_reduce_kernel, dim3((unsigned)((red + 255) / 256)), dim3(256), 0, s,
+                           Yp.p, nchunks, M, 16, nr, y + r0 * n2);
         BEM_LAUNCH_CHECK();
     }
+    BEM_HIP(hipStreamSynchronize(s));   // XT, Yp are released on return
 }
 
 int64_t dense_gemm_scratch_bytes(const bem_mesh *m, int R) {
@@ -530,9 +654,9 @@ int64_t dense_gemm_scratch_bytes(const bem_mesh *m, int R) {
 
 void dense_apply(const DenseOperator &op, const double2 *x, double2 *y, int R,
                  DevBuf<float2> &xs, hipStream_t s, const TuneEntry *forced) {
-    const int gmin = forced ? forced->gemm_min : tune_lookup(op.T, R).gemm_min;
-    if (R >= gmin) dense_gemm(op, x, y, R, s);
-    else dense_gemv(op, x, y, R, xs, s);
+    const TuneEntry te = forced ? *forced : tune_lookup(op.T, R);
+    if (R >= te.gemm_min) dense_gemm(op, x, y, R, s);
+    else dense_gemv(op, x, y, R, xs, s, R >= te.skinny_min);
 }
 
 void dense_gemm(const DenseOperator &op, const double2 *x, double2 *y, int R, hipStream_t s) {

@@ -5,7 +5,7 @@
 // right-hand-side bucket), optionally persisted in a text file, one entry
 // per line:
 //   bem-tune-v1 <arch> T=<triangles> R=<bucket> block=<b> multi=<m>
-//       gemm_min=<g> path=<p> t_mf=<s> t_dense=<s> t_asm=<s>
+//       gemm_min=<g> [skinny_min=<s>] path=<p> t_mf=<s> t_dense=<s> t_asm=<s>
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -39,10 +39,10 @@ std::string device_arch() {
 std::string format_entry(const std::string &arch, int64_t T, int R, const TuneEntry &e) {
     char buf[512];
     std::snprintf(buf, sizeof(buf),
-                  "bem-tune-v1 %s T=%lld R=%d block=%d multi=%d gemm_min=%d path=%d t_mf=%.9g "
-                  "t_dense=%.9g t_asm=%.9g",
-                  arch.c_str(), (long long)T, R, e.block, e.multi, e.gemm_min, e.path, e.t_mf,
-                  e.t_dense, e.t_asm);
+                  "bem-tune-v1 %s T=%lld R=%d block=%d multi=%d gemm_min=%d skinny_min=%d "
+                  "path=%d t_mf=%.9g t_dense=%.9g t_asm=%.9g",
+                  arch.c_str(), (long long)T, R, e.block, e.multi, e.gemm_min, e.skinny_min,
+                  e.path, e.t_mf, e.t_dense, e.t_asm);
     return buf;
 }
 
@@ -65,6 +65,7 @@ bool parse_entry(const std::string &line, const std::string &arch, int64_t &T, i
         e.block = std::stoi(kv.at("block"));
         e.multi = std::stoi(kv.at("multi"));
         e.gemm_min = std::stoi(kv.at("gemm_min"));
+        if (kv.count("skinny_min")) e.skinny_min = std::stoi(kv.at("skinny_min"));
         e.path = std::stoi(kv.at("path"));
         e.t_mf = std::stod(kv.at("t_mf"));
         e.t_dense = std::stod(kv.at("t_dense"));
@@ -73,7 +74,7 @@ bool parse_entry(const std::string &line, const std::string &arch, int64_t &T, i
         return false;
     }
     return T > 0 && R == tune_bucket(R) && (e.block == 64 || e.block == 128 || e.block == 256) &&
-           (e.multi == 1 || e.multi == 2 || e.multi == 4) && e.gemm_min >= 1 &&
+           (e.multi == 1 || e.multi == 2 || e.multi == 4) && e.gemm_min >= 1 && e.skinny_min >= 2 &&
            e.path >= -1 && e.path <= 1;
 }
 
@@ -127,6 +128,7 @@ TuneEntry tune_lookup(int64_t T, int R) {
     e.block = t.farfield_block;
     e.multi = t.farfield_multi_max;
     e.gemm_min = t.dense_gemm_min_rhs;
+    e.skinny_min = t.dense_skinny_min_rhs;
     return e;
 }
 
@@ -204,17 +206,22 @@ TuneEntry autotune(bem_mesh *m, double2 k0, double2 k1, double rho, int R, int e
         best.t_asm = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         DevBuf<float2> xs;
         TuneEntry c = best;
-        c.gemm_min = R + 1;   // multi-vector product
+        c.gemm_min = R + 1;   // multi-vector GEMV
+        c.skinny_min = R + 1;
         const double t_gemv = time_best([&] { dense_apply(*op, X.p, Y.p, R, xs, s, &c); }, s);
-        double t_gemm = 1e300;
+        double t_skinny = 1e300, t_gemm = 1e300;
         if (R >= 2) {
-            c.gemm_min = R;   // MFMA product
+            c.skinny_min = 2;   // skinny MFMA product
+            t_skinny = time_best([&] { dense_apply(*op, X.p, Y.p, R, xs, s, &c); }, s);
+            c.gemm_min = R;     // MFMA GEMM
             t_gemm = time_best([&] { dense_apply(*op, X.p, Y.p, R, xs, s, &c); }, s);
         }
         // the whole bucket [b, 2b) takes the faster product
         const int b = tune_bucket(R);
-        best.gemm_min = t_gemm < t_gemv ? b : 2 * b;
-        best.t_dense = std::min(t_gemv, t_gemm);
+        const double t_small = std::min(t_gemv, t_skinny);
+        best.gemm_min = t_gemm < t_small ? b : 2 * b;
+        best.skinny_min = t_skinny < t_gemv ? std::max(2, b) : 2 * b;
+        best.t_dense = std::min(t_small, t_gemm);
         const double E = std::max(1, expected);
         best.path = best.t_asm + E * best.t_dense < E * best.t_mf ? 1 : 0;
     }
@@ -232,6 +239,7 @@ void to_c(const bem::TuneEntry &e, bem_tune_entry *o) {
     o->block = e.block;
     o->multi = e.multi;
     o->gemm_min = e.gemm_min;
+    o->skinny_min = e.skinny_min;
     o->path = e.path;
     o->t_matrix_free = e.t_mf;
     o->t_assembled = e.t_dense;

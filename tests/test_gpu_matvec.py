@@ -121,14 +121,10 @@ def test_matvec_deterministic_and_batched(P):
         assert torch.equal(ys[0], ys[1]) and torch.equal(ys[0], ys[2])
         for r in range(3):
             yr = P.pmchwt_matvec(M, 2.0, 3.0, 1.5, X[r].contiguous(), precision=prec)
-            # the multi-vector pair kernels sum in another order
+            # multi-vector kernels (pair kernel, skinny MFMA product) sum in
+            # another order than the single-vector ones
             rel = (torch.linalg.norm(yr - ys[0][r]) / torch.linalg.norm(yr)).item()
-            if prec == "fp32":
-                assert rel < 2e-6
-            elif prec == "fp64":
-                assert rel < 1e-13
-            else:
-                assert torch.equal(yr, ys[0][r])
+            assert rel < (1e-13 if prec == "fp64" else 2e-6), (prec, r, rel)
 
 
 def test_rhs_matches_oracle(P):
@@ -190,8 +186,9 @@ def test_dense_mfma_gemm_matches_gemv_and_oracle(P, n_rhs):
 
 @pytest.mark.parametrize("n_rhs", [2, 5, 8, 11])
 def test_dense_multi_vector_product(P, n_rhs):
-    """Multi-vector product (one pass over the matrix per 8 right-hand sides)
-    against single-vector products and the oracle's dense matrix."""
+    """Skinny MFMA product (one pass over the matrix per 8 right-hand sides,
+    ragged last group at 11) against single-vector products and the oracle's
+    dense matrix."""
     import torch
     mesh = icosphere(3)
     N = mesh.n_vertices
@@ -203,7 +200,7 @@ def test_dense_multi_vector_product(P, n_rhs):
     for r in range(n_rhs):
         g = P.pmchwt_matvec(M, 2.0, 3.0, 1.5, X[r].contiguous(),
                             precision="fp32_dense").cpu().numpy()
-        assert np.linalg.norm(Y[r] - g) / np.linalg.norm(g) < 1e-12
+        assert np.linalg.norm(Y[r] - g) / np.linalg.norm(g) < 2e-6
         err = rel_blocks(Y[r], B @ Xn[r], N)
         assert max(err.values()) <= 1e-5, err
 

@@ -12,7 +12,7 @@ def P():
 
 
 LINES = [
-    "bem-tune-v1 gfx950 T=20480 R=4 block=128 multi=4 gemm_min=8 path=1 t_mf=0.05 t_dense=0.002 t_asm=0.09",
+    "bem-tune-v1 gfx950 T=20480 R=4 block=128 multi=4 gemm_min=8 skinny_min=4 path=1 t_mf=0.05 t_dense=0.002 t_asm=0.09",
     "bem-tune-v1 gfx950 T=20480 R=1 block=256 multi=1 gemm_min=2 path=0 t_mf=0.0225 t_dense=0 t_asm=0",
     "bem-tune-v1 gfx942 T=20480 R=1 block=64 multi=1 gemm_min=2 path=1 t_mf=1 t_dense=1 t_asm=1",
     "bem-tune-v1 gfx950 T=1280 R=3 block=64 multi=2 gemm_min=4 path=0 t_mf=1 t_dense=0 t_asm=0",
@@ -31,9 +31,11 @@ def test_cache_load_and_lookup(P, tmp_path):
     assert n == 3   # R=3 is not a bucket; block=96, path=7 and short lines rejected
     e, tuned = P.tune_lookup(20480, 5)   # bucket 4..7
     assert tuned and e["block"] == 128 and e["multi"] == 4 and e["path"] == 1
+    assert e["skinny_min"] == 4
     assert e["t_assembly"] == pytest.approx(0.09)
     e, tuned = P.tune_lookup(20480, 1)
     assert tuned and e["path"] == 0 and e["t_matrix_free"] == pytest.approx(0.0225)
+    assert e["skinny_min"] == 5   # absent from the line: default
     e, tuned = P.tune_lookup(5120, 40)   # bucket 16+
     assert tuned and e["gemm_min"] == 16
     e, tuned = P.tune_lookup(1280, 2)

@@ -157,22 +157,32 @@ def serving_measure(P, n_requests: int, workers: int = 4, seed: int = 5) -> dict
         return srv.submit(ids[r["mesh"]], r["k_ext"], r["k_int"], r["rho"], r["directions"],
                           1e-6, precision="fp32")
 
+    def progress(msg):
+        print(f"serving: {msg}", file=sys.stderr, flush=True)
+
     n_sat = max(8, n_requests // 4)
     t0 = time.perf_counter()
-    for rid in [submit(r) for r in reqs[:n_sat]]:
+    for i, rid in enumerate([submit(r) for r in reqs[:n_sat]]):
         srv.wait(rid)
+        progress(f"saturated phase {i + 1}/{n_sat} done")
     sat = n_sat / (time.perf_counter() - t0)
     print(f"serving: saturated {sat:.2f} solves/s over {n_sat} requests", file=sys.stderr,
           flush=True)
     lam = 0.7 * sat
     t0 = time.perf_counter()
     pending = []
-    for r in reqs:
+    for i, r in enumerate(reqs):
         dt = r["arrival"] / lam - (time.perf_counter() - t0)
         if dt > 0:
             time.sleep(dt)
         pending.append((r, submit(r)))
-    results = [(r, srv.wait(rid)) for r, rid in pending]
+        if (i + 1) % 16 == 0:
+            progress(f"submitted {i + 1}/{n_requests}")
+    results = []
+    for i, (r, rid) in enumerate(pending):
+        results.append((r, srv.wait(rid)))
+        if (i + 1) % 16 == 0:
+            progress(f"completed {i + 1}/{n_requests}")
     elapsed = time.perf_counter() - t0
     stats = srv.stats()
     srv.close()

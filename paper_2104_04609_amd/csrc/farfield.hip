@@ -105,6 +105,25 @@ template <> struct Math<double> {
         s = (q & 2) ? -s0 : s0;
         c = ((q + 1) & 2) ? -c0 : c0;
     }
+    // sin/cos of 2 pi t with a table of e^{2 pi i n / 256}: t = n/256 + f,
+    // |f| <= 1/512, so |2 pi f| <= 0.0123 and short Taylor series suffice
+    // (truncation x^7/7! < 4e-18, x^8/8! < 2e-20); then one complex product.
+    static __device__ __forceinline__ void sincos_tab(double t, double &s, double &c,
+                                                      const double2 *tab) {
+        const double n = __builtin_rint(256.0 * t);
+        const double f = __builtin_fma(-0.00390625, n, t);
+        const double x = f * 6.283185307179586476925286766559;
+        const double x2 = x * x;
+        double ps = __builtin_fma(x2, 1.0 / 120.0, -1.0 / 6.0);
+        ps = __builtin_fma(ps, x2, 1.0);
+        const double sn = ps * x;
+        double pc = __builtin_fma(x2, -1.0 / 720.0, 1.0 / 24.0);
+        pc = __builtin_fma(pc, x2, -0.5);
+        const double cs = __builtin_fma(pc, x2, 1.0);
+        const double2 e = tab[((int)n) & 255];
+        c = __builtin_fma(e.x, cs, -e.y * sn);
+        s = __builtin_fma(e.y, cs, e.x * sn);
+    }
     // 1/sqrt(x): hardware estimate refined by two Newton steps
     static __device__ __forceinline__ double rsq(double x) {
         double y = __builtin_amdgcn_rsq(x);
@@ -189,10 +208,20 @@ void farfield_kernel(
     using MT = Math<R>;
     constexpr bool F32 = std::is_same<R, float>::value;
     __shared__ R tile[FF_TILE * SRC];
+    // FP64: e^{2 pi i n / 256}, n < 256, for the table-based sin/cos
+    __shared__ double2 etab[F32 ? 1 : 256];
     extern __shared__ double sums[];   // FP32: [FF_ROWS][blockDim.x] (dynamic)
     const int nthr = blockDim.x;
     const int tau = blockIdx.x * nthr + threadIdx.x;
     const int split = blockIdx.y;
+    if constexpr (!F32) {
+        for (int n = threadIdx.x; n < 256; n += nthr) {
+            double sn, cs;
+            MT::template sincos_rev<true>(n * 0.00390625, sn, cs);
+            etab[n] = make_double2(cs, sn);
+        }
+        // the first tile's barrier orders these writes before any read
+    }
     const int s_begin = split * split_len;
     const int s_end = min(T, s_begin + split_len);
     const bool active = tau < T;
@@ -306,8 +335,13 @@ void farfield_kernel(
                     // E_m = e^{i k_m r} (masked to 0 for the interior term of
                     // triangles on different objects)
                     R E0r, E0i, E1r, E1i;
-                    MT::template sincos_rev<FR>(r * cf.krev0, E0i, E0r);
-                    MT::template sincos_rev<FR>(r * cf.krev1, E1i, E1r);
+                    if constexpr (F32) {
+                        MT::template sincos_rev<FR>(r * cf.krev0, E0i, E0r);
+                        MT::template sincos_rev<FR>(r * cf.krev1, E1i, E1r);
+                    } else {
+                        MT::sincos_tab(r * cf.krev0, E0i, E0r, etab);
+                        MT::sincos_tab(r * cf.krev1, E1i, E1r, etab);
+                    }
                     if (CK0) {
                         const R d0 = MT::exp2(r * cf.kdec0);
                         E0r *= d0;
@@ -431,8 +465,17 @@ void farfield_multi_kernel(
     constexpr int SM = srcm<NR>();
     constexpr int OBJ = GEO_STRIDE, VID = GEO_STRIDE + 1, DYN0 = GEO_STRIDE + 4;
     __shared__ R tile[FF_TILE * SM];
+    __shared__ double2 etab[FRM ? 256 : 1];
     const int nthr = blockDim.x;
     const int tau = blockIdx.x * nthr + threadIdx.x;
+    if constexpr (FRM) {
+        for (int n = threadIdx.x; n < 256; n += nthr) {
+            double sn, cs;
+            MT::template sincos_rev<true>(n * 0.00390625, sn, cs);
+            etab[n] = make_double2(cs, sn);
+        }
+        // the first tile's barrier orders these writes before any read
+    }
     const int split = blockIdx.y;
     const int s_begin = split * split_len;
     const int s_end = min(T, s_begin + split_len);
@@ -539,8 +582,13 @@ void farfield_multi_kernel(
                     const R ri = MT::rsq(r2);
                     const R rr = r2 * ri;
                     R E0r, E0i, E1r, E1i;
-                    MT::template sincos_rev<FRM>(rr * cf.krev0, E0i, E0r);
-                    MT::template sincos_rev<FRM>(rr * cf.krev1, E1i, E1r);
+                    if constexpr (FRM) {
+                        MT::sincos_tab(rr * cf.krev0, E0i, E0r, etab);
+                        MT::sincos_tab(rr * cf.krev1, E1i, E1r, etab);
+                    } else {
+                        MT::template sincos_rev<false>(rr * cf.krev0, E0i, E0r);
+                        MT::template sincos_rev<false>(rr * cf.krev1, E1i, E1r);
+                    }
                     if (CK0) {
                         const R d0 = MT::exp2(rr * cf.kdec0);
                         E0r *= d0;

@@ -279,7 +279,8 @@ def main():
     # measured issue rates of FMA and the transcendental instructions
     rates = P.valu_rates()
     pairs = RL.far_pairs_per_matvec(mesh.triangles)
-    roof = RL.pair_kernel_roofline(pairs, kern_ms * 1e-3, "fp32", rates)
+    symmetric = P.tune_get("farfield.symmetric") == 1
+    roof = RL.pair_kernel_roofline(pairs, kern_ms * 1e-3, "fp32", rates, symmetric=symmetric)
     traffic = pmc_traffic()
     roof["traffic"] = traffic["bytes"] if traffic else None
     roof["traffic_detail"] = traffic
@@ -357,7 +358,8 @@ def main():
                    "rho": RHO, "parallelism": "single GPU"},
         "roofline": {**roof, "kernel": "farfield_fp32",
                      "kernel_ms": kern_ms, "point_pairs_per_launch": pairs,
-                     "flops_per_pair": RL.FLOPS_PER_PAIR, "valu_rates": rates},
+                     "flops_per_unit": RL.FLOPS_PER_UPAIR if symmetric else RL.FLOPS_PER_PAIR,
+                     "valu_rates": rates},
         "fp64_matvec": {"ms_per_step": step64_s * 1e3,
                         "tri_pair_evals_per_s": T * (T - 1) / step64_s,
                         "kernel_ms": kern64_ms, "roofline_frac": roof64["frac"]},

@@ -279,6 +279,12 @@ int bem_profile_read(const char *kernel, double *total_ms, int64_t *launches);
  *                         the FP32 matrix-free path: 1, 2 or 4 (default 4)
  *   "farfield.block"      test triangles per pair-kernel workgroup: 64, 128
  *                         or 256 (default 256)
+ *   "farfield.symmetric"  1: a single FP32 right-hand side evaluates every
+ *                         separated triangle pair once and adds it to the
+ *                         rows of both triangles (the kernels of V, K, K'
+ *                         and D in Maue form depend on the points only
+ *                         through r; Sec. 2.2); 0: each ordered pair in the
+ *                         one-directional kernel (default 1)
  *   "dense.skinny_min_rhs" right-hand-side count (>= 2) from which products
  *                         with the assembled operator below gemm_min use the
  *                         16-column MFMA kernel instead of the multi-vector

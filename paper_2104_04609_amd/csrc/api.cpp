@@ -69,6 +69,8 @@ void mesh_trim(bem_mesh *m) {
     m->dyn32.release();
     m->partial.release();
     m->trirows.release();
+    m->sym_items.release();
+    m->sym_plan_id = nullptr;
 }
 }   // namespace bem
 
@@ -76,7 +78,8 @@ int64_t bem_mesh::device_bytes() const {
     int64_t b = geo64.bytes() + geo32.bytes() + tst.bytes() + tobj_d.bytes() + tri_d.bytes() +
                 star_ptr.bytes() + star_idx.bytes() + near_pairs.bytes() + nf_rowptr.bytes() +
                 nf_col.bytes() + nf_cptr.bytes() + nf_contrib.bytes() + ss_tab.bytes() +
-                dyn64.bytes() + dyn32.bytes() + partial.bytes() + trirows.bytes();
+                dyn64.bytes() + dyn32.bytes() + partial.bytes() + trirows.bytes() +
+                sym_items.bytes();
     for (const auto &kv : near_cache) b += kv.second->vals.bytes();
     for (const auto &kv : dense_cache) b += kv.second->B.bytes();
     b += xs32.bytes();
@@ -244,6 +247,9 @@ int bem_tune_set(const char *key, int64_t value) {
     } else if (k == "farfield.block") {
         if (value != 64 && value != 128 && value != 256) fail(BEM_E_INVAL, "farfield.block: 64, 128 or 256");
         t.farfield_block = (int)value;
+    } else if (k == "farfield.symmetric") {
+        if (value != 0 && value != 1) fail(BEM_E_INVAL, "farfield.symmetric: 0 or 1");
+        t.farfield_symmetric = (int)value;
     } else if (k == "dense.skinny_min_rhs") {
         if (value < 2 || value > 1 << 20) fail(BEM_E_INVAL, "dense.skinny_min_rhs out of range");
         t.dense_skinny_min_rhs = (int)value;
@@ -264,6 +270,7 @@ int bem_tune_get(const char *key, int64_t *value) {
     bem::Tuning &t = bem::tuning();
     if (k == "farfield.multi_max") *value = t.farfield_multi_max;
     else if (k == "farfield.block") *value = t.farfield_block;
+    else if (k == "farfield.symmetric") *value = t.farfield_symmetric;
     else if (k == "dense.skinny_min_rhs") *value = t.dense_skinny_min_rhs;
     else if (k == "dense.gemm_min_rhs") *value = t.dense_gemm_min_rhs;
     else fail(BEM_E_INVAL, "unknown tuning key " + k);

@@ -188,6 +188,8 @@ struct bem_mesh {
     bem::DevBuf<float> dyn32;
     bem::DevBuf<double> partial;
     bem::DevBuf<double> trirows;
+    bem::DevBuf<int32_t> sym_items;      // work items of the symmetric pair kernel
+    const void *sym_plan_id = nullptr;   // plan whose items sym_items holds
 
     int64_t device_bytes() const;
     ~bem_mesh();
@@ -199,6 +201,7 @@ namespace bem {
 struct Tuning {
     std::atomic<int> farfield_multi_max{4};   // right-hand sides per pair-kernel launch
     std::atomic<int> farfield_block{256};     // test triangles per pair-kernel workgroup
+    std::atomic<int> farfield_symmetric{1};   // FP32 single vector: each separated pair once
     std::atomic<int> dense_gemm_min_rhs{16};  // MFMA product from this many right-hand sides
     std::atomic<int> dense_skinny_min_rhs{5}; // skinny MFMA product from this many (else multi-GEMV)
 };

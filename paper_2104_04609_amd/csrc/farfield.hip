@@ -25,9 +25,12 @@
 // c_tau - y.n_tau (per y, folded into s_psi), and k_0^2 (n_x.n_y) per triangle pair.
 // Interior terms (index 1) are masked out for triangles of different objects.
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <functional>
 #include <map>
 #include <mutex>
+#include <queue>
 #include <type_traits>
 #include <utility>
 
@@ -440,6 +443,319 @@ void farfield_kernel(
     for (int c = 0; c < 6; c++) outA[c] = sum_get(ROW_STRIDE + c);
 }
 
+// ------------------------------------------------- symmetric pair kernel
+// G_V, G_W, G_N and F depend on the two points only through r, and the
+// geometric factors of K and K' exchange roles when (x, tau) and (y, sigma)
+// are swapped: (y_j - x_i).n_sigma = c_sigma - x_i.n_sigma =: dny_i and
+// (x_i - y_j).n_tau = c_tau - y_j.n_tau =: dnx_j serve both directions.  So
+// every unordered pair of separated triangles tau < sigma is evaluated once
+// and its 36 point-pair values feed the rows of tau (test tau, trial sigma)
+// and the rows of sigma (test sigma, trial tau), identical sums to the
+// one-directional kernel up to the order of additions.
+//
+// Work item (b, c): the blk test triangles of block b (one per thread)
+// against the chunk [b blk + c L, b blk + (c + 1) L) of sigma; pairs with
+// tau >= sigma and pairs sharing a vertex are skipped.  Rows of tau: FP32 per
+// tile of trial triangles, FP64 sums in LDS, stored at ptau[item][blk][18]
+// (12 rows, 6 curl sums).  Rows of sigma: every thread contracts its
+// contribution to sigma's three vertices, each wave adds its 64 lanes with a
+// fixed DPP tree, the waves' sums are added in FP64 in wave order and stored
+// at psig[sig_off(b) + sigma - b blk][18].  Every slot is written by exactly
+// one work item, so the reduction over slots is deterministic.
+constexpr int SIG_VALS = ROW_STRIDE + 6;
+constexpr int SYM_WAVES = FF_BLOCK / 64;
+
+// Sum over the 64 lanes of a wave, result in lane 63: quad, row and
+// cross-row steps in a fixed order (all lanes must be active).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_add(float v) {
+    const int s = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWS, 0xF, false);
+    return v + __builtin_bit_cast(float, s);
+}
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+    v = dpp_add<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+    v = dpp_add<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+    v = dpp_add<0x124, 0xF>(v);   // row_ror:4
+    v = dpp_add<0x128, 0xF>(v);   // row_ror:8
+    v = dpp_add<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+// First storage slot of block b in the sigma partials: blocks b' < b hold
+// T - b' blk rows each.
+__host__ __device__ inline int64_t sym_sig_off(int64_t b, int64_t T, int64_t blk) {
+    return b * T - blk * (b * (b - 1) / 2);
+}
+
+template <class R, bool CK0, bool CK1, bool MULTI, bool FR>
+__global__ __launch_bounds__(FF_BLOCK) __attribute__((amdgpu_waves_per_eu(3)))
+void farfield_sym_kernel(
+    const R *__restrict__ geo, const R *__restrict__ dyn,
+    const int32_t *__restrict__ tobj, const int32_t *__restrict__ tri, int T,
+    const int32_t *__restrict__ items, int chunk_len, Coef<R> cf,
+    double *__restrict__ ptau, double *__restrict__ psig) {
+    static_assert(std::is_same<R, float>::value, "symmetric kernel: FP32 only");
+    using MT = Math<R>;
+    __shared__ R tile[FF_TILE * SRC];
+    __shared__ float sig[SYM_WAVES * FF_TILE * SIG_VALS];
+    extern __shared__ double sums[];   // [FF_ROWS][blockDim.x]
+    const int nthr = blockDim.x;
+    const int b = items[3 * blockIdx.x], c = items[3 * blockIdx.x + 1],
+              canon = items[3 * blockIdx.x + 2];
+    const int tau = b * nthr + threadIdx.x;
+    const int lo = b * nthr + c * chunk_len;
+    const int hi = min(T, lo + chunk_len);
+    const bool active = tau < T;
+    const int tt = active ? tau : 0;
+    const int wave = threadIdx.x >> 6;
+    const bool lane63 = (threadIdx.x & 63) == 63;
+
+    R px[6], py[6], pz[6];
+    for (int i = 0; i < 6; i++) {
+        px[i] = geo[GEO_STRIDE * tt + 3 * i];
+        py[i] = geo[GEO_STRIDE * tt + 3 * i + 1];
+        pz[i] = geo[GEO_STRIDE * tt + 3 * i + 2];
+    }
+    const R ntx = geo[GEO_STRIDE * tt + 18], nty = geo[GEO_STRIDE * tt + 19],
+            ntz = geo[GEO_STRIDE * tt + 20], ct = geo[GEO_STRIDE * tt + 21];
+    const R ot = MULTI ? (R)tobj[tt] : (R)0;
+    const R tv0 = (R)tri[3 * tt], tv1 = (R)tri[3 * tt + 1], tv2 = (R)tri[3 * tt + 2];
+    // tau as a trial triangle: s_psi, s_phi at its points, curl sums
+    R tspr[6], tspi[6], tsfr[6], tsfi[6], tscr[3], tsci[3];
+    for (int i = 0; i < 6; i++) {
+        tspr[i] = dyn[DYN_STRIDE * tt + 2 * i];
+        tspi[i] = dyn[DYN_STRIDE * tt + 2 * i + 1];
+        tsfr[i] = dyn[DYN_STRIDE * tt + 12 + 2 * i];
+        tsfi[i] = dyn[DYN_STRIDE * tt + 12 + 2 * i + 1];
+    }
+    for (int k = 0; k < 3; k++) {
+        tscr[k] = dyn[DYN_STRIDE * tt + 24 + 2 * k];
+        tsci[k] = dyn[DYN_STRIDE * tt + 24 + 2 * k + 1];
+    }
+
+    R a1r[6], a1i[6], a2r[6], a2i[6], Ar[3], Ai[3];
+    for (int i = 0; i < 6; i++) a1r[i] = a1i[i] = a2r[i] = a2i[i] = 0;
+    for (int k = 0; k < 3; k++) Ar[k] = Ai[k] = 0;
+    for (int k = 0; k < FF_ROWS; k++) sums[k * nthr + threadIdx.x] = 0;
+    auto flush = [&]() {
+        for (int a = 0; a < 3; a++) {
+            double r1r = 0, r1i = 0, r2r = 0, r2i = 0;
+            for (int i = 0; i < 6; i++) {
+                const double wb = qw(i) * qb(i, a);
+                r1r += wb * (double)a1r[i];
+                r1i += wb * (double)a1i[i];
+                r2r += wb * (double)a2r[i];
+                r2i += wb * (double)a2i[i];
+            }
+            sums[(2 * a) * nthr + threadIdx.x] += r1r;
+            sums[(2 * a + 1) * nthr + threadIdx.x] += r1i;
+            sums[(6 + 2 * a) * nthr + threadIdx.x] += r2r;
+            sums[(6 + 2 * a + 1) * nthr + threadIdx.x] += r2i;
+        }
+        for (int k = 0; k < 3; k++) {
+            sums[(ROW_STRIDE + 2 * k) * nthr + threadIdx.x] += (double)Ar[k];
+            sums[(ROW_STRIDE + 2 * k + 1) * nthr + threadIdx.x] += (double)Ai[k];
+            Ar[k] = Ai[k] = 0;
+        }
+        for (int i = 0; i < 6; i++) a1r[i] = a1i[i] = a2r[i] = a2i[i] = 0;
+    };
+    // rows of sigma of one tile: wave sums (LDS) -> FP64 in wave order
+    const int nw = nthr >> 6;
+    double *psb = psig + (sym_sig_off(b, T, nthr) - (int64_t)b * nthr) * SIG_VALS;
+    auto combine = [&](int tb, int tcnt) {
+        for (int idx = threadIdx.x; idx < tcnt * SIG_VALS; idx += nthr) {
+            const int s = idx / SIG_VALS, k = idx - s * SIG_VALS;
+            double acc = 0;
+            for (int w = 0; w < nw; w++) acc += (double)sig[(w * FF_TILE + s) * SIG_VALS + k];
+            psb[(int64_t)(tb + s) * SIG_VALS + k] = acc;
+        }
+    };
+
+    int prev_base = -1;
+    for (int base = lo; base < hi; base += FF_TILE) {
+        const int cnt = min(FF_TILE, hi - base);
+        __syncthreads();
+        if (prev_base >= 0) combine(prev_base, FF_TILE);
+        for (int idx = threadIdx.x; idx < cnt * SRC; idx += nthr) {
+            int s = idx / SRC, f = idx - s * SRC;
+            R v;
+            if (f < GEO_STRIDE) v = geo[(int64_t)GEO_STRIDE * (base + s) + f];
+            else if (f < GEO_STRIDE + DYN_STRIDE)
+                v = dyn[(int64_t)DYN_STRIDE * (base + s) + (f - GEO_STRIDE)];
+            else if (f == GEO_STRIDE + DYN_STRIDE) v = MULTI ? (R)tobj[base + s] : (R)0;
+            else v = (R)tri[3 * (base + s) + (f - GEO_STRIDE - DYN_STRIDE - 1)];
+            tile[idx] = v;
+        }
+        __syncthreads();
+        for (int s = 0; s < cnt; s++) {
+            const R *src = &tile[s * SRC];
+            const R *sv = src + GEO_STRIDE + DYN_STRIDE + 1;
+            const bool adj = sv[0] == tv0 || sv[0] == tv1 || sv[0] == tv2 || sv[1] == tv0 ||
+                             sv[1] == tv1 || sv[1] == tv2 || sv[2] == tv0 || sv[2] == tv1 ||
+                             sv[2] == tv2;
+            // rows of sigma contributed by this thread: 12 rows, 6 curl sums
+            R o[SIG_VALS];
+            for (int k = 0; k < SIG_VALS; k++) o[k] = 0;
+            if (active && tau < base + s && !adj) {
+                const R nsx = src[18], nsy = src[19], nsz = src[20], cs = src[21];
+                const R m1 = MULTI ? (src[GEO_STRIDE + DYN_STRIDE] == ot ? (R)1 : (R)0) : (R)1;
+                const R nn = ntx * nsx + nty * nsy + ntz * nsz;
+                const R gnr = cf.n0r * nn, gni = cf.n0i * nn;
+                // dny_i = (y - x_i).n_sigma; sigma-side trial weights
+                // spy_i = dny_i s_psi(x_i)
+                R dny[6], spyr[6], spyi[6];
+                for (int i = 0; i < 6; i++) {
+                    dny[i] = cs - (px[i] * nsx + py[i] * nsy + pz[i] * nsz);
+                    spyr[i] = dny[i] * tspr[i];
+                    spyi[i] = dny[i] * tspi[i];
+                }
+                R gwr = 0, gwi = 0;
+#pragma unroll
+                for (int j = 0; j < 6; j++) {
+                    const R yx = src[3 * j], yy = src[3 * j + 1], yz = src[3 * j + 2];
+                    const R spr = src[GEO_STRIDE + 2 * j], spi = src[GEO_STRIDE + 2 * j + 1];
+                    const R sfr = src[GEO_STRIDE + 12 + 2 * j], sfi = src[GEO_STRIDE + 12 + 2 * j + 1];
+                    // dnx_j = (x - y_j).n_tau; tau-side weights spx_j = dnx_j s_psi(y_j)
+                    // and gsf_j = -k_0^2 (n_x.n_y) s_phi(y_j)
+                    const R dnx = ct - (yx * ntx + yy * nty + yz * ntz);
+                    const R spxr = dnx * spr, spxi = dnx * spi;
+                    const R gsfr = -(gnr * sfr - gni * sfi), gsfi = -(gnr * sfi + gni * sfr);
+                    // sigma-side sums over i at y_j
+                    R u1r = 0, u1i = 0, qr = 0, qi = 0, u2r = 0, u2i = 0, nr = 0, ni = 0;
+#pragma unroll
+                    for (int i = 0; i < 6; i++) {
+                        const R dx = yx - px[i];
+                        const R dy = yy - py[i];
+                        const R dz = yz - pz[i];
+                        const R r2 = dx * dx + dy * dy + dz * dz;
+                        const R ri = MT::rsq(r2);
+                        const R r = r2 * ri;
+                        R E0r, E0i, E1r, E1i;
+                        MT::template sincos_rev<FR>(r * cf.krev0, E0i, E0r);
+                        MT::template sincos_rev<FR>(r * cf.krev1, E1i, E1r);
+                        if (CK0) {
+                            const R d0 = MT::exp2(r * cf.kdec0);
+                            E0r *= d0;
+                            E0i *= d0;
+                        }
+                        if (CK1 || MULTI) {
+                            R d1 = m1;
+                            if (CK1) d1 *= MT::exp2(r * cf.kdec1);
+                            E1r *= d1;
+                            E1i *= d1;
+                        }
+                        const R G0r = E0r * ri, G0i = E0i * ri;
+                        const R G1r = E1r * ri, G1i = E1i * ri;
+                        R Fr = -(G0r + G1r), Fi = -(G0i + G1i);
+                        Fr = fmac(-cf.k0r, E0i, Fr);
+                        Fi = fmac(cf.k0r, E0r, Fi);
+                        Fr = fmac(-cf.k1r, E1i, Fr);
+                        Fi = fmac(cf.k1r, E1r, Fi);
+                        if (CK0) {
+                            Fr = fmac(-cf.k0i, E0r, Fr);
+                            Fi = fmac(-cf.k0i, E0i, Fi);
+                        }
+                        if (CK1) {
+                            Fr = fmac(-cf.k1i, E1r, Fr);
+                            Fi = fmac(-cf.k1i, E1i, Fi);
+                        }
+                        const R ri2 = ri * ri;
+                        Fr *= ri2;
+                        Fi *= ri2;
+                        const R GVr = fmac(cf.rho, G1r, G0r), GVi = fmac(cf.rho, G1i, G0i);
+                        const R GWr = fmac(cf.irho, G1r, G0r), GWi = fmac(cf.irho, G1i, G0i);
+                        R GNr = fmac(cf.n10r, G1r, G0r), GNi = fmac(cf.n10r, G1i, G0i);
+                        if (CK0 || CK1) {
+                            GNr = fmac(-cf.n10i, G1i, GNr);
+                            GNi = fmac(cf.n10i, G1r, GNi);
+                        }
+                        // tau at x_i: G_V s_psi(y_j) - F dny_i s_phi(y_j)
+                        //             + F spx_j + G_N gsf_j
+                        const R dsr = dny[i] * sfr, dsi = dny[i] * sfi;
+                        R t1r = a1r[i], t1i = a1i[i], t2r = a2r[i], t2i = a2i[i];
+                        t1r = fmac(GVr, spr, t1r);
+                        t1r = fmac(-GVi, spi, t1r);
+                        t1i = fmac(GVr, spi, t1i);
+                        t1i = fmac(GVi, spr, t1i);
+                        t1r = fmac(-Fr, dsr, t1r);
+                        t1r = fmac(Fi, dsi, t1r);
+                        t1i = fmac(-Fr, dsi, t1i);
+                        t1i = fmac(-Fi, dsr, t1i);
+                        t2r = fmac(Fr, spxr, t2r);
+                        t2r = fmac(-Fi, spxi, t2r);
+                        t2i = fmac(Fr, spxi, t2i);
+                        t2i = fmac(Fi, spxr, t2i);
+                        t2r = fmac(GNr, gsfr, t2r);
+                        t2r = fmac(-GNi, gsfi, t2r);
+                        t2i = fmac(GNr, gsfi, t2i);
+                        t2i = fmac(GNi, gsfr, t2i);
+                        a1r[i] = t1r;
+                        a1i[i] = t1i;
+                        a2r[i] = t2r;
+                        a2i[i] = t2i;
+                        const R ww = (R)(qw(i) * qw(j));
+                        gwr = fmac(ww, GWr, gwr);
+                        gwi = fmac(ww, GWi, gwi);
+                        // sigma at y_j: sums over i of G_V s_psi(x_i), F s_phi(x_i),
+                        // F spy_i and G_N s_phi(x_i)
+                        u1r = fmac(GVr, tspr[i], u1r);
+                        u1r = fmac(-GVi, tspi[i], u1r);
+                        u1i = fmac(GVr, tspi[i], u1i);
+                        u1i = fmac(GVi, tspr[i], u1i);
+                        qr = fmac(Fr, tsfr[i], qr);
+                        qr = fmac(-Fi, tsfi[i], qr);
+                        qi = fmac(Fr, tsfi[i], qi);
+                        qi = fmac(Fi, tsfr[i], qi);
+                        u2r = fmac(Fr, spyr[i], u2r);
+                        u2r = fmac(-Fi, spyi[i], u2r);
+                        u2i = fmac(Fr, spyi[i], u2i);
+                        u2i = fmac(Fi, spyr[i], u2i);
+                        nr = fmac(GNr, tsfr[i], nr);
+                        nr = fmac(-GNi, tsfi[i], nr);
+                        ni = fmac(GNr, tsfi[i], ni);
+                        ni = fmac(GNi, tsfr[i], ni);
+                    }
+                    // sigma at y_j: row 1 = u1 - dnx_j q; row 2 = u2 - k_0^2 (n.n) n;
+                    // contracted with w_j phi_a(y_j)
+                    const R r1r = fmac(-dnx, qr, u1r), r1i = fmac(-dnx, qi, u1i);
+                    R r2r = fmac(-gnr, nr, u2r), r2i = fmac(-gnr, ni, u2i);
+                    r2r = fmac(gni, ni, r2r);
+                    r2i = fmac(-gni, nr, r2i);
+#pragma unroll
+                    for (int a = 0; a < 3; a++) {
+                        const R wb = (R)(qw(j) * qb(j, a));
+                        o[2 * a] = fmac(wb, r1r, o[2 * a]);
+                        o[2 * a + 1] = fmac(wb, r1i, o[2 * a + 1]);
+                        o[6 + 2 * a] = fmac(wb, r2r, o[6 + 2 * a]);
+                        o[6 + 2 * a + 1] = fmac(wb, r2i, o[6 + 2 * a + 1]);
+                    }
+                }
+                // curl terms: A_tau += g_W C_sigma, A_sigma += g_W C_tau
+                for (int k = 0; k < 3; k++) {
+                    const R scr = src[GEO_STRIDE + 24 + 2 * k], sci = src[GEO_STRIDE + 24 + 2 * k + 1];
+                    Ar[k] += gwr * scr - gwi * sci;
+                    Ai[k] += gwr * sci + gwi * scr;
+                    o[ROW_STRIDE + 2 * k] = gwr * tscr[k] - gwi * tsci[k];
+                    o[ROW_STRIDE + 2 * k + 1] = gwr * tsci[k] + gwi * tscr[k];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < SIG_VALS; k++) {
+                const float w = wave_sum_to_lane63((float)o[k]);
+                if (lane63) sig[(wave * FF_TILE + s) * SIG_VALS + k] = w;
+            }
+        }
+        flush();
+        prev_base = base;
+    }
+    __syncthreads();
+    if (prev_base >= 0) combine(prev_base, hi - prev_base);
+    if (!active) return;
+    double *out = ptau + ((int64_t)canon * nthr + threadIdx.x) * SIG_VALS;
+    for (int k = 0; k < SIG_VALS; k++) out[k] = sums[k * nthr + threadIdx.x];
+}
+
 // ----------------------------------------- multi-right-hand-side pair kernel
 // NR right-hand sides share every kernel evaluation (geometry, phases,
 // G_V, G_W, G_N, F); only the accumulations are per right-hand side.  FP32,
@@ -712,6 +1028,42 @@ __global__ __launch_bounds__(256) void reduce_splits_kernel(
     for (int c = 0; c < 12; c++) trirows[(int64_t)ROW_STRIDE * t + c] = sc * acc[c];
 }
 
+// ------------------------------------------- symmetric-kernel reduction
+// Rows of test triangle tau from the symmetric kernel: its own work items
+// as tau (chunk order), then the blocks b <= block(tau) as sigma (block
+// order); then the curl contraction and |tau|/(4 pi) as in the split
+// reduction.
+__global__ __launch_bounds__(256) void reduce_sym_kernel(
+    const double *__restrict__ ptau, const double *__restrict__ psig,
+    const double *__restrict__ tst, int T, int blk, int chunk_len,
+    double *__restrict__ trirows) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    const int b = t / blk, l = t - b * blk;
+    int64_t first = 0;
+    for (int bb = 0; bb < b; bb++) first += (T - bb * blk + chunk_len - 1) / chunk_len;
+    const int nch = (T - b * blk + chunk_len - 1) / chunk_len;
+    double acc[SIG_VALS];
+    for (int k = 0; k < SIG_VALS; k++) acc[k] = 0;
+    for (int c = 0; c < nch; c++) {
+        const double *p = ptau + ((first + c) * blk + l) * SIG_VALS;
+        for (int k = 0; k < SIG_VALS; k++) acc[k] += p[k];
+    }
+    for (int bb = 0; bb <= b; bb++) {
+        const double *q = psig + (sym_sig_off(bb, T, blk) + t - (int64_t)bb * blk) * SIG_VALS;
+        for (int k = 0; k < SIG_VALS; k++) acc[k] += q[k];
+    }
+    const double *ts = tst + (int64_t)TST_STRIDE * t;
+    const double sc = ts[0] * 0.079577471545947667884441881686257;   // |tau|/(4 pi)
+    const double *A = acc + ROW_STRIDE;
+    for (int a = 0; a < 3; a++) {
+        const double *cu = ts + 1 + 3 * a;
+        acc[6 + 2 * a] += cu[0] * A[0] + cu[1] * A[2] + cu[2] * A[4];
+        acc[6 + 2 * a + 1] += cu[0] * A[1] + cu[1] * A[3] + cu[2] * A[5];
+    }
+    for (int c = 0; c < ROW_STRIDE; c++) trirows[(int64_t)ROW_STRIDE * t + c] = sc * acc[c];
+}
+
 // ------------------------------------- vertex gather + near-field CSR SpMV
 __global__ __launch_bounds__(256) void finalize_kernel(
     const double *__restrict__ trirows, const int32_t *__restrict__ star_ptr,
@@ -926,6 +1278,120 @@ FarPlan far_plan(const bem_mesh *m, int precision, double2 k0, double2 k1, int b
 
 int valid_block(int b) { return b == 64 || b == 128 || b == 256 ? b : 256; }
 
+// Symmetric kernel variant for the runtime flags (code = 4 ck0 + 2 ck1 + multi).
+template <bool FR> const void *sym_kernel(int code) {
+    switch (code) {
+    case 0: return (const void *)farfield_sym_kernel<float, false, false, false, FR>;
+    case 1: return (const void *)farfield_sym_kernel<float, false, false, true, FR>;
+    case 2: return (const void *)farfield_sym_kernel<float, false, true, false, FR>;
+    case 3: return (const void *)farfield_sym_kernel<float, false, true, true, FR>;
+    case 4: return (const void *)farfield_sym_kernel<float, true, false, false, FR>;
+    case 5: return (const void *)farfield_sym_kernel<float, true, false, true, FR>;
+    case 6: return (const void *)farfield_sym_kernel<float, true, true, false, FR>;
+    default: return (const void *)farfield_sym_kernel<float, true, true, true, FR>;
+    }
+}
+
+template <bool FR>
+void launch_sym(int code, int n_items, int blk, hipStream_t s, const float *geo, const float *dyn,
+                const int32_t *tobj, const int32_t *tri, int T, const int32_t *items, int chunk,
+                Coef<float> cf, double *ptau, double *psig) {
+    switch (code) {
+#define BEM_CASE(c, a, b, m)                                                                     \
+    case c:                                                                                      \
+        hipLaunchKernelGGL((farfield_sym_kernel<float, a, b, m, FR>), dim3(n_items), dim3(blk),  \
+                           far_smem<float>(blk), s, geo, dyn, tobj, tri, T, items, chunk, cf,    \
+                           ptau, psig);                                                          \
+        break;
+        BEM_CASE(0, false, false, false)
+        BEM_CASE(1, false, false, true)
+        BEM_CASE(2, false, true, false)
+        BEM_CASE(3, false, true, true)
+        BEM_CASE(4, true, false, false)
+        BEM_CASE(5, true, false, true)
+        BEM_CASE(6, true, true, false)
+        BEM_CASE(7, true, true, true)
+#undef BEM_CASE
+    }
+}
+
+// Work items of the symmetric kernel.  Block b (test triangles
+// [b blk, b blk + blk)) meets the trial triangles [b blk, T) in chunks of
+// `chunk`; the chunk length is the multiple of the tile that minimises the
+// makespan of a greedy list schedule of the items (longest first) on the
+// resident workgroup slots.  Launch order: full chunks, then the shorter
+// last chunks by decreasing length; storage order of the tau rows: b-major.
+struct SymPlan {
+    int blk = 0, chunk = 0, nblk = 0;
+    std::vector<int32_t> items;   // launch order: (b, c, storage index)
+    int64_t tau_doubles = 0, sig_doubles = 0;
+};
+
+const SymPlan &sym_plan(int T, int blk, int slots) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int>, SymPlan> cache;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find({T, blk, slots});
+    if (it != cache.end()) return it->second;
+    const int nblk = (T + blk - 1) / blk;
+    const double fixed = 2.0;
+    int best_L = T;
+    double best_cost = 1e300;
+    std::vector<int> lens;
+    for (int L = 4 * FF_TILE; L < T + FF_TILE; L += FF_TILE) {
+        int64_t n_items = 0;
+        for (int b = 0; b < nblk; b++) n_items += (T - b * blk + L - 1) / L;
+        if (n_items > 50000) continue;   // partial buffers and plan cost grow with the count
+        lens.clear();
+        for (int b = 0; b < nblk; b++)
+            for (int lo = b * blk; lo < T; lo += L) lens.push_back(std::min(L, T - lo));
+        std::sort(lens.begin(), lens.end(), std::greater<int>());
+        std::priority_queue<double, std::vector<double>, std::greater<double>> q;
+        for (int i = 0; i < slots; i++) q.push(0.0);
+        double makespan = 0;
+        for (int len : lens) {
+            const double t = q.top() + len + fixed;
+            q.pop();
+            q.push(t);
+            makespan = std::max(makespan, t);
+        }
+        if (makespan < best_cost * (1.0 - 1e-9)) {
+            best_cost = makespan;
+            best_L = L;
+        }
+        if (L >= 4096) break;
+    }
+    SymPlan p;
+    p.blk = blk;
+    p.chunk = best_L;
+    p.nblk = nblk;
+    std::vector<std::array<int32_t, 4>> all;   // (len, b, c, canon)
+    int32_t canon = 0;
+    for (int b = 0; b < nblk; b++) {
+        int c = 0;
+        for (int lo = b * blk; lo < T; lo += best_L, c++)
+            all.push_back({std::min(best_L, T - lo), b, c, canon++});
+    }
+    std::stable_sort(all.begin(), all.end(),
+                     [](const std::array<int32_t, 4> &x, const std::array<int32_t, 4> &y) {
+                         return x[0] > y[0];
+                     });
+    for (const auto &e : all) {
+        p.items.push_back(e[1]);
+        p.items.push_back(e[2]);
+        p.items.push_back(e[3]);
+    }
+    p.tau_doubles = (int64_t)canon * blk * SIG_VALS;
+    p.sig_doubles = sym_sig_off(nblk, T, blk) * SIG_VALS;
+    return cache.emplace(std::make_tuple(T, blk, slots), std::move(p)).first->second;
+}
+
+const SymPlan &sym_plan_for(const bem_mesh *m, const FarPlan &fp) {
+    const void *k = fp.fr ? sym_kernel<true>(fp.code) : sym_kernel<false>(fp.code);
+    return sym_plan((int)m->T, fp.blk, far_slots(k, fp.blk, far_smem<float>(fp.blk)));
+}
+
+
 }   // namespace
 
 // right-hand sides per multi-vector pair-kernel launch
@@ -942,9 +1408,14 @@ int64_t farfield_scratch_bytes(const bem_mesh *m, int precision, double2 k0, dou
     for (int blk : {64, 128, 256}) {
         const FarPlan p = far_plan(m, precision, k0, k1, blk);
         part = std::max(part, (int64_t)p.nsplit * T * (ROW_STRIDE + 6) * 8);
+        if (f32) {
+            const SymPlan &sp = sym_plan_for(m, p);
+            part = std::max(part, (sp.tau_doubles + sp.sig_doubles) * 8 +
+                                      (int64_t)sp.items.size() * 4);
+        }
         if (R < 2 || (f32 && p.fr)) continue;
         for (int nr : {2, 4}) {
-            if (nr > R || (!f32 && nr > FF_MULTI_MAX_FP64)) continue;
+            if (nr > R || nr > (f32 ? FF_MULTI_MAX : FF_MULTI_MAX_FP64)) continue;
             const void *k = f32 ? (nr == 4 ? multi_kernel<float, 4>(p.code)
                                            : multi_kernel<float, 2>(p.code))
                                 : multi_kernel<double, 2>(p.code);
@@ -966,12 +1437,45 @@ void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
     const int nsplit = plan.nsplit;
     const bool ck0 = k0.y != 0.0, ck1 = k1.y != 0.0, multi = m->nobj > 1, fr = plan.fr;
     const int split_len = (T + nsplit - 1) / nsplit;
+    const bool sym = precision == BEM_FP32 && tuning().farfield_symmetric;
     const size_t need = (size_t)nsplit * T * (ROW_STRIDE + 6);
-    if (m->partial.n < need) m->partial.alloc(need);
+    if (!sym && m->partial.n < need) m->partial.alloc(need);
     if (m->trirows.n < (size_t)T * ROW_STRIDE) m->trirows.alloc((size_t)T * ROW_STRIDE);
     dim3 gg((T + 255) / 256);
     dim3 grid((T + blk - 1) / blk, nsplit);
-    if (precision == BEM_FP32) {
+    if (sym) {
+        // each separated pair once, rows of both triangles
+        if (m->dyn32.n < (size_t)T * DYN_STRIDE) m->dyn32.alloc((size_t)T * DYN_STRIDE);
+        hipLaunchKernelGGL(source_gather_kernel<float>, gg, dim3(256), 0, s, m->tri_d.p,
+                           m->tst.p, x, m->N, T, m->dyn32.p);
+        BEM_LAUNCH_CHECK();
+        const SymPlan &sp = sym_plan_for(m, plan);
+        const size_t sneed = (size_t)(sp.tau_doubles + sp.sig_doubles);
+        if (m->partial.n < sneed) m->partial.alloc(sneed);
+        if (m->sym_items.n < sp.items.size() || m->sym_plan_id != &sp) {
+            if (m->sym_items.n < sp.items.size()) m->sym_items.alloc(sp.items.size());
+            BEM_HIP(hipMemcpyAsync(m->sym_items.p, sp.items.data(), sp.items.size() * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, s));
+            m->sym_plan_id = &sp;
+        }
+        double *ptau = m->partial.p, *psig = m->partial.p + sp.tau_doubles;
+        const int n_items = (int)(sp.items.size() / 3);
+        {
+            Timer tm("farfield_fp32", s);
+            if (!fr)
+                launch_sym<false>(plan.code, n_items, blk, s, m->geo32.p, m->dyn32.p, m->tobj_d.p,
+                                  m->tri_d.p, T, m->sym_items.p, sp.chunk,
+                                  make_coef<float>(k0, k1, rho), ptau, psig);
+            else
+                launch_sym<true>(plan.code, n_items, blk, s, m->geo32.p, m->dyn32.p, m->tobj_d.p,
+                                 m->tri_d.p, T, m->sym_items.p, sp.chunk,
+                                 make_coef<float>(k0, k1, rho), ptau, psig);
+            BEM_LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(reduce_sym_kernel, gg, dim3(256), 0, s, ptau, psig, m->tst.p, T, blk,
+                           sp.chunk, m->trirows.p);
+        BEM_LAUNCH_CHECK();
+    } else if (precision == BEM_FP32) {
         if (m->dyn32.n < (size_t)T * DYN_STRIDE) m->dyn32.alloc((size_t)T * DYN_STRIDE);
         hipLaunchKernelGGL(source_gather_kernel<float>, gg, dim3(256), 0, s, m->tri_d.p,
                            m->tst.p, x, m->N, T, m->dyn32.p);
@@ -996,9 +1500,11 @@ void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
                              make_coef<double>(k0, k1, rho), m->partial.p, ck0, ck1, multi);
         BEM_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(reduce_splits_kernel, gg, dim3(256), 0, s, m->partial.p, m->tst.p,
-                       T, nsplit, m->trirows.p);
-    BEM_LAUNCH_CHECK();
+    if (!sym) {
+        hipLaunchKernelGGL(reduce_splits_kernel, gg, dim3(256), 0, s, m->partial.p, m->tst.p,
+                           T, nsplit, m->trirows.p);
+        BEM_LAUNCH_CHECK();
+    }
     Timer tf("finalize", s);
     hipLaunchKernelGGL(finalize_kernel, dim3((m->N + 255) / 256), dim3(256), 0, s,
                        m->trirows.p, m->star_ptr.p, m->star_idx.p, m->nf_rowptr.p,

@@ -14,8 +14,11 @@ P32 = 157.3 TFLOP/s (published vector FP32 peak of MI355X) and P_t the issue
 rate of each transcendental instruction, measured on the device by
 ``bem_valu_rates``.  The roofline object reports achieved and peak in
 flop-equivalents at the P32 rate, so frac = achieved pairs/s / model pairs/s.
-FP64: software sin/cos and a refined 1/sqrt at about 30 flops each, against
-the 78.6 TFLOP/s FP64 vector peak.
+FP64: table-based sin/cos and a refined 1/sqrt counted in flops (55 per
+pair), against the 78.6 TFLOP/s FP64 vector peak.  The symmetric FP32
+kernel (each separated triangle pair once) uses the unordered point pair
+as its unit: 164 flops (the accumulations twice) and the same 5
+transcendentals.
 """
 from __future__ import annotations
 
@@ -30,12 +33,27 @@ FLOPS_ITEMS = {
 }
 FLOPS_PER_PAIR = sum(FLOPS_ITEMS.values())            # 110
 TRANS_PER_PAIR = {"sin_f32": 2, "cos_f32": 2, "rsq_f32": 1}
-FP64_SOFT_TRANS_FLOPS = 30                            # per software transcendental
+# FP64: sin and cos of each phase from a 256-entry table of e^{2 pi i n/256}
+# and short Taylor series (reduction 5, two series 12, complex product 6
+# flops per phase), 1/sqrt from the hardware estimate and two Newton steps (9)
+FP64_TRANS_FLOPS_PER_PAIR = 2 * 23 + 9
 
 # VALU instructions per point pair of the tuned FP32 kernel (real wavenumbers,
 # one object), counted in its gfx950 assembly: 1890 VALU FP32 instructions per
 # 36-pair unrolled trial-triangle iteration, transcendentals excluded.
 KERNEL_VALU_PER_PAIR = 52.5
+
+# Symmetric FP32 kernel (each separated triangle pair once, rows of both
+# triangles): unit = one unordered point pair.  The geometry, wavenumber and
+# combination items serve both directions; the accumulations are done for
+# each direction.
+FLOPS_ITEMS_SYM = dict(FLOPS_ITEMS)
+FLOPS_ITEMS_SYM["accumulations: V, K, K', D normal and curl-curl parts"] = 2 * 54
+FLOPS_PER_UPAIR = sum(FLOPS_ITEMS_SYM.values())        # 164
+# its gfx950 assembly (real wavenumbers, one object): VALU instructions per
+# unordered point pair, transcendentals excluded, including the per-trial-
+# triangle work and the cross-lane sums of the rows of sigma
+KERNEL_VALU_PER_UPAIR = 77.0
 
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 LANE_ISSUE_PER_S = 256 * 4 * 16 * 2.4e9                  # 3.93e13 (wave64 op = 4 cycles)
@@ -90,8 +108,24 @@ def far_pairs_per_matvec(triangles: np.ndarray) -> int:
 
 
 def pair_kernel_roofline(point_pairs: int, seconds_per_launch: float,
-                         precision: str = "fp32", rates: dict | None = None) -> dict:
+                         precision: str = "fp32", rates: dict | None = None,
+                         symmetric: bool = False) -> dict:
+    """point_pairs: ordered separated point pairs per matvec.  symmetric: the
+    FP32 kernel evaluates each unordered pair once (unit = unordered pair)."""
     pairs_s = point_pairs / seconds_per_launch
+    if precision == "fp32" and symmetric:
+        r = rates or QUARTER_RATES
+        upairs_s = pairs_s / 2
+        tt = trans_seconds_per_pair(r)
+        fe = FLOPS_PER_UPAIR + PEAK_FP32_TFLOPS * 1e12 * tt
+        achieved = upairs_s * fe / 1e12
+        t_issue = KERNEL_VALU_PER_UPAIR / r["fma_f32"] + tt
+        return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "work_unit": "unordered point pair", "flop_eq_per_unit": fe,
+                "units_per_s": upairs_s, "point_pairs_per_s": pairs_s,
+                "model_units_per_s": 1.0 / (FLOPS_PER_UPAIR / (PEAK_FP32_TFLOPS * 1e12) + tt),
+                "issue_frac": upairs_s * t_issue, "rates_measured": rates is not None}
     if precision == "fp32":
         fe = flop_eq_per_pair(rates)
         achieved = pairs_s * fe / 1e12
@@ -105,7 +139,7 @@ def pair_kernel_roofline(point_pairs: int, seconds_per_launch: float,
         out["issue_frac"] = pairs_s * t_issue
         out["rates_measured"] = rates is not None
         return out
-    fe = FLOPS_PER_PAIR + sum(TRANS_PER_PAIR.values()) * FP64_SOFT_TRANS_FLOPS
+    fe = FLOPS_PER_PAIR + FP64_TRANS_FLOPS_PER_PAIR
     achieved = pairs_s * fe / 1e12
     return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "flop_eq_per_pair": fe,

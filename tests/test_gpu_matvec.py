@@ -295,3 +295,55 @@ def test_matvec_workgroup_sizes(P, block, precision):
             assert max(err.values()) <= TOL[precision], err
     finally:
         P.tune_set("farfield.block", old)
+
+
+@pytest.fixture
+def far_tuning(P):
+    old = {k: P.tune_get(k) for k in ("farfield.block", "farfield.symmetric")}
+    yield lambda k, v: P.tune_set(k, v)
+    for k, v in old.items():
+        P.tune_set(k, v)
+
+
+@pytest.mark.parametrize("block", [64, 128, 256])
+def test_symmetric_kernel_matches_one_directional(P, far_tuning, block):
+    """FP32 kernel that evaluates each separated triangle pair once and adds
+    it to the rows of both triangles, against the kernel that evaluates every
+    ordered pair (same arithmetic per pair, another order of additions) and
+    against the oracle: complex wavenumbers, two objects, ragged last block."""
+    far_tuning("farfield.block", block)
+    for case in ("C1_ico3", "ico2_lossy", "geodesic3_ragged", "two_spheres1"):
+        make, k0, k1, rho = CASES[case]
+        mesh = make()
+        N = mesh.n_vertices
+        print(f"symmetric {case} block {block}", flush=True)
+        x = complex_normal(2 * N, seed=3)
+        ref = dense(mesh, k0, k1, rho) @ x
+        far_tuning("farfield.symmetric", 1)
+        ys = gpu_matvec(P, mesh, k0, k1, rho, x, "fp32")
+        far_tuning("farfield.symmetric", 0)
+        yd = gpu_matvec(P, mesh, k0, k1, rho, x, "fp32")
+        d, e = rel_blocks(ys, yd, N), rel_blocks(ys, ref, N)
+        print(case, block, d, e)
+        assert max(d.values()) <= 2e-6, d
+        assert max(e.values()) <= TOL["fp32"], e
+
+
+def test_fp32_kernels_large_phases(P, far_tuning):
+    """Phases k r / 2 pi above 256 revolutions: both FP32 kernels reduce the
+    phase to [0, 1) before v_sin/v_cos.  Against each other (2e-6) and the
+    oracle: the FP32 rounding of r and k r / 2 pi leaves a phase error of a
+    few t 2^-24 revolutions (t <= 390 here, about 6e-4 rad), hence 2e-3."""
+    mesh = icosphere(2)
+    k0, k1, rho = 500.0, 700.0, 1.3
+    N = mesh.n_vertices
+    x = complex_normal(2 * N, seed=5)
+    ref = dense(mesh, k0, k1, rho) @ x
+    out = {}
+    for sym in (1, 0):
+        far_tuning("farfield.symmetric", sym)
+        out[sym] = gpu_matvec(P, mesh, k0, k1, rho, x, "fp32")
+    d, e = rel_blocks(out[1], out[0], N), rel_blocks(out[1], ref, N)
+    print(d, e)
+    assert max(d.values()) <= 2e-6, d
+    assert max(e.values()) <= 2e-3, e

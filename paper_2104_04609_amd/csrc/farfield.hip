@@ -1319,7 +1319,7 @@ void launch_sym(int code, int n_items, int blk, hipStream_t s, const float *geo,
 // [b blk, b blk + blk)) meets the trial triangles [b blk, T) in chunks of
 // `chunk`; the chunk length is the multiple of the tile that minimises the
 // makespan of a greedy list schedule of the items (longest first) on the
-// resident workgroup slots.  Launch order: full chunks, then the shorter
+// resident workgroup slots, among lengths giving at most 8 items per slot.  Launch order: full chunks, then the shorter
 // last chunks by decreasing length; storage order of the tau rows: b-major.
 struct SymPlan {
     int blk = 0, chunk = 0, nblk = 0;
@@ -1338,10 +1338,11 @@ const SymPlan &sym_plan(int T, int blk, int slots) {
     int best_L = T;
     double best_cost = 1e300;
     std::vector<int> lens;
-    for (int L = 4 * FF_TILE; L < T + FF_TILE; L += FF_TILE) {
+    for (int L = FF_TILE; L < T + FF_TILE; L += FF_TILE) {
         int64_t n_items = 0;
         for (int b = 0; b < nblk; b++) n_items += (T - b * blk + L - 1) / L;
-        if (n_items > 50000) continue;   // partial buffers and plan cost grow with the count
+        // beyond a few rounds finer chunks only add partial-buffer traffic
+        if (n_items > std::min<int64_t>(50000, 8 * (int64_t)slots)) continue;
         lens.clear();
         for (int b = 0; b < nblk; b++)
             for (int lo = b * blk; lo < T; lo += L) lens.push_back(std::min(L, T - lo));

@@ -79,13 +79,27 @@ __global__ __launch_bounds__(LVL_THREADS) void ldl_dense_kernel(LdlDev L, TaskLi
     for (int r = threadIdx.x; r < w; r += LVL_THREADS) tb[r] = y[s0 + r];
     __syncthreads();
     for (int r = threadIdx.x; r < w; r += LVL_THREADS) {
-        double2 acc = make_double2(0.0, 0.0);
+        // eight independent partial sums (loads in flight), added in a fixed order
+        double2 a[8];
+        for (int k = 0; k < 8; k++) a[k] = make_double2(0.0, 0.0);
         const int c0 = FWD ? 0 : r, c1 = FWD ? r + 1 : w;
-        for (int c = c0; c < c1; c++) {
-            const double2 p = cmul(dense[(int64_t)c * w + r], tb[c]);
-            acc.x += p.x;
-            acc.y += p.y;
+        int c = c0;
+        for (; c + 8 <= c1; c += 8) {
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                const double2 p = cmul(dense[(int64_t)(c + k) * w + r], tb[c + k]);
+                a[k].x += p.x;
+                a[k].y += p.y;
+            }
         }
+        for (; c < c1; c++) {
+            const double2 p = cmul(dense[(int64_t)c * w + r], tb[c]);
+            a[0].x += p.x;
+            a[0].y += p.y;
+        }
+        double2 acc;
+        acc.x = ((a[0].x + a[1].x) + (a[2].x + a[3].x)) + ((a[4].x + a[5].x) + (a[6].x + a[7].x));
+        acc.y = ((a[0].y + a[1].y) + (a[2].y + a[3].y)) + ((a[4].y + a[5].y) + (a[6].y + a[7].y));
         y[s0 + r] = acc;
         if (!FWD) t.out[L.perm[s0 + r]] = cmul(t.scale, acc);
     }

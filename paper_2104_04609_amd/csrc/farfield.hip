@@ -611,7 +611,10 @@ void farfield_sym_kernel(
                     spyi[i] = dny[i] * tspi[i];
                 }
                 R gwr = 0, gwi = 0;
-#pragma unroll
+                // j stays a loop: the compact body lets two waves issue VALU
+                // instructions together more often (measured: 15 % of issue
+                // slots instead of 9 %), which outweighs the loop overhead
+#pragma unroll 1
                 for (int j = 0; j < 6; j++) {
                     const R yx = src[3 * j], yy = src[3 * j + 1], yz = src[3 * j + 2];
                     const R spr = src[GEO_STRIDE + 2 * j], spi = src[GEO_STRIDE + 2 * j + 1];

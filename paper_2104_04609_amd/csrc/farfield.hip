@@ -477,8 +477,12 @@ __device__ __forceinline__ float wave_sum_to_lane63(float v) {
     v = dpp_add<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
     v = dpp_add<0x124, 0xF>(v);   // row_ror:4
     v = dpp_add<0x128, 0xF>(v);   // row_ror:8
-    v = dpp_add<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
-    v = dpp_add<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+    // row broadcasts: rows outside the mask keep v (one masked DPP add; the
+    // s_nop covers the two wait states between a VALU write and a DPP read)
+    asm volatile("s_nop 1\n\tv_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf"
+                 : "+v"(v));
+    asm volatile("s_nop 1\n\tv_add_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf"
+                 : "+v"(v));
     return v;
 }
 
@@ -743,10 +747,12 @@ void farfield_sym_kernel(
                     o[ROW_STRIDE + 2 * k + 1] = gwr * tsci[k] + gwi * tscr[k];
                 }
             }
+            float ws[SIG_VALS];
 #pragma unroll
-            for (int k = 0; k < SIG_VALS; k++) {
-                const float w = wave_sum_to_lane63((float)o[k]);
-                if (lane63) sig[(wave * FF_TILE + s) * SIG_VALS + k] = w;
+            for (int k = 0; k < SIG_VALS; k++) ws[k] = wave_sum_to_lane63((float)o[k]);
+            if (lane63) {
+#pragma unroll
+                for (int k = 0; k < SIG_VALS; k++) sig[(wave * FF_TILE + s) * SIG_VALS + k] = ws[k];
             }
         }
         flush();

@@ -51,10 +51,10 @@ FLOPS_ITEMS_SYM = dict(FLOPS_ITEMS)
 FLOPS_ITEMS_SYM["accumulations: V, K, K', D normal and curl-curl parts"] = 2 * 54
 FLOPS_PER_UPAIR = sum(FLOPS_ITEMS_SYM.values())        # 164
 # its instruction stream (real wavenumbers, one object; SQ_INSTS_VALU per
-# wave and unordered point pair, 84.4, minus the 5 transcendentals),
+# wave and unordered point pair, 82.4, minus the 5 transcendentals),
 # including the per-trial-triangle work and the cross-lane sums of the rows
 # of sigma
-KERNEL_VALU_PER_UPAIR = 79.4
+KERNEL_VALU_PER_UPAIR = 77.4
 
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 LANE_ISSUE_PER_S = 256 * 4 * 16 * 2.4e9                  # 3.93e13 (wave64 op = 4 cycles)

@@ -126,7 +126,11 @@ def pair_kernel_roofline(point_pairs: int, seconds_per_launch: float,
                 "work_unit": "unordered point pair", "flop_eq_per_unit": fe,
                 "units_per_s": upairs_s, "point_pairs_per_s": pairs_s,
                 "model_units_per_s": 1.0 / (FLOPS_PER_UPAIR / (PEAK_FP32_TFLOPS * 1e12) + tt),
-                "issue_frac": upairs_s * t_issue, "rates_measured": rates is not None}
+                "issue_frac": upairs_s * t_issue, "rates_measured": rates is not None,
+                # the same launch priced in the one-directional unit (ordered
+                # pairs, 110 flops + 5 transcendentals each): what a kernel
+                # evaluating every ordered pair would need to reach
+                "frac_ordered_unit": pairs_s / model_pairs_per_s(rates)}
     if precision == "fp32":
         fe = flop_eq_per_pair(rates)
         achieved = pairs_s * fe / 1e12

@@ -310,28 +310,30 @@ void farfield_kernel(
             const R nn = ntx * nsx + nty * nsy + ntz * nsz;
             // factor of the G_N term pulled out of the j sum: k_0^2 (n_x . n_y)
             const R gnr = cf.n0r * nn, gni = cf.n0i * nn;
-            // (x_i - y).n_x s_psi(y_j) = ((y_j - x_i).n_x ... ) folded per point j:
-            // spx_j = (c_tau - y_j.n_x) s_psi(y_j)
-            R spxr[6], spxi[6], dny[6];
-            for (int j = 0; j < 6; j++) {
-                const R dnx = ct - (src[3 * j] * ntx + src[3 * j + 1] * nty + src[3 * j + 2] * ntz);
-                spxr[j] = dnx * src[GEO_STRIDE + 2 * j];
-                spxi[j] = dnx * src[GEO_STRIDE + 2 * j + 1];
-            }
+            R dny[6];
             for (int i = 0; i < 6; i++)
                 dny[i] = cs - (px[i] * nsx + py[i] * nsy + pz[i] * nsz);
+            // per test point: sums over j of F s_phi and (G_0 + n10 G_1) s_phi,
+            // scaled by (y - x).n_y resp. k_0^2 (n_x . n_y) after the j loop
+            R qr[6], qi[6], nr[6], ni[6];
+            for (int i = 0; i < 6; i++) qr[i] = qi[i] = nr[i] = ni[i] = 0;
             R gwr = 0, gwi = 0;
+            // j outer and not unrolled: few values live across the loop and
+            // a compact body (i unrolled inside)
+#pragma unroll 1
+            for (int j = 0; j < 6; j++) {
+                const R yx = src[3 * j], yy = src[3 * j + 1], yz = src[3 * j + 2];
+                const R spr = src[GEO_STRIDE + 2 * j], spi = src[GEO_STRIDE + 2 * j + 1];
+                const R sfr = src[GEO_STRIDE + 12 + 2 * j], sfi = src[GEO_STRIDE + 12 + 2 * j + 1];
+                // (x_i - y_j).n_x s_psi(y_j) = (c_tau - y_j.n_x) s_psi(y_j)
+                const R dnx = ct - (yx * ntx + yy * nty + yz * ntz);
+                const R spxr = dnx * spr, spxi = dnx * spi;
+                const R wj = (R)qw(j);
 #pragma unroll
-            for (int i = 0; i < 6; i++) {
-                // per test point: sum_j F s_phi and sum_j (G_0 + n10 G_1) s_phi,
-                // scaled by (y - x).n_y resp. k_0^2 (n_x . n_y) after the j loop
-                R qr = 0, qi = 0, nr = 0, ni = 0;
-                R t1r = a1r[i], t1i = a1i[i], t2r = a2r[i], t2i = a2i[i];
-#pragma unroll
-                for (int j = 0; j < 6; j++) {
-                    const R dx = src[3 * j] - px[i];
-                    const R dy = src[3 * j + 1] - py[i];
-                    const R dz = src[3 * j + 2] - pz[i];
+                for (int i = 0; i < 6; i++) {
+                    const R dx = yx - px[i];
+                    const R dy = yy - py[i];
+                    const R dz = yz - pz[i];
                     const R r2 = dx * dx + dy * dy + dz * dz;
                     const R ri = MT::rsq(r2);
                     const R r = r2 * ri;
@@ -384,39 +386,42 @@ void farfield_kernel(
                         GNr = fmac(-cf.n10i, G1i, GNr);
                         GNi = fmac(cf.n10i, G1r, GNi);
                     }
-                    const R spr = src[GEO_STRIDE + 2 * j], spi = src[GEO_STRIDE + 2 * j + 1];
-                    const R sfr = src[GEO_STRIDE + 12 + 2 * j],
-                            sfi = src[GEO_STRIDE + 12 + 2 * j + 1];
                     // complex multiply-accumulates as explicit FMA chains
+                    R t1r = a1r[i], t1i = a1i[i], t2r = a2r[i], t2i = a2i[i];
                     t1r = fmac(GVr, spr, t1r);
                     t1r = fmac(-GVi, spi, t1r);
                     t1i = fmac(GVr, spi, t1i);
                     t1i = fmac(GVi, spr, t1i);
-                    qr = fmac(Fr, sfr, qr);
-                    qr = fmac(-Fi, sfi, qr);
-                    qi = fmac(Fr, sfi, qi);
-                    qi = fmac(Fi, sfr, qi);
-                    t2r = fmac(Fr, spxr[j], t2r);
-                    t2r = fmac(-Fi, spxi[j], t2r);
-                    t2i = fmac(Fr, spxi[j], t2i);
-                    t2i = fmac(Fi, spxr[j], t2i);
-                    nr = fmac(GNr, sfr, nr);
-                    nr = fmac(-GNi, sfi, nr);
-                    ni = fmac(GNr, sfi, ni);
-                    ni = fmac(GNi, sfr, ni);
-                    const R ww = (R)(qw(i) * qw(j));
+                    t2r = fmac(Fr, spxr, t2r);
+                    t2r = fmac(-Fi, spxi, t2r);
+                    t2i = fmac(Fr, spxi, t2i);
+                    t2i = fmac(Fi, spxr, t2i);
+                    a1r[i] = t1r;
+                    a1i[i] = t1i;
+                    a2r[i] = t2r;
+                    a2i[i] = t2i;
+                    qr[i] = fmac(Fr, sfr, qr[i]);
+                    qr[i] = fmac(-Fi, sfi, qr[i]);
+                    qi[i] = fmac(Fr, sfi, qi[i]);
+                    qi[i] = fmac(Fi, sfr, qi[i]);
+                    nr[i] = fmac(GNr, sfr, nr[i]);
+                    nr[i] = fmac(-GNi, sfi, nr[i]);
+                    ni[i] = fmac(GNr, sfi, ni[i]);
+                    ni[i] = fmac(GNi, sfr, ni[i]);
+                    const R ww = (R)qw(i) * wj;
                     gwr = fmac(ww, GWr, gwr);
                     gwi = fmac(ww, GWi, gwi);
                 }
-                // row 1: - F (y - x).n_y s_phi; row 2: - G_N (n_x . n_y) s_phi
-                t1r = fmac(-dny[i], qr, t1r);
-                t1i = fmac(-dny[i], qi, t1i);
-                t2r = fmac(-gnr, nr, t2r);
-                t2r = fmac(gni, ni, t2r);
-                t2i = fmac(-gnr, ni, t2i);
-                t2i = fmac(-gni, nr, t2i);
-                a1r[i] = t1r;
-                a1i[i] = t1i;
+            }
+            // row 1: - F (y - x).n_y s_phi; row 2: - G_N (n_x . n_y) s_phi
+            for (int i = 0; i < 6; i++) {
+                a1r[i] = fmac(-dny[i], qr[i], a1r[i]);
+                a1i[i] = fmac(-dny[i], qi[i], a1i[i]);
+                R t2r = a2r[i], t2i = a2i[i];
+                t2r = fmac(-gnr, nr[i], t2r);
+                t2r = fmac(gni, ni[i], t2r);
+                t2i = fmac(-gnr, ni[i], t2i);
+                t2i = fmac(-gni, nr[i], t2i);
                 a2r[i] = t2r;
                 a2i[i] = t2i;
             }

@@ -144,7 +144,26 @@ typedef struct {
     int path;            /* FP32 form inner operator: 0 matrix-free pair kernel,
                             1 assembled dense complex64 operator, 2 dense when
                             it fits in device memory (default) */
+    int formulation;     /* preconditioner of B x = f (all give the same x):
+                            BEM_FORM_OSRC (default), BEM_FORM_MASS,
+                            BEM_FORM_CALDERON (one object only) */
 } bem_solve_opts;
+
+/* Preconditioned forms of the permuted PMCHWT system B x = f:
+ *   BEM_FORM_OSRC      L M^{-1} B x = L M^{-1} f, L = diag(L_DtN, L_NtD)
+ *                      (OSRC square-root operators, Sec. 2.6, 2.7)
+ *   BEM_FORM_MASS      M^{-1} B x = M^{-1} f (mass preconditioning, Sec. 2.4)
+ *   BEM_FORM_CALDERON  M^{-1} C M^{-1} B~ u = M^{-1} C M^{-1} f on the
+ *                      paper's ordering u = [phi; psi] (B~ = A_0 + A^_1,
+ *                      B~ u = B x), C the block-diagonal Calderon
+ *                      preconditioner (Sec. 2.5; with one object C = B~ in
+ *                      full).  GMRES runs on x = [psi; phi] with the operator
+ *                      conjugated by the half swap, which leaves its residual
+ *                      history unchanged; two operator applications per
+ *                      iteration.  Meshes with several objects:
+ *                      BEM_E_UNSUPPORTED.
+ * rel_residual and the tolerance refer to the chosen preconditioned system. */
+enum { BEM_FORM_OSRC = 0, BEM_FORM_MASS = 1, BEM_FORM_CALDERON = 2 };
 
 typedef struct {
     int iterations;      /* GMRES iterations (all inner solves) */

@@ -1,4 +1,6 @@
-"""OSRC-preconditioned permuted PMCHWT solve (oracle only).
+"""Preconditioned PMCHWT solves (oracle only; test infrastructure, not part of
+the product path): OSRC (Sec. 2.7), mass only (Sec. 2.4) and block-diagonal
+Calderon (Sec. 2.5).
 
 Preconditioned strong-form system (Sec. 2.4 mass preconditioning, Sec. 2.7
 OSRC-preconditioned PMCHWT):
@@ -59,3 +61,51 @@ class PreconditionedSystem:
         b = self.rhs(d)
         x, it, hist = gmres(self.apply, b, tol=tol, maxiter=maxiter)
         return x, it, hist
+
+
+class MassPreconditionedSystem(PreconditionedSystem):
+    """PMCHWT with mass preconditioning only (Sec. 2.4): M^{-1} B x = M^{-1} f,
+    M^{-1} applied to each N-block.  Same discrete system B x = f as the
+    OSRC-preconditioned one."""
+
+    def apply(self, x):
+        return self.strong(self.B @ x)
+
+    def rhs(self, d):
+        return self.strong(plane_wave_rhs(self.mesh, self.k_ext, d))
+
+
+class CalderonPreconditionedSystem(PreconditionedSystem):
+    """PMCHWT with the block-diagonal Calderon preconditioner (Sec. 2.5):
+    M^{-1} C M^{-1} Bu u = M^{-1} C M^{-1} f with Bu = A_0 + A^_1 acting on
+    u = [phi; psi] (the paper's ordering) and C = diag_m(A_{0,mm} + A^_m), the
+    self-interaction blocks of each object (with one object C = Bu).  The
+    solution is returned in the permuted ordering x = [psi; phi] of B."""
+
+    def __init__(self, mesh, k_ext, k_int, rho, **kw):
+        super().__init__(mesh, k_ext, k_int, rho, **kw)
+        N = self.N
+        perm = np.concatenate([np.arange(N, 2 * N), np.arange(N)])   # [phi; psi] -> [psi; phi]
+        self.Bu = self.B[:, perm]
+        C = self.Bu.copy()
+        if mesh.n_objects() > 1:
+            # drop the exterior coupling between different objects (the
+            # interior operators act within one object already)
+            vobj = np.full(N, -1)
+            for o in range(mesh.n_objects()):
+                vobj[np.unique(mesh.triangles[mesh.object_id == o])] = o
+            same = vobj[:, None] == vobj[None, :]
+            mask = np.block([[same, same], [same, same]])
+            C = np.where(mask, C, 0.0)
+        self.C = C
+
+    def apply(self, u):
+        return self.strong(self.C @ self.strong(self.Bu @ u))
+
+    def rhs(self, d):
+        return self.strong(self.C @ self.strong(plane_wave_rhs(self.mesh, self.k_ext, d)))
+
+    def solve(self, d, tol=1e-8, maxiter=500):
+        u, it, hist = gmres(self.apply, self.rhs(d), tol=tol, maxiter=maxiter)
+        N = self.N
+        return np.concatenate([u[N:], u[:N]]), it, hist

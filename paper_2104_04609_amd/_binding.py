@@ -44,7 +44,7 @@ class SolveOpts(ctypes.Structure):
                 ("osrc_interior", ctypes.c_int), ("R", ctypes.c_double),
                 ("precision", ctypes.c_int), ("maxiter", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
-                ("path", ctypes.c_int)]
+                ("path", ctypes.c_int), ("formulation", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -257,15 +257,22 @@ def default_opts() -> SolveOpts:
     return o
 
 
+# preconditioned forms of the PMCHWT system (BEM_FORM_*)
+FORMULATIONS = {"osrc": 0, "mass": 1, "calderon": 2}
+
+
 def pmchwt_solve(mesh: Mesh, k_ext, k_int, rho: float, directions, tol: float,
                  opts: Optional[SolveOpts] = None, stream=None, **overrides):
-    """OSRC-preconditioned PMCHWT solve; returns (solution [n_waves, 2N], infos, rc)."""
+    """Preconditioned PMCHWT solve (formulation="osrc" (default), "mass" or
+    "calderon"); returns (solution [n_waves, 2N], infos, rc)."""
     import torch
     d = np.ascontiguousarray(np.atleast_2d(directions), dtype=np.float64)
     o = default_opts() if opts is None else opts
     for k, v in overrides.items():
         if k == "precision":
             v = _PREC[v]
+        if k == "formulation" and isinstance(v, str):
+            v = FORMULATIONS[v]
         setattr(o, k, v)
     sol = torch.empty((d.shape[0], 2 * mesh.n_vertices), dtype=torch.complex128,
                       device="cuda")

@@ -25,8 +25,25 @@ namespace {
 
 using cdd = std::complex<double>;
 
+void copy_vec(double2 *dst, const double2 *src, int64_t n, hipStream_t s);
+
+// Halves of each of R vectors [R][2N] exchanged: out_r = [in_r[N:]; in_r[:N]].
+void swap_halves(const double2 *in, double2 *out, int64_t N, int R, hipStream_t s) {
+    for (int r = 0; r < R; r++) {
+        copy_vec(out + 2 * N * r, in + 2 * N * r + N, N, s);
+        copy_vec(out + 2 * N * r + N, in + 2 * N * r, N, s);
+    }
+}
+
 // P applied to R right-hand sides at once (contiguous [R][2N] in and out):
-// weak operator (assembled or pair kernel + near field), then L M^{-1}.
+// weak operator (assembled or pair kernel + near field), then the
+// preconditioner of the formulation: L M^{-1} (OSRC), M^{-1} (mass), or
+// M^{-1} C M^{-1} (Calderon, with C = B read on the [phi; psi] ordering:
+// the strong-form rows [phi-like; psi-like] enter B as [psi; phi]).  The
+// Calderon result is swapped once more so that GMRES, which iterates on
+// x = [psi; phi], sees S Q^2 S with S the half swap and Q y = M^{-1} B S y:
+// unitarily similar to the operator Q^2 of the [phi; psi] ordering, hence the
+// same residual history, where Q^2 S alone would carry the +-1 spectrum of S.
 struct Op {
     bem_mesh *m;
     const NearOperator *nf;
@@ -34,17 +51,39 @@ struct Op {
     double rho;
     OsrcState *st;
     hipStream_t s;
+    int form = BEM_FORM_OSRC;
     const DenseOperator *dense = nullptr;   // assembled operator (FP32 form)
-    DevBuf<double2> yw;                      // weak-form scratch [R][2N]
+    DevBuf<double2> yw, t1, t2;              // weak-form scratch [R][2N]
+    void weak(const double2 *in, double2 *out, int R, int precision) {
+        if (precision == BEM_FP32_DENSE) {
+            dense_apply(*dense, in, out, R, m->xs32, s);
+        } else {
+            farfield_apply_batch(m, *nf, k0, k1, rho, in, out, R, precision, s);
+        }
+    }
+    // the preconditioner on a weak-form vector yw -> out; `precision` is the
+    // operator precision of the second application (Calderon)
+    void precondition(const double2 *w, double2 *out, int R, int precision) {
+        const int64_t n2 = 2 * m->N;
+        if (form == BEM_FORM_OSRC) {
+            osrc_apply_from_weak(m, *st, w, out, R, s);
+        } else if (form == BEM_FORM_MASS) {
+            osrc_mass_solve(m, *st, w, out, 2 * R, s);
+        } else {
+            if (t1.n < (size_t)(R * n2)) t1.alloc((size_t)(R * n2));
+            if (t2.n < (size_t)(R * n2)) t2.alloc((size_t)(R * n2));
+            osrc_mass_solve(m, *st, w, t1.p, 2 * R, s);
+            swap_halves(t1.p, t2.p, m->N, R, s);
+            weak(t2.p, t1.p, R, precision);
+            osrc_mass_solve(m, *st, t1.p, t2.p, 2 * R, s);
+            swap_halves(t2.p, out, m->N, R, s);
+        }
+    }
     void apply(const double2 *in, double2 *out, int R, int precision) {
         const int64_t n2 = 2 * m->N;
         if (yw.n < (size_t)(R * n2)) yw.alloc((size_t)(R * n2));
-        if (precision == BEM_FP32_DENSE) {
-            dense_apply(*dense, in, yw.p, R, m->xs32, s);
-        } else {
-            farfield_apply_batch(m, *nf, k0, k1, rho, in, yw.p, R, precision, s);
-        }
-        osrc_apply_from_weak(m, *st, yw.p, out, R, s);
+        weak(in, yw.p, R, precision);
+        precondition(yw.p, out, R, precision);
     }
 };
 
@@ -250,6 +289,10 @@ void solve_check(const bem_mesh *m, double2 k0, double2 k1, double rho, const do
     if (o.precision != BEM_FP64 && o.precision != BEM_FP32) fail(BEM_E_INVAL, "precision");
     if (o.maxiter < 1 || o.max_outer < 1 || !(o.inner_tol > 0)) fail(BEM_E_INVAL, "opts");
     if (o.path < 0 || o.path > 2) fail(BEM_E_INVAL, "path must be 0, 1 or 2");
+    if (o.formulation < BEM_FORM_OSRC || o.formulation > BEM_FORM_CALDERON)
+        fail(BEM_E_INVAL, "formulation must be 0, 1 or 2");
+    if (o.formulation == BEM_FORM_CALDERON && m->nobj > 1)
+        fail(BEM_E_UNSUPPORTED, "the Calderon formulation supports one object");
     for (int w = 0; w < n_waves; w++) {
         const double *d = dirs + 3 * w;
         if (!(std::fabs(std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) - 1.0) < 1e-6))
@@ -272,6 +315,7 @@ int64_t solve_footprint(bem_mesh *m, double2 k0, double2 k1, double rho,
     if (dense) b += dense_bytes(m) + dense_assembly_scratch_bytes(m) + 2 * G * n2 * 8 +
                     dense_gemm_scratch_bytes(m, G);
     b += ((int64_t)n_waves + 8 * (int64_t)G) * n2 * c16;      // f, B, X, R, D, T, yw, vin, vout
+    if (o.formulation == BEM_FORM_CALDERON) b += 2 * (int64_t)G * n2 * c16;   // t1, t2
     b += G * (workspace_peak_vectors(o.maxiter) * n2 * c16 + (2 * (int64_t)o.maxiter + 8) * c16);
     return b;
 }
@@ -292,6 +336,7 @@ int solve_run(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dir
     DevBuf<double2> f((size_t)n_waves * n2);
     rhs_project(m, k0, directions, n_waves, f.p, s);
     Op op{m, &nf, k0, k1, rho, &st, s};
+    op.form = o.formulation;
     int inner = BEM_FP32;
     if (o.precision == BEM_FP32 && o.path != 0) {
         bool use = o.path == 1;
@@ -320,7 +365,7 @@ int solve_run(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dir
         std::vector<int> n64(R, 0), n32(R, 0), its(R, 0), outer(R, 0);
         std::vector<double> bn(R), rel(R, 0.0);
         std::vector<char> cv(R, 0);
-        osrc_apply_from_weak(m, st, f.p + (size_t)w0 * n2, B.p, R, s);
+        op.precondition(f.p + (size_t)w0 * n2, B.p, R, BEM_FP64);
         dev_norms(B.p, n2, R, nb.p, bn.data(), s);
         if (o.precision == BEM_FP64) {
             std::vector<double> tl(R, tol);
@@ -427,6 +472,7 @@ void bem_solve_opts_default(bem_solve_opts *o) {
     o->inner_tol = 0.3;
     o->max_outer = 8;
     o->path = 2;
+    o->formulation = BEM_FORM_OSRC;
 }
 
 int pmchwt_solve(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,

@@ -105,6 +105,23 @@ int pmchwt_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int,
                   int precision, void *hip_stream);
 
 /*
+ * y = B_M x: the Galerkin Mueller operator I + A_0 - A^_1 (Sec. 2.2; every
+ * interface m contributes I_m + A_{0,mm} - A^_m, exterior operators A_{0,mn}
+ * couple the objects) on the permuted unknowns x = [psi; phi] of
+ * pmchwt_matvec:
+ *     B_M = [[ V_0 - rho V_1  ,  M - (K_0 - K_1)   ],
+ *            [ M + K'_0 - K'_1,  D_0 - D_1 / rho   ]],
+ * M the P1 mass matrix (the identity tested against P1 functions, paired
+ * with each trace row's own trace, hence off the diagonal after the
+ * permutation).  Same quadrature, layouts, precisions and errors as
+ * pmchwt_matvec; its near-field operator is cached apart from PMCHWT's.
+ *   x, y  device, bem_c64 [n_rhs][2N]
+ */
+int muller_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int,
+                  double rho, const bem_c64 *x, bem_c64 *y, int n_rhs,
+                  int precision, void *hip_stream);
+
+/*
  * y = diag(L_DtN, L_NtD) x in strong form (coefficients to coefficients),
  * the OSRC operators of Sec. 2.6 with damped wavenumber k_eps, square root
  * localised by an N_p-term Pade series with branch-cut rotation theta
@@ -144,26 +161,32 @@ typedef struct {
     int path;            /* FP32 form inner operator: 0 matrix-free pair kernel,
                             1 assembled dense complex64 operator, 2 dense when
                             it fits in device memory (default) */
-    int formulation;     /* preconditioner of B x = f (all give the same x):
-                            BEM_FORM_OSRC (default), BEM_FORM_MASS,
-                            BEM_FORM_CALDERON (one object only) */
+    int formulation;     /* BEM_FORM_OSRC (default), BEM_FORM_PMCHWT,
+                            BEM_FORM_CALDERON (one object only) or
+                            BEM_FORM_MULLER; see below */
 } bem_solve_opts;
 
-/* Preconditioned forms of the permuted PMCHWT system B x = f:
- *   BEM_FORM_OSRC      L M^{-1} B x = L M^{-1} f, L = diag(L_DtN, L_NtD)
- *                      (OSRC square-root operators, Sec. 2.6, 2.7)
- *   BEM_FORM_MASS      M^{-1} B x = M^{-1} f (mass preconditioning, Sec. 2.4)
- *   BEM_FORM_CALDERON  M^{-1} C M^{-1} B~ u = M^{-1} C M^{-1} f on the
- *                      paper's ordering u = [phi; psi] (B~ = A_0 + A^_1,
- *                      B~ u = B x), C the block-diagonal Calderon
- *                      preconditioner (Sec. 2.5; with one object C = B~ in
- *                      full).  GMRES runs on x = [psi; phi] with the operator
- *                      conjugated by the half swap, which leaves its residual
- *                      history unchanged; two operator applications per
- *                      iteration.  Meshes with several objects:
- *                      BEM_E_UNSUPPORTED.
- * rel_residual and the tolerance refer to the chosen preconditioned system. */
-enum { BEM_FORM_OSRC = 0, BEM_FORM_MASS = 1, BEM_FORM_CALDERON = 2 };
+/* Formulations (the four compared in Sec. 3.1), all in strong form (mass
+ * preconditioning, Sec. 2.4, M^{-1} on each N-block), f the weak right-hand
+ * side, S the exchange of the two halves of a vector:
+ *   BEM_FORM_OSRC      L M^{-1} B x = L M^{-1} f on x = [psi; phi],
+ *                      L = diag(L_DtN, L_NtD) (OSRC, Sec. 2.6, 2.7)
+ *   BEM_FORM_PMCHWT    M^{-1} B~ u = M^{-1} f, the standard PMCHWT on the
+ *                      paper's ordering u = [phi; psi] (Sec. 2.2), B~ u = B x
+ *   BEM_FORM_CALDERON  M^{-1} C M^{-1} B~ u = M^{-1} C M^{-1} f, C the
+ *                      block-diagonal Calderon preconditioner (Sec. 2.5;
+ *                      with one object C = B~ in full); two operator
+ *                      applications per iteration.  Meshes with several
+ *                      objects: BEM_E_UNSUPPORTED.
+ *   BEM_FORM_MULLER    M^{-1} B~_M u = M^{-1} f, the second-kind Mueller
+ *                      formulation (Sec. 2.2, operator of muller_matvec)
+ * OSRC, PMCHWT and Calderon solve the same discrete system B x = f; Mueller
+ * is a different discretisation of the same problem.  GMRES always iterates
+ * on x = [psi; phi] = S u; for the formulations on u it runs with the
+ * operator conjugated by S, which leaves the residual history unchanged.
+ * The solution is returned as x.  rel_residual and the tolerance refer to
+ * the chosen preconditioned system. */
+enum { BEM_FORM_OSRC = 0, BEM_FORM_PMCHWT = 1, BEM_FORM_CALDERON = 2, BEM_FORM_MULLER = 3 };
 
 typedef struct {
     int iterations;      /* GMRES iterations (all inner solves) */

@@ -7,7 +7,8 @@ psi = exterior Neumann trace, phi = Dirichlet trace of the total field
     B = [[ V_0 + rho V_1 ,  -(K_0 + K_1)        ],
          [ K'_0 + K'_1   ,   D_0 + D_1 / rho    ]],   rho = rho_int / rho_ext,
 
-right-hand side [gamma_D u_inc; gamma_N u_inc].  Exterior operators (index 0)
+right-hand side [gamma_D u_inc; gamma_N u_inc].  The Mueller operator
+(Sec. 2.2) is built on the same unknowns by muller_matrix.  Exterior operators (index 0)
 couple all triangles; interior ones (index 1) act within each object only
 (Sec. 2.7, multiple scattering).
 """
@@ -96,6 +97,28 @@ def pmchwt_matrix(mesh, k_ext, k_int, rho, n_ss=4):
     return pmchwt_blocks(ops0, ops1, rho)
 
 
+def muller_blocks(ops0, ops1, rho, M):
+    """Combine exterior (ops0) and interior (ops1) operators and the P1 mass
+    matrix M into the weak Mueller operator (I + A_0 - A^_1) of Sec. 2.2 on the
+    permuted unknowns [psi; phi] of B: the interior terms enter with the
+    opposite sign, and the identity, tested in both trace rows against P1
+    functions, is M acting on the row's own trace (phi in the first row, psi
+    in the second), i.e. on the off-diagonal blocks after the permutation."""
+    B11 = ops0["V"] - rho * ops1["V"]
+    B12 = M - (ops0["K"] - ops1["K"])
+    B21 = M + (ops0["Kp"] - ops1["Kp"])
+    B22 = ops0["D"] - ops1["D"] / rho
+    return np.block([[B11, B12], [B21, B22]])
+
+
+def muller_matrix(mesh, k_ext, k_int, rho, n_ss=4):
+    """Weak-form Mueller matrix on the permuted unknowns, complex [2N, 2N]."""
+    from .osrc import mass_matrix
+    ops0 = assemble(mesh, k_ext, interior=False, n_ss=n_ss)
+    ops1 = assemble(mesh, k_int, interior=True, n_ss=n_ss)
+    return muller_blocks(ops0, ops1, rho, mass_matrix(mesh).toarray())
+
+
 def _matvec_tris(mesh, k, interior, test, xs, n_ss=4):
     lib = _load()
     R = rules(n_ss)
@@ -154,3 +177,30 @@ def pair_kernel_integral(vx, vy, which, px, py, k, power, n_ss=4):
         ctypes.c_double(complex(k).real), ctypes.c_double(complex(k).imag),
         ctypes.c_int(power), _ptr(res))
     return res[0] + 1j * res[1]
+
+
+def muller_matvec_rows(mesh, k_ext, k_int, rho, x, rows, n_ss=4):
+    """Rows `rows` of both block rows of y = B_M x (Mueller operator of
+    muller_blocks), matrix-free: interior terms with the opposite sign, plus
+    the P1 mass matrix applied to the row's own trace (phi in the first row,
+    psi in the second).  x = [psi; phi] complex [2N].  Returns (y1[rows],
+    y2[rows])."""
+    from .osrc import mass_matrix
+    N = mesh.n_vertices
+    psi, phi = x[:N], x[N:]
+    rows = np.asarray(rows)
+    T = mesh.triangles
+    mask = np.isin(T, rows).any(axis=1)
+    test = np.nonzero(mask)[0]
+    o0 = _matvec_tris(mesh, k_ext, False, test, (psi, phi, psi, phi), n_ss)
+    o1 = _matvec_tris(mesh, k_int, True, test, (psi, phi, psi, phi), n_ss)
+    r1 = (o0[:, 0] - rho * o1[:, 0]) - (o0[:, 1] - o1[:, 1])
+    r2 = (o0[:, 2] - o1[:, 2]) + (o0[:, 3] - o1[:, 3] / rho)
+    y1 = np.zeros(N, np.complex128)
+    y2 = np.zeros(N, np.complex128)
+    tv = T[test]
+    for a in range(3):
+        np.add.at(y1, tv[:, a], r1[:, a])
+        np.add.at(y2, tv[:, a], r2[:, a])
+    M = mass_matrix(mesh)
+    return y1[rows] + M[rows] @ phi, y2[rows] + M[rows] @ psi

@@ -1,6 +1,8 @@
-"""Preconditioned PMCHWT solves (oracle only; test infrastructure, not part of
-the product path): OSRC (Sec. 2.7), mass only (Sec. 2.4) and block-diagonal
-Calderon (Sec. 2.5).
+"""Preconditioned solves (oracle only; test infrastructure, not part of the
+product path): the OSRC-preconditioned permuted PMCHWT (Sec. 2.7) and the
+formulations it is compared with (Sec. 3.1): standard PMCHWT and Mueller in
+strong form (Sec. 2.2, 2.4) and the block-diagonal Calderon preconditioner
+(Sec. 2.5).
 
 Preconditioned strong-form system (Sec. 2.4 mass preconditioning, Sec. 2.7
 OSRC-preconditioned PMCHWT):
@@ -15,7 +17,7 @@ from __future__ import annotations
 import numpy as np
 
 from .gmres import gmres
-from .operators import pmchwt_matrix
+from .operators import muller_matrix, pmchwt_matrix
 from .osrc import OSRC, damped_wavenumber, object_radius
 from .rhs import plane_wave_rhs
 
@@ -63,19 +65,48 @@ class PreconditionedSystem:
         return x, it, hist
 
 
-class MassPreconditionedSystem(PreconditionedSystem):
-    """PMCHWT with mass preconditioning only (Sec. 2.4): M^{-1} B x = M^{-1} f,
+class _PaperOrderingSystem(PreconditionedSystem):
+    """Base of the formulations iterated on the paper's ordering
+    u = [phi; psi] (Sec. 2.2): Bu = B[:, perm] with Bu u = B x for
+    x = [psi; phi]; the solution is returned in the permuted ordering x."""
+
+    def __init__(self, mesh, k_ext, k_int, rho, **kw):
+        super().__init__(mesh, k_ext, k_int, rho, **kw)
+        N = self.N
+        perm = np.concatenate([np.arange(N, 2 * N), np.arange(N)])   # [phi; psi] -> [psi; phi]
+        self.Bu = self.B[:, perm]
+
+    def solve(self, d, tol=1e-8, maxiter=500):
+        u, it, hist = gmres(self.apply, self.rhs(d), tol=tol, maxiter=maxiter)
+        N = self.N
+        return np.concatenate([u[N:], u[:N]]), it, hist
+
+
+class PMCHWTSystem(_PaperOrderingSystem):
+    """Standard PMCHWT formulation in strong form (Sec. 2.2, mass
+    preconditioning Sec. 2.4): M^{-1} Bu u = M^{-1} f on u = [phi; psi],
     M^{-1} applied to each N-block.  Same discrete system B x = f as the
     OSRC-preconditioned one."""
 
-    def apply(self, x):
-        return self.strong(self.B @ x)
+    def apply(self, u):
+        return self.strong(self.Bu @ u)
 
     def rhs(self, d):
         return self.strong(plane_wave_rhs(self.mesh, self.k_ext, d))
 
 
-class CalderonPreconditionedSystem(PreconditionedSystem):
+class MullerSystem(PMCHWTSystem):
+    """Mueller formulation in strong form (Sec. 2.2, Sec. 2.4):
+    M^{-1} (I + A_0 - A^_1) u = M^{-1} f on u = [phi; psi], the weak operator
+    from muller_matrix (B holds it here, in the permuted ordering)."""
+
+    def __init__(self, mesh, k_ext, k_int, rho, B=None, **kw):
+        if B is None:
+            B = muller_matrix(mesh, k_ext, k_int, rho)
+        super().__init__(mesh, k_ext, k_int, rho, B=B, **kw)
+
+
+class CalderonPreconditionedSystem(_PaperOrderingSystem):
     """PMCHWT with the block-diagonal Calderon preconditioner (Sec. 2.5):
     M^{-1} C M^{-1} Bu u = M^{-1} C M^{-1} f with Bu = A_0 + A^_1 acting on
     u = [phi; psi] (the paper's ordering) and C = diag_m(A_{0,mm} + A^_m), the
@@ -85,8 +116,6 @@ class CalderonPreconditionedSystem(PreconditionedSystem):
     def __init__(self, mesh, k_ext, k_int, rho, **kw):
         super().__init__(mesh, k_ext, k_int, rho, **kw)
         N = self.N
-        perm = np.concatenate([np.arange(N, 2 * N), np.arange(N)])   # [phi; psi] -> [psi; phi]
-        self.Bu = self.B[:, perm]
         C = self.Bu.copy()
         if mesh.n_objects() > 1:
             # drop the exterior coupling between different objects (the
@@ -104,8 +133,3 @@ class CalderonPreconditionedSystem(PreconditionedSystem):
 
     def rhs(self, d):
         return self.strong(self.C @ self.strong(plane_wave_rhs(self.mesh, self.k_ext, d)))
-
-    def solve(self, d, tol=1e-8, maxiter=500):
-        u, it, hist = gmres(self.apply, self.rhs(d), tol=tol, maxiter=maxiter)
-        N = self.N
-        return np.concatenate([u[N:], u[:N]]), it, hist

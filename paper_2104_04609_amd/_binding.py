@@ -100,6 +100,8 @@ lib.bem_mesh_info.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_i64)]
 lib.pmchwt_matvec.argtypes = [_vp, c64, c64, ctypes.c_double, _vp, _vp,
                               ctypes.c_int, ctypes.c_int, _vp]
+lib.muller_matvec.argtypes = [_vp, c64, c64, ctypes.c_double, _vp, _vp,
+                              ctypes.c_int, ctypes.c_int, _vp]
 lib.osrc_apply.argtypes = [_vp, ctypes.c_int, ctypes.c_double, c64, c64, _vp, _vp,
                            ctypes.c_int, _vp]
 lib.pmchwt_rhs.argtypes = [_vp, c64, _vp, ctypes.c_int, _vp, _vp]
@@ -211,19 +213,29 @@ class Mesh:
             self._h = None
 
 
-def pmchwt_matvec(mesh: Mesh, k_ext, k_int, rho: float, x, y=None,
-                  precision="fp64", stream=None):
-    """y = B x (weak-form permuted PMCHWT); x, y complex128 [n_rhs, 2N] on device."""
+def _operator_matvec(fn, mesh, k_ext, k_int, rho, x, y, precision, stream):
     import torch
     n2 = 2 * mesh.n_vertices
     n_rhs = _dev_c128(x, n2, "x")
     if y is None:
         y = torch.empty_like(x)
     _dev_c128(y, n2, "y")
-    _check(lib.pmchwt_matvec(mesh.handle, _c(k_ext), _c(k_int), float(rho),
-                             _vp(x.data_ptr()), _vp(y.data_ptr()), n_rhs,
-                             _PREC[precision], _stream(stream)))
+    _check(fn(mesh.handle, _c(k_ext), _c(k_int), float(rho), _vp(x.data_ptr()),
+              _vp(y.data_ptr()), n_rhs, _PREC[precision], _stream(stream)))
     return y
+
+
+def pmchwt_matvec(mesh: Mesh, k_ext, k_int, rho: float, x, y=None,
+                  precision="fp64", stream=None):
+    """y = B x (weak-form permuted PMCHWT); x, y complex128 [n_rhs, 2N] on device."""
+    return _operator_matvec(lib.pmchwt_matvec, mesh, k_ext, k_int, rho, x, y, precision, stream)
+
+
+def muller_matvec(mesh: Mesh, k_ext, k_int, rho: float, x, y=None,
+                  precision="fp64", stream=None):
+    """y = B_M x (weak-form Mueller operator on the permuted unknowns [psi; phi]);
+    x, y complex128 [n_rhs, 2N] on device."""
+    return _operator_matvec(lib.muller_matvec, mesh, k_ext, k_int, rho, x, y, precision, stream)
 
 
 def osrc_apply(mesh: Mesh, pade_terms: int, theta: float, k, k_eps, x, y=None,
@@ -257,14 +269,15 @@ def default_opts() -> SolveOpts:
     return o
 
 
-# preconditioned forms of the PMCHWT system (BEM_FORM_*)
-FORMULATIONS = {"osrc": 0, "mass": 1, "calderon": 2}
+# formulations (BEM_FORM_*)
+FORMULATIONS = {"osrc": 0, "pmchwt": 1, "calderon": 2, "muller": 3}
 
 
 def pmchwt_solve(mesh: Mesh, k_ext, k_int, rho: float, directions, tol: float,
                  opts: Optional[SolveOpts] = None, stream=None, **overrides):
-    """Preconditioned PMCHWT solve (formulation="osrc" (default), "mass" or
-    "calderon"); returns (solution [n_waves, 2N], infos, rc)."""
+    """Strong-form solve of formulation "osrc" (default), "pmchwt",
+    "calderon" or "muller"; returns (solution [n_waves, 2N] as [psi; phi],
+    infos, rc)."""
     import torch
     d = np.ascontiguousarray(np.atleast_2d(directions), dtype=np.float64)
     o = default_opts() if opts is None else opts

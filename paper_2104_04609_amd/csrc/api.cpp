@@ -152,10 +152,12 @@ int bem_mesh_info(const bem_mesh *m, int64_t *nv, int64_t *nt, int32_t *nobj,
     BEM_API_END
 }
 
-int pmchwt_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
-                  const bem_c64 *x, bem_c64 *y, int n_rhs, int precision,
-                  void *hip_stream) {
-    BEM_API_BEGIN
+namespace {
+
+// Body of pmchwt_matvec (s1 = +1) and muller_matvec (s1 = -1); throws.
+void operator_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
+                     const bem_c64 *x, bem_c64 *y, int n_rhs, int precision,
+                     void *hip_stream, int s1) {
     check_mesh(mesh);
     check_k(k_ext, "k_ext");
     check_k(k_int, "k_int");
@@ -168,14 +170,32 @@ int pmchwt_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho
     bem_mesh *m = const_cast<bem_mesh *>(mesh);
     hipStream_t s = (hipStream_t)hip_stream;
     double2 k0 = make_double2(k_ext.re, k_ext.im), k1 = make_double2(k_int.re, k_int.im);
-    const bem::NearOperator &nf = bem::nearfield_get(m, k0, k1, rho, s);
+    const bem::NearOperator &nf = bem::nearfield_get(m, k0, k1, rho, s, s1);
     if (precision == BEM_FP32_DENSE) {
-        const bem::DenseOperator &op = bem::dense_get(m, k0, k1, rho, s);
+        const bem::DenseOperator &op = bem::dense_get(m, k0, k1, rho, s, s1);
         bem::dense_apply(op, (const double2 *)x, (double2 *)y, n_rhs, m->xs32, s);
-        return BEM_OK;
+        return;
     }
     bem::farfield_apply_batch(m, nf, k0, k1, rho, (const double2 *)x, (double2 *)y, n_rhs,
                               precision, s);
+}
+
+}   // namespace
+
+int pmchwt_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
+                  const bem_c64 *x, bem_c64 *y, int n_rhs, int precision,
+                  void *hip_stream) {
+    BEM_API_BEGIN
+    operator_matvec(mesh, k_ext, k_int, rho, x, y, n_rhs, precision, hip_stream, 1);
+    return BEM_OK;
+    BEM_API_END
+}
+
+int muller_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
+                  const bem_c64 *x, bem_c64 *y, int n_rhs, int precision,
+                  void *hip_stream) {
+    BEM_API_BEGIN
+    operator_matvec(mesh, k_ext, k_int, rho, x, y, n_rhs, precision, hip_stream, -1);
     return BEM_OK;
     BEM_API_END
 }

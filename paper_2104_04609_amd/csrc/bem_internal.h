@@ -99,16 +99,20 @@ constexpr int TST_STRIDE = 10;
 //   row1[a] (re,im) a=0..2, row2[a] (re,im) a=0..2
 constexpr int ROW_STRIDE = 12;
 
+// s1: sign of the interior operators, +1 PMCHWT, -1 Mueller (which also
+// carries the identity term in its near field)
 struct NearKey {
     double k0r, k0i, k1r, k1i, rho;
+    int s1;
     bool operator<(const NearKey &o) const {
-        return std::tie(k0r, k0i, k1r, k1i, rho) <
-               std::tie(o.k0r, o.k0i, o.k1r, o.k1i, o.rho);
+        return std::tie(k0r, k0i, k1r, k1i, rho, s1) <
+               std::tie(o.k0r, o.k0i, o.k1r, o.k1i, o.rho, o.s1);
     }
 };
 
 struct NearOperator {
     DevBuf<double> vals;   // [4 blocks][nnz] complex (interleaved): B11 B12 B21 B22
+    int s1 = 1;            // operator the values belong to (NearKey::s1)
 };
 
 // Assembled complex64 operator [2N][2N] (row-major).
@@ -235,16 +239,21 @@ void farfield_apply_batch(bem_mesh *m, const NearOperator &nf, double2 k0, doubl
 // farfield_apply_batch needs for this precision, wavenumber pair and R
 int64_t farfield_scratch_bytes(const bem_mesh *m, int precision, double2 k0, double2 k1, int R);
 // nearfield.hip
+// s1 = +1: near field of the permuted PMCHWT operator; s1 = -1: of the
+// Mueller operator on the same unknowns (interior terms negated, P1 mass
+// matrix added to the two off-diagonal blocks).  The pair kernels read s1
+// from the near operator they are given.
 std::unique_ptr<NearOperator> nearfield_build(bem_mesh *m, double2 k0, double2 k1,
-                                              double rho, hipStream_t s);
+                                              double rho, hipStream_t s, int s1);
 const NearOperator &nearfield_get(bem_mesh *m, double2 k0, double2 k1, double rho,
-                                  hipStream_t s);
+                                  hipStream_t s, int s1 = 1);
 // dense.hip
 int64_t dense_bytes(const bem_mesh *m);
 int64_t dense_assembly_scratch_bytes(const bem_mesh *m);
 std::unique_ptr<DenseOperator> dense_assemble(bem_mesh *m, const NearOperator &nf, double2 k0,
                                               double2 k1, double rho, hipStream_t s);
-const DenseOperator &dense_get(bem_mesh *m, double2 k0, double2 k1, double rho, hipStream_t s);
+const DenseOperator &dense_get(bem_mesh *m, double2 k0, double2 k1, double rho, hipStream_t s,
+                               int s1 = 1);
 // y_r = B x_r, r < R (x, y RHS-major [R][2N]): multi-vector product reading B
 // once per 8 right-hand sides
 void dense_gemv(const DenseOperator &op, const double2 *x, double2 *y, int R, DevBuf<float2> &xs,

@@ -34,6 +34,7 @@ constexpr int JT = 512;   // trial vertices per assembly tile
 
 struct DCoef {
     float krev0, krev1, k0r, k0i, k1r, k1i, kdec0, kdec1, rho, irho, n0r, n0i, n10r, n10i;
+    float ns1;   // -s_1 (interior sign: +1 PMCHWT, -1 Mueller)
 };
 
 __device__ __forceinline__ void sincos_rev(float t, float &s, float &c) {
@@ -118,7 +119,7 @@ __global__ __launch_bounds__(256) void dense_pairs_kernel(
                 }
                 const float G0r = E0r * ri, G0i = E0i * ri, G1r = E1r * ri, G1i = E1i * ri;
                 // F r^2 = i (k_0 E_0 + k_1 E_1) - G_0 - G_1
-                float Fr = -(G0r + G1r), Fi = -(G0i + G1i);
+                float Fr = __builtin_fmaf(cf.ns1, G1r, -G0r), Fi = __builtin_fmaf(cf.ns1, G1i, -G0i);
                 Fr = __builtin_fmaf(-cf.k0r, E0i, Fr);
                 Fi = __builtin_fmaf(cf.k0r, E0r, Fi);
                 Fr = __builtin_fmaf(-cf.k1r, E1i, Fr);
@@ -509,7 +510,9 @@ __global__ __launch_bounds__(256) void to_c64_kernel(const double2 *__restrict__
     if (i < n) o[i] = make_float2((float)x[i].x, (float)x[i].y);
 }
 
-DCoef make_dcoef(double2 k0, double2 k1, double rho) {
+// s1 = -1 negates the interior terms (Mueller operator, Sec. 2.2): folded
+// into rho, 1/rho, k_1^2/(rho k_0^2), k_1 (only in F) and ns1.
+DCoef make_dcoef(double2 k0, double2 k1, double rho, int s1) {
     const double inv2pi = 0.15915494309189533576888376337251;
     const double log2e = 1.4426950408889634073599246810019;
     DCoef c;
@@ -531,6 +534,15 @@ DCoef make_dcoef(double2 k0, double2 k1, double rho) {
     const double d = n0r * n0r + n0i * n0i;
     c.n10r = (float)((n1r * n0r + n1i * n0i) / d);
     c.n10i = (float)((n1i * n0r - n1r * n0i) / d);
+    if (s1 < 0) {
+        c.k1r = -c.k1r;
+        c.k1i = -c.k1i;
+        c.rho = -c.rho;
+        c.irho = -c.irho;
+        c.n10r = -c.n10r;
+        c.n10i = -c.n10i;
+    }
+    c.ns1 = s1 < 0 ? 1.0f : -1.0f;
     return c;
 }
 
@@ -556,7 +568,7 @@ std::unique_ptr<DenseOperator> dense_assemble(bem_mesh *m, const NearOperator &n
     op->T = m->T;
     op->B.alloc((size_t)(n2 * n2));
     DevBuf<float2> Q((size_t)m->T * JT * 12);
-    const DCoef cf = make_dcoef(k0, k1, rho);
+    const DCoef cf = make_dcoef(k0, k1, rho, nf.s1);
     const int code = (k0.y != 0 ? 4 : 0) | (k1.y != 0 ? 2 : 0) | (m->nobj > 1 ? 1 : 0);
     Timer tm("dense_assemble", s);
     for (int64_t j0 = 0; j0 < N; j0 += JT) {
@@ -683,11 +695,12 @@ void dense_gemm(const DenseOperator &op, const double2 *x, double2 *y, int R, hi
     BEM_HIP(hipStreamSynchronize(s));   // Xp, Yp are released on return
 }
 
-const DenseOperator &dense_get(bem_mesh *m, double2 k0, double2 k1, double rho, hipStream_t s) {
-    NearKey key{k0.x, k0.y, k1.x, k1.y, rho};
+const DenseOperator &dense_get(bem_mesh *m, double2 k0, double2 k1, double rho, hipStream_t s,
+                               int s1) {
+    NearKey key{k0.x, k0.y, k1.x, k1.y, rho, s1};
     auto it = m->dense_cache.find(key);
     if (it != m->dense_cache.end()) return *it->second;
-    const NearOperator &nf = nearfield_get(m, k0, k1, rho, s);
+    const NearOperator &nf = nearfield_get(m, k0, k1, rho, s, s1);
     // one resident dense operator per mesh unless memory allows more
     size_t free_b = 0, total_b = 0;
     BEM_HIP(hipMemGetInfo(&free_b, &total_b));

@@ -24,6 +24,9 @@
 // the y sum: (y - x).n_y = c_sigma - x.n_sigma (per x), (x - y).n_x =
 // c_tau - y.n_tau (per y, folded into s_psi), and k_0^2 (n_x.n_y) per triangle pair.
 // Interior terms (index 1) are masked out for triangles of different objects.
+// The Mueller operator (Sec. 2.2) is the same sum with the interior terms
+// negated; its identity part lives in the near-field operator, so the pair
+// kernels only see the sign, folded into the launch coefficients.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -153,6 +156,7 @@ template <class R> struct Coef {
     R rho, irho;
     R n0r, n0i;              // k_0^2
     R n10r, n10i;            // k_1^2 / (rho k_0^2)
+    R ns1;                   // -s_1
 };
 
 // ------------------------------------------------------------ source gather
@@ -362,7 +366,7 @@ void farfield_kernel(
                     const R G1r = E1r * ri, G1i = E1i * ri;
                     // F r^2 = G_0 (i k_0 r - 1) + G_1 (i k_1 r - 1)
                     //       = i (k_0 E_0 + k_1 E_1) - (G_0 + G_1)       (r / r = 1)
-                    R Fr = -(G0r + G1r), Fi = -(G0i + G1i);
+                    R Fr = fmac(cf.ns1, G1r, -G0r), Fi = fmac(cf.ns1, G1i, -G0i);
                     Fr = fmac(-cf.k0r, E0i, Fr);
                     Fi = fmac(cf.k0r, E0r, Fi);
                     Fr = fmac(-cf.k1r, E1i, Fr);
@@ -662,7 +666,7 @@ void farfield_sym_kernel(
                         }
                         const R G0r = E0r * ri, G0i = E0i * ri;
                         const R G1r = E1r * ri, G1i = E1i * ri;
-                        R Fr = -(G0r + G1r), Fi = -(G0i + G1i);
+                        R Fr = fmac(cf.ns1, G1r, -G0r), Fi = fmac(cf.ns1, G1i, -G0i);
                         Fr = fmac(-cf.k0r, E0i, Fr);
                         Fi = fmac(cf.k0r, E0r, Fi);
                         Fr = fmac(-cf.k1r, E1i, Fr);
@@ -938,7 +942,7 @@ void farfield_multi_kernel(
                     }
                     const R G0r = E0r * ri, G0i = E0i * ri;
                     const R G1r = E1r * ri, G1i = E1i * ri;
-                    R Fr = -(G0r + G1r), Fi = -(G0i + G1i);
+                    R Fr = fmac(cf.ns1, G1r, -G0r), Fi = fmac(cf.ns1, G1i, -G0i);
                     Fr = fmac(-cf.k0r, E0i, Fr);
                     Fi = fmac(cf.k0r, E0r, Fi);
                     Fr = fmac(-cf.k1r, E1i, Fr);
@@ -1116,7 +1120,11 @@ __global__ __launch_bounds__(256) void finalize_kernel(
     y[N + i] = make_double2(y2r, y2i);
 }
 
-template <class R> Coef<R> make_coef(double2 k0, double2 k1, double rho) {
+// s1 = +1: PMCHWT (A_0 + A^_1); s1 = -1: the interior terms of the Mueller
+// operator (A_0 - A^_1).  The sign is folded into every interior coefficient:
+// rho, 1/rho, k_1^2/(rho k_0^2) and k_1 (which enters only through F), and
+// ns1 carries it into the -(G_0 + s1 G_1) part of F.
+template <class R> Coef<R> make_coef(double2 k0, double2 k1, double rho, int s1) {
     Coef<R> c;
     const double inv2pi = 0.15915494309189533576888376337251;
     const double log2e = 1.4426950408889634073599246810019;
@@ -1138,6 +1146,15 @@ template <class R> Coef<R> make_coef(double2 k0, double2 k1, double rho) {
     const double d = n0r * n0r + n0i * n0i;
     c.n10r = (R)((n1r * n0r + n1i * n0i) / d);
     c.n10i = (R)((n1i * n0r - n1r * n0i) / d);
+    if (s1 < 0) {
+        c.k1r = -c.k1r;
+        c.k1i = -c.k1i;
+        c.rho = -c.rho;
+        c.irho = -c.irho;
+        c.n10r = -c.n10r;
+        c.n10i = -c.n10i;
+    }
+    c.ns1 = (R)(s1 < 0 ? 1.0 : -1.0);
     return c;
 }
 
@@ -1494,11 +1511,11 @@ void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
             if (!fr)
                 launch_sym<false>(plan.code, n_items, blk, s, m->geo32.p, m->dyn32.p, m->tobj_d.p,
                                   m->tri_d.p, T, m->sym_items.p, sp.chunk,
-                                  make_coef<float>(k0, k1, rho), ptau, psig);
+                                  make_coef<float>(k0, k1, rho, nf.s1), ptau, psig);
             else
                 launch_sym<true>(plan.code, n_items, blk, s, m->geo32.p, m->dyn32.p, m->tobj_d.p,
                                  m->tri_d.p, T, m->sym_items.p, sp.chunk,
-                                 make_coef<float>(k0, k1, rho), ptau, psig);
+                                 make_coef<float>(k0, k1, rho, nf.s1), ptau, psig);
             BEM_LAUNCH_CHECK();
         }
         hipLaunchKernelGGL(reduce_sym_kernel, gg, dim3(256), 0, s, ptau, psig, m->tst.p, T, blk,
@@ -1512,11 +1529,11 @@ void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
         Timer tm("farfield_fp32", s);
         if (!fr)
             dispatch_far<float, false>(grid, blk, s, m->geo32.p, m->dyn32.p, m->tobj_d.p, m->tri_d.p,
-                                       T, split_len, make_coef<float>(k0, k1, rho),
+                                       T, split_len, make_coef<float>(k0, k1, rho, nf.s1),
                                        m->partial.p, ck0, ck1, multi);
         else
             dispatch_far<float, true>(grid, blk, s, m->geo32.p, m->dyn32.p, m->tobj_d.p, m->tri_d.p,
-                                      T, split_len, make_coef<float>(k0, k1, rho),
+                                      T, split_len, make_coef<float>(k0, k1, rho, nf.s1),
                                       m->partial.p, ck0, ck1, multi);
         BEM_LAUNCH_CHECK();
     } else {
@@ -1526,7 +1543,7 @@ void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
         BEM_LAUNCH_CHECK();
         Timer tm("farfield_fp64", s);
         dispatch_far<double, true>(grid, blk, s, m->geo64.p, m->dyn64.p, m->tobj_d.p, m->tri_d.p, T, split_len,
-                             make_coef<double>(k0, k1, rho), m->partial.p, ck0, ck1, multi);
+                             make_coef<double>(k0, k1, rho, nf.s1), m->partial.p, ck0, ck1, multi);
         BEM_LAUNCH_CHECK();
     }
     if (!sym) {
@@ -1575,7 +1592,7 @@ void farfield_multi_apply(bem_mesh *m, const NearOperator &nf, double2 k0, doubl
     {
         Timer tm(F32 ? "farfield_fp32_multi" : "farfield_fp64_multi", s);
         launch_multi<R, NR>(code, dim3((T + blk - 1) / blk, nsplit), blk, s, geo, dyn,
-                            m->tobj_d.p, m->tri_d.p, T, split_len, make_coef<R>(k0, k1, rho),
+                            m->tobj_d.p, m->tri_d.p, T, split_len, make_coef<R>(k0, k1, rho, nf.s1),
                             m->partial.p);
         BEM_LAUNCH_CHECK();
     }

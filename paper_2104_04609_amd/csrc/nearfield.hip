@@ -1,5 +1,5 @@
 // Near-field operator of the permuted PMCHWT matvec (FP64, built once per
-// (k_ext, k_int, rho) and kept on the device).
+// (k_ext, k_int, rho, s1) and kept on the device).
 //
 // For every ordered triangle pair (tau, sigma) sharing at least one vertex the
 // four combined 3x3 blocks
@@ -8,7 +8,10 @@
 // are integrated with the singular rule of the pair's class (coincident,
 // common edge, common vertex); the matrix-free pair kernel skips exactly these
 // pairs.  The blocks are summed into a vertex-by-vertex CSR matrix in a fixed
-// order.
+// order.  With s1 = -1 the interior terms enter with the opposite sign and the
+// coincident pairs add the local P1 mass matrix |tau| (1 + delta_ab) / 12 to
+// B12 and B21: the Mueller operator I + A_0 - A^_1 of Sec. 2.2 on the
+// permuted unknowns, whose identity pairs each trace row with its own trace.
 #include <cmath>
 
 #include "bem_internal.h"
@@ -20,6 +23,7 @@ namespace {
 struct NearCoef {
     double2 k0, k1;
     double rho;
+    double s1;   // +1 PMCHWT, -1 Mueller
 };
 
 __device__ inline double2 cmul(double2 a, double2 b) {
@@ -75,8 +79,9 @@ __global__ __launch_bounds__(64) void near_pairs_kernel(
 #pragma unroll
     for (int i = 0; i < NACC; i++) acc[i] = 0.0;
     const double k0sq_r = cf.k0.x * cf.k0.x - cf.k0.y * cf.k0.y, k0sq_i = 2 * cf.k0.x * cf.k0.y;
-    const double k1sq_r = (cf.k1.x * cf.k1.x - cf.k1.y * cf.k1.y) / cf.rho,
-                 k1sq_i = 2 * cf.k1.x * cf.k1.y / cf.rho;
+    const double k1sq_r = cf.s1 * (cf.k1.x * cf.k1.x - cf.k1.y * cf.k1.y) / cf.rho,
+                 k1sq_i = cf.s1 * 2 * cf.k1.x * cf.k1.y / cf.rho;
+    const double rho1 = cf.s1 * cf.rho, irho1 = cf.s1 / cf.rho;
 
     for (int q = lane; q < nss; q += 64) {
         double lx[3], ly[3];
@@ -98,11 +103,11 @@ __global__ __launch_bounds__(64) void near_pairs_kernel(
         double2 G0, F0, G1, F1;
         green(cf.k0, r, G0, F0);
         green(cf.k1, r, G1, F1);
-        double2 GV = make_double2(G0.x + cf.rho * G1.x, G0.y + cf.rho * G1.y);
-        double2 GW = make_double2(G0.x + G1.x / cf.rho, G0.y + G1.y / cf.rho);
+        double2 GV = make_double2(G0.x + rho1 * G1.x, G0.y + rho1 * G1.y);
+        double2 GW = make_double2(G0.x + irho1 * G1.x, G0.y + irho1 * G1.y);
         double2 GN = make_double2(k0sq_r * G0.x - k0sq_i * G0.y + k1sq_r * G1.x - k1sq_i * G1.y,
                                   k0sq_r * G0.y + k0sq_i * G0.x + k1sq_r * G1.y + k1sq_i * G1.x);
-        double2 FK = make_double2(F0.x + F1.x, F0.y + F1.y);
+        double2 FK = make_double2(F0.x + cf.s1 * F1.x, F0.y + cf.s1 * F1.y);
         double dny = -(d[0] * ns[0] + d[1] * ns[1] + d[2] * ns[2]);   // (y-x).n_y
         double dnx = d[0] * nt[0] + d[1] * nt[1] + d[2] * nt[2];      // (x-y).n_x
 #pragma unroll
@@ -142,6 +147,8 @@ __global__ __launch_bounds__(64) void near_pairs_kernel(
                 v.x += cc * acc[72];
                 v.y += cc * acc[73];
             }
+            if (cf.s1 < 0 && t == s && (blk == 1 || blk == 2))
+                v.x += at * (a == b ? 2.0 : 1.0) / 12.0;   // Mueller identity: P1 mass
             blocks[36 * p + e] = v;
         }
     }
@@ -171,14 +178,15 @@ __global__ __launch_bounds__(256) void near_csr_kernel(
 }   // namespace
 
 std::unique_ptr<NearOperator> nearfield_build(bem_mesh *m, double2 k0, double2 k1,
-                                              double rho, hipStream_t s) {
+                                              double rho, hipStream_t s, int s1) {
     auto op = std::make_unique<NearOperator>();
+    op->s1 = s1 < 0 ? -1 : 1;
     op->vals.alloc(4 * (size_t)m->nf_nnz * 2);
     DevBuf<double> Pd;
     std::vector<double> Ph(m->P);
     Pd.upload(Ph);
     DevBuf<double2> blocks(36 * (size_t)m->n_near);
-    NearCoef cf{k0, k1, rho};
+    NearCoef cf{k0, k1, rho, (double)op->s1};
     {
         Timer tm("nearfield_build", s);
         hipLaunchKernelGGL(near_pairs_kernel, dim3((unsigned)m->n_near), dim3(64), 0, s,
@@ -196,12 +204,13 @@ std::unique_ptr<NearOperator> nearfield_build(bem_mesh *m, double2 k0, double2 k
 }
 
 const NearOperator &nearfield_get(bem_mesh *m, double2 k0, double2 k1, double rho,
-                                  hipStream_t s) {
-    NearKey key{k0.x, k0.y, k1.x, k1.y, rho};
+                                  hipStream_t s, int s1) {
+    s1 = s1 < 0 ? -1 : 1;
+    NearKey key{k0.x, k0.y, k1.x, k1.y, rho, s1};
     auto it = m->near_cache.find(key);
     if (it != m->near_cache.end()) return *it->second;
     if (m->near_cache.size() >= 8) m->near_cache.erase(m->near_cache.begin());
-    auto op = nearfield_build(m, k0, k1, rho, s);
+    auto op = nearfield_build(m, k0, k1, rho, s, s1);
     auto &ref = *op;
     m->near_cache.emplace(key, std::move(op));
     return ref;

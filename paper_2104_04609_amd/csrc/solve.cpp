@@ -3,6 +3,10 @@
 //
 //   P x = b,  P = L M^{-1} B,  b = L M^{-1} f,  L = diag(L_DtN, L_NtD) per object.
 //
+// The formulations it is compared with (Sec. 3.1) share the driver: standard
+// PMCHWT and Mueller (Sec. 2.2) in strong form, and PMCHWT with the
+// block-diagonal Calderon preconditioner (Sec. 2.5); see Op.
+//
 // The preconditioner is applied to the weak vector directly: L M^{-1} y uses
 // M (M^{-1} y) = y, so no separate mass solve is needed.  GMRES runs in FP64:
 // Arnoldi by classical Gram-Schmidt with one reorthogonalisation (CGS2) on the
@@ -36,14 +40,15 @@ void swap_halves(const double2 *in, double2 *out, int64_t N, int R, hipStream_t 
 }
 
 // P applied to R right-hand sides at once (contiguous [R][2N] in and out):
-// weak operator (assembled or pair kernel + near field), then the
-// preconditioner of the formulation: L M^{-1} (OSRC), M^{-1} (mass), or
-// M^{-1} C M^{-1} (Calderon, with C = B read on the [phi; psi] ordering:
-// the strong-form rows [phi-like; psi-like] enter B as [psi; phi]).  The
-// Calderon result is swapped once more so that GMRES, which iterates on
-// x = [psi; phi], sees S Q^2 S with S the half swap and Q y = M^{-1} B S y:
-// unitarily similar to the operator Q^2 of the [phi; psi] ordering, hence the
-// same residual history, where Q^2 S alone would carry the +-1 spectrum of S.
+// weak operator (assembled or pair kernel + near field; the Mueller operator
+// when the near field is Mueller's), then the preconditioner of the
+// formulation.  OSRC: L M^{-1}.  The others are defined on the paper's
+// ordering u = [phi; psi] (B~ u = B S u with S the half swap) while GMRES
+// iterates on x = [psi; phi] = S u: they apply S P~ S, unitarily similar to
+// P~, so the residual history is that of P~ on u.  PMCHWT and Mueller:
+// P~ = M^{-1} B~, so S P~ S x = S M^{-1} B x.  Calderon: P~ = Q^2 with
+// Q y = M^{-1} B S y (C = B~ for one object), so S P~ S x =
+// S M^{-1} B S M^{-1} B x.
 struct Op {
     bem_mesh *m;
     const NearOperator *nf;
@@ -67,8 +72,10 @@ struct Op {
         const int64_t n2 = 2 * m->N;
         if (form == BEM_FORM_OSRC) {
             osrc_apply_from_weak(m, *st, w, out, R, s);
-        } else if (form == BEM_FORM_MASS) {
-            osrc_mass_solve(m, *st, w, out, 2 * R, s);
+        } else if (form == BEM_FORM_PMCHWT || form == BEM_FORM_MULLER) {
+            if (t1.n < (size_t)(R * n2)) t1.alloc((size_t)(R * n2));
+            osrc_mass_solve(m, *st, w, t1.p, 2 * R, s);
+            swap_halves(t1.p, out, m->N, R, s);
         } else {
             if (t1.n < (size_t)(R * n2)) t1.alloc((size_t)(R * n2));
             if (t2.n < (size_t)(R * n2)) t2.alloc((size_t)(R * n2));
@@ -289,8 +296,8 @@ void solve_check(const bem_mesh *m, double2 k0, double2 k1, double rho, const do
     if (o.precision != BEM_FP64 && o.precision != BEM_FP32) fail(BEM_E_INVAL, "precision");
     if (o.maxiter < 1 || o.max_outer < 1 || !(o.inner_tol > 0)) fail(BEM_E_INVAL, "opts");
     if (o.path < 0 || o.path > 2) fail(BEM_E_INVAL, "path must be 0, 1 or 2");
-    if (o.formulation < BEM_FORM_OSRC || o.formulation > BEM_FORM_CALDERON)
-        fail(BEM_E_INVAL, "formulation must be 0, 1 or 2");
+    if (o.formulation < BEM_FORM_OSRC || o.formulation > BEM_FORM_MULLER)
+        fail(BEM_E_INVAL, "formulation must be 0, 1, 2 or 3");
     if (o.formulation == BEM_FORM_CALDERON && m->nobj > 1)
         fail(BEM_E_UNSUPPORTED, "the Calderon formulation supports one object");
     for (int w = 0; w < n_waves; w++) {
@@ -316,6 +323,7 @@ int64_t solve_footprint(bem_mesh *m, double2 k0, double2 k1, double rho,
                     dense_gemm_scratch_bytes(m, G);
     b += ((int64_t)n_waves + 8 * (int64_t)G) * n2 * c16;      // f, B, X, R, D, T, yw, vin, vout
     if (o.formulation == BEM_FORM_CALDERON) b += 2 * (int64_t)G * n2 * c16;   // t1, t2
+    else if (o.formulation != BEM_FORM_OSRC) b += (int64_t)G * n2 * c16;       // t1
     b += G * (workspace_peak_vectors(o.maxiter) * n2 * c16 + (2 * (int64_t)o.maxiter + 8) * c16);
     return b;
 }
@@ -326,7 +334,8 @@ int solve_run(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dir
     solve_check(m, k0, k1, rho, directions, n_waves, tol, o);
     if (!solution) fail(BEM_E_INVAL, "solution is NULL");
     const int64_t n2 = 2 * m->N;
-    const NearOperator &nf = nearfield_get(m, k0, k1, rho, s);
+    const int s1 = o.formulation == BEM_FORM_MULLER ? -1 : 1;   // Mueller operator
+    const NearOperator &nf = nearfield_get(m, k0, k1, rho, s, s1);
     const double2 ko = o.osrc_interior ? k1 : k0;
     std::vector<double2> keps(m->nobj);
     for (int ob = 0; ob < m->nobj; ob++)
@@ -349,7 +358,7 @@ int solve_run(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dir
             use = fits && !(tune_find(m->T, std::min(n_waves, SOLVE_BATCH), &te) && te.path == 0);
         }
         if (use) {
-            op.dense = &dense_get(m, k0, k1, rho, s);
+            op.dense = &dense_get(m, k0, k1, rho, s, s1);
             inner = BEM_FP32_DENSE;
         }
     }

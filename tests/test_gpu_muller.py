@@ -1,0 +1,179 @@
+"""GPU parity of the Mueller operator (Sec. 2.2) through muller_matvec
+against the FP64 oracle, element by element.
+
+Bar as for the PMCHWT matvec: relative L2 error <= 1e-10 (FP64) and <= 1e-5
+(FP32, FP32 assembled) per block row and overall.  The pair kernels carry the
+interior sign in their launch coefficients, so every FP32 kernel variant is
+run (symmetric and one-directional, shared by 2 and 4 right-hand sides,
+complex wavenumbers, two objects, ragged triangle counts), plus the full
+icosphere L5 workload on seed-sampled rows and the same-material case, where
+the operator reduces to the mass matrix.
+"""
+import numpy as np
+import pytest
+
+from bem_inputs import complex_normal, geodesic_sphere, icosphere, sample_rows, two_spheres
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "fp32_dense": 1e-5}
+
+CASES = {
+    "C1_ico3": (lambda: icosphere(3), 2.0, 3.0, 1.5),
+    "ico2_lossy": (lambda: icosphere(2), 2.5 + 0.3j, 4.0 + 0.6j, 1.9),
+    "geodesic3_ragged": (lambda: geodesic_sphere(3), 1.5, 2.2, 0.7),
+    "two_spheres1": (lambda: two_spheres(1, offset=1.5), 2.0, 3.5 + 0.2j, 1.3),
+}
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2104_04609_amd as P
+    return P
+
+
+_DENSE = {}
+
+
+def dense(mesh, k0, k1, rho):
+    from oracle.operators import muller_matrix
+    key = (mesh.name, complex(k0), complex(k1), rho)
+    if key not in _DENSE:
+        _DENSE[key] = muller_matrix(mesh, k0, k1, rho)
+    return _DENSE[key]
+
+
+def rel_blocks(y, ref, N):
+    return {name: np.linalg.norm(y[sl] - ref[sl]) / np.linalg.norm(ref[sl])
+            for name, sl in (("row1", slice(0, N)), ("row2", slice(N, 2 * N)),
+                             ("all", slice(0, 2 * N)))}
+
+
+def gpu_muller(P, mesh, k0, k1, rho, x, precision):
+    import torch
+    M = P.Mesh.from_inputs(mesh)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    y = P.muller_matvec(M, k0, k1, rho, xt, precision=precision)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+@pytest.fixture
+def tuning(P):
+    keys = ("farfield.block", "farfield.symmetric", "farfield.multi_max")
+    old = {k: P.tune_get(k) for k in keys}
+    yield lambda k, v: P.tune_set(k, v)
+    for k, v in old.items():
+        P.tune_set(k, v)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_dense"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_muller_matches_dense_oracle(P, case, precision):
+    make, k0, k1, rho = CASES[case]
+    mesh = make()
+    N = mesh.n_vertices
+    print(f"muller {case} N={N} {precision}", flush=True)
+    x = complex_normal(2 * N, seed=0)
+    ref = dense(mesh, k0, k1, rho) @ x
+    err = rel_blocks(gpu_muller(P, mesh, k0, k1, rho, x, precision), ref, N)
+    print(case, precision, err)
+    assert max(err.values()) <= TOL[precision], err
+
+
+def test_muller_and_pmchwt_near_fields_coexist(P):
+    """Both operators on one mesh handle at the same (k, rho): each keeps
+    its own near-field (and assembled) operator."""
+    import torch
+    from oracle.operators import pmchwt_matrix
+    make, k0, k1, rho = CASES["C1_ico3"]
+    mesh = make()
+    N = mesh.n_vertices
+    M = P.Mesh.from_inputs(mesh)
+    x = complex_normal(2 * N, seed=2)
+    xt = torch.from_numpy(x).cuda()
+    for prec in ("fp64", "fp32_dense"):
+        y_p = P.pmchwt_matvec(M, k0, k1, rho, xt, precision=prec).cpu().numpy()
+        y_m = P.muller_matvec(M, k0, k1, rho, xt, precision=prec).cpu().numpy()
+        y_p2 = P.pmchwt_matvec(M, k0, k1, rho, xt, precision=prec).cpu().numpy()
+        assert np.array_equal(y_p, y_p2)
+        assert max(rel_blocks(y_p, pmchwt_matrix(mesh, k0, k1, rho) @ x, N).values()) <= TOL[prec]
+        assert max(rel_blocks(y_m, dense(mesh, k0, k1, rho) @ x, N).values()) <= TOL[prec]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_muller_same_material_is_mass_matrix(P, tuning, precision):
+    """k_int = k_ext, rho = 1: A^_1 = A_0, so B_M x = [M phi; M psi]."""
+    from oracle.osrc import mass_matrix
+    mesh = icosphere(3)
+    N = mesh.n_vertices
+    k = 2.0 + 0.2j
+    x = complex_normal(2 * N, seed=4)
+    Mm = mass_matrix(mesh)
+    ref = np.concatenate([Mm @ x[N:], Mm @ x[:N]])
+    for sym in ((1, 0) if precision == "fp32" else (0,)):
+        tuning("farfield.symmetric", sym)
+        y = gpu_muller(P, mesh, k, k, 1.0, x, precision)
+        err = rel_blocks(y, ref, N)
+        print(precision, sym, err)
+        assert max(err.values()) <= (1e-12 if precision == "fp64" else 1e-6), err
+
+
+@pytest.mark.parametrize("block", [64, 256])
+def test_muller_symmetric_and_one_directional(P, tuning, block):
+    tuning("farfield.block", block)
+    for case in ("ico2_lossy", "geodesic3_ragged", "two_spheres1"):
+        make, k0, k1, rho = CASES[case]
+        mesh = make()
+        N = mesh.n_vertices
+        print(f"muller symmetric {case} block {block}", flush=True)
+        x = complex_normal(2 * N, seed=3)
+        ref = dense(mesh, k0, k1, rho) @ x
+        tuning("farfield.symmetric", 1)
+        ys = gpu_muller(P, mesh, k0, k1, rho, x, "fp32")
+        tuning("farfield.symmetric", 0)
+        yd = gpu_muller(P, mesh, k0, k1, rho, x, "fp32")
+        d, e = rel_blocks(ys, yd, N), rel_blocks(ys, ref, N)
+        print(case, block, d, e)
+        assert max(d.values()) <= 2e-6, d
+        assert max(e.values()) <= TOL["fp32"], e
+
+
+@pytest.mark.parametrize("precision,mm", [("fp32", 2), ("fp32", 4), ("fp64", 2)])
+def test_muller_multi_rhs(P, tuning, precision, mm):
+    import torch
+    for case in ("ico2_lossy", "two_spheres1"):
+        make, k0, k1, rho = CASES[case]
+        mesh = make()
+        N = mesh.n_vertices
+        M = P.Mesh.from_inputs(mesh)
+        print(f"muller multi {case} {precision} {mm}", flush=True)
+        X = torch.from_numpy(complex_normal((5, 2 * N), seed=9)).cuda()
+        tuning("farfield.multi_max", mm)
+        Y = P.muller_matvec(M, k0, k1, rho, X, precision=precision).cpu().numpy()
+        B = dense(mesh, k0, k1, rho)
+        Xn = X.cpu().numpy()
+        for r in range(5):
+            err = rel_blocks(Y[r], B @ Xn[r], N)
+            assert max(err.values()) <= TOL[precision], (case, r, err)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_muller_full_size_sampled_rows(P, precision):
+    """Icosphere L5 (10 242 vertices), k_ext = 10, k_int = 15, rho = 1.5; 40
+    seed-sampled rows of each block row against the oracle's matrix-free
+    Mueller rows."""
+    from oracle.operators import muller_matvec_rows
+    mesh = icosphere(5)
+    N = mesh.n_vertices
+    x = complex_normal(2 * N, seed=0)
+    rows = sample_rows(N, 40, seed=1)
+    print(f"muller ico5 sampled rows {precision}", flush=True)
+    r1, r2 = muller_matvec_rows(mesh, 10.0, 15.0, 1.5, x, rows)
+    y = gpu_muller(P, mesh, 10.0, 15.0, 1.5, x, precision)
+    e1 = np.linalg.norm(y[rows] - r1) / np.linalg.norm(r1)
+    e2 = np.linalg.norm(y[N + rows] - r2) / np.linalg.norm(r2)
+    print(precision, e1, e2)
+    assert e1 <= TOL[precision] and e2 <= TOL[precision], (e1, e2)

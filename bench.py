@@ -337,6 +337,24 @@ def main():
             gbytes = (2 * N) ** 2 * 8
             solve["dense_gemv"] = {"ms": gms / gn, "GB_per_s": gbytes / (gms / gn * 1e-3) / 1e9,
                                    "matrix_bytes": gbytes}
+            # the four formulations compared in the paper (OSRC, PMCHWT, Calderon,
+            # Mueller; strong form), FP32 assembled operator + refinement to the
+            # same tolerance, each operator assembled and factorised beforehand
+            forms = {}
+            for form in ("osrc", "pmchwt", "calderon", "muller"):
+                P.pmchwt_solve(M, K_EXT, K_INT, RHO, [[0, 0, 1]], 1e-6, precision="fp32", path=1,
+                               formulation=form, maxiter=1)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info, rc = P.pmchwt_solve(M, K_EXT, K_INT, RHO, [[0, 0, 1]], 1e-6,
+                                             precision="fp32", path=1, formulation=form)
+                torch.cuda.synchronize()
+                forms[form] = {"seconds": time.perf_counter() - t0, "rc": rc,
+                               "iterations": info[0]["iterations"],
+                               "outer_steps": info[0]["outer_steps"],
+                               "rel_residual": info[0]["rel_residual"]}
+                print(f"formulation {form}: {forms[form]}", file=sys.stderr, flush=True)
+            solve["formulations_fp32_dense"] = forms
         except P.BemError as e:
             solve = {"error": str(e)}
 

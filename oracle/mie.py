@@ -10,6 +10,7 @@ u and of (1/rho) du/dr at r = a.  With g = k1 rho0 / (k0 rho1):
           / [h_n'(k0a) j_n(k1a) - g h_n(k0a) j_n'(k1a)],
     B_n = [j_n(k0a) + A_n h_n(k0a)] / j_n(k1a).
 Far field (u_sca ~ F exp(i k0 r)/r): F(t) = (-i/k0) sum (2n+1) A_n P_n(cos t).
+Total field at a point: u_inc + u_sca outside, u_int inside.
 """
 from __future__ import annotations
 
@@ -57,3 +58,29 @@ def surface_traces(k0, k1, rho, cos_t, a=1.0):
     phi = (c * B * spherical_jn(n, k1 * a)) @ P
     psi = k0 * (c * (spherical_jn(n, k0 * a, True) + A * _h(n, k0 * a, True))) @ P
     return phi, psi
+
+
+def total_field(k0, k1, rho, points, a=1.0):
+    """Total field at points [m, 3] (sphere at the origin, wave along +z)."""
+    p = np.atleast_2d(np.asarray(points, float))
+    r = np.linalg.norm(p, axis=1)
+    ct = np.where(r > 0, p[:, 2] / np.where(r > 0, r, 1.0), 1.0)
+    A, B = coefficients(k0, k1, rho, a)
+    n = np.arange(len(A))
+    c = (1j ** n) * (2 * n + 1)
+    P = np.array([eval_legendre(m, ct) for m in n])          # [n, m]
+    out = np.empty(len(p), np.complex128)
+    ext = r >= a
+    for sel, inside in ((ext, False), (~ext, True)):
+        if not sel.any():
+            continue
+        rs = r[sel][None, :]
+        nn = n[:, None]
+        if inside:
+            out[sel] = np.sum(c[:, None] * B[:, None] * spherical_jn(nn, k1 * rs) * P[:, sel],
+                              axis=0)
+        else:
+            # the incident wave in closed form (its series needs ~k0 r terms)
+            us = np.sum(c[:, None] * A[:, None] * _h(nn, k0 * rs) * P[:, sel], axis=0)
+            out[sel] = np.exp(1j * k0 * p[sel, 2]) + us
+    return out

@@ -355,6 +355,22 @@ def main():
                                "rel_residual": info[0]["rel_residual"]}
                 print(f"formulation {form}: {forms[form]}", file=sys.stderr, flush=True)
             solve["formulations_fp32_dense"] = forms
+            # total field on the 101 x 101 grid of the paper's accuracy test (3 x 3
+            # square through the centre, x-y plane) from the last solution
+            g = np.linspace(-1.5, 1.5, 101)
+            GX, GY = np.meshgrid(g, g)
+            pts = torch.from_numpy(np.stack([GX.ravel(), GY.ravel(), np.zeros(GX.size)], 1)).cuda()
+            P.pmchwt_field(M, K_EXT, K_INT, RHO, [0, 0, 1.0], sol[0].contiguous(), pts)
+            P.profile_enable(True)
+            for _ in range(3):
+                P.pmchwt_field(M, K_EXT, K_INT, RHO, [0, 0, 1.0], sol[0].contiguous(), pts)
+            fms, fn = P.profile_read("field_eval")
+            wms, wn = P.profile_read("field_winding")
+            P.profile_enable(False)
+            fpairs = pts.shape[0] * 6 * T
+            solve["field_101x101"] = {"points": int(pts.shape[0]), "kernel_ms": fms / fn,
+                                      "winding_ms": wms / wn,
+                                      "roofline": RL.field_roofline(fpairs, fms / fn * 1e-3)}
         except P.BemError as e:
             solve = {"error": str(e)}
 

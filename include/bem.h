@@ -217,6 +217,32 @@ int pmchwt_solve(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int,
                  bem_solve_info *info, void *hip_stream);
 
 /*
+ * Total field at points off the surface from a solution x = [psi; phi] of
+ * the plane wave u_inc = exp(i k_ext d.p), by the representation formulas
+ * of Sec. 2.2 with the surface potentials of the total field:
+ *   outside every object:  u(p) = u_inc(p) + sum over all triangles of
+ *       int [ -G_0(p,y) psi(y) + (n_y . grad_y G_0(p,y)) phi(y) ] dy
+ *   inside object m:       u(p) = int over object m's triangles of
+ *       [ rho G_1(p,y) psi(y) - (n_y . grad_y G_1(p,y)) phi(y) ] dy
+ * (G_m = e^{ik_m r}/(4 pi r); inside, the Neumann trace is rho times the
+ * exterior one).  psi and phi are the P1 functions of the coefficients, the
+ * 6-point rule per triangle is used, FP64 throughout.  The rule is that of
+ * the matvec: accuracy drops for points closer to the surface than about
+ * one triangle; points on the surface are not supported.  A point is inside
+ * object m when the solid angle of m's surface at it (exact per flat
+ * triangle) exceeds 2 pi in magnitude.
+ *   direction  host float64 [3], unit;  solution  device bem_c64 [2N]
+ *   points     device float64 [n_points][3];  out  device bem_c64 [n_points]
+ *   region     device int32 [n_points] or NULL: 0 outside, m + 1 inside object m
+ * n_points == 0 returns BEM_OK without touching the pointers.  Synchronises
+ * the stream before returning.  Errors: BEM_E_INVAL (rho <= 0, bad k,
+ * direction not unit, NULL pointers, n_points < 0).
+ */
+int pmchwt_field(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
+                 const double *direction, const bem_c64 *solution, const double *points,
+                 int64_t n_points, bem_c64 *out, int32_t *region, void *hip_stream);
+
+/*
  * Far-field pattern F(xhat) of a solution: u_sca ~ F exp(i k r)/r with
  * F = 1/(4 pi) int exp(-i k xhat.y) [-psi - i k (xhat.n) phi] dy, from the
  * exterior representation formula (Sec. 2.2).

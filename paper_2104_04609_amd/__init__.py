@@ -2,19 +2,20 @@
 
 Python face of the C-ABI library ``libbem.so`` (declared in include/bem.h):
 mesh state, the matrix-free permuted PMCHWT (and Mueller) Galerkin matvec, the OSRC Pade
-preconditioner, plane-wave right-hand sides, the preconditioned GMRES solve
-and the far field.  All arithmetic runs in the library's HIP kernels.
+preconditioner, plane-wave right-hand sides, the preconditioned GMRES solve,
+the far field and the field off the surface.  All arithmetic runs in the library's HIP kernels.
 """
 from ._binding import (BEM_FP32, BEM_FP32_DENSE, BEM_FP64, BemError, Mesh, Server, SolveInfo,
                        SolveOpts,
-                       default_opts, far_field, lib, muller_matvec, osrc_apply, pmchwt_matvec,
+                       default_opts, far_field, lib, muller_matvec, osrc_apply, pmchwt_field, pmchwt_matvec,
                        pmchwt_rhs, pmchwt_solve, profile_enable, profile_read,
                        autotune, tune_cache_load, tune_clear, tune_get, tune_lookup, tune_set,
                        valu_rates)
 
 __all__ = ["BEM_FP32", "BEM_FP32_DENSE", "BEM_FP64", "BemError", "Mesh", "Server", "SolveInfo",
            "SolveOpts",
-           "default_opts", "far_field", "lib", "muller_matvec", "osrc_apply", "pmchwt_matvec",
+           "default_opts", "far_field", "lib", "muller_matvec", "osrc_apply", "pmchwt_field",
+           "pmchwt_matvec",
            "pmchwt_rhs", "pmchwt_solve", "profile_enable", "profile_read",
            "autotune", "tune_cache_load", "tune_clear", "tune_get", "tune_lookup", "tune_set",
            "valu_rates"]

@@ -110,6 +110,7 @@ lib.bem_solve_opts_default.restype = None
 lib.pmchwt_solve.argtypes = [_vp, c64, c64, ctypes.c_double, _vp, ctypes.c_int,
                              ctypes.c_double, ctypes.POINTER(SolveOpts), _vp, _vp, _vp]
 lib.bem_far_field.argtypes = [_vp, c64, _vp, _vp, ctypes.c_int, _vp, _vp]
+lib.pmchwt_field.argtypes = [_vp, c64, c64, ctypes.c_double, _vp, _vp, _vp, _i64, _vp, _vp, _vp]
 lib.bem_profile_enable.argtypes = [ctypes.c_int]
 lib.bem_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(_i64)]
@@ -304,6 +305,28 @@ def far_field(mesh: Mesh, k_ext, solution, dirs, stream=None) -> np.ndarray:
     _check(lib.bem_far_field(mesh.handle, _c(k_ext), _vp(solution.data_ptr()),
                              _np_ptr(d), d.shape[0], _np_ptr(out), _stream(stream)))
     return out
+
+
+def pmchwt_field(mesh: Mesh, k_ext, k_int, rho: float, direction, solution, points,
+                 stream=None):
+    """Total field at points off the surface (device float64 [n, 3]) for the
+    solution [psi; phi] of the plane wave along `direction`; returns
+    (field complex128 [n], region int32 [n]: 0 outside, m + 1 inside object m),
+    both on the device."""
+    import torch
+    if _dev_c128(solution, 2 * mesh.n_vertices, "solution") != 1:
+        raise ValueError("solution must hold one vector [psi; phi] of 2N entries")
+    if not (points.is_cuda and points.dtype == torch.float64 and points.is_contiguous()
+            and points.dim() == 2 and points.shape[1] == 3):
+        raise ValueError("points must be a contiguous float64 [n, 3] device tensor")
+    n = points.shape[0]
+    d = np.ascontiguousarray(direction, dtype=np.float64).reshape(3)
+    out = torch.empty(n, dtype=torch.complex128, device=points.device)
+    reg = torch.empty(n, dtype=torch.int32, device=points.device)
+    _check(lib.pmchwt_field(mesh.handle, _c(k_ext), _c(k_int), float(rho), _np_ptr(d),
+                            _vp(solution.data_ptr()), _vp(points.data_ptr()), n,
+                            _vp(out.data_ptr()), _vp(reg.data_ptr()), _stream(stream)))
+    return out, reg
 
 
 class Server:

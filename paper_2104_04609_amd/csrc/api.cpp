@@ -79,7 +79,7 @@ int64_t bem_mesh::device_bytes() const {
                 star_ptr.bytes() + star_idx.bytes() + near_pairs.bytes() + nf_rowptr.bytes() +
                 nf_col.bytes() + nf_cptr.bytes() + nf_contrib.bytes() + ss_tab.bytes() +
                 dyn64.bytes() + dyn32.bytes() + partial.bytes() + trirows.bytes() +
-                sym_items.bytes();
+                sym_items.bytes() + P_d.bytes();
     for (const auto &kv : near_cache) b += kv.second->vals.bytes();
     for (const auto &kv : dense_cache) b += kv.second->B.bytes();
     b += xs32.bytes();
@@ -252,6 +252,29 @@ int bem_far_field(const bem_mesh *mesh, bem_c64 k_ext, const bem_c64 *solution,
     bem::far_field_eval(const_cast<bem_mesh *>(mesh), make_double2(k_ext.re, k_ext.im),
                         (const double2 *)solution, dirs, n_dirs, (double2 *)out,
                         (hipStream_t)hip_stream);
+    return BEM_OK;
+    BEM_API_END
+}
+
+int pmchwt_field(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
+                 const double *direction, const bem_c64 *solution, const double *points,
+                 int64_t n_points, bem_c64 *out, int32_t *region, void *hip_stream) {
+    BEM_API_BEGIN
+    check_mesh(mesh);
+    check_k(k_ext, "k_ext");
+    check_k(k_int, "k_int");
+    if (!(rho > 0) || !std::isfinite(rho)) fail(BEM_E_INVAL, "rho must be positive");
+    if (n_points < 0) fail(BEM_E_INVAL, "n_points must be >= 0");
+    if (!direction) fail(BEM_E_INVAL, "direction is NULL");
+    const double *d = direction;
+    if (!(std::fabs(std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) - 1.0) < 1e-6))
+        fail(BEM_E_INVAL, "direction must be a unit vector");
+    if (n_points == 0) return BEM_OK;
+    if (!solution || !points || !out) fail(BEM_E_INVAL, "solution, points and out must be device pointers");
+    if ((n_points + 255) / 256 > INT32_MAX) fail(BEM_E_INVAL, "n_points too large");
+    bem::field_eval(const_cast<bem_mesh *>(mesh), make_double2(k_ext.re, k_ext.im),
+                    make_double2(k_int.re, k_int.im), rho, d, (const double2 *)solution, points,
+                    n_points, (double2 *)out, region, (hipStream_t)hip_stream);
     return BEM_OK;
     BEM_API_END
 }

@@ -168,6 +168,7 @@ struct bem_mesh {
     bem::DevBuf<int32_t> tri_d;     // [T][3]
     bem::DevBuf<int32_t> star_ptr;  // [N+1] vertex -> (tri*3 + a), ascending
     bem::DevBuf<int32_t> star_idx;
+    bem::DevBuf<double> P_d;        // [N][3] vertices (field evaluation; on first use)
 
     // near field: ordered pairs (tau, sigma) sharing >= 1 vertex
     int64_t n_near = 0;
@@ -268,6 +269,13 @@ void dense_apply(const DenseOperator &op, const double2 *x, double2 *y, int R,
 // Issue rates (lane operations per second over the device) of v_fma_f32,
 // v_sin_f32, v_cos_f32, v_rsq_f32 and v_fma_f64; rates[5].
 void valu_rates(double *rates, hipStream_t s);
+
+// field.hip: total field at n points (device [n][3]) for the solution x of
+// the plane wave along dir (host [3]); out device [n]; region device [n] or
+// NULL (0 outside, m + 1 inside object m)
+void field_eval(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dir,
+                const double2 *x, const double *pts, int64_t n, double2 *out, int32_t *region,
+                hipStream_t s);
 
 // mesh.cpp
 void mesh_build(bem_mesh *m, const double *P, int64_t N, const int32_t *tri,

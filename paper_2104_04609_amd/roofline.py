@@ -149,3 +149,22 @@ def pair_kernel_roofline(point_pairs: int, seconds_per_launch: float,
     return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "flop_eq_per_pair": fe,
             "point_pairs_per_s": pairs_s}
+
+
+# Field off the surface (FP64): unit = one (target point, trial quadrature
+# point) pair.  y - p, r^2 (8), r and 1/r, phase, decay and G (5), F = G (ikr - 1)
+# / r^2 (13), the single- and double-layer accumulations (16): 42 flops; the
+# sin/cos of the phase and the square root priced as in the FP64 matvec (23 +
+# 9 flops); per triangle (y - p).n (6) and the double-layer product (4) are
+# spread over its 6 points.
+FIELD_FLOPS_PER_PAIR = 42 + 10 / 6
+FIELD_TRANS_FLOPS_PER_PAIR = 23 + 9
+
+
+def field_roofline(point_pairs: int, seconds_per_launch: float) -> dict:
+    pairs_s = point_pairs / seconds_per_launch
+    fe = FIELD_FLOPS_PER_PAIR + FIELD_TRANS_FLOPS_PER_PAIR
+    achieved = pairs_s * fe / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "flop_eq_per_pair": fe,
+            "point_pairs_per_s": pairs_s}

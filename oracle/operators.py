@@ -97,6 +97,35 @@ def pmchwt_matrix(mesh, k_ext, k_int, rho, n_ss=4):
     return pmchwt_blocks(ops0, ops1, rho)
 
 
+def vertex_objects(mesh):
+    """Object of each vertex (objects are disjoint closed surfaces)."""
+    v = np.zeros(mesh.n_vertices, int)
+    if mesh.object_id is not None:
+        for o in range(mesh.n_objects()):
+            v[np.unique(mesh.triangles[mesh.object_id == o])] = o
+    return v
+
+
+def pmchwt_matrix_multi(mesh, k_ext, k_int, rho, n_ss=4):
+    """Permuted PMCHWT matrix with object m's own interior material
+    (k_int[m], rho[m]) (Sec. 2.7, several scatterers): the exterior operators
+    couple all objects, the interior operators of object m are taken at
+    k_int[m] and weighted by rho[m] and 1/rho[m]."""
+    ops0 = assemble(mesh, k_ext, interior=False, n_ss=n_ss)
+    B11, B12 = ops0["V"].copy(), -ops0["K"]
+    B21, B22 = ops0["Kp"].copy(), ops0["D"].copy()
+    vobj = vertex_objects(mesh)
+    for m in range(mesh.n_objects()):
+        ops1 = assemble(mesh, k_int[m], interior=True, n_ss=n_ss)
+        sel = vobj == m
+        mask = np.outer(sel, sel)
+        B11 = B11 + rho[m] * ops1["V"] * mask
+        B12 = B12 - ops1["K"] * mask
+        B21 = B21 + ops1["Kp"] * mask
+        B22 = B22 + ops1["D"] / rho[m] * mask
+    return np.block([[B11, B12], [B21, B22]])
+
+
 def muller_blocks(ops0, ops1, rho, M):
     """Combine exterior (ops0) and interior (ops1) operators and the P1 mass
     matrix M into the weak Mueller operator (I + A_0 - A^_1) of Sec. 2.2 on the

@@ -130,11 +130,14 @@ def object_radius(mesh, obj):
 
 
 class OSRC:
-    """diag(L_DtN, L_NtD) in strong form, one wavenumber k, per-vertex k_eps."""
+    """diag(L_DtN, L_NtD) in strong form, per-vertex wavenumber k (one value,
+    or that of each vertex's object) and per-vertex k_eps."""
 
     def __init__(self, mesh, k, k_eps, n_p=4, theta=np.pi / 3):
         self.N = mesh.n_vertices
-        self.k = complex(k)
+        # the operators are block diagonal by object: the factor ik of each
+        # object's L_DtN (1/ik of L_NtD) scales that object's rows
+        self.k = np.broadcast_to(np.asarray(k, np.complex128), (self.N,))
         keps = np.broadcast_to(np.asarray(k_eps, np.complex128), (self.N,))
         self.M = mass_matrix(mesh).tocsc()
         self.S = stiffness_matrix(mesh).tocsc()

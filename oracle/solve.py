@@ -17,35 +17,47 @@ from __future__ import annotations
 import numpy as np
 
 from .gmres import gmres
-from .operators import muller_matrix, pmchwt_matrix
+from .operators import muller_matrix, pmchwt_matrix, pmchwt_matrix_multi, vertex_objects
 from .osrc import OSRC, damped_wavenumber, object_radius
 from .rhs import plane_wave_rhs
 
 
 def osrc_keps_per_vertex(mesh, k, R=None):
-    """Per-vertex damped wavenumber: each object's k_eps from its own R."""
+    """Per-vertex damped wavenumber: each object's k_eps from its own R (and
+    its own k when k is a sequence with one entry per object)."""
     N = mesh.n_vertices
     keps = np.empty(N, np.complex128)
     nobj = mesh.n_objects()
+    ks = np.broadcast_to(np.asarray(k, np.complex128), (nobj,))
     for o in range(nobj):
         Ro = 0.1 * object_radius(mesh, o) if R is None else R
         if mesh.object_id is None:
             vid = np.arange(N)
         else:
             vid = np.unique(mesh.triangles[mesh.object_id == o])
-        keps[vid] = damped_wavenumber(k, Ro)
+        keps[vid] = damped_wavenumber(ks[o], Ro)
     return keps
 
 
 class PreconditionedSystem:
+    """k_int and rho: one material for every object, or sequences with one
+    entry per object (Sec. 2.7, several scatterers)."""
+
     def __init__(self, mesh, k_ext, k_int, rho, n_p=4, theta=np.pi / 3,
                  osrc_interior=True, R=None, B=None):
         self.mesh = mesh
         self.N = mesh.n_vertices
         self.k_ext, self.k_int, self.rho = k_ext, k_int, rho
-        self.B = pmchwt_matrix(mesh, k_ext, k_int, rho) if B is None else B
-        k = k_int if osrc_interior else k_ext
-        self.osrc = OSRC(mesh, k, osrc_keps_per_vertex(mesh, k, R), n_p, theta)
+        multi = np.ndim(k_int) > 0 or np.ndim(rho) > 0
+        if B is None:
+            B = (pmchwt_matrix_multi(mesh, k_ext, k_int, rho) if multi
+                 else pmchwt_matrix(mesh, k_ext, k_int, rho))
+        self.B = B
+        nobj = mesh.n_objects()
+        k_obj = np.broadcast_to(np.asarray(k_int if osrc_interior else k_ext, np.complex128),
+                                (nobj,))
+        k_vert = k_obj[vertex_objects(mesh)]
+        self.osrc = OSRC(mesh, k_vert, osrc_keps_per_vertex(mesh, k_obj, R), n_p, theta)
 
     def strong(self, y):
         N = self.N

@@ -163,3 +163,20 @@ def two_spheres(level: int = 4, offset: float = 1.5,
     oid = np.concatenate([np.zeros(a.n_triangles, np.int32),
                           np.ones(b.n_triangles, np.int32)])
     return Mesh(P, T, oid, name=f"two_spheres{level}", radius=float(radius))
+
+
+def four_spheres(level: int = 2, radius: float = 1.0) -> Mesh:
+    """Four disjoint spheres of the given radius with centres at
+    (+-3, +-1.5, 0) radii: the layout of the paper's multiple-scattering test
+    (radius 5 mm, centres (+-15, +-7.5, 0) mm) in units of the radius.
+    Objects 0..3 in the order (-3,-1.5), (3,-1.5), (-3,1.5), (3,1.5)."""
+    parts = [icosphere(level, radius, centre=(sx * 3.0 * radius, sy * 1.5 * radius, 0.0))
+             for sy in (-1, 1) for sx in (-1, 1)]
+    P, T, oid, off = [], [], [], 0
+    for o, p in enumerate(parts):
+        P.append(p.vertices)
+        T.append(p.triangles + off)
+        oid.append(np.full(p.n_triangles, o, np.int32))
+        off += p.n_vertices
+    return Mesh(np.vstack(P), np.vstack(T).astype(np.int32), np.concatenate(oid),
+                name=f"four_spheres{level}", radius=float(radius))

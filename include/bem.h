@@ -105,6 +105,21 @@ int pmchwt_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int,
                   int precision, void *hip_stream);
 
 /*
+ * pmchwt_matvec for objects of different materials (Sec. 2.7, multiple
+ * scatterers; the paper's four-sphere test mixes two materials): object m
+ * has interior wavenumber k_int[m] and density ratio rho[m] =
+ * rho_int,m / rho_ext, so its interior operators are V_m, K_m, K'_m, D_m at
+ * k_int[m], weighted by rho[m] and 1/rho[m]; the exterior operators couple
+ * all objects as before.
+ *   k_int, rho  host arrays [n_objects];  x, y as for pmchwt_matvec
+ * The near-field and assembled operators are cached per set of materials.
+ * Errors: as pmchwt_matvec, for every k_int[m] and rho[m].
+ */
+int pmchwt_matvec_multi(const bem_mesh *mesh, bem_c64 k_ext, const bem_c64 *k_int,
+                        const double *rho, const bem_c64 *x, bem_c64 *y, int n_rhs,
+                        int precision, void *hip_stream);
+
+/*
  * y = B_M x: the Galerkin Mueller operator I + A_0 - A^_1 (Sec. 2.2; every
  * interface m contributes I_m + A_{0,mm} - A^_m, exterior operators A_{0,mn}
  * couple the objects) on the permuted unknowns x = [psi; phi] of
@@ -241,6 +256,21 @@ int pmchwt_solve(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int,
 int pmchwt_field(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
                  const double *direction, const bem_c64 *solution, const double *points,
                  int64_t n_points, bem_c64 *out, int32_t *region, void *hip_stream);
+
+/*
+ * pmchwt_solve and pmchwt_field for objects of different materials (see
+ * pmchwt_matvec_multi): k_int, rho host arrays [n_objects].  The OSRC
+ * preconditioner of object m uses k_int[m] (osrc_interior) or k_ext, with
+ * that object's damped wavenumber.
+ */
+int pmchwt_solve_multi(const bem_mesh *mesh, bem_c64 k_ext, const bem_c64 *k_int,
+                       const double *rho, const double *directions, int n_waves, double tol,
+                       const bem_solve_opts *opts, bem_c64 *solution, bem_solve_info *info,
+                       void *hip_stream);
+int pmchwt_field_multi(const bem_mesh *mesh, bem_c64 k_ext, const bem_c64 *k_int,
+                       const double *rho, const double *direction, const bem_c64 *solution,
+                       const double *points, int64_t n_points, bem_c64 *out, int32_t *region,
+                       void *hip_stream);
 
 /*
  * Far-field pattern F(xhat) of a solution: u_sca ~ F exp(i k r)/r with

@@ -89,7 +89,7 @@ def layer_potentials(mesh, k, x, points, tri_mask=None):
 
 def field(mesh, k_ext, k_int, rho, x, d, points):
     """Total field at points for the solution x = [psi; phi] of the plane
-    wave exp(i k_ext d . p)."""
+    wave exp(i k_ext d . p).  k_int, rho: one material, or one per object."""
     points = np.atleast_2d(np.asarray(points, float))
     d = np.asarray(d, float)
     reg = regions(mesh, points)
@@ -99,9 +99,12 @@ def field(mesh, k_ext, k_int, rho, x, d, points):
     if ext.any():
         S, D = layer_potentials(mesh, k_ext, x, points[ext])
         u[ext] = np.exp(1j * k_ext * points[ext] @ d) - S + D
-    for m in range(mesh.n_objects()):
+    nobj = mesh.n_objects()
+    ks = np.broadcast_to(np.asarray(k_int, np.complex128), (nobj,))
+    rs = np.broadcast_to(np.asarray(rho, float), (nobj,))
+    for m in range(nobj):
         sel = reg == m + 1
         if sel.any():
-            S, D = layer_potentials(mesh, k_int, x, points[sel], tri_mask=obj == m)
-            u[sel] = rho * S - D
+            S, D = layer_potentials(mesh, ks[m], x, points[sel], tri_mask=obj == m)
+            u[sel] = rs[m] * S - D
     return u, reg

@@ -8,6 +8,7 @@ the far field and the field off the surface.  All arithmetic runs in the library
 from ._binding import (BEM_FP32, BEM_FP32_DENSE, BEM_FP64, BemError, Mesh, Server, SolveInfo,
                        SolveOpts,
                        default_opts, far_field, lib, muller_matvec, osrc_apply, pmchwt_field, pmchwt_matvec,
+                       pmchwt_matvec_multi, pmchwt_solve_multi,
                        pmchwt_rhs, pmchwt_solve, profile_enable, profile_read,
                        autotune, tune_cache_load, tune_clear, tune_get, tune_lookup, tune_set,
                        valu_rates)
@@ -15,7 +16,7 @@ from ._binding import (BEM_FP32, BEM_FP32_DENSE, BEM_FP64, BemError, Mesh, Serve
 __all__ = ["BEM_FP32", "BEM_FP32_DENSE", "BEM_FP64", "BemError", "Mesh", "Server", "SolveInfo",
            "SolveOpts",
            "default_opts", "far_field", "lib", "muller_matvec", "osrc_apply", "pmchwt_field",
-           "pmchwt_matvec",
+           "pmchwt_matvec", "pmchwt_matvec_multi", "pmchwt_solve_multi",
            "pmchwt_rhs", "pmchwt_solve", "profile_enable", "profile_read",
            "autotune", "tune_cache_load", "tune_clear", "tune_get", "tune_lookup", "tune_set",
            "valu_rates"]

@@ -100,6 +100,10 @@ lib.bem_mesh_info.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_i64)]
 lib.pmchwt_matvec.argtypes = [_vp, c64, c64, ctypes.c_double, _vp, _vp,
                               ctypes.c_int, ctypes.c_int, _vp]
+lib.pmchwt_matvec_multi.argtypes = [_vp, c64, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]
+lib.pmchwt_solve_multi.argtypes = [_vp, c64, _vp, _vp, _vp, ctypes.c_int, ctypes.c_double,
+                                   ctypes.POINTER(SolveOpts), _vp, _vp, _vp]
+lib.pmchwt_field_multi.argtypes = [_vp, c64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp]
 lib.muller_matvec.argtypes = [_vp, c64, c64, ctypes.c_double, _vp, _vp,
                               ctypes.c_int, ctypes.c_int, _vp]
 lib.osrc_apply.argtypes = [_vp, ctypes.c_int, ctypes.c_double, c64, c64, _vp, _vp,
@@ -191,6 +195,7 @@ class Mesh:
         self._h = h
         self.n_vertices = P.shape[0]
         self.n_triangles = T.shape[0]
+        self.n_objects = int(O.max()) + 1 if O is not None and O.size else 1
 
     @classmethod
     def from_inputs(cls, m):
@@ -230,6 +235,34 @@ def pmchwt_matvec(mesh: Mesh, k_ext, k_int, rho: float, x, y=None,
                   precision="fp64", stream=None):
     """y = B x (weak-form permuted PMCHWT); x, y complex128 [n_rhs, 2N] on device."""
     return _operator_matvec(lib.pmchwt_matvec, mesh, k_ext, k_int, rho, x, y, precision, stream)
+
+
+def _materials(mesh: Mesh, k_int, rho):
+    """Host arrays (c64 [n_objects], float64 [n_objects]) of per-object materials."""
+    k = np.atleast_1d(np.asarray(k_int, dtype=np.complex128))
+    r = np.atleast_1d(np.asarray(rho, dtype=np.float64))
+    n = mesh.n_objects
+    if k.shape != (n,) or r.shape != (n,):
+        raise ValueError(f"k_int and rho need one entry per object ({n})")
+    kc = (c64 * n)(*[c64(complex(v).real, complex(v).imag) for v in k])
+    rc = np.ascontiguousarray(r)
+    return kc, rc
+
+
+def pmchwt_matvec_multi(mesh: Mesh, k_ext, k_int, rho, x, y=None, precision="fp64",
+                        stream=None):
+    """y = B x with object m's interior material (k_int[m], rho[m])."""
+    import torch
+    kc, rc = _materials(mesh, k_int, rho)
+    n2 = 2 * mesh.n_vertices
+    n_rhs = _dev_c128(x, n2, "x")
+    if y is None:
+        y = torch.empty_like(x)
+    _dev_c128(y, n2, "y")
+    _check(lib.pmchwt_matvec_multi(mesh.handle, _c(k_ext), ctypes.cast(kc, _vp), _np_ptr(rc),
+                                   _vp(x.data_ptr()), _vp(y.data_ptr()), n_rhs,
+                                   _PREC[precision], _stream(stream)))
+    return y
 
 
 def muller_matvec(mesh: Mesh, k_ext, k_int, rho: float, x, y=None,
@@ -298,6 +331,29 @@ def pmchwt_solve(mesh: Mesh, k_ext, k_int, rho: float, directions, tol: float,
     return sol, [i.as_dict() for i in infos], rc
 
 
+def pmchwt_solve_multi(mesh: Mesh, k_ext, k_int, rho, directions, tol: float,
+                       opts: Optional[SolveOpts] = None, stream=None, **overrides):
+    """pmchwt_solve with object m's interior material (k_int[m], rho[m])."""
+    import torch
+    kc, rc = _materials(mesh, k_int, rho)
+    d = np.ascontiguousarray(np.atleast_2d(directions), dtype=np.float64)
+    o = default_opts() if opts is None else opts
+    for k, v in overrides.items():
+        if k == "precision":
+            v = _PREC[v]
+        if k == "formulation" and isinstance(v, str):
+            v = FORMULATIONS[v]
+        setattr(o, k, v)
+    sol = torch.empty((d.shape[0], 2 * mesh.n_vertices), dtype=torch.complex128,
+                      device="cuda")
+    infos = (SolveInfo * d.shape[0])()
+    rc_ = _check(lib.pmchwt_solve_multi(mesh.handle, _c(k_ext), ctypes.cast(kc, _vp),
+                                        _np_ptr(rc), _np_ptr(d), d.shape[0], float(tol),
+                                        ctypes.byref(o), _vp(sol.data_ptr()),
+                                        ctypes.cast(infos, _vp), _stream(stream)))
+    return sol, [i.as_dict() for i in infos], rc_
+
+
 def far_field(mesh: Mesh, k_ext, solution, dirs, stream=None) -> np.ndarray:
     d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
     _dev_c128(solution, 2 * mesh.n_vertices, "solution")
@@ -307,13 +363,17 @@ def far_field(mesh: Mesh, k_ext, solution, dirs, stream=None) -> np.ndarray:
     return out
 
 
-def pmchwt_field(mesh: Mesh, k_ext, k_int, rho: float, direction, solution, points,
+def pmchwt_field(mesh: Mesh, k_ext, k_int, rho, direction, solution, points,
                  stream=None):
     """Total field at points off the surface (device float64 [n, 3]) for the
     solution [psi; phi] of the plane wave along `direction`; returns
     (field complex128 [n], region int32 [n]: 0 outside, m + 1 inside object m),
-    both on the device."""
+    both on the device.  k_int and rho: one material for every object, or
+    sequences with one per object (pmchwt_field_multi)."""
     import torch
+    multi = np.ndim(k_int) > 0 or np.ndim(rho) > 0
+    if multi:
+        kc, rc = _materials(mesh, k_int, rho)
     if _dev_c128(solution, 2 * mesh.n_vertices, "solution") != 1:
         raise ValueError("solution must hold one vector [psi; phi] of 2N entries")
     if not (points.is_cuda and points.dtype == torch.float64 and points.is_contiguous()
@@ -323,9 +383,15 @@ def pmchwt_field(mesh: Mesh, k_ext, k_int, rho: float, direction, solution, poin
     d = np.ascontiguousarray(direction, dtype=np.float64).reshape(3)
     out = torch.empty(n, dtype=torch.complex128, device=points.device)
     reg = torch.empty(n, dtype=torch.int32, device=points.device)
-    _check(lib.pmchwt_field(mesh.handle, _c(k_ext), _c(k_int), float(rho), _np_ptr(d),
-                            _vp(solution.data_ptr()), _vp(points.data_ptr()), n,
-                            _vp(out.data_ptr()), _vp(reg.data_ptr()), _stream(stream)))
+    if multi:
+        _check(lib.pmchwt_field_multi(mesh.handle, _c(k_ext), ctypes.cast(kc, _vp), _np_ptr(rc),
+                                      _np_ptr(d), _vp(solution.data_ptr()),
+                                      _vp(points.data_ptr()), n, _vp(out.data_ptr()),
+                                      _vp(reg.data_ptr()), _stream(stream)))
+    else:
+        _check(lib.pmchwt_field(mesh.handle, _c(k_ext), _c(k_int), float(rho), _np_ptr(d),
+                                _vp(solution.data_ptr()), _vp(points.data_ptr()), n,
+                                _vp(out.data_ptr()), _vp(reg.data_ptr()), _stream(stream)))
     return out, reg
 
 

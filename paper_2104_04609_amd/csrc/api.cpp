@@ -155,9 +155,21 @@ int bem_mesh_info(const bem_mesh *m, int64_t *nv, int64_t *nt, int32_t *nobj,
 namespace {
 
 // Body of pmchwt_matvec (s1 = +1) and muller_matvec (s1 = -1); throws.
+bem::ObjMaterials materials(const bem_mesh *mesh, const bem_c64 *k_int, const double *rho) {
+    if (!k_int || !rho) fail(BEM_E_INVAL, "k_int and rho must not be NULL");
+    check_mesh(mesh);
+    bem::ObjMaterials om;
+    for (int o = 0; o < mesh->nobj; o++) {
+        om.k.push_back(make_double2(k_int[o].re, k_int[o].im));
+        om.rho.push_back(rho[o]);
+    }
+    bem::check_materials(mesh, om);
+    return om;
+}
+
 void operator_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
                      const bem_c64 *x, bem_c64 *y, int n_rhs, int precision,
-                     void *hip_stream, int s1) {
+                     void *hip_stream, int s1, const bem::ObjMaterials *om = nullptr) {
     check_mesh(mesh);
     check_k(k_ext, "k_ext");
     check_k(k_int, "k_int");
@@ -170,9 +182,9 @@ void operator_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double 
     bem_mesh *m = const_cast<bem_mesh *>(mesh);
     hipStream_t s = (hipStream_t)hip_stream;
     double2 k0 = make_double2(k_ext.re, k_ext.im), k1 = make_double2(k_int.re, k_int.im);
-    const bem::NearOperator &nf = bem::nearfield_get(m, k0, k1, rho, s, s1);
+    const bem::NearOperator &nf = bem::nearfield_get(m, k0, k1, rho, s, s1, om);
     if (precision == BEM_FP32_DENSE) {
-        const bem::DenseOperator &op = bem::dense_get(m, k0, k1, rho, s, s1);
+        const bem::DenseOperator &op = bem::dense_get(m, k0, k1, rho, s, s1, om);
         bem::dense_apply(op, (const double2 *)x, (double2 *)y, n_rhs, m->xs32, s);
         return;
     }
@@ -187,6 +199,16 @@ int pmchwt_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho
                   void *hip_stream) {
     BEM_API_BEGIN
     operator_matvec(mesh, k_ext, k_int, rho, x, y, n_rhs, precision, hip_stream, 1);
+    return BEM_OK;
+    BEM_API_END
+}
+
+int pmchwt_matvec_multi(const bem_mesh *mesh, bem_c64 k_ext, const bem_c64 *k_int,
+                        const double *rho, const bem_c64 *x, bem_c64 *y, int n_rhs,
+                        int precision, void *hip_stream) {
+    BEM_API_BEGIN
+    const bem::ObjMaterials om = materials(mesh, k_int, rho);
+    operator_matvec(mesh, k_ext, k_int[0], rho[0], x, y, n_rhs, precision, hip_stream, 1, &om);
     return BEM_OK;
     BEM_API_END
 }
@@ -256,9 +278,12 @@ int bem_far_field(const bem_mesh *mesh, bem_c64 k_ext, const bem_c64 *solution,
     BEM_API_END
 }
 
-int pmchwt_field(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
-                 const double *direction, const bem_c64 *solution, const double *points,
-                 int64_t n_points, bem_c64 *out, int32_t *region, void *hip_stream) {
+namespace {
+
+int field_entry(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
+                const bem::ObjMaterials *om, const double *direction, const bem_c64 *solution,
+                const double *points, int64_t n_points, bem_c64 *out, int32_t *region,
+                void *hip_stream) {
     BEM_API_BEGIN
     check_mesh(mesh);
     check_k(k_ext, "k_ext");
@@ -274,8 +299,28 @@ int pmchwt_field(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
     if ((n_points + 255) / 256 > INT32_MAX) fail(BEM_E_INVAL, "n_points too large");
     bem::field_eval(const_cast<bem_mesh *>(mesh), make_double2(k_ext.re, k_ext.im),
                     make_double2(k_int.re, k_int.im), rho, d, (const double2 *)solution, points,
-                    n_points, (double2 *)out, region, (hipStream_t)hip_stream);
+                    n_points, (double2 *)out, region, (hipStream_t)hip_stream, om);
     return BEM_OK;
+    BEM_API_END
+}
+
+}   // namespace
+
+int pmchwt_field(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
+                 const double *direction, const bem_c64 *solution, const double *points,
+                 int64_t n_points, bem_c64 *out, int32_t *region, void *hip_stream) {
+    return field_entry(mesh, k_ext, k_int, rho, nullptr, direction, solution, points, n_points,
+                       out, region, hip_stream);
+}
+
+int pmchwt_field_multi(const bem_mesh *mesh, bem_c64 k_ext, const bem_c64 *k_int,
+                       const double *rho, const double *direction, const bem_c64 *solution,
+                       const double *points, int64_t n_points, bem_c64 *out, int32_t *region,
+                       void *hip_stream) {
+    BEM_API_BEGIN
+    const bem::ObjMaterials om = materials(mesh, k_int, rho);
+    return field_entry(mesh, k_ext, k_int[0], rho[0], &om, direction, solution, points,
+                       n_points, out, region, hip_stream);
     BEM_API_END
 }
 

@@ -104,15 +104,32 @@ constexpr int ROW_STRIDE = 12;
 struct NearKey {
     double k0r, k0i, k1r, k1i, rho;
     int s1;
+    std::vector<double> om;   // per object (Re k_m, Im k_m, rho_m) when they differ, else empty
     bool operator<(const NearKey &o) const {
-        return std::tie(k0r, k0i, k1r, k1i, rho, s1) <
-               std::tie(o.k0r, o.k0i, o.k1r, o.k1i, o.rho, o.s1);
+        return std::tie(k0r, k0i, k1r, k1i, rho, s1, om) <
+               std::tie(o.k0r, o.k0i, o.k1r, o.k1i, o.rho, o.s1, o.om);
     }
 };
 
 struct NearOperator {
     DevBuf<double> vals;   // [4 blocks][nnz] complex (interleaved): B11 B12 B21 B22
     int s1 = 1;            // operator the values belong to (NearKey::s1)
+    // interior material of each object, and the wavenumber that decides the
+    // pair kernels' variant (largest |Re k_m|; complex when any k_m is)
+    std::vector<double2> k1o;
+    std::vector<double> rhoo;
+    double2 k1_plan{0.0, 0.0};
+    // per-object interior coefficients of the pair kernels (several objects;
+    // filled on first use)
+    mutable DevBuf<float> itab32;
+    mutable DevBuf<double> itab64;
+};
+
+// Interior materials of the objects when they differ (Sec. 2.7, several
+// scatterers): k_m and rho_m = rho_int,m / rho_ext per object.
+struct ObjMaterials {
+    std::vector<double2> k;
+    std::vector<double> rho;
 };
 
 // Assembled complex64 operator [2N][2N] (row-major).
@@ -126,8 +143,10 @@ struct OsrcKey {
     int np;
     double theta, kr, ki;
     std::vector<double> keps;   // (re, im) of k_eps per object
+    std::vector<double> kobj;   // (re, im) of k per object when they differ, else empty
     bool operator<(const OsrcKey &o) const {
-        return std::tie(np, theta, kr, ki, keps) < std::tie(o.np, o.theta, o.kr, o.ki, o.keps);
+        return std::tie(np, theta, kr, ki, keps, kobj) <
+               std::tie(o.np, o.theta, o.kr, o.ki, o.keps, o.kobj);
     }
 };
 
@@ -244,17 +263,23 @@ int64_t farfield_scratch_bytes(const bem_mesh *m, int precision, double2 k0, dou
 // Mueller operator on the same unknowns (interior terms negated, P1 mass
 // matrix added to the two off-diagonal blocks).  The pair kernels read s1
 // from the near operator they are given.
+// om: per-object materials (nullptr: every object has k1, rho).
 std::unique_ptr<NearOperator> nearfield_build(bem_mesh *m, double2 k0, double2 k1,
-                                              double rho, hipStream_t s, int s1);
+                                              double rho, hipStream_t s, int s1,
+                                              const ObjMaterials *om = nullptr);
 const NearOperator &nearfield_get(bem_mesh *m, double2 k0, double2 k1, double rho,
-                                  hipStream_t s, int s1 = 1);
+                                  hipStream_t s, int s1 = 1, const ObjMaterials *om = nullptr);
+// cache key of (k0, k1, rho, s1, om); materials that are all equal reduce to
+// the uniform key
+NearKey near_key(const bem_mesh *m, double2 k0, double2 k1, double rho, int s1,
+                 const ObjMaterials *om);
 // dense.hip
 int64_t dense_bytes(const bem_mesh *m);
 int64_t dense_assembly_scratch_bytes(const bem_mesh *m);
 std::unique_ptr<DenseOperator> dense_assemble(bem_mesh *m, const NearOperator &nf, double2 k0,
                                               double2 k1, double rho, hipStream_t s);
 const DenseOperator &dense_get(bem_mesh *m, double2 k0, double2 k1, double rho, hipStream_t s,
-                               int s1 = 1);
+                               int s1 = 1, const ObjMaterials *om = nullptr);
 // y_r = B x_r, r < R (x, y RHS-major [R][2N]): multi-vector product reading B
 // once per 8 right-hand sides
 void dense_gemv(const DenseOperator &op, const double2 *x, double2 *y, int R, DevBuf<float2> &xs,
@@ -275,7 +300,7 @@ void valu_rates(double *rates, hipStream_t s);
 // NULL (0 outside, m + 1 inside object m)
 void field_eval(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dir,
                 const double2 *x, const double *pts, int64_t n, double2 *out, int32_t *region,
-                hipStream_t s);
+                hipStream_t s, const ObjMaterials *om = nullptr);
 
 // mesh.cpp
 void mesh_build(bem_mesh *m, const double *P, int64_t N, const int32_t *tri,
@@ -286,8 +311,10 @@ void rhs_project(bem_mesh *m, double2 k0, const double *dirs, int n, double2 *f,
 void far_field_eval(bem_mesh *m, double2 k0, const double2 *x, const double *dirs,
                     int n, double2 *out, hipStream_t s);
 // osrc.cpp / osrc.hip
+// k_obj: wavenumber of each object when they differ (nullptr: k for all)
 OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
-                    const std::vector<double2> &keps_obj, hipStream_t s);
+                    const std::vector<double2> &keps_obj, hipStream_t s,
+                    const std::vector<double2> *k_obj = nullptr);
 // R right-hand sides, [R][2N] contiguous each
 void osrc_apply_strong(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y, int R,
                        hipStream_t s);
@@ -302,9 +329,12 @@ void osrc_prepare(bem_mesh *m);
 int64_t osrc_state_bytes(bem_mesh *m, int np, int R);
 // solve.cpp
 // Validated OSRC-preconditioned solve (the body of pmchwt_solve); throws Error.
+// om: per-object interior materials (nullptr: k1, rho for every object)
 int solve_run(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dirs,
               int n_waves, double tol, const bem_solve_opts &o, double2 *solution,
-              bem_solve_info *info, hipStream_t s);
+              bem_solve_info *info, hipStream_t s, const ObjMaterials *om = nullptr);
+// one valid (k_m, rho_m) per object, else throws BEM_E_INVAL
+void check_materials(const bem_mesh *m, const ObjMaterials &om);
 void solve_check(const bem_mesh *m, double2 k0, double2 k1, double rho, const double *dirs,
                  int n_waves, double tol, const bem_solve_opts &o);
 // Upper bound of the device memory one solve adds to a mesh handle with no

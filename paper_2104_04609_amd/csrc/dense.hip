@@ -14,6 +14,7 @@
 // Each separated triangle pair is evaluated three times (once per trial
 // vertex), about three matrix-free matvecs of work per assembly.
 #include <cmath>
+#include <cstring>
 
 #include "bem_internal.h"
 
@@ -32,9 +33,14 @@ __host__ __device__ constexpr double qb(int i, int a) {
 
 constexpr int JT = 512;   // trial vertices per assembly tile
 
-struct DCoef {
-    float krev0, krev1, k0r, k0i, k1r, k1i, kdec0, kdec1, rho, irho, n0r, n0i, n10r, n10i;
+// interior coefficients of one object (several objects: a per-object table)
+struct DInt {
+    float krev1, k1r, k1i, kdec1, rho, irho, n10r, n10i;
     float ns1;   // -s_1 (interior sign: +1 PMCHWT, -1 Mueller)
+};
+struct DCoef {
+    float krev0, k0r, k0i, kdec0, n0r, n0i;
+    DInt in;
 };
 
 __device__ __forceinline__ void sincos_rev(float t, float &s, float &c) {
@@ -48,7 +54,7 @@ __global__ __launch_bounds__(256) void dense_pairs_kernel(
     const float *__restrict__ geo, const double *__restrict__ tst,
     const int32_t *__restrict__ tobj, const int32_t *__restrict__ tri,
     const int32_t *__restrict__ star_ptr, const int32_t *__restrict__ star_idx, int T, int j0,
-    int64_t N, DCoef cf, float2 *__restrict__ Q) {
+    int64_t N, DCoef cf, const DInt *__restrict__ itab, float2 *__restrict__ Q) {
     const int tau = blockIdx.x * 256 + threadIdx.x;
     const int jl = blockIdx.y;
     const int64_t j = j0 + jl;
@@ -80,6 +86,8 @@ __global__ __launch_bounds__(256) void dense_pairs_kernel(
         const float nsx = h[18], nsy = h[19], nsz = h[20], cs = h[21];
         const float as = (float)tst[TST_STRIDE * s];
         const float m1 = MULTI ? (tobj[s] == ot ? 1.f : 0.f) : 1.f;
+        // sigma is the same for the whole block: its object's interior part
+        const DInt c1 = MULTI ? itab[__builtin_amdgcn_readfirstlane(tobj[s])] : cf.in;
         const float nn = ntx * nsx + nty * nsy + ntz * nsz;
         // factor of the G_N term taken out of the q sum: k_0^2 (n_x . n_y)
         const float gnr = cf.n0r * nn, gni = cf.n0i * nn;
@@ -105,7 +113,7 @@ __global__ __launch_bounds__(256) void dense_pairs_kernel(
                 // E_m = e^{i k_m r} (interior term masked across objects)
                 float E0r, E0i, E1r, E1i;
                 sincos_rev(r * cf.krev0, E0i, E0r);
-                sincos_rev(r * cf.krev1, E1i, E1r);
+                sincos_rev(r * c1.krev1, E1i, E1r);
                 if (CK0) {
                     const float d0 = __builtin_amdgcn_exp2f(r * cf.kdec0);
                     E0r *= d0;
@@ -113,32 +121,32 @@ __global__ __launch_bounds__(256) void dense_pairs_kernel(
                 }
                 if (CK1 || MULTI) {
                     float d1 = m1;
-                    if (CK1) d1 *= __builtin_amdgcn_exp2f(r * cf.kdec1);
+                    if (CK1) d1 *= __builtin_amdgcn_exp2f(r * c1.kdec1);
                     E1r *= d1;
                     E1i *= d1;
                 }
                 const float G0r = E0r * ri, G0i = E0i * ri, G1r = E1r * ri, G1i = E1i * ri;
                 // F r^2 = i (k_0 E_0 + k_1 E_1) - G_0 - G_1
-                float Fr = __builtin_fmaf(cf.ns1, G1r, -G0r), Fi = __builtin_fmaf(cf.ns1, G1i, -G0i);
+                float Fr = __builtin_fmaf(c1.ns1, G1r, -G0r), Fi = __builtin_fmaf(c1.ns1, G1i, -G0i);
                 Fr = __builtin_fmaf(-cf.k0r, E0i, Fr);
                 Fi = __builtin_fmaf(cf.k0r, E0r, Fi);
-                Fr = __builtin_fmaf(-cf.k1r, E1i, Fr);
-                Fi = __builtin_fmaf(cf.k1r, E1r, Fi);
+                Fr = __builtin_fmaf(-c1.k1r, E1i, Fr);
+                Fi = __builtin_fmaf(c1.k1r, E1r, Fi);
                 if (CK0) {
                     Fr = __builtin_fmaf(-cf.k0i, E0r, Fr);
                     Fi = __builtin_fmaf(-cf.k0i, E0i, Fi);
                 }
                 if (CK1) {
-                    Fr = __builtin_fmaf(-cf.k1i, E1r, Fr);
-                    Fi = __builtin_fmaf(-cf.k1i, E1i, Fi);
+                    Fr = __builtin_fmaf(-c1.k1i, E1r, Fr);
+                    Fi = __builtin_fmaf(-c1.k1i, E1i, Fi);
                 }
                 const float ri2 = ri * ri;
                 Fr *= ri2;
                 Fi *= ri2;
                 const float t = tq[q];
                 // V-row psi column: G_V t
-                vr = __builtin_fmaf(__builtin_fmaf(cf.rho, G1r, G0r), t, vr);
-                vi = __builtin_fmaf(__builtin_fmaf(cf.rho, G1i, G0i), t, vi);
+                vr = __builtin_fmaf(__builtin_fmaf(c1.rho, G1r, G0r), t, vr);
+                vi = __builtin_fmaf(__builtin_fmaf(c1.rho, G1i, G0i), t, vi);
                 // V-row phi column: -(y - x).n_y F t (the factor after the q sum)
                 fr = __builtin_fmaf(Fr, t, fr);
                 fi = __builtin_fmaf(Fi, t, fi);
@@ -146,16 +154,16 @@ __global__ __launch_bounds__(256) void dense_pairs_kernel(
                 kr = __builtin_fmaf(Fr, tx[q], kr);
                 ki = __builtin_fmaf(Fi, tx[q], ki);
                 // D-row phi column: -k_0^2 (n_x.n_y) (G_0 + k_1^2/(rho k_0^2) G_1) t
-                float Nr = __builtin_fmaf(cf.n10r, G1r, G0r), Ni = __builtin_fmaf(cf.n10r, G1i, G0i);
+                float Nr = __builtin_fmaf(c1.n10r, G1r, G0r), Ni = __builtin_fmaf(c1.n10r, G1i, G0i);
                 if (CK0 || CK1) {
-                    Nr = __builtin_fmaf(-cf.n10i, G1i, Nr);
-                    Ni = __builtin_fmaf(cf.n10i, G1r, Ni);
+                    Nr = __builtin_fmaf(-c1.n10i, G1i, Nr);
+                    Ni = __builtin_fmaf(c1.n10i, G1r, Ni);
                 }
                 nr = __builtin_fmaf(Nr, t, nr);
                 ni = __builtin_fmaf(Ni, t, ni);
                 const float ww = (float)(qw(p) * qw(q));
-                gwr = __builtin_fmaf(ww, __builtin_fmaf(cf.irho, G1r, G0r), gwr);
-                gwi = __builtin_fmaf(ww, __builtin_fmaf(cf.irho, G1i, G0i), gwi);
+                gwr = __builtin_fmaf(ww, __builtin_fmaf(c1.irho, G1r, G0r), gwr);
+                gwi = __builtin_fmaf(ww, __builtin_fmaf(c1.irho, G1i, G0i), gwi);
             }
             ar[0][p] = vr;
             ai[0][p] = vi;
@@ -512,22 +520,16 @@ __global__ __launch_bounds__(256) void to_c64_kernel(const double2 *__restrict__
 
 // s1 = -1 negates the interior terms (Mueller operator, Sec. 2.2): folded
 // into rho, 1/rho, k_1^2/(rho k_0^2), k_1 (only in F) and ns1.
-DCoef make_dcoef(double2 k0, double2 k1, double rho, int s1) {
+DInt make_dint(double2 k0, double2 k1, double rho, int s1) {
     const double inv2pi = 0.15915494309189533576888376337251;
     const double log2e = 1.4426950408889634073599246810019;
-    DCoef c;
-    c.krev0 = (float)(k0.x * inv2pi);
+    DInt c;
     c.krev1 = (float)(k1.x * inv2pi);
-    c.k0r = (float)k0.x;
-    c.k0i = (float)k0.y;
     c.k1r = (float)k1.x;
     c.k1i = (float)k1.y;
-    c.kdec0 = (float)(-k0.y * log2e);
     c.kdec1 = (float)(-k1.y * log2e);
     c.rho = (float)rho;
     c.irho = (float)(1.0 / rho);
-    c.n0r = (float)(k0.x * k0.x - k0.y * k0.y);
-    c.n0i = (float)(2.0 * k0.x * k0.y);
     // k_1^2 / (rho k_0^2); k_0 != 0 is checked at the entry points
     const double n0r = k0.x * k0.x - k0.y * k0.y, n0i = 2.0 * k0.x * k0.y;
     const double n1r = (k1.x * k1.x - k1.y * k1.y) / rho, n1i = 2.0 * k1.x * k1.y / rho;
@@ -546,11 +548,26 @@ DCoef make_dcoef(double2 k0, double2 k1, double rho, int s1) {
     return c;
 }
 
+DCoef make_dcoef(double2 k0, const NearOperator &nf) {
+    const double inv2pi = 0.15915494309189533576888376337251;
+    const double log2e = 1.4426950408889634073599246810019;
+    DCoef c;
+    c.krev0 = (float)(k0.x * inv2pi);
+    c.k0r = (float)k0.x;
+    c.k0i = (float)k0.y;
+    c.kdec0 = (float)(-k0.y * log2e);
+    c.n0r = (float)(k0.x * k0.x - k0.y * k0.y);
+    c.n0i = (float)(2.0 * k0.x * k0.y);
+    c.in = make_dint(k0, nf.k1o[0], nf.rhoo[0], nf.s1);
+    return c;
+}
+
 template <bool A, bool B, bool C>
-void launch_pairs(dim3 grid, hipStream_t s, bem_mesh *m, int j0, DCoef cf, float2 *Q) {
+void launch_pairs(dim3 grid, hipStream_t s, bem_mesh *m, int j0, DCoef cf, const DInt *itab,
+                  float2 *Q) {
     hipLaunchKernelGGL((dense_pairs_kernel<A, B, C>), grid, dim3(256), 0, s, m->geo32.p, m->tst.p,
                        m->tobj_d.p, m->tri_d.p, m->star_ptr.p, m->star_idx.p, (int)m->T, j0,
-                       m->N, cf, Q);
+                       m->N, cf, itab, Q);
 }
 
 }   // namespace
@@ -568,21 +585,30 @@ std::unique_ptr<DenseOperator> dense_assemble(bem_mesh *m, const NearOperator &n
     op->T = m->T;
     op->B.alloc((size_t)(n2 * n2));
     DevBuf<float2> Q((size_t)m->T * JT * 12);
-    const DCoef cf = make_dcoef(k0, k1, rho, nf.s1);
-    const int code = (k0.y != 0 ? 4 : 0) | (k1.y != 0 ? 2 : 0) | (m->nobj > 1 ? 1 : 0);
+    const DCoef cf = make_dcoef(k0, nf);
+    DevBuf<float> itab;   // per-object interior parts (several objects)
+    if (m->nobj > 1) {
+        std::vector<float> h((size_t)m->nobj * (sizeof(DInt) / sizeof(float)));
+        for (int o = 0; o < m->nobj; o++) {
+            const DInt c = make_dint(k0, nf.k1o[o], nf.rhoo[o], nf.s1);
+            std::memcpy(h.data() + (size_t)o * (sizeof(DInt) / sizeof(float)), &c, sizeof(c));
+        }
+        itab.upload(h);
+    }
+    const int code = (k0.y != 0 ? 4 : 0) | (nf.k1_plan.y != 0 ? 2 : 0) | (m->nobj > 1 ? 1 : 0);
     Timer tm("dense_assemble", s);
     for (int64_t j0 = 0; j0 < N; j0 += JT) {
         const int jt = (int)std::min<int64_t>(JT, N - j0);
         dim3 grid((unsigned)((m->T + 255) / 256), jt);
         switch (code) {
-        case 0: launch_pairs<false, false, false>(grid, s, m, (int)j0, cf, Q.p); break;
-        case 1: launch_pairs<false, false, true>(grid, s, m, (int)j0, cf, Q.p); break;
-        case 2: launch_pairs<false, true, false>(grid, s, m, (int)j0, cf, Q.p); break;
-        case 3: launch_pairs<false, true, true>(grid, s, m, (int)j0, cf, Q.p); break;
-        case 4: launch_pairs<true, false, false>(grid, s, m, (int)j0, cf, Q.p); break;
-        case 5: launch_pairs<true, false, true>(grid, s, m, (int)j0, cf, Q.p); break;
-        case 6: launch_pairs<true, true, false>(grid, s, m, (int)j0, cf, Q.p); break;
-        default: launch_pairs<true, true, true>(grid, s, m, (int)j0, cf, Q.p); break;
+        case 0: launch_pairs<false, false, false>(grid, s, m, (int)j0, cf, (const DInt *)itab.p, Q.p); break;
+        case 1: launch_pairs<false, false, true>(grid, s, m, (int)j0, cf, (const DInt *)itab.p, Q.p); break;
+        case 2: launch_pairs<false, true, false>(grid, s, m, (int)j0, cf, (const DInt *)itab.p, Q.p); break;
+        case 3: launch_pairs<false, true, true>(grid, s, m, (int)j0, cf, (const DInt *)itab.p, Q.p); break;
+        case 4: launch_pairs<true, false, false>(grid, s, m, (int)j0, cf, (const DInt *)itab.p, Q.p); break;
+        case 5: launch_pairs<true, false, true>(grid, s, m, (int)j0, cf, (const DInt *)itab.p, Q.p); break;
+        case 6: launch_pairs<true, true, false>(grid, s, m, (int)j0, cf, (const DInt *)itab.p, Q.p); break;
+        default: launch_pairs<true, true, true>(grid, s, m, (int)j0, cf, (const DInt *)itab.p, Q.p); break;
         }
         BEM_LAUNCH_CHECK();
         hipLaunchKernelGGL(dense_gather_kernel, dim3((unsigned)N, (jt + 255) / 256), dim3(256), 0,
@@ -696,11 +722,11 @@ void dense_gemm(const DenseOperator &op, const double2 *x, double2 *y, int R, hi
 }
 
 const DenseOperator &dense_get(bem_mesh *m, double2 k0, double2 k1, double rho, hipStream_t s,
-                               int s1) {
-    NearKey key{k0.x, k0.y, k1.x, k1.y, rho, s1};
+                               int s1, const ObjMaterials *om) {
+    const NearKey key = near_key(m, k0, k1, rho, s1, om);
     auto it = m->dense_cache.find(key);
     if (it != m->dense_cache.end()) return *it->second;
-    const NearOperator &nf = nearfield_get(m, k0, k1, rho, s, s1);
+    const NearOperator &nf = nearfield_get(m, k0, k1, rho, s, s1, om);
     // one resident dense operator per mesh unless memory allows more
     size_t free_b = 0, total_b = 0;
     BEM_HIP(hipMemGetInfo(&free_b, &total_b));

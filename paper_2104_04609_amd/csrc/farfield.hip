@@ -30,6 +30,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstring>
 #include <functional>
 #include <map>
 #include <mutex>
@@ -148,16 +149,40 @@ __device__ __forceinline__ double fmac(double a, double b, double c) {
     return __builtin_fma(a, b, c);
 }
 
-// Wavenumber-dependent coefficients of one launch.
-template <class R> struct Coef {
-    R krev0, krev1;          // Re k / (2 pi)
-    R k0r, k0i, k1r, k1i;    // k
-    R kdec0, kdec1;          // -Im k * log2(e)
+// Interior coefficients of one object (material k_1, rho of that object).
+constexpr int INT_COEFS = 9;
+template <class R> struct Int {
+    R krev1;                 // Re k_1 / (2 pi)
+    R k1r, k1i;              // k_1
+    R kdec1;                 // -Im k_1 * log2(e)
     R rho, irho;
-    R n0r, n0i;              // k_0^2
     R n10r, n10i;            // k_1^2 / (rho k_0^2)
     R ns1;                   // -s_1
 };
+
+// Wavenumber-dependent coefficients of one launch.  Kernels for several
+// objects take the interior part of each trial triangle's object from a
+// per-object table instead of `in`.
+template <class R> struct Coef {
+    R krev0;                 // Re k_0 / (2 pi)
+    R k0r, k0i;              // k_0
+    R kdec0;                 // -Im k_0 * log2(e)
+    R n0r, n0i;              // k_0^2
+    Int<R> in;
+};
+
+// interior coefficients for a trial triangle of object `obj` (uniform over
+// the wave: every lane reads the same trial triangle)
+template <bool MULTI, class R>
+__device__ __forceinline__ Int<R> interior(const Coef<R> &cf, const Int<R> *__restrict__ itab,
+                                           R obj) {
+    if constexpr (MULTI) {
+        const int ob = __builtin_amdgcn_readfirstlane((int)obj);
+        return itab[ob];
+    } else {
+        return cf.in;
+    }
+}
 
 // ------------------------------------------------------------ source gather
 template <class R>
@@ -211,7 +236,8 @@ __global__ __launch_bounds__(FF_BLOCK) __attribute__((amdgpu_waves_per_eu(ff_wav
 void farfield_kernel(
     const R *__restrict__ geo, const R *__restrict__ dyn,
     const int32_t *__restrict__ tobj, const int32_t *__restrict__ tri, int T,
-    int split_len, Coef<R> cf, double *__restrict__ partial) {
+    int split_len, Coef<R> cf, const Int<R> *__restrict__ itab,
+    double *__restrict__ partial) {
     using MT = Math<R>;
     constexpr bool F32 = std::is_same<R, float>::value;
     __shared__ R tile[FF_TILE * SRC];
@@ -311,6 +337,7 @@ void farfield_kernel(
             }
             const R nsx = src[18], nsy = src[19], nsz = src[20], cs = src[21];
             const R m1 = MULTI ? (src[GEO_STRIDE + DYN_STRIDE] == ot ? (R)1 : (R)0) : (R)1;
+            const Int<R> c1 = interior<MULTI>(cf, itab, src[GEO_STRIDE + DYN_STRIDE]);
             const R nn = ntx * nsx + nty * nsy + ntz * nsz;
             // factor of the G_N term pulled out of the j sum: k_0^2 (n_x . n_y)
             const R gnr = cf.n0r * nn, gni = cf.n0i * nn;
@@ -346,10 +373,10 @@ void farfield_kernel(
                     R E0r, E0i, E1r, E1i;
                     if constexpr (F32) {
                         MT::template sincos_rev<FR>(r * cf.krev0, E0i, E0r);
-                        MT::template sincos_rev<FR>(r * cf.krev1, E1i, E1r);
+                        MT::template sincos_rev<FR>(r * c1.krev1, E1i, E1r);
                     } else {
                         MT::sincos_tab(r * cf.krev0, E0i, E0r, etab);
-                        MT::sincos_tab(r * cf.krev1, E1i, E1r, etab);
+                        MT::sincos_tab(r * c1.krev1, E1i, E1r, etab);
                     }
                     if (CK0) {
                         const R d0 = MT::exp2(r * cf.kdec0);
@@ -358,7 +385,7 @@ void farfield_kernel(
                     }
                     if (CK1 || MULTI) {
                         R d1 = m1;
-                        if (CK1) d1 *= MT::exp2(r * cf.kdec1);
+                        if (CK1) d1 *= MT::exp2(r * c1.kdec1);
                         E1r *= d1;
                         E1i *= d1;
                     }
@@ -366,29 +393,29 @@ void farfield_kernel(
                     const R G1r = E1r * ri, G1i = E1i * ri;
                     // F r^2 = G_0 (i k_0 r - 1) + G_1 (i k_1 r - 1)
                     //       = i (k_0 E_0 + k_1 E_1) - (G_0 + G_1)       (r / r = 1)
-                    R Fr = fmac(cf.ns1, G1r, -G0r), Fi = fmac(cf.ns1, G1i, -G0i);
+                    R Fr = fmac(c1.ns1, G1r, -G0r), Fi = fmac(c1.ns1, G1i, -G0i);
                     Fr = fmac(-cf.k0r, E0i, Fr);
                     Fi = fmac(cf.k0r, E0r, Fi);
-                    Fr = fmac(-cf.k1r, E1i, Fr);
-                    Fi = fmac(cf.k1r, E1r, Fi);
+                    Fr = fmac(-c1.k1r, E1i, Fr);
+                    Fi = fmac(c1.k1r, E1r, Fi);
                     if (CK0) {
                         Fr = fmac(-cf.k0i, E0r, Fr);
                         Fi = fmac(-cf.k0i, E0i, Fi);
                     }
                     if (CK1) {
-                        Fr = fmac(-cf.k1i, E1r, Fr);
-                        Fi = fmac(-cf.k1i, E1i, Fi);
+                        Fr = fmac(-c1.k1i, E1r, Fr);
+                        Fi = fmac(-c1.k1i, E1i, Fi);
                     }
                     const R ri2 = ri * ri;
                     Fr *= ri2;
                     Fi *= ri2;
-                    const R GVr = fmac(cf.rho, G1r, G0r), GVi = fmac(cf.rho, G1i, G0i);
-                    const R GWr = fmac(cf.irho, G1r, G0r), GWi = fmac(cf.irho, G1i, G0i);
+                    const R GVr = fmac(c1.rho, G1r, G0r), GVi = fmac(c1.rho, G1i, G0i);
+                    const R GWr = fmac(c1.irho, G1r, G0r), GWi = fmac(c1.irho, G1i, G0i);
                     // G_0 + (k_1^2 / (rho k_0^2)) G_1
-                    R GNr = fmac(cf.n10r, G1r, G0r), GNi = fmac(cf.n10r, G1i, G0i);
+                    R GNr = fmac(c1.n10r, G1r, G0r), GNi = fmac(c1.n10r, G1i, G0i);
                     if (CK0 || CK1) {
-                        GNr = fmac(-cf.n10i, G1i, GNr);
-                        GNi = fmac(cf.n10i, G1r, GNi);
+                        GNr = fmac(-c1.n10i, G1i, GNr);
+                        GNi = fmac(c1.n10i, G1r, GNi);
                     }
                     // complex multiply-accumulates as explicit FMA chains
                     R t1r = a1r[i], t1i = a1i[i], t2r = a2r[i], t2i = a2i[i];
@@ -506,7 +533,7 @@ __global__ __launch_bounds__(FF_BLOCK) __attribute__((amdgpu_waves_per_eu(3)))
 void farfield_sym_kernel(
     const R *__restrict__ geo, const R *__restrict__ dyn,
     const int32_t *__restrict__ tobj, const int32_t *__restrict__ tri, int T,
-    const int32_t *__restrict__ items, int chunk_len, Coef<R> cf,
+    const int32_t *__restrict__ items, int chunk_len, Coef<R> cf, const Int<R> *__restrict__ itab,
     double *__restrict__ ptau, double *__restrict__ psig) {
     static_assert(std::is_same<R, float>::value, "symmetric kernel: FP32 only");
     using MT = Math<R>;
@@ -613,6 +640,7 @@ void farfield_sym_kernel(
             if (active && tau < base + s && !adj) {
                 const R nsx = src[18], nsy = src[19], nsz = src[20], cs = src[21];
                 const R m1 = MULTI ? (src[GEO_STRIDE + DYN_STRIDE] == ot ? (R)1 : (R)0) : (R)1;
+                const Int<R> c1 = interior<MULTI>(cf, itab, src[GEO_STRIDE + DYN_STRIDE]);
                 const R nn = ntx * nsx + nty * nsy + ntz * nsz;
                 const R gnr = cf.n0r * nn, gni = cf.n0i * nn;
                 // dny_i = (y - x_i).n_sigma; sigma-side trial weights
@@ -652,7 +680,7 @@ void farfield_sym_kernel(
                         const R r = r2 * ri;
                         R E0r, E0i, E1r, E1i;
                         MT::template sincos_rev<FR>(r * cf.krev0, E0i, E0r);
-                        MT::template sincos_rev<FR>(r * cf.krev1, E1i, E1r);
+                        MT::template sincos_rev<FR>(r * c1.krev1, E1i, E1r);
                         if (CK0) {
                             const R d0 = MT::exp2(r * cf.kdec0);
                             E0r *= d0;
@@ -660,34 +688,34 @@ void farfield_sym_kernel(
                         }
                         if (CK1 || MULTI) {
                             R d1 = m1;
-                            if (CK1) d1 *= MT::exp2(r * cf.kdec1);
+                            if (CK1) d1 *= MT::exp2(r * c1.kdec1);
                             E1r *= d1;
                             E1i *= d1;
                         }
                         const R G0r = E0r * ri, G0i = E0i * ri;
                         const R G1r = E1r * ri, G1i = E1i * ri;
-                        R Fr = fmac(cf.ns1, G1r, -G0r), Fi = fmac(cf.ns1, G1i, -G0i);
+                        R Fr = fmac(c1.ns1, G1r, -G0r), Fi = fmac(c1.ns1, G1i, -G0i);
                         Fr = fmac(-cf.k0r, E0i, Fr);
                         Fi = fmac(cf.k0r, E0r, Fi);
-                        Fr = fmac(-cf.k1r, E1i, Fr);
-                        Fi = fmac(cf.k1r, E1r, Fi);
+                        Fr = fmac(-c1.k1r, E1i, Fr);
+                        Fi = fmac(c1.k1r, E1r, Fi);
                         if (CK0) {
                             Fr = fmac(-cf.k0i, E0r, Fr);
                             Fi = fmac(-cf.k0i, E0i, Fi);
                         }
                         if (CK1) {
-                            Fr = fmac(-cf.k1i, E1r, Fr);
-                            Fi = fmac(-cf.k1i, E1i, Fi);
+                            Fr = fmac(-c1.k1i, E1r, Fr);
+                            Fi = fmac(-c1.k1i, E1i, Fi);
                         }
                         const R ri2 = ri * ri;
                         Fr *= ri2;
                         Fi *= ri2;
-                        const R GVr = fmac(cf.rho, G1r, G0r), GVi = fmac(cf.rho, G1i, G0i);
-                        const R GWr = fmac(cf.irho, G1r, G0r), GWi = fmac(cf.irho, G1i, G0i);
-                        R GNr = fmac(cf.n10r, G1r, G0r), GNi = fmac(cf.n10r, G1i, G0i);
+                        const R GVr = fmac(c1.rho, G1r, G0r), GVi = fmac(c1.rho, G1i, G0i);
+                        const R GWr = fmac(c1.irho, G1r, G0r), GWi = fmac(c1.irho, G1i, G0i);
+                        R GNr = fmac(c1.n10r, G1r, G0r), GNi = fmac(c1.n10r, G1i, G0i);
                         if (CK0 || CK1) {
-                            GNr = fmac(-cf.n10i, G1i, GNr);
-                            GNi = fmac(cf.n10i, G1r, GNi);
+                            GNr = fmac(-c1.n10i, G1i, GNr);
+                            GNi = fmac(c1.n10i, G1r, GNi);
                         }
                         // tau at x_i: G_V s_psi(y_j) - F dny_i s_phi(y_j)
                         //             + F spx_j + G_N gsf_j
@@ -798,7 +826,8 @@ __global__ __launch_bounds__(FF_BLOCK) __attribute__((amdgpu_waves_per_eu(multi_
 void farfield_multi_kernel(
     const R *__restrict__ geo, const R *__restrict__ dyn,
     const int32_t *__restrict__ tobj, const int32_t *__restrict__ tri, int T,
-    int split_len, Coef<R> cf, double *__restrict__ partial) {
+    int split_len, Coef<R> cf, const Int<R> *__restrict__ itab,
+    double *__restrict__ partial) {
     using MT = Math<R>;
     // FP32 phases are below 256 revolutions on this path; FP64 always reduces
     constexpr bool FRM = std::is_same<R, double>::value;
@@ -901,6 +930,7 @@ void farfield_multi_kernel(
             }
             const R nsx = src[18], nsy = src[19], nsz = src[20], cs = src[21];
             const R m1 = MULTI ? (src[OBJ] == ot ? (R)1 : (R)0) : (R)1;
+            const Int<R> c1 = interior<MULTI>(cf, itab, src[OBJ]);
             const R nn = ntx * nsx + nty * nsy + ntz * nsz;
             const R gnr = cf.n0r * nn, gni = cf.n0i * nn;
             R dnx[6], dny[6];
@@ -924,10 +954,10 @@ void farfield_multi_kernel(
                     R E0r, E0i, E1r, E1i;
                     if constexpr (FRM) {
                         MT::sincos_tab(rr * cf.krev0, E0i, E0r, etab);
-                        MT::sincos_tab(rr * cf.krev1, E1i, E1r, etab);
+                        MT::sincos_tab(rr * c1.krev1, E1i, E1r, etab);
                     } else {
                         MT::template sincos_rev<false>(rr * cf.krev0, E0i, E0r);
-                        MT::template sincos_rev<false>(rr * cf.krev1, E1i, E1r);
+                        MT::template sincos_rev<false>(rr * c1.krev1, E1i, E1r);
                     }
                     if (CK0) {
                         const R d0 = MT::exp2(rr * cf.kdec0);
@@ -936,34 +966,34 @@ void farfield_multi_kernel(
                     }
                     if (CK1 || MULTI) {
                         R d1 = m1;
-                        if (CK1) d1 *= MT::exp2(rr * cf.kdec1);
+                        if (CK1) d1 *= MT::exp2(rr * c1.kdec1);
                         E1r *= d1;
                         E1i *= d1;
                     }
                     const R G0r = E0r * ri, G0i = E0i * ri;
                     const R G1r = E1r * ri, G1i = E1i * ri;
-                    R Fr = fmac(cf.ns1, G1r, -G0r), Fi = fmac(cf.ns1, G1i, -G0i);
+                    R Fr = fmac(c1.ns1, G1r, -G0r), Fi = fmac(c1.ns1, G1i, -G0i);
                     Fr = fmac(-cf.k0r, E0i, Fr);
                     Fi = fmac(cf.k0r, E0r, Fi);
-                    Fr = fmac(-cf.k1r, E1i, Fr);
-                    Fi = fmac(cf.k1r, E1r, Fi);
+                    Fr = fmac(-c1.k1r, E1i, Fr);
+                    Fi = fmac(c1.k1r, E1r, Fi);
                     if (CK0) {
                         Fr = fmac(-cf.k0i, E0r, Fr);
                         Fi = fmac(-cf.k0i, E0i, Fi);
                     }
                     if (CK1) {
-                        Fr = fmac(-cf.k1i, E1r, Fr);
-                        Fi = fmac(-cf.k1i, E1i, Fi);
+                        Fr = fmac(-c1.k1i, E1r, Fr);
+                        Fi = fmac(-c1.k1i, E1i, Fi);
                     }
                     const R ri2 = ri * ri;
                     Fr *= ri2;
                     Fi *= ri2;
-                    const R GVr = fmac(cf.rho, G1r, G0r), GVi = fmac(cf.rho, G1i, G0i);
-                    const R GWr = fmac(cf.irho, G1r, G0r), GWi = fmac(cf.irho, G1i, G0i);
-                    R GNr = fmac(cf.n10r, G1r, G0r), GNi = fmac(cf.n10r, G1i, G0i);
+                    const R GVr = fmac(c1.rho, G1r, G0r), GVi = fmac(c1.rho, G1i, G0i);
+                    const R GWr = fmac(c1.irho, G1r, G0r), GWi = fmac(c1.irho, G1i, G0i);
+                    R GNr = fmac(c1.n10r, G1r, G0r), GNi = fmac(c1.n10r, G1i, G0i);
                     if (CK0 || CK1) {
-                        GNr = fmac(-cf.n10i, G1i, GNr);
-                        GNi = fmac(cf.n10i, G1r, GNi);
+                        GNr = fmac(-c1.n10i, G1i, GNr);
+                        GNi = fmac(c1.n10i, G1r, GNi);
                     }
                     const R Fxr = Fr * dnx[j], Fxi = Fi * dnx[j];
 #pragma unroll
@@ -1124,22 +1154,16 @@ __global__ __launch_bounds__(256) void finalize_kernel(
 // operator (A_0 - A^_1).  The sign is folded into every interior coefficient:
 // rho, 1/rho, k_1^2/(rho k_0^2) and k_1 (which enters only through F), and
 // ns1 carries it into the -(G_0 + s1 G_1) part of F.
-template <class R> Coef<R> make_coef(double2 k0, double2 k1, double rho, int s1) {
-    Coef<R> c;
+template <class R> Int<R> make_int(double2 k0, double2 k1, double rho, int s1) {
+    Int<R> c;
     const double inv2pi = 0.15915494309189533576888376337251;
     const double log2e = 1.4426950408889634073599246810019;
-    c.krev0 = (R)(k0.x * inv2pi);
     c.krev1 = (R)(k1.x * inv2pi);
-    c.k0r = (R)k0.x;
-    c.k0i = (R)k0.y;
     c.k1r = (R)k1.x;
     c.k1i = (R)k1.y;
-    c.kdec0 = (R)(-k0.y * log2e);
     c.kdec1 = (R)(-k1.y * log2e);
     c.rho = (R)rho;
     c.irho = (R)(1.0 / rho);
-    c.n0r = (R)(k0.x * k0.x - k0.y * k0.y);
-    c.n0i = (R)(2.0 * k0.x * k0.y);
     // k_1^2 / (rho k_0^2); k_0 != 0 is checked at the entry points
     const double n0r = k0.x * k0.x - k0.y * k0.y, n0i = 2.0 * k0.x * k0.y;
     const double n1r = (k1.x * k1.x - k1.y * k1.y) / rho, n1i = 2.0 * k1.x * k1.y / rho;
@@ -1158,6 +1182,45 @@ template <class R> Coef<R> make_coef(double2 k0, double2 k1, double rho, int s1)
     return c;
 }
 
+// Launch coefficients from the near-field operator's materials: the first
+// object's interior part by value (one object); kernels for several objects
+// read every object's from interior_table().
+template <class R> Coef<R> make_coef(double2 k0, const NearOperator &nf) {
+    Coef<R> c;
+    const double inv2pi = 0.15915494309189533576888376337251;
+    const double log2e = 1.4426950408889634073599246810019;
+    c.krev0 = (R)(k0.x * inv2pi);
+    c.k0r = (R)k0.x;
+    c.k0i = (R)k0.y;
+    c.kdec0 = (R)(-k0.y * log2e);
+    c.n0r = (R)(k0.x * k0.x - k0.y * k0.y);
+    c.n0i = (R)(2.0 * k0.x * k0.y);
+    c.in = make_int<R>(k0, nf.k1o[0], nf.rhoo[0], nf.s1);
+    return c;
+}
+
+// per-object interior coefficients on the device (built on first use, kept
+// with the near-field operator), or nullptr for one object
+template <class R> const Int<R> *interior_table(const bem_mesh *m, const NearOperator &nf,
+                                                double2 k0) {
+    if (m->nobj < 2) return nullptr;
+    static_assert(sizeof(Int<R>) == INT_COEFS * sizeof(R), "Int<R> layout");
+    constexpr bool F32 = std::is_same<R, float>::value;
+    auto &buf = [&]() -> auto & {
+        if constexpr (F32) return nf.itab32;
+        else return nf.itab64;
+    }();
+    if (!buf.p) {
+        std::vector<R> h((size_t)m->nobj * INT_COEFS);
+        for (int o = 0; o < m->nobj; o++) {
+            const Int<R> c = make_int<R>(k0, nf.k1o[o], nf.rhoo[o], nf.s1);
+            std::memcpy(h.data() + (size_t)o * INT_COEFS, &c, sizeof(c));
+        }
+        buf.upload(h);
+    }
+    return (const Int<R> *)buf.p;
+}
+
 // dynamic LDS of the single-vector kernel: FP32 per-thread FP64 sums
 template <class R> size_t far_smem(int blk) {
     return std::is_same<R, float>::value ? (size_t)FF_ROWS * blk * sizeof(double) : 0;
@@ -1166,9 +1229,9 @@ template <class R> size_t far_smem(int blk) {
 template <class R, bool CK0, bool CK1, bool MULTI, bool FR>
 void launch_far(dim3 grid, int blk, hipStream_t s, const R *geo, const R *dyn,
                 const int32_t *tobj, const int32_t *tri, int T, int split_len, Coef<R> cf,
-                double *partial) {
+                const Int<R> *itab, double *partial) {
     hipLaunchKernelGGL((farfield_kernel<R, CK0, CK1, MULTI, FR>), grid, dim3(blk), far_smem<R>(blk),
-                       s, geo, dyn, tobj, tri, T, split_len, cf, partial);
+                       s, geo, dyn, tobj, tri, T, split_len, cf, itab, partial);
 }
 
 // fr: reduce phases to [0, 1) revolutions before v_sin/v_cos (needed when
@@ -1176,11 +1239,14 @@ void launch_far(dim3 grid, int blk, hipStream_t s, const R *geo, const R *dyn,
 template <class R, bool FR>
 void dispatch_far(dim3 grid, int blk, hipStream_t s, const R *geo, const R *dyn,
                   const int32_t *tobj, const int32_t *tri, int T, int split_len, Coef<R> cf,
-                  double *partial, bool ck0, bool ck1, bool multi) {
+                  const Int<R> *itab, double *partial, bool ck0, bool ck1, bool multi) {
     int code = (ck0 ? 4 : 0) | (ck1 ? 2 : 0) | (multi ? 1 : 0);
     switch (code) {
 #define BEM_CASE(c, a, b, m) \
-    case c: launch_far<R, a, b, m, FR>(grid, blk, s, geo, dyn, tobj, tri, T, split_len, cf, partial); break;
+    case c:                                                                                      \
+        launch_far<R, a, b, m, FR>(grid, blk, s, geo, dyn, tobj, tri, T, split_len, cf, itab,    \
+                                   partial);                                                     \
+        break;
         BEM_CASE(0, false, false, false)
         BEM_CASE(1, false, false, true)
         BEM_CASE(2, false, true, false)
@@ -1223,12 +1289,12 @@ template <class R, int NR> const void *multi_kernel(int code) {
 template <class R, int NR>
 void launch_multi(int code, dim3 grid, int blk, hipStream_t s, const R *geo, const R *dyn,
                   const int32_t *tobj, const int32_t *tri, int T, int split_len, Coef<R> cf,
-                  double *partial) {
+                  const Int<R> *itab, double *partial) {
     switch (code) {
 #define BEM_CASE(c, a, b, m)                                                                     \
     case c:                                                                                      \
         hipLaunchKernelGGL((farfield_multi_kernel<R, a, b, m, NR>), grid, dim3(blk), 0, s,      \
-                           geo, dyn, tobj, tri, T, split_len, cf, partial);                      \
+                           geo, dyn, tobj, tri, T, split_len, cf, itab, partial);                \
         break;
         BEM_CASE(0, false, false, false)
         BEM_CASE(1, false, false, true)
@@ -1332,13 +1398,13 @@ template <bool FR> const void *sym_kernel(int code) {
 template <bool FR>
 void launch_sym(int code, int n_items, int blk, hipStream_t s, const float *geo, const float *dyn,
                 const int32_t *tobj, const int32_t *tri, int T, const int32_t *items, int chunk,
-                Coef<float> cf, double *ptau, double *psig) {
+                Coef<float> cf, const Int<float> *itab, double *ptau, double *psig) {
     switch (code) {
 #define BEM_CASE(c, a, b, m)                                                                     \
     case c:                                                                                      \
         hipLaunchKernelGGL((farfield_sym_kernel<float, a, b, m, FR>), dim3(n_items), dim3(blk),  \
                            far_smem<float>(blk), s, geo, dyn, tobj, tri, T, items, chunk, cf,    \
-                           ptau, psig);                                                          \
+                           itab, ptau, psig);                                                    \
         break;
         BEM_CASE(0, false, false, false)
         BEM_CASE(1, false, false, true)
@@ -1478,10 +1544,10 @@ void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
                     hipStream_t s, int block) {
     const int T = (int)m->T;
     const FarPlan plan =
-        far_plan(m, precision, k0, k1, valid_block(block > 0 ? block : tune_lookup(T, 1).block));
+        far_plan(m, precision, k0, nf.k1_plan, valid_block(block > 0 ? block : tune_lookup(T, 1).block));
     const int blk = plan.blk;
     const int nsplit = plan.nsplit;
-    const bool ck0 = k0.y != 0.0, ck1 = k1.y != 0.0, multi = m->nobj > 1, fr = plan.fr;
+    const bool ck0 = k0.y != 0.0, ck1 = nf.k1_plan.y != 0.0, multi = m->nobj > 1, fr = plan.fr;
     const int split_len = (T + nsplit - 1) / nsplit;
     const bool sym = precision == BEM_FP32 && tuning().farfield_symmetric;
     const size_t need = (size_t)nsplit * T * (ROW_STRIDE + 6);
@@ -1511,11 +1577,11 @@ void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
             if (!fr)
                 launch_sym<false>(plan.code, n_items, blk, s, m->geo32.p, m->dyn32.p, m->tobj_d.p,
                                   m->tri_d.p, T, m->sym_items.p, sp.chunk,
-                                  make_coef<float>(k0, k1, rho, nf.s1), ptau, psig);
+                                  make_coef<float>(k0, nf), interior_table<float>(m, nf, k0), ptau, psig);
             else
                 launch_sym<true>(plan.code, n_items, blk, s, m->geo32.p, m->dyn32.p, m->tobj_d.p,
                                  m->tri_d.p, T, m->sym_items.p, sp.chunk,
-                                 make_coef<float>(k0, k1, rho, nf.s1), ptau, psig);
+                                 make_coef<float>(k0, nf), interior_table<float>(m, nf, k0), ptau, psig);
             BEM_LAUNCH_CHECK();
         }
         hipLaunchKernelGGL(reduce_sym_kernel, gg, dim3(256), 0, s, ptau, psig, m->tst.p, T, blk,
@@ -1529,12 +1595,14 @@ void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
         Timer tm("farfield_fp32", s);
         if (!fr)
             dispatch_far<float, false>(grid, blk, s, m->geo32.p, m->dyn32.p, m->tobj_d.p, m->tri_d.p,
-                                       T, split_len, make_coef<float>(k0, k1, rho, nf.s1),
-                                       m->partial.p, ck0, ck1, multi);
+                                       T, split_len, make_coef<float>(k0, nf),
+                                       interior_table<float>(m, nf, k0), m->partial.p, ck0, ck1,
+                                       multi);
         else
             dispatch_far<float, true>(grid, blk, s, m->geo32.p, m->dyn32.p, m->tobj_d.p, m->tri_d.p,
-                                      T, split_len, make_coef<float>(k0, k1, rho, nf.s1),
-                                      m->partial.p, ck0, ck1, multi);
+                                      T, split_len, make_coef<float>(k0, nf),
+                                      interior_table<float>(m, nf, k0), m->partial.p, ck0, ck1,
+                                      multi);
         BEM_LAUNCH_CHECK();
     } else {
         if (m->dyn64.n < (size_t)T * DYN_STRIDE) m->dyn64.alloc((size_t)T * DYN_STRIDE);
@@ -1543,7 +1611,8 @@ void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
         BEM_LAUNCH_CHECK();
         Timer tm("farfield_fp64", s);
         dispatch_far<double, true>(grid, blk, s, m->geo64.p, m->dyn64.p, m->tobj_d.p, m->tri_d.p, T, split_len,
-                             make_coef<double>(k0, k1, rho, nf.s1), m->partial.p, ck0, ck1, multi);
+                             make_coef<double>(k0, nf), interior_table<double>(m, nf, k0), m->partial.p, ck0,
+                             ck1, multi);
         BEM_LAUNCH_CHECK();
     }
     if (!sym) {
@@ -1592,8 +1661,8 @@ void farfield_multi_apply(bem_mesh *m, const NearOperator &nf, double2 k0, doubl
     {
         Timer tm(F32 ? "farfield_fp32_multi" : "farfield_fp64_multi", s);
         launch_multi<R, NR>(code, dim3((T + blk - 1) / blk, nsplit), blk, s, geo, dyn,
-                            m->tobj_d.p, m->tri_d.p, T, split_len, make_coef<R>(k0, k1, rho, nf.s1),
-                            m->partial.p);
+                            m->tobj_d.p, m->tri_d.p, T, split_len, make_coef<R>(k0, nf),
+                            interior_table<R>(m, nf, k0), m->partial.p);
         BEM_LAUNCH_CHECK();
     }
     for (int r = 0; r < NR; r++) {
@@ -1615,7 +1684,7 @@ void farfield_apply_batch(bem_mesh *m, const NearOperator &nf, double2 k0, doubl
     const int64_t n2 = 2 * m->N;
     const TuneEntry te = forced ? *forced : tune_lookup(m->T, R);
     const int blk = valid_block(te.block);
-    const FarPlan plan = far_plan(m, precision, k0, k1, blk);
+    const FarPlan plan = far_plan(m, precision, k0, nf.k1_plan, blk);
     int r0 = 0;
     const int mm = te.multi;
     if (precision == BEM_FP32 && !plan.fr && mm >= 2) {

@@ -8,7 +8,8 @@
 //   outside every object:  u = u_inc + sum over all triangles of
 //       int [ -G_0 psi + (n_y . grad_y G_0) phi ] dy
 //   inside object m:       u = int over object m of
-//       [ rho G_1 psi - (n_y . grad_y G_1) phi ] dy
+//       [ rho_m G_m psi - (n_y . grad_y G_m) phi ] dy
+// (k_m, rho_m the object's interior material)
 // with n_y . grad_y G(p, y) = ((y - p) . n_y) G (i k r - 1) / r^2; the
 // factor (y - p) . n_y = c_sigma - p . n_sigma is constant on a flat
 // triangle.  6-point rule per triangle (the sources w |sigma| psi_h and
@@ -156,7 +157,7 @@ __global__ __launch_bounds__(256) void region_kernel(const double *__restrict__ 
 __global__ __launch_bounds__(256) void field_kernel(
     const double *__restrict__ src, const double *__restrict__ geo,
     const int32_t *__restrict__ tobj, int T, int split_len, const double *__restrict__ pts,
-    const int32_t *__restrict__ region, int64_t n, double2 k0, double2 k1,
+    const int32_t *__restrict__ region, int64_t n, double2 k0, const double *__restrict__ omat,
     double *__restrict__ part) {
     __shared__ double tile[FT * FS];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -164,7 +165,8 @@ __global__ __launch_bounds__(256) void field_kernel(
     const double px = pts[3 * pp], py = pts[3 * pp + 1], pz = pts[3 * pp + 2];
     const int reg = region[pp];
     const bool ext = reg == 0;
-    const double2 k = ext ? k0 : k1;
+    // interior material of the enclosing object: omat[object] = (Re k, Im k, rho)
+    const double2 k = ext ? k0 : make_double2(omat[3 * (reg - 1)], omat[3 * (reg - 1) + 1]);
     const int t0 = blockIdx.y * split_len, t1 = min(T, t0 + split_len);
     double sr = 0, si = 0, dr = 0, di = 0;
     for (int base = t0; base < t1; base += FT) {
@@ -223,8 +225,8 @@ __global__ __launch_bounds__(256) void field_kernel(
 // splits added in order; coefficients of the region; incident wave outside
 __global__ __launch_bounds__(256) void field_reduce_kernel(
     const double *__restrict__ part, int nsplit, const double *__restrict__ pts,
-    const int32_t *__restrict__ region, int64_t n, double2 k0, double rho, double dx,
-    double dy, double dz, double2 *__restrict__ out) {
+    const int32_t *__restrict__ region, int64_t n, double2 k0, const double *__restrict__ omat,
+    double dx, double dy, double dz, double2 *__restrict__ out) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     double sr = 0, si = 0, dr = 0, di = 0;
@@ -236,7 +238,8 @@ __global__ __launch_bounds__(256) void field_reduce_kernel(
         di += o[3];
     }
     double ur, ui;
-    if (region[p] == 0) {
+    const int reg = region[p];
+    if (reg == 0) {
         const double dp = dx * pts[3 * p] + dy * pts[3 * p + 1] + dz * pts[3 * p + 2];
         double sn, cs;
         sincos(k0.x * dp, &sn, &cs);
@@ -244,6 +247,7 @@ __global__ __launch_bounds__(256) void field_reduce_kernel(
         ur = a * cs + INV4PI * (dr - sr);
         ui = a * sn + INV4PI * (di - si);
     } else {
+        const double rho = omat[3 * (reg - 1) + 2];
         ur = INV4PI * (rho * sr - dr);
         ui = INV4PI * (rho * si - di);
     }
@@ -254,10 +258,19 @@ __global__ __launch_bounds__(256) void field_reduce_kernel(
 
 void field_eval(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dir,
                 const double2 *x, const double *pts, int64_t n, double2 *out, int32_t *region,
-                hipStream_t s) {
+                hipStream_t s, const ObjMaterials *om) {
     if (n == 0) return;
     const int T = (int)m->T;
     if (!m->P_d.p) m->P_d.upload(m->P);
+    std::vector<double> mat(3 * (size_t)m->nobj);
+    for (int o = 0; o < m->nobj; o++) {
+        const double2 ko = om ? om->k[o] : k1;
+        mat[3 * o] = ko.x;
+        mat[3 * o + 1] = ko.y;
+        mat[3 * o + 2] = om ? om->rho[o] : rho;
+    }
+    DevBuf<double> matd;
+    matd.upload(mat);
     const unsigned pb = (unsigned)((n + 255) / 256);
     // enough workgroups to fill the device (about 2048), splits of >= 4 tiles
     const int max_split = std::max(1, T / (4 * FT));
@@ -285,11 +298,12 @@ void field_eval(bem_mesh *m, double2 k0, double2 k1, double rho, const double *d
     {
         Timer tm("field_eval", s);
         hipLaunchKernelGGL(field_kernel, dim3(pb, (unsigned)nsplit), dim3(256), 0, s, src.p,
-                           m->geo64.p, m->tobj_d.p, T, split_len, pts, reg, n, k0, k1, part.p);
+                           m->geo64.p, m->tobj_d.p, T, split_len, pts, reg, n, k0, matd.p,
+                           part.p);
         BEM_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(field_reduce_kernel, dim3(pb), dim3(256), 0, s, part.p, nsplit, pts, reg, n,
-                       k0, rho, dir[0], dir[1], dir[2], out);
+                       k0, matd.p, dir[0], dir[1], dir[2], out);
     BEM_LAUNCH_CHECK();
     BEM_HIP(hipStreamSynchronize(s));   // src, part and the own region buffer are released on return
 }

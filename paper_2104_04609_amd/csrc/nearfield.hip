@@ -8,7 +8,8 @@
 // are integrated with the singular rule of the pair's class (coincident,
 // common edge, common vertex); the matrix-free pair kernel skips exactly these
 // pairs.  The blocks are summed into a vertex-by-vertex CSR matrix in a fixed
-// order.  With s1 = -1 the interior terms enter with the opposite sign and the
+// order.  The interior terms of a pair use its object's material.  With s1 =
+// -1 the interior terms enter with the opposite sign and the
 // coincident pairs add the local P1 mass matrix |tau| (1 + delta_ab) / 12 to
 // B12 and B21: the Mueller operator I + A_0 - A^_1 of Sec. 2.2 on the
 // permuted unknowns, whose identity pairs each trace row with its own trace.
@@ -21,8 +22,7 @@ namespace bem {
 namespace {
 
 struct NearCoef {
-    double2 k0, k1;
-    double rho;
+    double2 k0;
     double s1;   // +1 PMCHWT, -1 Mueller
 };
 
@@ -50,7 +50,8 @@ __global__ __launch_bounds__(64) void near_pairs_kernel(
     const int32_t *__restrict__ pairs, int64_t n_pairs, const double *__restrict__ P,
     const int32_t *__restrict__ tri, const double *__restrict__ tst,
     const double *__restrict__ geo, const double *__restrict__ tab, int off0, int off1,
-    int off2, int off3, NearCoef cf, double2 *__restrict__ blocks) {
+    int off2, int off3, NearCoef cf, const int32_t *__restrict__ tobj,
+    const double *__restrict__ omat, double2 *__restrict__ blocks) {
     const int64_t p = blockIdx.x;
     if (p >= n_pairs) return;
     const int lane = threadIdx.x;
@@ -79,9 +80,14 @@ __global__ __launch_bounds__(64) void near_pairs_kernel(
 #pragma unroll
     for (int i = 0; i < NACC; i++) acc[i] = 0.0;
     const double k0sq_r = cf.k0.x * cf.k0.x - cf.k0.y * cf.k0.y, k0sq_i = 2 * cf.k0.x * cf.k0.y;
-    const double k1sq_r = cf.s1 * (cf.k1.x * cf.k1.x - cf.k1.y * cf.k1.y) / cf.rho,
-                 k1sq_i = cf.s1 * 2 * cf.k1.x * cf.k1.y / cf.rho;
-    const double rho1 = cf.s1 * cf.rho, irho1 = cf.s1 / cf.rho;
+    // interior material of the pair's object (a pair sharing a vertex lies
+    // within one object): omat[object] = (Re k_1, Im k_1, rho)
+    const int ob = tobj[t];
+    const double2 k1 = make_double2(omat[3 * ob], omat[3 * ob + 1]);
+    const double rho = omat[3 * ob + 2];
+    const double k1sq_r = cf.s1 * (k1.x * k1.x - k1.y * k1.y) / rho,
+                 k1sq_i = cf.s1 * 2 * k1.x * k1.y / rho;
+    const double rho1 = cf.s1 * rho, irho1 = cf.s1 / rho;
 
     for (int q = lane; q < nss; q += 64) {
         double lx[3], ly[3];
@@ -102,7 +108,7 @@ __global__ __launch_bounds__(64) void near_pairs_kernel(
         double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         double2 G0, F0, G1, F1;
         green(cf.k0, r, G0, F0);
-        green(cf.k1, r, G1, F1);
+        green(k1, r, G1, F1);
         double2 GV = make_double2(G0.x + rho1 * G1.x, G0.y + rho1 * G1.y);
         double2 GW = make_double2(G0.x + irho1 * G1.x, G0.y + irho1 * G1.y);
         double2 GN = make_double2(k0sq_r * G0.x - k0sq_i * G0.y + k1sq_r * G1.x - k1sq_i * G1.y,
@@ -177,22 +183,63 @@ __global__ __launch_bounds__(256) void near_csr_kernel(
 
 }   // namespace
 
+NearKey near_key(const bem_mesh *m, double2 k0, double2 k1, double rho, int s1,
+                 const ObjMaterials *om) {
+    s1 = s1 < 0 ? -1 : 1;
+    NearKey key{k0.x, k0.y, k1.x, k1.y, rho, s1, {}};
+    if (om) {
+        bool same = true;
+        for (int o = 1; o < m->nobj; o++)
+            same = same && om->k[o].x == om->k[0].x && om->k[o].y == om->k[0].y &&
+                   om->rho[o] == om->rho[0];
+        key.k1r = om->k[0].x;
+        key.k1i = om->k[0].y;
+        key.rho = om->rho[0];
+        if (!same)
+            for (int o = 0; o < m->nobj; o++) {
+                key.om.push_back(om->k[o].x);
+                key.om.push_back(om->k[o].y);
+                key.om.push_back(om->rho[o]);
+            }
+    }
+    return key;
+}
+
 std::unique_ptr<NearOperator> nearfield_build(bem_mesh *m, double2 k0, double2 k1,
-                                              double rho, hipStream_t s, int s1) {
+                                              double rho, hipStream_t s, int s1,
+                                              const ObjMaterials *om) {
     auto op = std::make_unique<NearOperator>();
     op->s1 = s1 < 0 ? -1 : 1;
+    op->k1o.assign(m->nobj, k1);
+    op->rhoo.assign(m->nobj, rho);
+    if (om) {
+        op->k1o = om->k;
+        op->rhoo = om->rho;
+    }
+    std::vector<double> mat(3 * (size_t)m->nobj);
+    bool complex_k = false;
+    op->k1_plan = op->k1o[0];
+    for (int o = 0; o < m->nobj; o++) {
+        mat[3 * o] = op->k1o[o].x;
+        mat[3 * o + 1] = op->k1o[o].y;
+        mat[3 * o + 2] = op->rhoo[o];
+        complex_k = complex_k || op->k1o[o].y != 0.0;
+        if (std::fabs(op->k1o[o].x) > std::fabs(op->k1_plan.x)) op->k1_plan = op->k1o[o];
+    }
+    if (complex_k && op->k1_plan.y == 0.0) op->k1_plan.y = 1.0;   // any complex k_m: complex variant
     op->vals.alloc(4 * (size_t)m->nf_nnz * 2);
-    DevBuf<double> Pd;
+    DevBuf<double> Pd, matd;
     std::vector<double> Ph(m->P);
     Pd.upload(Ph);
+    matd.upload(mat);
     DevBuf<double2> blocks(36 * (size_t)m->n_near);
-    NearCoef cf{k0, k1, rho, (double)op->s1};
+    NearCoef cf{k0, (double)op->s1};
     {
         Timer tm("nearfield_build", s);
         hipLaunchKernelGGL(near_pairs_kernel, dim3((unsigned)m->n_near), dim3(64), 0, s,
                            m->near_pairs.p, m->n_near, Pd.p, m->tri_d.p, m->tst.p,
                            m->geo64.p, m->ss_tab.p, m->ss_off[0], m->ss_off[1],
-                           m->ss_off[2], m->ss_off[3], cf, blocks.p);
+                           m->ss_off[2], m->ss_off[3], cf, m->tobj_d.p, matd.p, blocks.p);
         BEM_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(near_csr_kernel, dim3((unsigned)((m->nf_nnz + 255) / 256)), dim3(256),
@@ -204,13 +251,13 @@ std::unique_ptr<NearOperator> nearfield_build(bem_mesh *m, double2 k0, double2 k
 }
 
 const NearOperator &nearfield_get(bem_mesh *m, double2 k0, double2 k1, double rho,
-                                  hipStream_t s, int s1) {
-    s1 = s1 < 0 ? -1 : 1;
-    NearKey key{k0.x, k0.y, k1.x, k1.y, rho, s1};
+                                  hipStream_t s, int s1, const ObjMaterials *om) {
+    const NearKey key = near_key(m, k0, k1, rho, s1, om);
     auto it = m->near_cache.find(key);
     if (it != m->near_cache.end()) return *it->second;
     if (m->near_cache.size() >= 8) m->near_cache.erase(m->near_cache.begin());
-    auto op = nearfield_build(m, k0, k1, rho, s, s1);
+    auto op = nearfield_build(m, k0, make_double2(key.k1r, key.k1i), key.rho, s, key.s1,
+                              key.om.empty() ? nullptr : om);
     auto &ref = *op;
     m->near_cache.emplace(key, std::move(op));
     return ref;

@@ -42,8 +42,9 @@ int64_t OsrcSymbolicState::bytes() const {
            brange_d.bytes() + doff_d.bytes() + Mv_d.bytes() + Sv_d.bytes();
 }
 int64_t OsrcState::bytes() const {
-    return cvert.bytes() + Dinv.bytes() + Lcsr.bytes() + Lcsc.bytes() + invL.bytes() +
-           invLT.bytes() + work.bytes() + obuf.bytes() + wbuf.bytes();
+    return cvert.bytes() + ikv.bytes() + iikv.bytes() + Dinv.bytes() + Lcsr.bytes() +
+           Lcsc.bytes() + invL.bytes() + invLT.bytes() + work.bytes() + obuf.bytes() +
+           wbuf.bytes();
 }
 
 void OsrcState::ensure_batch(int R) {
@@ -188,12 +189,29 @@ int64_t osrc_state_bytes(bem_mesh *m, int np, int R) {
 }
 
 OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
-                    const std::vector<double2> &keps_obj, hipStream_t s) {
+                    const std::vector<double2> &keps_obj, hipStream_t s,
+                    const std::vector<double2> *k_obj) {
     if ((int)keps_obj.size() != m->nobj) fail(BEM_E_INVAL, "one k_eps per object expected");
-    OsrcKey key{np, theta, k.x, k.y, {}};
+    if (k_obj && (int)k_obj->size() != m->nobj) fail(BEM_E_INVAL, "one k per object expected");
+    OsrcKey key{np, theta, k.x, k.y, {}, {}};
     for (const double2 &ke : keps_obj) {
         key.keps.push_back(ke.x);
         key.keps.push_back(ke.y);
+    }
+    if (k_obj) {
+        bool same = true;
+        for (const double2 &ko : *k_obj) same = same && ko.x == (*k_obj)[0].x && ko.y == (*k_obj)[0].y;
+        if (same) {
+            k = (*k_obj)[0];
+            key.kr = k.x;
+            key.ki = k.y;
+            k_obj = nullptr;
+        } else {
+            for (const double2 &ko : *k_obj) {
+                key.kobj.push_back(ko.x);
+                key.kobj.push_back(ko.y);
+            }
+        }
     }
     auto it = m->osrc_cache.find(key);
     if (it != m->osrc_cache.end()) return *it->second;
@@ -237,6 +255,16 @@ OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
     }
     for (int v = 0; v < n; v++) cv[v] = d2(cobj[m->vobj[v]]);
     st->cvert.upload(cv);
+    if (k_obj) {   // ik and 1/(ik) of each vertex's object
+        std::vector<double2> a(n), ai(n);
+        for (int v = 0; v < n; v++) {
+            const cdd ik = cdd(0, 1) * cdd((*k_obj)[m->vobj[v]].x, (*k_obj)[m->vobj[v]].y);
+            a[v] = d2(ik);
+            ai[v] = d2(1.0 / ik);
+        }
+        st->ikv.upload(a);
+        st->iikv.upload(ai);
+    }
     // numeric factorisations, one thread per system
     const int nf = np + 2;
     st->nfactors = nf;
@@ -312,7 +340,7 @@ void osrc_apply_from_weak(bem_mesh *m, OsrcState &st, const double2 *yw, double2
     ta.work_stride = ws;
     launch_ldl_solve(L, ta, np + 2, R, s);
     // z1 = ik (C_0' M^{-1} y1 - sum_j (A_j/B_j) s_j);  m2 = M v
-    launch_pade_sum(n, st.pf, d2(ik), u1, os, ob, n, os, z, n2, R, s);
+    launch_pade_sum(n, st.pf, d2(ik), st.ikv.p, u1, os, ob, n, os, z, n2, R, s);
     launch_spmv_real(n, R, sy.gptr_d.p, sy.gcol_d.p, sy.Mv_d.p, v, os, m2, os, s);
     // stage 2: shifted solves on M v (NtD)
     TaskList tb{};
@@ -322,7 +350,7 @@ void osrc_apply_from_weak(bem_mesh *m, OsrcState &st, const double2 *yw, double2
     tb.work_stride = ws;
     launch_ldl_solve(L, tb, np, R, s);
     // z2 = (1/ik) (C_0' v - sum_j (A_j/B_j) s'_j)
-    launch_pade_sum(n, st.pf, d2(1.0 / ik), v, os, ob, n, os, z + n, n2, R, s);
+    launch_pade_sum(n, st.pf, d2(1.0 / ik), st.iikv.p, v, os, ob, n, os, z + n, n2, R, s);
 }
 
 void osrc_apply_strong(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y, int R,

@@ -75,6 +75,7 @@ struct OsrcState {
     std::vector<double2> B;      // Pade B_j
     int nfactors = 0;            // np shifts, (M - S/k_eps^2), M
     DevBuf<double2> cvert;       // 1/k_eps^2 of each vertex's object
+    DevBuf<double2> ikv, iikv;   // ik and 1/(ik) per vertex (objects with their own k), else empty
     DevBuf<double2> Dinv, Lcsr, Lcsc, invL, invLT;
     // per right-hand side r of a batched apply (capacity `batch`):
     DevBuf<double2> work;        // [r][np + 2][n] solve work vectors
@@ -97,9 +98,9 @@ struct TaskList {
 void launch_ldl_solve(const LdlDev &L, TaskList tasks, int ntasks, int nrhs, hipStream_t s);
 // out_r = alpha (C0 u_r - sum_j A_j s_{r,j})   (elementwise, r < nrhs):
 // u_r = u + r ustride, s_{r,j} = sv + r vstride + j sstride, out_r = out + r ostride
-void launch_pade_sum(int n, const PadeCoef &pc, double2 alpha, const double2 *u,
-                     int64_t ustride, const double2 *sv, int64_t sstride, int64_t vstride,
-                     double2 *out, int64_t ostride, int nrhs, hipStream_t s);
+void launch_pade_sum(int n, const PadeCoef &pc, double2 alpha, const double2 *alpha_v,
+                     const double2 *u, int64_t ustride, const double2 *sv, int64_t sstride,
+                     int64_t vstride, double2 *out, int64_t ostride, int nrhs, hipStream_t s);
 // out_b = V in_b for b < nblk, in_b = in + b istride, out_b = out + b ostride
 void launch_spmv_real(int n, int nblk, const int32_t *gptr, const int32_t *gcol,
                       const double *V, const double2 *in, int64_t istride, double2 *out,

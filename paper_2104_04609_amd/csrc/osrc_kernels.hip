@@ -175,6 +175,7 @@ __global__ __launch_bounds__(LVL_THREADS) void ldl_level_kernel(LdlDev L, TaskLi
 
 // out_r[i] = alpha (C0 u_r[i] - sum_j A_j s_{r,j}[i]), r = blockIdx.y
 __global__ __launch_bounds__(256) void pade_sum_kernel(int n, PadeCoef pc, double2 alpha,
+                                                       const double2 *__restrict__ alpha_v,
                                                        const double2 *__restrict__ u,
                                                        int64_t ustride,
                                                        const double2 *__restrict__ sv,
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(256) void pade_sum_kernel(int n, PadeCoef pc, doubl
         acc.x -= p.x;
         acc.y -= p.y;
     }
-    out[i] = cmul(alpha, acc);
+    out[i] = cmul(alpha_v ? alpha_v[i] : alpha, acc);
 }
 
 // out_b[i] = sum_e V_e in_b[col_e]  (real sparse matrix, complex vectors),
@@ -241,11 +242,11 @@ void launch_ldl_solve(const LdlDev &L, TaskList tasks, int ntasks, int nrhs, hip
         level(l, ldl_level_kernel<false>, ldl_ext_kernel<false>, ldl_dense_kernel<false>);
 }
 
-void launch_pade_sum(int n, const PadeCoef &pc, double2 alpha, const double2 *u,
-                     int64_t ustride, const double2 *sv, int64_t sstride, int64_t vstride,
-                     double2 *out, int64_t ostride, int nrhs, hipStream_t s) {
+void launch_pade_sum(int n, const PadeCoef &pc, double2 alpha, const double2 *alpha_v,
+                     const double2 *u, int64_t ustride, const double2 *sv, int64_t sstride,
+                     int64_t vstride, double2 *out, int64_t ostride, int nrhs, hipStream_t s) {
     hipLaunchKernelGGL(pade_sum_kernel, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, n, pc,
-                       alpha, u, ustride, sv, sstride, vstride, out, ostride);
+                       alpha, alpha_v, u, ustride, sv, sstride, vstride, out, ostride);
     BEM_LAUNCH_CHECK();
 }
 

@@ -307,6 +307,17 @@ void solve_check(const bem_mesh *m, double2 k0, double2 k1, double rho, const do
     }
 }
 
+void check_materials(const bem_mesh *m, const ObjMaterials &om) {
+    if ((int)om.k.size() != m->nobj || (int)om.rho.size() != m->nobj)
+        fail(BEM_E_INVAL, "one interior wavenumber and density ratio per object expected");
+    for (int o = 0; o < m->nobj; o++) {
+        const double2 k = om.k[o];
+        if (!std::isfinite(k.x) || !std::isfinite(k.y) || k.y < 0 || (k.x == 0 && k.y == 0))
+            fail(BEM_E_INVAL, "wavenumbers must be finite, nonzero, Im k >= 0");
+        if (!(om.rho[o] > 0) || !std::isfinite(om.rho[o])) fail(BEM_E_INVAL, "rho must be positive");
+    }
+}
+
 int64_t solve_footprint(bem_mesh *m, double2 k0, double2 k1, double rho,
                         const bem_solve_opts &o, int n_waves) {
     (void)rho;
@@ -330,17 +341,20 @@ int64_t solve_footprint(bem_mesh *m, double2 k0, double2 k1, double rho,
 
 int solve_run(bem_mesh *m, double2 k0, double2 k1, double rho, const double *directions,
               int n_waves, double tol, const bem_solve_opts &o, double2 *solution,
-              bem_solve_info *info, hipStream_t s) {
+              bem_solve_info *info, hipStream_t s, const ObjMaterials *om) {
     solve_check(m, k0, k1, rho, directions, n_waves, tol, o);
+    if (om) check_materials(m, *om);
     if (!solution) fail(BEM_E_INVAL, "solution is NULL");
     const int64_t n2 = 2 * m->N;
     const int s1 = o.formulation == BEM_FORM_MULLER ? -1 : 1;   // Mueller operator
-    const NearOperator &nf = nearfield_get(m, k0, k1, rho, s, s1);
-    const double2 ko = o.osrc_interior ? k1 : k0;
+    const NearOperator &nf = nearfield_get(m, k0, k1, rho, s, s1, om);
+    // OSRC wavenumber of each object: its interior one, or the exterior one
+    std::vector<double2> ko(m->nobj, o.osrc_interior ? k1 : k0);
+    if (om && o.osrc_interior) ko = om->k;
     std::vector<double2> keps(m->nobj);
     for (int ob = 0; ob < m->nobj; ob++)
-        keps[ob] = damped(ko, o.R > 0 ? o.R : 0.1 * m->obj_radius[ob]);
-    OsrcState &st = osrc_get(m, o.pade_terms, o.theta, ko, keps, s);
+        keps[ob] = damped(ko[ob], o.R > 0 ? o.R : 0.1 * m->obj_radius[ob]);
+    OsrcState &st = osrc_get(m, o.pade_terms, o.theta, ko[0], keps, s, &ko);
 
     DevBuf<double2> f((size_t)n_waves * n2);
     rhs_project(m, k0, directions, n_waves, f.p, s);
@@ -358,7 +372,7 @@ int solve_run(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dir
             use = fits && !(tune_find(m->T, std::min(n_waves, SOLVE_BATCH), &te) && te.path == 0);
         }
         if (use) {
-            op.dense = &dense_get(m, k0, k1, rho, s, s1);
+            op.dense = &dense_get(m, k0, k1, rho, s, s1, om);
             inner = BEM_FP32_DENSE;
         }
     }
@@ -484,10 +498,12 @@ void bem_solve_opts_default(bem_solve_opts *o) {
     o->formulation = BEM_FORM_OSRC;
 }
 
-int pmchwt_solve(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
-                 const double *directions, int n_waves, double tol,
-                 const bem_solve_opts *opts_in, bem_c64 *solution, bem_solve_info *info,
-                 void *hip_stream) {
+namespace {
+
+int solve_entry(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
+                const bem::ObjMaterials *om, const double *directions, int n_waves, double tol,
+                const bem_solve_opts *opts_in, bem_c64 *solution, bem_solve_info *info,
+                void *hip_stream) {
     try {
         if (!mesh) fail(BEM_E_INVAL, "mesh is NULL");
         if (!directions || !solution || n_waves < 1) fail(BEM_E_INVAL, "bad directions/solution");
@@ -496,7 +512,7 @@ int pmchwt_solve(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
         if (opts_in) o = *opts_in;
         return bem::solve_run(const_cast<bem_mesh *>(mesh), make_double2(k_ext.re, k_ext.im),
                               make_double2(k_int.re, k_int.im), rho, directions, n_waves, tol, o,
-                              (double2 *)solution, info, (hipStream_t)hip_stream);
+                              (double2 *)solution, info, (hipStream_t)hip_stream, om);
     } catch (const bem::Error &e) {
         bem::set_last_error(e.msg);
         return e.code;
@@ -504,6 +520,33 @@ int pmchwt_solve(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
         bem::set_last_error("host allocation failed");
         return BEM_E_NOMEM;
     }
+}
+
+}   // namespace
+
+int pmchwt_solve(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
+                 const double *directions, int n_waves, double tol,
+                 const bem_solve_opts *opts_in, bem_c64 *solution, bem_solve_info *info,
+                 void *hip_stream) {
+    return solve_entry(mesh, k_ext, k_int, rho, nullptr, directions, n_waves, tol, opts_in,
+                       solution, info, hip_stream);
+}
+
+int pmchwt_solve_multi(const bem_mesh *mesh, bem_c64 k_ext, const bem_c64 *k_int,
+                       const double *rho, const double *directions, int n_waves, double tol,
+                       const bem_solve_opts *opts_in, bem_c64 *solution, bem_solve_info *info,
+                       void *hip_stream) {
+    if (!mesh || !k_int || !rho) {
+        bem::set_last_error("mesh, k_int and rho must not be NULL");
+        return BEM_E_INVAL;
+    }
+    bem::ObjMaterials om;
+    for (int ob = 0; ob < mesh->nobj; ob++) {
+        om.k.push_back(make_double2(k_int[ob].re, k_int[ob].im));
+        om.rho.push_back(rho[ob]);
+    }
+    return solve_entry(mesh, k_ext, k_int[0], rho[0], &om, directions, n_waves, tol, opts_in,
+                       solution, info, hip_stream);
 }
 
 }   // extern "C"

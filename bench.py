@@ -145,7 +145,8 @@ def multi_material_measure(P, RL) -> dict:
     vertices, 20 480 triangles in all).  One FP32 matvec (pair kernel with
     per-object materials) timed over 5 launches, then OSRC-preconditioned
     solves to 1e-6 (FP32 + refinement on the matrix-free and assembled
-    paths), and the PMCHWT and Mueller formulations on the assembled path."""
+    paths), and the PMCHWT, Calderon and Mueller formulations on the assembled
+    path."""
     import torch
     from bem_inputs import complex_normal, density_ratio, four_spheres, wavenumber
     f, a = 5e5, 5e-3
@@ -174,7 +175,8 @@ def multi_material_measure(P, RL) -> dict:
                                                symmetric=P.tune_get("farfield.symmetric") == 1)}
     d = [[1.0, 0.0, 0.0]]
     for name, path, form in (("osrc_fp32", 0, "osrc"), ("osrc_fp32_dense", 1, "osrc"),
-                             ("pmchwt_fp32_dense", 1, "pmchwt"), ("muller_fp32_dense", 1, "muller")):
+                             ("pmchwt_fp32_dense", 1, "pmchwt"), ("calderon_fp32_dense", 1, "calderon"),
+                             ("muller_fp32_dense", 1, "muller")):
         P.pmchwt_solve_multi(M, k0, ks, rs, d, 1e-6, precision="fp32", path=path,
                              formulation=form, maxiter=1)
         torch.cuda.synchronize()

@@ -177,8 +177,7 @@ typedef struct {
                             1 assembled dense complex64 operator, 2 dense when
                             it fits in device memory (default) */
     int formulation;     /* BEM_FORM_OSRC (default), BEM_FORM_PMCHWT,
-                            BEM_FORM_CALDERON (one object only) or
-                            BEM_FORM_MULLER; see below */
+                            BEM_FORM_CALDERON or BEM_FORM_MULLER; see below */
 } bem_solve_opts;
 
 /* Formulations (the four compared in Sec. 3.1), all in strong form (mass
@@ -189,10 +188,12 @@ typedef struct {
  *   BEM_FORM_PMCHWT    M^{-1} B~ u = M^{-1} f, the standard PMCHWT on the
  *                      paper's ordering u = [phi; psi] (Sec. 2.2), B~ u = B x
  *   BEM_FORM_CALDERON  M^{-1} C M^{-1} B~ u = M^{-1} C M^{-1} f, C the
- *                      block-diagonal Calderon preconditioner (Sec. 2.5;
- *                      with one object C = B~ in full); two operator
- *                      applications per iteration.  Meshes with several
- *                      objects: BEM_E_UNSUPPORTED.
+ *                      block-diagonal Calderon preconditioner (Sec. 2.5):
+ *                      each object's own PMCHWT operator A_{0,mm} + A^_m
+ *                      (with one object C = B~ in full; with several, C is
+ *                      applied object by object through a mesh of each
+ *                      object, built on first use and kept with the handle);
+ *                      two operator applications per iteration.
  *   BEM_FORM_MULLER    M^{-1} B~_M u = M^{-1} f, the second-kind Mueller
  *                      formulation (Sec. 2.2, operator of muller_matvec)
  * OSRC, PMCHWT and Calderon solve the same discrete system B x = f; Mueller

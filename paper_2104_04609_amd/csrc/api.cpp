@@ -71,6 +71,8 @@ void mesh_trim(bem_mesh *m) {
     m->trirows.release();
     m->sym_items.release();
     m->sym_plan_id = nullptr;
+    m->parts.clear();
+    m->part_vidx.clear();
 }
 }   // namespace bem
 
@@ -85,6 +87,8 @@ int64_t bem_mesh::device_bytes() const {
     b += xs32.bytes();
     for (const auto &kv : osrc_cache) b += bem::osrc_bytes(*kv.second);
     if (osrc_sym) b += bem::osrc_sym_bytes(*osrc_sym);
+    for (const auto &pm : parts) b += pm->device_bytes();
+    for (const auto &v : part_vidx) b += v.bytes();
     return b;
 }
 

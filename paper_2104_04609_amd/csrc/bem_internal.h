@@ -215,6 +215,12 @@ struct bem_mesh {
     bem::DevBuf<int32_t> sym_items;      // work items of the symmetric pair kernel
     const void *sym_plan_id = nullptr;   // plan whose items sym_items holds
 
+    // each object as a mesh of its own (block-diagonal Calderon
+    // preconditioner; built on first use): part o holds object o's vertices
+    // in ascending global order, part_vidx[o] their global ids
+    std::vector<std::unique_ptr<bem_mesh>> parts;
+    std::vector<bem::DevBuf<int32_t>> part_vidx;
+
     int64_t device_bytes() const;
     ~bem_mesh();
 };
@@ -345,6 +351,8 @@ int64_t solve_footprint(bem_mesh *m, double2 k0, double2 k1, double rho,
 // mesh.cpp: release cached operators and scratch (geometry and the OSRC
 // symbolic analysis stay)
 void mesh_trim(bem_mesh *m);
+// build m->parts / m->part_vidx if not yet built (several objects)
+void mesh_parts(bem_mesh *m);
 // profiling (api.cpp)
 struct Timer {
     hipEvent_t a = nullptr, b = nullptr;

@@ -19,4 +19,11 @@ void blas_normalize(double2 *v, const double2 *nrm2, int64_t n, hipStream_t s);
 void blas_axpby(double2 a, const double2 *x, double2 b, const double2 *y, double2 *out,
                 int64_t n, hipStream_t s);
 
+// sub[r] = [x_r[idx]; x_r[N + idx]] for R vectors (x [R][2N], sub [R][2 nm])
+void gather_halves(const double2 *x, const int32_t *idx, int64_t N, int64_t nm, int R,
+                   double2 *sub, hipStream_t s);
+// the inverse: x_r[idx] = sub_r[:nm], x_r[N + idx] = sub_r[nm:]
+void scatter_halves(const double2 *sub, const int32_t *idx, int64_t N, int64_t nm, int R,
+                    double2 *x, hipStream_t s);
+
 }   // namespace bem

@@ -93,6 +93,47 @@ void blas_normalize(double2 *v, const double2 *nrm2, int64_t n, hipStream_t s) {
     BEM_LAUNCH_CHECK();
 }
 
+namespace {
+
+// one object's entries of R vectors [R][2N]: sub[r] = [x_r[idx]; x_r[N + idx]]
+__global__ __launch_bounds__(256) void gather_halves_kernel(const double2 *__restrict__ x,
+                                                            const int32_t *__restrict__ idx,
+                                                            int64_t N, int64_t nm,
+                                                            double2 *__restrict__ sub) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nm) return;
+    const int64_t r = blockIdx.y, v = idx[i];
+    sub[2 * nm * r + i] = x[2 * N * r + v];
+    sub[2 * nm * r + nm + i] = x[2 * N * r + N + v];
+}
+
+__global__ __launch_bounds__(256) void scatter_halves_kernel(const double2 *__restrict__ sub,
+                                                             const int32_t *__restrict__ idx,
+                                                             int64_t N, int64_t nm,
+                                                             double2 *__restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nm) return;
+    const int64_t r = blockIdx.y, v = idx[i];
+    x[2 * N * r + v] = sub[2 * nm * r + i];
+    x[2 * N * r + N + v] = sub[2 * nm * r + nm + i];
+}
+
+}   // namespace
+
+void gather_halves(const double2 *x, const int32_t *idx, int64_t N, int64_t nm, int R,
+                   double2 *sub, hipStream_t s) {
+    hipLaunchKernelGGL(gather_halves_kernel, dim3(blocks(nm), R), dim3(BT), 0, s, x, idx, N, nm,
+                       sub);
+    BEM_LAUNCH_CHECK();
+}
+
+void scatter_halves(const double2 *sub, const int32_t *idx, int64_t N, int64_t nm, int R,
+                    double2 *x, hipStream_t s) {
+    hipLaunchKernelGGL(scatter_halves_kernel, dim3(blocks(nm), R), dim3(BT), 0, s, sub, idx, N,
+                       nm, x);
+    BEM_LAUNCH_CHECK();
+}
+
 void blas_axpby(double2 a, const double2 *x, double2 b, const double2 *y, double2 *out,
                 int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(axpby_kernel, dim3(blocks(n)), dim3(BT), 0, s, a, x, b, y, out, n);

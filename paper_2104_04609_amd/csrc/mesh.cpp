@@ -307,4 +307,31 @@ void mesh_build(bem_mesh *m, const double *P, int64_t N, const int32_t *tri,
     m->ss_tab.upload(tab);
 }
 
+void mesh_parts(bem_mesh *m) {
+    if (!m->parts.empty()) return;
+    std::vector<int64_t> local(m->N, -1);
+    for (int o = 0; o < m->nobj; o++) {
+        std::vector<int32_t> vid;
+        for (int64_t v = 0; v < m->N; v++)
+            if (m->vobj[v] == o) {
+                local[v] = (int64_t)vid.size();
+                vid.push_back((int32_t)v);
+            }
+        std::vector<double> P(3 * vid.size());
+        for (size_t i = 0; i < vid.size(); i++)
+            for (int c = 0; c < 3; c++) P[3 * i + c] = m->P[3 * (size_t)vid[i] + c];
+        std::vector<int32_t> tri;
+        for (int64_t t = 0; t < m->T; t++)
+            if (m->tobj[t] == o)
+                for (int a = 0; a < 3; a++) tri.push_back((int32_t)local[m->tri[3 * t + a]]);
+        auto pm = std::make_unique<bem_mesh>();
+        mesh_build(pm.get(), P.data(), (int64_t)vid.size(), tri.data(), (int64_t)tri.size() / 3,
+                   nullptr);
+        m->parts.push_back(std::move(pm));
+        DevBuf<int32_t> d;
+        d.upload(vid);
+        m->part_vidx.push_back(std::move(d));
+    }
+}
+
 }   // namespace bem

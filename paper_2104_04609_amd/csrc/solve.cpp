@@ -58,12 +58,41 @@ struct Op {
     hipStream_t s;
     int form = BEM_FORM_OSRC;
     const DenseOperator *dense = nullptr;   // assembled operator (FP32 form)
+    const ObjMaterials *om = nullptr;       // per-object materials, or k1, rho for all
     DevBuf<double2> yw, t1, t2;              // weak-form scratch [R][2N]
+    DevBuf<double2> px, py;                  // one object's entries [R][2 N_m]
     void weak(const double2 *in, double2 *out, int R, int precision) {
         if (precision == BEM_FP32_DENSE) {
             dense_apply(*dense, in, out, R, m->xs32, s);
         } else {
             farfield_apply_batch(m, *nf, k0, k1, rho, in, out, R, precision, s);
+        }
+    }
+    // C y of the block-diagonal Calderon preconditioner on x-ordered vectors:
+    // the whole operator for one object; with several, each object's own
+    // PMCHWT operator (its exterior self-interaction and interior operators)
+    // on its own entries, through the object's mesh of its own
+    void calderon_c(const double2 *in, double2 *out, int R, int precision) {
+        if (m->nobj == 1) {
+            weak(in, out, R, precision);
+            return;
+        }
+        mesh_parts(m);
+        for (int o = 0; o < m->nobj; o++) {
+            bem_mesh *pm = m->parts[o].get();
+            const int64_t nm = pm->N;
+            if (px.n < (size_t)(2 * nm * R)) px.alloc((size_t)(2 * nm * R));
+            if (py.n < (size_t)(2 * nm * R)) py.alloc((size_t)(2 * nm * R));
+            gather_halves(in, m->part_vidx[o].p, m->N, nm, R, px.p, s);
+            const double2 ko = om ? om->k[o] : k1;
+            const double ro = om ? om->rho[o] : rho;
+            if (precision == BEM_FP32_DENSE) {
+                dense_apply(dense_get(pm, k0, ko, ro, s), px.p, py.p, R, pm->xs32, s);
+            } else {
+                const NearOperator &nfo = nearfield_get(pm, k0, ko, ro, s);
+                farfield_apply_batch(pm, nfo, k0, ko, ro, px.p, py.p, R, precision, s);
+            }
+            scatter_halves(py.p, m->part_vidx[o].p, m->N, nm, R, out, s);
         }
     }
     // the preconditioner on a weak-form vector yw -> out; `precision` is the
@@ -81,7 +110,7 @@ struct Op {
             if (t2.n < (size_t)(R * n2)) t2.alloc((size_t)(R * n2));
             osrc_mass_solve(m, *st, w, t1.p, 2 * R, s);
             swap_halves(t1.p, t2.p, m->N, R, s);
-            weak(t2.p, t1.p, R, precision);
+            calderon_c(t2.p, t1.p, R, precision);
             osrc_mass_solve(m, *st, t1.p, t2.p, 2 * R, s);
             swap_halves(t2.p, out, m->N, R, s);
         }
@@ -298,8 +327,6 @@ void solve_check(const bem_mesh *m, double2 k0, double2 k1, double rho, const do
     if (o.path < 0 || o.path > 2) fail(BEM_E_INVAL, "path must be 0, 1 or 2");
     if (o.formulation < BEM_FORM_OSRC || o.formulation > BEM_FORM_MULLER)
         fail(BEM_E_INVAL, "formulation must be 0, 1, 2 or 3");
-    if (o.formulation == BEM_FORM_CALDERON && m->nobj > 1)
-        fail(BEM_E_UNSUPPORTED, "the Calderon formulation supports one object");
     for (int w = 0; w < n_waves; w++) {
         const double *d = dirs + 3 * w;
         if (!(std::fabs(std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) - 1.0) < 1e-6))
@@ -333,7 +360,11 @@ int64_t solve_footprint(bem_mesh *m, double2 k0, double2 k1, double rho,
     if (dense) b += dense_bytes(m) + dense_assembly_scratch_bytes(m) + 2 * G * n2 * 8 +
                     dense_gemm_scratch_bytes(m, G);
     b += ((int64_t)n_waves + 8 * (int64_t)G) * n2 * c16;      // f, B, X, R, D, T, yw, vin, vout
-    if (o.formulation == BEM_FORM_CALDERON) b += 2 * (int64_t)G * n2 * c16;   // t1, t2
+    if (o.formulation == BEM_FORM_CALDERON) {
+        b += 2 * (int64_t)G * n2 * c16;                       // t1, t2
+        if (m->nobj > 1) b += 4 * m->nf_nnz * c16 + G * n2 * c16 +   // parts: near fields, px, py
+                              (dense ? dense_bytes(m) / m->nobj : 0);
+    }
     else if (o.formulation != BEM_FORM_OSRC) b += (int64_t)G * n2 * c16;       // t1
     b += G * (workspace_peak_vectors(o.maxiter) * n2 * c16 + (2 * (int64_t)o.maxiter + 8) * c16);
     return b;
@@ -360,6 +391,7 @@ int solve_run(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dir
     rhs_project(m, k0, directions, n_waves, f.p, s);
     Op op{m, &nf, k0, k1, rho, &st, s};
     op.form = o.formulation;
+    op.om = om;
     int inner = BEM_FP32;
     if (o.precision == BEM_FP32 && o.path != 0) {
         bool use = o.path == 1;

@@ -72,11 +72,36 @@ def test_fp32_refinement(P, path, form):
         assert _rel(sol[w].cpu().numpy(), ref[w].cpu().numpy()) <= 1e-6
 
 
+def test_calderon_several_objects_matches_oracle(P):
+    """Block-diagonal C with several objects (Sec. 2.5): each object's own
+    operator, applied through a mesh of each object; two spheres with one
+    material and four spheres of fat and bone (a material per object)."""
+    import oracle.solve as OS
+    from bem_inputs import density_ratio, four_spheres, wavenumber
+    f, a = 5e5, 5e-3
+    tissue = ["fat", "bone", "bone", "fat"]
+    cases = [(two_spheres(1, offset=1.5), 2.0, 3.5 + 0.2j, 1.3),
+             (four_spheres(1), wavenumber("water", f, a), [wavenumber(t, f, a) for t in tissue],
+              [density_ratio(t) for t in tissue])]
+    for mesh, k0, k1, rho in cases:
+        d = [0.0, 0.6, 0.8]
+        xo, it_o, _ = OS.CalderonPreconditionedSystem(mesh, k0, k1, rho).solve(d, tol=1e-10)
+        M = P.Mesh.from_inputs(mesh)
+        multi = np.ndim(k1) > 0
+        for prec, path in (("fp64", 0), ("fp32", 1)):
+            print(f"calderon {mesh.name} {prec}", flush=True)
+            fn = P.pmchwt_solve_multi if multi else P.pmchwt_solve
+            sol, info, rc = fn(M, k0, k1, rho, [d], 1e-10 if prec == "fp64" else 1e-9,
+                               formulation="calderon", precision=prec, path=path)
+            x = sol.cpu().numpy()[0]
+            print(mesh.name, prec, _rel(x, xo), info[0]["iterations"], it_o)
+            assert rc == 0
+            assert _rel(x, xo) <= (1e-8 if prec == "fp64" else 1e-7)
+            if prec == "fp64":
+                assert abs(info[0]["iterations"] - it_o) <= 3
+
+
 def test_formulation_errors(P):
-    m2 = two_spheres(1, offset=1.5)
-    M2 = P.Mesh.from_inputs(m2)
-    with pytest.raises(P.BemError):
-        P.pmchwt_solve(M2, 2.0, 3.0, 1.5, [[0, 0, 1.0]], 1e-6, formulation="calderon")
     M = P.Mesh.from_inputs(icosphere(1))
     with pytest.raises(P.BemError):
         P.pmchwt_solve(M, 2.0, 3.0, 1.5, [[0, 0, 1.0]], 1e-6, formulation=7)

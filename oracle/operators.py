@@ -141,11 +141,27 @@ def muller_blocks(ops0, ops1, rho, M):
 
 
 def muller_matrix(mesh, k_ext, k_int, rho, n_ss=4):
-    """Weak-form Mueller matrix on the permuted unknowns, complex [2N, 2N]."""
+    """Weak-form Mueller matrix on the permuted unknowns, complex [2N, 2N].
+    k_int, rho: one material, or one per object (object m's interior terms at
+    k_int[m] with rho[m])."""
     from .osrc import mass_matrix
+    M = mass_matrix(mesh).toarray()
     ops0 = assemble(mesh, k_ext, interior=False, n_ss=n_ss)
-    ops1 = assemble(mesh, k_int, interior=True, n_ss=n_ss)
-    return muller_blocks(ops0, ops1, rho, mass_matrix(mesh).toarray())
+    if np.ndim(k_int) == 0 and np.ndim(rho) == 0:
+        ops1 = assemble(mesh, k_int, interior=True, n_ss=n_ss)
+        return muller_blocks(ops0, ops1, rho, M)
+    B11, B12 = ops0["V"].copy(), M - ops0["K"]
+    B21, B22 = M + ops0["Kp"], ops0["D"].copy()
+    vobj = vertex_objects(mesh)
+    for m in range(mesh.n_objects()):
+        ops1 = assemble(mesh, k_int[m], interior=True, n_ss=n_ss)
+        sel = vobj == m
+        mask = np.outer(sel, sel)
+        B11 = B11 - rho[m] * ops1["V"] * mask
+        B12 = B12 + ops1["K"] * mask
+        B21 = B21 - ops1["Kp"] * mask
+        B22 = B22 - ops1["D"] / rho[m] * mask
+    return np.block([[B11, B12], [B21, B22]])
 
 
 def _matvec_tris(mesh, k, interior, test, xs, n_ss=4):

@@ -43,6 +43,32 @@ __device__ inline double qb(int i, int a) {
 
 constexpr double INV4PI = 0.079577471545947667884441881686257;
 constexpr double TWO_PI = 6.283185307179586476925286766559;
+constexpr double INV2PI = 0.15915494309189533576888376337251;
+
+// sin and cos of 2 pi t from a table of e^{2 pi i n / 256} (n = nearest
+// integer to 256 t) and the Taylor series of the remainder 2 pi f, |f| <=
+// 1/512 (terms beyond x^6 below 4e-18), joined by one complex product
+__device__ __forceinline__ void sincos_turns(double t, double &s, double &c,
+                                             const double2 *__restrict__ tab) {
+    const double n = __builtin_rint(256.0 * t);
+    const double x = __builtin_fma(-0.00390625, n, t) * TWO_PI;
+    const double x2 = x * x;
+    const double sn = __builtin_fma(__builtin_fma(x2, 1.0 / 120.0, -1.0 / 6.0), x2, 1.0) * x;
+    const double cs =
+        __builtin_fma(__builtin_fma(__builtin_fma(x2, -1.0 / 720.0, 1.0 / 24.0), x2, -0.5), x2, 1.0);
+    const double2 e = tab[((int64_t)n) & 255];
+    c = __builtin_fma(e.x, cs, -e.y * sn);
+    s = __builtin_fma(e.y, cs, e.x * sn);
+}
+
+// 1/sqrt(x): hardware estimate and two Newton steps
+__device__ __forceinline__ double rsq64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * __builtin_fma(-h * y, y, 1.5);
+    y = y * __builtin_fma(-h * y, y, 1.5);
+    return y;
+}
 
 // per triangle: the 6 rule points, w |sigma| psi_h and w |sigma| phi_h there
 constexpr int SRC_STRIDE = 42;   // [0,18) points, [18,30) s_psi, [30,42) s_phi
@@ -160,6 +186,13 @@ __global__ __launch_bounds__(256) void field_kernel(
     const int32_t *__restrict__ region, int64_t n, double2 k0, const double *__restrict__ omat,
     double *__restrict__ part) {
     __shared__ double tile[FT * FS];
+    __shared__ double2 etab[256];   // e^{2 pi i n / 256}
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) {
+        double sn, cs;
+        sincos(i * (TWO_PI / 256.0), &sn, &cs);
+        etab[i] = make_double2(cs, sn);
+    }
+    // (the first tile's barrier orders these writes before any read)
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t pp = p < n ? p : 0;
     const double px = pts[3 * pp], py = pts[3 * pp + 1], pz = pts[3 * pp + 2];
@@ -167,6 +200,7 @@ __global__ __launch_bounds__(256) void field_kernel(
     const bool ext = reg == 0;
     // interior material of the enclosing object: omat[object] = (Re k, Im k, rho)
     const double2 k = ext ? k0 : make_double2(omat[3 * (reg - 1)], omat[3 * (reg - 1) + 1]);
+    const double krev = k.x * INV2PI;
     const int t0 = blockIdx.y * split_len, t1 = min(T, t0 + split_len);
     double sr = 0, si = 0, dr = 0, di = 0;
     for (int base = t0; base < t1; base += FT) {
@@ -192,15 +226,16 @@ __global__ __launch_bounds__(256) void field_kernel(
             double fr = 0, fi = 0;
             for (int q = 0; q < 6; q++) {
                 const double ex = s[3 * q] - px, ey = s[3 * q + 1] - py, ez = s[3 * q + 2] - pz;
-                const double r = sqrt(ex * ex + ey * ey + ez * ez);
-                const double ri = 1.0 / r;
+                const double r2 = ex * ex + ey * ey + ez * ez;
+                const double ri = rsq64(r2);
+                const double r = r2 * ri;
                 double sn, cs;
-                sincos(k.x * r, &sn, &cs);
+                sincos_turns(krev * r, sn, cs, etab);
                 const double mag = (k.y != 0.0 ? exp(-k.y * r) : 1.0) * ri;
                 const double Gr = cs * mag, Gi = sn * mag;     // 4 pi G
                 // 4 pi G (i k r - 1) / r^2
                 const double tr = -1.0 - k.y * r, ti = k.x * r;
-                const double ri2 = ri * ri;
+                const double ri2 = ri * ri;   // (= 1 / r2)
                 const double Fr = (Gr * tr - Gi * ti) * ri2, Fi = (Gr * ti + Gi * tr) * ri2;
                 const double ar = s[18 + 2 * q], ai = s[18 + 2 * q + 1];
                 const double br = s[30 + 2 * q], bi = s[30 + 2 * q + 1];

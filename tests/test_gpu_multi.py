@@ -173,3 +173,20 @@ def test_multi_invalid_materials(P):
         P.pmchwt_matvec_multi(M, 2.0, [3.0, 0.0], [1.5, 1.0], x)
     with pytest.raises(ValueError):
         P.pmchwt_matvec_multi(M, 2.0, [3.0], [1.5], x)
+
+
+def test_muller_solve_multi_matches_oracle(P):
+    """Mueller formulation with a material per object: four spheres of fat
+    and bone against the oracle's Mueller solve."""
+    from oracle.operators import muller_matrix
+    from oracle.solve import MullerSystem
+    m, k0, ks, rs = CASES["four_spheres1_tissue"]()
+    d = [1.0, 0.0, 0.0]
+    S = MullerSystem(m, k0, ks, rs, B=muller_matrix(m, k0, ks, rs))
+    xo, it_o, _ = S.solve(d, tol=1e-10)
+    M = P.Mesh.from_inputs(m)
+    sol, info, rc = P.pmchwt_solve_multi(M, k0, ks, rs, [d], 1e-10, formulation="muller")
+    x = sol.cpu().numpy()[0]
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    print("muller multi", err, info[0]["iterations"], it_o)
+    assert rc == 0 and err <= 1e-8 and abs(info[0]["iterations"] - it_o) <= 3

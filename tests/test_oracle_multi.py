@@ -7,7 +7,9 @@ bone):
   alone with its own (k_m, rho_m), and the blocks coupling two objects hold
   the exterior operators only;
 * the OSRC-preconditioned GMRES solution (OSRC wavenumber and damping per
-  object) solves B x = f.
+  object) solves B x = f;
+* the Mueller matrix with a material per object has the single-sphere
+  Mueller matrices as its object blocks.
 """
 import numpy as np
 
@@ -58,3 +60,19 @@ def test_multi_material_solve_solves_the_weak_system():
     xd = np.linalg.solve(S.B, f)
     print(it, _rel(x, xd))
     assert _rel(x, xd) < 1e-8 and it < 100
+
+
+def test_muller_per_object_blocks():
+    """Mueller with a material per object: each object's block is that
+    sphere's Mueller matrix assembled alone; one material reduces to
+    muller_matrix."""
+    from oracle.operators import muller_matrix
+    m = two_spheres(1, offset=1.5)
+    N = m.n_vertices
+    h = N // 2
+    B = muller_matrix(m, K0, KS, RHOS)
+    assert _rel(muller_matrix(m, K0, [3.0, 3.0], [1.5, 1.5]), muller_matrix(m, K0, 3.0, 1.5)) < 1e-14
+    for o, c in enumerate([(0.0, -1.5, 0.0), (0.0, 1.5, 0.0)]):
+        Bs = muller_matrix(icosphere(1, 1.0, centre=c), K0, KS[o], RHOS[o])
+        idx = np.concatenate([np.arange(o * h, (o + 1) * h), N + np.arange(o * h, (o + 1) * h)])
+        assert _rel(B[np.ix_(idx, idx)], Bs) < 1e-13

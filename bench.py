@@ -191,6 +191,46 @@ def multi_material_measure(P, RL) -> dict:
     return out
 
 
+def frequency_sweep(P) -> dict:
+    """GMRES iterations against frequency (the paper's frequency-dependency
+    test, Sec. 3): a sphere of radius 5 mm in water, interior fat or bone
+    (Table 1 media), 0.5 - 2.5 MHz, about six elements per wavelength (geodesic
+    spheres of 10 n^2 + 2 vertices near the paper's node counts), plane wave
+    along +z, tolerance 1e-7 on the preconditioned residual (Sec. 3.1).  Every
+    formulation: PMCHWT, Mueller, Calderon, OSRC with the interior and with the
+    exterior wavenumber; FP32 assembled operator + FP64 refinement, so the
+    count is the total of the inner GMRES iterations."""
+    import torch
+    from bem_inputs import density_ratio, geodesic_sphere, wavenumber
+    a = 5e-3
+    sizes = {0.5e6: 13, 1.0e6: 27, 1.5e6: 40, 2.0e6: 52, 2.5e6: 65}
+    forms = (("pmchwt", "pmchwt", 1), ("muller", "muller", 1), ("calderon", "calderon", 1),
+             ("osrc_int", "osrc", 1), ("osrc_ext", "osrc", 0))
+    out = []
+    for f, n in sizes.items():
+        mesh = geodesic_sphere(n)
+        M = P.Mesh.from_inputs(mesh)
+        k0 = wavenumber("water", f, a)
+        for medium in ("fat", "bone"):
+            k1, rho = wavenumber(medium, f, a), density_ratio(medium)
+            row = {"f_MHz": f / 1e6, "medium": medium, "n_vertices": mesh.n_vertices}
+            for name, form, interior in forms:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info, rc = P.pmchwt_solve(M, k0, k1, rho, [[0.0, 0.0, 1.0]], 1e-7,
+                                             precision="fp32", path=1, formulation=form,
+                                             osrc_interior=interior)
+                torch.cuda.synchronize()
+                row[name] = {"iterations": info[0]["iterations"],
+                             "outer_steps": info[0]["outer_steps"],
+                             "seconds": time.perf_counter() - t0, "rc": rc}
+            out.append(row)
+            print("sweep " + json.dumps(row), file=sys.stderr, flush=True)
+        del M
+        P.tune_clear()
+    return {"frequency_sweep": out}
+
+
 def serving_measure(P, n_requests: int, workers: int = 4, seed: int = 5) -> dict:
     """Serving mix: meshes {icosphere L3, L4, L5, ellipsoid (geodesic 45
     scaled by (1, 0.6, 0.4)), two level-4 spheres}, k_ext ~ U[1, 20],
@@ -277,6 +317,8 @@ def main():
     ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--serving", type=int, default=32, metavar="N",
                     help="requests of the serving mix to replay (0: skip)")
+    ap.add_argument("--frequency-sweep", action="store_true",
+                    help="only the iteration-count sweep over frequency (one JSON line)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB read + 256 MiB write elementwise kernel 3 times, "
                          "to scale HBM byte counters (FETCH_SIZE, WRITE_SIZE)")
@@ -290,6 +332,10 @@ def main():
     import paper_2104_04609_amd as P
     from paper_2104_04609_amd import roofline as RL
     from bem_inputs import complex_normal, icosphere
+
+    if args.frequency_sweep:
+        print(json.dumps(frequency_sweep(P)), flush=True)
+        return
 
     mesh = icosphere(5)
     N, T = mesh.n_vertices, mesh.n_triangles

@@ -165,13 +165,20 @@ def two_spheres(level: int = 4, offset: float = 1.5,
     return Mesh(P, T, oid, name=f"two_spheres{level}", radius=float(radius))
 
 
-def four_spheres(level: int = 2, radius: float = 1.0) -> Mesh:
+def four_spheres(level: int = 2, radius: float = 1.0, geodesic: int = 0) -> Mesh:
     """Four disjoint spheres of the given radius with centres at
     (+-3, +-1.5, 0) radii: the layout of the paper's multiple-scattering test
     (radius 5 mm, centres (+-15, +-7.5, 0) mm) in units of the radius.
-    Objects 0..3 in the order (-3,-1.5), (3,-1.5), (-3,1.5), (3,1.5)."""
-    parts = [icosphere(level, radius, centre=(sx * 3.0 * radius, sy * 1.5 * radius, 0.0))
-             for sy in (-1, 1) for sx in (-1, 1)]
+    Objects 0..3 in the order (-3,-1.5), (3,-1.5), (-3,1.5), (3,1.5).  Each
+    sphere is an icosphere of the given level, or with geodesic > 0 a
+    geodesic sphere of 10 geodesic^2 + 2 vertices."""
+    centres = [(sx * 3.0 * radius, sy * 1.5 * radius, 0.0) for sy in (-1, 1) for sx in (-1, 1)]
+    if geodesic > 0:
+        g = geodesic_sphere(geodesic, radius)
+        parts = [Mesh(g.vertices + np.asarray(c), g.triangles.copy(), None, name=g.name,
+                      radius=float(radius)) for c in centres]
+    else:
+        parts = [icosphere(level, radius, centre=c) for c in centres]
     P, T, oid, off = [], [], [], 0
     for o, p in enumerate(parts):
         P.append(p.vertices)
@@ -179,4 +186,5 @@ def four_spheres(level: int = 2, radius: float = 1.0) -> Mesh:
         oid.append(np.full(p.n_triangles, o, np.int32))
         off += p.n_vertices
     return Mesh(np.vstack(P), np.vstack(T).astype(np.int32), np.concatenate(oid),
-                name=f"four_spheres{level}", radius=float(radius))
+                name=f"four_spheres{level}" if geodesic <= 0 else f"four_spheres_g{geodesic}",
+                radius=float(radius))

@@ -199,9 +199,10 @@ def frequency_sweep(P) -> dict:
     along +z, tolerance 1e-7 on the preconditioned residual (Sec. 3.1).  Every
     formulation: PMCHWT, Mueller, Calderon, OSRC with the interior and with the
     exterior wavenumber; FP32 assembled operator + FP64 refinement, so the
-    count is the total of the inner GMRES iterations."""
+    count is the total of the inner GMRES iterations.  Then the four-sphere
+    layout (two fat, two bone) at 0.5 - 1.5 MHz, wave along +x."""
     import torch
-    from bem_inputs import density_ratio, geodesic_sphere, wavenumber
+    from bem_inputs import density_ratio, four_spheres, geodesic_sphere, wavenumber
     a = 5e-3
     sizes = {0.5e6: 13, 1.0e6: 27, 1.5e6: 40, 2.0e6: 52, 2.5e6: 65}
     forms = (("pmchwt", "pmchwt", 1), ("muller", "muller", 1), ("calderon", "calderon", 1),
@@ -228,7 +229,31 @@ def frequency_sweep(P) -> dict:
             print("sweep " + json.dumps(row), file=sys.stderr, flush=True)
         del M
         P.tune_clear()
-    return {"frequency_sweep": out}
+    # the four-sphere test (two fat, two bone; 6 823 / 26 801 / 59 758 nodes at
+    # 0.5 / 1 / 1.5 MHz in the paper; 2 MHz would need a 340 GB assembled operator)
+    four = []
+    tissue = ["fat", "bone", "bone", "fat"]
+    for f, n in {0.5e6: 13, 1.0e6: 26, 1.5e6: 39}.items():
+        mesh = four_spheres(geodesic=n)
+        M = P.Mesh.from_inputs(mesh)
+        k0 = wavenumber("water", f, a)
+        ks = [wavenumber(t, f, a) for t in tissue]
+        rs = [density_ratio(t) for t in tissue]
+        row = {"f_MHz": f / 1e6, "n_vertices": mesh.n_vertices}
+        for name, form, interior in forms:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info, rc = P.pmchwt_solve_multi(M, k0, ks, rs, [[1.0, 0.0, 0.0]], 1e-7,
+                                               precision="fp32", path=1, formulation=form,
+                                               osrc_interior=interior)
+            torch.cuda.synchronize()
+            row[name] = {"iterations": info[0]["iterations"], "outer_steps": info[0]["outer_steps"],
+                         "seconds": time.perf_counter() - t0, "rc": rc}
+        four.append(row)
+        print("sweep four spheres " + json.dumps(row), file=sys.stderr, flush=True)
+        del M
+        P.tune_clear()
+    return {"frequency_sweep": out, "four_spheres": four}
 
 
 def serving_measure(P, n_requests: int, workers: int = 4, seed: int = 5) -> dict:

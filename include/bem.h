@@ -171,7 +171,7 @@ typedef struct {
     int maxiter;         /* GMRES iterations cap (total), default 1000 */
     double inner_tol;    /* FP32 form: each inner GMRES stops at an absolute
                             residual inner_tol * tol * ||b|| (at most half of
-                            the current outer residual); default 0.3 */
+                            the current outer residual); default 0.6 */
     int max_outer;       /* refinement steps cap, default 8 */
     int path;            /* FP32 form inner operator: 0 matrix-free pair kernel,
                             1 assembled dense complex64 operator, 2 dense when

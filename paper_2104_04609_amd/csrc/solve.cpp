@@ -524,7 +524,7 @@ void bem_solve_opts_default(bem_solve_opts *o) {
     o->R = 0;
     o->precision = BEM_FP64;
     o->maxiter = 1000;
-    o->inner_tol = 0.3;
+    o->inner_tol = 0.6;
     o->max_outer = 8;
     o->path = 2;
     o->formulation = BEM_FORM_OSRC;

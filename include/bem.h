@@ -355,6 +355,12 @@ int bem_server_submit(bem_server *srv, int mesh_id, bem_c64 k_ext, bem_c64 k_int
                       const double *directions, int n_waves, double tol,
                       const bem_solve_opts *opts, bem_c64 *solution, bem_solve_info *info,
                       int64_t *request_id);
+/* bem_server_submit for objects of different materials (see
+ * pmchwt_matvec_multi): k_int, rho host arrays [n_objects], copied. */
+int bem_server_submit_multi(bem_server *srv, int mesh_id, bem_c64 k_ext, const bem_c64 *k_int,
+                            const double *rho, const double *directions, int n_waves, double tol,
+                            const bem_solve_opts *opts, bem_c64 *solution, bem_solve_info *info,
+                            int64_t *request_id);
 /* Wait up to timeout_s seconds (< 0: forever).  Returns BEM_OK when the
  * request has completed (its status, timing and path in *stats; the request
  * is then forgotten), BEM_W_PENDING on time-out, BEM_E_INVAL for an unknown

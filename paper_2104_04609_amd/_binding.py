@@ -136,6 +136,9 @@ lib.bem_server_add_mesh.argtypes = [_vp, _vp, _i64, _vp, _i64, _vp, ctypes.POINT
 lib.bem_server_submit.argtypes = [_vp, ctypes.c_int, c64, c64, ctypes.c_double, _vp, ctypes.c_int,
                                   ctypes.c_double, ctypes.POINTER(SolveOpts), _vp, _vp,
                                   ctypes.POINTER(_i64)]
+lib.bem_server_submit_multi.argtypes = [_vp, ctypes.c_int, c64, _vp, _vp, _vp, ctypes.c_int,
+                                        ctypes.c_double, ctypes.POINTER(SolveOpts), _vp, _vp,
+                                        ctypes.POINTER(_i64)]
 lib.bem_server_wait.argtypes = [_vp, _i64, ctypes.c_double, ctypes.POINTER(RequestStats)]
 lib.bem_server_stats_get.argtypes = [_vp, ctypes.POINTER(ServerStats)]
 lib.bem_last_error.restype = ctypes.c_char_p
@@ -432,15 +435,29 @@ class Server:
         for k, v in overrides.items():
             if k == "precision":
                 v = _PREC[v]
+            if k == "formulation" and isinstance(v, str):
+                v = FORMULATIONS[v]
             setattr(o, k, v)
         n = self._meshes.get(mesh_id, 1)   # an unknown id is rejected by the library
         sol = torch.empty((d.shape[0], 2 * n), dtype=torch.complex128, device="cuda")
         infos = (SolveInfo * d.shape[0])()
         rid = _i64()
-        _check(lib.bem_server_submit(self._h, int(mesh_id), _c(k_ext), _c(k_int), float(rho),
-                                     _np_ptr(d), d.shape[0], float(tol), ctypes.byref(o),
-                                     _vp(sol.data_ptr()), ctypes.cast(infos, _vp),
-                                     ctypes.byref(rid)))
+        if np.ndim(k_int) > 0 or np.ndim(rho) > 0:   # a material per object
+            k = np.atleast_1d(np.asarray(k_int, dtype=np.complex128))
+            kc = (c64 * len(k))(*[c64(v.real, v.imag) for v in k])
+            rc = np.ascontiguousarray(np.atleast_1d(rho), dtype=np.float64)
+            if len(k) != len(rc):
+                raise ValueError("k_int and rho need one entry per object")
+            _check(lib.bem_server_submit_multi(self._h, int(mesh_id), _c(k_ext),
+                                               ctypes.cast(kc, _vp), _np_ptr(rc), _np_ptr(d),
+                                               d.shape[0], float(tol), ctypes.byref(o),
+                                               _vp(sol.data_ptr()), ctypes.cast(infos, _vp),
+                                               ctypes.byref(rid)))
+        else:
+            _check(lib.bem_server_submit(self._h, int(mesh_id), _c(k_ext), _c(k_int), float(rho),
+                                         _np_ptr(d), d.shape[0], float(tol), ctypes.byref(o),
+                                         _vp(sol.data_ptr()), ctypes.cast(infos, _vp),
+                                         ctypes.byref(rid)))
         self._pending[rid.value] = (sol, infos)
         return rid.value
 

@@ -44,6 +44,8 @@ struct Request {
     int mesh = 0;
     double2 k0{}, k1{};
     double rho = 0, tol = 0;
+    bool per_object = false;   // om holds a material per object
+    ObjMaterials om;
     std::vector<double> dirs;
     int n_waves = 0;
     bem_solve_opts o{};
@@ -212,7 +214,8 @@ struct bem_server {
             try {
                 if (!rep->h) rep->h = bem::create_handle(me);
                 status = bem::solve_run(rep->h, r->k0, r->k1, r->rho, r->dirs.data(), r->n_waves,
-                                        r->tol, r->o, r->solution, r->info, s);
+                                        r->tol, r->o, r->solution, r->info, s,
+                                        r->per_object ? &r->om : nullptr);
             } catch (const bem::Error &e) {
                 status = e.code;
                 msg = e.msg;
@@ -352,10 +355,12 @@ int bem_server_add_mesh(bem_server *srv, const double *vertices, int64_t n_verti
     }
 }
 
-int bem_server_submit(bem_server *srv, int mesh_id, bem_c64 k_ext, bem_c64 k_int, double rho,
-                      const double *directions, int n_waves, double tol,
-                      const bem_solve_opts *opts, bem_c64 *solution, bem_solve_info *info,
-                      int64_t *request_id) {
+namespace {
+
+int server_submit(bem_server *srv, int mesh_id, bem_c64 k_ext, bem_c64 k_int, double rho,
+                  const bem_c64 *k_obj, const double *rho_obj, const double *directions,
+                  int n_waves, double tol, const bem_solve_opts *opts, bem_c64 *solution,
+                  bem_solve_info *info, int64_t *request_id) {
     int prev = -1;
     try {
         if (!srv || !request_id) fail(BEM_E_INVAL, "server or request_id is NULL");
@@ -379,6 +384,15 @@ int bem_server_submit(bem_server *srv, int mesh_id, bem_c64 k_ext, bem_c64 k_int
         bem_solve_opts_default(&r->o);
         if (opts) r->o = *opts;
         bem::solve_check(h0, r->k0, r->k1, rho, directions, n_waves, tol, r->o);
+        if (k_obj) {
+            if (!rho_obj) fail(BEM_E_INVAL, "rho is NULL");
+            r->per_object = true;
+            for (int ob = 0; ob < h0->nobj; ob++) {
+                r->om.k.push_back(make_double2(k_obj[ob].re, k_obj[ob].im));
+                r->om.rho.push_back(rho_obj[ob]);
+            }
+            bem::check_materials(h0, r->om);
+        }
         r->dirs.assign(directions, directions + 3 * n_waves);
         r->solution = (double2 *)solution;
         r->info = info;
@@ -413,6 +427,28 @@ int bem_server_submit(bem_server *srv, int mesh_id, bem_c64 k_ext, bem_c64 k_int
         bem::set_last_error("host allocation failed");
         return BEM_E_NOMEM;
     }
+}
+
+}   // namespace
+
+int bem_server_submit(bem_server *srv, int mesh_id, bem_c64 k_ext, bem_c64 k_int, double rho,
+                      const double *directions, int n_waves, double tol,
+                      const bem_solve_opts *opts, bem_c64 *solution, bem_solve_info *info,
+                      int64_t *request_id) {
+    return server_submit(srv, mesh_id, k_ext, k_int, rho, nullptr, nullptr, directions, n_waves,
+                         tol, opts, solution, info, request_id);
+}
+
+int bem_server_submit_multi(bem_server *srv, int mesh_id, bem_c64 k_ext, const bem_c64 *k_int,
+                            const double *rho, const double *directions, int n_waves, double tol,
+                            const bem_solve_opts *opts, bem_c64 *solution, bem_solve_info *info,
+                            int64_t *request_id) {
+    if (!k_int || !rho) {
+        bem::set_last_error("k_int and rho must not be NULL");
+        return BEM_E_INVAL;
+    }
+    return server_submit(srv, mesh_id, k_ext, k_int[0], rho[0], k_int, rho, directions, n_waves,
+                         tol, opts, solution, info, request_id);
 }
 
 int bem_server_wait(bem_server *srv, int64_t request_id, double timeout_s,

@@ -99,6 +99,29 @@ def test_server_matches_direct_solve(P):
     assert [x["iterations"] for x in infos] == [x["iterations"] for x in info]
 
 
+def test_server_per_object_materials_and_formulation(P):
+    """A request with a material per object and another formulation equals
+    the direct pmchwt_solve_multi bitwise."""
+    import torch
+    m = MESHES["two2"]()
+    k0, ks, rs = 2.0, [3.2, 4.0 + 0.3j], [1.7, 0.9]
+    d = _dirs(2, 17)
+    M = P.Mesh.from_inputs(m)
+    srv = P.Server(workers=2)
+    mid = srv.add_mesh(m.vertices, m.triangles, m.object_id)
+    for form in ("osrc", "calderon"):
+        ref, info, rc = P.pmchwt_solve_multi(M, k0, ks, rs, d, 1e-8, precision="fp32", path=1,
+                                             formulation=form)
+        rid = srv.submit(mid, k0, ks, rs, d, 1e-8, precision="fp32", path=1, formulation=form)
+        sol, infos, st = srv.wait(rid)
+        assert rc == 0 and st["status"] == 0
+        assert torch.equal(sol, ref), form
+        assert [x["iterations"] for x in infos] == [x["iterations"] for x in info]
+    with pytest.raises(P.BemError):
+        srv.submit(mid, k0, [3.2, 4.0], [1.7, -1.0], d, 1e-8)
+    srv.close()
+
+
 def test_budget_admission_and_rejection(P):
     m3, m5 = icosphere(3), icosphere(5)
     srv = P.Server(hbm_budget=160 << 20, workers=2)

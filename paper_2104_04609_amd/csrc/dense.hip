@@ -293,6 +293,73 @@ __global__ __launch_bounds__(256) void dense_gemv_kernel(const float2 *__restric
         for (int r = 0; r < NR; r++) y[r * ystride + row] = make_double2(sr[r], si[r]);
 }
 
+// y = B x for one vector: GEMV1_ROWS rows per wavefront (each chunk of x, read from
+// cache, serves them all), 16-byte loads (two complex entries; 2N is even, so
+// every row starts 16-byte aligned), eight loads of each row in flight per
+// lane, B streamed with non-temporal loads.  FP32 partial sums over chunks
+// of 1024 entries are added in FP64, then a fixed-order wave reduction.
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+constexpr int GEMV1_ROWS = 4;   // rows per wavefront
+
+__global__ __launch_bounds__(256) void dense_gemv1_kernel(const float2 *__restrict__ B,
+                                                          int64_t n2,
+                                                          const float2 *__restrict__ x,
+                                                          double2 *__restrict__ y) {
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * GEMV1_ROWS;
+    const int lane = threadIdx.x & 63;
+    if (row0 >= n2) return;
+    const int nrow = n2 - row0 < GEMV1_ROWS ? (int)(n2 - row0) : GEMV1_ROWS;
+    const fvec4 *b4[GEMV1_ROWS];
+    for (int q = 0; q < GEMV1_ROWS; q++)
+        b4[q] = reinterpret_cast<const fvec4 *>(B + (row0 + (q < nrow ? q : 0)) * n2);
+    const fvec4 *x4 = reinterpret_cast<const fvec4 *>(x);
+    const int64_t n4 = n2 / 2;
+    double sr[GEMV1_ROWS], si[GEMV1_ROWS];
+    for (int q = 0; q < GEMV1_ROWS; q++) sr[q] = si[q] = 0.0;
+    int64_t c0 = 0;
+    for (; c0 + 512 <= n4; c0 += 512) {
+        fvec4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) v[u] = x4[c0 + u * 64 + lane];
+#pragma unroll
+        for (int q = 0; q < GEMV1_ROWS; q++) {
+            fvec4 a[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) a[u] = __builtin_nontemporal_load(b4[q] + c0 + u * 64 + lane);
+            float pr = 0.f, pi = 0.f;
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                pr += a[u].x * v[u].x - a[u].y * v[u].y;
+                pi += a[u].x * v[u].y + a[u].y * v[u].x;
+                pr += a[u].z * v[u].z - a[u].w * v[u].w;
+                pi += a[u].z * v[u].w + a[u].w * v[u].z;
+            }
+            sr[q] += pr;
+            si[q] += pi;
+        }
+    }
+    for (int q = 0; q < GEMV1_ROWS; q++) {
+        float pr = 0.f, pi = 0.f;
+        for (int64_t c = c0 + lane; c < n4; c += 64) {
+            const fvec4 a = __builtin_nontemporal_load(b4[q] + c);
+            const fvec4 v = x4[c];
+            pr += a.x * v.x - a.y * v.y;
+            pi += a.x * v.y + a.y * v.x;
+            pr += a.z * v.z - a.w * v.w;
+            pi += a.z * v.w + a.w * v.z;
+        }
+        sr[q] += pr;
+        si[q] += pi;
+    }
+    for (int q = 0; q < GEMV1_ROWS; q++)
+        for (int o = 32; o > 0; o >>= 1) {
+            sr[q] += __shfl_xor(sr[q], o, 64);
+            si[q] += __shfl_xor(si[q], o, 64);
+        }
+    if (lane == 0)
+        for (int q = 0; q < nrow; q++) y[row0 + q] = make_double2(sr[q], si[q]);
+}
+
 // ------------------------------------------------ multi-RHS product on MFMA
 // Y = B X for n_rhs right-hand sides as one real FP32 GEMM: B is read as a
 // real [M][Kp] matrix (M = 2N rows, Kp = 4N: re/im interleaved), X as the
@@ -647,7 +714,11 @@ void dense_gemv(const DenseOperator &op, const double2 *x, double2 *y, int R, De
             Timer tm("dense_gemv", s);
             double2 *yr = y + r0 * n2;
             switch (nr) {
-            case 1: launch_gemv<1>(op, xs.p, yr, s); break;
+            case 1:
+                hipLaunchKernelGGL(dense_gemv1_kernel,
+                                   dim3((unsigned)((n2 + 4 * GEMV1_ROWS - 1) / (4 * GEMV1_ROWS))),
+                                   dim3(256), 0, s, op.B.p, n2, xs.p, yr);
+                break;
             case 2: launch_gemv<2>(op, xs.p, yr, s); break;
             case 3: launch_gemv<3>(op, xs.p, yr, s); break;
             case 4: launch_gemv<4>(op, xs.p, yr, s); break;

@@ -393,7 +393,7 @@ int bem_profile_read(const char *kernel, double *total_ms, int64_t *launches);
  *   "dense.skinny_min_rhs" right-hand-side count (>= 2) from which products
  *                         with the assembled operator below gemm_min use the
  *                         16-column MFMA kernel instead of the multi-vector
- *                         GEMV (default 5)
+ *                         GEMV (default 8)
  *   "dense.gemm_min_rhs"  right-hand-side count from which the assembled
  *                         operator is applied with the MFMA product instead of
  *                         the multi-vector product (default 16)

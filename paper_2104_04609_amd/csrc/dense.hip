@@ -31,6 +31,8 @@ __host__ __device__ constexpr double qb(int i, int a) {
     return (a == i % 3) ? (1.0 - 2.0 * (i < 3 ? DUN_A1 : DUN_A2)) : (i < 3 ? DUN_A1 : DUN_A2);
 }
 
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+
 constexpr int JT = 512;   // trial vertices per assembly tile
 
 // interior coefficients of one object (several objects: a per-object table)
@@ -260,23 +262,49 @@ __global__ __launch_bounds__(256) void dense_gemv_kernel(const float2 *__restric
                                                          const float2 *__restrict__ x,
                                                          double2 *__restrict__ y,
                                                          int64_t ystride) {
+    // one row per wavefront; 16-byte loads (two complex entries; 2N is even,
+    // so rows and vectors start 16-byte aligned), four loads of B in flight
+    // per lane, B streamed with non-temporal loads; FP32 partial sums over
+    // chunks of 512 entries added in FP64, fixed-order wave reduction
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= n2) return;
-    const float2 *b = B + row * n2;
+    const fvec4 *b4 = reinterpret_cast<const fvec4 *>(B + row * n2);
+    const fvec4 *x4 = reinterpret_cast<const fvec4 *>(x);
+    const int64_t n4 = n2 / 2;
     double sr[NR], si[NR];
     for (int r = 0; r < NR; r++) sr[r] = si[r] = 0.0;
-    for (int64_t c0 = 0; c0 < n2; c0 += 64 * 16) {
+    int64_t c0 = 0;
+    for (; c0 + 256 <= n4; c0 += 256) {
+        fvec4 a[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) a[u] = __builtin_nontemporal_load(b4 + c0 + u * 64 + lane);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            float pr = 0.f, pi = 0.f;
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const fvec4 v = x4[r * n4 + c0 + u * 64 + lane];
+                pr += a[u].x * v.x - a[u].y * v.y;
+                pi += a[u].x * v.y + a[u].y * v.x;
+                pr += a[u].z * v.z - a[u].w * v.w;
+                pi += a[u].z * v.w + a[u].w * v.z;
+            }
+            sr[r] += pr;
+            si[r] += pi;
+        }
+    }
+    {
         float pr[NR], pi[NR];
         for (int r = 0; r < NR; r++) pr[r] = pi[r] = 0.f;
-        const int64_t c1 = c0 + 64 * 16 < n2 ? c0 + 64 * 16 : n2;
-        for (int64_t c = c0 + lane; c < c1; c += 64) {
-            const float2 a = b[c];
-#pragma unroll
+        for (int64_t c = c0 + lane; c < n4; c += 64) {
+            const fvec4 a = __builtin_nontemporal_load(b4 + c);
             for (int r = 0; r < NR; r++) {
-                const float2 v = x[r * n2 + c];
+                const fvec4 v = x4[r * n4 + c];
                 pr[r] += a.x * v.x - a.y * v.y;
                 pi[r] += a.x * v.y + a.y * v.x;
+                pr[r] += a.z * v.z - a.w * v.w;
+                pi[r] += a.z * v.w + a.w * v.z;
             }
         }
         for (int r = 0; r < NR; r++) {
@@ -298,7 +326,6 @@ __global__ __launch_bounds__(256) void dense_gemv_kernel(const float2 *__restric
 // every row starts 16-byte aligned), eight loads of each row in flight per
 // lane, B streamed with non-temporal loads.  FP32 partial sums over chunks
 // of 1024 entries are added in FP64, then a fixed-order wave reduction.
-typedef float fvec4 __attribute__((ext_vector_type(4)));
 constexpr int GEMV1_ROWS = 4;   // rows per wavefront
 
 __global__ __launch_bounds__(256) void dense_gemv1_kernel(const float2 *__restrict__ B,

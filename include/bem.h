@@ -393,10 +393,11 @@ int bem_profile_read(const char *kernel, double *total_ms, int64_t *launches);
  *   "dense.skinny_min_rhs" right-hand-side count (>= 2) from which products
  *                         with the assembled operator below gemm_min use the
  *                         16-column MFMA kernel instead of the multi-vector
- *                         GEMV (default 8)
+ *                         GEMV (default 24: not below the default gemm_min)
  *   "dense.gemm_min_rhs"  right-hand-side count from which the assembled
  *                         operator is applied with the MFMA product instead of
- *                         the multi-vector product (default 16)
+ *                         the multi-vector product, 8 vectors per pass
+ *                         (default 24)
  * Results of a solve depend on these (the summation order changes), within
  * the FP32 accuracy.  BEM_E_INVAL for an unknown key or value. */
 int bem_tune_set(const char *key, int64_t value);

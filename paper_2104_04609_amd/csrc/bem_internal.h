@@ -232,8 +232,8 @@ struct Tuning {
     std::atomic<int> farfield_multi_max{4};   // right-hand sides per pair-kernel launch
     std::atomic<int> farfield_block{256};     // test triangles per pair-kernel workgroup
     std::atomic<int> farfield_symmetric{1};   // FP32 single vector: each separated pair once
-    std::atomic<int> dense_gemm_min_rhs{16};  // MFMA product from this many right-hand sides
-    std::atomic<int> dense_skinny_min_rhs{8}; // skinny MFMA product from this many (else multi-GEMV)
+    std::atomic<int> dense_gemm_min_rhs{24};  // MFMA product from this many right-hand sides
+    std::atomic<int> dense_skinny_min_rhs{24}; // skinny MFMA product from this many (else multi-GEMV)
 };
 Tuning &tuning();
 
@@ -242,8 +242,8 @@ Tuning &tuning();
 struct TuneEntry {
     int block = 256;           // test triangles per pair-kernel workgroup: 64, 128, 256
     int multi = 4;             // right-hand sides per pair-kernel launch: 1, 2, 4
-    int gemm_min = 16;         // MFMA product from this many right-hand sides
-    int skinny_min = 8;        // below gemm_min: skinny MFMA product from this many, else multi-vector GEMV
+    int gemm_min = 24;         // MFMA product from this many right-hand sides
+    int skinny_min = 24;       // below gemm_min: skinny MFMA product from this many, else multi-vector GEMV
     int path = -1;             // FP32 solves: -1 no preference, 0 matrix-free, 1 assembled
     double t_mf = 0, t_dense = 0, t_asm = 0;   // seconds (R vectors; assembly)
 };

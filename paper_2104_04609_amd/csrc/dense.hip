@@ -256,69 +256,77 @@ __global__ __launch_bounds__(256) void dense_add_near_kernel(const int32_t *__re
 // once; per right-hand side, FP32 products over chunks of 16 x 64 columns,
 // FP64 lane partial sums and a fixed-order butterfly reduction.
 // x: [NR][n2] complex64; y_r = y + r ystride.
+// y_r = B x_r for NR vectors (2..8): two rows per wavefront (eight per
+// workgroup); each chunk of the NR vectors (512 entries each) is staged in
+// LDS once per workgroup and read by all eight rows, so x costs the L2 one
+// pass per eight rows instead of one per row.  16-byte loads of B (2N even:
+// rows and vectors 16-byte aligned), non-temporal; FP32 partial sums per
+// chunk added in FP64, fixed-order wave reduction.
+constexpr int GV_RW = 2;     // rows per wavefront
+constexpr int GV_CH = 256;   // float4 (two complex entries) per chunk and vector
+
 template <int NR>
 __global__ __launch_bounds__(256) void dense_gemv_kernel(const float2 *__restrict__ B,
                                                          int64_t n2,
                                                          const float2 *__restrict__ x,
                                                          double2 *__restrict__ y,
                                                          int64_t ystride) {
-    // one row per wavefront; 16-byte loads (two complex entries; 2N is even,
-    // so rows and vectors start 16-byte aligned), four loads of B in flight
-    // per lane, B streamed with non-temporal loads; FP32 partial sums over
-    // chunks of 512 entries added in FP64, fixed-order wave reduction
-    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (row >= n2) return;
-    const fvec4 *b4 = reinterpret_cast<const fvec4 *>(B + row * n2);
+    __shared__ fvec4 xs[NR * GV_CH];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * GV_RW;
+    const int nrow = row0 >= n2 ? 0 : (n2 - row0 < GV_RW ? (int)(n2 - row0) : GV_RW);
+    const fvec4 *b4[GV_RW];
+    for (int q = 0; q < GV_RW; q++)
+        b4[q] = reinterpret_cast<const fvec4 *>(B + (q < nrow ? row0 + q : 0) * n2);
     const fvec4 *x4 = reinterpret_cast<const fvec4 *>(x);
     const int64_t n4 = n2 / 2;
-    double sr[NR], si[NR];
-    for (int r = 0; r < NR; r++) sr[r] = si[r] = 0.0;
-    int64_t c0 = 0;
-    for (; c0 + 256 <= n4; c0 += 256) {
-        fvec4 a[4];
-#pragma unroll
-        for (int u = 0; u < 4; u++) a[u] = __builtin_nontemporal_load(b4 + c0 + u * 64 + lane);
-#pragma unroll
-        for (int r = 0; r < NR; r++) {
-            float pr = 0.f, pi = 0.f;
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const fvec4 v = x4[r * n4 + c0 + u * 64 + lane];
-                pr += a[u].x * v.x - a[u].y * v.y;
-                pi += a[u].x * v.y + a[u].y * v.x;
-                pr += a[u].z * v.z - a[u].w * v.w;
-                pi += a[u].z * v.w + a[u].w * v.z;
-            }
-            sr[r] += pr;
-            si[r] += pi;
+    double sr[GV_RW][NR], si[GV_RW][NR];
+    for (int q = 0; q < GV_RW; q++)
+        for (int r = 0; r < NR; r++) sr[q][r] = si[q][r] = 0.0;
+    for (int64_t c0 = 0; c0 < n4; c0 += GV_CH) {
+        const int cnt = n4 - c0 < GV_CH ? (int)(n4 - c0) : GV_CH;
+        __syncthreads();   // the previous chunk's readers are done
+        for (int idx = threadIdx.x; idx < NR * GV_CH; idx += 256) {
+            const int r = idx / GV_CH, c = idx - r * GV_CH;
+            xs[idx] = c < cnt ? x4[r * n4 + c0 + c] : fvec4{0.f, 0.f, 0.f, 0.f};
         }
-    }
-    {
-        float pr[NR], pi[NR];
-        for (int r = 0; r < NR; r++) pr[r] = pi[r] = 0.f;
-        for (int64_t c = c0 + lane; c < n4; c += 64) {
-            const fvec4 a = __builtin_nontemporal_load(b4 + c);
+        __syncthreads();
+        if (nrow == 0) continue;   // (the barriers above stay uniform)
+#pragma unroll
+        for (int q = 0; q < GV_RW; q++) {
+            fvec4 a[GV_CH / 64];
+#pragma unroll
+            for (int u = 0; u < GV_CH / 64; u++) {
+                const int c = u * 64 + lane;
+                a[u] = c < cnt ? __builtin_nontemporal_load(b4[q] + c0 + c)
+                               : fvec4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
             for (int r = 0; r < NR; r++) {
-                const fvec4 v = x4[r * n4 + c];
-                pr[r] += a.x * v.x - a.y * v.y;
-                pi[r] += a.x * v.y + a.y * v.x;
-                pr[r] += a.z * v.z - a.w * v.w;
-                pi[r] += a.z * v.w + a.w * v.z;
+                float pr = 0.f, pi = 0.f;
+#pragma unroll
+                for (int u = 0; u < GV_CH / 64; u++) {
+                    const fvec4 v = xs[r * GV_CH + u * 64 + lane];
+                    pr += a[u].x * v.x - a[u].y * v.y;
+                    pi += a[u].x * v.y + a[u].y * v.x;
+                    pr += a[u].z * v.z - a[u].w * v.w;
+                    pi += a[u].z * v.w + a[u].w * v.z;
+                }
+                sr[q][r] += pr;
+                si[q][r] += pi;
             }
         }
-        for (int r = 0; r < NR; r++) {
-            sr[r] += pr[r];
-            si[r] += pi[r];
-        }
     }
-    for (int r = 0; r < NR; r++)
-        for (int o = 32; o > 0; o >>= 1) {
-            sr[r] += __shfl_xor(sr[r], o, 64);
-            si[r] += __shfl_xor(si[r], o, 64);
-        }
+    if (nrow == 0) return;
+    for (int q = 0; q < GV_RW; q++)
+        for (int r = 0; r < NR; r++)
+            for (int o = 32; o > 0; o >>= 1) {
+                sr[q][r] += __shfl_xor(sr[q][r], o, 64);
+                si[q][r] += __shfl_xor(si[q][r], o, 64);
+            }
     if (lane == 0)
-        for (int r = 0; r < NR; r++) y[r * ystride + row] = make_double2(sr[r], si[r]);
+        for (int q = 0; q < nrow; q++)
+            for (int r = 0; r < NR; r++) y[r * ystride + row0 + q] = make_double2(sr[q][r], si[q][r]);
 }
 
 // y = B x for one vector: GEMV1_ROWS rows per wavefront (each chunk of x, read from
@@ -719,8 +727,8 @@ std::unique_ptr<DenseOperator> dense_assemble(bem_mesh *m, const NearOperator &n
 
 template <int NR>
 void launch_gemv(const DenseOperator &op, const float2 *xs, double2 *y, hipStream_t s) {
-    hipLaunchKernelGGL(dense_gemv_kernel<NR>, dim3((unsigned)((op.n2 + 3) / 4)), dim3(256), 0, s,
-                       op.B.p, op.n2, xs, y, op.n2);
+    hipLaunchKernelGGL(dense_gemv_kernel<NR>, dim3((unsigned)((op.n2 + 4 * GV_RW - 1) / (4 * GV_RW))),
+                       dim3(256), 0, s, op.B.p, op.n2, xs, y, op.n2);
 }
 
 constexpr int GEMV_MAX_RHS = 8;   // right-hand sides per multi-vector GEMV launch

@@ -163,11 +163,21 @@ def test_invalid_arguments_raise(P):
         P.pmchwt_matvec(M, 2.0, 3.0, 1.0, x[:-1].contiguous())
 
 
+@pytest.fixture
+def dense_paths(P):
+    keys = ("dense.gemm_min_rhs", "dense.skinny_min_rhs")
+    old = {k: P.tune_get(k) for k in keys}
+    yield lambda k, v: P.tune_set(k, v)
+    for k, v in old.items():
+        P.tune_set(k, v)
+
+
 @pytest.mark.parametrize("n_rhs", [16, 67])
-def test_dense_mfma_gemm_matches_gemv_and_oracle(P, n_rhs):
-    """Multi-RHS product on MFMA (n_rhs >= 16, ragged column tile at 67)
-    against per-column dense GEMVs and the oracle's dense matrix."""
+def test_dense_mfma_gemm_matches_gemv_and_oracle(P, dense_paths, n_rhs):
+    """Multi-RHS product on MFMA (from 16 vectors here, ragged column tile at
+    67) against per-column dense GEMVs and the oracle's dense matrix."""
     import torch
+    dense_paths("dense.gemm_min_rhs", 16)
     mesh = icosphere(3)
     N = mesh.n_vertices
     M = P.Mesh.from_inputs(mesh)
@@ -184,12 +194,15 @@ def test_dense_mfma_gemm_matches_gemv_and_oracle(P, n_rhs):
         assert max(err.values()) <= 1e-5, err
 
 
-@pytest.mark.parametrize("n_rhs", [2, 5, 8, 11])
-def test_dense_multi_vector_product(P, n_rhs):
-    """Skinny MFMA product (one pass over the matrix per 8 right-hand sides,
-    ragged last group at 11) against single-vector products and the oracle's
-    dense matrix."""
+@pytest.mark.parametrize("skinny", [True, False])
+@pytest.mark.parametrize("n_rhs", [2, 5, 8, 11, 20])
+def test_dense_multi_vector_product(P, dense_paths, n_rhs, skinny):
+    """Skinny MFMA product (16 columns per pass; from 5 vectors here) and the
+    multi-vector GEMV (8 vectors per pass, ragged last group at 11 and 20)
+    against single-vector products and the oracle's dense matrix."""
     import torch
+    dense_paths("dense.gemm_min_rhs", 24)
+    dense_paths("dense.skinny_min_rhs", 5 if skinny else 24)
     mesh = icosphere(3)
     N = mesh.n_vertices
     M = P.Mesh.from_inputs(mesh)

@@ -35,7 +35,7 @@ def test_cache_load_and_lookup(P, tmp_path):
     assert e["t_assembly"] == pytest.approx(0.09)
     e, tuned = P.tune_lookup(20480, 1)
     assert tuned and e["path"] == 0 and e["t_matrix_free"] == pytest.approx(0.0225)
-    assert e["skinny_min"] == 8   # absent from the line: default
+    assert e["skinny_min"] == 24   # absent from the line: default
     e, tuned = P.tune_lookup(5120, 40)   # bucket 16+
     assert tuned and e["gemm_min"] == 16
     e, tuned = P.tune_lookup(1280, 2)

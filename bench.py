@@ -386,7 +386,7 @@ def main():
                          "to scale HBM byte counters (FETCH_SIZE, WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+        print("bench.py: the library runs on one GPU; --gpus must be 1 "
               "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
         sys.exit(2)
 

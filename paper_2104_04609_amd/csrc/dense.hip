@@ -252,11 +252,8 @@ __global__ __launch_bounds__(256) void dense_add_near_kernel(const int32_t *__re
     }
 }
 
-// y_r = B x_r for NR right-hand sides: one wavefront per row reads the row
-// once; per right-hand side, FP32 products over chunks of 16 x 64 columns,
-// FP64 lane partial sums and a fixed-order butterfly reduction.
-// x: [NR][n2] complex64; y_r = y + r ystride.
-// y_r = B x_r for NR vectors (2..8): two rows per wavefront (eight per
+// y_r = B x_r for NR vectors (2..8); x: [NR][n2] complex64, y_r = y + r ystride.
+// Two rows per wavefront (eight per
 // workgroup); each chunk of the NR vectors (512 entries each) is staged in
 // LDS once per workgroup and read by all eight rows, so x costs the L2 one
 // pass per eight rows instead of one per row.  16-byte loads of B (2N even:

@@ -187,7 +187,9 @@ def _matvec_tris(mesh, k, interior, test, xs, n_ss=4):
 def pmchwt_matvec_rows(mesh, k_ext, k_int, rho, x, rows, n_ss=4):
     """Rows `rows` (vertex indices) of both block rows of y = B x, matrix-free.
 
-    x = [psi; phi] complex [2N].  Returns (y1[rows], y2[rows]).
+    x = [psi; phi] complex [2N].  Returns (y1[rows], y2[rows]).  k_int, rho:
+    one material, or one per object (a test triangle's interior terms at its
+    object's k_int[m], rho[m]).
     """
     N = mesh.n_vertices
     psi, phi = x[:N], x[N:]
@@ -196,9 +198,18 @@ def pmchwt_matvec_rows(mesh, k_ext, k_int, rho, x, rows, n_ss=4):
     mask = np.isin(T, rows).any(axis=1)
     test = np.nonzero(mask)[0]
     o0 = _matvec_tris(mesh, k_ext, False, test, (psi, phi, psi, phi), n_ss)
-    o1 = _matvec_tris(mesh, k_int, True, test, (psi, phi, psi, phi), n_ss)
-    r1 = (o0[:, 0] + rho * o1[:, 0]) - (o0[:, 1] + o1[:, 1])
-    r2 = (o0[:, 2] + o1[:, 2]) + (o0[:, 3] + o1[:, 3] / rho)
+    if np.ndim(k_int) == 0 and np.ndim(rho) == 0:
+        o1 = _matvec_tris(mesh, k_int, True, test, (psi, phi, psi, phi), n_ss)
+        rt = np.full(len(test), float(rho))
+    else:
+        obj = mesh.object_id[test]
+        o1 = np.zeros_like(o0)
+        for m in np.unique(obj):
+            sel = obj == m
+            o1[sel] = _matvec_tris(mesh, k_int[m], True, test[sel], (psi, phi, psi, phi), n_ss)
+        rt = np.asarray(rho, float)[obj]
+    r1 = (o0[:, 0] + rt[:, None] * o1[:, 0]) - (o0[:, 1] + o1[:, 1])
+    r2 = (o0[:, 2] + o1[:, 2]) + (o0[:, 3] + o1[:, 3] / rt[:, None])
     y1 = np.zeros(N, np.complex128)
     y2 = np.zeros(N, np.complex128)
     tv = T[test]

@@ -160,7 +160,7 @@ def test_muller_multi_rhs(P, tuning, precision, mm):
             assert max(err.values()) <= TOL[precision], (case, r, err)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_dense"])
 def test_muller_full_size_sampled_rows(P, precision):
     """Icosphere L5 (10 242 vertices), k_ext = 10, k_int = 15, rho = 1.5; 40
     seed-sampled rows of each block row against the oracle's matrix-free

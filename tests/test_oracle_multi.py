@@ -76,3 +76,17 @@ def test_muller_per_object_blocks():
         Bs = muller_matrix(icosphere(1, 1.0, centre=c), K0, KS[o], RHOS[o])
         idx = np.concatenate([np.arange(o * h, (o + 1) * h), N + np.arange(o * h, (o + 1) * h)])
         assert _rel(B[np.ix_(idx, idx)], Bs) < 1e-13
+
+
+def test_matrix_free_rows_per_object_materials():
+    """The matrix-free rows with a material per object (used at full size)
+    against the dense matrix."""
+    from oracle.operators import pmchwt_matvec_rows
+    m = two_spheres(1, offset=1.5)
+    N = m.n_vertices
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(2 * N) + 1j * rng.standard_normal(2 * N)
+    y = pmchwt_matrix_multi(m, K0, KS, RHOS) @ x
+    rows = np.array([0, 7, N // 2 + 3, N - 1])
+    r1, r2 = pmchwt_matvec_rows(m, K0, KS, RHOS, x, rows)
+    assert _rel(r1, y[rows]) < 1e-12 and _rel(r2, y[N + rows]) < 1e-12

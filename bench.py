@@ -461,7 +461,7 @@ def main():
             # FP64 GMRES, FP32 matrix-free + refinement, FP32 assembled dense
             # operator + refinement (assembly included in its time)
             for name, prec, path in (("fp64", "fp64", 0), ("fp32", "fp32", 0),
-                                     ("fp32_dense", "fp32", 1)):
+                                     ("fp32_dense", "fp32", 1), ("fp64_dense", "fp64", 1)):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 sol, info, rc = P.pmchwt_solve(M, K_EXT, K_INT, RHO, [[0, 0, 1]], 1e-6,
@@ -491,6 +491,9 @@ def main():
                                                        solve["fp32_autotuned"]["seconds"])
             solve["speedup_fp32_dense_refine_vs_fp64"] = (solve["fp64"]["seconds"] /
                                                           solve["fp32_dense"]["seconds"])
+            # on the assembled operators: FP32 + refinement against FP64 GMRES
+            solve["speedup_fp32_dense_vs_fp64_dense"] = (solve["fp64_dense"]["seconds"] /
+                                                         solve["fp32_dense"]["seconds"])
             # dense GEMV throughput (operator resident after the solve)
             P.profile_enable(True)
             for _ in range(5):
@@ -501,6 +504,15 @@ def main():
             gbytes = (2 * N) ** 2 * 8
             solve["dense_gemv"] = {"ms": gms / gn, "GB_per_s": gbytes / (gms / gn * 1e-3) / 1e9,
                                    "matrix_bytes": gbytes}
+            P.profile_enable(True)
+            for _ in range(5):
+                P.pmchwt_matvec(M, K_EXT, K_INT, RHO, x, y, precision="fp64_dense")
+            torch.cuda.synchronize()
+            gms, gn = P.profile_read("dense_gemv_fp64")
+            P.profile_enable(False)
+            solve["dense_gemv_fp64"] = {"ms": gms / gn,
+                                        "GB_per_s": 2 * gbytes / (gms / gn * 1e-3) / 1e9,
+                                        "matrix_bytes": 2 * gbytes}
             # the four formulations compared in the paper (OSRC, PMCHWT, Calderon,
             # Mueller; strong form), FP32 assembled operator + refinement to the
             # same tolerance, each operator assembled and factorised beforehand

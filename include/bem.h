@@ -55,8 +55,12 @@ enum {
  *   BEM_FP32_DENSE  assembled dense complex64 operator [2N][2N] (FP32 pair
  *                   sums plus the FP64 near field rounded once), built on
  *                   first use for a (k_ext, k_int, rho) and kept resident;
- *                   needs 16 N^2 bytes of device memory (BEM_E_NOMEM else) */
-enum { BEM_FP64 = 0, BEM_FP32 = 1, BEM_FP32_DENSE = 2 };
+ *                   needs 16 N^2 bytes of device memory (BEM_E_NOMEM else)
+ *   BEM_FP64_DENSE  assembled dense complex128 operator (FP64 pair sums, the
+ *                   FP64 pair kernel's quadrature and arithmetic), kept apart
+ *                   from the complex64 one; 32 N^2 bytes.  One pass over it
+ *                   per vector. */
+enum { BEM_FP64 = 0, BEM_FP32 = 1, BEM_FP32_DENSE = 2, BEM_FP64_DENSE = 3 };
 
 /*
  * Create the device state of a triangle surface mesh (Sec. 2.1: bounded
@@ -95,7 +99,7 @@ int bem_mesh_info(const bem_mesh *mesh, int64_t *n_vertices,
  * pair not sharing a vertex; Sauter-Schwab-type rules (4 Gauss points per
  * dimension) for coinciding, edge- and vertex-adjacent pairs.
  *   x, y       device, bem_c64 [n_rhs][2N]
- *   precision  BEM_FP64, BEM_FP32 or BEM_FP32_DENSE (see above)
+ *   precision  BEM_FP64, BEM_FP32, BEM_FP32_DENSE or BEM_FP64_DENSE (see above)
  * The first call for a (k_ext, k_int, rho) builds and caches the near-field
  * operator on the device.  Errors: BEM_E_INVAL (rho <= 0, Im k < 0, k == 0,
  * n_rhs < 1, NULL pointers), BEM_E_NOMEM, BEM_E_DEVICE.
@@ -175,7 +179,9 @@ typedef struct {
     int max_outer;       /* refinement steps cap, default 8 */
     int path;            /* FP32 form inner operator: 0 matrix-free pair kernel,
                             1 assembled dense complex64 operator, 2 dense when
-                            it fits in device memory (default) */
+                            it fits in device memory (default).  FP64 form:
+                            1 assembled dense complex128 operator, else
+                            matrix-free */
     int formulation;     /* BEM_FORM_OSRC (default), BEM_FORM_PMCHWT,
                             BEM_FORM_CALDERON or BEM_FORM_MULLER; see below */
 } bem_solve_opts;

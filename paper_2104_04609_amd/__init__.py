@@ -5,7 +5,7 @@ mesh state, the matrix-free permuted PMCHWT (and Mueller) Galerkin matvec, the O
 preconditioner, plane-wave right-hand sides, the preconditioned GMRES solve,
 the far field and the field off the surface.  All arithmetic runs in the library's HIP kernels.
 """
-from ._binding import (BEM_FP32, BEM_FP32_DENSE, BEM_FP64, BemError, Mesh, Server, SolveInfo,
+from ._binding import (BEM_FP32, BEM_FP32_DENSE, BEM_FP64, BEM_FP64_DENSE, BemError, Mesh, Server, SolveInfo,
                        SolveOpts,
                        default_opts, far_field, lib, muller_matvec, osrc_apply, pmchwt_field, pmchwt_matvec,
                        pmchwt_matvec_multi, pmchwt_solve_multi,
@@ -13,7 +13,7 @@ from ._binding import (BEM_FP32, BEM_FP32_DENSE, BEM_FP64, BemError, Mesh, Serve
                        autotune, tune_cache_load, tune_clear, tune_get, tune_lookup, tune_set,
                        valu_rates)
 
-__all__ = ["BEM_FP32", "BEM_FP32_DENSE", "BEM_FP64", "BemError", "Mesh", "Server", "SolveInfo",
+__all__ = ["BEM_FP32", "BEM_FP32_DENSE", "BEM_FP64", "BEM_FP64_DENSE", "BemError", "Mesh", "Server", "SolveInfo",
            "SolveOpts",
            "default_opts", "far_field", "lib", "muller_matvec", "osrc_apply", "pmchwt_field",
            "pmchwt_matvec", "pmchwt_matvec_multi", "pmchwt_solve_multi",

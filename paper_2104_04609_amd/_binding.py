@@ -22,9 +22,10 @@ if not os.path.exists(LIB_PATH):
 
 lib = ctypes.CDLL(LIB_PATH)
 
-BEM_FP64, BEM_FP32, BEM_FP32_DENSE = 0, 1, 2
+BEM_FP64, BEM_FP32, BEM_FP32_DENSE, BEM_FP64_DENSE = 0, 1, 2, 3
 _PREC = {"fp64": BEM_FP64, "fp32": BEM_FP32, "fp32_dense": BEM_FP32_DENSE,
-         BEM_FP64: BEM_FP64, BEM_FP32: BEM_FP32, BEM_FP32_DENSE: BEM_FP32_DENSE}
+         "fp64_dense": BEM_FP64_DENSE, BEM_FP64: BEM_FP64, BEM_FP32: BEM_FP32,
+         BEM_FP32_DENSE: BEM_FP32_DENSE, BEM_FP64_DENSE: BEM_FP64_DENSE}
 ERRORS = {1: "BEM_W_NOT_CONVERGED", 2: "BEM_W_PENDING", 3: "BEM_W_DEFAULT", -1: "BEM_E_INVAL", -2: "BEM_E_BAD_MESH",
           -3: "BEM_E_NOMEM", -4: "BEM_E_DEVICE", -5: "BEM_E_NAN",
           -6: "BEM_E_UNSUPPORTED"}

@@ -63,6 +63,7 @@ Tuning &tuning() {
 void mesh_trim(bem_mesh *m) {
     m->near_cache.clear();
     m->dense_cache.clear();
+    m->dense64_cache.clear();
     m->osrc_cache.clear();
     m->xs32.release();
     m->dyn64.release();
@@ -84,6 +85,7 @@ int64_t bem_mesh::device_bytes() const {
                 sym_items.bytes() + P_d.bytes();
     for (const auto &kv : near_cache) b += kv.second->vals.bytes();
     for (const auto &kv : dense_cache) b += kv.second->B.bytes();
+    for (const auto &kv : dense64_cache) b += kv.second->B64.bytes();
     b += xs32.bytes();
     for (const auto &kv : osrc_cache) b += bem::osrc_bytes(*kv.second);
     if (osrc_sym) b += bem::osrc_sym_bytes(*osrc_sym);
@@ -181,14 +183,16 @@ void operator_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double 
     if (!x || !y) fail(BEM_E_INVAL, "x and y must be device pointers");
     if (x == y) fail(BEM_E_INVAL, "x and y must not alias");
     if (n_rhs < 1) fail(BEM_E_INVAL, "n_rhs must be >= 1");
-    if (precision != BEM_FP64 && precision != BEM_FP32 && precision != BEM_FP32_DENSE)
+    if (precision != BEM_FP64 && precision != BEM_FP32 && precision != BEM_FP32_DENSE &&
+        precision != BEM_FP64_DENSE)
         fail(BEM_E_INVAL, "bad precision");
     bem_mesh *m = const_cast<bem_mesh *>(mesh);
     hipStream_t s = (hipStream_t)hip_stream;
     double2 k0 = make_double2(k_ext.re, k_ext.im), k1 = make_double2(k_int.re, k_int.im);
     const bem::NearOperator &nf = bem::nearfield_get(m, k0, k1, rho, s, s1, om);
-    if (precision == BEM_FP32_DENSE) {
-        const bem::DenseOperator &op = bem::dense_get(m, k0, k1, rho, s, s1, om);
+    if (precision == BEM_FP32_DENSE || precision == BEM_FP64_DENSE) {
+        const bem::DenseOperator &op =
+            bem::dense_get(m, k0, k1, rho, s, s1, om, precision == BEM_FP64_DENSE);
         bem::dense_apply(op, (const double2 *)x, (double2 *)y, n_rhs, m->xs32, s);
         return;
     }

@@ -136,7 +136,9 @@ struct ObjMaterials {
 struct DenseOperator {
     int64_t n2 = 0;
     int64_t T = 0;             // triangles of the mesh (tuning lookups)
+    bool fp64 = false;         // B64 (complex128) instead of B (complex64)
     DevBuf<float2> B;
+    DevBuf<double2> B64;
 };
 
 struct OsrcKey {
@@ -201,6 +203,7 @@ struct bem_mesh {
     int ss_off[4] = {0, 0, 0, 0};      // row offsets of the three rules
     std::map<bem::NearKey, std::unique_ptr<bem::NearOperator>> near_cache;
     std::map<bem::NearKey, std::unique_ptr<bem::DenseOperator>> dense_cache;
+    std::map<bem::NearKey, std::unique_ptr<bem::DenseOperator>> dense64_cache;   // complex128
     bem::DevBuf<float2> xs32;          // complex64 copy of a matvec input
 
     // OSRC: P1 vertex graph, M and S values, factor state per parameter set
@@ -280,12 +283,15 @@ const NearOperator &nearfield_get(bem_mesh *m, double2 k0, double2 k1, double rh
 NearKey near_key(const bem_mesh *m, double2 k0, double2 k1, double rho, int s1,
                  const ObjMaterials *om);
 // dense.hip
-int64_t dense_bytes(const bem_mesh *m);
-int64_t dense_assembly_scratch_bytes(const bem_mesh *m);
+int64_t dense_bytes(const bem_mesh *m, bool fp64 = false);
+int64_t dense_assembly_scratch_bytes(const bem_mesh *m, bool fp64 = false);
 std::unique_ptr<DenseOperator> dense_assemble(bem_mesh *m, const NearOperator &nf, double2 k0,
-                                              double2 k1, double rho, hipStream_t s);
+                                              double2 k1, double rho, hipStream_t s,
+                                              bool fp64 = false);
+// fp64: the complex128 operator (FP64 assembly, kept apart from the
+// complex64 one)
 const DenseOperator &dense_get(bem_mesh *m, double2 k0, double2 k1, double rho, hipStream_t s,
-                               int s1 = 1, const ObjMaterials *om = nullptr);
+                               int s1 = 1, const ObjMaterials *om = nullptr, bool fp64 = false);
 // y_r = B x_r, r < R (x, y RHS-major [R][2N]): multi-vector product reading B
 // once per 8 right-hand sides
 void dense_gemv(const DenseOperator &op, const double2 *x, double2 *y, int R, DevBuf<float2> &xs,

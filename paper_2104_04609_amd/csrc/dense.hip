@@ -32,50 +32,102 @@ __host__ __device__ constexpr double qb(int i, int a) {
 }
 
 typedef float fvec4 __attribute__((ext_vector_type(4)));
+typedef double dvec2 __attribute__((ext_vector_type(2)));
 
 constexpr int JT = 512;   // trial vertices per assembly tile
 
 // interior coefficients of one object (several objects: a per-object table)
-struct DInt {
-    float krev1, k1r, k1i, kdec1, rho, irho, n10r, n10i;
-    float ns1;   // -s_1 (interior sign: +1 PMCHWT, -1 Mueller)
+template <class R> struct DIntT {
+    R krev1, k1r, k1i, kdec1, rho, irho, n10r, n10i;
+    R ns1;   // -s_1 (interior sign: +1 PMCHWT, -1 Mueller)
 };
-struct DCoef {
-    float krev0, k0r, k0i, kdec0, n0r, n0i;
-    DInt in;
+template <class R> struct DCoefT {
+    R krev0, k0r, k0i, kdec0, n0r, n0i;
+    DIntT<R> in;
 };
 
-__device__ __forceinline__ void sincos_rev(float t, float &s, float &c) {
-    const float f = __builtin_amdgcn_fractf(t);   // hardware sin/cos take revolutions
-    s = __builtin_amdgcn_sinf(f);
-    c = __builtin_amdgcn_cosf(f);
-}
+__device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-template <bool CK0, bool CK1, bool MULTI>
+// Arithmetic of the assembly kernel per precision.  FP32: hardware sin/cos
+// (in revolutions), 1/sqrt and exp2; the operator is stored as complex64.
+// FP64: sin/cos of 2 pi t from a table of e^{2 pi i n/256} and the Taylor
+// series of the remainder (|2 pi f| <= pi/256, terms beyond x^6 below 4e-18),
+// 1/sqrt from the hardware estimate and two Newton steps; complex128.
+template <class R> struct DM;
+template <> struct DM<float> {
+    using C = float2;
+    static __device__ __forceinline__ void fill_table(double2 *) {}
+    static __device__ __forceinline__ void sincos(float t, float &s, float &c, const double2 *) {
+        const float f = __builtin_amdgcn_fractf(t);   // hardware sin/cos take revolutions
+        s = __builtin_amdgcn_sinf(f);
+        c = __builtin_amdgcn_cosf(f);
+    }
+    static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+    static __device__ __forceinline__ float2 mk(float a, float b) { return make_float2(a, b); }
+};
+template <> struct DM<double> {
+    using C = double2;
+    static __device__ __forceinline__ void fill_table(double2 *tab) {
+        for (int n = threadIdx.x; n < 256; n += blockDim.x) {
+            double sn, cs;
+            ::sincos(n * (6.283185307179586476925286766559 / 256.0), &sn, &cs);
+            tab[n] = make_double2(cs, sn);
+        }
+    }
+    static __device__ __forceinline__ void sincos(double t, double &s, double &c,
+                                                  const double2 *tab) {
+        const double n = __builtin_rint(256.0 * t);
+        const double x = __builtin_fma(-0.00390625, n, t) * 6.283185307179586476925286766559;
+        const double x2 = x * x;
+        const double sn = __builtin_fma(__builtin_fma(x2, 1.0 / 120.0, -1.0 / 6.0), x2, 1.0) * x;
+        const double cs =
+            __builtin_fma(__builtin_fma(__builtin_fma(x2, -1.0 / 720.0, 1.0 / 24.0), x2, -0.5), x2, 1.0);
+        const double2 e = tab[((int64_t)n) & 255];
+        c = __builtin_fma(e.x, cs, -e.y * sn);
+        s = __builtin_fma(e.y, cs, e.x * sn);
+    }
+    static __device__ __forceinline__ double rsq(double x) {
+        double y = __builtin_amdgcn_rsq(x);
+        const double h = 0.5 * x;
+        y = y * __builtin_fma(-h * y, y, 1.5);
+        y = y * __builtin_fma(-h * y, y, 1.5);
+        return y;
+    }
+    static __device__ __forceinline__ double exp2(double x) { return ::exp2(x); }
+    static __device__ __forceinline__ double2 mk(double a, double b) { return make_double2(a, b); }
+};
+
+template <class R, bool CK0, bool CK1, bool MULTI>
 __global__ __launch_bounds__(256) void dense_pairs_kernel(
-    const float *__restrict__ geo, const double *__restrict__ tst,
+    const R *__restrict__ geo, const double *__restrict__ tst,
     const int32_t *__restrict__ tobj, const int32_t *__restrict__ tri,
     const int32_t *__restrict__ star_ptr, const int32_t *__restrict__ star_idx, int T, int j0,
-    int64_t N, DCoef cf, const DInt *__restrict__ itab, float2 *__restrict__ Q) {
+    int64_t N, DCoefT<R> cf, const DIntT<R> *__restrict__ itab, typename DM<R>::C *__restrict__ Q) {
+    using M = DM<R>;
+    __shared__ double2 etab[std::is_same<R, double>::value ? 256 : 1];   // FP64 sin/cos table
+    M::fill_table(etab);
+    __syncthreads();
     const int tau = blockIdx.x * 256 + threadIdx.x;
     const int jl = blockIdx.y;
     const int64_t j = j0 + jl;
     const bool active = tau < T && j < N;
     const int tt = tau < T ? tau : 0;
-    const float *g = geo + (int64_t)GEO_STRIDE * tt;
-    float px[6], py[6], pz[6];
+    const R *g = geo + (int64_t)GEO_STRIDE * tt;
+    R px[6], py[6], pz[6];
     for (int i = 0; i < 6; i++) {
         px[i] = g[3 * i];
         py[i] = g[3 * i + 1];
         pz[i] = g[3 * i + 2];
     }
-    const float ntx = g[18], nty = g[19], ntz = g[20], ct = g[21];
+    const R ntx = g[18], nty = g[19], ntz = g[20], ct = g[21];
     const int tv0 = tri[3 * tt], tv1 = tri[3 * tt + 1], tv2 = tri[3 * tt + 2];
     const int ot = MULTI ? tobj[tt] : 0;
-    float cu[9];
-    for (int c = 0; c < 9; c++) cu[c] = (float)tst[TST_STRIDE * tt + 1 + c];
-    float outr[12], outi[12];   // [blk * 3 + a]
-    for (int c = 0; c < 12; c++) outr[c] = outi[c] = 0.f;
+    R cu[9];
+    for (int c = 0; c < 9; c++) cu[c] = (R)tst[TST_STRIDE * tt + 1 + c];
+    R outr[12], outi[12];   // [blk * 3 + a]
+    for (int c = 0; c < 12; c++) outr[c] = outi[c] = (R)0;
     const int e0 = j < N ? star_ptr[j] : 0, e1 = j < N ? star_ptr[j + 1] : 0;
     for (int e = e0; e < e1; e++) {
         const int sb = star_idx[e];
@@ -84,88 +136,88 @@ __global__ __launch_bounds__(256) void dense_pairs_kernel(
         const bool adj = sv0 == tv0 || sv0 == tv1 || sv0 == tv2 || sv1 == tv0 || sv1 == tv1 ||
                          sv1 == tv2 || sv2 == tv0 || sv2 == tv1 || sv2 == tv2;
         if (adj) continue;   // near field
-        const float *h = geo + (int64_t)GEO_STRIDE * s;
-        const float nsx = h[18], nsy = h[19], nsz = h[20], cs = h[21];
-        const float as = (float)tst[TST_STRIDE * s];
-        const float m1 = MULTI ? (tobj[s] == ot ? 1.f : 0.f) : 1.f;
+        const R *h = geo + (int64_t)GEO_STRIDE * s;
+        const R nsx = h[18], nsy = h[19], nsz = h[20], cs = h[21];
+        const R as = (R)tst[TST_STRIDE * s];
+        const R m1 = MULTI ? (tobj[s] == ot ? (R)1 : (R)0) : (R)1;
         // sigma is the same for the whole block: its object's interior part
-        const DInt c1 = MULTI ? itab[__builtin_amdgcn_readfirstlane(tobj[s])] : cf.in;
-        const float nn = ntx * nsx + nty * nsy + ntz * nsz;
+        const DIntT<R> c1 = MULTI ? itab[__builtin_amdgcn_readfirstlane(tobj[s])] : cf.in;
+        const R nn = ntx * nsx + nty * nsy + ntz * nsz;
         // factor of the G_N term taken out of the q sum: k_0^2 (n_x . n_y)
-        const float gnr = cf.n0r * nn, gni = cf.n0i * nn;
-        float tq[6], tx[6], dny[6];
+        const R gnr = cf.n0r * nn, gni = cf.n0i * nn;
+        R tq[6], tx[6], dny[6];
         for (int q = 0; q < 6; q++) {
-            tq[q] = (float)(qw(q) * qb(q, b)) * as;
+            tq[q] = (R)(qw(q) * qb(q, b)) * as;
             // (x - y).n_x = c_tau - y.n_tau, folded into the trial weight
             tx[q] = (ct - (h[3 * q] * ntx + h[3 * q + 1] * nty + h[3 * q + 2] * ntz)) * tq[q];
         }
         for (int p = 0; p < 6; p++) dny[p] = cs - (px[p] * nsx + py[p] * nsy + pz[p] * nsz);
-        float ar[4][6], ai[4][6];
-        float gwr = 0.f, gwi = 0.f;
+        R ar[4][6], ai[4][6];
+        R gwr = (R)0, gwi = (R)0;
 #pragma unroll
         for (int p = 0; p < 6; p++) {
-            float vr = 0.f, vi = 0.f, fr = 0.f, fi = 0.f, kr = 0.f, ki = 0.f, nr = 0.f, ni = 0.f;
+            R vr = (R)0, vi = (R)0, fr = (R)0, fi = (R)0, kr = (R)0, ki = (R)0, nr = (R)0, ni = (R)0;
 #pragma unroll
             for (int q = 0; q < 6; q++) {
-                const float dx = h[3 * q] - px[p], dy = h[3 * q + 1] - py[p],
+                const R dx = h[3 * q] - px[p], dy = h[3 * q + 1] - py[p],
                             dz = h[3 * q + 2] - pz[p];
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                const float ri = __builtin_amdgcn_rsqf(r2);
-                const float r = r2 * ri;
+                const R r2 = dx * dx + dy * dy + dz * dz;
+                const R ri = M::rsq(r2);
+                const R r = r2 * ri;
                 // E_m = e^{i k_m r} (interior term masked across objects)
-                float E0r, E0i, E1r, E1i;
-                sincos_rev(r * cf.krev0, E0i, E0r);
-                sincos_rev(r * c1.krev1, E1i, E1r);
+                R E0r, E0i, E1r, E1i;
+                M::sincos(r * cf.krev0, E0i, E0r, etab);
+                M::sincos(r * c1.krev1, E1i, E1r, etab);
                 if (CK0) {
-                    const float d0 = __builtin_amdgcn_exp2f(r * cf.kdec0);
+                    const R d0 = M::exp2(r * cf.kdec0);
                     E0r *= d0;
                     E0i *= d0;
                 }
                 if (CK1 || MULTI) {
-                    float d1 = m1;
-                    if (CK1) d1 *= __builtin_amdgcn_exp2f(r * c1.kdec1);
+                    R d1 = m1;
+                    if (CK1) d1 *= M::exp2(r * c1.kdec1);
                     E1r *= d1;
                     E1i *= d1;
                 }
-                const float G0r = E0r * ri, G0i = E0i * ri, G1r = E1r * ri, G1i = E1i * ri;
+                const R G0r = E0r * ri, G0i = E0i * ri, G1r = E1r * ri, G1i = E1i * ri;
                 // F r^2 = i (k_0 E_0 + k_1 E_1) - G_0 - G_1
-                float Fr = __builtin_fmaf(c1.ns1, G1r, -G0r), Fi = __builtin_fmaf(c1.ns1, G1i, -G0i);
-                Fr = __builtin_fmaf(-cf.k0r, E0i, Fr);
-                Fi = __builtin_fmaf(cf.k0r, E0r, Fi);
-                Fr = __builtin_fmaf(-c1.k1r, E1i, Fr);
-                Fi = __builtin_fmaf(c1.k1r, E1r, Fi);
+                R Fr = fmaR(c1.ns1, G1r, -G0r), Fi = fmaR(c1.ns1, G1i, -G0i);
+                Fr = fmaR(-cf.k0r, E0i, Fr);
+                Fi = fmaR(cf.k0r, E0r, Fi);
+                Fr = fmaR(-c1.k1r, E1i, Fr);
+                Fi = fmaR(c1.k1r, E1r, Fi);
                 if (CK0) {
-                    Fr = __builtin_fmaf(-cf.k0i, E0r, Fr);
-                    Fi = __builtin_fmaf(-cf.k0i, E0i, Fi);
+                    Fr = fmaR(-cf.k0i, E0r, Fr);
+                    Fi = fmaR(-cf.k0i, E0i, Fi);
                 }
                 if (CK1) {
-                    Fr = __builtin_fmaf(-c1.k1i, E1r, Fr);
-                    Fi = __builtin_fmaf(-c1.k1i, E1i, Fi);
+                    Fr = fmaR(-c1.k1i, E1r, Fr);
+                    Fi = fmaR(-c1.k1i, E1i, Fi);
                 }
-                const float ri2 = ri * ri;
+                const R ri2 = ri * ri;
                 Fr *= ri2;
                 Fi *= ri2;
-                const float t = tq[q];
+                const R t = tq[q];
                 // V-row psi column: G_V t
-                vr = __builtin_fmaf(__builtin_fmaf(c1.rho, G1r, G0r), t, vr);
-                vi = __builtin_fmaf(__builtin_fmaf(c1.rho, G1i, G0i), t, vi);
+                vr = fmaR(fmaR(c1.rho, G1r, G0r), t, vr);
+                vi = fmaR(fmaR(c1.rho, G1i, G0i), t, vi);
                 // V-row phi column: -(y - x).n_y F t (the factor after the q sum)
-                fr = __builtin_fmaf(Fr, t, fr);
-                fi = __builtin_fmaf(Fi, t, fi);
+                fr = fmaR(Fr, t, fr);
+                fi = fmaR(Fi, t, fi);
                 // D-row psi column: F (x - y).n_x t
-                kr = __builtin_fmaf(Fr, tx[q], kr);
-                ki = __builtin_fmaf(Fi, tx[q], ki);
+                kr = fmaR(Fr, tx[q], kr);
+                ki = fmaR(Fi, tx[q], ki);
                 // D-row phi column: -k_0^2 (n_x.n_y) (G_0 + k_1^2/(rho k_0^2) G_1) t
-                float Nr = __builtin_fmaf(c1.n10r, G1r, G0r), Ni = __builtin_fmaf(c1.n10r, G1i, G0i);
+                R Nr = fmaR(c1.n10r, G1r, G0r), Ni = fmaR(c1.n10r, G1i, G0i);
                 if (CK0 || CK1) {
-                    Nr = __builtin_fmaf(-c1.n10i, G1i, Nr);
-                    Ni = __builtin_fmaf(c1.n10i, G1r, Ni);
+                    Nr = fmaR(-c1.n10i, G1i, Nr);
+                    Ni = fmaR(c1.n10i, G1r, Ni);
                 }
-                nr = __builtin_fmaf(Nr, t, nr);
-                ni = __builtin_fmaf(Ni, t, ni);
-                const float ww = (float)(qw(p) * qw(q));
-                gwr = __builtin_fmaf(ww, __builtin_fmaf(c1.irho, G1r, G0r), gwr);
-                gwi = __builtin_fmaf(ww, __builtin_fmaf(c1.irho, G1i, G0i), gwi);
+                nr = fmaR(Nr, t, nr);
+                ni = fmaR(Ni, t, ni);
+                const R ww = (R)(qw(p) * qw(q));
+                gwr = fmaR(ww, fmaR(c1.irho, G1r, G0r), gwr);
+                gwi = fmaR(ww, fmaR(c1.irho, G1i, G0i), gwi);
             }
             ar[0][p] = vr;
             ai[0][p] = vi;
@@ -177,47 +229,49 @@ __global__ __launch_bounds__(256) void dense_pairs_kernel(
             ai[3][p] = -(gnr * ni + gni * nr);
         }
         // contract with the test functions; curl-curl part of D
-        float scb[3];
-        for (int c = 0; c < 3; c++) scb[c] = (float)tst[TST_STRIDE * s + 1 + 3 * b + c];
+        R scb[3];
+        for (int c = 0; c < 3; c++) scb[c] = (R)tst[TST_STRIDE * s + 1 + 3 * b + c];
 #pragma unroll
         for (int a = 0; a < 3; a++) {
 #pragma unroll
             for (int k = 0; k < 4; k++) {
-                float sr = 0.f, si = 0.f;
+                R sr = (R)0, si = (R)0;
 #pragma unroll
                 for (int p = 0; p < 6; p++) {
-                    const float wp = (float)(qw(p) * qb(p, a));
+                    const R wp = (R)(qw(p) * qb(p, a));
                     sr += wp * ar[k][p];
                     si += wp * ai[k][p];
                 }
                 outr[3 * k + a] += sr;
                 outi[3 * k + a] += si;
             }
-            const float cc = (cu[3 * a] * scb[0] + cu[3 * a + 1] * scb[1] + cu[3 * a + 2] * scb[2]) * as;
+            const R cc = (cu[3 * a] * scb[0] + cu[3 * a + 1] * scb[1] + cu[3 * a + 2] * scb[2]) * as;
             outr[9 + a] += cc * gwr;
             outi[9 + a] += cc * gwi;
         }
     }
     if (!active) return;
-    const float sc = (float)(tst[TST_STRIDE * tt] * 0.079577471545947667884441881686257);
-    float2 *o = Q + ((int64_t)tau * JT + jl) * 12;
-    for (int c = 0; c < 12; c++) o[c] = make_float2(sc * outr[c], sc * outi[c]);
+    const R sc = (R)(tst[TST_STRIDE * tt] * 0.079577471545947667884441881686257);
+    typename M::C *o = Q + ((int64_t)tau * JT + jl) * 12;
+    for (int c = 0; c < 12; c++) o[c] = M::mk(sc * outr[c], sc * outi[c]);
 }
 
 // B[i][j], B[i][N+j], B[N+i][j], B[N+i][N+j] from the star of test vertex i
-__global__ __launch_bounds__(256) void dense_gather_kernel(const float2 *__restrict__ Q,
+template <class C>
+__global__ __launch_bounds__(256) void dense_gather_kernel(const C *__restrict__ Q,
                                                            const int32_t *__restrict__ star_ptr,
                                                            const int32_t *__restrict__ star_idx,
                                                            int64_t N, int j0, int jt,
-                                                           float2 *__restrict__ B) {
+                                                           C *__restrict__ B) {
     const int jl = blockIdx.y * 256 + threadIdx.x;
     const int64_t i = blockIdx.x;
     if (jl >= jt) return;
-    float2 acc[4] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+    C acc[4];
+    for (int k = 0; k < 4; k++) acc[k].x = acc[k].y = 0;
     for (int e = star_ptr[i]; e < star_ptr[i + 1]; e++) {
         const int ta = star_idx[e];
         const int t = ta / 3, a = ta - 3 * t;
-        const float2 *q = Q + ((int64_t)t * JT + jl) * 12;
+        const C *q = Q + ((int64_t)t * JT + jl) * 12;
         for (int k = 0; k < 4; k++) {
             acc[k].x += q[3 * k + a].x;
             acc[k].y += q[3 * k + a].y;
@@ -230,7 +284,7 @@ __global__ __launch_bounds__(256) void dense_gather_kernel(const float2 *__restr
     B[(N + i) * n2 + N + j] = acc[3];
 }
 
-// add the FP64 near-field operator (rounded to complex64)
+// add the FP64 near-field operator (complex64: summed in FP64, rounded once)
 __global__ __launch_bounds__(256) void dense_add_near_kernel(const int32_t *__restrict__ rowptr,
                                                              const int32_t *__restrict__ col,
                                                              const double2 *__restrict__ nf,
@@ -246,10 +300,79 @@ __global__ __launch_bounds__(256) void dense_add_near_kernel(const int32_t *__re
         for (int k = 0; k < 4; k++) {
             const double2 v = nf[k * nnz + e];
             float2 o = B[pos[k]];
-            // sum in FP64, round once
             B[pos[k]] = make_float2((float)((double)o.x + v.x), (float)((double)o.y + v.y));
         }
     }
+}
+
+__global__ __launch_bounds__(256) void dense_add_near64_kernel(const int32_t *__restrict__ rowptr,
+                                                               const int32_t *__restrict__ col,
+                                                               const double2 *__restrict__ nf,
+                                                               int64_t nnz, int64_t N,
+                                                               double2 *__restrict__ B) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int64_t n2 = 2 * N;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; e++) {
+        const int64_t j = col[e];
+        const int64_t pos[4] = {i * n2 + j, i * n2 + N + j, (N + i) * n2 + j,
+                                (N + i) * n2 + N + j};
+        for (int k = 0; k < 4; k++) {
+            const double2 v = nf[k * nnz + e];
+            B[pos[k]].x += v.x;
+            B[pos[k]].y += v.y;
+        }
+    }
+}
+
+// y = B x with the complex128 operator, one vector: two rows per wavefront,
+// 16-byte loads (one complex entry), eight per row in flight per lane, B
+// streamed with non-temporal loads; FP64 sums, fixed-order wave reduction.
+constexpr int G64_RW = 2;
+__global__ __launch_bounds__(256) void dense_gemv64_kernel(const double2 *__restrict__ B,
+                                                           int64_t n2,
+                                                           const double2 *__restrict__ x,
+                                                           double2 *__restrict__ y) {
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * G64_RW;
+    const int lane = threadIdx.x & 63;
+    if (row0 >= n2) return;
+    const int nrow = n2 - row0 < G64_RW ? (int)(n2 - row0) : G64_RW;
+    const dvec2 *b[G64_RW];
+    for (int q = 0; q < G64_RW; q++)
+        b[q] = reinterpret_cast<const dvec2 *>(B + (row0 + (q < nrow ? q : 0)) * n2);
+    double sr[G64_RW], si[G64_RW];
+    for (int q = 0; q < G64_RW; q++) sr[q] = si[q] = 0.0;
+    int64_t c0 = 0;
+    for (; c0 + 512 <= n2; c0 += 512) {
+        double2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) v[u] = x[c0 + u * 64 + lane];
+#pragma unroll
+        for (int q = 0; q < G64_RW; q++) {
+            dvec2 a[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) a[u] = __builtin_nontemporal_load(b[q] + c0 + u * 64 + lane);
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                sr[q] = __builtin_fma(a[u].x, v[u].x, __builtin_fma(-a[u].y, v[u].y, sr[q]));
+                si[q] = __builtin_fma(a[u].x, v[u].y, __builtin_fma(a[u].y, v[u].x, si[q]));
+            }
+        }
+    }
+    for (int q = 0; q < G64_RW; q++)
+        for (int64_t c = c0 + lane; c < n2; c += 64) {
+            const dvec2 a = __builtin_nontemporal_load(b[q] + c);
+            const double2 v = x[c];
+            sr[q] = __builtin_fma(a.x, v.x, __builtin_fma(-a.y, v.y, sr[q]));
+            si[q] = __builtin_fma(a.x, v.y, __builtin_fma(a.y, v.x, si[q]));
+        }
+    for (int q = 0; q < G64_RW; q++)
+        for (int o = 32; o > 0; o >>= 1) {
+            sr[q] += __shfl_xor(sr[q], o, 64);
+            si[q] += __shfl_xor(si[q], o, 64);
+        }
+    if (lane == 0)
+        for (int q = 0; q < nrow; q++) y[row0 + q] = make_double2(sr[q], si[q]);
 }
 
 // y_r = B x_r for NR vectors (2..8); x: [NR][n2] complex64, y_r = y + r ystride.
@@ -619,22 +742,22 @@ __global__ __launch_bounds__(256) void to_c64_kernel(const double2 *__restrict__
 
 // s1 = -1 negates the interior terms (Mueller operator, Sec. 2.2): folded
 // into rho, 1/rho, k_1^2/(rho k_0^2), k_1 (only in F) and ns1.
-DInt make_dint(double2 k0, double2 k1, double rho, int s1) {
+template <class R> DIntT<R> make_dint(double2 k0, double2 k1, double rho, int s1) {
     const double inv2pi = 0.15915494309189533576888376337251;
     const double log2e = 1.4426950408889634073599246810019;
-    DInt c;
-    c.krev1 = (float)(k1.x * inv2pi);
-    c.k1r = (float)k1.x;
-    c.k1i = (float)k1.y;
-    c.kdec1 = (float)(-k1.y * log2e);
-    c.rho = (float)rho;
-    c.irho = (float)(1.0 / rho);
+    DIntT<R> c;
+    c.krev1 = (R)(k1.x * inv2pi);
+    c.k1r = (R)k1.x;
+    c.k1i = (R)k1.y;
+    c.kdec1 = (R)(-k1.y * log2e);
+    c.rho = (R)rho;
+    c.irho = (R)(1.0 / rho);
     // k_1^2 / (rho k_0^2); k_0 != 0 is checked at the entry points
     const double n0r = k0.x * k0.x - k0.y * k0.y, n0i = 2.0 * k0.x * k0.y;
     const double n1r = (k1.x * k1.x - k1.y * k1.y) / rho, n1i = 2.0 * k1.x * k1.y / rho;
     const double d = n0r * n0r + n0i * n0i;
-    c.n10r = (float)((n1r * n0r + n1i * n0i) / d);
-    c.n10i = (float)((n1i * n0r - n1r * n0i) / d);
+    c.n10r = (R)((n1r * n0r + n1i * n0i) / d);
+    c.n10i = (R)((n1i * n0r - n1r * n0i) / d);
     if (s1 < 0) {
         c.k1r = -c.k1r;
         c.k1i = -c.k1i;
@@ -643,82 +766,112 @@ DInt make_dint(double2 k0, double2 k1, double rho, int s1) {
         c.n10r = -c.n10r;
         c.n10i = -c.n10i;
     }
-    c.ns1 = s1 < 0 ? 1.0f : -1.0f;
+    c.ns1 = (R)(s1 < 0 ? 1.0 : -1.0);
     return c;
 }
 
-DCoef make_dcoef(double2 k0, const NearOperator &nf) {
+template <class R> DCoefT<R> make_dcoef(double2 k0, const NearOperator &nf) {
     const double inv2pi = 0.15915494309189533576888376337251;
     const double log2e = 1.4426950408889634073599246810019;
-    DCoef c;
-    c.krev0 = (float)(k0.x * inv2pi);
-    c.k0r = (float)k0.x;
-    c.k0i = (float)k0.y;
-    c.kdec0 = (float)(-k0.y * log2e);
-    c.n0r = (float)(k0.x * k0.x - k0.y * k0.y);
-    c.n0i = (float)(2.0 * k0.x * k0.y);
-    c.in = make_dint(k0, nf.k1o[0], nf.rhoo[0], nf.s1);
+    DCoefT<R> c;
+    c.krev0 = (R)(k0.x * inv2pi);
+    c.k0r = (R)k0.x;
+    c.k0i = (R)k0.y;
+    c.kdec0 = (R)(-k0.y * log2e);
+    c.n0r = (R)(k0.x * k0.x - k0.y * k0.y);
+    c.n0i = (R)(2.0 * k0.x * k0.y);
+    c.in = make_dint<R>(k0, nf.k1o[0], nf.rhoo[0], nf.s1);
     return c;
 }
 
-template <bool A, bool B, bool C>
-void launch_pairs(dim3 grid, hipStream_t s, bem_mesh *m, int j0, DCoef cf, const DInt *itab,
-                  float2 *Q) {
-    hipLaunchKernelGGL((dense_pairs_kernel<A, B, C>), grid, dim3(256), 0, s, m->geo32.p, m->tst.p,
+template <class R, bool A, bool B, bool C>
+void launch_pairs(dim3 grid, hipStream_t s, bem_mesh *m, int j0, DCoefT<R> cf,
+                  const DIntT<R> *itab, typename DM<R>::C *Q) {
+    const R *geo;
+    if constexpr (std::is_same<R, float>::value) geo = m->geo32.p;
+    else geo = m->geo64.p;
+    hipLaunchKernelGGL((dense_pairs_kernel<R, A, B, C>), grid, dim3(256), 0, s, geo, m->tst.p,
                        m->tobj_d.p, m->tri_d.p, m->star_ptr.p, m->star_idx.p, (int)m->T, j0,
                        m->N, cf, itab, Q);
 }
 
-}   // namespace
-
-int64_t dense_bytes(const bem_mesh *m) { return 4 * m->N * m->N * (int64_t)sizeof(float2); }
-int64_t dense_assembly_scratch_bytes(const bem_mesh *m) {
-    return m->T * (int64_t)JT * 12 * (int64_t)sizeof(float2) + 2 * m->N * (int64_t)sizeof(float2);
-}
-
-std::unique_ptr<DenseOperator> dense_assemble(bem_mesh *m, const NearOperator &nf, double2 k0,
-                                              double2 k1, double rho, hipStream_t s) {
-    auto op = std::make_unique<DenseOperator>();
-    const int64_t N = m->N, n2 = 2 * N;
-    op->n2 = n2;
-    op->T = m->T;
-    op->B.alloc((size_t)(n2 * n2));
-    DevBuf<float2> Q((size_t)m->T * JT * 12);
-    const DCoef cf = make_dcoef(k0, nf);
-    DevBuf<float> itab;   // per-object interior parts (several objects)
+// assembly of the operator in precision R into B ([2N][2N], row-major)
+template <class R>
+void assemble_into(bem_mesh *m, const NearOperator &nf, double2 k0, typename DM<R>::C *B,
+                   hipStream_t s) {
+    using C = typename DM<R>::C;
+    const int64_t N = m->N;
+    DevBuf<C> Q((size_t)m->T * JT * 12);
+    const DCoefT<R> cf = make_dcoef<R>(k0, nf);
+    DevBuf<R> itab;   // per-object interior parts (several objects)
     if (m->nobj > 1) {
-        std::vector<float> h((size_t)m->nobj * (sizeof(DInt) / sizeof(float)));
+        constexpr size_t W = sizeof(DIntT<R>) / sizeof(R);
+        std::vector<R> h((size_t)m->nobj * W);
         for (int o = 0; o < m->nobj; o++) {
-            const DInt c = make_dint(k0, nf.k1o[o], nf.rhoo[o], nf.s1);
-            std::memcpy(h.data() + (size_t)o * (sizeof(DInt) / sizeof(float)), &c, sizeof(c));
+            const DIntT<R> c = make_dint<R>(k0, nf.k1o[o], nf.rhoo[o], nf.s1);
+            std::memcpy(h.data() + (size_t)o * W, &c, sizeof(c));
         }
         itab.upload(h);
     }
+    const DIntT<R> *it = (const DIntT<R> *)itab.p;
     const int code = (k0.y != 0 ? 4 : 0) | (nf.k1_plan.y != 0 ? 2 : 0) | (m->nobj > 1 ? 1 : 0);
-    Timer tm("dense_assemble", s);
     for (int64_t j0 = 0; j0 < N; j0 += JT) {
         const int jt = (int)std::min<int64_t>(JT, N - j0);
         dim3 grid((unsigned)((m->T + 255) / 256), jt);
         switch (code) {
-        case 0: launch_pairs<false, false, false>(grid, s, m, (int)j0, cf, (const DInt *)itab.p, Q.p); break;
-        case 1: launch_pairs<false, false, true>(grid, s, m, (int)j0, cf, (const DInt *)itab.p, Q.p); break;
-        case 2: launch_pairs<false, true, false>(grid, s, m, (int)j0, cf, (const DInt *)itab.p, Q.p); break;
-        case 3: launch_pairs<false, true, true>(grid, s, m, (int)j0, cf, (const DInt *)itab.p, Q.p); break;
-        case 4: launch_pairs<true, false, false>(grid, s, m, (int)j0, cf, (const DInt *)itab.p, Q.p); break;
-        case 5: launch_pairs<true, false, true>(grid, s, m, (int)j0, cf, (const DInt *)itab.p, Q.p); break;
-        case 6: launch_pairs<true, true, false>(grid, s, m, (int)j0, cf, (const DInt *)itab.p, Q.p); break;
-        default: launch_pairs<true, true, true>(grid, s, m, (int)j0, cf, (const DInt *)itab.p, Q.p); break;
+        case 0: launch_pairs<R, false, false, false>(grid, s, m, (int)j0, cf, it, Q.p); break;
+        case 1: launch_pairs<R, false, false, true>(grid, s, m, (int)j0, cf, it, Q.p); break;
+        case 2: launch_pairs<R, false, true, false>(grid, s, m, (int)j0, cf, it, Q.p); break;
+        case 3: launch_pairs<R, false, true, true>(grid, s, m, (int)j0, cf, it, Q.p); break;
+        case 4: launch_pairs<R, true, false, false>(grid, s, m, (int)j0, cf, it, Q.p); break;
+        case 5: launch_pairs<R, true, false, true>(grid, s, m, (int)j0, cf, it, Q.p); break;
+        case 6: launch_pairs<R, true, true, false>(grid, s, m, (int)j0, cf, it, Q.p); break;
+        default: launch_pairs<R, true, true, true>(grid, s, m, (int)j0, cf, it, Q.p); break;
         }
         BEM_LAUNCH_CHECK();
-        hipLaunchKernelGGL(dense_gather_kernel, dim3((unsigned)N, (jt + 255) / 256), dim3(256), 0,
-                           s, Q.p, m->star_ptr.p, m->star_idx.p, N, (int)j0, jt, op->B.p);
+        hipLaunchKernelGGL(dense_gather_kernel<C>, dim3((unsigned)N, (jt + 255) / 256), dim3(256),
+                           0, s, Q.p, m->star_ptr.p, m->star_idx.p, N, (int)j0, jt, B);
         BEM_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(dense_add_near_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
-                       m->nf_rowptr.p, m->nf_col.p, (const double2 *)nf.vals.p, m->nf_nnz, N,
-                       op->B.p);
+    if constexpr (std::is_same<R, float>::value)
+        hipLaunchKernelGGL(dense_add_near_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0,
+                           s, m->nf_rowptr.p, m->nf_col.p, (const double2 *)nf.vals.p, m->nf_nnz,
+                           N, B);
+    else
+        hipLaunchKernelGGL(dense_add_near64_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256),
+                           0, s, m->nf_rowptr.p, m->nf_col.p, (const double2 *)nf.vals.p,
+                           m->nf_nnz, N, B);
     BEM_LAUNCH_CHECK();
-    BEM_HIP(hipStreamSynchronize(s));   // Q is released on return
+    BEM_HIP(hipStreamSynchronize(s));   // Q and the table are released on return
+}
+
+}   // namespace
+
+int64_t dense_bytes(const bem_mesh *m, bool fp64) {
+    return 4 * m->N * m->N * (int64_t)(fp64 ? sizeof(double2) : sizeof(float2));
+}
+int64_t dense_assembly_scratch_bytes(const bem_mesh *m, bool fp64) {
+    const int64_t c = fp64 ? sizeof(double2) : sizeof(float2);
+    return m->T * (int64_t)JT * 12 * c + 2 * m->N * (int64_t)sizeof(float2);
+}
+
+std::unique_ptr<DenseOperator> dense_assemble(bem_mesh *m, const NearOperator &nf, double2 k0,
+                                              double2 k1, double rho, hipStream_t s, bool fp64) {
+    (void)k1;
+    (void)rho;
+    auto op = std::make_unique<DenseOperator>();
+    const int64_t n2 = 2 * m->N;
+    op->n2 = n2;
+    op->T = m->T;
+    op->fp64 = fp64;
+    Timer tm(fp64 ? "dense_assemble_fp64" : "dense_assemble", s);
+    if (fp64) {
+        op->B64.alloc((size_t)(n2 * n2));
+        assemble_into<double>(m, nf, k0, op->B64.p, s);
+    } else {
+        op->B.alloc((size_t)(n2 * n2));
+        assemble_into<float>(m, nf, k0, op->B.p, s);
+    }
     return op;
 }
 
@@ -795,6 +948,16 @@ int64_t dense_gemm_scratch_bytes(const bem_mesh *m, int R) {
 
 void dense_apply(const DenseOperator &op, const double2 *x, double2 *y, int R,
                  DevBuf<float2> &xs, hipStream_t s, const TuneEntry *forced) {
+    if (op.fp64) {   // complex128 operator: one pass per vector
+        Timer tm("dense_gemv_fp64", s);
+        for (int r = 0; r < R; r++) {
+            hipLaunchKernelGGL(dense_gemv64_kernel,
+                               dim3((unsigned)((op.n2 + 4 * G64_RW - 1) / (4 * G64_RW))),
+                               dim3(256), 0, s, op.B64.p, op.n2, x + r * op.n2, y + r * op.n2);
+            BEM_LAUNCH_CHECK();
+        }
+        return;
+    }
     const TuneEntry te = forced ? *forced : tune_lookup(op.T, R);
     if (R >= te.gemm_min) dense_gemm(op, x, y, R, s);
     else dense_gemv(op, x, y, R, xs, s, R >= te.skinny_min);
@@ -825,24 +988,28 @@ void dense_gemm(const DenseOperator &op, const double2 *x, double2 *y, int R, hi
 }
 
 const DenseOperator &dense_get(bem_mesh *m, double2 k0, double2 k1, double rho, hipStream_t s,
-                               int s1, const ObjMaterials *om) {
+                               int s1, const ObjMaterials *om, bool fp64) {
     const NearKey key = near_key(m, k0, k1, rho, s1, om);
-    auto it = m->dense_cache.find(key);
-    if (it != m->dense_cache.end()) return *it->second;
+    auto &cache = fp64 ? m->dense64_cache : m->dense_cache;
+    auto it = cache.find(key);
+    if (it != cache.end()) return *it->second;
     const NearOperator &nf = nearfield_get(m, k0, k1, rho, s, s1, om);
     // one resident dense operator per mesh unless memory allows more
+    const int64_t need = dense_bytes(m, fp64) + dense_assembly_scratch_bytes(m, fp64) +
+                         (int64_t)(1ll << 30);
     size_t free_b = 0, total_b = 0;
     BEM_HIP(hipMemGetInfo(&free_b, &total_b));
-    while (!m->dense_cache.empty() && (int64_t)free_b < dense_bytes(m) + (int64_t)(1ll << 30)) {
-        m->dense_cache.erase(m->dense_cache.begin());
+    while ((!m->dense_cache.empty() || !m->dense64_cache.empty()) && (int64_t)free_b < need) {
+        auto &victim = m->dense64_cache.empty() ? m->dense_cache : m->dense64_cache;
+        victim.erase(victim.begin());
         BEM_HIP(hipMemGetInfo(&free_b, &total_b));
     }
-    if ((int64_t)free_b < dense_bytes(m) + (int64_t)(1ll << 30))
-        fail(BEM_E_NOMEM, "dense operator of " + std::to_string(dense_bytes(m)) +
+    if ((int64_t)free_b < need)
+        fail(BEM_E_NOMEM, "dense operator of " + std::to_string(dense_bytes(m, fp64)) +
                               " bytes does not fit in device memory");
-    auto op = dense_assemble(m, nf, k0, k1, rho, s);
+    auto op = dense_assemble(m, nf, k0, k1, rho, s, fp64);
     auto &ref = *op;
-    m->dense_cache.emplace(key, std::move(op));
+    cache.emplace(key, std::move(op));
     return ref;
 }
 

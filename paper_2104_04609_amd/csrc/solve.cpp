@@ -58,12 +58,15 @@ struct Op {
     hipStream_t s;
     int form = BEM_FORM_OSRC;
     const DenseOperator *dense = nullptr;   // assembled operator (FP32 form)
+    const DenseOperator *dense64 = nullptr; // assembled complex128 operator (FP64 form, path 1)
     const ObjMaterials *om = nullptr;       // per-object materials, or k1, rho for all
     DevBuf<double2> yw, t1, t2;              // weak-form scratch [R][2N]
     DevBuf<double2> px, py;                  // one object's entries [R][2 N_m]
     void weak(const double2 *in, double2 *out, int R, int precision) {
         if (precision == BEM_FP32_DENSE) {
             dense_apply(*dense, in, out, R, m->xs32, s);
+        } else if (precision == BEM_FP64 && dense64) {
+            dense_apply(*dense64, in, out, R, m->xs32, s);
         } else {
             farfield_apply_batch(m, *nf, k0, k1, rho, in, out, R, precision, s);
         }
@@ -86,8 +89,10 @@ struct Op {
             gather_halves(in, m->part_vidx[o].p, m->N, nm, R, px.p, s);
             const double2 ko = om ? om->k[o] : k1;
             const double ro = om ? om->rho[o] : rho;
-            if (precision == BEM_FP32_DENSE) {
-                dense_apply(dense_get(pm, k0, ko, ro, s), px.p, py.p, R, pm->xs32, s);
+            if (precision == BEM_FP32_DENSE || (precision == BEM_FP64 && dense64)) {
+                const bool f64 = precision == BEM_FP64;
+                dense_apply(dense_get(pm, k0, ko, ro, s, 1, nullptr, f64), px.p, py.p, R,
+                            pm->xs32, s);
             } else {
                 const NearOperator &nfo = nearfield_get(pm, k0, ko, ro, s);
                 farfield_apply_batch(pm, nfo, k0, ko, ro, px.p, py.p, R, precision, s);
@@ -354,6 +359,8 @@ int64_t solve_footprint(bem_mesh *m, double2 k0, double2 k1, double rho,
     b += osrc_state_bytes(m, o.pade_terms, G);                 // OSRC factors + batch buffers
     int64_t scratch = farfield_scratch_bytes(m, BEM_FP64, k0, k1, G);
     const bool dense = o.precision == BEM_FP32 && o.path == 1;
+    if (o.precision == BEM_FP64 && o.path == 1)
+        b += dense_bytes(m, true) + dense_assembly_scratch_bytes(m, true);
     if (o.precision == BEM_FP32 && !dense)
         scratch += farfield_scratch_bytes(m, BEM_FP32, k0, k1, G);   // dyn32 beside dyn64
     b += scratch;
@@ -393,6 +400,7 @@ int solve_run(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dir
     op.form = o.formulation;
     op.om = om;
     int inner = BEM_FP32;
+    if (o.precision == BEM_FP64 && o.path == 1) op.dense64 = &dense_get(m, k0, k1, rho, s, s1, om, true);
     if (o.precision == BEM_FP32 && o.path != 0) {
         bool use = o.path == 1;
         if (o.path == 2) {   // autotuned choice, else dense when it fits with room to spare

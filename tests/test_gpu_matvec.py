@@ -15,7 +15,7 @@ from bem_inputs import (complex_normal, geodesic_sphere, icosphere, sample_rows,
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-10, "fp32": 1e-5, "fp32_dense": 1e-5}
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "fp32_dense": 1e-5, "fp64_dense": 1e-10}
 
 
 @pytest.fixture(scope="module")
@@ -62,7 +62,7 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_dense"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_dense", "fp64_dense"])
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_matvec_matches_dense_oracle(P, case, precision):
     make, k0, k1, rho = CASES[case]
@@ -90,7 +90,7 @@ def test_matvec_smooth_input_fp32(P):
     assert max(err.values()) <= TOL["fp32"], err
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_dense"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_dense", "fp64_dense"])
 def test_matvec_full_size_sampled_rows(P, precision):
     """Icosphere L5 (10 242 vertices), k_ext = 10, k_int = 15, rho = 1.5, in
     the launch configuration used for timing; 40 seed-sampled rows of each

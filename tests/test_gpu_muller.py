@@ -16,7 +16,7 @@ from bem_inputs import complex_normal, geodesic_sphere, icosphere, sample_rows, 
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-10, "fp32": 1e-5, "fp32_dense": 1e-5}
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "fp32_dense": 1e-5, "fp64_dense": 1e-10}
 
 CASES = {
     "C1_ico3": (lambda: icosphere(3), 2.0, 3.0, 1.5),
@@ -69,7 +69,7 @@ def tuning(P):
         P.tune_set(k, v)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_dense"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_dense", "fp64_dense"])
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_muller_matches_dense_oracle(P, case, precision):
     make, k0, k1, rho = CASES[case]

@@ -16,7 +16,7 @@ from bem_inputs import (complex_normal, density_ratio, four_spheres, two_spheres
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-10, "fp32": 1e-5, "fp32_dense": 1e-5}
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "fp32_dense": 1e-5, "fp64_dense": 1e-10}
 F, A = 5e5, 5e-3
 K0 = wavenumber("water", F, A)
 TISSUE = ["fat", "bone", "bone", "fat"]
@@ -69,7 +69,7 @@ def tuning(P):
         P.tune_set(k, v)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_dense"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_dense", "fp64_dense"])
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_matvec_multi_matches_oracle(P, tuning, case, precision):
     import torch

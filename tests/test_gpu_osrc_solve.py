@@ -89,14 +89,17 @@ SOLVE_CASES = {
 }
 
 
+@pytest.mark.parametrize("path", [0, 1])
 @pytest.mark.parametrize("case", sorted(SOLVE_CASES))
-def test_solve_fp64_matches_oracle(P, case):
+def test_solve_fp64_matches_oracle(P, case, path):
+    """FP64 GMRES on the matrix-free operator (path 0) and on the assembled
+    complex128 operator (path 1)."""
     make, k0, k1, rho = SOLVE_CASES[case]
     mesh = make()
-    print(f"solve {case}", flush=True)
+    print(f"solve {case} path {path}", flush=True)
     S, xo, it_o = oracle_solve(mesh, k0, k1, rho, 1e-10)
     M = P.Mesh.from_inputs(mesh)
-    sol, info, rc = P.pmchwt_solve(M, k0, k1, rho, [[0.0, 0.0, 1.0]], 1e-10)
+    sol, info, rc = P.pmchwt_solve(M, k0, k1, rho, [[0.0, 0.0, 1.0]], 1e-10, path=path)
     x = sol.cpu().numpy()[0]
     err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
     print(case, "err", err, "iters gpu", info[0]["iterations"], "oracle", it_o, info[0])

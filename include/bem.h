@@ -216,7 +216,10 @@ typedef struct {
     int fp64_matvecs;
     int fp32_matvecs;
     double rel_residual; /* ||b - P x|| / ||b||, P with the FP64 operator */
-    double seconds;      /* wall time of this wave's solve */
+    double seconds;      /* wall time of the solve of this wave's lockstep group, from
+                            its first preconditioning to convergence; the set-up shared
+                            by all waves (near field, OSRC factors, assembled operator)
+                            is not included */
 } bem_solve_info;
 
 /* Fill *opts with the defaults above. */

@@ -158,9 +158,11 @@ int bem_mesh_info(const bem_mesh *m, int64_t *nv, int64_t *nt, int32_t *nobj,
     BEM_API_END
 }
 
+}   // extern "C"
+
 namespace {
 
-// Body of pmchwt_matvec (s1 = +1) and muller_matvec (s1 = -1); throws.
+// Per-object interior wavenumbers and density ratios, checked; throws.
 bem::ObjMaterials materials(const bem_mesh *mesh, const bem_c64 *k_int, const double *rho) {
     if (!k_int || !rho) fail(BEM_E_INVAL, "k_int and rho must not be NULL");
     check_mesh(mesh);
@@ -173,6 +175,7 @@ bem::ObjMaterials materials(const bem_mesh *mesh, const bem_c64 *k_int, const do
     return om;
 }
 
+// Body of pmchwt_matvec (s1 = +1) and muller_matvec (s1 = -1); throws.
 void operator_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
                      const bem_c64 *x, bem_c64 *y, int n_rhs, int precision,
                      void *hip_stream, int s1, const bem::ObjMaterials *om = nullptr) {
@@ -201,6 +204,8 @@ void operator_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double 
 }
 
 }   // namespace
+
+extern "C" {
 
 int pmchwt_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
                   const bem_c64 *x, bem_c64 *y, int n_rhs, int precision,

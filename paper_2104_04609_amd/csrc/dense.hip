@@ -6,13 +6,24 @@
 //
 // Entries are the same sums as the matrix-free matvec: the 6x6 rule (FP32)
 // over every test/trial triangle pair sharing no vertex, plus the FP64
-// near-field operator of the pairs that do.  Assembly is deterministic: per
-// tile J of trial vertices,
+// near-field operator of the pairs that do.
+//
+// The far part is symmetric under exchange of test and trial functions (the
+// same rule on both sides, a kernel symmetric in x and y): V and D are
+// symmetric and K' = K^T, so B[j][i] = B[i][j], B[N+j][N+i] = B[N+i][N+j] and
+// B[N+j][i] = -B[i][N+j].  Only the entries with rank(i) <= rank(j) are
+// evaluated, rank being the vertex's place in a Morton order of the vertex
+// coordinates (vertices of one triangle get close ranks, so that about half
+// of the work remains); dense_mirror_kernel fills in the others.  Per tile J
+// of trial vertices (consecutive ranks),
 //   dense_pairs_kernel:  Q[tau][j][a][blk] = sum_{sigma in star(j)} local
-//                        block (tau, sigma)[a][b(sigma, j)]    (thread (tau, j))
-//   dense_gather_kernel: B[i][j] = sum_{(tau, a) in star(i)} Q[tau][j][a]   (thread (i, j))
-// Each separated triangle pair is evaluated three times (once per trial
-// vertex), about three matrix-free matvecs of work per assembly.
+//                        block (tau, sigma)[a][b(sigma, j)]    (thread (tau, j),
+//                        only where min rank(tau) <= rank(j))
+//   dense_gather_kernel: B[i][j] = sum_{(tau, a) in star(i)} Q[tau][j][a]   (thread (i, j),
+//                        only where rank(i) <= rank(j))
+// Each separated triangle pair is evaluated about 1.5 times (three times for
+// every trial vertex without the symmetry); assembly is deterministic.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -103,16 +114,21 @@ template <class R, bool CK0, bool CK1, bool MULTI>
 __global__ __launch_bounds__(256) void dense_pairs_kernel(
     const R *__restrict__ geo, const double *__restrict__ tst,
     const int32_t *__restrict__ tobj, const int32_t *__restrict__ tri,
-    const int32_t *__restrict__ star_ptr, const int32_t *__restrict__ star_idx, int T, int j0,
-    int64_t N, DCoefT<R> cf, const DIntT<R> *__restrict__ itab, typename DM<R>::C *__restrict__ Q) {
+    const int32_t *__restrict__ star_ptr, const int32_t *__restrict__ star_idx,
+    const int32_t *__restrict__ order, int n_tau, const int32_t *__restrict__ rank,
+    const int32_t *__restrict__ byrank, int T, int r0, int64_t N, DCoefT<R> cf,
+    const DIntT<R> *__restrict__ itab, typename DM<R>::C *__restrict__ Q) {
     using M = DM<R>;
     __shared__ double2 etab[std::is_same<R, double>::value ? 256 : 1];   // FP64 sin/cos table
     M::fill_table(etab);
     __syncthreads();
-    const int tau = blockIdx.x * 256 + threadIdx.x;
+    // test triangles in ascending order of their smallest vertex rank: the
+    // first n_tau of them have a vertex ranked inside or before this tile
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    const int tau = k < n_tau ? order[k] : T;
     const int jl = blockIdx.y;
-    const int64_t j = j0 + jl;
-    const bool active = tau < T && j < N;
+    const int rj = r0 + jl;
+    const int j = rj < N ? byrank[rj] : 0;
     const int tt = tau < T ? tau : 0;
     const R *g = geo + (int64_t)GEO_STRIDE * tt;
     R px[6], py[6], pz[6];
@@ -123,12 +139,15 @@ __global__ __launch_bounds__(256) void dense_pairs_kernel(
     }
     const R ntx = g[18], nty = g[19], ntz = g[20], ct = g[21];
     const int tv0 = tri[3 * tt], tv1 = tri[3 * tt + 1], tv2 = tri[3 * tt + 2];
+    // Q[tau][j] is read only for rows i of tau with rank(i) <= rank(j)
+    const bool active = tau < T && rj < N &&
+                        min(rank[tv0], min(rank[tv1], rank[tv2])) <= rj;
     const int ot = MULTI ? tobj[tt] : 0;
     R cu[9];
     for (int c = 0; c < 9; c++) cu[c] = (R)tst[TST_STRIDE * tt + 1 + c];
     R outr[12], outi[12];   // [blk * 3 + a]
     for (int c = 0; c < 12; c++) outr[c] = outi[c] = (R)0;
-    const int e0 = j < N ? star_ptr[j] : 0, e1 = j < N ? star_ptr[j + 1] : 0;
+    const int e0 = active ? star_ptr[j] : 0, e1 = active ? star_ptr[j + 1] : 0;
     for (int e = e0; e < e1; e++) {
         const int sb = star_idx[e];
         const int s = sb / 3, b = sb - 3 * s;
@@ -256,16 +275,19 @@ __global__ __launch_bounds__(256) void dense_pairs_kernel(
     for (int c = 0; c < 12; c++) o[c] = M::mk(sc * outr[c], sc * outi[c]);
 }
 
-// B[i][j], B[i][N+j], B[N+i][j], B[N+i][N+j] from the star of test vertex i
+// B[i][j], B[i][N+j], B[N+i][j], B[N+i][N+j] from the star of test vertex i,
+// for the trial vertices j of the tile with rank(j) >= rank(i)
 template <class C>
 __global__ __launch_bounds__(256) void dense_gather_kernel(const C *__restrict__ Q,
                                                            const int32_t *__restrict__ star_ptr,
                                                            const int32_t *__restrict__ star_idx,
-                                                           int64_t N, int j0, int jt,
+                                                           const int32_t *__restrict__ rank,
+                                                           const int32_t *__restrict__ byrank,
+                                                           int64_t N, int r0, int jt,
                                                            C *__restrict__ B) {
     const int jl = blockIdx.y * 256 + threadIdx.x;
     const int64_t i = blockIdx.x;
-    if (jl >= jt) return;
+    if (jl >= jt || rank[i] > r0 + jl) return;
     C acc[4];
     for (int k = 0; k < 4; k++) acc[k].x = acc[k].y = 0;
     for (int e = star_ptr[i]; e < star_ptr[i + 1]; e++) {
@@ -277,11 +299,51 @@ __global__ __launch_bounds__(256) void dense_gather_kernel(const C *__restrict__
             acc[k].y += q[3 * k + a].y;
         }
     }
-    const int64_t n2 = 2 * N, j = j0 + jl;
+    const int64_t n2 = 2 * N, j = byrank[r0 + jl];
     B[i * n2 + j] = acc[0];
     B[i * n2 + N + j] = acc[1];
     B[(N + i) * n2 + j] = acc[2];
     B[(N + i) * n2 + N + j] = acc[3];
+}
+
+// Entries with rank(i) > rank(j) from their mirror images (blockIdx.z picks
+// the block): B[i][j] = B[j][i], B[N+i][N+j] = B[N+j][N+i],
+// B[N+i][j] = -B[j][N+i], B[i][N+j] = -B[N+j][i].  32 x 32 tiles transposed
+// through LDS; the entries read are never written here (their row ranks lower).
+template <class C>
+__global__ __launch_bounds__(256) void dense_mirror_kernel(const int32_t *__restrict__ rank,
+                                                           int64_t N, C *__restrict__ B) {
+    __shared__ C tile[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int64_t I0 = (int64_t)blockIdx.x * 32, J0 = (int64_t)blockIdx.y * 32;
+    const int64_t n2 = 2 * N;
+    const int z = blockIdx.z;
+    const int64_t ro = (z == 0 || z == 2) ? 0 : N;   // row offset of the entries read
+    const int64_t co = (z == 0 || z == 3) ? 0 : N;   // column offset of the entries read
+    const float sg = z < 2 ? 1.0f : -1.0f;
+    // read B[ro + j][co + i] for j in the J tile, i in the I tile
+    const int64_t ic = I0 + tx;
+    const int ri = ic < N ? rank[ic] : 0;
+    for (int rr = 0; rr < 32; rr += 8) {
+        const int64_t jr = J0 + ty + rr;
+        C v;
+        v.x = v.y = 0;
+        if (jr < N && ic < N && rank[jr] < ri) v = B[(ro + jr) * n2 + co + ic];
+        tile[ty + rr][tx] = v;
+    }
+    __syncthreads();
+    // write B[co + i][ro + j] for i in the I tile, j in the J tile
+    const int64_t jc = J0 + tx;
+    const int rjc = jc < N ? rank[jc] : 0;
+    for (int rr = 0; rr < 32; rr += 8) {
+        const int64_t ir = I0 + ty + rr;
+        if (ir < N && jc < N && rank[ir] > rjc) {
+            C v = tile[tx][ty + rr];
+            v.x *= sg;
+            v.y *= sg;
+            B[(co + ir) * n2 + ro + jc] = v;
+        }
+    }
 }
 
 // add the FP64 near-field operator (complex64: summed in FP64, rounded once)
@@ -784,15 +846,67 @@ template <class R> DCoefT<R> make_dcoef(double2 k0, const NearOperator &nf) {
     return c;
 }
 
+struct RankOrder {
+    DevBuf<int32_t> rank, byrank, order;   // [N], [N], [T]
+    std::vector<int32_t> minrank_sorted;   // [T]
+    explicit RankOrder(const bem_mesh *m);
+    int count_below(int r) const;
+};
+
 template <class R, bool A, bool B, bool C>
-void launch_pairs(dim3 grid, hipStream_t s, bem_mesh *m, int j0, DCoefT<R> cf,
-                  const DIntT<R> *itab, typename DM<R>::C *Q) {
+void launch_pairs(dim3 grid, hipStream_t s, bem_mesh *m, const RankOrder &ro, int n_tau, int r0,
+                  DCoefT<R> cf, const DIntT<R> *itab, typename DM<R>::C *Q) {
     const R *geo;
     if constexpr (std::is_same<R, float>::value) geo = m->geo32.p;
     else geo = m->geo64.p;
     hipLaunchKernelGGL((dense_pairs_kernel<R, A, B, C>), grid, dim3(256), 0, s, geo, m->tst.p,
-                       m->tobj_d.p, m->tri_d.p, m->star_ptr.p, m->star_idx.p, (int)m->T, j0,
-                       m->N, cf, itab, Q);
+                       m->tobj_d.p, m->tri_d.p, m->star_ptr.p, m->star_idx.p, ro.order.p, n_tau,
+                       ro.rank.p, ro.byrank.p, (int)m->T, r0, m->N, cf, itab, Q);
+}
+
+// Vertex ranks in Morton order of the coordinates (10 bits per axis over the
+// bounding box, ties by index) and the triangles in ascending order of their
+// smallest vertex rank; minrank_sorted[k] is that rank for order[k].
+RankOrder::RankOrder(const bem_mesh *m) {
+    const int64_t N = m->N, T = m->T;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t v = 0; v < N; v++)
+        for (int a = 0; a < 3; a++) {
+            lo[a] = std::min(lo[a], m->P[3 * v + a]);
+            hi[a] = std::max(hi[a], m->P[3 * v + a]);
+        }
+    std::vector<uint64_t> code(N);
+    for (int64_t v = 0; v < N; v++) {
+        uint64_t c = 0;
+        for (int a = 0; a < 3; a++) {
+            const double ext = hi[a] - lo[a];
+            const double u = ext > 0 ? (m->P[3 * v + a] - lo[a]) / ext : 0.0;
+            const uint64_t q = (uint64_t)std::min(1023.0, std::max(0.0, u * 1023.0));
+            for (int b = 0; b < 10; b++) c |= ((q >> b) & 1u) << (3 * b + a);
+        }
+        code[v] = c;
+    }
+    std::vector<int32_t> by(N), rk(N);
+    for (int64_t v = 0; v < N; v++) by[v] = (int32_t)v;
+    std::stable_sort(by.begin(), by.end(), [&](int32_t a, int32_t b) { return code[a] < code[b]; });
+    for (int64_t r = 0; r < N; r++) rk[by[r]] = (int32_t)r;
+    std::vector<int32_t> mr(T), ord(T);
+    for (int64_t t = 0; t < T; t++) {
+        mr[t] = std::min(rk[m->tri[3 * t]], std::min(rk[m->tri[3 * t + 1]], rk[m->tri[3 * t + 2]]));
+        ord[t] = (int32_t)t;
+    }
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return mr[a] < mr[b]; });
+    minrank_sorted.resize(T);
+    for (int64_t k = 0; k < T; k++) minrank_sorted[k] = mr[ord[k]];
+    rank.upload(rk);
+    byrank.upload(by);
+    order.upload(ord);
+}
+
+// number of triangles whose smallest vertex rank is below r
+int RankOrder::count_below(int r) const {
+    return (int)(std::lower_bound(minrank_sorted.begin(), minrank_sorted.end(), r) -
+                 minrank_sorted.begin());
 }
 
 // assembly of the operator in precision R into B ([2N][2N], row-major)
@@ -815,22 +929,35 @@ void assemble_into(bem_mesh *m, const NearOperator &nf, double2 k0, typename DM<
     }
     const DIntT<R> *it = (const DIntT<R> *)itab.p;
     const int code = (k0.y != 0 ? 4 : 0) | (nf.k1_plan.y != 0 ? 2 : 0) | (m->nobj > 1 ? 1 : 0);
-    for (int64_t j0 = 0; j0 < N; j0 += JT) {
-        const int jt = (int)std::min<int64_t>(JT, N - j0);
-        dim3 grid((unsigned)((m->T + 255) / 256), jt);
-        switch (code) {
-        case 0: launch_pairs<R, false, false, false>(grid, s, m, (int)j0, cf, it, Q.p); break;
-        case 1: launch_pairs<R, false, false, true>(grid, s, m, (int)j0, cf, it, Q.p); break;
-        case 2: launch_pairs<R, false, true, false>(grid, s, m, (int)j0, cf, it, Q.p); break;
-        case 3: launch_pairs<R, false, true, true>(grid, s, m, (int)j0, cf, it, Q.p); break;
-        case 4: launch_pairs<R, true, false, false>(grid, s, m, (int)j0, cf, it, Q.p); break;
-        case 5: launch_pairs<R, true, false, true>(grid, s, m, (int)j0, cf, it, Q.p); break;
-        case 6: launch_pairs<R, true, true, false>(grid, s, m, (int)j0, cf, it, Q.p); break;
-        default: launch_pairs<R, true, true, true>(grid, s, m, (int)j0, cf, it, Q.p); break;
+    const RankOrder ro(m);
+    for (int64_t r0 = 0; r0 < N; r0 += JT) {
+        const int jt = (int)std::min<int64_t>(JT, N - r0);
+        // test triangles with a vertex ranked below the tile's end
+        const int n_tau = ro.count_below((int)(r0 + jt));
+        if (n_tau > 0) {
+            dim3 grid((unsigned)((n_tau + 255) / 256), jt);
+            const int r = (int)r0;
+            switch (code) {
+            case 0: launch_pairs<R, false, false, false>(grid, s, m, ro, n_tau, r, cf, it, Q.p); break;
+            case 1: launch_pairs<R, false, false, true>(grid, s, m, ro, n_tau, r, cf, it, Q.p); break;
+            case 2: launch_pairs<R, false, true, false>(grid, s, m, ro, n_tau, r, cf, it, Q.p); break;
+            case 3: launch_pairs<R, false, true, true>(grid, s, m, ro, n_tau, r, cf, it, Q.p); break;
+            case 4: launch_pairs<R, true, false, false>(grid, s, m, ro, n_tau, r, cf, it, Q.p); break;
+            case 5: launch_pairs<R, true, false, true>(grid, s, m, ro, n_tau, r, cf, it, Q.p); break;
+            case 6: launch_pairs<R, true, true, false>(grid, s, m, ro, n_tau, r, cf, it, Q.p); break;
+            default: launch_pairs<R, true, true, true>(grid, s, m, ro, n_tau, r, cf, it, Q.p); break;
+            }
+            BEM_LAUNCH_CHECK();
         }
-        BEM_LAUNCH_CHECK();
         hipLaunchKernelGGL(dense_gather_kernel<C>, dim3((unsigned)N, (jt + 255) / 256), dim3(256),
-                           0, s, Q.p, m->star_ptr.p, m->star_idx.p, N, (int)j0, jt, B);
+                           0, s, Q.p, m->star_ptr.p, m->star_idx.p, ro.rank.p, ro.byrank.p, N,
+                           (int)r0, jt, B);
+        BEM_LAUNCH_CHECK();
+    }
+    {
+        const unsigned nt = (unsigned)((N + 31) / 32);
+        hipLaunchKernelGGL(dense_mirror_kernel<C>, dim3(nt, nt, 4), dim3(256), 0, s, ro.rank.p, N,
+                           B);
         BEM_LAUNCH_CHECK();
     }
     if constexpr (std::is_same<R, float>::value)

@@ -177,11 +177,12 @@ typedef struct {
                             residual inner_tol * tol * ||b|| (at most half of
                             the current outer residual); default 0.6 */
     int max_outer;       /* refinement steps cap, default 8 */
-    int path;            /* FP32 form inner operator: 0 matrix-free pair kernel,
-                            1 assembled dense complex64 operator, 2 dense when
-                            it fits in device memory (default).  FP64 form:
-                            1 assembled dense complex128 operator, else
-                            matrix-free */
+    int path;            /* operator of the GMRES iterations: 0 matrix-free
+                            pair kernel, 1 assembled dense operator (complex64
+                            for the FP32 form's inner solves, complex128 for
+                            the FP64 form), 2 assembled when it fits in device
+                            memory and the autotuned table does not prefer
+                            the matrix-free path (default) */
     int formulation;     /* BEM_FORM_OSRC (default), BEM_FORM_PMCHWT,
                             BEM_FORM_CALDERON or BEM_FORM_MULLER; see below */
 } bem_solve_opts;
@@ -311,8 +312,10 @@ int bem_far_field(const bem_mesh *mesh, bem_c64 k_ext, const bem_c64 *solution,
  * arrival order, except that a request that fits may pass one that does not
  * while the latter has waited less than 2 s.
  *
- * Path: opts.path 2 (auto) with FP32 becomes the assembled path when the
- * dense complex64 operator is at most dense_max_bytes, else matrix-free; the
+ * Path: opts.path 2 (auto) becomes the assembled path when the dense
+ * operator (complex64 for FP32, complex128 for FP64) is at most
+ * dense_max_bytes and the autotuned table does not prefer the matrix-free
+ * path, else matrix-free; the
  * choice depends only on the request, so a result does not depend on the
  * other requests in flight.
  */
@@ -327,7 +330,7 @@ typedef struct {
 
 typedef struct {
     int status;              /* return code of the solve (BEM_OK, BEM_W_NOT_CONVERGED, < 0) */
-    int path;                /* 0 matrix-free, 1 assembled (FP32 inner operator) */
+    int path;                /* 0 matrix-free, 1 assembled operator */
     double t_submit;         /* seconds since server creation */
     double t_admit;
     double t_end;

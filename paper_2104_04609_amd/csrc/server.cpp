@@ -397,10 +397,11 @@ int server_submit(bem_server *srv, int mesh_id, bem_c64 k_ext, bem_c64 k_int, do
         r->solution = (double2 *)solution;
         r->info = info;
         // the path depends on the request alone (and the autotuned table)
-        if (r->o.precision == BEM_FP32 && r->o.path == 2) {
+        if (r->o.path == 2) {
             bem::TuneEntry te;
             const bool mf = bem::tune_find(h0->T, std::min(n_waves, 16), &te) && te.path == 0;
-            r->o.path = !mf && bem::dense_bytes(h0) <= srv->o.dense_max_bytes ? 1 : 0;
+            const bool f64 = r->o.precision == BEM_FP64;
+            r->o.path = !mf && bem::dense_bytes(h0, f64) <= srv->o.dense_max_bytes ? 1 : 0;
         }
         BEM_HIP(hipGetDevice(&prev));
         BEM_HIP(hipSetDevice(srv->device));
@@ -470,7 +471,7 @@ int bem_server_wait(bem_server *srv, int64_t request_id, double timeout_s,
         return BEM_W_PENDING;
     if (stats) {
         stats->status = r->status;
-        stats->path = r->o.precision == BEM_FP32 && r->o.path == 1 ? 1 : 0;
+        stats->path = r->o.path == 1 ? 1 : 0;
         stats->t_submit = r->t_submit;
         stats->t_admit = r->t_admit;
         stats->t_end = r->t_end;

@@ -370,7 +370,9 @@ int64_t solve_footprint(bem_mesh *m, double2 k0, double2 k1, double rho,
     if (o.formulation == BEM_FORM_CALDERON) {
         b += 2 * (int64_t)G * n2 * c16;                       // t1, t2
         if (m->nobj > 1) b += 4 * m->nf_nnz * c16 + G * n2 * c16 +   // parts: near fields, px, py
-                              (dense ? dense_bytes(m) / m->nobj : 0);
+                              (dense ? dense_bytes(m) / m->nobj : 0) +
+                              (o.precision == BEM_FP64 && o.path == 1 ? dense_bytes(m, true) / m->nobj
+                                                                      : 0);
     }
     else if (o.formulation != BEM_FORM_OSRC) b += (int64_t)G * n2 * c16;       // t1
     b += G * (workspace_peak_vectors(o.maxiter) * n2 * c16 + (2 * (int64_t)o.maxiter + 8) * c16);
@@ -400,18 +402,23 @@ int solve_run(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dir
     op.form = o.formulation;
     op.om = om;
     int inner = BEM_FP32;
-    if (o.precision == BEM_FP64 && o.path == 1) op.dense64 = &dense_get(m, k0, k1, rho, s, s1, om, true);
-    if (o.precision == BEM_FP32 && o.path != 0) {
+    if (o.path != 0) {
+        const bool f64 = o.precision == BEM_FP64;
         bool use = o.path == 1;
         if (o.path == 2) {   // autotuned choice, else dense when it fits with room to spare
             size_t free_b = 0, total_b = 0;
             BEM_HIP(hipMemGetInfo(&free_b, &total_b));
-            const bool fits = dense_bytes(m) + (int64_t)(2ll << 30) < (int64_t)free_b ||
-                              !m->dense_cache.empty();
+            const int64_t need = f64 ? dense_bytes(m, true) + dense_assembly_scratch_bytes(m, true) +
+                                           (int64_t)(1ll << 30)
+                                     : dense_bytes(m) + (int64_t)(2ll << 30);
+            const bool fits = need < (int64_t)free_b ||
+                              !(f64 ? m->dense64_cache.empty() : m->dense_cache.empty());
             TuneEntry te;
             use = fits && !(tune_find(m->T, std::min(n_waves, SOLVE_BATCH), &te) && te.path == 0);
         }
-        if (use) {
+        if (use && f64) {
+            op.dense64 = &dense_get(m, k0, k1, rho, s, s1, om, true);
+        } else if (use) {
             op.dense = &dense_get(m, k0, k1, rho, s, s1, om);
             inner = BEM_FP32_DENSE;
         }

@@ -112,6 +112,34 @@ def test_solve_fp64_matches_oracle(P, case, path):
     assert np.linalg.norm(S.apply(x) - b) / np.linalg.norm(b) <= 2e-10
 
 
+def test_auto_path_fp64_uses_assembled_operator(P):
+    """path 2 (the default) with FP64 on a mesh whose complex128 operator fits:
+    the same operator as path 1, so the same solution bit for bit (fixed
+    reduction order); the matrix-free path 0 agrees within the solve accuracy.
+    The server resolves the request the same way and reports path 1."""
+    import torch
+    P.tune_clear()   # no autotuned preference for the matrix-free path
+    mesh = icosphere(3)
+    M = P.Mesh.from_inputs(mesh)
+    d = [[0.0, 0.0, 1.0]]
+    print("auto path fp64 ico3", flush=True)
+    s2, i2, rc2 = P.pmchwt_solve(M, 2.0, 3.0, 1.5, d, 1e-10, precision="fp64", path=2)
+    s1, i1, rc1 = P.pmchwt_solve(M, 2.0, 3.0, 1.5, d, 1e-10, precision="fp64", path=1)
+    s0, i0, rc0 = P.pmchwt_solve(M, 2.0, 3.0, 1.5, d, 1e-10, precision="fp64", path=0)
+    assert rc0 == rc1 == rc2 == 0
+    assert torch.equal(s1, s2) and i1[0]["iterations"] == i2[0]["iterations"]
+    assert (torch.linalg.norm(s0 - s2) / torch.linalg.norm(s0)).item() <= 1e-8
+    srv = P.Server(workers=1)
+    try:
+        mid = srv.add_mesh(mesh.vertices, mesh.triangles)
+        rid = srv.submit(mid, 2.0, 3.0, 1.5, d, 1e-10, precision="fp64", path=2)
+        sol, info, st = srv.wait(rid)
+    finally:
+        srv.close()
+    assert st["status"] == 0 and st["path"] == 1
+    assert torch.equal(sol.to(s2.device), s2)
+
+
 @pytest.mark.parametrize("path", [0, 1])
 def test_solve_fp32_refinement(P, path):
     """path 0: FP32 matrix-free pair kernel; path 1: assembled complex64."""

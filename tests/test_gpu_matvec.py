@@ -78,6 +78,63 @@ def test_matvec_matches_dense_oracle(P, case, precision):
         assert v <= TOL[precision], err
 
 
+def _relabelled(mesh, seed):
+    """The same surface with its vertices numbered in a seeded random order
+    (within each object's range: the vertices of an object stay contiguous)."""
+    from bem_inputs import Mesh
+    rng = np.random.default_rng(seed)
+    vobj = np.zeros(mesh.n_vertices, dtype=np.int64)
+    if mesh.object_id is not None:
+        vobj[mesh.triangles.ravel()] = np.repeat(mesh.object_id, 3)
+    perm = np.arange(mesh.n_vertices)
+    for o in np.unique(vobj):
+        idx = np.flatnonzero(vobj == o)
+        perm[idx] = rng.permutation(idx)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(mesh.n_vertices)
+    return Mesh(vertices=mesh.vertices[perm], triangles=inv[mesh.triangles].astype(np.int32),
+                object_id=mesh.object_id, name=mesh.name + f"_relabel{seed}",
+                radius=mesh.radius)
+
+
+@pytest.mark.parametrize("precision", ["fp32_dense", "fp64_dense"])
+@pytest.mark.parametrize("operator", ["pmchwt", "pmchwt_multi", "muller"])
+def test_assembled_operator_any_vertex_numbering(P, operator, precision):
+    """The assembled operators evaluate the entries with rank(i) <= rank(j)
+    (vertex ranks in a spatial order) and mirror the others: parity with the
+    oracle on meshes whose vertex numbering is a random permutation (one and
+    two objects, one material per object), so that ranks and indices are
+    unrelated."""
+    import torch
+    from oracle.operators import muller_matrix, pmchwt_matrix, pmchwt_matrix_multi
+    if operator == "pmchwt":
+        mesh, k0, k1, rho = _relabelled(icosphere(3), 7), 2.0, 3.0 + 0.1j, 1.5
+        A = pmchwt_matrix(mesh, k0, k1, rho)
+    elif operator == "pmchwt_multi":
+        mesh = _relabelled(two_spheres(1, offset=1.5), 8)
+        k0, k1, rho = 2.0, [3.5 + 0.2j, 2.5], [1.3, 0.8]
+        A = pmchwt_matrix_multi(mesh, k0, k1, rho)
+    else:
+        mesh, k0, k1, rho = _relabelled(geodesic_sphere(3), 9), 1.5, 2.2, 0.7
+        A = muller_matrix(mesh, k0, k1, rho)
+    print(f"relabelled {operator} N={mesh.n_vertices} {precision}", flush=True)
+    N = mesh.n_vertices
+    x = complex_normal(2 * N, seed=11)
+    M = P.Mesh.from_inputs(mesh)
+    xt = torch.from_numpy(x[None, :].copy()).cuda()
+    if operator == "pmchwt":
+        y = P.pmchwt_matvec(M, k0, k1, rho, xt, precision=precision)
+    elif operator == "pmchwt_multi":
+        y = P.pmchwt_matvec_multi(M, k0, k1, rho, xt, precision=precision)
+    else:
+        y = P.muller_matvec(M, k0, k1, rho, xt, precision=precision)
+    torch.cuda.synchronize()
+    err = rel_blocks(y.cpu().numpy()[0], A @ x, N)
+    print(operator, precision, err)
+    for v in err.values():
+        assert v <= TOL[precision], err
+
+
 def test_matvec_smooth_input_fp32(P):
     # a converged-solution-like smooth input (low-order harmonics)
     mesh = icosphere(3)

@@ -977,7 +977,8 @@ int64_t dense_bytes(const bem_mesh *m, bool fp64) {
 }
 int64_t dense_assembly_scratch_bytes(const bem_mesh *m, bool fp64) {
     const int64_t c = fp64 ? sizeof(double2) : sizeof(float2);
-    return m->T * (int64_t)JT * 12 * c + 2 * m->N * (int64_t)sizeof(float2);
+    return m->T * (int64_t)JT * 12 * c + 2 * m->N * (int64_t)sizeof(float2) +
+           (2 * m->N + m->T) * (int64_t)sizeof(int32_t);   // vertex ranks, triangle order
 }
 
 std::unique_ptr<DenseOperator> dense_assemble(bem_mesh *m, const NearOperator &nf, double2 k0,

@@ -408,9 +408,11 @@ int solve_run(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dir
         if (o.path == 2) {   // autotuned choice, else dense when it fits with room to spare
             size_t free_b = 0, total_b = 0;
             BEM_HIP(hipMemGetInfo(&free_b, &total_b));
-            const int64_t need = f64 ? dense_bytes(m, true) + dense_assembly_scratch_bytes(m, true) +
-                                           (int64_t)(1ll << 30)
-                                     : dense_bytes(m) + (int64_t)(2ll << 30);
+            int64_t need = f64 ? dense_bytes(m, true) + dense_assembly_scratch_bytes(m, true) +
+                                     (int64_t)(1ll << 30)
+                               : dense_bytes(m) + (int64_t)(2ll << 30);
+            // Calderon on several objects: each object's own operator as well
+            if (o.formulation == BEM_FORM_CALDERON && m->nobj > 1) need += dense_bytes(m, f64) / m->nobj;
             const bool fits = need < (int64_t)free_b ||
                               !(f64 ? m->dense64_cache.empty() : m->dense_cache.empty());
             TuneEntry te;

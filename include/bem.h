@@ -216,7 +216,11 @@ typedef struct {
     int outer_steps;     /* refinement steps (1 for FP64) */
     int fp64_matvecs;
     int fp32_matvecs;
-    double rel_residual; /* ||b - P x|| / ||b||, P with the FP64 operator */
+    double rel_residual; /* ||b - P x|| / ||b||, P with the FP64 operator; FP32
+                            refinement with "solve.refine_update" = 1: an upper
+                            bound, the FP64 residual of an earlier iterate
+                            updated by FP32 products of the later corrections
+                            plus the bound on their error */
     double seconds;      /* wall time of the solve of this wave's lockstep group, from
                             its first preconditioning to convergence; the set-up shared
                             by all waves (near field, OSRC factors, assembled operator)
@@ -232,7 +236,9 @@ void bem_solve_opts_default(bem_solve_opts *opts);
  *     L M^{-1} B x = L M^{-1} f,   L = diag(L_DtN, L_NtD) per object,
  * with unrestarted GMRES from x_0 = 0 (Sec. 3.1) to ||b - P x|| <= tol ||b||.
  * precision BEM_FP32: iterative refinement, outer residual with the FP64
- * operator, inner GMRES on the operator with the FP32 pair kernel.
+ * operator (later ones updated with FP32 products of the corrections, see
+ * "solve.refine_update"), inner GMRES on the operator with the FP32 pair
+ * kernel.
  *   directions  host [n_waves][3];  solution  device [n_waves][2N]
  *   info        host [n_waves] or NULL
  * Returns BEM_W_NOT_CONVERGED (best iterate written) if maxiter is reached.
@@ -410,6 +416,15 @@ int bem_profile_read(const char *kernel, double *total_ms, int64_t *launches);
  *                         operator is applied with the MFMA product instead of
  *                         the multi-vector product, 8 vectors per pass
  *                         (default 24)
+ *   "solve.refine_update" FP32 refinement (precision BEM_FP32 in
+ *                         pmchwt_solve): 1 forms the first outer residual
+ *                         b - P64 x with the FP64 operator and updates the
+ *                         later ones as r - P32 d, the FP32 product of the
+ *                         small correction d, carrying the bound 1e-4 |P32 d|
+ *                         of that product's error into the reported residual
+ *                         (formed in FP64 again before the carried bound
+ *                         reaches tol / 10); 0 forms every outer residual with
+ *                         the FP64 operator (default 1)
  * Results of a solve depend on these (the summation order changes), within
  * the FP32 accuracy.  BEM_E_INVAL for an unknown key or value. */
 int bem_tune_set(const char *key, int64_t value);

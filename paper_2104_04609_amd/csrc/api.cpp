@@ -33,7 +33,15 @@ void prof_clear_locked() {
 
 void set_last_error(const std::string &msg) { g_last_error = msg; }
 
+namespace {
+thread_local bool t_no_timer = false;
+}
+
+NoTimerScope::NoTimerScope() : prev(t_no_timer) { t_no_timer = true; }
+NoTimerScope::~NoTimerScope() { t_no_timer = prev; }
+
 Timer::Timer(const char *kernel, hipStream_t stream) : name(kernel), s(stream) {
+    if (t_no_timer) return;
     std::lock_guard<std::mutex> g(g_prof_mu);
     if (!g_prof_on) return;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
@@ -357,6 +365,9 @@ int bem_tune_set(const char *key, int64_t value) {
     } else if (k == "dense.gemm_min_rhs") {
         if (value < 1 || value > 1 << 20) fail(BEM_E_INVAL, "dense.gemm_min_rhs out of range");
         t.dense_gemm_min_rhs = (int)value;
+    } else if (k == "solve.refine_update") {
+        if (value != 0 && value != 1) fail(BEM_E_INVAL, "solve.refine_update: 0 or 1");
+        t.solve_refine_update = (int)value;
     } else {
         fail(BEM_E_INVAL, "unknown tuning key " + k);
     }
@@ -374,6 +385,7 @@ int bem_tune_get(const char *key, int64_t *value) {
     else if (k == "farfield.symmetric") *value = t.farfield_symmetric;
     else if (k == "dense.skinny_min_rhs") *value = t.dense_skinny_min_rhs;
     else if (k == "dense.gemm_min_rhs") *value = t.dense_gemm_min_rhs;
+    else if (k == "solve.refine_update") *value = t.solve_refine_update;
     else fail(BEM_E_INVAL, "unknown tuning key " + k);
     return BEM_OK;
     BEM_API_END

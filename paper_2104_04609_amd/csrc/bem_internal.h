@@ -237,6 +237,7 @@ struct Tuning {
     std::atomic<int> farfield_symmetric{1};   // FP32 single vector: each separated pair once
     std::atomic<int> dense_gemm_min_rhs{24};  // MFMA product from this many right-hand sides
     std::atomic<int> dense_skinny_min_rhs{24}; // skinny MFMA product from this many (else multi-GEMV)
+    std::atomic<int> solve_refine_update{1};  // FP32 refinement: later residuals updated in FP32
 };
 Tuning &tuning();
 
@@ -327,11 +328,22 @@ void far_field_eval(bem_mesh *m, double2 k0, const double2 *x, const double *dir
 OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
                     const std::vector<double2> &keps_obj, hipStream_t s,
                     const std::vector<double2> *k_obj = nullptr);
+// the cached state of these parameters, or nullptr (nothing is created)
+OsrcState *osrc_find(bem_mesh *m, int np, double theta, double2 k,
+                     const std::vector<double2> &keps_obj);
+// Work memory of an apply of R right-hand sides: work [R][np + 2][n],
+// obuf [R][np + 3][n], wbuf [R][2][n] (complex128 each).  nullptr: the
+// state's own buffers, grown to R on demand.
+struct OsrcScratch {
+    double2 *work, *obuf, *wbuf;
+};
+// complex128 entries of OsrcScratch per right-hand side
+int64_t osrc_scratch_per_rhs(int np, int64_t n);
 // R right-hand sides, [R][2N] contiguous each
 void osrc_apply_strong(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y, int R,
-                       hipStream_t s);
+                       hipStream_t s, const OsrcScratch *scr = nullptr);
 void osrc_apply_from_weak(bem_mesh *m, OsrcState &st, const double2 *yw, double2 *z, int R,
-                          hipStream_t s);
+                          hipStream_t s, const OsrcScratch *scr = nullptr);
 void osrc_mass_solve(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y,
                      int nblocks, hipStream_t s);
 // symbolic analysis of the OSRC systems (once per mesh handle)
@@ -360,6 +372,14 @@ void mesh_trim(bem_mesh *m);
 // build m->parts / m->part_vidx if not yet built (several objects)
 void mesh_parts(bem_mesh *m);
 // profiling (api.cpp)
+// While one is alive on a thread, Timer records nothing (no HIP events are
+// created): for calls that must not allocate.
+struct NoTimerScope {
+    NoTimerScope();
+    ~NoTimerScope();
+    bool prev;
+};
+
 struct Timer {
     hipEvent_t a = nullptr, b = nullptr;
     const char *name = nullptr;

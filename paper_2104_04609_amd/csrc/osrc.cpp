@@ -188,11 +188,10 @@ int64_t osrc_state_bytes(bem_mesh *m, int np, int R) {
            (n + nf * (n + 2 * nnz + 2 * nd) + (int64_t)R * ((np + 2) + (np + 3) + 2) * n);
 }
 
-OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
-                    const std::vector<double2> &keps_obj, hipStream_t s,
-                    const std::vector<double2> *k_obj) {
-    if ((int)keps_obj.size() != m->nobj) fail(BEM_E_INVAL, "one k_eps per object expected");
-    if (k_obj && (int)k_obj->size() != m->nobj) fail(BEM_E_INVAL, "one k per object expected");
+// Cache key of a state; k_obj with equal entries collapses to k (set to
+// nullptr, k replaced by the common value).
+static OsrcKey osrc_key(int np, double theta, double2 &k, const std::vector<double2> &keps_obj,
+                 const std::vector<double2> *&k_obj) {
     OsrcKey key{np, theta, k.x, k.y, {}, {}};
     for (const double2 &ke : keps_obj) {
         key.keps.push_back(ke.x);
@@ -213,6 +212,25 @@ OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
             }
         }
     }
+    return key;
+}
+
+OsrcState *osrc_find(bem_mesh *m, int np, double theta, double2 k,
+                     const std::vector<double2> &keps_obj) {
+    if ((int)keps_obj.size() != m->nobj) fail(BEM_E_INVAL, "one k_eps per object expected");
+    const std::vector<double2> *k_obj = nullptr;
+    auto it = m->osrc_cache.find(osrc_key(np, theta, k, keps_obj, k_obj));
+    return it == m->osrc_cache.end() ? nullptr : it->second.get();
+}
+
+int64_t osrc_scratch_per_rhs(int np, int64_t n) { return ((np + 2) + (np + 3) + 2) * n; }
+
+OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
+                    const std::vector<double2> &keps_obj, hipStream_t s,
+                    const std::vector<double2> *k_obj) {
+    if ((int)keps_obj.size() != m->nobj) fail(BEM_E_INVAL, "one k_eps per object expected");
+    if (k_obj && (int)k_obj->size() != m->nobj) fail(BEM_E_INVAL, "one k per object expected");
+    const OsrcKey key = osrc_key(np, theta, k, keps_obj, k_obj);
     auto it = m->osrc_cache.find(key);
     if (it != m->osrc_cache.end()) return *it->second;
     OsrcSymbolicState &sy = symbolic(m);
@@ -317,17 +335,17 @@ OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
 }
 
 void osrc_apply_from_weak(bem_mesh *m, OsrcState &st, const double2 *yw, double2 *z, int R,
-                          hipStream_t s) {
+                          hipStream_t s, const OsrcScratch *scr) {
     OsrcSymbolicState &sy = *m->osrc_sym;
     const int n = sy.n, np = st.np;
-    st.ensure_batch(R);
+    if (!scr) st.ensure_batch(R);
     const LdlDev L = ldl_view(sy, st);
     const cdd ik = cdd(0, 1) * cdd(st.k.x, st.k.y);
     const double2 one = make_double2(1.0, 0.0);
     // right-hand side r: yw + r 2n in, z + r 2n out, obuf + r (np + 3) n,
     // work + r (np + 2) n
     const int64_t n2 = 2 * (int64_t)n, os = (int64_t)(np + 3) * n, ws = (int64_t)(np + 2) * n;
-    double2 *ob = st.obuf.p, *wk = st.work.p;
+    double2 *ob = scr ? scr->obuf : st.obuf.p, *wk = scr ? scr->work : st.work.p;
     double2 *u1 = ob + (size_t)np * n, *v = ob + (size_t)(np + 1) * n, *m2 = ob + (size_t)(np + 2) * n;
     Timer tm("osrc_apply", s);
     // stage 1: shifted solves and M^{-1} on y1 (DtN); (M - S/k_eps^2)^{-1} on y2 (NtD)
@@ -354,12 +372,12 @@ void osrc_apply_from_weak(bem_mesh *m, OsrcState &st, const double2 *yw, double2
 }
 
 void osrc_apply_strong(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y, int R,
-                       hipStream_t s) {
+                       hipStream_t s, const OsrcScratch *scr) {
     OsrcSymbolicState &sy = *m->osrc_sym;
-    st.ensure_batch(R);
-    launch_spmv_real(sy.n, 2 * R, sy.gptr_d.p, sy.gcol_d.p, sy.Mv_d.p, x, sy.n, st.wbuf.p, sy.n,
-                     s);
-    osrc_apply_from_weak(m, st, st.wbuf.p, y, R, s);
+    if (!scr) st.ensure_batch(R);
+    double2 *wb = scr ? scr->wbuf : st.wbuf.p;
+    launch_spmv_real(sy.n, 2 * R, sy.gptr_d.p, sy.gcol_d.p, sy.Mv_d.p, x, sy.n, wb, sy.n, s);
+    osrc_apply_from_weak(m, st, wb, y, R, s, scr);
 }
 
 void osrc_mass_solve(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y, int nblocks,

@@ -1,0 +1,145 @@
+"""Solves on the metric workload against the oracle: unit sphere as icosphere
+level 5 (10 242 vertices, 20 480 triangles), k_ext = 10, k_int = 15,
+rho = 1.5, plane wave along +z, OSRC with 4 Pade terms, theta = pi/3
+(Sec. 2.7, 3.1).
+
+The oracle's solution (dense complex128 assembly, SciPy LU for the OSRC
+systems, MGS GMRES to 1e-10) is stored in tests/golden/c2_solution.npz by
+tests/golden/make_c2_solution.py, which calls only the oracle.
+
+* FP64 GMRES, matrix-free (path 0) and assembled complex128 (path 1), to
+  1e-10: solution within 1e-8 of the oracle's, iterations within 2.
+* FP32 + refinement, matrix-free and assembled complex64, to 1e-6: the
+  reported residual is an upper bound of the FP64 one (formed here with the
+  oracle's OSRC and mass matrix around the GPU's FP64 operator, whose rows are
+  checked against the oracle's on 32 sampled rows of this very product), and
+  the solution is within 1e-4 of the oracle's.
+* Far field against the series solution: |e_GPU - e_oracle| <= 1e-3
+  (181 polar angles in the x-z plane).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from bem_inputs import icosphere, sample_rows
+
+pytestmark = pytest.mark.gpu
+
+K_EXT, K_INT, RHO = 10.0, 15.0, 1.5
+D = [[0.0, 0.0, 1.0]]
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2104_04609_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def c2():
+    mesh = icosphere(5)
+    assert mesh.n_vertices == 10242 and mesh.n_triangles == 20480
+    return mesh
+
+
+@pytest.fixture(scope="module")
+def handle(P, c2):
+    return P.Mesh.from_inputs(c2)
+
+
+@pytest.fixture(scope="module")
+def golden():
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "c2_solution.npz"))
+    assert float(g["k_ext"]) == K_EXT and float(g["k_int"]) == K_INT
+    assert float(g["rho"]) == RHO and np.array_equal(g["direction"], D[0])
+    return g
+
+
+@pytest.fixture(scope="module")
+def oracle_prec(c2):
+    """The oracle's L M^{-1} (strong-form OSRC at the interior wavenumber) and
+    its preconditioned right-hand side b = L M^{-1} f."""
+    from oracle.osrc import OSRC, damped_wavenumber, object_radius
+    from oracle.rhs import plane_wave_rhs
+    keps = damped_wavenumber(K_INT, 0.1 * object_radius(c2, 0))
+    op = OSRC(c2, K_INT, keps, 4, np.pi / 3)
+    N = c2.n_vertices
+
+    def prec(y):
+        return op.apply(np.concatenate([op.mass_solve(y[:N]), op.mass_solve(y[N:])]))
+
+    return prec, prec(plane_wave_rhs(c2, K_EXT, D[0]))
+
+
+def _residual(P, c2, handle, oracle_prec, sol):
+    """||b - L M^{-1} B x|| / ||b|| with the oracle's L and M^{-1} and the
+    GPU's FP64 B x, whose sampled rows are checked against the oracle's."""
+    from oracle.operators import pmchwt_matvec_rows
+    prec, b = oracle_prec
+    N = c2.n_vertices
+    y = P.pmchwt_matvec(handle, K_EXT, K_INT, RHO, sol, precision="fp64").cpu().numpy()
+    x = sol.cpu().numpy()
+    rows = sample_rows(N, 32, seed=3)
+    r1, r2 = pmchwt_matvec_rows(c2, K_EXT, K_INT, RHO, x, rows)
+    for got, ref in ((y[rows], r1), (y[N + rows], r2)):
+        assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
+    return np.linalg.norm(b - prec(y)) / np.linalg.norm(b)
+
+
+def _mie_error(P, handle, sol):
+    from oracle import mie
+    th = np.linspace(0.0, np.pi, 181)
+    dirs = np.stack([np.sin(th), 0 * th, np.cos(th)], 1)
+    Fm = mie.far_field(K_EXT, K_INT, RHO, th)
+    Fg = P.far_field(handle, K_EXT, sol, dirs)
+    return np.linalg.norm(Fg - Fm) / np.linalg.norm(Fm)
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_c2_fp64_solve_matches_oracle(P, c2, handle, golden, oracle_prec, path):
+    print(f"C2 FP64 solve path {path}", flush=True)
+    sol, info, rc = P.pmchwt_solve(handle, K_EXT, K_INT, RHO, D, 1e-10, precision="fp64",
+                                   path=path)
+    print(info[0], "oracle iterations", int(golden["iterations"]))
+    assert rc == 0 and info[0]["rel_residual"] <= 1e-10
+    x = sol.cpu().numpy()[0]
+    xo = golden["x"]
+    assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
+    assert abs(info[0]["iterations"] - int(golden["iterations"])) <= 2
+    res = _residual(P, c2, handle, oracle_prec, sol[0].contiguous())
+    print("oracle residual of the GPU solution", res)
+    assert res <= 3e-10
+    e = _mie_error(P, handle, sol[0].contiguous())
+    print("far-field error vs series", e, "oracle", float(golden["mie_error"]))
+    assert abs(e - float(golden["mie_error"])) <= 1e-3
+
+
+@pytest.mark.parametrize("update", [1, 0])
+@pytest.mark.parametrize("path", [0, 1])
+def test_c2_fp32_refinement_matches_oracle(P, c2, handle, golden, oracle_prec, path, update):
+    """FP32 + refinement to 1e-6; with update = 1 the later outer residuals
+    are updated with FP32 products (one FP64 operator application in all)."""
+    P.tune_set("solve.refine_update", update)
+    try:
+        print(f"C2 FP32+refine path {path} update {update}", flush=True)
+        sol, info, rc = P.pmchwt_solve(handle, K_EXT, K_INT, RHO, D, 1e-6, precision="fp32",
+                                       path=path)
+    finally:
+        P.tune_set("solve.refine_update", 1)
+    print(info[0])
+    assert rc == 0 and info[0]["rel_residual"] <= 1e-6
+    if update:
+        assert info[0]["fp64_matvecs"] == 1
+    res = _residual(P, c2, handle, oracle_prec, sol[0].contiguous())
+    print("oracle residual of the GPU solution", res, "reported", info[0]["rel_residual"])
+    # the GPU's and the oracle's OSRC and mass solves differ by rounding
+    assert res <= info[0]["rel_residual"] + 1e-9
+    x = sol.cpu().numpy()[0]
+    xo = golden["x"]
+    assert np.linalg.norm(x - xo) <= 1e-4 * np.linalg.norm(xo)
+    e = _mie_error(P, handle, sol[0].contiguous())
+    print("far-field error vs series", e, "oracle", float(golden["mie_error"]))
+    assert abs(e - float(golden["mie_error"])) <= 1e-3

@@ -345,6 +345,30 @@ def test_matvec_multi_rhs_full_size_sampled_rows(P, multi_max):
         assert e1 <= TOL["fp32"] and e2 <= TOL["fp32"]
 
 
+def test_dense_mfma_gemm_full_size_sampled_rows(P, dense_paths):
+    """The batching workload's product: icosphere L5, k_ext = 16, k_int = 24,
+    rho = 1.5, the assembled complex64 operator times a 64-column block on
+    MFMA; 40 seed-sampled rows of each block row of three columns against the
+    oracle's matrix-free rows (<= 1e-5)."""
+    import torch
+    from oracle.operators import pmchwt_matvec_rows
+    dense_paths("dense.gemm_min_rhs", 24)
+    mesh = icosphere(5)
+    N = mesh.n_vertices
+    X = complex_normal((64, 2 * N), seed=2104)
+    rows = sample_rows(N, 40, seed=1)
+    M = P.Mesh.from_inputs(mesh)
+    print("C4 MFMA product, 64 columns", flush=True)
+    Y = P.pmchwt_matvec(M, 16.0, 24.0, 1.5, torch.from_numpy(X).cuda(),
+                        precision="fp32_dense").cpu().numpy()
+    for r in (0, 31, 63):
+        r1, r2 = pmchwt_matvec_rows(mesh, 16.0, 24.0, 1.5, X[r], rows)
+        e1 = np.linalg.norm(Y[r][rows] - r1) / np.linalg.norm(r1)
+        e2 = np.linalg.norm(Y[r][N + rows] - r2) / np.linalg.norm(r2)
+        print(r, e1, e2)
+        assert e1 <= TOL["fp32"] and e2 <= TOL["fp32"]
+
+
 @pytest.mark.parametrize("block", [64, 128])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_matvec_workgroup_sizes(P, block, precision):

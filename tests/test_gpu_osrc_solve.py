@@ -186,6 +186,24 @@ def test_solve_not_converged_returns_best_iterate(P):
     assert np.isfinite(sol.cpu().numpy()).all()
 
 
+@pytest.mark.parametrize("precision,path", [("fp64", 0), ("fp64", 1), ("fp32", 0)])
+def test_solve_reports_nan(P, precision, path):
+    """A density ratio whose reciprocal overflows (rho = 1e-320 > 0 passes the
+    argument checks, 1/rho = inf): the operator holds Inf, the first Arnoldi
+    step meets NaN, and the solve returns BEM_E_NAN instead of iterating."""
+    mesh = icosphere(1)
+    M = P.Mesh.from_inputs(mesh)
+    assert 1.0 / 1e-320 == float("inf")
+    with pytest.raises(P.BemError) as e:
+        P.pmchwt_solve(M, 2.0, 3.0, 1e-320, [[0.0, 0.0, 1.0]], 1e-8, precision=precision,
+                       path=path)
+    assert e.value.code == -5, e.value
+    # the handle stays usable
+    sol, info, rc = P.pmchwt_solve(M, 2.0, 3.0, 1.5, [[0.0, 0.0, 1.0]], 1e-8,
+                                   precision=precision, path=path)
+    assert rc == 0 and info[0]["rel_residual"] <= 1e-8
+
+
 def test_solve_multiple_waves(P):
     """FP64: waves solved in one lockstep group (pair kernel shared by two
     vectors, summed in another order) against each wave alone, both to 1e-9;

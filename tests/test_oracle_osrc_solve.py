@@ -14,14 +14,14 @@ import numpy as np
 import pytest
 import scipy.linalg as sla
 
-from bem_inputs import icosphere
+from bem_inputs import ellipsoid, icosphere, two_spheres
 from oracle import mie
 from oracle.gmres import gmres
-from oracle.osrc import (OSRC, damped_wavenumber, mass_matrix, pade_coefficients,
-                         pade_eval, pade_unrotated, stiffness_matrix,
+from oracle.osrc import (OSRC, damped_wavenumber, mass_matrix, object_radius,
+                         pade_coefficients, pade_eval, pade_unrotated, stiffness_matrix,
                          triangle_geometry)
 from oracle.rhs import far_field
-from oracle.solve import PreconditionedSystem
+from oracle.solve import PreconditionedSystem, osrc_keps_per_vertex
 
 
 def test_pade_theta_zero_reduces_to_unrotated():
@@ -52,6 +52,40 @@ def test_damped_wavenumber_matches_alternative_algebra():
         R = 0.1
         alt = k + 0.4j * k ** (1 / 3) * R ** (-2 / 3)
         assert abs(damped_wavenumber(k, R) - alt) < 1e-12 * abs(k)
+
+
+def test_object_radius_closed_forms():
+    """R of k_eps (Sec. 2.6, 3.1) is read as the circumradius of each object
+    about its own vertex centroid: a sphere of radius a gives a wherever it
+    sits (an origin-based or diameter-based reading gives 8.6 or 5 here), two
+    unit spheres give 1 each (one radius for both objects would be 2.5), and
+    the (1, 0.6, 0.4) ellipsoid gives its largest semi-axis, since subdivision
+    places vertices at (+-1, 0, 0)."""
+    assert abs(object_radius(icosphere(3), 0) - 1.0) < 1e-12
+    moved = icosphere(2, radius=2.5, centre=(3.0, -2.0, 5.0))
+    assert abs(object_radius(moved, 0) - 2.5) < 1e-12
+    two = two_spheres(2, offset=1.5)
+    for o in (0, 1):
+        assert abs(object_radius(two, o) - 1.0) < 1e-12
+    assert abs(object_radius(ellipsoid(icosphere(3)), 0) - 1.0) < 1e-12
+
+
+def test_keps_per_vertex_closed_form():
+    """Each object's vertices carry k_eps = k (1 + 0.4 i (k R)^(-2/3)) with its
+    own k and R = 0.1 (one tenth of the unit radius, Sec. 3.1): k = 10 gives
+    10 + 4i exactly; k = 30 + 1.5i the principal-branch value."""
+    two = two_spheres(2, offset=1.5)
+    k = [10.0, 30.0 + 1.5j]
+    ke = osrc_keps_per_vertex(two, k)
+    nv = two.n_vertices // 2
+    k1 = 30.0 + 1.5j
+    z = (k1 * 0.1) ** (-2.0 / 3.0)
+    z_ref = abs(k1 * 0.1) ** (-2.0 / 3.0) * np.exp(-2.0j / 3.0 * np.angle(k1 * 0.1))
+    assert abs(z - z_ref) < 1e-14
+    assert np.allclose(ke[:nv], 10.0 + 4.0j, rtol=0, atol=1e-12)
+    assert np.allclose(ke[nv:], k1 * (1 + 0.4j * z_ref), rtol=0, atol=1e-12)
+    # an explicit R overrides the radius
+    assert np.allclose(osrc_keps_per_vertex(two, 10.0, R=1.0), 10.0 * (1 + 0.4j * 10.0 ** (-2 / 3)))
 
 
 def test_mass_and_stiffness_closed_forms():

@@ -157,6 +157,29 @@ int osrc_apply(const bem_mesh *mesh, int pade_terms, double theta,
                int n_rhs, void *hip_stream);
 
 /*
+ * osrc_apply without device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same operation, arguments, layouts and results as osrc_apply.
+ *   - The OSRC factors for (pade_terms, theta, k, k_eps) must already be
+ *     resident on the mesh handle (an earlier osrc_apply, or pmchwt_solve
+ *     with those values, created them); otherwise BEM_E_INVAL and nothing is
+ *     done.
+ *   - The work vectors of the sweeps live in a library-owned device array of
+ *     BEM_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends:
+ *     min(n_rhs, 16) * (2 pade_terms + 7) * n_vertices * 16 bytes must fit
+ *     (BEM_E_INVAL otherwise), e.g. 16 vectors of 10 242 vertices with
+ *     4 Pade terms.  Nothing in it needs to start at zero.
+ *   - Every call on one GPU uses that GPU's array: calls that overlap in time
+ *     on one GPU (other streams, other threads) race; the caller serialises
+ *     them.
+ *   - No hipMalloc, hipFree or HIP event is made (profiling records nothing).
+ */
+#define BEM_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int osrc_apply_noalloc(const bem_mesh *mesh, int pade_terms, double theta,
+                       bem_c64 k, bem_c64 k_eps, const bem_c64 *x, bem_c64 *y,
+                       int n_rhs, void *hip_stream);
+
+/*
  * Weak right-hand side [f_D; f_N] of the PMCHWT system for unit-amplitude
  * plane waves u_inc = exp(i k_ext d.x) (Sec. 2.1, Sec. 2.7):
  * f_D,i = int u_inc phi_i, f_N,i = int i k_ext (d.n) u_inc phi_i, 6-point rule.

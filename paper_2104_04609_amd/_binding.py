@@ -109,6 +109,8 @@ lib.muller_matvec.argtypes = [_vp, c64, c64, ctypes.c_double, _vp, _vp,
                               ctypes.c_int, ctypes.c_int, _vp]
 lib.osrc_apply.argtypes = [_vp, ctypes.c_int, ctypes.c_double, c64, c64, _vp, _vp,
                            ctypes.c_int, _vp]
+lib.osrc_apply_noalloc.argtypes = [_vp, ctypes.c_int, ctypes.c_double, c64, c64, _vp, _vp,
+                                   ctypes.c_int, _vp]
 lib.pmchwt_rhs.argtypes = [_vp, c64, _vp, ctypes.c_int, _vp, _vp]
 lib.bem_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
 lib.bem_solve_opts_default.restype = None
@@ -287,6 +289,20 @@ def osrc_apply(mesh: Mesh, pade_terms: int, theta: float, k, k_eps, x, y=None,
     _dev_c128(y, n2, "y")
     _check(lib.osrc_apply(mesh.handle, int(pade_terms), float(theta), _c(k), _c(k_eps),
                           _vp(x.data_ptr()), _vp(y.data_ptr()), n_rhs, _stream(stream)))
+    return y
+
+
+def osrc_apply_noalloc(mesh: Mesh, pade_terms: int, theta: float, k, k_eps, x, y,
+                       stream=None):
+    """osrc_apply into a caller-allocated y, without device allocation in the
+    library (the factors must be resident: call osrc_apply once first)."""
+    n2 = 2 * mesh.n_vertices
+    n_rhs = _dev_c128(x, n2, "x")
+    if _dev_c128(y, n2, "y") != n_rhs:
+        raise ValueError("x and y hold different numbers of vectors")
+    _check(lib.osrc_apply_noalloc(mesh.handle, int(pade_terms), float(theta), _c(k),
+                                  _c(k_eps), _vp(x.data_ptr()), _vp(y.data_ptr()), n_rhs,
+                                  _stream(stream)))
     return y
 
 

@@ -166,9 +166,11 @@ int osrc_apply(const bem_mesh *mesh, int pade_terms, double theta,
  *     done.
  *   - The work vectors of the sweeps live in a library-owned device array of
  *     BEM_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends:
- *     min(n_rhs, 16) * (2 pade_terms + 7) * n_vertices * 16 bytes must fit
- *     (BEM_E_INVAL otherwise), e.g. 16 vectors of 10 242 vertices with
- *     4 Pade terms.  Nothing in it needs to start at zero.
+ *     min(n_rhs, 16) * ((pade_terms + 2) (2 n_vertices + P) +
+ *     (pade_terms + 5) n_vertices) * 16 bytes must fit (BEM_E_INVAL
+ *     otherwise), P = 0 unless the two-part block solve is on ("osrc.split":
+ *     then the partial sums of its top rows), e.g. 8 vectors of 10 242
+ *     vertices with 4 Pade terms.  Nothing in it needs to start at zero.
  *   - Every call on one GPU uses that GPU's array: calls that overlap in time
  *     on one GPU (other streams, other threads) race; the caller serialises
  *     them.
@@ -448,6 +450,19 @@ int bem_profile_read(const char *kernel, double *total_ms, int64_t *launches);
  *                         (formed in FP64 again before the carried bound
  *                         reaches tol / 10); 0 forms every outer residual with
  *                         the FP64 operator (default 1)
+ *   "osrc.split"          OSRC block solves (keys read when a mesh handle
+ *                         first builds its OSRC state): 2 solves the bottom
+ *                         subtrees of the nested dissection in one workgroup
+ *                         each (rows in LDS) and the top separators after
+ *                         them (3 launches per solve when the top is small);
+ *                         0 one launch per dissection level (two for the
+ *                         levels of few, large blocks); 1 the two-part solve
+ *                         above 16 384 vertices, levels below (default 1)
+ *   "osrc.sub_rows"       largest bottom subtree in rows, 64..8192, 0 for
+ *                         4096 or the device's LDS limit (default 0)
+ *   "osrc.top_single_work" top part in one workgroup when its entries (L and
+ *                         dense block inverses) are at most this many, else
+ *                         level by level (default 300000)
  * Results of a solve depend on these (the summation order changes), within
  * the FP32 accuracy.  BEM_E_INVAL for an unknown key or value. */
 int bem_tune_set(const char *key, int64_t value);

@@ -368,6 +368,15 @@ int bem_tune_set(const char *key, int64_t value) {
     } else if (k == "solve.refine_update") {
         if (value != 0 && value != 1) fail(BEM_E_INVAL, "solve.refine_update: 0 or 1");
         t.solve_refine_update = (int)value;
+    } else if (k == "osrc.split") {
+        if (value < 0 || value > 2) fail(BEM_E_INVAL, "osrc.split: 0, 1 or 2");
+        t.osrc_split = (int)value;
+    } else if (k == "osrc.sub_rows") {
+        if (value != 0 && (value < 64 || value > 8192)) fail(BEM_E_INVAL, "osrc.sub_rows: 0 or 64..8192");
+        t.osrc_sub_rows = (int)value;
+    } else if (k == "osrc.top_single_work") {
+        if (value < 0 || value > (int64_t)1 << 30) fail(BEM_E_INVAL, "osrc.top_single_work out of range");
+        t.osrc_top_single_work = (int)value;
     } else {
         fail(BEM_E_INVAL, "unknown tuning key " + k);
     }
@@ -386,6 +395,9 @@ int bem_tune_get(const char *key, int64_t *value) {
     else if (k == "dense.skinny_min_rhs") *value = t.dense_skinny_min_rhs;
     else if (k == "dense.gemm_min_rhs") *value = t.dense_gemm_min_rhs;
     else if (k == "solve.refine_update") *value = t.solve_refine_update;
+    else if (k == "osrc.split") *value = t.osrc_split;
+    else if (k == "osrc.sub_rows") *value = t.osrc_sub_rows;
+    else if (k == "osrc.top_single_work") *value = t.osrc_top_single_work;
     else fail(BEM_E_INVAL, "unknown tuning key " + k);
     return BEM_OK;
     BEM_API_END

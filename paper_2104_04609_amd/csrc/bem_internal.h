@@ -238,6 +238,10 @@ struct Tuning {
     std::atomic<int> dense_gemm_min_rhs{24};  // MFMA product from this many right-hand sides
     std::atomic<int> dense_skinny_min_rhs{24}; // skinny MFMA product from this many (else multi-GEMV)
     std::atomic<int> solve_refine_update{1};  // FP32 refinement: later residuals updated in FP32
+    // OSRC block solves (read when a mesh's OSRC symbolic state is built)
+    std::atomic<int> osrc_split{1};           // 0 levels, 1 automatic, 2 two-part when it fits
+    std::atomic<int> osrc_sub_rows{0};        // largest bottom subtree (rows); 0: 4096 or the LDS limit
+    std::atomic<int> osrc_top_single_work{300000};   // top part in one workgroup up to this work
 };
 Tuning &tuning();
 
@@ -337,8 +341,11 @@ OsrcState *osrc_find(bem_mesh *m, int np, double theta, double2 k,
 struct OsrcScratch {
     double2 *work, *obuf, *wbuf;
 };
-// complex128 entries of OsrcScratch per right-hand side
-int64_t osrc_scratch_per_rhs(int np, int64_t n);
+// complex128 entries of OsrcScratch per right-hand side (the mesh's OSRC
+// symbolic state must exist)
+int64_t osrc_scratch_per_rhs(const bem_mesh *m, int np);
+// work entries of one system of the solves (n + partial sums); state must exist
+int64_t osrc_work_len(const bem_mesh *m);
 // R right-hand sides, [R][2N] contiguous each
 void osrc_apply_strong(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y, int R,
                        hipStream_t s, const OsrcScratch *scr = nullptr);

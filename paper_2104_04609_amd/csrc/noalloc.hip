@@ -64,17 +64,19 @@ extern "C" int osrc_apply_noalloc(const bem_mesh *mesh, int pade_terms, double t
                                    "call osrc_apply (or pmchwt_solve) with them once first");
         const int64_t n = m->N, n2 = 2 * n;
         const int batch = std::min(n_rhs, 16);   // right-hand sides per pass, as osrc_apply
-        const int64_t per = bem::osrc_scratch_per_rhs(pade_terms, n);
+        const int64_t per = bem::osrc_scratch_per_rhs(m, pade_terms);
         const int64_t cap = (int64_t)(NOALLOC_SCRATCH_BYTES / sizeof(double2));
         if ((int64_t)batch * per > cap)
             bem::fail(BEM_E_INVAL,
-                      "min(n_rhs, 16) * (2 pade_terms + 7) * n_vertices * 16 bytes = " +
+                      "min(n_rhs, 16) * ((pade_terms + 2) (2 n_vertices + P) + "
+                      "(pade_terms + 5) n_vertices) * 16 bytes = " +
                           std::to_string((int64_t)batch * per * 16) +
                           " exceeds the no-allocation scratch of " +
                           std::to_string(NOALLOC_SCRATCH_BYTES) + " bytes");
         double2 *base = scratch_ptr();
-        const bem::OsrcScratch scr{base, base + (int64_t)batch * (pade_terms + 2) * n,
-                                   base + (int64_t)batch * (2 * pade_terms + 5) * n};
+        const int64_t wl = bem::osrc_work_len(m);
+        double2 *obuf = base + (int64_t)batch * (pade_terms + 2) * wl;
+        const bem::OsrcScratch scr{base, obuf, obuf + (int64_t)batch * (pade_terms + 3) * n};
         const bem::NoTimerScope no_events;
         hipStream_t s = (hipStream_t)hip_stream;
         for (int r0 = 0; r0 < n_rhs; r0 += batch)

@@ -50,7 +50,7 @@ int64_t OsrcState::bytes() const {
 void OsrcState::ensure_batch(int R) {
     if (R <= batch) return;
     const size_t n = cvert.n;
-    work.alloc((size_t)R * (np + 2) * n);
+    work.alloc((size_t)R * (np + 2) * wlen);
     obuf.alloc((size_t)R * (np + 3) * n);
     wbuf.alloc((size_t)R * 2 * n);
     batch = R;
@@ -144,8 +144,83 @@ OsrcSymbolicState &symbolic(bem_mesh *m) {
     st->frange_d.upload(fr);
     st->brange_d.upload(br);
     st->doff_d.upload(doff);
+    st->blk_d.upload(S.blk);
+    // two-part schedule: bottom subtrees in LDS, the top part in one
+    // workgroup when its own work is small, else level by level
+    st->wlen = 2 * (int64_t)n;   // y, z
+    const Tuning &tn = tuning();
+    // automatic choice (measured on the 10 242- and 40 962-vertex meshes): one
+    // launch per level up to 16 384 vertices, the two-part solve above
+    const int split_mode = tn.osrc_split.load();
+    if (split_mode == 2 || (split_mode == 1 && n > 16384)) {
+        const int phase_rows = 4 * 1024;   // rows a 1024-thread workgroup keeps in registers
+        int sub_rows = std::min(ldl_split_max_sub_rows(), 4096);
+        if (tn.osrc_sub_rows.load() > 0)
+            sub_rows = std::min(ldl_split_max_sub_rows(), tn.osrc_sub_rows.load());
+        LdlSplit P = ldl_split_plan(S, sub_rows, 8192, phase_rows);
+        if (P.ok) {
+            int64_t top_dense = 0;
+            for (int b = 0; b < nb; b++)
+                if (S.bheight[b] >= P.H) {
+                    const int64_t w = S.bstart[b + 1] - S.bstart[b];
+                    top_dense += w * w;
+                }
+            const int64_t top_work = (int64_t)P.tf_pos.size() + (int64_t)P.tb_pos.size() + top_dense;
+            st->top_single =
+                P.ntop <= ldl_split_max_sub_rows() && top_work <= tn.osrc_top_single_work.load() ? 1
+                                                                                                : 0;
+            st->sp_sub_r0.upload(P.sub_r0);
+            st->sp_sub_r1.upload(P.sub_r1);
+            st->sp_sub_hptr.upload(P.sub_hptr);
+            st->sp_srow.upload(P.srow);
+            st->sp_top_row.upload(P.top_row);
+            st->sp_top_hptr.upload(P.top_hptr);
+            st->sp_tlist.upload(P.tlist);
+            st->sp_part_b.upload(P.part_b);
+            st->sp_part_e.upload(P.part_e);
+            st->sp_tf_ptr.upload(P.tf_ptr);
+            st->sp_tf_pos.upload(P.tf_pos);
+            st->sp_tf_col.upload(P.tf_col);
+            st->sp_tb_ptr.upload(P.tb_ptr);
+            st->sp_tb_pos.upload(P.tb_pos);
+            st->sp_tb_row.upload(P.tb_row);
+            st->sp_bsplit.upload(P.bsplit);
+            st->wlen = 2 * (int64_t)n + (int64_t)P.nsub * P.ntop;
+            st->split = std::move(P);
+        }
+    }
     m->osrc_sym = std::move(st);
     return *m->osrc_sym;
+}
+
+LdlSplitDev split_view(const OsrcSymbolicState &sy) {
+    LdlSplitDev P{};
+    const LdlSplit &q = sy.split;
+    P.ok = q.ok ? 1 : 0;
+    if (!q.ok) return P;
+    P.H = q.H;
+    P.nsub = q.nsub;
+    P.ntop = q.ntop;
+    P.nht = q.ntop > 0 ? (int)q.top_hptr.size() - 1 : 0;
+    P.top_single = sy.top_single;
+    P.sub_rows = q.max_sub_rows;
+    P.sub_r0 = sy.sp_sub_r0.p;
+    P.sub_r1 = sy.sp_sub_r1.p;
+    P.sub_hptr = sy.sp_sub_hptr.p;
+    P.srow = sy.sp_srow.p;
+    P.top_row = sy.sp_top_row.p;
+    P.top_hptr = sy.sp_top_hptr.p;
+    P.tlist = sy.sp_tlist.p;
+    P.part_b = sy.sp_part_b.p;
+    P.part_e = sy.sp_part_e.p;
+    P.tf_ptr = sy.sp_tf_ptr.p;
+    P.tf_pos = sy.sp_tf_pos.p;
+    P.tf_col = sy.sp_tf_col.p;
+    P.tb_ptr = sy.sp_tb_ptr.p;
+    P.tb_pos = sy.sp_tb_pos.p;
+    P.tb_row = sy.sp_tb_row.p;
+    P.bsplit = sy.sp_bsplit.p;
+    return P;
 }
 
 LdlDev ldl_view(const OsrcSymbolicState &sy, const OsrcState &st) {
@@ -172,6 +247,8 @@ LdlDev ldl_view(const OsrcSymbolicState &sy, const OsrcState &st) {
     L.Lcsc = st.Lcsc.p;
     L.invL = st.invL.p;
     L.invLT = st.invLT.p;
+    L.blk = sy.blk_d.p;
+    L.wlen = sy.wlen;
     return L;
 }
 
@@ -185,7 +262,8 @@ int64_t osrc_state_bytes(bem_mesh *m, int np, int R) {
     // cvert, Dinv, L (CSR + CSC), dense block inverses (+ transposes); per
     // right-hand side work, outputs and weak vectors; complex128 each
     return (int64_t)sizeof(double2) *
-           (n + nf * (n + 2 * nnz + 2 * nd) + (int64_t)R * ((np + 2) + (np + 3) + 2) * n);
+           (n + nf * (n + 2 * nnz + 2 * nd) +
+            (int64_t)R * ((np + 2) * sy.wlen + ((np + 3) + 2) * n));
 }
 
 // Cache key of a state; k_obj with equal entries collapses to k (set to
@@ -223,7 +301,12 @@ OsrcState *osrc_find(bem_mesh *m, int np, double theta, double2 k,
     return it == m->osrc_cache.end() ? nullptr : it->second.get();
 }
 
-int64_t osrc_scratch_per_rhs(int np, int64_t n) { return ((np + 2) + (np + 3) + 2) * n; }
+int64_t osrc_work_len(const bem_mesh *m) { return m->osrc_sym->wlen; }
+
+int64_t osrc_scratch_per_rhs(const bem_mesh *m, int np) {
+    const int64_t n = m->osrc_sym->n, wlen = m->osrc_sym->wlen;
+    return (np + 2) * wlen + ((np + 3) + 2) * n;
+}
 
 OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
                     const std::vector<double2> &keps_obj, hipStream_t s,
@@ -237,6 +320,7 @@ OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
     const int n = sy.n;
     auto st = std::unique_ptr<OsrcState, OsrcDeleter>(new OsrcState());
     st->np = np;
+    st->wlen = sy.wlen;
     st->k = k;
     // Pade coefficients
     const cdd e = std::exp(cdd(0, -theta));
@@ -344,29 +428,31 @@ void osrc_apply_from_weak(bem_mesh *m, OsrcState &st, const double2 *yw, double2
     const double2 one = make_double2(1.0, 0.0);
     // right-hand side r: yw + r 2n in, z + r 2n out, obuf + r (np + 3) n,
     // work + r (np + 2) n
-    const int64_t n2 = 2 * (int64_t)n, os = (int64_t)(np + 3) * n, ws = (int64_t)(np + 2) * n;
+    const int64_t wl = sy.wlen;
+    const int64_t n2 = 2 * (int64_t)n, os = (int64_t)(np + 3) * n, ws = (int64_t)(np + 2) * wl;
     double2 *ob = scr ? scr->obuf : st.obuf.p, *wk = scr ? scr->work : st.work.p;
+    const LdlSplitDev P = split_view(sy);
     double2 *u1 = ob + (size_t)np * n, *v = ob + (size_t)(np + 1) * n, *m2 = ob + (size_t)(np + 2) * n;
     Timer tm("osrc_apply", s);
     // stage 1: shifted solves and M^{-1} on y1 (DtN); (M - S/k_eps^2)^{-1} on y2 (NtD)
     TaskList ta{};
-    for (int j = 0; j < np; j++) ta.t[j] = SolveTask{j, yw, ob + (size_t)j * n, one, wk + (size_t)j * n};
-    ta.t[np] = SolveTask{np + 1, yw, u1, one, wk + (size_t)np * n};
-    ta.t[np + 1] = SolveTask{np, yw + n, v, one, wk + (size_t)(np + 1) * n};
+    for (int j = 0; j < np; j++) ta.t[j] = SolveTask{j, yw, ob + (size_t)j * n, one, wk + j * wl};
+    ta.t[np] = SolveTask{np + 1, yw, u1, one, wk + np * wl};
+    ta.t[np + 1] = SolveTask{np, yw + n, v, one, wk + (np + 1) * wl};
     ta.in_stride = n2;
     ta.out_stride = os;
     ta.work_stride = ws;
-    launch_ldl_solve(L, ta, np + 2, R, s);
+    launch_ldl_solve(L, P, ta, np + 2, R, s);
     // z1 = ik (C_0' M^{-1} y1 - sum_j (A_j/B_j) s_j);  m2 = M v
     launch_pade_sum(n, st.pf, d2(ik), st.ikv.p, u1, os, ob, n, os, z, n2, R, s);
     launch_spmv_real(n, R, sy.gptr_d.p, sy.gcol_d.p, sy.Mv_d.p, v, os, m2, os, s);
     // stage 2: shifted solves on M v (NtD)
     TaskList tb{};
-    for (int j = 0; j < np; j++) tb.t[j] = SolveTask{j, m2, ob + (size_t)j * n, one, wk + (size_t)j * n};
+    for (int j = 0; j < np; j++) tb.t[j] = SolveTask{j, m2, ob + (size_t)j * n, one, wk + j * wl};
     tb.in_stride = os;
     tb.out_stride = os;
     tb.work_stride = ws;
-    launch_ldl_solve(L, tb, np, R, s);
+    launch_ldl_solve(L, P, tb, np, R, s);
     // z2 = (1/ik) (C_0' v - sum_j (A_j/B_j) s'_j)
     launch_pade_sum(n, st.pf, d2(1.0 / ik), st.iikv.p, v, os, ob, n, os, z + n, n2, R, s);
 }
@@ -391,8 +477,8 @@ void osrc_mass_solve(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y, i
         int cnt = std::min(nb, nblocks - b0);
         for (int b = 0; b < cnt; b++)
             t.t[b] = SolveTask{st.np + 1, x + (size_t)(b0 + b) * n, y + (size_t)(b0 + b) * n,
-                               make_double2(1.0, 0.0), st.work.p + (size_t)b * n};
-        launch_ldl_solve(L, t, cnt, 1, s);
+                               make_double2(1.0, 0.0), st.work.p + (size_t)b * sy.wlen};
+        launch_ldl_solve(L, split_view(sy), t, cnt, 1, s);
     }
 }
 

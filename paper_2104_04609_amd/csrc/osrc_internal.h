@@ -41,6 +41,23 @@ struct LdlDev {
     const double2 *Lcsc;      // [factors][nnz]
     const double2 *invL;      // [factors][ndense]
     const double2 *invLT;     // [factors][ndense]
+    const int32_t *blk;       // row -> dissection block
+    int64_t wlen;             // work length per system: n + partial sums of the split solve
+};
+
+// Device view of the two-part schedule (LdlSplit): bottom subtrees solved
+// in LDS by one workgroup each, the top part by one workgroup (top_single)
+// or level by level.
+struct LdlSplitDev {
+    int ok;                   // 0: level-by-level solve only
+    int H, nsub, ntop, nht;   // cut height, subtrees, top rows, top heights
+    int top_single;           // 1: the top part in one workgroup
+    int sub_rows;             // largest subtree (rows)
+    const int32_t *sub_r0, *sub_r1, *sub_hptr, *srow;
+    const int32_t *top_row, *top_hptr, *tlist;
+    const int32_t *part_b, *part_e;
+    const int32_t *tf_ptr, *tf_pos, *tf_col, *tb_ptr, *tb_pos, *tb_row;
+    const int32_t *bsplit;
 };
 
 // One system solve: out = scale * A_factor^{-1} in (vectors of length n).
@@ -62,13 +79,22 @@ struct OsrcSymbolicState {
     DevBuf<int32_t> gptr_d, gcol_d, perm_d, Rj_d, Li_d, bstart_d, lbptr_d, lblk_d, lptr_d, lrow_d;
     DevBuf<int2> frange_d, brange_d;
     DevBuf<int64_t> doff_d;
+    DevBuf<int32_t> blk_d;
     std::vector<int32_t> lbcount, lrcount;   // blocks and rows per level (host)
+    // two-part schedule of the block solves (empty if not ok)
+    LdlSplit split;
+    DevBuf<int32_t> sp_sub_r0, sp_sub_r1, sp_sub_hptr, sp_srow, sp_top_row, sp_top_hptr,
+        sp_tlist, sp_part_b, sp_part_e, sp_tf_ptr, sp_tf_pos, sp_tf_col, sp_tb_ptr, sp_tb_pos,
+        sp_tb_row, sp_bsplit;
+    int top_single = 0;
+    int64_t wlen = 0;   // work length per system (n + partial sums)
     DevBuf<double> Mv_d, Sv_d;
     int64_t bytes() const;
 };
 
 struct OsrcState {
     int np = 0;
+    int64_t wlen = 0;            // work length per system (OsrcSymbolicState::wlen)
     double2 k{0, 0};
     PadeCoef pc{};               // C_0, A_j of the Pade approximant
     PadeCoef pf{};               // partial fractions: C_0', A_j / B_j
@@ -95,7 +121,10 @@ struct TaskList {
     int64_t in_stride, out_stride, work_stride;
 };
 
-void launch_ldl_solve(const LdlDev &L, TaskList tasks, int ntasks, int nrhs, hipStream_t s);
+void launch_ldl_solve(const LdlDev &L, const LdlSplitDev &P, TaskList tasks, int ntasks,
+                      int nrhs, hipStream_t s);
+// rows of LDS a bottom-subtree workgroup may hold on this device
+int ldl_split_max_sub_rows();
 // out_r = alpha (C0 u_r - sum_j A_j s_{r,j})   (elementwise, r < nrhs):
 // u_r = u + r ustride, s_{r,j} = sv + r vstride + j sstride, out_r = out + r ostride
 void launch_pade_sum(int n, const PadeCoef &pc, double2 alpha, const double2 *alpha_v,

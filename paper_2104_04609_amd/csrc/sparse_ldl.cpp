@@ -15,9 +15,11 @@ int dissect(std::vector<int32_t> &vs, const std::vector<int32_t> &ptr,
             const std::vector<int32_t> &col, const std::vector<double> &xyz,
             std::vector<int32_t> &side, NdOrder &nd, int leaf) {
     if (vs.empty()) return -1;
+    const int first = (int)nd.bheight.size();   // blocks of this call start here
     auto emit = [&](const std::vector<int32_t> &blk, int h) {
         nd.bstart.push_back((int32_t)nd.order.size());
         nd.bheight.push_back(h);
+        nd.bfirst.push_back(first);
         nd.order.insert(nd.order.end(), blk.begin(), blk.end());
     };
     if ((int)vs.size() <= leaf) {
@@ -189,6 +191,7 @@ LdlSymbolic ldl_symbolic(int n, const std::vector<int32_t> &ptr,
     // dissection blocks, dense offsets, level schedule, external entry ranges
     S.bstart = nd.bstart;
     S.bheight = nd.bheight;
+    S.bfirst = nd.bfirst;
     const int nb = (int)S.bheight.size();
     S.blk.assign(n, 0);
     S.doff.assign(nb + 1, 0);
@@ -338,6 +341,212 @@ void ldl_solve_blocks_host(const LdlSymbolic &S, const std::vector<cd> &D,
         }
         for (int r = S.lptr[l]; r < S.lptr[l + 1]; r++) y[S.lrow[r]] = z[S.lrow[r]];
     }
+    x.assign(n, cd(0));
+    for (int i = 0; i < n; i++) x[S.perm[i]] = y[i];
+}
+
+namespace {
+
+// The plan at cut height H (ok = false if a limit is exceeded or the
+// structure is not the one the kernels assume).
+LdlSplit split_at(const LdlSymbolic &S, int H, int sub_max_rows, int top_max_rows,
+                  int phase_max_rows) {
+    LdlSplit P;
+    const int n = S.n, nb = (int)S.bheight.size();
+    P.H = H;
+    P.hmax = 0;
+    for (int b = 0; b < nb; b++) P.hmax = std::max(P.hmax, (int)S.bheight[b]);
+    // roots of the bottom subtrees (scan from the top: subtrees are contiguous)
+    std::vector<int32_t> roots, topb, sub_of(n, -1);
+    for (int b = nb - 1; b >= 0;) {
+        if (S.bheight[b] < H) {
+            roots.push_back(b);
+            b = S.bfirst[b] - 1;
+        } else {
+            topb.push_back(b);
+            b--;
+        }
+    }
+    std::reverse(roots.begin(), roots.end());
+    std::reverse(topb.begin(), topb.end());
+    P.nsub = (int)roots.size();
+    for (int s = 0; s < P.nsub; s++) {
+        const int root = roots[s], r0 = S.bstart[S.bfirst[root]], r1 = S.bstart[root + 1];
+        if (r1 - r0 > sub_max_rows) return P;
+        P.max_sub_rows = std::max(P.max_sub_rows, r1 - r0);
+        P.sub_r0.push_back(r0);
+        P.sub_r1.push_back(r1);
+        for (int r = r0; r < r1; r++) sub_of[r] = s;
+        std::vector<std::vector<int32_t>> byh(H);
+        for (int b = S.bfirst[root]; b <= root; b++)
+            for (int r = S.bstart[b]; r < S.bstart[b + 1]; r++) byh[S.bheight[b]].push_back(r);
+        for (int h = 0; h < H; h++) {
+            if ((int)byh[h].size() > phase_max_rows) return P;
+            P.sub_hptr.push_back((int32_t)P.srow.size());
+            P.srow.insert(P.srow.end(), byh[h].begin(), byh[h].end());
+        }
+    }
+    P.sub_hptr.push_back((int32_t)P.srow.size());
+    // top part
+    std::vector<int32_t> tl(n, -1);
+    for (int b : topb)
+        for (int r = S.bstart[b]; r < S.bstart[b + 1]; r++) P.top_row.push_back(r);
+    P.ntop = (int)P.top_row.size();
+    if (P.ntop > top_max_rows) return P;
+    for (int t = 0; t < P.ntop; t++) tl[P.top_row[t]] = t;
+    if (P.ntop > 0) {
+        std::vector<std::vector<int32_t>> byh(P.hmax - H + 1);
+        for (int t = 0; t < P.ntop; t++) byh[S.bheight[S.blk[P.top_row[t]]] - H].push_back(t);
+        for (auto &v : byh) {
+            if ((int)v.size() > phase_max_rows) return P;
+            P.top_hptr.push_back((int32_t)P.tlist.size());
+            P.tlist.insert(P.tlist.end(), v.begin(), v.end());
+        }
+        P.top_hptr.push_back((int32_t)P.tlist.size());
+    }
+    // every row is in exactly one subtree or in the top
+    for (int r = 0; r < n; r++)
+        if ((sub_of[r] >= 0) == (tl[r] >= 0)) return P;
+    // bottom rows: forward entries inside the own subtree, backward entries in
+    // the own subtree first, then in the top part
+    P.bsplit.assign(n, 0);
+    for (int s = 0; s < P.nsub; s++)
+        for (int j = P.sub_r0[s]; j < P.sub_r1[s]; j++) {
+            for (int q = S.Rp[j]; q < S.fext[j]; q++)
+                if (S.Rj[q] < P.sub_r0[s] || S.Rj[q] >= j) return P;
+            int e = S.bext[j];
+            while (e < S.Lp[j + 1] && S.Li[e] < P.sub_r1[s]) e++;
+            for (int e2 = e; e2 < S.Lp[j + 1]; e2++)
+                if (tl[S.Li[e2]] < 0) return P;
+            P.bsplit[j] = e;
+        }
+    // top rows: forward entries by subtree (contiguous column ranges) and in the
+    // top part; backward entries all in the top part
+    P.part_b.assign((size_t)P.nsub * P.ntop, 0);
+    P.part_e.assign((size_t)P.nsub * P.ntop, 0);
+    P.tf_ptr.push_back(0);
+    P.tb_ptr.push_back(0);
+    for (int t = 0; t < P.ntop; t++) {
+        const int j = P.top_row[t];
+        int counted = 0;
+        for (int s = 0; s < P.nsub; s++) {
+            const int32_t *c0 = S.Rj.data() + S.Rp[j], *c1 = S.Rj.data() + S.fext[j];
+            const int b = (int)(std::lower_bound(c0, c1, P.sub_r0[s]) - S.Rj.data());
+            const int e = (int)(std::lower_bound(c0, c1, P.sub_r1[s]) - S.Rj.data());
+            P.part_b[(size_t)s * P.ntop + t] = b;
+            P.part_e[(size_t)s * P.ntop + t] = e;
+            counted += e - b;
+        }
+        for (int q = S.Rp[j]; q < S.fext[j]; q++)
+            if (tl[S.Rj[q]] >= 0) {
+                P.tf_pos.push_back(q);
+                P.tf_col.push_back(tl[S.Rj[q]]);
+                counted++;
+            }
+        if (counted != S.fext[j] - S.Rp[j]) return P;
+        P.tf_ptr.push_back((int32_t)P.tf_pos.size());
+        for (int e = S.bext[j]; e < S.Lp[j + 1]; e++) {
+            if (tl[S.Li[e]] < 0) return P;
+            P.tb_pos.push_back(e);
+            P.tb_row.push_back(tl[S.Li[e]]);
+        }
+        P.tb_ptr.push_back((int32_t)P.tb_pos.size());
+    }
+    P.ok = true;
+    return P;
+}
+
+}   // namespace
+
+LdlSplit ldl_split_plan(const LdlSymbolic &S, int sub_max_rows, int top_max_rows,
+                        int phase_max_rows) {
+    int hmax = 0;
+    for (int h : S.bheight) hmax = std::max(hmax, h);
+    // the largest cut height that fits: the smallest top part
+    for (int H = hmax + 1; H >= 1; H--) {
+        LdlSplit P = split_at(S, H, sub_max_rows, top_max_rows, phase_max_rows);
+        if (P.ok) return P;
+    }
+    return LdlSplit{};
+}
+
+void ldl_solve_split_host(const LdlSymbolic &S, const LdlSplit &P, const std::vector<cd> &D,
+                          const std::vector<cd> &Lx, const std::vector<cd> &invL,
+                          const std::vector<cd> &invLT, const std::vector<cd> &b,
+                          std::vector<cd> &x) {
+    const int n = S.n;
+    std::vector<cd> y(n), z(n), part((size_t)P.nsub * P.ntop);
+    auto dense = [&](const int32_t *rows, int cnt, bool fwd) {
+        for (int k = 0; k < cnt; k++) {
+            const int i = rows[k], bb = S.blk[i], s0 = S.bstart[bb], w = S.bstart[bb + 1] - s0;
+            cd acc = 0.0;
+            if (fwd)
+                for (int t = 0; t <= i - s0; t++) acc += invL[S.doff[bb] + (i - s0) * w + t] * y[s0 + t];
+            else
+                for (int t = i - s0; t < w; t++) acc += invLT[S.doff[bb] + (i - s0) * w + t] * y[s0 + t];
+            z[i] = acc;
+        }
+        for (int k = 0; k < cnt; k++) y[rows[k]] = z[rows[k]];
+    };
+    // bottom, forward, and the partial sums of the top rows
+    for (int s = 0; s < P.nsub; s++) {
+        for (int h = 0; h < P.H; h++) {
+            const int a = P.sub_hptr[s * P.H + h], e = P.sub_hptr[s * P.H + h + 1];
+            for (int k = a; k < e; k++) {
+                const int j = P.srow[k];
+                cd acc = 0.0;
+                for (int q = S.Rp[j]; q < S.fext[j]; q++) acc += Lx[S.Rmap[q]] * y[S.Rj[q]];
+                y[j] = b[S.perm[j]] - acc;
+            }
+            dense(P.srow.data() + a, e - a, true);
+        }
+        for (int t = 0; t < P.ntop; t++) {
+            cd acc = 0.0;
+            for (int q = P.part_b[(size_t)s * P.ntop + t]; q < P.part_e[(size_t)s * P.ntop + t]; q++)
+                acc += Lx[S.Rmap[q]] * y[S.Rj[q]];
+            part[(size_t)s * P.ntop + t] = acc;
+        }
+    }
+    // top, forward then backward
+    const int nht = (int)P.top_hptr.size() - 1;
+    std::vector<int32_t> rows;
+    for (int h = 0; h < nht; h++) {
+        rows.clear();
+        for (int k = P.top_hptr[h]; k < P.top_hptr[h + 1]; k++) {
+            const int t = P.tlist[k], j = P.top_row[t];
+            cd acc = 0.0;
+            for (int s = 0; s < P.nsub; s++) acc += part[(size_t)s * P.ntop + t];
+            for (int q = P.tf_ptr[t]; q < P.tf_ptr[t + 1]; q++)
+                acc += Lx[S.Rmap[P.tf_pos[q]]] * y[P.top_row[P.tf_col[q]]];
+            y[j] = b[S.perm[j]] - acc;
+            rows.push_back(j);
+        }
+        dense(rows.data(), (int)rows.size(), true);
+    }
+    for (int h = nht - 1; h >= 0; h--) {
+        rows.clear();
+        for (int k = P.top_hptr[h]; k < P.top_hptr[h + 1]; k++) {
+            const int t = P.tlist[k], j = P.top_row[t];
+            cd acc = 0.0;
+            for (int q = P.tb_ptr[t]; q < P.tb_ptr[t + 1]; q++)
+                acc += Lx[P.tb_pos[q]] * y[P.top_row[P.tb_row[q]]];
+            y[j] = y[j] / D[j] - acc;
+            rows.push_back(j);
+        }
+        dense(rows.data(), (int)rows.size(), false);
+    }
+    // bottom, backward
+    for (int s = 0; s < P.nsub; s++)
+        for (int h = P.H - 1; h >= 0; h--) {
+            const int a = P.sub_hptr[s * P.H + h], e = P.sub_hptr[s * P.H + h + 1];
+            for (int k = a; k < e; k++) {
+                const int j = P.srow[k];
+                cd acc = 0.0;
+                for (int q = S.bext[j]; q < S.Lp[j + 1]; q++) acc += Lx[q] * y[S.Li[q]];
+                y[j] = y[j] / D[j] - acc;
+            }
+            dense(P.srow.data() + a, e - a, false);
+        }
     x.assign(n, cd(0));
     for (int i = 0; i < n; i++) x[S.perm[i]] = y[i];
 }

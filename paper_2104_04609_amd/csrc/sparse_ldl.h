@@ -32,6 +32,9 @@ struct LdlSymbolic {
     // (leaves 0) makes the level schedule of the block solves.  Rows of one
     // block only reference rows of the same block or of its descendants.
     std::vector<int32_t> bstart, bheight, blk;   // blk[row] = block id
+    // the subtree rooted at block b is the contiguous block range
+    // [bfirst[b], b] (rows [bstart[bfirst[b]], bstart[b + 1]))
+    std::vector<int32_t> bfirst;
     std::vector<int64_t> doff;                   // dense offset of block b (sum of w^2)
     int64_t ndense = 0;
     // level schedule: rows of all blocks of height l are lrow[lptr[l] .. lptr[l+1])
@@ -48,6 +51,7 @@ struct NdOrder {
     std::vector<int32_t> order;    // order[new] = old
     std::vector<int32_t> bstart;   // block boundaries (size nblocks + 1)
     std::vector<int32_t> bheight;  // block heights in the dissection tree
+    std::vector<int32_t> bfirst;   // first block of the subtree rooted at each block
 };
 
 // Geometric nested dissection of an undirected graph (CSR incl. diagonal)
@@ -83,6 +87,43 @@ void ldl_solve_blocks_host(const LdlSymbolic &S, const std::vector<cd> &D,
                            const std::vector<cd> &Lx, const std::vector<cd> &invL,
                            const std::vector<cd> &invLT, const std::vector<cd> &b,
                            std::vector<cd> &x);
+
+// Two-part schedule of the block solves.  The dissection tree is cut at
+// height H: the maximal subtrees of blocks of height < H ("bottom"; rows
+// [r0, r1) each, contiguous) are solved independently, each by one device
+// workgroup holding its rows in LDS; the blocks of height >= H ("top") are
+// solved by one workgroup per system.  A top row's forward external update
+// is split into its entries in each subtree (partial sums formed by the
+// subtree's workgroup) and its entries inside the top part.  H is the
+// largest height at which every subtree has at most sub_max_rows rows, the
+// top part at most top_max_rows rows and every (subtree or top, height)
+// group at most phase_max_rows rows; ok = false if there is none.
+struct LdlSplit {
+    bool ok = false;
+    int H = 0, hmax = 0, nsub = 0, ntop = 0;
+    int max_sub_rows = 0;
+    std::vector<int32_t> sub_r0, sub_r1;   // subtree s: rows [r0, r1)
+    std::vector<int32_t> sub_hptr;         // [nsub][H + 1]: subtree s, height h -> srow range
+    std::vector<int32_t> srow;             // bottom rows by (subtree, height), ascending
+    std::vector<int32_t> top_row;          // top rows ascending (global); t = local index
+    std::vector<int32_t> top_hptr;         // [hmax - H + 2]: height H + i -> tlist range
+    std::vector<int32_t> tlist;            // top local indices by height, ascending
+    std::vector<int32_t> part_b, part_e;   // [nsub][ntop]: CSR entries of top row t in subtree s
+    std::vector<int32_t> tf_ptr, tf_pos, tf_col;   // top row t: forward entries in the top
+                                                   // part (CSR position, local column)
+    std::vector<int32_t> tb_ptr, tb_pos, tb_row;   // top row t: backward entries (CSC
+                                                   // position, local row); all in the top
+    std::vector<int32_t> bsplit;           // bottom row j: first CSC position in
+                                           // [bext[j], Lp[j+1]) whose row is in the top
+};
+LdlSplit ldl_split_plan(const LdlSymbolic &S, int sub_max_rows, int top_max_rows,
+                        int phase_max_rows);
+
+// The two-part block solve on the host (the order of the device kernels).
+void ldl_solve_split_host(const LdlSymbolic &S, const LdlSplit &P, const std::vector<cd> &D,
+                          const std::vector<cd> &Lx, const std::vector<cd> &invL,
+                          const std::vector<cd> &invLT, const std::vector<cd> &b,
+                          std::vector<cd> &x);
 
 // Reference solve A x = b in the original ordering (tests and debugging).
 void ldl_solve_host(const LdlSymbolic &S, const std::vector<cd> &D, const std::vector<cd> &Lx,

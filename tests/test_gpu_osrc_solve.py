@@ -36,6 +36,7 @@ OSRC_CASES = {
     "ico2_np8_lossy": (lambda: icosphere(2), 6.0 + 0.3j, 8, np.pi / 3, 0.1),
     "ico2_np1_theta0": (lambda: icosphere(2), 2.0, 1, 0.0, 0.5),
     "two_spheres2": (lambda: two_spheres(2, offset=1.5), 4.0, 4, np.pi / 3, 0.1),
+    "ico5_np4": (lambda: icosphere(5), 15.0, 4, np.pi / 3, 0.1),
 }
 
 
@@ -56,6 +57,53 @@ def test_osrc_apply_matches_oracle(P, case):
         err = np.linalg.norm(y[sl] - ref[sl]) / np.linalg.norm(ref[sl])
         print(case, err)
         assert err <= 1e-10, err
+
+
+# schedules of the block solves: (osrc.split, osrc.sub_rows, osrc.top_single_work)
+SCHEDULES = {
+    "levels": (0, 0, 300000),              # one launch per dissection level
+    "auto": (1, 0, 300000),                # the default (levels at these sizes)
+    "split_default": (2, 0, 300000),
+    "split_top_single": (2, 512, 1 << 30),  # many subtrees, big top in one workgroup
+    "split_top_levels": (2, 512, 0),        # many subtrees, top level by level
+    "split_tiny": (2, 64, 1 << 30),
+}
+
+
+@pytest.fixture
+def osrc_schedule(P):
+    keys = ("osrc.split", "osrc.sub_rows", "osrc.top_single_work")
+    old = [P.tune_get(k) for k in keys]
+
+    def set_(vals):
+        for k, v in zip(keys, vals):
+            P.tune_set(k, v)
+    yield set_
+    set_(old)
+
+
+@pytest.mark.parametrize("mesh_name", ["ico4", "two_spheres3"])
+@pytest.mark.parametrize("schedule", sorted(SCHEDULES))
+def test_osrc_apply_schedules(P, osrc_schedule, schedule, mesh_name):
+    """Every schedule of the block solves (fresh mesh handles, since the
+    schedule is fixed when a handle builds its OSRC state) against the oracle,
+    4 vectors with 8 Pade terms and a lossy wavenumber."""
+    from oracle.osrc import OSRC, damped_wavenumber
+    mesh = icosphere(4) if mesh_name == "ico4" else two_spheres(3, offset=1.5)
+    N = mesh.n_vertices
+    k = 9.0 + 0.4j
+    keps = damped_wavenumber(k, 0.1)
+    osrc_schedule(SCHEDULES[schedule])
+    M = P.Mesh.from_inputs(mesh)
+    X = complex_normal((4, 2 * N), seed=17)
+    print(f"osrc schedule {schedule} {mesh_name}", flush=True)
+    Y = P.osrc_apply(M, 8, np.pi / 3, k, keps, _dev(X)).cpu().numpy()
+    op = OSRC(mesh, k, keps, 8, np.pi / 3)
+    for r in range(4):
+        ref = op.apply(X[r])
+        for sl in (slice(0, N), slice(N, 2 * N)):
+            err = np.linalg.norm(Y[r][sl] - ref[sl]) / np.linalg.norm(ref[sl])
+            assert err <= 1e-10, (schedule, r, err)
 
 
 def test_osrc_apply_batched_rhs(P):

@@ -59,8 +59,19 @@ enum {
  *   BEM_FP64_DENSE  assembled dense complex128 operator (FP64 pair sums, the
  *                   FP64 pair kernel's quadrature and arithmetic), kept apart
  *                   from the complex64 one; 32 N^2 bytes.  One pass over it
- *                   per vector. */
-enum { BEM_FP64 = 0, BEM_FP32 = 1, BEM_FP32_DENSE = 2, BEM_FP64_DENSE = 3 };
+ *                   per vector.
+ *   BEM_FP32_HMAT   hierarchical form of the far part (the paper's operator
+ *                   compression, Sec. 3.1): vertex cluster tree, admissible
+ *                   cluster pairs (max diam <= eta dist) as adaptive cross
+ *                   approximations U V^T to the relative tolerance tol,
+ *                   other leaf pairs dense, entries as BEM_FP32_DENSE (FP32),
+ *                   the FP64 near-field operator added; built on first use per
+ *                   (k_ext, k_int, rho) and kept with the handle (two at
+ *                   most); parameters from the tuning keys "hmat.*"; see
+ *                   bem_hmat_info for its size.  Error against the exact
+ *                   operator of the order of tol. */
+
+enum { BEM_FP64 = 0, BEM_FP32 = 1, BEM_FP32_DENSE = 2, BEM_FP64_DENSE = 3, BEM_FP32_HMAT = 4 };
 
 /*
  * Create the device state of a triangle surface mesh (Sec. 2.1: bounded
@@ -450,6 +461,13 @@ int bem_profile_read(const char *kernel, double *total_ms, int64_t *launches);
  *                         (formed in FP64 again before the carried bound
  *                         reaches tol / 10); 0 forms every outer residual with
  *                         the FP64 operator (default 1)
+ *   "hmat.leaf"           compressed operator: vertices per leaf cluster,
+ *                         8..64 (default 64)
+ *   "hmat.eta_pct"        admissibility parameter eta in percent (default
+ *                         100: max diameter <= distance)
+ *   "hmat.tol_ppb"        ACA tolerance in parts per 1e9 (default 10000 =
+ *                         1e-5, the paper's)
+ *   "hmat.kmax"           largest rank of a block, 4..512 (default 128)
  *   "osrc.split"          OSRC block solves (keys read when a mesh handle
  *                         first builds its OSRC state): 2 solves the bottom
  *                         subtrees of the nested dissection in one workgroup
@@ -467,6 +485,26 @@ int bem_profile_read(const char *kernel, double *total_ms, int64_t *launches);
  * the FP32 accuracy.  BEM_E_INVAL for an unknown key or value. */
 int bem_tune_set(const char *key, int64_t value);
 int bem_tune_get(const char *key, int64_t *value);
+
+/* Size and set-up cost of the compressed operator (BEM_FP32_HMAT) of a
+ * wavenumber pair; builds it if needed. */
+typedef struct {
+    int64_t bytes;            /* device bytes of the whole operator */
+    int64_t lowrank_bytes;    /* U, V factors */
+    int64_t dense_bytes;      /* dense leaf blocks */
+    int32_t n_clusters, n_admissible, n_dense, max_rank;
+    int32_t split_blocks;     /* admissible blocks split into their children after
+                                 kmax terms above the tolerance */
+    int32_t leaf, kmax;
+    double mean_rank;
+    double admissible_fraction;   /* share of the 4 N^2 entries in low-rank blocks */
+    double eta, tol;
+    double setup_seconds;     /* tree, ACA and dense blocks (wall clock) */
+    double alpha;             /* scaling of the phi rows and columns during the
+                                 cross approximation (balances the blocks) */
+} bem_hmat_stats;
+int bem_hmat_info(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
+                  bem_hmat_stats *out, void *hip_stream);
 
 /*
  * Autotuner.  For a mesh size (triangle count) and a right-hand-side count it

@@ -22,10 +22,11 @@ if not os.path.exists(LIB_PATH):
 
 lib = ctypes.CDLL(LIB_PATH)
 
-BEM_FP64, BEM_FP32, BEM_FP32_DENSE, BEM_FP64_DENSE = 0, 1, 2, 3
+BEM_FP64, BEM_FP32, BEM_FP32_DENSE, BEM_FP64_DENSE, BEM_FP32_HMAT = 0, 1, 2, 3, 4
 _PREC = {"fp64": BEM_FP64, "fp32": BEM_FP32, "fp32_dense": BEM_FP32_DENSE,
-         "fp64_dense": BEM_FP64_DENSE, BEM_FP64: BEM_FP64, BEM_FP32: BEM_FP32,
-         BEM_FP32_DENSE: BEM_FP32_DENSE, BEM_FP64_DENSE: BEM_FP64_DENSE}
+         "fp64_dense": BEM_FP64_DENSE, "fp32_hmat": BEM_FP32_HMAT, BEM_FP64: BEM_FP64,
+         BEM_FP32: BEM_FP32, BEM_FP32_DENSE: BEM_FP32_DENSE, BEM_FP64_DENSE: BEM_FP64_DENSE,
+         BEM_FP32_HMAT: BEM_FP32_HMAT}
 ERRORS = {1: "BEM_W_NOT_CONVERGED", 2: "BEM_W_PENDING", 3: "BEM_W_DEFAULT", -1: "BEM_E_INVAL", -2: "BEM_E_BAD_MESH",
           -3: "BEM_E_NOMEM", -4: "BEM_E_DEVICE", -5: "BEM_E_NAN",
           -6: "BEM_E_UNSUPPORTED"}
@@ -62,6 +63,20 @@ class TuneEntry(ctypes.Structure):
                 ("skinny_min", ctypes.c_int), ("path", ctypes.c_int),
                 ("t_matrix_free", ctypes.c_double),
                 ("t_assembled", ctypes.c_double), ("t_assembly", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class HMatStats(ctypes.Structure):
+    _fields_ = [("bytes", ctypes.c_int64), ("lowrank_bytes", ctypes.c_int64),
+                ("dense_bytes", ctypes.c_int64), ("n_clusters", ctypes.c_int32),
+                ("n_admissible", ctypes.c_int32), ("n_dense", ctypes.c_int32),
+                ("max_rank", ctypes.c_int32), ("split_blocks", ctypes.c_int32),
+                ("leaf", ctypes.c_int32), ("kmax", ctypes.c_int32),
+                ("mean_rank", ctypes.c_double), ("admissible_fraction", ctypes.c_double),
+                ("eta", ctypes.c_double), ("tol", ctypes.c_double),
+                ("setup_seconds", ctypes.c_double), ("alpha", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -123,6 +138,7 @@ lib.bem_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double
                                  ctypes.POINTER(_i64)]
 lib.bem_valu_rates.argtypes = [_vp, _vp]
 lib.bem_tune_set.argtypes = [ctypes.c_char_p, _i64]
+lib.bem_hmat_info.argtypes = [_vp, c64, c64, ctypes.c_double, ctypes.POINTER(HMatStats), _vp]
 lib.bem_autotune.argtypes = [_vp, c64, c64, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                              ctypes.POINTER(TuneEntry), _vp]
 lib.bem_tune_cache_load.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]
@@ -541,6 +557,15 @@ def tune_lookup(n_triangles: int, n_rhs: int = 1):
 
 def tune_clear():
     lib.bem_tune_clear()
+
+
+def hmat_info(mesh: Mesh, k_ext, k_int, rho: float, stream=None) -> dict:
+    """Size and set-up time of the compressed operator (precision
+    "fp32_hmat") of a wavenumber pair; builds it if needed."""
+    st = HMatStats()
+    _check(lib.bem_hmat_info(mesh.handle, _c(k_ext), _c(k_int), float(rho), ctypes.byref(st),
+                             _stream(stream)))
+    return st.as_dict()
 
 
 def tune_set(key: str, value: int):

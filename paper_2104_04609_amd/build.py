@@ -22,7 +22,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["api.cpp", "mesh.cpp", "quadrature.cpp", "farfield.hip",
            "nearfield.hip", "rhs.hip", "sparse_ldl.cpp", "osrc.cpp",
            "osrc_kernels.hip", "blas.hip", "dense.hip", "solve.cpp", "probe.hip",
-           "server.cpp", "tune.cpp", "field.hip", "noalloc.hip"]
+           "server.cpp", "tune.cpp", "field.hip", "noalloc.hip", "hmat.hip"]
 
 FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Wall", "-Wno-unused-function", "-Wno-unused-result",

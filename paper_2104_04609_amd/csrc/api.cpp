@@ -94,6 +94,7 @@ int64_t bem_mesh::device_bytes() const {
     for (const auto &kv : near_cache) b += kv.second->vals.bytes();
     for (const auto &kv : dense_cache) b += kv.second->B.bytes();
     for (const auto &kv : dense64_cache) b += kv.second->B64.bytes();
+    for (const auto &kv : hmat_cache) b += bem::hmat_bytes(*kv.second);
     b += xs32.bytes();
     for (const auto &kv : osrc_cache) b += bem::osrc_bytes(*kv.second);
     if (osrc_sym) b += bem::osrc_sym_bytes(*osrc_sym);
@@ -195,7 +196,7 @@ void operator_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double 
     if (x == y) fail(BEM_E_INVAL, "x and y must not alias");
     if (n_rhs < 1) fail(BEM_E_INVAL, "n_rhs must be >= 1");
     if (precision != BEM_FP64 && precision != BEM_FP32 && precision != BEM_FP32_DENSE &&
-        precision != BEM_FP64_DENSE)
+        precision != BEM_FP64_DENSE && precision != BEM_FP32_HMAT)
         fail(BEM_E_INVAL, "bad precision");
     bem_mesh *m = const_cast<bem_mesh *>(mesh);
     hipStream_t s = (hipStream_t)hip_stream;
@@ -205,6 +206,13 @@ void operator_matvec(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double 
         const bem::DenseOperator &op =
             bem::dense_get(m, k0, k1, rho, s, s1, om, precision == BEM_FP64_DENSE);
         bem::dense_apply(op, (const double2 *)x, (double2 *)y, n_rhs, m->xs32, s);
+        return;
+    }
+    if (precision == BEM_FP32_HMAT) {
+        bem::HMatrix &h = bem::hmat_get(m, k0, k1, rho, s, s1, om);
+        const int64_t n2 = 2 * m->N;
+        for (int r = 0; r < n_rhs; r++)
+            bem::hmat_apply(h, m, nf, (const double2 *)x + r * n2, (double2 *)y + r * n2, s);
         return;
     }
     bem::farfield_apply_batch(m, nf, k0, k1, rho, (const double2 *)x, (double2 *)y, n_rhs,
@@ -345,6 +353,39 @@ int pmchwt_field_multi(const bem_mesh *mesh, bem_c64 k_ext, const bem_c64 *k_int
     BEM_API_END
 }
 
+int bem_hmat_info(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int, double rho,
+                  bem_hmat_stats *out, void *hip_stream) {
+    BEM_API_BEGIN
+    check_mesh(mesh);
+    check_k(k_ext, "k_ext");
+    check_k(k_int, "k_int");
+    if (!(rho > 0) || !std::isfinite(rho)) fail(BEM_E_INVAL, "rho must be positive");
+    if (!out) fail(BEM_E_INVAL, "out is NULL");
+    bem_mesh *m = const_cast<bem_mesh *>(mesh);
+    const bem::HMatStats &st =
+        bem::hmat_stats(bem::hmat_get(m, make_double2(k_ext.re, k_ext.im),
+                                      make_double2(k_int.re, k_int.im), rho,
+                                      (hipStream_t)hip_stream));
+    out->bytes = st.bytes;
+    out->lowrank_bytes = st.lowrank_bytes;
+    out->dense_bytes = st.dense_bytes;
+    out->n_clusters = st.n_clusters;
+    out->n_admissible = st.n_admissible;
+    out->n_dense = st.n_dense;
+    out->max_rank = st.max_rank;
+    out->split_blocks = st.split_blocks;
+    out->leaf = st.leaf;
+    out->kmax = st.kmax;
+    out->mean_rank = st.mean_rank;
+    out->admissible_fraction = st.admissible_fraction;
+    out->eta = st.eta;
+    out->tol = st.tol;
+    out->setup_seconds = st.setup_seconds;
+    out->alpha = st.alpha;
+    return BEM_OK;
+    BEM_API_END
+}
+
 int bem_tune_set(const char *key, int64_t value) {
     BEM_API_BEGIN
     if (!key) fail(BEM_E_INVAL, "key is NULL");
@@ -368,6 +409,18 @@ int bem_tune_set(const char *key, int64_t value) {
     } else if (k == "solve.refine_update") {
         if (value != 0 && value != 1) fail(BEM_E_INVAL, "solve.refine_update: 0 or 1");
         t.solve_refine_update = (int)value;
+    } else if (k == "hmat.leaf") {
+        if (value < 8 || value > 64) fail(BEM_E_INVAL, "hmat.leaf: 8..64");
+        t.hmat_leaf = (int)value;
+    } else if (k == "hmat.eta_pct") {
+        if (value < 10 || value > 1000) fail(BEM_E_INVAL, "hmat.eta_pct: 10..1000");
+        t.hmat_eta_pct = (int)value;
+    } else if (k == "hmat.tol_ppb") {
+        if (value < 100 || value > 100000000) fail(BEM_E_INVAL, "hmat.tol_ppb: 100..1e8");
+        t.hmat_tol_ppb = value;
+    } else if (k == "hmat.kmax") {
+        if (value < 4 || value > 512) fail(BEM_E_INVAL, "hmat.kmax: 4..512");
+        t.hmat_kmax = (int)value;
     } else if (k == "osrc.split") {
         if (value < 0 || value > 2) fail(BEM_E_INVAL, "osrc.split: 0, 1 or 2");
         t.osrc_split = (int)value;
@@ -395,6 +448,10 @@ int bem_tune_get(const char *key, int64_t *value) {
     else if (k == "dense.skinny_min_rhs") *value = t.dense_skinny_min_rhs;
     else if (k == "dense.gemm_min_rhs") *value = t.dense_gemm_min_rhs;
     else if (k == "solve.refine_update") *value = t.solve_refine_update;
+    else if (k == "hmat.leaf") *value = t.hmat_leaf;
+    else if (k == "hmat.eta_pct") *value = t.hmat_eta_pct;
+    else if (k == "hmat.tol_ppb") *value = t.hmat_tol_ppb;
+    else if (k == "hmat.kmax") *value = t.hmat_kmax;
     else if (k == "osrc.split") *value = t.osrc_split;
     else if (k == "osrc.sub_rows") *value = t.osrc_sub_rows;
     else if (k == "osrc.top_single_work") *value = t.osrc_top_single_work;

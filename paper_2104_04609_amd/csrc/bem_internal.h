@@ -157,6 +157,11 @@ struct OsrcDeleter {
     void operator()(OsrcState *p) const;   // osrc.cpp
 };
 int64_t osrc_bytes(const OsrcState &st);
+struct HMatrix;   // hmat.hip
+struct HMatDeleter {
+    void operator()(HMatrix *p) const;
+};
+
 struct OsrcSymbolicState;   // osrc.cpp
 struct OsrcSymDeleter {
     void operator()(OsrcSymbolicState *p) const;
@@ -204,6 +209,7 @@ struct bem_mesh {
     std::map<bem::NearKey, std::unique_ptr<bem::NearOperator>> near_cache;
     std::map<bem::NearKey, std::unique_ptr<bem::DenseOperator>> dense_cache;
     std::map<bem::NearKey, std::unique_ptr<bem::DenseOperator>> dense64_cache;   // complex128
+    std::map<bem::NearKey, std::unique_ptr<bem::HMatrix, bem::HMatDeleter>> hmat_cache;
     bem::DevBuf<float2> xs32;          // complex64 copy of a matvec input
 
     // OSRC: P1 vertex graph, M and S values, factor state per parameter set
@@ -238,6 +244,11 @@ struct Tuning {
     std::atomic<int> dense_gemm_min_rhs{24};  // MFMA product from this many right-hand sides
     std::atomic<int> dense_skinny_min_rhs{24}; // skinny MFMA product from this many (else multi-GEMV)
     std::atomic<int> solve_refine_update{1};  // FP32 refinement: later residuals updated in FP32
+    // compressed operator (read when one is built)
+    std::atomic<int> hmat_leaf{64};           // vertices per leaf cluster (<= 64)
+    std::atomic<int> hmat_eta_pct{100};       // admissibility max(diam) <= eta dist, percent
+    std::atomic<int64_t> hmat_tol_ppb{10000}; // ACA tolerance, parts per 1e9 (1e-5)
+    std::atomic<int> hmat_kmax{128};          // largest rank of a block
     // OSRC block solves (read when a mesh's OSRC symbolic state is built)
     std::atomic<int> osrc_split{1};           // 0 levels, 1 automatic, 2 two-part when it fits
     std::atomic<int> osrc_sub_rows{0};        // largest bottom subtree (rows); 0: 4096 or the LDS limit
@@ -287,6 +298,24 @@ const NearOperator &nearfield_get(bem_mesh *m, double2 k0, double2 k1, double rh
 // the uniform key
 NearKey near_key(const bem_mesh *m, double2 k0, double2 k1, double rho, int s1,
                  const ObjMaterials *om);
+// hmat.hip: hierarchical (ACA) form of the far part of B
+struct HMatStats {
+    int n_clusters = 0, n_admissible = 0, n_dense = 0, max_rank = 0;
+    int split_blocks = 0;   // admissible blocks split after kmax terms
+    double mean_rank = 0, admissible_fraction = 0, eta = 0, tol = 0, setup_seconds = 0;
+    double alpha = 1;       // scaling of the phi rows and columns in the cross approximation
+    int leaf = 0, kmax = 0;
+    int64_t bytes = 0, lowrank_bytes = 0, dense_bytes = 0;
+};
+std::unique_ptr<HMatrix, HMatDeleter> hmat_build(bem_mesh *m, const NearOperator &nf, double2 k0,
+                                                 hipStream_t s);
+void hmat_apply(HMatrix &H, bem_mesh *m, const NearOperator &nf, const double2 *x, double2 *y,
+                hipStream_t s);
+int64_t hmat_bytes(const HMatrix &h);
+const HMatStats &hmat_stats(const HMatrix &h);
+// cached per wavenumber pair and materials (built on first use)
+HMatrix &hmat_get(bem_mesh *m, double2 k0, double2 k1, double rho, hipStream_t s, int s1 = 1,
+                  const ObjMaterials *om = nullptr);
 // dense.hip
 int64_t dense_bytes(const bem_mesh *m, bool fp64 = false);
 int64_t dense_assembly_scratch_bytes(const bem_mesh *m, bool fp64 = false);

@@ -1,0 +1,146 @@
+"""The compressed operator (precision "fp32_hmat": vertex cluster tree,
+adaptive cross approximation of admissible blocks to 1e-5, the paper's
+tolerance, Sec. 3.1; dense leaf blocks; FP64 near field) against the oracle.
+
+* small sphere: every row against the oracle's dense matrix, per block row;
+* unit sphere level 5 (the metric's mesh): 32 sampled rows of each block row
+  against the oracle's matrix-free rows, and all rows against the GPU's FP64
+  matrix-free product;
+* lossy ellipsoid (40 962 vertices): the 512 stored oracle rows;
+* Mueller operator and two objects with a material each;
+* deterministic (bitwise repeat), smaller than the dense operator.
+The bound 2e-4 leaves room over the ACA tolerance for the sum of the block
+errors and the complex64 storage of the factors.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from bem_inputs import complex_normal, ellipsoid, icosphere, sample_rows, two_spheres
+
+pytestmark = pytest.mark.gpu
+TOL = 2e-4
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2104_04609_amd as P
+    return P
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.fixture
+def small_leaves(P):
+    """Leaves of 16 vertices, so that a 642-vertex mesh has admissible blocks."""
+    old = P.tune_get("hmat.leaf")
+    P.tune_set("hmat.leaf", 16)
+    yield
+    P.tune_set("hmat.leaf", old)
+
+
+def test_hmat_small_sphere_against_oracle_matrix(P, small_leaves):
+    from oracle.operators import pmchwt_matrix
+    mesh = icosphere(3)
+    N = mesh.n_vertices
+    M = P.Mesh.from_inputs(mesh)
+    x = complex_normal(2 * N, seed=4)
+    print("hmat ico3", flush=True)
+    y = P.pmchwt_matvec(M, 2.0, 3.0, 1.5, _dev(x), precision="fp32_hmat").cpu().numpy()
+    ref = pmchwt_matrix(mesh, 2.0, 3.0, 1.5) @ x
+    st = P.hmat_info(M, 2.0, 3.0, 1.5)
+    print(st)
+    assert st["n_admissible"] > 0
+    for sl in (slice(0, N), slice(N, 2 * N)):
+        e = _rel(y[sl], ref[sl])
+        print("block row", e)
+        assert e <= TOL
+
+
+@pytest.fixture(scope="module")
+def l5(P):
+    mesh = icosphere(5)
+    return mesh, P.Mesh.from_inputs(mesh)
+
+
+def test_hmat_l5_rows_and_fp64_product(P, l5):
+    import torch
+    from oracle.operators import pmchwt_matvec_rows
+    mesh, M = l5
+    N = mesh.n_vertices
+    x = complex_normal(2 * N, seed=0)
+    xd = _dev(x)
+    print("hmat L5 build", flush=True)
+    y = P.pmchwt_matvec(M, 10.0, 15.0, 1.5, xd, precision="fp32_hmat")
+    y2 = P.pmchwt_matvec(M, 10.0, 15.0, 1.5, xd, precision="fp32_hmat")
+    assert torch.equal(y, y2)
+    y = y.cpu().numpy()
+    st = P.hmat_info(M, 10.0, 15.0, 1.5)
+    print(st)
+    assert st["max_rank"] <= st["kmax"]
+    assert st["bytes"] < 0.5 * 32 * N * N        # under half the complex64 dense operator
+    y64 = P.pmchwt_matvec(M, 10.0, 15.0, 1.5, xd, precision="fp64").cpu().numpy()
+    for sl in (slice(0, N), slice(N, 2 * N)):
+        e = _rel(y[sl], y64[sl])
+        print("vs FP64 product", e)
+        assert e <= TOL
+    rows = sample_rows(N, 32, seed=6)
+    r1, r2 = pmchwt_matvec_rows(mesh, 10.0, 15.0, 1.5, x, rows)
+    e1, e2 = _rel(y[rows], r1), _rel(y[N + rows], r2)
+    print("vs oracle rows", e1, e2)
+    assert e1 <= TOL and e2 <= TOL
+
+
+def test_hmat_lossy_ellipsoid_stored_rows(P):
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "c3_rows.npz"))
+    mesh = ellipsoid(icosphere(6))
+    N = mesh.n_vertices
+    x = complex_normal(2 * N, seed=int(g["seed_x"]))
+    rows = sample_rows(N, 512, seed=int(g["seed_rows"]))
+    assert np.array_equal(rows, g["rows"])
+    M = P.Mesh.from_inputs(mesh)
+    print("hmat C3 build", flush=True)
+    y = P.pmchwt_matvec(M, 20.0, 30.0 + 1.5j, 1.9, _dev(x), precision="fp32_hmat").cpu().numpy()
+    st = P.hmat_info(M, 20.0, 30.0 + 1.5j, 1.9)
+    print(st)
+    assert st["max_rank"] <= st["kmax"]
+    e1, e2 = _rel(y[rows], g["r1"]), _rel(y[N + rows], g["r2"])
+    print("vs oracle rows", e1, e2)
+    assert e1 <= TOL and e2 <= TOL
+
+
+def test_hmat_mueller_and_two_objects(P, small_leaves):
+    mesh = icosphere(3)
+    N = mesh.n_vertices
+    M = P.Mesh.from_inputs(mesh)
+    x = _dev(complex_normal(2 * N, seed=8))
+    print("hmat Mueller", flush=True)
+    y = P.muller_matvec(M, 3.0, 4.5, 1.6, x, precision="fp32_hmat").cpu().numpy()
+    ref = P.muller_matvec(M, 3.0, 4.5, 1.6, x, precision="fp64").cpu().numpy()
+    assert _rel(y, ref) <= TOL
+    two = two_spheres(3, offset=1.5)
+    N2 = two.n_vertices
+    M2 = P.Mesh.from_inputs(two)
+    x2 = _dev(complex_normal(2 * N2, seed=9))
+    k_int, rho = [3.0 + 0.2j, 5.0], [1.4, 1.9]
+    print("hmat two objects", flush=True)
+    y2 = P.pmchwt_matvec_multi(M2, 2.5, k_int, rho, x2, precision="fp32_hmat").cpu().numpy()
+    r2 = P.pmchwt_matvec_multi(M2, 2.5, k_int, rho, x2, precision="fp64").cpu().numpy()
+    for sl in (slice(0, N2), slice(N2, 2 * N2)):
+        assert _rel(y2[sl], r2[sl]) <= TOL
+
+
+def test_hmat_tuning_keys_rejected_out_of_range(P):
+    for key, bad in (("hmat.leaf", 65), ("hmat.eta_pct", 5), ("hmat.tol_ppb", 10), ("hmat.kmax", 2)):
+        with pytest.raises(P.BemError):
+            P.tune_set(key, bad)

@@ -12,6 +12,15 @@ evaluations per second of that step.  The solve comparison (FP64 GMRES vs
 FP32 pair kernel + FP64 true-residual refinement, both to 1e-6) and the FP64
 matvec are measured in the same run outside the timed steps.
 
+Legs reported beside the timed steps (each can be skipped): the OSRC apply
+(ms, algorithmic bytes, GB/s), the four-sphere multiple-scattering layout,
+batching (assembled complex64 operators x 64 right-hand sides on MFMA), the
+smallest workload (icosphere L3, FP64 solve to 1e-8 against the Mie series
+and the oracle's own solve), the lossy ellipsoid (40 962 vertices: matvecs,
+OSRC, FP64 against FP32 + refinement solves, the compressed operator), the
+compressed operator at 1e5 vertices, the 256-request serving stream, and the
+oracle baselines on the host cores.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -46,6 +55,7 @@ def cpu_baseline(mesh, n_test=2048):
     dt = time.perf_counter() - t0
     return {"value": n_test * T / dt, "unit": "tri-pair evals/s",
             "cores": int(lib.oracle_num_threads()), "kind": "oracle",
+            "seconds": dt, "n_test": n_test,
             "sample": f"{n_test} seeded test triangles x all {T} trial triangles, "
                       f"both wavenumbers, 4 operators, FP64 ({dt:.1f} s)"}
 
@@ -191,113 +201,271 @@ def multi_material_measure(P, RL) -> dict:
     return out
 
 
-def frequency_sweep(P) -> dict:
-    """GMRES iterations against frequency (the paper's frequency-dependency
-    test, Sec. 3): a sphere of radius 5 mm in water, interior fat or bone
-    (Table 1 media), 0.5 - 2.5 MHz, about six elements per wavelength (geodesic
-    spheres of 10 n^2 + 2 vertices near the paper's node counts), plane wave
-    along +z, tolerance 1e-7 on the preconditioned residual (Sec. 3.1).  Every
-    formulation: PMCHWT, Mueller, Calderon, OSRC with the interior and with the
-    exterior wavenumber; FP32 assembled operator + FP64 refinement, so the
-    count is the total of the inner GMRES iterations.  Then the four-sphere
-    layout (two fat, two bone) at 0.5 - 1.5 MHz, wave along +x."""
-    import torch
-    from bem_inputs import density_ratio, four_spheres, geodesic_sphere, wavenumber
-    a = 5e-3
-    sizes = {0.5e6: 13, 1.0e6: 27, 1.5e6: 40, 2.0e6: 52, 2.5e6: 65}
-    forms = (("pmchwt", "pmchwt", 1), ("muller", "muller", 1), ("calderon", "calderon", 1),
-             ("osrc_int", "osrc", 1), ("osrc_ext", "osrc", 0))
-    out = []
-    for f, n in sizes.items():
-        mesh = geodesic_sphere(n)
-        M = P.Mesh.from_inputs(mesh)
-        k0 = wavenumber("water", f, a)
-        for medium in ("fat", "bone"):
-            k1, rho = wavenumber(medium, f, a), density_ratio(medium)
-            row = {"f_MHz": f / 1e6, "medium": medium, "n_vertices": mesh.n_vertices}
-            for name, form, interior in forms:
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                _, info, rc = P.pmchwt_solve(M, k0, k1, rho, [[0.0, 0.0, 1.0]], 1e-7,
-                                             precision="fp32", path=1, formulation=form,
-                                             osrc_interior=interior)
-                torch.cuda.synchronize()
-                row[name] = {"iterations": info[0]["iterations"],
-                             "outer_steps": info[0]["outer_steps"],
-                             "seconds": time.perf_counter() - t0, "rc": rc}
-            out.append(row)
-            print("sweep " + json.dumps(row), file=sys.stderr, flush=True)
-        del M
-        P.tune_clear()
-    # the four-sphere test (two fat, two bone; 6 823 / 26 801 / 59 758 nodes at
-    # 0.5 / 1 / 1.5 MHz in the paper; 2 MHz would need a 340 GB assembled operator)
-    four = []
-    tissue = ["fat", "bone", "bone", "fat"]
-    for f, n in {0.5e6: 13, 1.0e6: 26, 1.5e6: 39}.items():
-        mesh = four_spheres(geodesic=n)
-        M = P.Mesh.from_inputs(mesh)
-        k0 = wavenumber("water", f, a)
-        ks = [wavenumber(t, f, a) for t in tissue]
-        rs = [density_ratio(t) for t in tissue]
-        row = {"f_MHz": f / 1e6, "n_vertices": mesh.n_vertices}
-        for name, form, interior in forms:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, info, rc = P.pmchwt_solve_multi(M, k0, ks, rs, [[1.0, 0.0, 0.0]], 1e-7,
-                                               precision="fp32", path=1, formulation=form,
-                                               osrc_interior=interior)
-            torch.cuda.synchronize()
-            row[name] = {"iterations": info[0]["iterations"], "outer_steps": info[0]["outer_steps"],
-                         "seconds": time.perf_counter() - t0, "rc": rc}
-        four.append(row)
-        print("sweep four spheres " + json.dumps(row), file=sys.stderr, flush=True)
-        del M
-        P.tune_clear()
-    return {"frequency_sweep": out, "four_spheres": four}
+def progress(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
-def sponge_sweep(P) -> dict:
-    """The paper's test on a domain with corners and inclusions: a level-2
-    Menger sponge of edge 10 mm, bone inside, water outside, plane wave along
-    +x, 0.5 / 1 / 1.5 MHz with every voxel face split 4 / 6 / 8 times
-    (16 736 / 37 856 / 67 424 vertices; the paper's Gmsh meshes have 13 568 /
-    34 975 / 62 291), tolerance 1e-7, every formulation on the FP32 assembled
-    operator + FP64 refinement (up to 2 000 iterations).  2 MHz (105 440
-    vertices) would need a 356 GB assembled operator."""
+def event_ms(fn, reps):
+    """Average milliseconds of fn() over reps calls, HIP events on the current
+    stream (the library's calls run on it)."""
     import torch
-    from bem_inputs import density_ratio, menger_sponge, wavenumber
-    forms = (("pmchwt", "pmchwt", 1), ("muller", "muller", 1), ("calderon", "calderon", 1),
-             ("osrc_int", "osrc", 1), ("osrc_ext", "osrc", 0))
-    out = []
-    for f, k in {0.5e6: 4, 1.0e6: 6, 1.5e6: 8}.items():
-        mesh = menger_sponge(2, k, edge=10.0)
-        M = P.Mesh.from_inputs(mesh)
-        k0, k1, rho = wavenumber("water", f, 1e-3), wavenumber("bone", f, 1e-3), density_ratio("bone")
-        row = {"f_MHz": f / 1e6, "n_vertices": mesh.n_vertices}
-        for name, form, interior in forms:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, info, rc = P.pmchwt_solve(M, k0, k1, rho, [[1.0, 0.0, 0.0]], 1e-7,
-                                         precision="fp32", path=1, formulation=form,
-                                         osrc_interior=interior, maxiter=2000)
-            torch.cuda.synchronize()
-            row[name] = {"iterations": info[0]["iterations"], "outer_steps": info[0]["outer_steps"],
-                         "seconds": time.perf_counter() - t0, "rc": rc,
+    fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def osrc_measure(P, M, k, n_p, theta=np.pi / 3, R=None):
+    """OSRC apply (strong form, Sec. 2.6-2.7) at the solver's damped
+    wavenumber k_eps = k (1 + 0.4 i (k R)^(-2/3)), R = 0.1 (object radius 1),
+    on one and eight vectors: ms per apply, the algorithmic bytes of
+    bem_osrc_info and the implied GB/s."""
+    import torch
+    from bem_inputs import complex_normal
+    N = M.n_vertices
+    R = R if R is not None else 0.1
+    k = complex(k)
+    keps = k * (1.0 + 0.4j * (k * R) ** (-2.0 / 3.0))
+    info = P.osrc_info(M, n_p, theta, k, keps)
+    out = {"k": [complex(k).real, complex(k).imag], "k_eps": [keps.real, keps.imag],
+           "pade_terms": n_p, "theta": theta, "info": info}
+    for r in (1, 8):
+        x = torch.from_numpy(complex_normal(r * 2 * N, seed=11).reshape(r, 2 * N)).cuda()
+        y = torch.empty_like(x)
+        ms = event_ms(lambda: P.osrc_apply(M, n_p, theta, k, keps, x, y), 20)
+        byt = info["bytes_per_apply"] * r
+        out[f"vectors_{r}"] = {"ms": ms, "ms_per_vector": ms / r,
+                               "algorithmic_GB_per_s": byt / (ms * 1e-3) / 1e9,
+                               "frac_of_hbm": byt / (ms * 1e-3) / 1e9 / 8000.0}
+    return out
+
+
+def c1_leg(P, RL, cpu: bool) -> dict:
+    """Plain method at the smallest workload: unit sphere as icosphere level 3
+    (642 vertices), k_ext = 2, k_int = 3, rho = 1.5, plane wave along +z,
+    FP64 GMRES to 1e-8 on the matrix-free path and its far field against the
+    Mie series (181 polar angles).  With cpu: the oracle's full solve (dense
+    complex128 assembly, sparse LU OSRC, GMRES) timed on the host cores."""
+    import torch
+    from bem_inputs import complex_normal, icosphere
+    mesh = icosphere(3)
+    N, T = mesh.n_vertices, mesh.n_triangles
+    M = P.Mesh.from_inputs(mesh)
+    x = torch.from_numpy(complex_normal(2 * N, seed=0)).cuda()
+    y = torch.empty_like(x)
+    out = {"workload": "icosphere L3 unit sphere (642 vertices), k_ext=2, k_int=3, rho=1.5",
+           "n_vertices": N, "n_triangles": T}
+    for prec in ("fp32", "fp64"):
+        ms = event_ms(lambda: P.pmchwt_matvec(M, 2.0, 3.0, 1.5, x, y, precision=prec), 20)
+        out[f"{prec}_matvec"] = {"ms": ms, "tri_pair_evals_per_s": T * (T - 1) / (ms * 1e-3)}
+    P.pmchwt_solve(M, 2.0, 3.0, 1.5, [[0, 0, 1]], 1e-8, precision="fp64", path=0, maxiter=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sol, info, rc = P.pmchwt_solve(M, 2.0, 3.0, 1.5, [[0, 0, 1]], 1e-8, precision="fp64", path=0)
+    torch.cuda.synchronize()
+    out["fp64_solve"] = {"seconds": time.perf_counter() - t0, "rc": rc,
+                         "iterations": info[0]["iterations"],
                          "rel_residual": info[0]["rel_residual"]}
-            print(f"sponge {f / 1e6} MHz {name}: {row[name]}", file=sys.stderr, flush=True)
-        out.append(row)
-        del M
-        P.tune_clear()
-    return {"sponge_sweep": out}
+    from oracle import mie
+    th = np.linspace(0.0, np.pi, 181)
+    dirs = np.stack([np.sin(th), 0 * th, np.cos(th)], 1)
+    F = P.far_field(M, 2.0, sol[0].contiguous(), dirs)
+    Fm = mie.far_field(2.0, 3.0, 1.5, th)
+    out["fp64_solve"]["far_field_rel_error_vs_mie"] = float(np.linalg.norm(F - Fm) /
+                                                            np.linalg.norm(Fm))
+    if cpu:
+        from oracle import operators as O
+        from oracle.solve import PreconditionedSystem
+        t0 = time.perf_counter()
+        S = PreconditionedSystem(mesh, 2.0, 3.0, 1.5)
+        t1 = time.perf_counter()
+        xo, it, hist = S.solve([0.0, 0.0, 1.0], tol=1e-8)
+        t2 = time.perf_counter()
+        out["oracle_solve"] = {"kind": "oracle", "assembly_and_factor_s": t1 - t0,
+                               "gmres_s": t2 - t1, "seconds": t2 - t0, "iterations": it,
+                               "cores": int(O._load().oracle_num_threads()),
+                               "solution_rel_diff_gpu": float(
+                                   np.linalg.norm(sol[0].cpu().numpy() - xo) / np.linalg.norm(xo))}
+        out["gpu_speedup_vs_oracle_solve"] = out["oracle_solve"]["seconds"] / out["fp64_solve"]["seconds"]
+    del M
+    return out
 
 
-def serving_measure(P, n_requests: int, workers: int = 4, seed: int = 5) -> dict:
+def c2_oracle_extrapolation(mesh, cpu_rows: dict, iterations: int) -> dict:
+    """The oracle's full C2 solve, extrapolated (labelled as such): its far
+    field rows on a sample of test triangles (the cpu_baseline sample) scaled
+    to all triangles stand for the dense assembly (the same integrals), a
+    complex128 dense matvec timed at 4096 x 4096 and scaled by (2N / 4096)^2
+    (memory bound), and the oracle OSRC apply and mass solves timed at full
+    size; GMRES iterations are those of the GPU's FP64 solve of the same
+    system (the two agree within 2 at every size the tests run)."""
+    from oracle.solve import PreconditionedSystem
+    N, T = mesh.n_vertices, mesh.n_triangles
+    n_test = cpu_rows["n_test"]
+    assembly_s = cpu_rows["seconds"] * T / n_test
+    rng = np.random.default_rng(0)
+    m = 4096
+    A = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    v = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    A @ v
+    t0 = time.perf_counter()
+    for _ in range(5):
+        A @ v
+    dense_s = (time.perf_counter() - t0) / 5 * (2 * N / m) ** 2
+    del A
+    t0 = time.perf_counter()
+    S = PreconditionedSystem(mesh, K_EXT, K_INT, RHO, B=np.zeros((1, 1), np.complex128))
+    osrc_setup_s = time.perf_counter() - t0
+    y = rng.standard_normal(2 * N) + 1j * rng.standard_normal(2 * N)
+    S.osrc.apply(S.strong(y))
+    t0 = time.perf_counter()
+    for _ in range(3):
+        S.osrc.apply(S.strong(y))
+    osrc_s = (time.perf_counter() - t0) / 3
+    total = assembly_s + osrc_setup_s + iterations * (dense_s + osrc_s)
+    return {"kind": "oracle", "extrapolated": True, "seconds": total,
+            "assembly_s": assembly_s, "osrc_setup_s": osrc_setup_s,
+            "dense_matvec_s": dense_s, "osrc_apply_s": osrc_s, "iterations": iterations,
+            "method": "assembly = oracle far-field rows of the sampled test triangles x "
+                      f"{T}/{n_test}; dense c128 matvec timed at 4096^2 x (2N/4096)^2; OSRC "
+                      "apply and mass solves timed at full size; iterations of the GPU FP64 "
+                      "solve at tol 1e-6"}
+
+
+def c3_leg(P, RL, rates, steps: int) -> dict:
+    """Precision form: ellipsoid with semi-axes (1, 0.6, 0.4) from an
+    icosphere of level 6 (40 962 vertices, 81 920 triangles; max edge about
+    lambda_int / 8), k_ext = 20, k_int = 30 + 1.5i (lossy interior), rho = 1.9,
+    OSRC with 8 Pade terms.  FP32 and FP64 matrix-free matvecs (tri-pair
+    evals/s, kernel roofline of the complex-k_int variant), the OSRC apply,
+    FP64 GMRES against FP32 + FP64 true-residual refinement to 1e-6 on the
+    matrix-free path, and the compressed operator (H-matrix, ACA 1e-5):
+    set-up, memory, ms per product and its error against the FP64 product."""
+    import torch
+    from bem_inputs import complex_normal, ellipsoid, icosphere
+    mesh = ellipsoid(icosphere(6))
+    N, T = mesh.n_vertices, mesh.n_triangles
+    k0, k1, rho, n_p = 20.0, 30.0 + 1.5j, 1.9, 8
+    M = P.Mesh.from_inputs(mesh)
+    x = torch.from_numpy(complex_normal(2 * N, seed=0)).cuda()
+    y = torch.empty_like(x)
+    out = {"workload": "ellipsoid (1, 0.6, 0.4) from icosphere L6 (40962 vertices), "
+                       "k_ext=20, k_int=30+1.5i, rho=1.9, 8 Pade terms",
+           "n_vertices": N, "n_triangles": T}
+    progress("C3 matvecs")
+    P.pmchwt_matvec(M, k0, k1, rho, x, y, precision="fp32")   # near field built here
+    torch.cuda.synchronize()
+    pairs = RL.far_pairs_per_matvec(mesh.triangles)
+    symmetric = P.tune_get("farfield.symmetric") == 1
+    for prec, reps in (("fp32", steps), ("fp64", 2)):
+        P.profile_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            P.pmchwt_matvec(M, k0, k1, rho, x, y, precision=prec)
+        torch.cuda.synchronize()
+        step = (time.perf_counter() - t0) / reps
+        kms, kn = P.profile_read(f"farfield_{prec}")
+        P.profile_enable(False)
+        kern = kms / max(kn, 1)
+        roof = (RL.pair_kernel_roofline(pairs, kern * 1e-3, "fp32", rates, symmetric=symmetric,
+                                        lossy=True) if prec == "fp32"
+                else RL.pair_kernel_roofline(pairs, kern * 1e-3, "fp64"))
+        out[f"{prec}_matvec"] = {"ms_per_step": step * 1e3, "kernel_ms": kern,
+                                 "tri_pair_evals_per_s": T * (T - 1) / step, "roofline": roof}
+    y64 = P.pmchwt_matvec(M, k0, k1, rho, x, precision="fp64")
+    y32 = P.pmchwt_matvec(M, k0, k1, rho, x, precision="fp32")
+    out["fp32_matvec"]["rel_error_vs_fp64"] = float(torch.linalg.norm(y32 - y64) /
+                                                    torch.linalg.norm(y64))
+    progress("C3 OSRC")
+    out["osrc"] = osrc_measure(P, M, k1, n_p)
+    progress("C3 solves")
+    P.pmchwt_solve(M, k0, k1, rho, [[0, 0, 1]], 1e-6, precision="fp64", path=0, maxiter=1,
+                   pade_terms=n_p)
+    solves = {}
+    for name, prec in (("fp32", "fp32"), ("fp64", "fp64")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info, rc = P.pmchwt_solve(M, k0, k1, rho, [[0, 0, 1]], 1e-6, precision=prec, path=0,
+                                     pade_terms=n_p)
+        torch.cuda.synchronize()
+        solves[name] = {**info[0], "seconds": time.perf_counter() - t0, "rc": rc}
+        progress(f"C3 solve {name}: {solves[name]['seconds']:.2f} s, "
+                 f"{solves[name]['iterations']} iterations")
+    solves["speedup_fp32_refine_vs_fp64"] = solves["fp64"]["seconds"] / solves["fp32"]["seconds"]
+    out["solve"] = solves
+    progress("C3 compressed operator")
+    out["compressed"] = hmat_measure(P, M, k0, k1, rho, x, y64)
+    del M
+    return out
+
+
+def hmat_measure(P, M, k0, k1, rho, x, y_ref=None) -> dict:
+    """Compressed operator (precision fp32_hmat): first call (tree, ACA, dense
+    leaves), device bytes, ms per product (HIP events) and, given an FP64
+    product of x, the relative error per block row."""
+    import torch
+    N = M.n_vertices
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    y = P.pmchwt_matvec(M, k0, k1, rho, x, precision="fp32_hmat")
+    torch.cuda.synchronize()
+    first = time.perf_counter() - t0
+    st = P.hmat_info(M, k0, k1, rho)
+    ms = event_ms(lambda: P.pmchwt_matvec(M, k0, k1, rho, x, y, precision="fp32_hmat"), 5)
+    out = {"first_call_s": first, "ms_per_product": ms, "bytes": st["bytes"],
+           "dense_complex64_bytes": 32 * N * N, "stats": st}
+    if y_ref is not None:
+        out["rel_error_vs_fp64"] = [
+            float(torch.linalg.norm(y[..., sl] - y_ref[..., sl]) / torch.linalg.norm(y_ref[..., sl]))
+            for sl in (slice(0, N), slice(N, 2 * N))]
+    return out
+
+
+def compression_large(P) -> dict:
+    """Compressed operator at about 1e5 vertices: geodesic sphere of
+    frequency 100 (100 002 vertices, 200 000 triangles), k_ext = 10,
+    k_int = 15, rho = 1.5; against one FP32 matrix-free product (the dense
+    complex64 operator, 320 GB, does not fit)."""
+    import torch
+    from bem_inputs import complex_normal, geodesic_sphere
+    mesh = geodesic_sphere(100)
+    N = mesh.n_vertices
+    M = P.Mesh.from_inputs(mesh)
+    x = torch.from_numpy(complex_normal(2 * N, seed=0)).cuda()
+    progress("1e5-vertex sphere: compressed operator")
+    out = {"workload": "geodesic sphere f=100 (100002 vertices, 200000 triangles), "
+                       "k_ext=10, k_int=15, rho=1.5", "n_vertices": N,
+           "n_triangles": mesh.n_triangles}
+    out.update(hmat_measure(P, M, 10.0, 15.0, 1.5, x))
+    progress("1e5-vertex sphere: matrix-free FP32 product")
+    y = P.pmchwt_matvec(M, 10.0, 15.0, 1.5, x, precision="fp32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    y = P.pmchwt_matvec(M, 10.0, 15.0, 1.5, x, y, precision="fp32")
+    torch.cuda.synchronize()
+    out["matrix_free_fp32_ms"] = (time.perf_counter() - t0) * 1e3
+    yh = P.pmchwt_matvec(M, 10.0, 15.0, 1.5, x, precision="fp32_hmat")
+    out["rel_diff_vs_matrix_free_fp32"] = [
+        float(torch.linalg.norm(yh[..., sl] - y[..., sl]) / torch.linalg.norm(y[..., sl]))
+        for sl in (slice(0, N), slice(N, 2 * N))]
+    del M
+    return out
+
+
+def serving_measure(P, n_requests: int, workers: int = 8, seed: int = 5) -> dict:
     """Serving mix: meshes {icosphere L3, L4, L5, ellipsoid (geodesic 45
     scaled by (1, 0.6, 0.4)), two level-4 spheres}, k_ext ~ U[1, 20],
     k_int/k_ext ~ U[1.3, 1.9], rho ~ U[1.2, 2.0], 1-8 plane waves, tol 1e-6,
-    FP32 + refinement, auto path (seeded stream, seed 5).  A prefix of the
-    stream submitted at once gives the saturated solves/s; the whole stream
-    then arrives as a Poisson process at 0.7 x that rate."""
+    FP32 + refinement, auto path (seeded stream, seed 5), a server of
+    `workers` concurrent requests.  Every 4th request of the stream submitted
+    at once gives the saturated solves/s; the whole stream then arrives as a
+    Poisson process at 0.7 x that rate."""
     from bem_inputs import ellipsoid, geodesic_sphere, icosphere, request_stream, two_spheres
     meshes = {"ico3": icosphere(3), "ico4": icosphere(4), "ico5": icosphere(5),
               "ellipsoid45": ellipsoid(geodesic_sphere(45)),
@@ -313,11 +481,15 @@ def serving_measure(P, n_requests: int, workers: int = 4, seed: int = 5) -> dict
     def progress(msg):
         print(f"serving: {msg}", file=sys.stderr, flush=True)
 
-    n_sat = max(8, n_requests // 4)
+    # saturated throughput: every 4th request of the stream (a sample with
+    # the stream's mix) submitted at once
+    sample = reqs[::4] if n_requests >= 32 else reqs
+    n_sat = len(sample)
     t0 = time.perf_counter()
-    for i, rid in enumerate([submit(r) for r in reqs[:n_sat]]):
+    for i, rid in enumerate([submit(r) for r in sample]):
         srv.wait(rid)
-        progress(f"saturated phase {i + 1}/{n_sat} done")
+        if (i + 1) % 8 == 0:
+            progress(f"saturated phase {i + 1}/{n_sat} done")
     sat = n_sat / (time.perf_counter() - t0)
     print(f"serving: saturated {sat:.2f} solves/s over {n_sat} requests", file=sys.stderr,
           flush=True)
@@ -352,7 +524,7 @@ def serving_measure(P, n_requests: int, workers: int = 4, seed: int = 5) -> dict
         e["paths"].add(st["path"])
     return {
         "requests": n_requests, "workers": workers, "seed": seed,
-        "saturated_solves_per_s": sat, "saturated_prefix": n_sat,
+        "saturated_solves_per_s": sat, "saturated_sample": n_sat,
         "arrival_rate_per_s": lam, "solves_per_s": n_requests / elapsed,
         "waves_per_s": sum(len(r["directions"]) for r in reqs) / elapsed,
         "p50_latency_s": float(np.percentile(lat, 50)),
@@ -361,6 +533,7 @@ def serving_measure(P, n_requests: int, workers: int = 4, seed: int = 5) -> dict
         "mean_concurrency": busy / elapsed, "peak_inflight": stats["peak_inflight"],
         "peak_bytes": stats["peak_bytes"], "budget": stats["budget"],
         "evictions": stats["evictions"], "rejected": stats["rejected"],
+        "krylov_growth_bytes": stats["krylov_growth_bytes"],
         "failed_or_unconverged": len(bad),
         "per_mesh": {k: {"n": v["n"], "p50_latency_s": float(np.median(v["latency_s"])),
                          "paths": sorted(v["paths"])} for k, v in by_mesh.items()},
@@ -375,12 +548,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-batching", action="store_true")
-    ap.add_argument("--serving", type=int, default=32, metavar="N",
+    ap.add_argument("--no-c1", action="store_true", help="skip the icosphere L3 leg")
+    ap.add_argument("--no-c3", action="store_true", help="skip the lossy-ellipsoid leg")
+    ap.add_argument("--no-compression", action="store_true",
+                    help="skip the compressed operator at 1e5 vertices")
+    ap.add_argument("--no-multi", action="store_true", help="skip the four-sphere leg")
+    ap.add_argument("--serving", type=int, default=256, metavar="N",
                     help="requests of the serving mix to replay (0: skip)")
-    ap.add_argument("--frequency-sweep", action="store_true",
-                    help="only the iteration-count sweep over frequency (one JSON line)")
-    ap.add_argument("--sponge-sweep", action="store_true",
-                    help="only the Menger-sponge sweep over frequency (one JSON line)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB read + 256 MiB write elementwise kernel 3 times, "
                          "to scale HBM byte counters (FETCH_SIZE, WRITE_SIZE)")
@@ -394,13 +568,6 @@ def main():
     import paper_2104_04609_amd as P
     from paper_2104_04609_amd import roofline as RL
     from bem_inputs import complex_normal, icosphere
-
-    if args.frequency_sweep:
-        print(json.dumps(frequency_sweep(P)), flush=True)
-        return
-    if args.sponge_sweep:
-        print(json.dumps(sponge_sweep(P)), flush=True)
-        return
 
     mesh = icosphere(5)
     N, T = mesh.n_vertices, mesh.n_triangles
@@ -429,6 +596,7 @@ def main():
         P.profile_enable(False)
         return dt / steps, ms_k / max(n_k, 1)
 
+    progress("C2 timed matvec steps")
     step_s, kern_ms = timed("fp32", args.steps, args.warmup)
     step64_s, kern64_ms = timed("fp64", max(3, args.steps // 4), 1)
 
@@ -453,6 +621,7 @@ def main():
 
     solve = None
     if not args.no_solve:
+        progress("C2 solves")
         try:
             solve = {}
             # near-field and OSRC factors are built once per handle: warm them so
@@ -558,15 +727,38 @@ def main():
         except P.BemError as e:
             solve = {"error": str(e)}
 
+    progress("C2 OSRC apply")
+    osrc = osrc_measure(P, M, K_INT, 4)
+
     multi = None
-    if not args.no_solve:
+    if not args.no_solve and not args.no_multi:
+        progress("four spheres")
         multi = multi_material_measure(P, RL)
 
     batching = None
     if not args.no_batching:
+        progress("batching")
         batching = batch_measure(P, M, mesh, step_s)
+    del M
 
-    serving = serving_measure(P, args.serving) if args.serving > 0 else None
+    c1 = None
+    if not args.no_c1:
+        progress("C1")
+        c1 = c1_leg(P, RL, cpu=not args.no_cpu_baseline)
+
+    c3 = None
+    if not args.no_c3:
+        progress("C3")
+        c3 = c3_leg(P, RL, rates, max(3, args.steps // 4))
+
+    large = None
+    if not args.no_compression:
+        large = compression_large(P)
+
+    serving = None
+    if args.serving > 0:
+        progress("serving")
+        serving = serving_measure(P, args.serving)
 
     out = {
         "metric": METRIC, "value": value, "unit": "tri-pair evals/s", "n_gpus": 1,
@@ -587,12 +779,23 @@ def main():
                         "kernel_ms": kern64_ms, "roofline_frac": roof64["frac"]},
         "setup_s": setup_s,
         "solve": solve,
+        "osrc": osrc,
         "multi_material": multi,
         "batching": batching,
+        "c1": c1,
+        "c3": c3,
+        "compression_1e5": large,
         "serving": serving,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(mesh)
+        progress("oracle baselines")
+        cb = cpu_baseline(mesh)
+        out["cpu_baseline"] = cb
+        if solve and "fp64" in solve:
+            ext = c2_oracle_extrapolation(mesh, cb, solve["fp64"]["iterations"])
+            ext["gpu_speedup_fp64"] = ext["seconds"] / solve["fp64"]["seconds"]
+            ext["gpu_speedup_fp32_refine"] = ext["seconds"] / solve["fp32"]["seconds"]
+            out["oracle_c2_solve"] = ext
     print(json.dumps(out))
 
 

@@ -168,6 +168,34 @@ int osrc_apply(const bem_mesh *mesh, int pade_terms, double theta,
                int n_rhs, void *hip_stream);
 
 /*
+ * Sizes of the OSRC factors for (pade_terms, theta, k, k_eps) on this mesh
+ * (created and cached as by osrc_apply when absent) and the algorithmic
+ * device bytes of one single-vector osrc_apply (Sec. 2.7: N_p + 2 factorised
+ * systems sharing one sparsity pattern; an apply makes 2 N_p + 2 block
+ * solves, three P1 mass products and two Pade sums).  Each block solve
+ * streams the entries of L outside the diagonal dissection blocks by rows and
+ * by columns (16-byte values, 4-byte indices), the inverses of the diagonal
+ * blocks of L and L^T, D^{-1}, and reads and writes one vector.
+ * Errors: as osrc_apply; BEM_E_INVAL if out is NULL.
+ */
+typedef struct {
+    int64_t n_vertices;
+    int32_t pade_terms;
+    int32_t n_factors;        /* pade_terms + 2 */
+    int32_t solves_per_apply; /* 2 pade_terms + 2 */
+    int32_t reserved0;
+    int64_t nnz_l;            /* strict lower entries of L (one factor) */
+    int64_t nnz_offblock;     /* of those, outside the diagonal dissection blocks */
+    int64_t dense_entries;    /* entries of the dense diagonal-block inverses (one factor) */
+    int64_t mass_nnz;         /* entries of the P1 mass matrix */
+    int64_t factor_bytes;     /* device bytes of all numeric factors */
+    int64_t bytes_per_apply;  /* algorithmic bytes of one single-vector apply */
+} bem_osrc_stats;
+int bem_osrc_info(const bem_mesh *mesh, int pade_terms, double theta,
+                  bem_c64 k, bem_c64 k_eps, bem_osrc_stats *out,
+                  void *hip_stream);
+
+/*
  * osrc_apply without device allocation, for callers that cannot allocate:
  * code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc.  Same operation, arguments, layouts and results as osrc_apply.
@@ -274,7 +302,8 @@ void bem_solve_opts_default(bem_solve_opts *opts);
  * precision BEM_FP32: iterative refinement, outer residual with the FP64
  * operator (later ones updated with FP32 products of the corrections, see
  * "solve.refine_update"), inner GMRES on the operator with the FP32 pair
- * kernel.
+ * kernel, or on the assembled complex64 operator (path 1; see
+ * "solve.residual_dense_gib" for how its FP64 residuals are formed).
  *   directions  host [n_waves][3];  solution  device [n_waves][2N]
  *   info        host [n_waves] or NULL
  * Returns BEM_W_NOT_CONVERGED (best iterate written) if maxiter is reached.
@@ -339,20 +368,29 @@ int bem_far_field(const bem_mesh *mesh, bem_c64 k_ext, const bem_c64 *solution,
  * Serving loop: a queue of solve requests run by a pool of worker threads,
  * each with its own HIP stream, so that the work of several requests overlaps
  * on the device.  Requests name a mesh registered with the server; each mesh
- * keeps up to max_replicas device-resident handles, whose near-field, OSRC
- * and dense-operator caches stay resident between requests.  A handle serves
- * one request at a time.
+ * keeps up to max_replicas device-resident handles, whose near-field and OSRC
+ * caches stay resident between requests; the handles of a mesh share its
+ * assembled operators (one assembly per wavenumbers and materials, awaited by
+ * a replica that needs one another replica is assembling; besides the ones
+ * running requests use, the most recent one is kept).  A handle serves one
+ * request at a time.
  *
  * Admission: a request starts when a worker and a handle of its mesh are free
  * and its device-memory footprint (an upper bound of what the solve
- * allocates: near field, OSRC factors, scratch, Krylov basis for maxiter
- * iterations, the dense operator on the assembled path) fits in the budget
- * beside the resident state of all handles and the footprints of running
- * requests.  When it does not fit, cached state of idle handles is released,
- * least recently used first.  A request that cannot fit even on an idle
- * server completes with status BEM_E_NOMEM.  Waiting requests are admitted in
- * arrival order, except that a request that fits may pass one that does not
- * while the latter has waited less than 2 s.
+ * allocates: near field, OSRC factors, scratch, the initial Krylov basis of 65
+ * vectors per wave, the dense operator on the assembled path) fits in the
+ * budget beside the resident state of all handles and the footprints of
+ * running requests.  A running request's Krylov basis doubles as it fills;
+ * each growth is added to its reservation as it happens, releasing cached
+ * state if needed, and runs on even when the budget is exceeded (at most
+ * maxiter + 1 vectors per wave).  When a request does not fit, cached state
+ * is released, least recently used first: assembled operators no request
+ * holds, then the caches of idle handles.  A request that cannot fit even on an idle
+ * server completes with status BEM_E_NOMEM.  Waiting requests are admitted
+ * smallest estimated work first (triangle pairs of the assembly or of the
+ * matrix-free products, operator entries read by the iterations), except that
+ * requests that have waited 2 s go first in arrival order, and once the
+ * oldest has waited 10 s no other request starts while it does not fit.
  *
  * Path: opts.path 2 (auto) becomes the assembled path when the dense
  * operator (complex64 for FP32, complex128 for FP64) is at most
@@ -387,7 +425,10 @@ typedef struct {
     int64_t peak_bytes;      /* max over time of resident + reserved */
     int inflight, peak_inflight, queued;
     int64_t completed, rejected;
-    int64_t evictions;       /* idle handles whose cached state was released */
+    int64_t evictions;       /* cached states released: idle handles' caches and
+                                assembled operators no request held */
+    int64_t krylov_growth_bytes; /* Krylov-basis growth reported by running
+                                    requests beyond their footprints (total) */
 } bem_server_stats;
 
 void bem_server_opts_default(bem_server_opts *opts);
@@ -461,6 +502,14 @@ int bem_profile_read(const char *kernel, double *total_ms, int64_t *launches);
  *                         (formed in FP64 again before the carried bound
  *                         reaches tol / 10); 0 forms every outer residual with
  *                         the FP64 operator (default 1)
+ *   "solve.residual_dense_gib" assembled FP32 path (path 1, precision
+ *                         BEM_FP32): when the complex128 operator is at most
+ *                         this many GiB, the operator is assembled once in
+ *                         FP64, the inner solves use its rounding to
+ *                         complex64 and the FP64 residuals the complex128
+ *                         operator; else the complex64 operator is assembled
+ *                         in FP32 and the FP64 residuals are matrix-free.
+ *                         0..1024, 0 disables (default 32)
  *   "hmat.leaf"           compressed operator: vertices per leaf cluster,
  *                         8..64 (default 64)
  *   "hmat.eta_pct"        admissibility parameter eta in percent (default

@@ -82,6 +82,18 @@ class HMatStats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class OsrcStats(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int64), ("pade_terms", ctypes.c_int32),
+                ("n_factors", ctypes.c_int32), ("solves_per_apply", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("nnz_l", ctypes.c_int64),
+                ("nnz_offblock", ctypes.c_int64), ("dense_entries", ctypes.c_int64),
+                ("mass_nnz", ctypes.c_int64), ("factor_bytes", ctypes.c_int64),
+                ("bytes_per_apply", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved0"}
+
+
 class ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_int64), ("workers", ctypes.c_int),
                 ("max_replicas", ctypes.c_int), ("dense_max_bytes", ctypes.c_int64)]
@@ -101,7 +113,8 @@ class ServerStats(ctypes.Structure):
                 ("reserved_bytes", ctypes.c_int64), ("peak_bytes", ctypes.c_int64),
                 ("inflight", ctypes.c_int), ("peak_inflight", ctypes.c_int),
                 ("queued", ctypes.c_int), ("completed", ctypes.c_int64),
-                ("rejected", ctypes.c_int64), ("evictions", ctypes.c_int64)]
+                ("rejected", ctypes.c_int64), ("evictions", ctypes.c_int64),
+                ("krylov_growth_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -139,6 +152,8 @@ lib.bem_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double
 lib.bem_valu_rates.argtypes = [_vp, _vp]
 lib.bem_tune_set.argtypes = [ctypes.c_char_p, _i64]
 lib.bem_hmat_info.argtypes = [_vp, c64, c64, ctypes.c_double, ctypes.POINTER(HMatStats), _vp]
+lib.bem_osrc_info.argtypes = [_vp, ctypes.c_int, ctypes.c_double, c64, c64,
+                              ctypes.POINTER(OsrcStats), _vp]
 lib.bem_autotune.argtypes = [_vp, c64, c64, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                              ctypes.POINTER(TuneEntry), _vp]
 lib.bem_tune_cache_load.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]
@@ -306,6 +321,15 @@ def osrc_apply(mesh: Mesh, pade_terms: int, theta: float, k, k_eps, x, y=None,
     _check(lib.osrc_apply(mesh.handle, int(pade_terms), float(theta), _c(k), _c(k_eps),
                           _vp(x.data_ptr()), _vp(y.data_ptr()), n_rhs, _stream(stream)))
     return y
+
+
+def osrc_info(mesh: Mesh, pade_terms: int, theta: float, k, k_eps, stream=None) -> dict:
+    """bem_osrc_info: OSRC factor sizes and the algorithmic bytes of one
+    single-vector apply (factors created and cached when absent)."""
+    st = OsrcStats()
+    _check(lib.bem_osrc_info(mesh.handle, int(pade_terms), float(theta), _c(k), _c(k_eps),
+                             ctypes.byref(st), _stream(stream)))
+    return st.as_dict()
 
 
 def osrc_apply_noalloc(mesh: Mesh, pade_terms: int, theta: float, k, k_eps, x, y,

@@ -72,6 +72,8 @@ void mesh_trim(bem_mesh *m) {
     m->near_cache.clear();
     m->dense_cache.clear();
     m->dense64_cache.clear();
+    m->dense_rounded_cache.clear();
+    m->hmat_cache.clear();
     m->osrc_cache.clear();
     m->xs32.release();
     m->dyn64.release();
@@ -94,6 +96,7 @@ int64_t bem_mesh::device_bytes() const {
     for (const auto &kv : near_cache) b += kv.second->vals.bytes();
     for (const auto &kv : dense_cache) b += kv.second->B.bytes();
     for (const auto &kv : dense64_cache) b += kv.second->B64.bytes();
+    for (const auto &kv : dense_rounded_cache) b += kv.second->B.bytes();
     for (const auto &kv : hmat_cache) b += bem::hmat_bytes(*kv.second);
     b += xs32.bytes();
     for (const auto &kv : osrc_cache) b += bem::osrc_bytes(*kv.second);
@@ -277,6 +280,37 @@ int osrc_apply(const bem_mesh *mesh, int pade_terms, double theta, bem_c64 k,
     BEM_API_END
 }
 
+int bem_osrc_info(const bem_mesh *mesh, int pade_terms, double theta, bem_c64 k, bem_c64 k_eps,
+                  bem_osrc_stats *out, void *hip_stream) {
+    BEM_API_BEGIN
+    check_mesh(mesh);
+    if (pade_terms < 1 || pade_terms > 32) fail(BEM_E_INVAL, "pade_terms must be in 1..32");
+    if (!std::isfinite(theta)) fail(BEM_E_INVAL, "theta not finite");
+    if (!std::isfinite(k.re) || !std::isfinite(k.im) || (k.re == 0 && k.im == 0))
+        fail(BEM_E_INVAL, "k must be finite and nonzero");
+    if (!std::isfinite(k_eps.re) || !std::isfinite(k_eps.im) ||
+        (k_eps.re == 0 && k_eps.im == 0))
+        fail(BEM_E_INVAL, "k_eps must be finite and nonzero");
+    if (!out) fail(BEM_E_INVAL, "out is NULL");
+    bem_mesh *m = const_cast<bem_mesh *>(mesh);
+    std::vector<double2> keps(m->nobj, make_double2(k_eps.re, k_eps.im));
+    const bem::OsrcState &st = bem::osrc_get(m, pade_terms, theta, make_double2(k.re, k.im),
+                                             keps, (hipStream_t)hip_stream);
+    const bem::OsrcStats o = bem::osrc_stats(m, st);
+    out->n_vertices = o.n;
+    out->pade_terms = o.np;
+    out->n_factors = o.nfactors;
+    out->solves_per_apply = o.solves;
+    out->nnz_l = o.nnz_l;
+    out->nnz_offblock = o.nnz_ext;
+    out->dense_entries = o.ndense;
+    out->mass_nnz = o.mass_nnz;
+    out->factor_bytes = o.factor_bytes;
+    out->bytes_per_apply = o.bytes_per_apply;
+    return BEM_OK;
+    BEM_API_END
+}
+
 int pmchwt_rhs(const bem_mesh *mesh, bem_c64 k_ext, const double *directions, int n_waves,
                bem_c64 *f, void *hip_stream) {
     BEM_API_BEGIN
@@ -409,6 +443,9 @@ int bem_tune_set(const char *key, int64_t value) {
     } else if (k == "solve.refine_update") {
         if (value != 0 && value != 1) fail(BEM_E_INVAL, "solve.refine_update: 0 or 1");
         t.solve_refine_update = (int)value;
+    } else if (k == "solve.residual_dense_gib") {
+        if (value < 0 || value > 1024) fail(BEM_E_INVAL, "solve.residual_dense_gib: 0..1024");
+        t.solve_residual_dense_gib = (int)value;
     } else if (k == "hmat.leaf") {
         if (value < 8 || value > 64) fail(BEM_E_INVAL, "hmat.leaf: 8..64");
         t.hmat_leaf = (int)value;
@@ -448,6 +485,7 @@ int bem_tune_get(const char *key, int64_t *value) {
     else if (k == "dense.skinny_min_rhs") *value = t.dense_skinny_min_rhs;
     else if (k == "dense.gemm_min_rhs") *value = t.dense_gemm_min_rhs;
     else if (k == "solve.refine_update") *value = t.solve_refine_update;
+    else if (k == "solve.residual_dense_gib") *value = t.solve_residual_dense_gib;
     else if (k == "hmat.leaf") *value = t.hmat_leaf;
     else if (k == "hmat.eta_pct") *value = t.hmat_eta_pct;
     else if (k == "hmat.tol_ppb") *value = t.hmat_tol_ppb;

@@ -5,7 +5,10 @@
 
 #include <cstdint>
 #include <atomic>
+#include <condition_variable>
 #include <map>
+#include <mutex>
+#include <set>
 #include <memory>
 #include <string>
 #include <tuple>
@@ -141,6 +144,34 @@ struct DenseOperator {
     DevBuf<double2> B64;
 };
 
+// Assembled operators: complex64 from the FP32 assembly, complex128 from the
+// FP64 assembly, and complex64 rounded from the complex128 one (the assembled
+// FP32 path when its FP64 residuals use the complex128 operator).
+enum DenseKind { DENSE_C64 = 0, DENSE_C128 = 1, DENSE_C64_ROUNDED = 2 };
+
+// Assembled operators shared by the handles (replicas) of one mesh in the
+// serving loop: one assembly per (wavenumbers, materials, precision), reused
+// by every replica; beyond `keep`, operators that no request holds are
+// dropped, least recently used first.
+struct DenseShare {
+    using Key = std::pair<NearKey, int>;   // int: DenseKind
+    struct Entry {
+        std::shared_ptr<DenseOperator> op;
+        uint64_t last = 0;
+    };
+    std::mutex mu;
+    std::condition_variable cv;
+    std::map<Key, Entry> ops;
+    std::set<Key> building;   // assemblies in progress (other replicas wait)
+    int keep = 2;   // e.g. a complex128 operator and its rounded complex64 one
+    int64_t bytes();
+    int64_t idle_bytes();   // operators no request holds (the others are in footprints)
+    // Drops the least recently used operator that no request holds; returns
+    // its bytes (0: none) and its last-use stamp through *last.
+    int64_t evict_idle_lru();
+    uint64_t oldest_idle();   // last-use stamp of that operator (UINT64_MAX: none)
+};
+
 struct OsrcKey {
     int np;
     double theta, kr, ki;
@@ -157,6 +188,11 @@ struct OsrcDeleter {
     void operator()(OsrcState *p) const;   // osrc.cpp
 };
 int64_t osrc_bytes(const OsrcState &st);
+struct OsrcStats {
+    int64_t n, nnz_l, nnz_ext, ndense, mass_nnz, factor_bytes, bytes_per_apply;
+    int np, nfactors, solves;
+};
+OsrcStats osrc_stats(const bem_mesh *m, const OsrcState &st);
 struct HMatrix;   // hmat.hip
 struct HMatDeleter {
     void operator()(HMatrix *p) const;
@@ -209,7 +245,9 @@ struct bem_mesh {
     std::map<bem::NearKey, std::unique_ptr<bem::NearOperator>> near_cache;
     std::map<bem::NearKey, std::unique_ptr<bem::DenseOperator>> dense_cache;
     std::map<bem::NearKey, std::unique_ptr<bem::DenseOperator>> dense64_cache;   // complex128
+    std::map<bem::NearKey, std::unique_ptr<bem::DenseOperator>> dense_rounded_cache;   // of dense64
     std::map<bem::NearKey, std::unique_ptr<bem::HMatrix, bem::HMatDeleter>> hmat_cache;
+    std::shared_ptr<bem::DenseShare> dense_share;   // set for serving replicas
     bem::DevBuf<float2> xs32;          // complex64 copy of a matvec input
 
     // OSRC: P1 vertex graph, M and S values, factor state per parameter set
@@ -244,6 +282,7 @@ struct Tuning {
     std::atomic<int> dense_gemm_min_rhs{24};  // MFMA product from this many right-hand sides
     std::atomic<int> dense_skinny_min_rhs{24}; // skinny MFMA product from this many (else multi-GEMV)
     std::atomic<int> solve_refine_update{1};  // FP32 refinement: later residuals updated in FP32
+    std::atomic<int> solve_residual_dense_gib{32};   // complex128 operator for FP32-path residuals
     // compressed operator (read when one is built)
     std::atomic<int> hmat_leaf{64};           // vertices per leaf cluster (<= 64)
     std::atomic<int> hmat_eta_pct{100};       // admissibility max(diam) <= eta dist, percent
@@ -319,6 +358,14 @@ HMatrix &hmat_get(bem_mesh *m, double2 k0, double2 k1, double rho, hipStream_t s
 // dense.hip
 int64_t dense_bytes(const bem_mesh *m, bool fp64 = false);
 int64_t dense_assembly_scratch_bytes(const bem_mesh *m, bool fp64 = false);
+// The assembled operator of m from its DenseShare (assembled once by the
+// first replica that needs it; held while the returned pointer lives).
+std::shared_ptr<const DenseOperator> dense_share_get(bem_mesh *m, double2 k0, double2 k1,
+                                                     double rho, hipStream_t s, int s1,
+                                                     const ObjMaterials *om, int kind);
+// complex64 operator rounded from the complex128 one (both cached on m)
+const DenseOperator &dense_get_rounded(bem_mesh *m, double2 k0, double2 k1, double rho,
+                                       hipStream_t s, int s1, const ObjMaterials *om);
 std::unique_ptr<DenseOperator> dense_assemble(bem_mesh *m, const NearOperator &nf, double2 k0,
                                               double2 k1, double rho, hipStream_t s,
                                               bool fp64 = false);
@@ -408,6 +455,18 @@ void mesh_trim(bem_mesh *m);
 // build m->parts / m->part_vidx if not yet built (several objects)
 void mesh_parts(bem_mesh *m);
 // profiling (api.cpp)
+// Device memory a solve takes beyond its admission footprint (its Krylov
+// basis as it grows) is reported, while a ReserveScope is alive on the
+// thread, to its hook: the serving loop accounts it against its budget.
+using ReserveHook = void (*)(void *ctx, int64_t delta_bytes);
+struct ReserveScope {
+    ReserveScope(ReserveHook hook, void *ctx);
+    ~ReserveScope();
+    ReserveHook prev_hook;
+    void *prev_ctx;
+};
+void reserve_bytes(int64_t delta_bytes);
+
 // While one is alive on a thread, Timer records nothing (no HIP events are
 // created): for calls that must not allocate.
 struct NoTimerScope {

@@ -743,23 +743,30 @@ int64_t dense_assembly_scratch_bytes(const bem_mesh *m, bool fp64) {
            (2 * m->N + m->T) * (int64_t)sizeof(int32_t);   // vertex ranks, triangle order
 }
 
+void dense_assemble_into(bem_mesh *m, const NearOperator &nf, double2 k0, hipStream_t s,
+                         bool fp64, DenseOperator &op) {
+    const int64_t n2 = 2 * m->N;
+    op.n2 = n2;
+    op.T = m->T;
+    op.fp64 = fp64;
+    Timer tm(fp64 ? "dense_assemble_fp64" : "dense_assemble", s);
+    if (fp64) {
+        op.B.release();
+        if (op.B64.n != (size_t)(n2 * n2)) op.B64.alloc((size_t)(n2 * n2));
+        assemble_into<double>(m, nf, k0, op.B64.p, s);
+    } else {
+        op.B64.release();
+        if (op.B.n != (size_t)(n2 * n2)) op.B.alloc((size_t)(n2 * n2));
+        assemble_into<float>(m, nf, k0, op.B.p, s);
+    }
+}
+
 std::unique_ptr<DenseOperator> dense_assemble(bem_mesh *m, const NearOperator &nf, double2 k0,
                                               double2 k1, double rho, hipStream_t s, bool fp64) {
     (void)k1;
     (void)rho;
     auto op = std::make_unique<DenseOperator>();
-    const int64_t n2 = 2 * m->N;
-    op->n2 = n2;
-    op->T = m->T;
-    op->fp64 = fp64;
-    Timer tm(fp64 ? "dense_assemble_fp64" : "dense_assemble", s);
-    if (fp64) {
-        op->B64.alloc((size_t)(n2 * n2));
-        assemble_into<double>(m, nf, k0, op->B64.p, s);
-    } else {
-        op->B.alloc((size_t)(n2 * n2));
-        assemble_into<float>(m, nf, k0, op->B.p, s);
-    }
+    dense_assemble_into(m, nf, k0, s, fp64, *op);
     return op;
 }
 
@@ -873,6 +880,173 @@ void dense_gemm(const DenseOperator &op, const double2 *x, double2 *y, int R, hi
                        Yp.p, nchunks, M, Np, R, y);
     BEM_LAUNCH_CHECK();
     BEM_HIP(hipStreamSynchronize(s));   // Xp, Yp are released on return
+}
+
+namespace {
+std::atomic<uint64_t> g_share_tick{0};   // last-use stamps comparable across meshes
+}
+
+int64_t DenseShare::bytes() {
+    std::lock_guard<std::mutex> g(mu);
+    int64_t b = 0;
+    for (const auto &kv : ops) b += kv.second.op->B.bytes() + kv.second.op->B64.bytes();
+    return b;
+}
+
+int64_t DenseShare::idle_bytes() {
+    std::lock_guard<std::mutex> g(mu);
+    int64_t b = 0;
+    for (const auto &kv : ops)
+        if (kv.second.op.use_count() == 1) b += kv.second.op->B.bytes() + kv.second.op->B64.bytes();
+    return b;
+}
+
+uint64_t DenseShare::oldest_idle() {
+    std::lock_guard<std::mutex> g(mu);
+    uint64_t t = UINT64_MAX;
+    for (const auto &kv : ops)
+        if (kv.second.op.use_count() == 1) t = std::min(t, kv.second.last);
+    return t;
+}
+
+int64_t DenseShare::evict_idle_lru() {
+    std::shared_ptr<DenseOperator> drop;   // freed outside the lock
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto victim = ops.end();
+        for (auto it = ops.begin(); it != ops.end(); ++it)
+            if (it->second.op.use_count() == 1 &&
+                (victim == ops.end() || it->second.last < victim->second.last))
+                victim = it;
+        if (victim == ops.end()) return 0;
+        drop = std::move(victim->second.op);
+        ops.erase(victim);
+    }
+    return drop->B.bytes() + drop->B64.bytes();
+}
+
+namespace {
+
+__global__ __launch_bounds__(256) void dense_round_kernel(const double2 *__restrict__ a,
+                                                          float2 *__restrict__ b, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256)
+        b[i] = make_float2((float)a[i].x, (float)a[i].y);
+}
+
+// into `op` (its complex64 buffer reused when it has the size)
+void dense_round_into(const DenseOperator &d64, DenseOperator &o, hipStream_t s) {
+    DenseOperator *op = &o;
+    op->n2 = d64.n2;
+    op->T = d64.T;
+    op->fp64 = false;
+    op->B64.release();
+    const int64_t n = d64.n2 * d64.n2;
+    if (op->B.n != (size_t)n) op->B.alloc((size_t)n);
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(dense_round_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d64.B64.p,
+                       op->B.p, n);
+    BEM_LAUNCH_CHECK();
+}
+
+std::unique_ptr<DenseOperator> dense_round(const DenseOperator &d64, hipStream_t s) {
+    auto op = std::make_unique<DenseOperator>();
+    dense_round_into(d64, *op, s);
+    return op;
+}
+
+}   // namespace
+
+const DenseOperator &dense_get_rounded(bem_mesh *m, double2 k0, double2 k1, double rho,
+                                       hipStream_t s, int s1, const ObjMaterials *om) {
+    const NearKey key = near_key(m, k0, k1, rho, s1, om);
+    auto it = m->dense_rounded_cache.find(key);
+    if (it != m->dense_rounded_cache.end()) return *it->second;
+    const DenseOperator &d64 = dense_get(m, k0, k1, rho, s, s1, om, true);
+    if (!m->dense_rounded_cache.empty()) m->dense_rounded_cache.clear();   // one at a time
+    auto op = dense_round(d64, s);
+    auto &ref = *op;
+    m->dense_rounded_cache.emplace(key, std::move(op));
+    return ref;
+}
+
+std::shared_ptr<const DenseOperator> dense_share_get(bem_mesh *m, double2 k0, double2 k1,
+                                                     double rho, hipStream_t s, int s1,
+                                                     const ObjMaterials *om, int kind) {
+    DenseShare &sh = *m->dense_share;
+    const DenseShare::Key key{near_key(m, k0, k1, rho, s1, om), kind};
+    {
+        std::unique_lock<std::mutex> lk(sh.mu);
+        for (;;) {
+            auto it = sh.ops.find(key);
+            if (it != sh.ops.end()) {
+                it->second.last = ++g_share_tick;
+                return it->second.op;
+            }
+            if (!sh.building.count(key)) break;
+            sh.cv.wait(lk);   // another replica assembles it
+        }
+        sh.building.insert(key);
+    }
+    // an idle operator of the same kind that the `keep` rule would drop gives
+    // its buffer to the new one (no device free and allocation per new
+    // wavenumber)
+    std::shared_ptr<DenseOperator> op;
+    {
+        std::lock_guard<std::mutex> g(sh.mu);
+        int idle = 0;
+        auto victim = sh.ops.end();
+        for (auto it = sh.ops.begin(); it != sh.ops.end(); ++it)
+            if (it->second.op.use_count() == 1) {
+                idle++;
+                if (it->first.second == kind &&
+                    (victim == sh.ops.end() || it->second.last < victim->second.last))
+                    victim = it;
+            }
+        if (idle >= sh.keep && victim != sh.ops.end()) {
+            op = std::move(victim->second.op);
+            sh.ops.erase(victim);
+        }
+    }
+    try {
+        if (!op) op = std::make_shared<DenseOperator>();
+        if (kind == DENSE_C64_ROUNDED) {
+            // from the shared complex128 operator (held until rounded)
+            const auto d64 = dense_share_get(m, k0, k1, rho, s, s1, om, DENSE_C128);
+            dense_round_into(*d64, *op, s);
+            BEM_HIP(hipStreamSynchronize(s));
+        } else {
+            const NearOperator &nf = nearfield_get(m, k0, k1, rho, s, s1, om);
+            dense_assemble_into(m, nf, k0, s, kind == DENSE_C128, *op);
+        }
+    } catch (...) {
+        std::lock_guard<std::mutex> g(sh.mu);
+        sh.building.erase(key);
+        sh.cv.notify_all();
+        throw;
+    }
+    std::vector<std::shared_ptr<DenseOperator>> drop;   // freed outside the lock
+    {
+        std::lock_guard<std::mutex> g(sh.mu);
+        sh.building.erase(key);
+        sh.ops[key] = DenseShare::Entry{op, ++g_share_tick};
+        // keep at most `keep` operators beside those in use
+        for (;;) {
+            int idle = 0;
+            auto victim = sh.ops.end();
+            for (auto it = sh.ops.begin(); it != sh.ops.end(); ++it)
+                if (it->second.op.use_count() == 1) {   // the new one is held by `op`
+                    idle++;
+                    if (victim == sh.ops.end() || it->second.last < victim->second.last)
+                        victim = it;
+                }
+            if (idle < sh.keep || victim == sh.ops.end()) break;
+            drop.push_back(std::move(victim->second.op));
+            sh.ops.erase(victim);
+        }
+        sh.cv.notify_all();
+    }
+    return op;
 }
 
 const DenseOperator &dense_get(bem_mesh *m, double2 k0, double2 k1, double rho, hipStream_t s,

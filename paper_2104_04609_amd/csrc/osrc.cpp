@@ -56,6 +56,35 @@ void OsrcState::ensure_batch(int R) {
     batch = R;
 }
 int64_t osrc_bytes(const OsrcState &st) { return st.bytes(); }
+
+OsrcStats osrc_stats(const bem_mesh *m, const OsrcState &st) {
+    const OsrcSymbolicState &sy = *m->osrc_sym;
+    const LdlSymbolic &S = sy.sym;
+    OsrcStats o;
+    o.n = sy.n;
+    o.np = st.np;
+    o.nfactors = st.nfactors;
+    o.solves = 2 * st.np + 2;
+    o.nnz_l = S.nnzL();
+    o.nnz_ext = 0;
+    for (int j = 0; j < sy.n; j++) o.nnz_ext += (S.fext[j] - S.Rp[j]) + (S.Lp[j + 1] - S.bext[j]);
+    o.nnz_ext /= 2;   // forward and backward sweeps visit the same entries
+    o.ndense = S.ndense;
+    o.mass_nnz = (int64_t)sy.gcol.size();
+    o.factor_bytes = st.Dinv.bytes() + st.Lcsr.bytes() + st.Lcsc.bytes() + st.invL.bytes() +
+                     st.invLT.bytes();
+    // one single-vector apply: per block solve the off-block entries of L (rows)
+    // and L^T (columns) with their indices, both dense inverses, D^{-1}, the
+    // input and the output; three mass products (8-byte values, column
+    // indices, row pointers, input, output); two Pade sums (np + 1 inputs,
+    // one output)
+    const int64_t c16 = 16, n = o.n;
+    const int64_t per_solve = 2 * o.nnz_ext * (c16 + 4) + 2 * o.ndense * c16 + n * c16 + 2 * n * c16;
+    const int64_t spmv = o.mass_nnz * 12 + (n + 1) * 4 + 2 * n * c16;
+    const int64_t sums = (int64_t)(st.np + 2) * n * c16;
+    o.bytes_per_apply = o.solves * per_solve + 3 * spmv + 2 * sums;
+    return o;
+}
 int64_t osrc_sym_bytes(const OsrcSymbolicState &st) { return st.bytes(); }
 
 namespace {

@@ -21,7 +21,8 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-constexpr double HEAD_PRIORITY_S = 2.0;   // after this wait, the oldest request blocks others
+constexpr double AGED_S = 2.0;            // after this wait, requests go in arrival order
+constexpr double HEAD_BLOCK_S = 10.0;     // after this wait, the oldest request blocks others
 
 struct Replica {
     bem_mesh *h = nullptr;    // created lazily by the worker that first runs on it
@@ -31,6 +32,7 @@ struct Replica {
 };
 
 struct MeshEntry {
+    std::shared_ptr<DenseShare> share = std::make_shared<DenseShare>();   // assembled operators
     std::vector<double> P;
     std::vector<int32_t> tri, obj;
     bool has_obj = false;
@@ -52,6 +54,7 @@ struct Request {
     double2 *solution = nullptr;
     bem_solve_info *info = nullptr;
     int64_t footprint = 0;    // solve footprint (without creating a handle)
+    double work = 0;          // admission order: estimated device work
     int64_t reserved = 0;     // footprint + handle creation when admitted
     Replica *rep = nullptr;
     int replica = -1;
@@ -68,6 +71,7 @@ bem_mesh *create_handle(const MeshEntry &me) {
     mesh_build(m.get(), me.P.data(), me.nv, me.tri.data(), me.nt,
                me.has_obj ? me.obj.data() : nullptr);
     osrc_prepare(m.get());
+    m->dense_share = me.share;
     return m.release();
 }
 
@@ -92,20 +96,37 @@ struct bem_server {
     int64_t reserved = 0, peak = 0;
     int inflight = 0, peak_inflight = 0;
     int64_t completed = 0, rejected = 0, evictions = 0;
+    int64_t grown = 0;   // Krylov growth reported by running requests (bytes, total)
 
     double now() const {
         return std::chrono::duration<double>(bem::Clock::now() - t0).count();
     }
     int64_t resident() const {
         int64_t b = 0;
-        for (const auto &me : meshes)
+        for (const auto &me : meshes) {
             for (const auto &r : me->reps) b += r->resident;
+            b += me->share->idle_bytes();   // those in use are in running footprints
+        }
         return b;
     }
-    // Release cached state of idle handles, least recently used first, until
-    // `need` more bytes fit.  Returns whether they fit.
+    // Release cached state, least recently used first, until `need` more bytes
+    // fit: assembled operators no request holds, then the caches of idle
+    // handles.  Returns whether they fit.
     bool make_room(int64_t need) {
         while (resident() + reserved + need > o.hbm_budget) {
+            bem::DenseShare *oldest = nullptr;
+            uint64_t t_old = UINT64_MAX;
+            for (auto &me : meshes) {
+                const uint64_t t = me->share->oldest_idle();
+                if (t < t_old) {
+                    t_old = t;
+                    oldest = me->share.get();
+                }
+            }
+            if (oldest && oldest->evict_idle_lru() > 0) {
+                evictions++;
+                continue;
+            }
             bem::Replica *lru = nullptr;
             bem::MeshEntry *lru_mesh = nullptr;
             for (auto &me : meshes)
@@ -136,11 +157,24 @@ struct bem_server {
         cv_done.notify_all();
     }
     // Next admissible request (lock held), or null.  Rejects requests that
-    // can never fit.
+    // can never fit.  Order: requests that have waited more than AGED_S in
+    // arrival order, then the others smallest estimated work first; once the
+    // oldest has waited HEAD_BLOCK_S, no other starts while it does not fit.
     std::shared_ptr<bem::Request> admit() {
         const double t = now();
-        for (size_t qi = 0; qi < queue.size();) {
-            if (qi > 0 && t - queue.front()->t_submit > bem::HEAD_PRIORITY_S) break;
+        std::vector<size_t> order(queue.size());
+        for (size_t i = 0; i < order.size(); i++) order[i] = i;
+        const bool head_due = !queue.empty() && t - queue.front()->t_submit > bem::HEAD_BLOCK_S;
+        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+            const bool aa = t - queue[a]->t_submit > bem::AGED_S;
+            const bool ab = t - queue[b]->t_submit > bem::AGED_S;
+            if (aa != ab) return aa;
+            if (aa) return false;   // both aged: arrival order (stable)
+            return queue[a]->work < queue[b]->work;
+        });
+        for (size_t oi = 0; oi < order.size();) {
+            if (head_due && oi > 0) break;
+            const size_t qi = order[oi];
             auto r = queue[qi];
             bem::MeshEntry &me = *meshes[r->mesh];
             bem::Replica *pick = nullptr;
@@ -156,7 +190,7 @@ struct bem_server {
             }
             const bool grow = !pick && (int)me.reps.size() < o.max_replicas;
             if (!pick && !grow) {
-                qi++;
+                oi++;
                 continue;
             }
             const bool fresh = grow || !pick->h;
@@ -170,9 +204,9 @@ struct bem_server {
                     rejected++;
                     queue.erase(queue.begin() + (long)qi);
                     finish(r);
-                    continue;
+                    return admit();   // indices changed
                 }
-                qi++;
+                oi++;
                 continue;
             }
             if (grow) {
@@ -196,6 +230,24 @@ struct bem_server {
         return nullptr;
     }
 
+    // Growth of a running request's device memory (its Krylov basis) beyond
+    // its admission footprint: accounted, with room made from idle caches.
+    struct Growth {
+        bem_server *srv;
+        bem::Request *r;
+    };
+    static void grow_hook(void *ctx, int64_t delta) {
+        Growth *g = static_cast<Growth *>(ctx);
+        std::lock_guard<std::mutex> lk(g->srv->mu);
+        g->r->reserved += delta;
+        g->srv->reserved += delta;
+        if (delta > 0) {
+            g->srv->grown += delta;
+            (void)g->srv->make_room(0);   // over the budget: runs on (bounded by maxiter)
+            g->srv->peak = std::max(g->srv->peak, g->srv->resident() + g->srv->reserved);
+        }
+    }
+
     void worker(int wi) {
         (void)hipSetDevice(device);
         hipStream_t s = streams[wi];
@@ -213,6 +265,8 @@ struct bem_server {
             int64_t res = 0;
             try {
                 if (!rep->h) rep->h = bem::create_handle(me);
+                Growth g{this, r.get()};
+                const bem::ReserveScope grow(&bem_server::grow_hook, &g);
                 status = bem::solve_run(rep->h, r->k0, r->k1, r->rho, r->dirs.data(), r->n_waves,
                                         r->tol, r->o, r->solution, r->info, s,
                                         r->per_object ? &r->om : nullptr);
@@ -406,6 +460,12 @@ int server_submit(bem_server *srv, int mesh_id, bem_c64 k_ext, bem_c64 k_int, do
         BEM_HIP(hipGetDevice(&prev));
         BEM_HIP(hipSetDevice(srv->device));
         r->footprint = bem::solve_footprint(h0, r->k0, r->k1, rho, r->o, n_waves);
+        // triangle pairs (assembly or matrix-free products) and, on the
+        // assembled path, the operator entries each wave's iterations read
+        r->work = (double)h0->T * (double)h0->T *
+                  (r->o.path == 1 ? 1.0 : std::min(n_waves, 16) * 50.0) +
+                  (r->o.path == 1 ? 4.0 * (double)h0->N * (double)h0->N * n_waves * 50.0 / 64.0
+                                  : 0.0);
         (void)hipSetDevice(prev);
         prev = -1;
         {
@@ -499,6 +559,7 @@ int bem_server_stats_get(bem_server *srv, bem_server_stats *st) {
     st->completed = srv->completed;
     st->rejected = srv->rejected;
     st->evictions = srv->evictions;
+    st->krylov_growth_bytes = srv->grown;
     return BEM_OK;
 }
 

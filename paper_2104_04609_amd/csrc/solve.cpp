@@ -37,6 +37,22 @@
 
 namespace bem {
 
+static thread_local ReserveHook t_reserve_hook = nullptr;
+static thread_local void *t_reserve_ctx = nullptr;
+
+ReserveScope::ReserveScope(ReserveHook hook, void *ctx)
+    : prev_hook(t_reserve_hook), prev_ctx(t_reserve_ctx) {
+    t_reserve_hook = hook;
+    t_reserve_ctx = ctx;
+}
+ReserveScope::~ReserveScope() {
+    t_reserve_hook = prev_hook;
+    t_reserve_ctx = prev_ctx;
+}
+void reserve_bytes(int64_t delta) {
+    if (t_reserve_hook) t_reserve_hook(t_reserve_ctx, delta);
+}
+
 namespace {
 
 using cdd = std::complex<double>;
@@ -140,6 +156,10 @@ struct Op {
     }
 };
 
+// Initial Krylov basis capacity (vectors beyond v_0); the basis doubles as it
+// fills.
+constexpr int KRYLOV_CAP0 = 64;
+
 struct Workspace {
     int64_t n2 = 0;
     int cap = 0;               // basis vectors beyond v_0
@@ -147,16 +167,24 @@ struct Workspace {
     DevBuf<double2> h;         // [2 (cap + 1) + 1]
     void ensure(int need, hipStream_t s) {   // need = number of vectors
         if (need <= cap + 1) return;
-        int ncap = std::max(need - 1, std::max(2 * cap, 64));
+        int ncap = std::max(need - 1, std::max(2 * cap, KRYLOV_CAP0));
+        // growth beyond the initial capacity is reported (the new basis is
+        // held beside the old one while it is copied)
+        const int64_t vb = n2 * (int64_t)sizeof(double2);
+        if (V.p) reserve_bytes((int64_t)(ncap + 1) * vb);
         DevBuf<double2> nv((size_t)(ncap + 1) * n2);
         if (V.p) BEM_HIP(hipMemcpyAsync(nv.p, V.p, (size_t)(cap + 1) * n2 * sizeof(double2),
                                         hipMemcpyDeviceToDevice, s));
         BEM_HIP(hipStreamSynchronize(s));
+        const int64_t old = V.p ? (int64_t)(cap + 1) * vb : 0;
         V = std::move(nv);
+        if (old) reserve_bytes(-old);
         h.alloc(2 * (size_t)(ncap + 1) + 1);
         cap = ncap;
     }
 };
+
+
 
 // Squared norms of R vectors (stride n) into host nrm[R] (one sync).
 void dev_norms(const double2 *v, int64_t n, int R, double2 *dbuf, double *nrm, hipStream_t s) {
@@ -309,21 +337,6 @@ void gmres_batch(Op &op, int prec, const double2 *b, double2 *x, int R, int64_t 
     }
 }
 
-// Krylov basis capacity after growing to `need` vectors (Workspace::ensure).
-int64_t workspace_peak_vectors(int maxiter) {
-    int cap = 0;
-    int64_t peak = 0;
-    auto ensure = [&](int need) {
-        if (need <= cap + 1) return;
-        const int ncap = std::max(need - 1, std::max(2 * cap, 64));
-        peak = std::max<int64_t>(peak, (int64_t)(cap + 1) + (ncap + 1));   // old + new
-        cap = ncap;
-    };
-    ensure(2);
-    ensure(maxiter + 1);
-    return std::max<int64_t>(peak, cap + 1);
-}
-
 double2 damped(double2 k, double R) {
     // k_eps = k (1 + 0.4 i (k R)^{-2/3}), principal branch (Sec. 2.6)
     cdd kk(k.x, k.y);
@@ -366,6 +379,16 @@ void check_materials(const bem_mesh *m, const ObjMaterials &om) {
     }
 }
 
+// The assembled FP32 path takes its FP64 residuals with the complex128
+// operator (assembled once, the complex64 one rounded from it) when that
+// operator is at most "solve.residual_dense_gib" GiB; a rule on the mesh and
+// options alone, so that a result never depends on memory in use.
+static bool residual_dense(const bem_mesh *m, const bem_solve_opts &o) {
+    const int64_t lim = (int64_t)tuning().solve_residual_dense_gib.load() << 30;
+    return o.precision == BEM_FP32 && lim > 0 && dense_bytes(m, true) <= lim &&
+           (o.formulation != BEM_FORM_CALDERON || m->nobj == 1);
+}
+
 int64_t solve_footprint(bem_mesh *m, double2 k0, double2 k1, double rho,
                         const bem_solve_opts &o, int n_waves) {
     (void)rho;
@@ -373,15 +396,23 @@ int64_t solve_footprint(bem_mesh *m, double2 k0, double2 k1, double rho,
     const int G = std::min(n_waves, SOLVE_BATCH);
     int64_t b = 4 * m->nf_nnz * c16;                          // near-field CSR values
     b += osrc_state_bytes(m, o.pade_terms, G);                 // OSRC factors + batch buffers
-    int64_t scratch = farfield_scratch_bytes(m, BEM_FP64, k0, k1, G);
     const bool dense = o.precision == BEM_FP32 && o.path == 1;
+    const bool rdense = dense && residual_dense(m, o);
+    // the pair kernel's scratch unless every product is assembled
+    const bool matrix_free = !(o.path == 1 && (o.precision == BEM_FP64 || rdense));
+    if (matrix_free) {
+        b += farfield_scratch_bytes(m, BEM_FP64, k0, k1, G);
+        if (o.precision == BEM_FP32 && !dense)
+            b += farfield_scratch_bytes(m, BEM_FP32, k0, k1, G);   // dyn32 beside dyn64
+    }
     if (o.precision == BEM_FP64 && o.path == 1)
         b += dense_bytes(m, true) + dense_assembly_scratch_bytes(m, true);
-    if (o.precision == BEM_FP32 && !dense)
-        scratch += farfield_scratch_bytes(m, BEM_FP32, k0, k1, G);   // dyn32 beside dyn64
-    b += scratch;
-    if (dense) b += dense_bytes(m) + dense_assembly_scratch_bytes(m) + 2 * G * n2 * 8 +
-                    dense_gemm_scratch_bytes(m, G);
+    if (dense) b += 2 * G * n2 * 8 + dense_gemm_scratch_bytes(m, G);
+    if (rdense)   // complex128 operator beside its assembly scratch, then its rounding
+        b += dense_bytes(m, true) +
+             std::max(dense_assembly_scratch_bytes(m, true), dense_bytes(m));
+    else if (dense)
+        b += dense_bytes(m) + dense_assembly_scratch_bytes(m);
     b += ((int64_t)n_waves + 8 * (int64_t)G) * n2 * c16;      // f, B, X, R, D, T, yw, vin, vout
     if (o.formulation == BEM_FORM_CALDERON) {
         b += 2 * (int64_t)G * n2 * c16;                       // t1, t2
@@ -391,7 +422,8 @@ int64_t solve_footprint(bem_mesh *m, double2 k0, double2 k1, double rho,
                                                                       : 0);
     }
     else if (o.formulation != BEM_FORM_OSRC) b += (int64_t)G * n2 * c16;       // t1
-    b += G * (workspace_peak_vectors(o.maxiter) * n2 * c16 + (2 * (int64_t)o.maxiter + 8) * c16);
+    // the initial Krylov basis; its growth is reported through reserve_bytes
+    b += G * ((int64_t)(KRYLOV_CAP0 + 1) * n2 * c16 + (2 * (int64_t)o.maxiter + 8) * c16);
     return b;
 }
 
@@ -418,26 +450,54 @@ int solve_run(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dir
     op.form = o.formulation;
     op.om = om;
     int inner = BEM_FP32;
+    std::shared_ptr<const DenseOperator> dense_hold, dense_hold64;   // shared operators held
     if (o.path != 0) {
         const bool f64 = o.precision == BEM_FP64;
         bool use = o.path == 1;
         if (o.path == 2) {   // autotuned choice, else dense when it fits with room to spare
             size_t free_b = 0, total_b = 0;
             BEM_HIP(hipMemGetInfo(&free_b, &total_b));
-            int64_t need = f64 ? dense_bytes(m, true) + dense_assembly_scratch_bytes(m, true) +
-                                     (int64_t)(1ll << 30)
-                               : dense_bytes(m) + (int64_t)(2ll << 30);
+            const bool rd = residual_dense(m, o);
+            int64_t need = f64 || rd ? dense_bytes(m, true) + dense_assembly_scratch_bytes(m, true) +
+                                           (int64_t)(1ll << 30)
+                                     : (int64_t)(2ll << 30);
+            if (!f64) need += dense_bytes(m);
             // Calderon on several objects: each object's own operator as well
             if (o.formulation == BEM_FORM_CALDERON && m->nobj > 1) need += dense_bytes(m, f64) / m->nobj;
             const bool fits = need < (int64_t)free_b ||
-                              !(f64 ? m->dense64_cache.empty() : m->dense_cache.empty());
+                              !(f64  ? m->dense64_cache.empty()
+                                : rd ? m->dense_rounded_cache.empty()
+                                     : m->dense_cache.empty());
             TuneEntry te;
             use = fits && !(tune_find(m->T, std::min(n_waves, SOLVE_BATCH), &te) && te.path == 0);
         }
         if (use && f64) {
-            op.dense64 = &dense_get(m, k0, k1, rho, s, s1, om, true);
+            if (m->dense_share) {
+                dense_hold = dense_share_get(m, k0, k1, rho, s, s1, om, DENSE_C128);
+                op.dense64 = dense_hold.get();
+            } else {
+                op.dense64 = &dense_get(m, k0, k1, rho, s, s1, om, true);
+            }
+        } else if (use && residual_dense(m, o)) {
+            // FP32 form whose FP64 residuals use the complex128 operator: the
+            // complex64 one is its rounding (one FP64 assembly)
+            if (m->dense_share) {
+                dense_hold64 = dense_share_get(m, k0, k1, rho, s, s1, om, DENSE_C128);
+                dense_hold = dense_share_get(m, k0, k1, rho, s, s1, om, DENSE_C64_ROUNDED);
+                op.dense64 = dense_hold64.get();
+                op.dense = dense_hold.get();
+            } else {
+                op.dense64 = &dense_get(m, k0, k1, rho, s, s1, om, true);
+                op.dense = &dense_get_rounded(m, k0, k1, rho, s, s1, om);
+            }
+            inner = BEM_FP32_DENSE;
         } else if (use) {
-            op.dense = &dense_get(m, k0, k1, rho, s, s1, om);
+            if (m->dense_share) {
+                dense_hold = dense_share_get(m, k0, k1, rho, s, s1, om, DENSE_C64);
+                op.dense = dense_hold.get();
+            } else {
+                op.dense = &dense_get(m, k0, k1, rho, s, s1, om);
+            }
             inner = BEM_FP32_DENSE;
         }
     }

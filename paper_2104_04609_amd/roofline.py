@@ -110,14 +110,26 @@ def far_pairs_per_matvec(triangles: np.ndarray) -> int:
 
 def pair_kernel_roofline(point_pairs: int, seconds_per_launch: float,
                          precision: str = "fp32", rates: dict | None = None,
-                         symmetric: bool = False) -> dict:
+                         symmetric: bool = False, lossy: bool = False) -> dict:
     """point_pairs: ordered separated point pairs per matvec.  symmetric: the
-    FP32 kernel evaluates each unordered pair once (unit = unordered pair)."""
+    FP32 kernel evaluates each unordered pair once (unit = unordered pair).
+    lossy: complex interior wavenumber, one more transcendental per pair (the
+    decay e^{-Im(k) r} as exp2, priced at the 1/sqrt issue rate: both are
+    quarter-rate transcendental instructions) and its multiply (2 flops)."""
     pairs_s = point_pairs / seconds_per_launch
     if precision == "fp32" and symmetric:
         r = rates or QUARTER_RATES
         upairs_s = pairs_s / 2
-        tt = trans_seconds_per_pair(r)
+        tt = trans_seconds_per_pair(r) + (1.0 / r["rsq_f32"] if lossy else 0.0)
+        if lossy:
+            fe_extra = 2 * 2   # the decay times both accumulated Green's functions
+            fe = FLOPS_PER_UPAIR + fe_extra + PEAK_FP32_TFLOPS * 1e12 * tt
+            achieved = upairs_s * fe / 1e12
+            return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                    "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                    "work_unit": "unordered point pair (complex k_int)",
+                    "flop_eq_per_unit": fe, "units_per_s": upairs_s,
+                    "point_pairs_per_s": pairs_s, "rates_measured": rates is not None}
         fe = FLOPS_PER_UPAIR + PEAK_FP32_TFLOPS * 1e12 * tt
         achieved = upairs_s * fe / 1e12
         t_issue = KERNEL_VALU_PER_UPAIR / r["fma_f32"] + tt

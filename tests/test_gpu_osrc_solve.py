@@ -118,6 +118,27 @@ def test_osrc_apply_batched_rhs(P):
         assert torch.equal(yr, Y[r])
 
 
+@pytest.mark.parametrize("level", [3, 4])
+def test_osrc_info_sizes(P, level):
+    """bem_osrc_info: the P1 mass pattern of a closed genus-0 triangulation
+    holds the diagonal and both directions of every edge, N + 2 (3N - 6)
+    entries (Euler: E = 3N - 6); N_p + 2 factors, 2 N_p + 2 block solves per
+    apply, the factor bytes of their stored parts."""
+    mesh = icosphere(level)
+    N = mesh.n_vertices
+    M = P.Mesh.from_inputs(mesh)
+    st = P.osrc_info(M, 4, np.pi / 3, 15.0, 15.0 + 2.0j)
+    print(st)
+    assert st["n_vertices"] == N
+    assert st["mass_nnz"] == 7 * N - 12
+    assert st["n_factors"] == 6 and st["solves_per_apply"] == 10
+    assert 0 < st["nnz_offblock"] <= st["nnz_l"]
+    assert st["factor_bytes"] == 16 * 6 * (N + 2 * st["nnz_l"] + 2 * st["dense_entries"])
+    assert st["bytes_per_apply"] > 10 * 16 * 2 * N
+    with pytest.raises(P.BemError):
+        P.osrc_info(M, 0, np.pi / 3, 15.0, 15.0 + 2.0j)
+
+
 _SOLVES = {}
 
 

@@ -128,8 +128,8 @@ def test_budget_admission_and_rejection(P):
     a = srv.add_mesh(m3.vertices, m3.triangles)
     b = srv.add_mesh(m5.vertices, m5.triangles)
     d = _dirs(1, 3)
-    # ico5: the Krylov basis for 1000 iterations alone is 336 MB
-    big = srv.submit(b, 2.0, 3.0, 1.5, d, 1e-6, precision="fp32", path=0, maxiter=1000)
+    # ico5 on the assembled path: the complex64 operator alone is 3.4 GB
+    big = srv.submit(b, 2.0, 3.0, 1.5, d, 1e-6, precision="fp32", path=1)
     small = [srv.submit(a, 2.0 + 0.5 * i, 3.0 + 0.5 * i, 1.5, d, 1e-6, precision="fp32",
                         path=0, maxiter=200) for i in range(4)]
     sol, info, st = srv.wait(big)
@@ -180,6 +180,62 @@ def test_resident_state_released_under_budget(P):
     for (s0, _, t0), (s1, _, t1) in zip(ref, got):
         assert t0["status"] == 0 and t1["status"] == 0
         assert torch.equal(s0, s1)
+
+
+def test_krylov_growth_accounted(P):
+    """A request whose basis outgrows the initial 65 vectors reports the
+    growth to the server (krylov_growth_bytes) and equals the direct solve."""
+    import torch
+    m = icosphere(3)
+    d = _dirs(1, 21)
+    M = P.Mesh.from_inputs(m)
+    # no OSRC (formulation "pmchwt"), k_int = 20 on 1280 triangles, tol 1e-12:
+    # the oracle takes 117 iterations
+    ref, info, rc = P.pmchwt_solve(M, 12.0, 20.0, 1.5, d, 1e-12, precision="fp64", path=1,
+                                   formulation="pmchwt", maxiter=300)
+    assert info[0]["iterations"] > 64, info
+    srv = P.Server(workers=1)
+    mid = srv.add_mesh(m.vertices, m.triangles)
+    rid = srv.submit(mid, 12.0, 20.0, 1.5, d, 1e-12, precision="fp64", path=1,
+                     formulation="pmchwt", maxiter=300)
+    sol, infos, st = srv.wait(rid)
+    stats = srv.stats()
+    srv.close()
+    print(stats, st)
+    assert st["status"] == rc
+    assert stats["krylov_growth_bytes"] > 0 and stats["reserved_bytes"] == 0
+    assert torch.equal(sol, ref)
+
+
+def test_replicas_share_assembled_operator(P):
+    """Requests with the same mesh and wavenumbers running on several
+    replicas use one assembled operator (one assembly, counted by the
+    library's profiler), and each result equals the direct solve."""
+    import torch
+    m = icosphere(4)
+    M = P.Mesh.from_inputs(m)
+    srv = P.Server(workers=3)
+    mid = srv.add_mesh(m.vertices, m.triangles)
+    ds = [_dirs(2, 30 + i) for i in range(3)]
+    P.profile_enable(True)
+    try:
+        rids = [srv.submit(mid, 4.0, 6.0, 1.5, d, 1e-8, precision="fp32", path=1) for d in ds]
+        out = [srv.wait(r) for r in rids]
+        torch.cuda.synchronize()
+        # the operator is assembled in FP32, or in FP64 and rounded
+        # ("solve.residual_dense_gib"): one assembly either way
+        n_asm = P.profile_read("dense_assemble")[1] + P.profile_read("dense_assemble_fp64")[1]
+    finally:
+        P.profile_enable(False)
+    stats = srv.stats()
+    srv.close()
+    print(stats, n_asm)
+    assert stats["peak_inflight"] >= 2
+    assert n_asm == 1
+    for d, (sol, infos, st) in zip(ds, out):
+        ref, info, rc = P.pmchwt_solve(M, 4.0, 6.0, 1.5, d, 1e-8, precision="fp32", path=1)
+        assert st["status"] == 0 and rc == 0
+        assert torch.equal(sol, ref)
 
 
 def test_invalid_requests(P):

@@ -7,13 +7,12 @@ directions and request streams.  Both the GPU path
 and the CPU oracle consume what it produces; neither shares any other code.
 """
 from .meshes import (icosphere, geodesic_sphere, ellipsoid, two_spheres,
-                     four_spheres, menger_sponge, mesh_counts, Mesh)
+                     four_spheres, mesh_counts, Mesh)
 from .materials import MEDIA, wavenumber, density_ratio
 from .vectors import (complex_normal, wave_directions, request_stream,
                       sample_rows)
 
 __all__ = ["icosphere", "geodesic_sphere", "ellipsoid", "two_spheres", "four_spheres",
-           "menger_sponge",
            "MEDIA", "wavenumber", "density_ratio",
            "mesh_counts", "Mesh", "complex_normal", "wave_directions",
            "request_stream", "sample_rows"]

@@ -188,55 +188,3 @@ def four_spheres(level: int = 2, radius: float = 1.0, geodesic: int = 0) -> Mesh
     return Mesh(np.vstack(P), np.vstack(T).astype(np.int32), np.concatenate(oid),
                 name=f"four_spheres{level}" if geodesic <= 0 else f"four_spheres_g{geodesic}",
                 radius=float(radius))
-
-
-def menger_sponge(level: int = 2, k: int = 4, edge: float = 10.0) -> Mesh:
-    """Surface of the Menger sponge of the given level (the paper's domain
-    with corners and inclusions: level 2, edge 10 mm), a cube of the given
-    edge centred at the origin.  The sponge is the union of the filled voxels
-    of a 3^level grid (a voxel is removed when at least two of its base-3
-    digits at some level are 1); every voxel face between a filled voxel and
-    empty space is split into k x k squares and each square into two
-    triangles, oriented with the outward normal.  Vertices lie on an integer
-    lattice and are shared exactly."""
-    n = 3 ** level
-    filled = np.ones((n, n, n), bool)
-    idx = np.arange(n)
-    for lv in range(level):
-        d = ((idx // 3 ** lv) % 3 == 1).astype(int)
-        filled &= (d[:, None, None] + d[None, :, None] + d[None, None, :]) < 2
-    g = np.pad(filled, 1)
-    verts: dict = {}
-    tris = []
-
-    def vid(p):
-        key = (int(p[0]), int(p[1]), int(p[2]))
-        if key not in verts:
-            verts[key] = len(verts)
-        return verts[key]
-
-    for ax in range(3):
-        u, v = [a for a in range(3) if a != ax]
-        for sgn in (-1, 1):
-            nb = np.roll(g, -sgn, axis=ax)[1:-1, 1:-1, 1:-1]
-            for cell in np.argwhere(filled & ~nb):
-                base = cell * k
-                base[ax] += k if sgn > 0 else 0
-                # (e_u, e_v, sgn e_ax) right-handed: counterclockwise from outside
-                eu, ev = np.zeros(3, int), np.zeros(3, int)
-                eu[u], ev[v] = 1, 1
-                if np.dot(np.cross(eu, ev), np.eye(3, dtype=int)[ax]) * sgn < 0:
-                    eu, ev = ev, eu
-                for a in range(k):
-                    for b in range(k):
-                        p00 = base + a * eu + b * ev
-                        i00, i10 = vid(p00), vid(p00 + eu)
-                        i11, i01 = vid(p00 + eu + ev), vid(p00 + ev)
-                        tris.append((i00, i10, i11))
-                        tris.append((i00, i11, i01))
-    P = np.zeros((len(verts), 3))
-    for key, i in verts.items():
-        P[i] = key
-    P = P * (edge / (n * k)) - edge / 2.0
-    return Mesh(P, np.asarray(tris, np.int32), None, name=f"menger{level}_k{k}",
-                radius=float(edge * np.sqrt(3) / 2))

@@ -384,23 +384,30 @@ def c3_leg(P, RL, rates, steps: int) -> dict:
                                                     torch.linalg.norm(y64))
     progress("C3 OSRC")
     out["osrc"] = osrc_measure(P, M, k1, n_p)
+    progress("C3 compressed operator")
+    out["compressed"] = hmat_measure(P, M, k0, k1, rho, x, y64)
     progress("C3 solves")
     P.pmchwt_solve(M, k0, k1, rho, [[0, 0, 1]], 1e-6, precision="fp64", path=0, maxiter=1,
                    pade_terms=n_p)
     solves = {}
-    for name, prec in (("fp32", "fp32"), ("fp64", "fp64")):
+    for name, prec, path in (("fp32", "fp32", 0), ("fp64", "fp64", 0),
+                             ("fp32_compressed", "fp32", 3)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, info, rc = P.pmchwt_solve(M, k0, k1, rho, [[0, 0, 1]], 1e-6, precision=prec, path=0,
-                                     pade_terms=n_p)
+        _, info, rc = P.pmchwt_solve(M, k0, k1, rho, [[0, 0, 1]], 1e-6, precision=prec,
+                                     path=path, pade_terms=n_p)
         torch.cuda.synchronize()
         solves[name] = {**info[0], "seconds": time.perf_counter() - t0, "rc": rc}
         progress(f"C3 solve {name}: {solves[name]['seconds']:.2f} s, "
                  f"{solves[name]['iterations']} iterations")
     solves["speedup_fp32_refine_vs_fp64"] = solves["fp64"]["seconds"] / solves["fp32"]["seconds"]
+    # the compressed operator was built above (hmat_measure): its set-up added
+    solves["fp32_compressed"]["setup_s"] = out["compressed"]["first_call_s"]
+    solves["fp32_compressed"]["seconds_with_setup"] = (solves["fp32_compressed"]["seconds"] +
+                                                       out["compressed"]["first_call_s"])
+    solves["speedup_fp32_compressed_refine_vs_fp64"] = (
+        solves["fp64"]["seconds"] / solves["fp32_compressed"]["seconds_with_setup"])
     out["solve"] = solves
-    progress("C3 compressed operator")
-    out["compressed"] = hmat_measure(P, M, k0, k1, rho, x, y64)
     del M
     return out
 
@@ -454,6 +461,14 @@ def compression_large(P) -> dict:
     out["rel_diff_vs_matrix_free_fp32"] = [
         float(torch.linalg.norm(yh[..., sl] - y[..., sl]) / torch.linalg.norm(y[..., sl]))
         for sl in (slice(0, N), slice(N, 2 * N))]
+    progress("1e5-vertex sphere: FP32 compressed solve with FP64 residuals")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info, rc = P.pmchwt_solve(M, 10.0, 15.0, 1.5, [[0, 0, 1]], 1e-6, precision="fp32", path=3)
+    torch.cuda.synchronize()
+    out["solve_fp32_compressed"] = {**info[0], "seconds": time.perf_counter() - t0, "rc": rc,
+                                    "note": "OSRC factors and near field built inside the call; "
+                                            "compressed operator already built above"}
     del M
     return out
 
@@ -629,12 +644,18 @@ def main():
             P.pmchwt_solve(M, K_EXT, K_INT, RHO, [[0, 0, 1]], 1e-6, precision="fp64", path=0,
                            maxiter=1)
             # FP64 GMRES and FP32 + refinement, each matrix-free and on the
-            # assembled operator (assembly included in its time)
+            # assembled operator (assembly included in its time: each assembled
+            # solve on a fresh handle whose near field and OSRC factors are warm)
             for name, prec, path in (("fp64", "fp64", 0), ("fp32", "fp32", 0),
                                      ("fp32_dense", "fp32", 1), ("fp64_dense", "fp64", 1)):
+                Ms = M
+                if path == 1:
+                    Ms = P.Mesh.from_inputs(mesh)
+                    P.pmchwt_solve(Ms, K_EXT, K_INT, RHO, [[0, 0, 1]], 1e-6, precision="fp64",
+                                   path=0, maxiter=1)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                sol, info, rc = P.pmchwt_solve(M, K_EXT, K_INT, RHO, [[0, 0, 1]], 1e-6,
+                sol, info, rc = P.pmchwt_solve(Ms, K_EXT, K_INT, RHO, [[0, 0, 1]], 1e-6,
                                                precision=prec, path=path)
                 torch.cuda.synchronize()
                 # "seconds": wall clock around the call, set-up (assembly) included;
@@ -642,6 +663,8 @@ def main():
                 wall = time.perf_counter() - t0
                 solve[name] = {**info[0], "seconds": wall, "solve_seconds": info[0]["seconds"],
                                "rc": rc}
+                if Ms is not M:
+                    del Ms
             # the autotuner's choice for this shape (matrix-free vs assembled), then a
             # solve on the auto path
             # (fresh handle with warm near field and OSRC, so that assembly, when
@@ -662,6 +685,17 @@ def main():
                                        "tune": tuned}
             P.tune_clear()
             del M2
+            # FP32 refinement with the compressed operator in the inner solves
+            # (H-matrix built inside the timed call) and FP64 matrix-free residuals
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info, rc = P.pmchwt_solve(M, K_EXT, K_INT, RHO, [[0, 0, 1]], 1e-6,
+                                         precision="fp32", path=3)
+            torch.cuda.synchronize()
+            solve["fp32_compressed"] = {**info[0], "seconds": time.perf_counter() - t0,
+                                        "solve_seconds": info[0]["seconds"], "rc": rc}
+            solve["speedup_fp32_compressed_refine_vs_fp64"] = (solve["fp64"]["seconds"] /
+                                                               solve["fp32_compressed"]["seconds"])
             solve["speedup_fp32_refine_vs_fp64"] = (solve["fp64"]["seconds"] /
                                                     solve["fp32"]["seconds"])
             solve["speedup_fp32_autotuned_vs_fp64"] = (solve["fp64"]["seconds"] /

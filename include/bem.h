@@ -246,7 +246,10 @@ typedef struct {
                             for the FP32 form's inner solves, complex128 for
                             the FP64 form), 2 assembled when it fits in device
                             memory and the autotuned table does not prefer
-                            the matrix-free path (default) */
+                            the matrix-free path (default), 3 the compressed
+                            operator (precision BEM_FP32 only: inner solves on
+                            the H-matrix of bem_hmat_info, every outer
+                            residual with the FP64 pair kernel) */
     int formulation;     /* BEM_FORM_OSRC (default), BEM_FORM_PMCHWT,
                             BEM_FORM_CALDERON or BEM_FORM_MULLER; see below */
 } bem_solve_opts;
@@ -303,10 +306,15 @@ void bem_solve_opts_default(bem_solve_opts *opts);
  * operator (later ones updated with FP32 products of the corrections, see
  * "solve.refine_update"), inner GMRES on the operator with the FP32 pair
  * kernel, or on the assembled complex64 operator (path 1; see
- * "solve.residual_dense_gib" for how its FP64 residuals are formed).
+ * "solve.residual_dense_gib" for how its FP64 residuals are formed), or on
+ * the compressed operator (path 3; the H-matrix at the paper's ACA tolerance
+ * 1e-5, Sec. 3.1), whose error the FP64 residuals of the outer steps remove.
  *   directions  host [n_waves][3];  solution  device [n_waves][2N]
  *   info        host [n_waves] or NULL
  * Returns BEM_W_NOT_CONVERGED (best iterate written) if maxiter is reached.
+ * Errors: BEM_E_INVAL (bad options or directions; path 3 with precision
+ * BEM_FP64), BEM_E_UNSUPPORTED (path 3 with the Calderon preconditioner of
+ * several objects), BEM_E_NAN, BEM_E_NOMEM.
  */
 int pmchwt_solve(const bem_mesh *mesh, bem_c64 k_ext, bem_c64 k_int,
                  double rho, const double *directions, int n_waves, double tol,
@@ -410,7 +418,7 @@ typedef struct {
 
 typedef struct {
     int status;              /* return code of the solve (BEM_OK, BEM_W_NOT_CONVERGED, < 0) */
-    int path;                /* 0 matrix-free, 1 assembled operator */
+    int path;                /* 0 matrix-free, 1 assembled, 3 compressed operator */
     double t_submit;         /* seconds since server creation */
     double t_admit;
     double t_end;

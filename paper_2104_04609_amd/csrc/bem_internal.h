@@ -353,6 +353,9 @@ void hmat_apply(HMatrix &H, bem_mesh *m, const NearOperator &nf, const double2 *
 int64_t hmat_bytes(const HMatrix &h);
 const HMatStats &hmat_stats(const HMatrix &h);
 // cached per wavenumber pair and materials (built on first use)
+// device bytes of the compressed operator: those of the cached one, else an
+// upper estimate (a quarter of the complex64 dense operator, at least 1 GiB)
+int64_t hmat_bytes_estimate(const bem_mesh *m, double2 k0, double2 k1, double rho);
 HMatrix &hmat_get(bem_mesh *m, double2 k0, double2 k1, double rho, hipStream_t s, int s1 = 1,
                   const ObjMaterials *om = nullptr);
 // dense.hip

@@ -1034,6 +1034,12 @@ std::unique_ptr<HMatrix, HMatDeleter> hmat_build(bem_mesh *m, const NearOperator
     return H;
 }
 
+int64_t hmat_bytes_estimate(const bem_mesh *m, double2 k0, double2 k1, double rho) {
+    auto it = m->hmat_cache.find(near_key(m, k0, k1, rho, 1, nullptr));
+    if (it != m->hmat_cache.end()) return hmat_bytes(*it->second);
+    return std::max<int64_t>(dense_bytes(m) / 4, (int64_t)1 << 30);
+}
+
 HMatrix &hmat_get(bem_mesh *m, double2 k0, double2 k1, double rho, hipStream_t s, int s1,
                   const ObjMaterials *om) {
     const NearKey key = near_key(m, k0, k1, rho, s1, om);

@@ -463,7 +463,7 @@ int server_submit(bem_server *srv, int mesh_id, bem_c64 k_ext, bem_c64 k_int, do
         // triangle pairs (assembly or matrix-free products) and, on the
         // assembled path, the operator entries each wave's iterations read
         r->work = (double)h0->T * (double)h0->T *
-                  (r->o.path == 1 ? 1.0 : std::min(n_waves, 16) * 50.0) +
+                  (r->o.path != 0 ? 1.0 : std::min(n_waves, 16) * 50.0) +
                   (r->o.path == 1 ? 4.0 * (double)h0->N * (double)h0->N * n_waves * 50.0 / 64.0
                                   : 0.0);
         (void)hipSetDevice(prev);
@@ -531,7 +531,7 @@ int bem_server_wait(bem_server *srv, int64_t request_id, double timeout_s,
         return BEM_W_PENDING;
     if (stats) {
         stats->status = r->status;
-        stats->path = r->o.path == 1 ? 1 : 0;
+        stats->path = r->o.path;   // 0, 1 or 3 (auto resolved at submission)
         stats->t_submit = r->t_submit;
         stats->t_admit = r->t_admit;
         stats->t_end = r->t_end;

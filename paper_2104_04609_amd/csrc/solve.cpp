@@ -87,12 +87,15 @@ struct Op {
     int form = BEM_FORM_OSRC;
     const DenseOperator *dense = nullptr;   // assembled operator (FP32 form)
     const DenseOperator *dense64 = nullptr; // assembled complex128 operator (FP64 form, path 1)
+    HMatrix *hm = nullptr;                  // compressed operator (FP32 form, path 3)
     const ObjMaterials *om = nullptr;       // per-object materials, or k1, rho for all
     DevBuf<double2> yw, t1, t2;              // weak-form scratch [R][2N]
     DevBuf<double2> px, py;                  // one object's entries [R][2 N_m]
     void weak(const double2 *in, double2 *out, int R, int precision) {
         if (precision == BEM_FP32_DENSE) {
             dense_apply(*dense, in, out, R, m->xs32, s);
+        } else if (precision == BEM_FP32_HMAT) {
+            for (int r = 0; r < R; r++) hmat_apply(*hm, m, *nf, in + r * 2 * m->N, out + r * 2 * m->N, s);
         } else if (precision == BEM_FP64 && dense64) {
             dense_apply(*dense64, in, out, R, m->xs32, s);
         } else {
@@ -358,7 +361,11 @@ void solve_check(const bem_mesh *m, double2 k0, double2 k1, double rho, const do
     if (o.pade_terms < 1 || o.pade_terms > PADE_MAX) fail(BEM_E_INVAL, "pade_terms");
     if (o.precision != BEM_FP64 && o.precision != BEM_FP32) fail(BEM_E_INVAL, "precision");
     if (o.maxiter < 1 || o.max_outer < 1 || !(o.inner_tol > 0)) fail(BEM_E_INVAL, "opts");
-    if (o.path < 0 || o.path > 2) fail(BEM_E_INVAL, "path must be 0, 1 or 2");
+    if (o.path < 0 || o.path > 3) fail(BEM_E_INVAL, "path must be 0, 1, 2 or 3");
+    if (o.path == 3 && o.precision != BEM_FP32)
+        fail(BEM_E_INVAL, "path 3 (compressed operator) serves the FP32 form's inner solves");
+    if (o.path == 3 && o.formulation == BEM_FORM_CALDERON && m->nobj > 1)
+        fail(BEM_E_UNSUPPORTED, "path 3: the Calderon preconditioner of several objects");
     if (o.formulation < BEM_FORM_OSRC || o.formulation > BEM_FORM_MULLER)
         fail(BEM_E_INVAL, "formulation must be 0, 1, 2 or 3");
     for (int w = 0; w < n_waves; w++) {
@@ -407,6 +414,7 @@ int64_t solve_footprint(bem_mesh *m, double2 k0, double2 k1, double rho,
     }
     if (o.precision == BEM_FP64 && o.path == 1)
         b += dense_bytes(m, true) + dense_assembly_scratch_bytes(m, true);
+    if (o.path == 3) b += hmat_bytes_estimate(m, k0, k1, rho);
     if (dense) b += 2 * G * n2 * 8 + dense_gemm_scratch_bytes(m, G);
     if (rdense)   // complex128 operator beside its assembly scratch, then its rounding
         b += dense_bytes(m, true) +
@@ -451,7 +459,10 @@ int solve_run(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dir
     op.om = om;
     int inner = BEM_FP32;
     std::shared_ptr<const DenseOperator> dense_hold, dense_hold64;   // shared operators held
-    if (o.path != 0) {
+    if (o.path == 3) {
+        op.hm = &hmat_get(m, k0, k1, rho, s, s1, om);
+        inner = BEM_FP32_HMAT;
+    } else if (o.path != 0) {
         const bool f64 = o.precision == BEM_FP64;
         bool use = o.path == 1;
         if (o.path == 2) {   // autotuned choice, else dense when it fits with room to spare
@@ -572,7 +583,9 @@ int solve_run(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dir
                 std::vector<int> upd, full;
                 for (int a = 0; a < A; a++) {
                     const int r = act[a];
-                    const bool cheap = update && exact[r] &&
+                    // (the bound on P32's error holds for the pair kernel and the
+                    // assembled operators, not for the compressed one)
+                    const bool cheap = update && inner != BEM_FP32_HMAT && exact[r] &&
                                        carried[r] + REFINE_OP_BOUND * rn[r] <= 0.1 * tol * bn[r];
                     (cheap ? upd : full).push_back(a);
                 }

@@ -143,3 +143,25 @@ def test_c2_fp32_refinement_matches_oracle(P, c2, handle, golden, oracle_prec, p
     e = _mie_error(P, handle, sol[0].contiguous())
     print("far-field error vs series", e, "oracle", float(golden["mie_error"]))
     assert abs(e - float(golden["mie_error"])) <= 1e-3
+
+
+def test_c2_fp32_compressed_matches_oracle(P, c2, handle, golden, oracle_prec):
+    """FP32 refinement with the compressed operator (H-matrix, ACA 1e-5) in the
+    inner solves and every outer residual with the FP64 pair kernel: the
+    oracle's residual of the GPU solution, the distance to the oracle's
+    solution and the far field as for the other FP32 paths."""
+    print("C2 FP32+refine path 3", flush=True)
+    sol, info, rc = P.pmchwt_solve(handle, K_EXT, K_INT, RHO, D, 1e-6, precision="fp32", path=3)
+    print(info[0])
+    assert rc == 0 and info[0]["rel_residual"] <= 1e-6
+    assert info[0]["fp64_matvecs"] == info[0]["outer_steps"]
+    res = _residual(P, c2, handle, oracle_prec, sol[0].contiguous())
+    print("oracle residual of the GPU solution", res, "reported", info[0]["rel_residual"])
+    assert res <= info[0]["rel_residual"] + 1e-9
+    x = sol.cpu().numpy()[0]
+    xo = golden["x"]
+    assert np.linalg.norm(x - xo) <= 1e-4 * np.linalg.norm(xo)
+    e = _mie_error(P, handle, sol[0].contiguous())
+    assert abs(e - float(golden["mie_error"])) <= 1e-3
+    with pytest.raises(P.BemError):
+        P.pmchwt_solve(handle, K_EXT, K_INT, RHO, D, 1e-6, precision="fp64", path=3)

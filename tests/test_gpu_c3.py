@@ -112,7 +112,7 @@ def _weak_residual_rows(P, c3, handle, sol):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("precision,path", [("fp32", 1), ("fp32", 0), ("fp64", 0)])
+@pytest.mark.parametrize("precision,path", [("fp32", 1), ("fp32", 0), ("fp64", 0), ("fp32", 3)])
 def test_c3_solve(P, c3, handle, precision, path):
     print(f"C3 solve {precision} path {path}", flush=True)
     sol, info, rc = P.pmchwt_solve(handle, K_EXT, K_INT, RHO, [[0.0, 0.0, 1.0]], 1e-6,

@@ -245,8 +245,10 @@ typedef struct {
                             pair kernel, 1 assembled dense operator (complex64
                             for the FP32 form's inner solves, complex128 for
                             the FP64 form), 2 assembled when it fits in device
-                            memory and the autotuned table does not prefer
-                            the matrix-free path (default), 3 the compressed
+                            memory and, for the FP32 form, the autotuned table
+                            does not prefer the matrix-free path (an assembly
+                            that runs out of memory falls back to the
+                            matrix-free operator) (default), 3 the compressed
                             operator (precision BEM_FP32 only: inner solves on
                             the H-matrix of bem_hmat_info, every outer
                             residual with the FP64 pair kernel) */
@@ -493,6 +495,10 @@ int bem_profile_read(const char *kernel, double *total_ms, int64_t *launches);
  *                         and D in Maue form depend on the points only
  *                         through r; Sec. 2.2); 0: each ordered pair in the
  *                         one-directional kernel (default 1)
+ *   "farfield.sym_round_mib" symmetric kernel: largest buffer of the partial
+ *                         sums of the second triangle's rows per launch, in
+ *                         MiB (1..65536, default 512); larger meshes run the
+ *                         test blocks in several launches, results unchanged
  *   "dense.skinny_min_rhs" right-hand-side count (>= 2) from which products
  *                         with the assembled operator below gemm_min use the
  *                         16-column MFMA kernel instead of the multi-vector

@@ -431,6 +431,9 @@ int bem_tune_set(const char *key, int64_t value) {
     } else if (k == "farfield.block") {
         if (value != 64 && value != 128 && value != 256) fail(BEM_E_INVAL, "farfield.block: 64, 128 or 256");
         t.farfield_block = (int)value;
+    } else if (k == "farfield.sym_round_mib") {
+        if (value < 1 || value > 65536) fail(BEM_E_INVAL, "farfield.sym_round_mib: 1..65536");
+        t.farfield_sym_round_mib = (int)value;
     } else if (k == "farfield.symmetric") {
         if (value != 0 && value != 1) fail(BEM_E_INVAL, "farfield.symmetric: 0 or 1");
         t.farfield_symmetric = (int)value;
@@ -482,6 +485,7 @@ int bem_tune_get(const char *key, int64_t *value) {
     if (k == "farfield.multi_max") *value = t.farfield_multi_max;
     else if (k == "farfield.block") *value = t.farfield_block;
     else if (k == "farfield.symmetric") *value = t.farfield_symmetric;
+    else if (k == "farfield.sym_round_mib") *value = t.farfield_sym_round_mib;
     else if (k == "dense.skinny_min_rhs") *value = t.dense_skinny_min_rhs;
     else if (k == "dense.gemm_min_rhs") *value = t.dense_gemm_min_rhs;
     else if (k == "solve.refine_update") *value = t.solve_refine_update;

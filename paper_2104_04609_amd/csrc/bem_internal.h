@@ -279,6 +279,7 @@ struct Tuning {
     std::atomic<int> farfield_multi_max{4};   // right-hand sides per pair-kernel launch
     std::atomic<int> farfield_block{256};     // test triangles per pair-kernel workgroup
     std::atomic<int> farfield_symmetric{1};   // FP32 single vector: each separated pair once
+    std::atomic<int> farfield_sym_round_mib{512};   // symmetric kernel: sigma partials per launch
     std::atomic<int> dense_gemm_min_rhs{24};  // MFMA product from this many right-hand sides
     std::atomic<int> dense_skinny_min_rhs{24}; // skinny MFMA product from this many (else multi-GEMV)
     std::atomic<int> solve_refine_update{1};  // FP32 refinement: later residuals updated in FP32
@@ -361,6 +362,8 @@ HMatrix &hmat_get(bem_mesh *m, double2 k0, double2 k1, double rho, hipStream_t s
 // dense.hip
 int64_t dense_bytes(const bem_mesh *m, bool fp64 = false);
 int64_t dense_assembly_scratch_bytes(const bem_mesh *m, bool fp64 = false);
+// operator and assembly scratch of a mesh of N vertices and T triangles
+int64_t dense_need_bytes(int64_t N, int64_t T, bool fp64);
 // The assembled operator of m from its DenseShare (assembled once by the
 // first replica that needs it; held while the returned pointer lives).
 std::shared_ptr<const DenseOperator> dense_share_get(bem_mesh *m, double2 k0, double2 k1,

@@ -738,9 +738,12 @@ int64_t dense_bytes(const bem_mesh *m, bool fp64) {
     return 4 * m->N * m->N * (int64_t)(fp64 ? sizeof(double2) : sizeof(float2));
 }
 int64_t dense_assembly_scratch_bytes(const bem_mesh *m, bool fp64) {
+    return dense_need_bytes(m->N, m->T, fp64) - dense_bytes(m, fp64);
+}
+int64_t dense_need_bytes(int64_t N, int64_t T, bool fp64) {
     const int64_t c = fp64 ? sizeof(double2) : sizeof(float2);
-    return m->T * (int64_t)JT * 12 * c + 2 * m->N * (int64_t)sizeof(float2) +
-           (2 * m->N + m->T) * (int64_t)sizeof(int32_t);   // vertex ranks, triangle order
+    return 4 * N * N * c + T * (int64_t)JT * 12 * c + 2 * N * (int64_t)sizeof(float2) +
+           (2 * N + T) * (int64_t)sizeof(int32_t);   // vertex ranks, triangle order
 }
 
 void dense_assemble_into(bem_mesh *m, const NearOperator &nf, double2 k0, hipStream_t s,

@@ -496,8 +496,11 @@ void farfield_kernel(
 // (12 rows, 6 curl sums).  Rows of sigma: every thread contracts its
 // contribution to sigma's three vertices, each wave adds its 64 lanes with a
 // fixed DPP tree, the waves' sums are added in FP64 in wave order and stored
-// at psig[sig_off(b) + sigma - b blk][18].  Every slot is written by exactly
-// one work item, so the reduction over slots is deterministic.
+// at psig[sig_off(b) - sig_base + sigma - b blk][18].  Every slot is written
+// by exactly one work item, so the reduction over slots is deterministic.
+// The blocks run in rounds (consecutive block ranges, one launch each) whose
+// sigma slots fit a bounded buffer; after each round sym_sig_accum_kernel
+// adds its slots to one FP64 sum per sigma, in block order.
 constexpr int SIG_VALS = ROW_STRIDE + 6;
 constexpr int SYM_WAVES = FF_BLOCK / 64;
 
@@ -534,7 +537,7 @@ void farfield_sym_kernel(
     const R *__restrict__ geo, const R *__restrict__ dyn,
     const int32_t *__restrict__ tobj, const int32_t *__restrict__ tri, int T,
     const int32_t *__restrict__ items, int chunk_len, Coef<R> cf, const Int<R> *__restrict__ itab,
-    double *__restrict__ ptau, double *__restrict__ psig) {
+    double *__restrict__ ptau, double *__restrict__ psig, int64_t sig_base) {
     static_assert(std::is_same<R, float>::value, "symmetric kernel: FP32 only");
     using MT = Math<R>;
     __shared__ R tile[FF_TILE * SRC];
@@ -602,7 +605,7 @@ void farfield_sym_kernel(
     };
     // rows of sigma of one tile: wave sums (LDS) -> FP64 in wave order
     const int nw = nthr >> 6;
-    double *psb = psig + (sym_sig_off(b, T, nthr) - (int64_t)b * nthr) * SIG_VALS;
+    double *psb = psig + (sym_sig_off(b, T, nthr) - sig_base - (int64_t)b * nthr) * SIG_VALS;
     auto combine = [&](int tb, int tcnt) {
         for (int idx = threadIdx.x; idx < tcnt * SIG_VALS; idx += nthr) {
             const int s = idx / SIG_VALS, k = idx - s * SIG_VALS;
@@ -1084,11 +1087,29 @@ __global__ __launch_bounds__(256) void reduce_splits_kernel(
 
 // ------------------------------------------- symmetric-kernel reduction
 // Rows of test triangle tau from the symmetric kernel: its own work items
-// as tau (chunk order), then the blocks b <= block(tau) as sigma (block
-// order); then the curl contraction and |tau|/(4 pi) as in the split
+// as tau (chunk order), then its sum as sigma over the blocks b <=
+// block(tau); then the curl contraction and |tau|/(4 pi) as in the split
 // reduction.
+// sigacc[sigma] (+)= the slots of blocks [b0, b1) for sigma (block order;
+// the round of block 0 starts every sum)
+__global__ __launch_bounds__(256) void sym_sig_accum_kernel(
+    const double *__restrict__ psig, int64_t sig_base, int b0, int b1, int T, int blk,
+    double *__restrict__ sigacc) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T || t < b0 * blk) return;
+    double acc[SIG_VALS];
+    double *o = sigacc + (int64_t)t * SIG_VALS;
+    for (int k = 0; k < SIG_VALS; k++) acc[k] = b0 == 0 ? 0.0 : o[k];
+    const int last = min(b1 - 1, t / blk);
+    for (int bb = b0; bb <= last; bb++) {
+        const double *q = psig + (sym_sig_off(bb, T, blk) - sig_base + t - (int64_t)bb * blk) * SIG_VALS;
+        for (int k = 0; k < SIG_VALS; k++) acc[k] += q[k];
+    }
+    for (int k = 0; k < SIG_VALS; k++) o[k] = acc[k];
+}
+
 __global__ __launch_bounds__(256) void reduce_sym_kernel(
-    const double *__restrict__ ptau, const double *__restrict__ psig,
+    const double *__restrict__ ptau, const double *__restrict__ sigacc,
     const double *__restrict__ tst, int T, int blk, int chunk_len,
     double *__restrict__ trirows) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1103,8 +1124,8 @@ __global__ __launch_bounds__(256) void reduce_sym_kernel(
         const double *p = ptau + ((first + c) * blk + l) * SIG_VALS;
         for (int k = 0; k < SIG_VALS; k++) acc[k] += p[k];
     }
-    for (int bb = 0; bb <= b; bb++) {
-        const double *q = psig + (sym_sig_off(bb, T, blk) + t - (int64_t)bb * blk) * SIG_VALS;
+    {
+        const double *q = sigacc + (int64_t)t * SIG_VALS;
         for (int k = 0; k < SIG_VALS; k++) acc[k] += q[k];
     }
     const double *ts = tst + (int64_t)TST_STRIDE * t;
@@ -1398,13 +1419,14 @@ template <bool FR> const void *sym_kernel(int code) {
 template <bool FR>
 void launch_sym(int code, int n_items, int blk, hipStream_t s, const float *geo, const float *dyn,
                 const int32_t *tobj, const int32_t *tri, int T, const int32_t *items, int chunk,
-                Coef<float> cf, const Int<float> *itab, double *ptau, double *psig) {
+                Coef<float> cf, const Int<float> *itab, double *ptau, double *psig,
+                int64_t sig_base) {
     switch (code) {
 #define BEM_CASE(c, a, b, m)                                                                     \
     case c:                                                                                      \
         hipLaunchKernelGGL((farfield_sym_kernel<float, a, b, m, FR>), dim3(n_items), dim3(blk),  \
                            far_smem<float>(blk), s, geo, dyn, tobj, tri, T, items, chunk, cf,    \
-                           itab, ptau, psig);                                                    \
+                           itab, ptau, psig, sig_base);                                          \
         break;
         BEM_CASE(0, false, false, false)
         BEM_CASE(1, false, false, true)
@@ -1424,17 +1446,27 @@ void launch_sym(int code, int n_items, int blk, hipStream_t s, const float *geo,
 // makespan of a greedy list schedule of the items (longest first) on the
 // resident workgroup slots, among lengths giving 1.5 to 8 items per slot.  Launch order: full chunks, then the shorter
 // last chunks by decreasing length; storage order of the tau rows: b-major.
+// Rounds: consecutive block ranges [b0, b1) whose sigma slots take at most
+// "farfield.sym_round_mib" (one launch each), their items at [item0, item0 +
+// nitems).
+struct SymRound {
+    int b0, b1, item0, nitems;
+    int64_t sig_base;   // sym_sig_off(b0)
+};
 struct SymPlan {
     int blk = 0, chunk = 0, nblk = 0;
-    std::vector<int32_t> items;   // launch order: (b, c, storage index)
-    int64_t tau_doubles = 0, sig_doubles = 0;
+    std::vector<int32_t> items;   // launch order, round after round: (b, c, storage index)
+    std::vector<SymRound> rounds;
+    int64_t tau_doubles = 0, sig_doubles = 0;   // sig_doubles: the largest round
 };
 
 const SymPlan &sym_plan(int T, int blk, int slots) {
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int>, SymPlan> cache;
+    static std::map<std::tuple<int, int, int, int>, SymPlan> cache;
+    const int cap_mib = tuning().farfield_sym_round_mib.load();
+    const int64_t sig_cap = (int64_t)cap_mib << 20;
     std::lock_guard<std::mutex> g(mu);
-    auto it = cache.find({T, blk, slots});
+    auto it = cache.find({T, blk, slots, cap_mib});
     if (it != cache.end()) return it->second;
     const int nblk = (T + blk - 1) / blk;
     const double fixed = 2.0;
@@ -1477,25 +1509,40 @@ const SymPlan &sym_plan(int T, int blk, int slots) {
     p.blk = blk;
     p.chunk = best_L;
     p.nblk = nblk;
-    std::vector<std::array<int32_t, 4>> all;   // (len, b, c, canon)
+    std::vector<std::array<int32_t, 4>> all;   // (len, b, c, canon), block-major
     int32_t canon = 0;
     for (int b = 0; b < nblk; b++) {
         int c = 0;
         for (int lo = b * blk; lo < T; lo += best_L, c++)
             all.push_back({std::min(best_L, T - lo), b, c, canon++});
     }
-    std::stable_sort(all.begin(), all.end(),
-                     [](const std::array<int32_t, 4> &x, const std::array<int32_t, 4> &y) {
-                         return x[0] > y[0];
-                     });
-    for (const auto &e : all) {
-        p.items.push_back(e[1]);
-        p.items.push_back(e[2]);
-        p.items.push_back(e[3]);
+    size_t e0 = 0;
+    for (int b0 = 0; b0 < nblk;) {
+        int b1 = b0 + 1;
+        while (b1 < nblk && (sym_sig_off(b1 + 1, T, blk) - sym_sig_off(b0, T, blk)) * SIG_VALS *
+                                    (int64_t)sizeof(double) <= sig_cap)
+            b1++;
+        size_t e1 = e0;
+        while (e1 < all.size() && all[e1][1] < b1) e1++;
+        std::vector<std::array<int32_t, 4>> rd(all.begin() + e0, all.begin() + e1);
+        std::stable_sort(rd.begin(), rd.end(),
+                         [](const std::array<int32_t, 4> &x, const std::array<int32_t, 4> &y) {
+                             return x[0] > y[0];
+                         });
+        p.rounds.push_back(SymRound{b0, b1, (int)(p.items.size() / 3), (int)rd.size(),
+                                    sym_sig_off(b0, T, blk)});
+        for (const auto &e : rd) {
+            p.items.push_back(e[1]);
+            p.items.push_back(e[2]);
+            p.items.push_back(e[3]);
+        }
+        p.sig_doubles = std::max(p.sig_doubles,
+                                 (sym_sig_off(b1, T, blk) - sym_sig_off(b0, T, blk)) * SIG_VALS);
+        e0 = e1;
+        b0 = b1;
     }
     p.tau_doubles = (int64_t)canon * blk * SIG_VALS;
-    p.sig_doubles = sym_sig_off(nblk, T, blk) * SIG_VALS;
-    return cache.emplace(std::make_tuple(T, blk, slots), std::move(p)).first->second;
+    return cache.emplace(std::make_tuple(T, blk, slots, cap_mib), std::move(p)).first->second;
 }
 
 const SymPlan &sym_plan_for(const bem_mesh *m, const FarPlan &fp) {
@@ -1522,7 +1569,7 @@ int64_t farfield_scratch_bytes(const bem_mesh *m, int precision, double2 k0, dou
         part = std::max(part, (int64_t)p.nsplit * T * (ROW_STRIDE + 6) * 8);
         if (f32) {
             const SymPlan &sp = sym_plan_for(m, p);
-            part = std::max(part, (sp.tau_doubles + sp.sig_doubles) * 8 +
+            part = std::max(part, (sp.tau_doubles + sp.sig_doubles + T * SIG_VALS) * 8 +
                                       (int64_t)sp.items.size() * 4);
         }
         if (R < 2 || (f32 && p.fr)) continue;
@@ -1562,7 +1609,7 @@ void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
                            m->tst.p, x, m->N, T, m->dyn32.p);
         BEM_LAUNCH_CHECK();
         const SymPlan &sp = sym_plan_for(m, plan);
-        const size_t sneed = (size_t)(sp.tau_doubles + sp.sig_doubles);
+        const size_t sneed = (size_t)(sp.tau_doubles + sp.sig_doubles + (int64_t)T * SIG_VALS);
         if (m->partial.n < sneed) m->partial.alloc(sneed);
         if (m->sym_items.n < sp.items.size() || m->sym_plan_id != &sp) {
             if (m->sym_items.n < sp.items.size()) m->sym_items.alloc(sp.items.size());
@@ -1570,21 +1617,34 @@ void farfield_apply(bem_mesh *m, const NearOperator &nf, double2 k0, double2 k1,
                                    hipMemcpyHostToDevice, s));
             m->sym_plan_id = &sp;
         }
-        double *ptau = m->partial.p, *psig = m->partial.p + sp.tau_doubles;
-        const int n_items = (int)(sp.items.size() / 3);
+        double *ptau = m->partial.p, *psig = ptau + sp.tau_doubles, *sigacc = psig + sp.sig_doubles;
+        const Coef<float> cf = make_coef<float>(k0, nf);
+        const Int<float> *it = interior_table<float>(m, nf, k0);
+        auto accum = [&](const SymRound &rd) {
+            hipLaunchKernelGGL(sym_sig_accum_kernel, gg, dim3(256), 0, s, psig, rd.sig_base, rd.b0,
+                               rd.b1, T, blk, sigacc);
+            BEM_LAUNCH_CHECK();
+        };
         {
             Timer tm("farfield_fp32", s);
-            if (!fr)
-                launch_sym<false>(plan.code, n_items, blk, s, m->geo32.p, m->dyn32.p, m->tobj_d.p,
-                                  m->tri_d.p, T, m->sym_items.p, sp.chunk,
-                                  make_coef<float>(k0, nf), interior_table<float>(m, nf, k0), ptau, psig);
-            else
-                launch_sym<true>(plan.code, n_items, blk, s, m->geo32.p, m->dyn32.p, m->tobj_d.p,
-                                 m->tri_d.p, T, m->sym_items.p, sp.chunk,
-                                 make_coef<float>(k0, nf), interior_table<float>(m, nf, k0), ptau, psig);
-            BEM_LAUNCH_CHECK();
+            const size_t nr = sp.rounds.size();
+            for (size_t r = 0; r < nr; r++) {
+                const SymRound &rd = sp.rounds[r];
+                const int32_t *items = m->sym_items.p + 3 * (int64_t)rd.item0;
+                if (!fr)
+                    launch_sym<false>(plan.code, rd.nitems, blk, s, m->geo32.p, m->dyn32.p,
+                                      m->tobj_d.p, m->tri_d.p, T, items, sp.chunk, cf, it, ptau,
+                                      psig, rd.sig_base);
+                else
+                    launch_sym<true>(plan.code, rd.nitems, blk, s, m->geo32.p, m->dyn32.p,
+                                     m->tobj_d.p, m->tri_d.p, T, items, sp.chunk, cf, it, ptau,
+                                     psig, rd.sig_base);
+                BEM_LAUNCH_CHECK();
+                if (r + 1 < nr) accum(rd);   // the slots are reused by the next round
+            }
         }
-        hipLaunchKernelGGL(reduce_sym_kernel, gg, dim3(256), 0, s, ptau, psig, m->tst.p, T, blk,
+        accum(sp.rounds.back());
+        hipLaunchKernelGGL(reduce_sym_kernel, gg, dim3(256), 0, s, ptau, sigacc, m->tst.p, T, blk,
                            sp.chunk, m->trirows.p);
         BEM_LAUNCH_CHECK();
     } else if (precision == BEM_FP32) {

@@ -453,8 +453,10 @@ int server_submit(bem_server *srv, int mesh_id, bem_c64 k_ext, bem_c64 k_int, do
         // the path depends on the request alone (and the autotuned table)
         if (r->o.path == 2) {
             bem::TuneEntry te;
-            const bool mf = bem::tune_find(h0->T, std::min(n_waves, 16), &te) && te.path == 0;
             const bool f64 = r->o.precision == BEM_FP64;
+            // the autotuned table times the FP32 products: it decides FP32 requests
+            const bool mf = !f64 && bem::tune_find(h0->T, std::min(n_waves, 16), &te) &&
+                            te.path == 0;
             r->o.path = !mf && bem::dense_bytes(h0, f64) <= srv->o.dense_max_bytes ? 1 : 0;
         }
         BEM_HIP(hipGetDevice(&prev));

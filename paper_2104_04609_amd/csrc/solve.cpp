@@ -28,6 +28,7 @@
 // carried bound would reach a tenth of the tolerance the residual is formed
 // in FP64 again (tuning key "solve.refine_update" = 0 forms every residual in
 // FP64).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -396,6 +397,25 @@ static bool residual_dense(const bem_mesh *m, const bem_solve_opts &o) {
            (o.formulation != BEM_FORM_CALDERON || m->nobj == 1);
 }
 
+// Device bytes the assembled path of these options allocates: the operators
+// it assembles (complex128 and its complex64 rounding, complex128, or
+// complex64) with the assembly scratch and, for the Calderon preconditioner
+// of several objects, each object's own operator and scratch.
+static int64_t dense_path_need(const bem_mesh *m, const bem_solve_opts &o) {
+    const bool f64 = o.precision == BEM_FP64, rd = residual_dense(m, o);
+    int64_t b = f64 || rd ? dense_bytes(m, true) +
+                                std::max(dense_assembly_scratch_bytes(m, true),
+                                         rd ? dense_bytes(m) : (int64_t)0)
+                          : dense_bytes(m) + dense_assembly_scratch_bytes(m);
+    if (o.formulation == BEM_FORM_CALDERON && m->nobj > 1)
+        for (int ob = 0; ob < m->nobj; ob++) {
+            const int64_t No = std::count(m->vobj.begin(), m->vobj.end(), ob);
+            const int64_t To = std::count(m->tobj.begin(), m->tobj.end(), ob);
+            b += dense_need_bytes(No, To, f64);
+        }
+    return b;
+}
+
 int64_t solve_footprint(bem_mesh *m, double2 k0, double2 k1, double rho,
                         const bem_solve_opts &o, int n_waves) {
     (void)rho;
@@ -412,22 +432,13 @@ int64_t solve_footprint(bem_mesh *m, double2 k0, double2 k1, double rho,
         if (o.precision == BEM_FP32 && !dense)
             b += farfield_scratch_bytes(m, BEM_FP32, k0, k1, G);   // dyn32 beside dyn64
     }
-    if (o.precision == BEM_FP64 && o.path == 1)
-        b += dense_bytes(m, true) + dense_assembly_scratch_bytes(m, true);
+    if (o.path == 1) b += dense_path_need(m, o);
     if (o.path == 3) b += hmat_bytes_estimate(m, k0, k1, rho);
     if (dense) b += 2 * G * n2 * 8 + dense_gemm_scratch_bytes(m, G);
-    if (rdense)   // complex128 operator beside its assembly scratch, then its rounding
-        b += dense_bytes(m, true) +
-             std::max(dense_assembly_scratch_bytes(m, true), dense_bytes(m));
-    else if (dense)
-        b += dense_bytes(m) + dense_assembly_scratch_bytes(m);
     b += ((int64_t)n_waves + 8 * (int64_t)G) * n2 * c16;      // f, B, X, R, D, T, yw, vin, vout
     if (o.formulation == BEM_FORM_CALDERON) {
         b += 2 * (int64_t)G * n2 * c16;                       // t1, t2
-        if (m->nobj > 1) b += 4 * m->nf_nnz * c16 + G * n2 * c16 +   // parts: near fields, px, py
-                              (dense ? dense_bytes(m) / m->nobj : 0) +
-                              (o.precision == BEM_FP64 && o.path == 1 ? dense_bytes(m, true) / m->nobj
-                                                                      : 0);
+        if (m->nobj > 1) b += 4 * m->nf_nnz * c16 + G * n2 * c16;   // parts: near fields, px, py
     }
     else if (o.formulation != BEM_FORM_OSRC) b += (int64_t)G * n2 * c16;       // t1
     // the initial Krylov basis; its growth is reported through reserve_bytes
@@ -469,47 +480,56 @@ int solve_run(bem_mesh *m, double2 k0, double2 k1, double rho, const double *dir
             size_t free_b = 0, total_b = 0;
             BEM_HIP(hipMemGetInfo(&free_b, &total_b));
             const bool rd = residual_dense(m, o);
-            int64_t need = f64 || rd ? dense_bytes(m, true) + dense_assembly_scratch_bytes(m, true) +
-                                           (int64_t)(1ll << 30)
-                                     : (int64_t)(2ll << 30);
-            if (!f64) need += dense_bytes(m);
-            // Calderon on several objects: each object's own operator as well
-            if (o.formulation == BEM_FORM_CALDERON && m->nobj > 1) need += dense_bytes(m, f64) / m->nobj;
+            const int64_t need = dense_path_need(m, o) + (int64_t)(1ll << 30);
             const bool fits = need < (int64_t)free_b ||
                               !(f64  ? m->dense64_cache.empty()
                                 : rd ? m->dense_rounded_cache.empty()
                                      : m->dense_cache.empty());
+            // the autotuned table times the FP32 products (pair kernel against
+            // complex64 operator): it decides FP32 solves only
             TuneEntry te;
-            use = fits && !(tune_find(m->T, std::min(n_waves, SOLVE_BATCH), &te) && te.path == 0);
+            use = fits && !(o.precision == BEM_FP32 &&
+                            tune_find(m->T, std::min(n_waves, SOLVE_BATCH), &te) && te.path == 0);
         }
-        if (use && f64) {
-            if (m->dense_share) {
-                dense_hold = dense_share_get(m, k0, k1, rho, s, s1, om, DENSE_C128);
-                op.dense64 = dense_hold.get();
-            } else {
-                op.dense64 = &dense_get(m, k0, k1, rho, s, s1, om, true);
+        try {
+            if (use && f64) {
+                if (m->dense_share) {
+                    dense_hold = dense_share_get(m, k0, k1, rho, s, s1, om, DENSE_C128);
+                    op.dense64 = dense_hold.get();
+                } else {
+                    op.dense64 = &dense_get(m, k0, k1, rho, s, s1, om, true);
+                }
+            } else if (use && residual_dense(m, o)) {
+                // FP32 form whose FP64 residuals use the complex128 operator: the
+                // complex64 one is its rounding (one FP64 assembly)
+                if (m->dense_share) {
+                    dense_hold64 = dense_share_get(m, k0, k1, rho, s, s1, om, DENSE_C128);
+                    dense_hold = dense_share_get(m, k0, k1, rho, s, s1, om, DENSE_C64_ROUNDED);
+                    op.dense64 = dense_hold64.get();
+                    op.dense = dense_hold.get();
+                } else {
+                    op.dense64 = &dense_get(m, k0, k1, rho, s, s1, om, true);
+                    op.dense = &dense_get_rounded(m, k0, k1, rho, s, s1, om);
+                }
+                inner = BEM_FP32_DENSE;
+            } else if (use) {
+                if (m->dense_share) {
+                    dense_hold = dense_share_get(m, k0, k1, rho, s, s1, om, DENSE_C64);
+                    op.dense = dense_hold.get();
+                } else {
+                    op.dense = &dense_get(m, k0, k1, rho, s, s1, om);
+                }
+                inner = BEM_FP32_DENSE;
             }
-        } else if (use && residual_dense(m, o)) {
-            // FP32 form whose FP64 residuals use the complex128 operator: the
-            // complex64 one is its rounding (one FP64 assembly)
-            if (m->dense_share) {
-                dense_hold64 = dense_share_get(m, k0, k1, rho, s, s1, om, DENSE_C128);
-                dense_hold = dense_share_get(m, k0, k1, rho, s, s1, om, DENSE_C64_ROUNDED);
-                op.dense64 = dense_hold64.get();
-                op.dense = dense_hold.get();
-            } else {
-                op.dense64 = &dense_get(m, k0, k1, rho, s, s1, om, true);
-                op.dense = &dense_get_rounded(m, k0, k1, rho, s, s1, om);
-            }
-            inner = BEM_FP32_DENSE;
-        } else if (use) {
-            if (m->dense_share) {
-                dense_hold = dense_share_get(m, k0, k1, rho, s, s1, om, DENSE_C64);
-                op.dense = dense_hold.get();
-            } else {
-                op.dense = &dense_get(m, k0, k1, rho, s, s1, om);
-            }
-            inner = BEM_FP32_DENSE;
+        } catch (const Error &e) {
+            // the automatic path falls back to the matrix-free operator when
+            // the assembled one does not fit after all
+            if (o.path != 2 || e.code != BEM_E_NOMEM) throw;
+            (void)hipGetLastError();
+            dense_hold.reset();
+            dense_hold64.reset();
+            op.dense = op.dense64 = nullptr;
+            inner = BEM_FP32;
         }
     }
     // waves are solved in lockstep groups of up to SOLVE_BATCH

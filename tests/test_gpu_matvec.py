@@ -393,7 +393,8 @@ def test_matvec_workgroup_sizes(P, block, precision):
 
 @pytest.fixture
 def far_tuning(P):
-    old = {k: P.tune_get(k) for k in ("farfield.block", "farfield.symmetric")}
+    old = {k: P.tune_get(k) for k in ("farfield.block", "farfield.symmetric",
+                                      "farfield.sym_round_mib")}
     yield lambda k, v: P.tune_set(k, v)
     for k, v in old.items():
         P.tune_set(k, v)
@@ -421,6 +422,35 @@ def test_symmetric_kernel_matches_one_directional(P, far_tuning, block):
         print(case, block, d, e)
         assert max(d.values()) <= 2e-6, d
         assert max(e.values()) <= TOL["fp32"], e
+
+
+@pytest.mark.parametrize("block", [64, 256])
+def test_symmetric_kernel_rounds_bitwise(P, far_tuning, block):
+    """The symmetric kernel in several launches (a 1 MiB buffer of the
+    partial sums of the second triangle's rows: a dozen or more rounds on an
+    icosphere of level 4, the last one ragged) gives bitwise the result of
+    one launch, and matches the oracle's rows."""
+    import torch
+    from oracle.operators import pmchwt_matvec_rows
+    far_tuning("farfield.block", block)
+    far_tuning("farfield.symmetric", 1)
+    mesh = icosphere(4)
+    N = mesh.n_vertices
+    M = P.Mesh.from_inputs(mesh)
+    x = complex_normal(2 * N, seed=12)
+    xd = torch.from_numpy(x).cuda()
+    print(f"symmetric rounds block {block}", flush=True)
+    y1 = P.pmchwt_matvec(M, 4.0, 6.0 + 0.5j, 1.5, xd, precision="fp32")
+    far_tuning("farfield.sym_round_mib", 1)
+    yr = P.pmchwt_matvec(M, 4.0, 6.0 + 0.5j, 1.5, xd, precision="fp32")
+    assert torch.equal(y1, yr)
+    rows = sample_rows(N, 24, seed=13)
+    r1, r2 = pmchwt_matvec_rows(mesh, 4.0, 6.0 + 0.5j, 1.5, x, rows)
+    y = yr.cpu().numpy()
+    for got, ref in ((y[rows], r1), (y[N + rows], r2)):
+        assert np.linalg.norm(got - ref) <= TOL["fp32"] * np.linalg.norm(ref)
+    with pytest.raises(P.BemError):
+        P.tune_set("farfield.sym_round_mib", 0)
 
 
 def test_fp32_kernels_large_phases(P, far_tuning):

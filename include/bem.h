@@ -393,9 +393,12 @@ int bem_far_field(const bem_mesh *mesh, bem_c64 k_ext, const bem_c64 *solution,
  * running requests.  A running request's Krylov basis doubles as it fills;
  * each growth is added to its reservation as it happens, releasing cached
  * state if needed, and runs on even when the budget is exceeded (at most
- * maxiter + 1 vectors per wave).  When a request does not fit, cached state
- * is released, least recently used first: assembled operators no request
- * holds, then the caches of idle handles.  A request that cannot fit even on an idle
+ * maxiter + 1 vectors per wave).  When a request does not fit, the caches of
+ * idle handles are released, least recently used first.  Assembled
+ * operators that no request holds stay resident outside the budget, as a
+ * cache whose buffers new operators reuse; when a device allocation fails,
+ * they are released first (least recently used), then the caches of idle
+ * handles, and the allocation is retried.  A request that cannot fit even on an idle
  * server completes with status BEM_E_NOMEM.  Waiting requests are admitted
  * smallest estimated work first (triangle pairs of the assembly or of the
  * matrix-free products, operator entries read by the iterations), except that
@@ -435,8 +438,9 @@ typedef struct {
     int64_t peak_bytes;      /* max over time of resident + reserved */
     int inflight, peak_inflight, queued;
     int64_t completed, rejected;
-    int64_t evictions;       /* cached states released: idle handles' caches and
-                                assembled operators no request held */
+    int64_t evictions;       /* cached states released: idle handles' caches, and
+                                assembled operators no request held (on a
+                                failed device allocation) */
     int64_t krylov_growth_bytes; /* Krylov-basis growth reported by running
                                     requests beyond their footprints (total) */
 } bem_server_stats;

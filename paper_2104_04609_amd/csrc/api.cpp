@@ -34,6 +34,34 @@ void prof_clear_locked() {
 void set_last_error(const std::string &msg) { g_last_error = msg; }
 
 namespace {
+std::mutex g_rel_mu;
+std::vector<std::pair<MemReleaser, void *>> g_releasers;
+}   // namespace
+
+void add_mem_releaser(MemReleaser fn, void *ctx) {
+    std::lock_guard<std::mutex> g(g_rel_mu);
+    g_releasers.emplace_back(fn, ctx);
+}
+void remove_mem_releaser(void *ctx) {
+    std::lock_guard<std::mutex> g(g_rel_mu);
+    g_releasers.erase(std::remove_if(g_releasers.begin(), g_releasers.end(),
+                                     [&](const std::pair<MemReleaser, void *> &r) {
+                                         return r.second == ctx;
+                                     }),
+                      g_releasers.end());
+}
+bool release_device_memory() {
+    std::vector<std::pair<MemReleaser, void *>> rs;
+    {
+        std::lock_guard<std::mutex> g(g_rel_mu);
+        rs = g_releasers;
+    }
+    for (const auto &r : rs)
+        if (r.first(r.second)) return true;
+    return false;
+}
+
+namespace {
 thread_local bool t_no_timer = false;
 }
 

@@ -26,6 +26,15 @@ struct Error {
 [[noreturn]] void fail(int code, const std::string &msg);
 void set_last_error(const std::string &msg);
 
+// Device memory pressure: when an allocation fails, the registered
+// releasers (the serving loop's idle caches) are asked to free something;
+// release_device_memory returns whether any did, and the allocation is
+// retried.
+using MemReleaser = bool (*)(void *ctx);
+void add_mem_releaser(MemReleaser fn, void *ctx);
+void remove_mem_releaser(void *ctx);
+bool release_device_memory();
+
 #define BEM_HIP(expr)                                                         \
     do {                                                                      \
         hipError_t e_ = (expr);                                               \
@@ -54,6 +63,10 @@ template <class T> struct DevBuf {
         release();
         if (count == 0) return;
         hipError_t e = hipMalloc((void **)&p, count * sizeof(T));
+        while (e == hipErrorOutOfMemory && release_device_memory()) {
+            (void)hipGetLastError();
+            e = hipMalloc((void **)&p, count * sizeof(T));
+        }
         if (e != hipSuccess) {
             p = nullptr;
             (void)hipGetLastError();

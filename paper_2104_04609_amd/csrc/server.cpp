@@ -101,45 +101,65 @@ struct bem_server {
     double now() const {
         return std::chrono::duration<double>(bem::Clock::now() - t0).count();
     }
+    // Cached state of the handles counted against the budget.  Assembled
+    // operators that no request holds are a cache outside it: a new request's
+    // operator reuses their buffers, and a device allocation that fails
+    // releases them (release_hook); those in use are in running footprints.
     int64_t resident() const {
         int64_t b = 0;
-        for (const auto &me : meshes) {
+        for (const auto &me : meshes)
             for (const auto &r : me->reps) b += r->resident;
-            b += me->share->idle_bytes();   // those in use are in running footprints
-        }
         return b;
     }
-    // Release cached state, least recently used first, until `need` more bytes
-    // fit: assembled operators no request holds, then the caches of idle
-    // handles.  Returns whether they fit.
+    // Drops the least recently used assembled operator no request holds (lock
+    // held); false if there is none.
+    bool evict_shared_op() {
+        bem::DenseShare *oldest = nullptr;
+        uint64_t t_old = UINT64_MAX;
+        for (auto &me : meshes) {
+            const uint64_t t = me->share->oldest_idle();
+            if (t < t_old) {
+                t_old = t;
+                oldest = me->share.get();
+            }
+        }
+        if (oldest && oldest->evict_idle_lru() > 0) {
+            evictions++;
+            return true;
+        }
+        return false;
+    }
+    // Releases the cached state of the least recently used idle handle (lock
+    // held); false if there is none.
+    bool trim_idle_handle() {
+        bem::Replica *lru = nullptr;
+        bem::MeshEntry *lru_mesh = nullptr;
+        for (auto &me : meshes)
+            for (auto &r : me->reps)
+                if (!r->busy && r->h && r->resident > me->base_bytes &&
+                    (!lru || r->last_used < lru->last_used)) {
+                    lru = r.get();
+                    lru_mesh = me.get();
+                }
+        if (!lru) return false;
+        bem::mesh_trim(lru->h);
+        lru->resident = std::max(lru->h->device_bytes(), lru_mesh->base_bytes);
+        evictions++;
+        return true;
+    }
+    // A device allocation failed: free an idle assembled operator, else an
+    // idle handle's caches.
+    static bool release_hook(void *ctx) {
+        bem_server *srv = static_cast<bem_server *>(ctx);
+        std::lock_guard<std::mutex> g(srv->mu);
+        return srv->evict_shared_op() || srv->trim_idle_handle();
+    }
+    // Release cached state of idle handles, least recently used first, until
+    // `need` more bytes fit.  Returns whether they fit.
     bool make_room(int64_t need) {
         while (resident() + reserved + need > o.hbm_budget) {
-            bem::DenseShare *oldest = nullptr;
-            uint64_t t_old = UINT64_MAX;
-            for (auto &me : meshes) {
-                const uint64_t t = me->share->oldest_idle();
-                if (t < t_old) {
-                    t_old = t;
-                    oldest = me->share.get();
-                }
-            }
-            if (oldest && oldest->evict_idle_lru() > 0) {
-                evictions++;
-                continue;
-            }
-            bem::Replica *lru = nullptr;
-            bem::MeshEntry *lru_mesh = nullptr;
-            for (auto &me : meshes)
-                for (auto &r : me->reps)
-                    if (!r->busy && r->h && r->resident > me->base_bytes &&
-                        (!lru || r->last_used < lru->last_used)) {
-                        lru = r.get();
-                        lru_mesh = me.get();
-                    }
-            if (!lru) return false;
-            bem::mesh_trim(lru->h);
-            lru->resident = std::max(lru->h->device_bytes(), lru_mesh->base_bytes);
-            evictions++;
+            if (trim_idle_handle()) continue;
+            return false;
         }
         return true;
     }
@@ -334,6 +354,7 @@ int bem_server_create(const bem_server_opts *opts, bem_server **out) {
             srv->streams.push_back(s);
         }
         bem_server *raw = srv.get();
+        bem::add_mem_releaser(&bem_server::release_hook, raw);
         for (int i = 0; i < o.workers; i++) srv->threads.emplace_back([raw, i] { raw->worker(i); });
         *out = srv.release();
         return BEM_OK;
@@ -360,6 +381,7 @@ void bem_server_destroy(bem_server *srv) {
     }
     srv->cv_work.notify_all();
     for (auto &t : srv->threads) t.join();
+    bem::remove_mem_releaser(srv);
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(srv->device);

@@ -16,12 +16,13 @@
 #include "sparse_ldl.h"
 
 // Definitions that live with the library's C entry points and its OSRC and
-// compressed-operator sources: the error helpers, the mesh handle's
-// destructor and its cache deleters.  The checks build no compressed operator,
+// compressed-operator sources: the error helpers, the device-memory release
+// registry, the mesh handle's destructor and its cache deleters.  The checks build no compressed operator,
 // so that deleter never runs.
 namespace bem {
 [[noreturn]] void fail(int code, const std::string &msg) { throw Error{code, msg}; }
 void set_last_error(const std::string &) {}
+bool release_device_memory() { return false; }   // no serving caches here
 void OsrcDeleter::operator()(OsrcState *p) const { delete p; }
 void OsrcSymDeleter::operator()(OsrcSymbolicState *p) const { delete p; }
 void HMatDeleter::operator()(HMatrix *) const { std::abort(); }

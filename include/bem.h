@@ -207,9 +207,10 @@ int bem_osrc_info(const bem_mesh *mesh, int pade_terms, double theta,
  *     BEM_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends:
  *     min(n_rhs, 16) * ((pade_terms + 2) (2 n_vertices + P) +
  *     (pade_terms + 5) n_vertices) * 16 bytes must fit (BEM_E_INVAL
- *     otherwise), P = 0 unless the two-part block solve is on ("osrc.split":
- *     then the partial sums of its top rows), e.g. 8 vectors of 10 242
- *     vertices with 4 Pade terms.  Nothing in it needs to start at zero.
+ *     otherwise), P the partial sums of the top rows of the two-part block
+ *     solve when the mesh's OSRC state has one ("osrc.split"; a few thousand
+ *     at 10 242 vertices), e.g. 8 vectors of 10 242 vertices with 4 Pade
+ *     terms.  Nothing in it needs to start at zero.
  *   - Every call on one GPU uses that GPU's array: calls that overlap in time
  *     on one GPU (other streams, other threads) race; the caller serialises
  *     them.
@@ -542,14 +543,17 @@ int bem_profile_read(const char *kernel, double *total_ms, int64_t *launches);
  *                         them (3 launches per solve when the top is small);
  *                         0 one launch per dissection level (two for the
  *                         levels of few, large blocks); 1 the two-part solve
- *                         above 16 384 vertices, levels below (default 1)
+ *                         above 16 384 vertices, and below it for batches of
+ *                         8 vectors or more (top part level by level),
+ *                         levels otherwise (default 1)
  *   "osrc.sub_rows"       largest bottom subtree in rows, 64..8192, 0 for
  *                         4096 or the device's LDS limit (default 0)
  *   "osrc.top_single_work" top part in one workgroup when its entries (L and
  *                         dense block inverses) are at most this many, else
  *                         level by level (default 300000)
  * Results of a solve depend on these (the summation order changes), within
- * the FP32 accuracy.  BEM_E_INVAL for an unknown key or value. */
+ * the FP32 accuracy; with "osrc.split" = 1 an OSRC apply's rounding also
+ * depends on the batch size.  BEM_E_INVAL for an unknown key or value. */
 int bem_tune_set(const char *key, int64_t value);
 int bem_tune_get(const char *key, int64_t *value);
 

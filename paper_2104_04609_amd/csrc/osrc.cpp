@@ -179,9 +179,11 @@ OsrcSymbolicState &symbolic(bem_mesh *m) {
     st->wlen = 2 * (int64_t)n;   // y, z
     const Tuning &tn = tuning();
     // automatic choice (measured on the 10 242- and 40 962-vertex meshes): one
-    // launch per level up to 16 384 vertices, the two-part solve above
+    // launch per level up to 16 384 vertices unless 8 or more vectors are
+    // solved at once, the two-part solve above
     const int split_mode = tn.osrc_split.load();
-    if (split_mode == 2 || (split_mode == 1 && n > 16384)) {
+    st->split_always = split_mode == 2 || n > 16384;
+    if (split_mode != 0) {
         const int phase_rows = 4 * 1024;   // rows a 1024-thread workgroup keeps in registers
         int sub_rows = std::min(ldl_split_max_sub_rows(), 4096);
         if (tn.osrc_sub_rows.load() > 0)
@@ -195,9 +197,11 @@ OsrcSymbolicState &symbolic(bem_mesh *m) {
                     top_dense += w * w;
                 }
             const int64_t top_work = (int64_t)P.tf_pos.size() + (int64_t)P.tb_pos.size() + top_dense;
-            st->top_single =
-                P.ntop <= ldl_split_max_sub_rows() && top_work <= tn.osrc_top_single_work.load() ? 1
-                                                                                                : 0;
+            // (used for batches only, the top part runs level by level)
+            st->top_single = st->split_always && P.ntop <= ldl_split_max_sub_rows() &&
+                                     top_work <= tn.osrc_top_single_work.load()
+                                 ? 1
+                                 : 0;
             st->sp_sub_r0.upload(P.sub_r0);
             st->sp_sub_r1.upload(P.sub_r1);
             st->sp_sub_hptr.upload(P.sub_hptr);
@@ -222,11 +226,11 @@ OsrcSymbolicState &symbolic(bem_mesh *m) {
     return *m->osrc_sym;
 }
 
-LdlSplitDev split_view(const OsrcSymbolicState &sy) {
+LdlSplitDev split_view(const OsrcSymbolicState &sy, int nrhs) {
     LdlSplitDev P{};
     const LdlSplit &q = sy.split;
-    P.ok = q.ok ? 1 : 0;
-    if (!q.ok) return P;
+    P.ok = q.ok && (sy.split_always || nrhs >= OSRC_SPLIT_MIN_RHS) ? 1 : 0;
+    if (!P.ok) return P;
     P.H = q.H;
     P.nsub = q.nsub;
     P.ntop = q.ntop;
@@ -460,7 +464,7 @@ void osrc_apply_from_weak(bem_mesh *m, OsrcState &st, const double2 *yw, double2
     const int64_t wl = sy.wlen;
     const int64_t n2 = 2 * (int64_t)n, os = (int64_t)(np + 3) * n, ws = (int64_t)(np + 2) * wl;
     double2 *ob = scr ? scr->obuf : st.obuf.p, *wk = scr ? scr->work : st.work.p;
-    const LdlSplitDev P = split_view(sy);
+    const LdlSplitDev P = split_view(sy, R);
     double2 *u1 = ob + (size_t)np * n, *v = ob + (size_t)(np + 1) * n, *m2 = ob + (size_t)(np + 2) * n;
     Timer tm("osrc_apply", s);
     // stage 1: shifted solves and M^{-1} on y1 (DtN); (M - S/k_eps^2)^{-1} on y2 (NtD)
@@ -507,7 +511,7 @@ void osrc_mass_solve(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y, i
         for (int b = 0; b < cnt; b++)
             t.t[b] = SolveTask{st.np + 1, x + (size_t)(b0 + b) * n, y + (size_t)(b0 + b) * n,
                                make_double2(1.0, 0.0), st.work.p + (size_t)b * sy.wlen};
-        launch_ldl_solve(L, split_view(sy), t, cnt, 1, s);
+        launch_ldl_solve(L, split_view(sy, 1), t, cnt, 1, s);
     }
 }
 

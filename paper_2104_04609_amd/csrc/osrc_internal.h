@@ -14,6 +14,10 @@ struct PadeCoef {
     double2 A[PADE_MAX];
 };
 
+// Vectors per batch from which the two-part block solve replaces the level
+// schedule on meshes where it is not used for every batch.
+constexpr int OSRC_SPLIT_MIN_RHS = 8;
+
 // Largest dissection block (rows) a level workgroup can hold in LDS.
 constexpr int LDL_MAX_BLOCK = 4096;
 
@@ -87,6 +91,8 @@ struct OsrcSymbolicState {
         sp_tlist, sp_part_b, sp_part_e, sp_tf_ptr, sp_tf_pos, sp_tf_col, sp_tb_ptr, sp_tb_pos,
         sp_tb_row, sp_bsplit;
     int top_single = 0;
+    bool split_always = false;   // the two-part solve for any batch (else batches of
+                                 // OSRC_SPLIT_MIN_RHS vectors and more)
     int64_t wlen = 0;   // work length per system (n + partial sums)
     DevBuf<double> Mv_d, Sv_d;
     int64_t bytes() const;

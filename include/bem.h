@@ -502,8 +502,9 @@ int bem_profile_read(const char *kernel, double *total_ms, int64_t *launches);
  *                         one-directional kernel (default 1)
  *   "farfield.sym_round_mib" symmetric kernel: largest buffer of the partial
  *                         sums of the second triangle's rows per launch, in
- *                         MiB (1..65536, default 512); larger meshes run the
- *                         test blocks in several launches, results unchanged
+ *                         MiB (1..65536, default 4096: one launch up to about
+ *                         60 000 vertices); larger meshes run the test blocks
+ *                         in several launches, results unchanged
  *   "dense.skinny_min_rhs" right-hand-side count (>= 2) from which products
  *                         with the assembled operator below gemm_min use the
  *                         16-column MFMA kernel instead of the multi-vector

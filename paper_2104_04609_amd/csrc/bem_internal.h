@@ -292,7 +292,7 @@ struct Tuning {
     std::atomic<int> farfield_multi_max{4};   // right-hand sides per pair-kernel launch
     std::atomic<int> farfield_block{256};     // test triangles per pair-kernel workgroup
     std::atomic<int> farfield_symmetric{1};   // FP32 single vector: each separated pair once
-    std::atomic<int> farfield_sym_round_mib{512};   // symmetric kernel: sigma partials per launch
+    std::atomic<int> farfield_sym_round_mib{4096};   // symmetric kernel: sigma partials per launch
     std::atomic<int> dense_gemm_min_rhs{24};  // MFMA product from this many right-hand sides
     std::atomic<int> dense_skinny_min_rhs{24}; // skinny MFMA product from this many (else multi-GEMV)
     std::atomic<int> solve_refine_update{1};  // FP32 refinement: later residuals updated in FP32

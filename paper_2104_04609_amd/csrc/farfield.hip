@@ -1469,41 +1469,57 @@ const SymPlan &sym_plan(int T, int blk, int slots) {
     auto it = cache.find({T, blk, slots, cap_mib});
     if (it != cache.end()) return it->second;
     const int nblk = (T + blk - 1) / blk;
+    // rounds: consecutive blocks whose sigma slots fit the cap
+    std::vector<std::pair<int, int>> rounds;
+    for (int b0 = 0; b0 < nblk;) {
+        int b1 = b0 + 1;
+        while (b1 < nblk && (sym_sig_off(b1 + 1, T, blk) - sym_sig_off(b0, T, blk)) * SIG_VALS *
+                                    (int64_t)sizeof(double) <= sig_cap)
+            b1++;
+        rounds.emplace_back(b0, b1);
+        b0 = b1;
+    }
+    const int64_t nr = (int64_t)rounds.size();
     const double fixed = 2.0;
     int best_L = T;
     double best_cost = 1e300;
     std::vector<int> lens;
     // At about one item per slot the launch measured 8 % slower than the
     // schedule predicts (icosphere L5: 17.2 ms at 800 items, 15.9 ms at 1562
-    // on 768 slots), so lengths giving at least 1.5 items per slot are
-    // preferred where the mesh has enough pairs.
+    // on 768 slots), so lengths giving at least 1.5 items per slot and round
+    // are preferred where the mesh has enough pairs; each round is a launch
+    // of its own, so the cost is the sum of the rounds' makespans.
     int64_t max_items = 0;
     for (int b = 0; b < nblk; b++) max_items += (T - b * blk + FF_TILE - 1) / FF_TILE;
-    const int64_t min_items = std::min<int64_t>(3 * (int64_t)slots / 2, max_items);
+    const int64_t min_items = std::min<int64_t>(3 * (int64_t)slots / 2 * nr, max_items);
     for (int L = FF_TILE; L < T + FF_TILE; L += FF_TILE) {
         int64_t n_items = 0;
         for (int b = 0; b < nblk; b++) n_items += (T - b * blk + L - 1) / L;
         // beyond a few rounds finer chunks only add partial-buffer traffic
-        if (n_items > std::min<int64_t>(50000, 8 * (int64_t)slots)) continue;
-        if (n_items < min_items) continue;
-        lens.clear();
-        for (int b = 0; b < nblk; b++)
-            for (int lo = b * blk; lo < T; lo += L) lens.push_back(std::min(L, T - lo));
-        std::sort(lens.begin(), lens.end(), std::greater<int>());
-        std::priority_queue<double, std::vector<double>, std::greater<double>> q;
-        for (int i = 0; i < slots; i++) q.push(0.0);
-        double makespan = 0;
-        for (int len : lens) {
-            const double t = q.top() + len + fixed;
-            q.pop();
-            q.push(t);
-            makespan = std::max(makespan, t);
+        if (n_items > std::min<int64_t>(50000, 8 * (int64_t)slots * nr)) continue;
+        if (n_items < min_items) break;   // fewer items for every longer chunk
+        double cost = 0;
+        for (const auto &r : rounds) {
+            lens.clear();
+            for (int b = r.first; b < r.second; b++)
+                for (int lo = b * blk; lo < T; lo += L) lens.push_back(std::min(L, T - lo));
+            std::sort(lens.begin(), lens.end(), std::greater<int>());
+            std::priority_queue<double, std::vector<double>, std::greater<double>> q;
+            for (int i = 0; i < slots; i++) q.push(0.0);
+            double makespan = 0;
+            for (int len : lens) {
+                const double t = q.top() + len + fixed;
+                q.pop();
+                q.push(t);
+                makespan = std::max(makespan, t);
+            }
+            cost += makespan;
         }
-        if (makespan < best_cost * (1.0 - 1e-9)) {
-            best_cost = makespan;
+        if (cost < best_cost * (1.0 - 1e-9)) {
+            best_cost = cost;
             best_L = L;
         }
-        if (L >= 4096) break;
+        if (L >= 8192) break;
     }
     SymPlan p;
     p.blk = blk;
@@ -1517,11 +1533,8 @@ const SymPlan &sym_plan(int T, int blk, int slots) {
             all.push_back({std::min(best_L, T - lo), b, c, canon++});
     }
     size_t e0 = 0;
-    for (int b0 = 0; b0 < nblk;) {
-        int b1 = b0 + 1;
-        while (b1 < nblk && (sym_sig_off(b1 + 1, T, blk) - sym_sig_off(b0, T, blk)) * SIG_VALS *
-                                    (int64_t)sizeof(double) <= sig_cap)
-            b1++;
+    for (const auto &r : rounds) {
+        const int b0 = r.first, b1 = r.second;
         size_t e1 = e0;
         while (e1 < all.size() && all[e1][1] < b1) e1++;
         std::vector<std::array<int32_t, 4>> rd(all.begin() + e0, all.begin() + e1);
@@ -1539,7 +1552,6 @@ const SymPlan &sym_plan(int T, int blk, int slots) {
         p.sig_doubles = std::max(p.sig_doubles,
                                  (sym_sig_off(b1, T, blk) - sym_sig_off(b0, T, blk)) * SIG_VALS);
         e0 = e1;
-        b0 = b1;
     }
     p.tau_doubles = (int64_t)canon * blk * SIG_VALS;
     return cache.emplace(std::make_tuple(T, blk, slots, cap_mib), std::move(p)).first->second;

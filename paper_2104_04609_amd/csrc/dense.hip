@@ -388,7 +388,8 @@ __global__ __launch_bounds__(256) void dense_gemv1_kernel(const float2 *__restri
 // (-Im X_k, Re X_k) per right-hand side (columns 2r, 2r+1), so that columns
 // 2r and 2r+1 of the product are Re and Im of column r of B X.
 constexpr int GM = 128, GN = 128, GK = 32;   // block tile and K step
-constexpr int GKC = 4096;                    // split-K chunk (FP32 MFMA accumulation)
+constexpr int GKC = 4096;                    // largest split-K chunk (FP32 MFMA accumulation)
+constexpr int GKC_MIN = 1024;                // smallest split-K chunk
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
@@ -415,43 +416,59 @@ __global__ __launch_bounds__(256) void gemm_xprep_kernel(const double2 *__restri
 __global__ __launch_bounds__(256) void gemm_mfma_kernel(const float *__restrict__ A,
                                                         const float *__restrict__ Xp,
                                                         float *__restrict__ Yp, int64_t M,
-                                                        int64_t Kp, int Np) {
+                                                        int64_t Kp, int Np, int kchunk) {
     __shared__ float As[2][GM][GK + 1];
     __shared__ float Bs[2][GK][GN];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t m0 = (int64_t)blockIdx.x * GM;
     const int n0 = blockIdx.y * GN;
-    const int64_t kbeg = (int64_t)blockIdx.z * GKC;
-    const int64_t kend = kbeg + GKC < Kp ? kbeg + GKC : Kp;
+    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+    const int64_t kend = kbeg + kchunk < Kp ? kbeg + kchunk : Kp;
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
     floatx16 acc[2][2];
+#pragma unroll
     for (int i = 0; i < 2; i++)
+#pragma unroll
         for (int j = 0; j < 2; j++)
+#pragma unroll
             for (int v = 0; v < 16; v++) acc[i][j][v] = 0.f;
     // per thread: 4 float4 of the A tile (rows idx / 8, columns 4 (idx % 8)) and
-    // 4 float4 of the B tile (rows idx / 32, columns 4 (idx % 32)), idx = i 256 + t
-    float4 ra[4], rb[4];
+    // 4 float4 of the B tile (rows idx / 32, columns 4 (idx % 32)), idx = i 256 + t,
+    // held in named registers (no local array)
+    float4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+#define BEM_GEMM_LOAD_ONE(i, RA, RB)                                                            \
+    {                                                                                          \
+        const int idx = (i) * 256 + t;                                                         \
+        const int64_t gr = m0 + idx / 8, gc = k0 + 4 * (idx % 8);                              \
+        RA = (gr < M && gc < kend) ? *(const float4 *)(A + gr * Kp + gc) : zero4;              \
+        const int64_t br = k0 + idx / 32;                                                      \
+        RB = br < kend ? *(const float4 *)(Xp + br * Np + n0 + 4 * (idx % 32)) : zero4;        \
+    }
+#define BEM_GEMM_STORE_ONE(i, RA, RB)                                                           \
+    {                                                                                          \
+        const int idx = (i) * 256 + t;                                                         \
+        float *a = &As[buf][idx / 8][4 * (idx % 8)];                                           \
+        a[0] = RA.x;                                                                           \
+        a[1] = RA.y;                                                                           \
+        a[2] = RA.z;                                                                           \
+        a[3] = RA.w;                                                                           \
+        *(float4 *)&Bs[buf][idx / 32][4 * (idx % 32)] = RB;                                     \
+    }
     auto gload = [&](int64_t k0) {
-        for (int i = 0; i < 4; i++) {
-            const int idx = i * 256 + t;
-            const int64_t gr = m0 + idx / 8, gc = k0 + 4 * (idx % 8);
-            ra[i] = (gr < M && gc < kend) ? *(const float4 *)(A + gr * Kp + gc) : zero4;
-            const int64_t br = k0 + idx / 32;
-            rb[i] = br < kend ? *(const float4 *)(Xp + br * Np + n0 + 4 * (idx % 32)) : zero4;
-        }
+        BEM_GEMM_LOAD_ONE(0, ra0, rb0)
+        BEM_GEMM_LOAD_ONE(1, ra1, rb1)
+        BEM_GEMM_LOAD_ONE(2, ra2, rb2)
+        BEM_GEMM_LOAD_ONE(3, ra3, rb3)
     };
     auto lstore = [&](int buf) {
-        for (int i = 0; i < 4; i++) {
-            const int idx = i * 256 + t;
-            float *a = &As[buf][idx / 8][4 * (idx % 8)];
-            a[0] = ra[i].x;
-            a[1] = ra[i].y;
-            a[2] = ra[i].z;
-            a[3] = ra[i].w;
-            *(float4 *)&Bs[buf][idx / 32][4 * (idx % 32)] = rb[i];
-        }
+        BEM_GEMM_STORE_ONE(0, ra0, rb0)
+        BEM_GEMM_STORE_ONE(1, ra1, rb1)
+        BEM_GEMM_STORE_ONE(2, ra2, rb2)
+        BEM_GEMM_STORE_ONE(3, ra3, rb3)
     };
+#undef BEM_GEMM_LOAD_ONE
+#undef BEM_GEMM_STORE_ONE
     gload(kbeg);
     lstore(0);
     __syncthreads();
@@ -474,8 +491,11 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const float *__restrict_
         cur ^= 1;
     }
     float *Y = Yp + (int64_t)blockIdx.z * M * Np;
+#pragma unroll
     for (int i = 0; i < 2; i++)
+#pragma unroll
         for (int j = 0; j < 2; j++)
+#pragma unroll
             for (int v = 0; v < 16; v++) {
                 // 32x32 accumulator layout: column lane % 32, row
                 // 8 (v / 4) + 4 (lane / 32) + v % 4
@@ -840,9 +860,39 @@ void dense_gemv(const DenseOperator &op, const double2 *x, double2 *y, int R, De
 
 int64_t dense_gemm_scratch_bytes(const bem_mesh *m, int R) {
     const int64_t M = 2 * m->N, Kp = 2 * M;
-    const int64_t Np = 2 * (((int64_t)R + 63) / 64) * 64, nchunks = (Kp + GKC - 1) / GKC;
+    const int64_t Np = 2 * (((int64_t)R + 63) / 64) * 64, nchunks = (Kp + GKC_MIN - 1) / GKC_MIN;
     return (Kp * Np + nchunks * M * Np) * (int64_t)sizeof(float);
 }
+
+namespace {
+
+// Split-K chunk of the MFMA product: the multiple of the K step between
+// GKC_MIN and GKC whose grid fills the resident workgroup slots most evenly
+// (whole waves of workgroups), longer chunks preferred at equal fill.
+int gemm_kchunk(int64_t mtiles, int64_t Kp) {
+    static int slots = 0;
+    if (slots == 0) {
+        int dev = 0, cus = 0, per = 0;
+        BEM_HIP(hipGetDevice(&dev));
+        BEM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        BEM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gemm_mfma_kernel, 256, 0));
+        slots = std::max(1, cus * std::max(per, 1));
+    }
+    int best = GKC;
+    double best_fill = -1;
+    for (int kc = GKC; kc >= GKC_MIN; kc -= GK) {
+        const int64_t nch = (Kp + kc - 1) / kc;
+        const double waves = (double)(mtiles * nch) / slots;
+        const double fill = waves / std::ceil(waves);
+        if (fill > best_fill + 0.01) {
+            best_fill = fill;
+            best = kc;
+        }
+    }
+    return best;
+}
+
+}   // namespace
 
 void dense_apply(const DenseOperator &op, const double2 *x, double2 *y, int R,
                  DevBuf<float2> &xs, hipStream_t s, const TuneEntry *forced) {
@@ -864,7 +914,8 @@ void dense_apply(const DenseOperator &op, const double2 *x, double2 *y, int R,
 void dense_gemm(const DenseOperator &op, const double2 *x, double2 *y, int R, hipStream_t s) {
     const int64_t M = op.n2, K = op.n2, Kp = 2 * K;
     const int Rp = ((R + 63) / 64) * 64, Np = 2 * Rp;
-    const int nchunks = (int)((Kp + GKC - 1) / GKC);
+    const int kchunk = gemm_kchunk(((M + GM - 1) / GM) * (Np / GN), Kp);
+    const int nchunks = (int)((Kp + kchunk - 1) / kchunk);
     DevBuf<float> Xp((size_t)(Kp * Np));
     DevBuf<float> Yp((size_t)nchunks * M * Np);
     const int64_t prep = K * Rp;
@@ -875,7 +926,7 @@ void dense_gemm(const DenseOperator &op, const double2 *x, double2 *y, int R, hi
         Timer tm("dense_gemm_mfma", s);
         hipLaunchKernelGGL(gemm_mfma_kernel,
                            dim3((unsigned)((M + GM - 1) / GM), Np / GN, nchunks), dim3(256), 0, s,
-                           (const float *)op.B.p, Xp.p, Yp.p, M, Kp, Np);
+                           (const float *)op.B.p, Xp.p, Yp.p, M, Kp, Np, kchunk);
         BEM_LAUNCH_CHECK();
     }
     const int64_t red = M * R;

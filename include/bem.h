@@ -208,9 +208,9 @@ int bem_osrc_info(const bem_mesh *mesh, int pade_terms, double theta,
  *     min(n_rhs, 16) * ((pade_terms + 2) (2 n_vertices + P) +
  *     (pade_terms + 5) n_vertices) * 16 bytes must fit (BEM_E_INVAL
  *     otherwise), P the partial sums of the top rows of the two-part block
- *     solve when the mesh's OSRC state has one ("osrc.split"; a few thousand
- *     at 10 242 vertices), e.g. 8 vectors of 10 242 vertices with 4 Pade
- *     terms.  Nothing in it needs to start at zero.
+ *     solve when the mesh's OSRC state has one ("osrc.split" = 2; a few
+ *     thousand at 10 242 vertices, else 0), e.g. 8 vectors of 10 242
+ *     vertices with 4 Pade terms.  Nothing in it needs to start at zero.
  *   - Every call on one GPU uses that GPU's array: calls that overlap in time
  *     on one GPU (other streams, other threads) race; the caller serialises
  *     them.
@@ -538,23 +538,30 @@ int bem_profile_read(const char *kernel, double *total_ms, int64_t *launches);
  *                         1e-5, the paper's)
  *   "hmat.kmax"           largest rank of a block, 4..512 (default 128)
  *   "osrc.split"          OSRC block solves (keys read when a mesh handle
- *                         first builds its OSRC state): 2 solves the bottom
- *                         subtrees of the nested dissection in one workgroup
- *                         each (rows in LDS) and the top separators after
- *                         them (3 launches per solve when the top is small);
- *                         0 one launch per dissection level (two for the
- *                         levels of few, large blocks); 1 the two-part solve
- *                         above 16 384 vertices, and below it for batches of
- *                         8 vectors or more (top part level by level),
- *                         levels otherwise (default 1)
- *   "osrc.sub_rows"       largest bottom subtree in rows, 64..8192, 0 for
- *                         4096 or the device's LDS limit (default 0)
- *   "osrc.top_single_work" top part in one workgroup when its entries (L and
- *                         dense block inverses) are at most this many, else
- *                         level by level (default 300000)
+ *                         first builds its OSRC state): 1 (default) solves
+ *                         the bottom subtrees of the nested dissection in
+ *                         one workgroup each (rows in LDS), then the top
+ *                         separators one launch per dissection level (two
+ *                         for the levels of few, large blocks); plans with
+ *                         subtrees of up to 512, 1024, 2048 and 4096 rows,
+ *                         each batch taking the largest subtrees that still
+ *                         give 256 workgroups (subtrees x systems x
+ *                         vectors); 0 one launch per level throughout; 2 the
+ *                         two-part solve whose subtree workgroups also form
+ *                         the top rows' partial sums, the top part in one
+ *                         workgroup when small; 3 as 1 with the one plan of
+ *                         "osrc.bottom_rows"
+ *   "osrc.sub_rows"       largest subtree of "osrc.split" 2 in rows,
+ *                         64..8192, 0 for 4096 or the device's LDS limit
+ *                         (default 0)
+ *   "osrc.top_single_work" "osrc.split" 2: top part in one workgroup when
+ *                         its entries (L and dense block inverses) are at
+ *                         most this many, else level by level (default 300000)
+ *   "osrc.bottom_rows"    largest subtree of "osrc.split" 3 in rows, 64..8192
+ *                         (default 1024)
  * Results of a solve depend on these (the summation order changes), within
  * the FP32 accuracy; with "osrc.split" = 1 an OSRC apply's rounding also
- * depends on the batch size.  BEM_E_INVAL for an unknown key or value. */
+ * depends on the batch size and the number of Pade terms.  BEM_E_INVAL for an unknown key or value. */
 int bem_tune_set(const char *key, int64_t value);
 int bem_tune_get(const char *key, int64_t *value);
 

@@ -490,7 +490,7 @@ int bem_tune_set(const char *key, int64_t value) {
         if (value < 4 || value > 512) fail(BEM_E_INVAL, "hmat.kmax: 4..512");
         t.hmat_kmax = (int)value;
     } else if (k == "osrc.split") {
-        if (value < 0 || value > 2) fail(BEM_E_INVAL, "osrc.split: 0, 1 or 2");
+        if (value < 0 || value > 3) fail(BEM_E_INVAL, "osrc.split: 0, 1, 2 or 3");
         t.osrc_split = (int)value;
     } else if (k == "osrc.sub_rows") {
         if (value != 0 && (value < 64 || value > 8192)) fail(BEM_E_INVAL, "osrc.sub_rows: 0 or 64..8192");
@@ -498,6 +498,9 @@ int bem_tune_set(const char *key, int64_t value) {
     } else if (k == "osrc.top_single_work") {
         if (value < 0 || value > (int64_t)1 << 30) fail(BEM_E_INVAL, "osrc.top_single_work out of range");
         t.osrc_top_single_work = (int)value;
+    } else if (k == "osrc.bottom_rows") {
+        if (value != 0 && (value < 64 || value > 8192)) fail(BEM_E_INVAL, "osrc.bottom_rows: 0 or 64..8192");
+        t.osrc_bottom_rows = (int)value;
     } else {
         fail(BEM_E_INVAL, "unknown tuning key " + k);
     }
@@ -525,6 +528,7 @@ int bem_tune_get(const char *key, int64_t *value) {
     else if (k == "osrc.split") *value = t.osrc_split;
     else if (k == "osrc.sub_rows") *value = t.osrc_sub_rows;
     else if (k == "osrc.top_single_work") *value = t.osrc_top_single_work;
+    else if (k == "osrc.bottom_rows") *value = t.osrc_bottom_rows;
     else fail(BEM_E_INVAL, "unknown tuning key " + k);
     return BEM_OK;
     BEM_API_END

@@ -303,7 +303,10 @@ struct Tuning {
     std::atomic<int64_t> hmat_tol_ppb{10000}; // ACA tolerance, parts per 1e9 (1e-5)
     std::atomic<int> hmat_kmax{128};          // largest rank of a block
     // OSRC block solves (read when a mesh's OSRC symbolic state is built)
-    std::atomic<int> osrc_split{1};           // 0 levels, 1 automatic, 2 two-part when it fits
+    std::atomic<int> osrc_split{1};           // 0 levels, 1 bottom subtrees (plan per
+                                              // batch), 2 two-part with partial sums,
+                                              // 3 bottom subtrees of osrc_bottom_rows
+    std::atomic<int> osrc_bottom_rows{1024};  // largest subtree of the bottom-subtree schedule
     std::atomic<int> osrc_sub_rows{0};        // largest bottom subtree (rows); 0: 4096 or the LDS limit
     std::atomic<int> osrc_top_single_work{300000};   // top part in one workgroup up to this work
 };

@@ -35,11 +35,18 @@ namespace bem {
 void OsrcDeleter::operator()(OsrcState *p) const { delete p; }
 void OsrcSymDeleter::operator()(OsrcSymbolicState *p) const { delete p; }
 
+int64_t SplitSchedule::bytes() const {
+    return sub_r0.bytes() + sub_r1.bytes() + sub_hptr.bytes() + srow.bytes() + top_row.bytes() +
+           top_hptr.bytes() + tlist.bytes() + part_b.bytes() + part_e.bytes() + tf_ptr.bytes() +
+           tf_pos.bytes() + tf_col.bytes() + tb_ptr.bytes() + tb_pos.bytes() + tb_row.bytes() +
+           bsplit.bytes() + sdesc.bytes();
+}
 int64_t OsrcSymbolicState::bytes() const {
     return gptr_d.bytes() + gcol_d.bytes() + perm_d.bytes() + Rj_d.bytes() + Li_d.bytes() +
            bstart_d.bytes() + lbptr_d.bytes() + lblk_d.bytes() + lptr_d.bytes() + lrow_d.bytes() +
-           frange_d.bytes() +
-           brange_d.bytes() + doff_d.bytes() + Mv_d.bytes() + Sv_d.bytes();
+           frange_d.bytes() + brange_d.bytes() + doff_d.bytes() + blk_d.bytes() + Mv_d.bytes() +
+           Sv_d.bytes() + jrow_d.bytes() + lrowd_d.bytes() + lblkd_d.bytes() + split.bytes() +
+           bottom[0].bytes() + bottom[1].bytes() + bottom[2].bytes() + bottom[3].bytes();
 }
 int64_t OsrcState::bytes() const {
     return cvert.bytes() + ikv.bytes() + iikv.bytes() + Dinv.bytes() + Lcsr.bytes() +
@@ -174,21 +181,97 @@ OsrcSymbolicState &symbolic(bem_mesh *m) {
     st->brange_d.upload(br);
     st->doff_d.upload(doff);
     st->blk_d.upload(S.blk);
-    // two-part schedule: bottom subtrees in LDS, the top part in one
-    // workgroup when its own work is small, else level by level
+    // row and block descriptors (one load per row / block in the solve kernels)
+    if (S.ndense >= ((int64_t)1 << 31)) fail(BEM_E_UNSUPPORTED, "dense block inverses too large");
+    std::vector<LdlRow> jrow(n);
+    for (int j = 0; j < n; j++) {
+        const int b = S.blk[j], s0 = S.bstart[b];
+        jrow[j] = LdlRow{j, S.perm[j], s0, S.bstart[b + 1] - s0, S.Rp[j], S.fext[j], S.bext[j],
+                         S.Lp[j + 1], (int)S.doff[b], j - s0, 0, 0};
+    }
+    std::vector<LdlRow> lrowd(S.lrow.size());
+    for (size_t r = 0; r < S.lrow.size(); r++) lrowd[r] = jrow[S.lrow[r]];
+    std::vector<int4> lblkd(nb);
+    for (int i = 0; i < nb; i++) {
+        const int b = lblk[i];
+        lblkd[i] = make_int4(S.bstart[b], S.bstart[b + 1] - S.bstart[b], (int)S.doff[b], 0);
+    }
+    st->jrow_d.upload(jrow);
+    st->lrowd_d.upload(lrowd);
+    st->lblkd_d.upload(lblkd);
+    st->lptr_h = S.lptr;
+    st->lbptr_h = lbptr;
+    st->lext_f.assign(nl, 0);
+    st->lext_b.assign(nl, 0);
+    for (int l = 0; l < nl; l++)
+        for (int r = S.lptr[l]; r < S.lptr[l + 1]; r++) {
+            const int j = S.lrow[r];
+            st->lext_f[l] += S.fext[j] - S.Rp[j];
+            st->lext_b[l] += S.Lp[j + 1] - S.bext[j];
+        }
+    // two-part schedules: bottom subtrees in LDS, the top part by the level
+    // kernels (or, in the form with partial sums, in one workgroup when its
+    // own work is small, else level by level)
     st->wlen = 2 * (int64_t)n;   // y, z
     const Tuning &tn = tuning();
-    // automatic choice (measured on the 10 242- and 40 962-vertex meshes): one
-    // launch per level up to 16 384 vertices unless 8 or more vectors are
-    // solved at once, the two-part solve above
+    auto make_split = [&](SplitSchedule &sc, int sub_rows, bool top_levels) {
+        // rows of one height are staged in LDS next to the subtree's rows
+        const int phase =
+            std::min(4096, (int)((ldl_split_max_lds() - 16 * (int64_t)sub_rows - 32) / 20));
+        if (phase < 64) return;
+        LdlSplit P = ldl_split_plan(S, sub_rows, 8192, phase);
+        if (!P.ok || P.H > LDL_SPLIT_MAX_H) return;
+        int hrows = 0;
+        for (int q = 0; q < P.nsub * P.H; q++)
+            hrows = std::max(hrows, P.sub_hptr[q + 1] - P.sub_hptr[q]);
+        for (size_t q = 0; q + 1 < P.top_hptr.size(); q++)
+            hrows = std::max(hrows, P.top_hptr[q + 1] - P.top_hptr[q]);
+        sc.hrows = hrows;
+        sc.desc_lds = ldl_split_lds(P.max_sub_rows, hrows, P.max_sub_rows) <=
+                              (size_t)ldl_split_max_lds()
+                          ? 1
+                          : 0;
+        sc.top_levels = top_levels ? 1 : 0;
+        sc.sub_r0.upload(P.sub_r0);
+        sc.sub_r1.upload(P.sub_r1);
+        sc.sub_hptr.upload(P.sub_hptr);
+        sc.srow.upload(P.srow);
+        sc.bsplit.upload(P.bsplit);
+        if (!top_levels) {   // the top part's own tables and the partial sums
+            sc.top_row.upload(P.top_row);
+            sc.top_hptr.upload(P.top_hptr);
+            sc.tlist.upload(P.tlist);
+            sc.part_b.upload(P.part_b);
+            sc.part_e.upload(P.part_e);
+            sc.tf_ptr.upload(P.tf_ptr);
+            sc.tf_pos.upload(P.tf_pos);
+            sc.tf_col.upload(P.tf_col);
+            sc.tb_ptr.upload(P.tb_ptr);
+            sc.tb_pos.upload(P.tb_pos);
+            sc.tb_row.upload(P.tb_row);
+        }
+        std::vector<LdlRow> sd(P.srow.size());
+        for (size_t k = 0; k < P.srow.size(); k++) {
+            sd[k] = jrow[P.srow[k]];
+            sd[k].bsplit = P.bsplit[P.srow[k]];
+        }
+        sc.sdesc.upload(sd);
+        sc.plan = std::move(P);
+    };
+    // 1 (automatic; measured on the 10 242- and 40 962-vertex meshes): the
+    // bottom-subtree schedule with the top levels one launch per level; plans
+    // with subtrees of up to 512 .. 4096 rows, each batch taking the one with
+    // the largest subtrees that still gives OSRC_SUB_MIN_GROUPS workgroups.
+    // 2: the two-part solve with partial sums; 3: one bottom-subtree plan of
+    // up to osrc.bottom_rows rows
     const int split_mode = tn.osrc_split.load();
-    st->split_always = split_mode == 2 || n > 16384;
-    if (split_mode != 0) {
-        const int phase_rows = 4 * 1024;   // rows a 1024-thread workgroup keeps in registers
+    st->split_mode = split_mode;
+    if (split_mode == 2) {
         int sub_rows = std::min(ldl_split_max_sub_rows(), 4096);
         if (tn.osrc_sub_rows.load() > 0)
             sub_rows = std::min(ldl_split_max_sub_rows(), tn.osrc_sub_rows.load());
-        LdlSplit P = ldl_split_plan(S, sub_rows, 8192, phase_rows);
+        make_split(st->split, sub_rows, false);
+        const LdlSplit &P = st->split.plan;
         if (P.ok) {
             int64_t top_dense = 0;
             for (int b = 0; b < nb; b++)
@@ -197,62 +280,81 @@ OsrcSymbolicState &symbolic(bem_mesh *m) {
                     top_dense += w * w;
                 }
             const int64_t top_work = (int64_t)P.tf_pos.size() + (int64_t)P.tb_pos.size() + top_dense;
-            // (used for batches only, the top part runs level by level)
-            st->top_single = st->split_always && P.ntop <= ldl_split_max_sub_rows() &&
-                                     top_work <= tn.osrc_top_single_work.load()
-                                 ? 1
-                                 : 0;
-            st->sp_sub_r0.upload(P.sub_r0);
-            st->sp_sub_r1.upload(P.sub_r1);
-            st->sp_sub_hptr.upload(P.sub_hptr);
-            st->sp_srow.upload(P.srow);
-            st->sp_top_row.upload(P.top_row);
-            st->sp_top_hptr.upload(P.top_hptr);
-            st->sp_tlist.upload(P.tlist);
-            st->sp_part_b.upload(P.part_b);
-            st->sp_part_e.upload(P.part_e);
-            st->sp_tf_ptr.upload(P.tf_ptr);
-            st->sp_tf_pos.upload(P.tf_pos);
-            st->sp_tf_col.upload(P.tf_col);
-            st->sp_tb_ptr.upload(P.tb_ptr);
-            st->sp_tb_pos.upload(P.tb_pos);
-            st->sp_tb_row.upload(P.tb_row);
-            st->sp_bsplit.upload(P.bsplit);
+            st->split.top_single = ldl_split_lds(P.ntop, st->split.hrows, 0) <=
+                                               (size_t)ldl_split_max_lds() &&
+                                           top_work <= tn.osrc_top_single_work.load()
+                                       ? 1
+                                       : 0;
             st->wlen = 2 * (int64_t)n + (int64_t)P.nsub * P.ntop;
-            st->split = std::move(P);
         }
+    } else if (split_mode == 1) {
+        for (int rows = 512; rows <= 4096; rows *= 2) {
+            if (rows > ldl_split_max_sub_rows()) break;
+            SplitSchedule &sc = st->bottom[st->nbottom];
+            make_split(sc, rows, true);
+            if (!sc.plan.ok) continue;
+            // keep only plans that differ from the previous one
+            if (st->nbottom > 0 && st->bottom[st->nbottom - 1].plan.H == sc.plan.H) {
+                sc = SplitSchedule();
+                continue;
+            }
+            st->nbottom++;
+        }
+    } else if (split_mode == 3) {
+        const int rows = tn.osrc_bottom_rows.load();
+        make_split(st->bottom[0], std::min(ldl_split_max_sub_rows(), rows), true);
+        if (st->bottom[0].plan.ok) st->nbottom = 1;
     }
     m->osrc_sym = std::move(st);
     return *m->osrc_sym;
 }
 
-LdlSplitDev split_view(const OsrcSymbolicState &sy, int nrhs) {
+// Schedule of one batched block solve of `ntasks` systems and nrhs vectors:
+// a bottom-subtree plan, the two-part solve with partial sums or, with
+// ok = 0, one launch per level.
+LdlSplitDev split_view(const OsrcSymbolicState &sy, int ntasks, int nrhs) {
     LdlSplitDev P{};
-    const LdlSplit &q = sy.split;
-    P.ok = q.ok && (sy.split_always || nrhs >= OSRC_SPLIT_MIN_RHS) ? 1 : 0;
-    if (!P.ok) return P;
+    const SplitSchedule *sc = nullptr;
+    if (sy.split_mode == 2 && sy.split.plan.ok) {
+        sc = &sy.split;
+    } else if (sy.nbottom > 0) {
+        // largest subtrees that still fill the device; else the smallest
+        sc = &sy.bottom[0];
+        for (int i = sy.nbottom - 1; i >= 0; i--)
+            if ((int64_t)sy.bottom[i].plan.nsub * ntasks * nrhs >= OSRC_SUB_MIN_GROUPS) {
+                sc = &sy.bottom[i];
+                break;
+            }
+    }
+    if (!sc) return P;
+    const LdlSplit &q = sc->plan;
+    P.ok = 1;
+    P.top_levels = sc->top_levels;
     P.H = q.H;
     P.nsub = q.nsub;
     P.ntop = q.ntop;
     P.nht = q.ntop > 0 ? (int)q.top_hptr.size() - 1 : 0;
-    P.top_single = sy.top_single;
+    P.top_single = sc->top_single;
     P.sub_rows = q.max_sub_rows;
-    P.sub_r0 = sy.sp_sub_r0.p;
-    P.sub_r1 = sy.sp_sub_r1.p;
-    P.sub_hptr = sy.sp_sub_hptr.p;
-    P.srow = sy.sp_srow.p;
-    P.top_row = sy.sp_top_row.p;
-    P.top_hptr = sy.sp_top_hptr.p;
-    P.tlist = sy.sp_tlist.p;
-    P.part_b = sy.sp_part_b.p;
-    P.part_e = sy.sp_part_e.p;
-    P.tf_ptr = sy.sp_tf_ptr.p;
-    P.tf_pos = sy.sp_tf_pos.p;
-    P.tf_col = sy.sp_tf_col.p;
-    P.tb_ptr = sy.sp_tb_ptr.p;
-    P.tb_pos = sy.sp_tb_pos.p;
-    P.tb_row = sy.sp_tb_row.p;
-    P.bsplit = sy.sp_bsplit.p;
+    P.hrows = sc->hrows;
+    P.desc_lds = sc->desc_lds;
+    P.sub_r0 = sc->sub_r0.p;
+    P.sub_r1 = sc->sub_r1.p;
+    P.sub_hptr = sc->sub_hptr.p;
+    P.srow = sc->srow.p;
+    P.sdesc = sc->sdesc.p;
+    P.top_row = sc->top_row.p;
+    P.top_hptr = sc->top_hptr.p;
+    P.tlist = sc->tlist.p;
+    P.part_b = sc->part_b.p;
+    P.part_e = sc->part_e.p;
+    P.tf_ptr = sc->tf_ptr.p;
+    P.tf_pos = sc->tf_pos.p;
+    P.tf_col = sc->tf_col.p;
+    P.tb_ptr = sc->tb_ptr.p;
+    P.tb_pos = sc->tb_pos.p;
+    P.tb_row = sc->tb_row.p;
+    P.bsplit = sc->bsplit.p;
     return P;
 }
 
@@ -282,6 +384,13 @@ LdlDev ldl_view(const OsrcSymbolicState &sy, const OsrcState &st) {
     L.invLT = st.invLT.p;
     L.blk = sy.blk_d.p;
     L.wlen = sy.wlen;
+    L.jrow = sy.jrow_d.p;
+    L.lrowd = sy.lrowd_d.p;
+    L.lblkd = sy.lblkd_d.p;
+    L.lptr_h = sy.lptr_h.data();
+    L.lbptr_h = sy.lbptr_h.data();
+    L.lext_f = sy.lext_f.data();
+    L.lext_b = sy.lext_b.data();
     return L;
 }
 
@@ -464,7 +573,7 @@ void osrc_apply_from_weak(bem_mesh *m, OsrcState &st, const double2 *yw, double2
     const int64_t wl = sy.wlen;
     const int64_t n2 = 2 * (int64_t)n, os = (int64_t)(np + 3) * n, ws = (int64_t)(np + 2) * wl;
     double2 *ob = scr ? scr->obuf : st.obuf.p, *wk = scr ? scr->work : st.work.p;
-    const LdlSplitDev P = split_view(sy, R);
+    const LdlSplitDev P = split_view(sy, np + 2, R);
     double2 *u1 = ob + (size_t)np * n, *v = ob + (size_t)(np + 1) * n, *m2 = ob + (size_t)(np + 2) * n;
     Timer tm("osrc_apply", s);
     // stage 1: shifted solves and M^{-1} on y1 (DtN); (M - S/k_eps^2)^{-1} on y2 (NtD)
@@ -477,8 +586,8 @@ void osrc_apply_from_weak(bem_mesh *m, OsrcState &st, const double2 *yw, double2
     ta.work_stride = ws;
     launch_ldl_solve(L, P, ta, np + 2, R, s);
     // z1 = ik (C_0' M^{-1} y1 - sum_j (A_j/B_j) s_j);  m2 = M v
-    launch_pade_sum(n, st.pf, d2(ik), st.ikv.p, u1, os, ob, n, os, z, n2, R, s);
-    launch_spmv_real(n, R, sy.gptr_d.p, sy.gcol_d.p, sy.Mv_d.p, v, os, m2, os, s);
+    launch_pade_sum_spmv(n, st.pf, d2(ik), st.ikv.p, u1, os, ob, n, os, z, n2, R, sy.gptr_d.p,
+                         sy.gcol_d.p, sy.Mv_d.p, v, os, m2, os, R, s);
     // stage 2: shifted solves on M v (NtD)
     TaskList tb{};
     for (int j = 0; j < np; j++) tb.t[j] = SolveTask{j, m2, ob + (size_t)j * n, one, wk + j * wl};
@@ -511,7 +620,7 @@ void osrc_mass_solve(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y, i
         for (int b = 0; b < cnt; b++)
             t.t[b] = SolveTask{st.np + 1, x + (size_t)(b0 + b) * n, y + (size_t)(b0 + b) * n,
                                make_double2(1.0, 0.0), st.work.p + (size_t)b * sy.wlen};
-        launch_ldl_solve(L, split_view(sy, 1), t, cnt, 1, s);
+        launch_ldl_solve(L, split_view(sy, cnt, 1), t, cnt, 1, s);
     }
 }
 

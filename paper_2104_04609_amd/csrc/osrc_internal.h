@@ -14,12 +14,24 @@ struct PadeCoef {
     double2 A[PADE_MAX];
 };
 
-// Vectors per batch from which the two-part block solve replaces the level
-// schedule on meshes where it is not used for every batch.
-constexpr int OSRC_SPLIT_MIN_RHS = 8;
+// Workgroups (subtrees x systems x vectors) a bottom-subtree plan should
+// give to be chosen for a batch.
+constexpr int OSRC_SUB_MIN_GROUPS = 256;
 
 // Largest dissection block (rows) a level workgroup can hold in LDS.
 constexpr int LDL_MAX_BLOCK = 4096;
+
+// Everything a solve kernel needs about one row, in one 48-byte record (one
+// round trip instead of a chain of dependent index loads).
+struct alignas(16) LdlRow {
+    int j, perm, s0, w;    // row (new order), perm[j], first row and width of its block
+    int fx, fy, bx, by;    // forward CSR / backward CSC external entry ranges
+    int doff, rr, bsplit, pad;   // dense inverse offset of the block, row within the
+                                 // block, first CSC position in the top (two-part solve)
+};
+
+// Deepest subtree (heights) of the two-part solve.
+constexpr int LDL_SPLIT_MAX_H = 48;
 
 // Device view of the shared LDL^T structure plus the numeric factors.
 struct LdlDev {
@@ -47,7 +59,18 @@ struct LdlDev {
     const double2 *invLT;     // [factors][ndense]
     const int32_t *blk;       // row -> dissection block
     int64_t wlen;             // work length per system: n + partial sums of the split solve
+    const LdlRow *jrow;       // row descriptors by row j
+    const LdlRow *lrowd;      // row descriptors in level order (lrow)
+    const int4 *lblkd;        // blocks in level order (lblk): {s0, w, doff, 0}
+    const int32_t *lptr_h;    // host copies of lptr / lbptr (launch arguments)
+    const int32_t *lbptr_h;
+    const int64_t *lext_f;    // host: external entries of each level, forward / backward
+    const int64_t *lext_b;
 };
+
+// Levels whose rows average more external entries than this run their
+// external updates with one workgroup per row.
+constexpr int LDL_WIDE_EXT = 128;
 
 // Device view of the two-part schedule (LdlSplit): bottom subtrees solved
 // in LDS by one workgroup each, the top part by one workgroup (top_single)
@@ -56,8 +79,13 @@ struct LdlSplitDev {
     int ok;                   // 0: level-by-level solve only
     int H, nsub, ntop, nht;   // cut height, subtrees, top rows, top heights
     int top_single;           // 1: the top part in one workgroup
+    int top_levels;           // 1: the top part by the level kernels of the one-launch-
+                              // per-level schedule (no partial sums)
     int sub_rows;             // largest subtree (rows)
+    int hrows;                // most rows of one (subtree or top part, height)
+    int desc_lds;             // 1: the subtree kernels keep their rows' descriptors in LDS
     const int32_t *sub_r0, *sub_r1, *sub_hptr, *srow;
+    const LdlRow *sdesc;      // row descriptors in srow order (bsplit filled)
     const int32_t *top_row, *top_hptr, *tlist;
     const int32_t *part_b, *part_e;
     const int32_t *tf_ptr, *tf_pos, *tf_col, *tb_ptr, *tb_pos, *tb_row;
@@ -73,6 +101,19 @@ struct SolveTask {
     double2 *work;
 };
 
+// One two-part schedule and its device copies.
+struct SplitSchedule {
+    LdlSplit plan;
+    DevBuf<int32_t> sub_r0, sub_r1, sub_hptr, srow, top_row, top_hptr, tlist, part_b, part_e,
+        tf_ptr, tf_pos, tf_col, tb_ptr, tb_pos, tb_row, bsplit;
+    DevBuf<LdlRow> sdesc;
+    int top_single = 0;
+    int top_levels = 0;   // the top part by the level kernels (no partial sums)
+    int hrows = 0;   // most rows of one (subtree or top part, height)
+    int desc_lds = 0;   // row descriptors of a subtree fit in LDS
+    int64_t bytes() const;
+};
+
 // Mesh-level (parameter-independent) OSRC data: P1 vertex graph, mass and
 // stiffness values, ordering and symbolic LDL^T, and their device copies.
 struct OsrcSymbolicState {
@@ -85,14 +126,17 @@ struct OsrcSymbolicState {
     DevBuf<int64_t> doff_d;
     DevBuf<int32_t> blk_d;
     std::vector<int32_t> lbcount, lrcount;   // blocks and rows per level (host)
-    // two-part schedule of the block solves (empty if not ok)
-    LdlSplit split;
-    DevBuf<int32_t> sp_sub_r0, sp_sub_r1, sp_sub_hptr, sp_srow, sp_top_row, sp_top_hptr,
-        sp_tlist, sp_part_b, sp_part_e, sp_tf_ptr, sp_tf_pos, sp_tf_col, sp_tb_ptr, sp_tb_pos,
-        sp_tb_row, sp_bsplit;
-    int top_single = 0;
-    bool split_always = false;   // the two-part solve for any batch (else batches of
-                                 // OSRC_SPLIT_MIN_RHS vectors and more)
+    std::vector<int32_t> lptr_h, lbptr_h;
+    std::vector<int64_t> lext_f, lext_b;
+    DevBuf<LdlRow> jrow_d, lrowd_d;
+    DevBuf<int4> lblkd_d;
+    // two-part schedules of the block solves: `split` with partial sums of the
+    // top rows (osrc.split 2), `bottom` with the top part by the level kernels
+    // (nbottom plans of growing subtrees, osrc.split 1 and 3)
+    int split_mode = 1;
+    SplitSchedule split;
+    SplitSchedule bottom[4];
+    int nbottom = 0;
     int64_t wlen = 0;   // work length per system (n + partial sums)
     DevBuf<double> Mv_d, Sv_d;
     int64_t bytes() const;
@@ -131,11 +175,25 @@ void launch_ldl_solve(const LdlDev &L, const LdlSplitDev &P, TaskList tasks, int
                       int nrhs, hipStream_t s);
 // rows of LDS a bottom-subtree workgroup may hold on this device
 int ldl_split_max_sub_rows();
+// LDS of a split workgroup: `rows` rows, `hrows` staged dense results and
+// their indices, `desc_rows` row descriptors; the device's limit
+size_t ldl_split_lds(int rows, int hrows, int desc_rows);
+int ldl_split_max_lds();
+// offset (in double2 past the staged results) of the descriptors, 16-byte aligned
+__host__ __device__ inline int ldl_split_desc_off(int hrows) { return hrows + (hrows * 4 + 15) / 16; }
 // out_r = alpha (C0 u_r - sum_j A_j s_{r,j})   (elementwise, r < nrhs):
 // u_r = u + r ustride, s_{r,j} = sv + r vstride + j sstride, out_r = out + r ostride
 void launch_pade_sum(int n, const PadeCoef &pc, double2 alpha, const double2 *alpha_v,
                      const double2 *u, int64_t ustride, const double2 *sv, int64_t sstride,
                      int64_t vstride, double2 *out, int64_t ostride, int nrhs, hipStream_t s);
+// both in one launch: npade Pade sums and nspmv mass products
+// (mout_b = M in_b, in_b = in + b istride, mout_b = mout + b mstride)
+void launch_pade_sum_spmv(int n, const PadeCoef &pc, double2 alpha, const double2 *alpha_v,
+                          const double2 *u, int64_t ustride, const double2 *sv, int64_t sstride,
+                          int64_t vstride, double2 *out, int64_t ostride, int npade,
+                          const int32_t *gptr, const int32_t *gcol, const double *V,
+                          const double2 *in, int64_t istride, double2 *mout, int64_t mstride,
+                          int nspmv, hipStream_t s);
 // out_b = V in_b for b < nblk, in_b = in + b istride, out_b = out + b ostride
 void launch_spmv_real(int n, int nblk, const int32_t *gptr, const int32_t *gcol,
                       const double *V, const double2 *in, int64_t istride, double2 *out,

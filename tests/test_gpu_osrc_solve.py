@@ -59,20 +59,24 @@ def test_osrc_apply_matches_oracle(P, case):
         assert err <= 1e-10, err
 
 
-# schedules of the block solves: (osrc.split, osrc.sub_rows, osrc.top_single_work)
+# schedules of the block solves:
+# (osrc.split, osrc.sub_rows, osrc.top_single_work, osrc.bottom_rows)
 SCHEDULES = {
-    "levels": (0, 0, 300000),              # one launch per dissection level
-    "auto": (1, 0, 300000),                # the default (levels at these sizes)
-    "split_default": (2, 0, 300000),
-    "split_top_single": (2, 512, 1 << 30),  # many subtrees, big top in one workgroup
-    "split_top_levels": (2, 512, 0),        # many subtrees, top level by level
-    "split_tiny": (2, 64, 1 << 30),
+    "levels": (0, 0, 300000, 1024),            # one launch per dissection level
+    "auto": (1, 0, 300000, 1024),              # the default: bottom subtrees, plan per batch
+    "split_default": (2, 0, 300000, 1024),     # two-part with partial sums of the top rows
+    "split_top_single": (2, 512, 1 << 30, 1024),  # many subtrees, big top in one workgroup
+    "split_top_levels": (2, 512, 0, 1024),        # many subtrees, top level by level
+    "split_tiny": (2, 64, 1 << 30, 1024),
+    "bottom_1024": (3, 0, 300000, 1024),       # one bottom-subtree plan, top by level kernels
+    "bottom_tiny": (3, 0, 300000, 64),
+    "bottom_large": (3, 0, 300000, 4096),
 }
 
 
 @pytest.fixture
 def osrc_schedule(P):
-    keys = ("osrc.split", "osrc.sub_rows", "osrc.top_single_work")
+    keys = ("osrc.split", "osrc.sub_rows", "osrc.top_single_work", "osrc.bottom_rows")
     old = [P.tune_get(k) for k in keys]
 
     def set_(vals):

@@ -205,12 +205,14 @@ int bem_osrc_info(const bem_mesh *mesh, int pade_terms, double theta,
  *     done.
  *   - The work vectors of the sweeps live in a library-owned device array of
  *     BEM_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends:
- *     min(n_rhs, 16) * ((pade_terms + 2) (2 n_vertices + P) +
- *     (pade_terms + 5) n_vertices) * 16 bytes must fit (BEM_E_INVAL
- *     otherwise), P the partial sums of the top rows of the two-part block
- *     solve when the mesh's OSRC state has one ("osrc.split" = 2; a few
- *     thousand at 10 242 vertices, else 0), e.g. 8 vectors of 10 242
- *     vertices with 4 Pade terms.  Nothing in it needs to start at zero.
+ *     min(n_rhs, 16) * ((2 pade_terms + 2) (3 n_vertices + P) +
+ *     2 n_vertices) * 16 bytes must fit for pade_terms <= 16 (for more
+ *     terms, whose solves run in two stages, (pade_terms + 2) (2 n_vertices
+ *     + P) + (pade_terms + 5) n_vertices per vector; BEM_E_INVAL otherwise),
+ *     P the partial sums of the top rows of the two-part block solve when
+ *     the mesh's OSRC state has one ("osrc.split" = 2; a few thousand at
+ *     10 242 vertices, else 0), e.g. 8 vectors of 10 242 vertices with 4
+ *     Pade terms.  Nothing in it needs to start at zero.
  *   - Every call on one GPU uses that GPU's array: calls that overlap in time
  *     on one GPU (other streams, other threads) race; the caller serialises
  *     them.
@@ -544,13 +546,13 @@ int bem_profile_read(const char *kernel, double *total_ms, int64_t *launches);
  *                         separators one launch per dissection level (two
  *                         for the levels of few, large blocks); plans with
  *                         subtrees of up to 512, 1024, 2048 and 4096 rows,
- *                         each batch taking the largest subtrees that still
- *                         give 256 workgroups (subtrees x systems x
- *                         vectors); 0 one launch per level throughout; 2 the
- *                         two-part solve whose subtree workgroups also form
- *                         the top rows' partial sums, the top part in one
- *                         workgroup when small; 3 as 1 with the one plan of
- *                         "osrc.bottom_rows"
+ *                         each batch taking subtrees of up to 2048 rows, or
+ *                         larger ones when they still give 1024 workgroups
+ *                         (subtrees x systems x vectors); 0 one launch per
+ *                         level throughout; 2 the two-part solve whose
+ *                         subtree workgroups also form the top rows' partial
+ *                         sums, the top part in one workgroup when small; 3
+ *                         as 1 with the one plan of "osrc.bottom_rows"
  *   "osrc.sub_rows"       largest subtree of "osrc.split" 2 in rows,
  *                         64..8192, 0 for 4096 or the device's LDS limit
  *                         (default 0)

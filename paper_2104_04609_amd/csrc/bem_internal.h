@@ -444,6 +444,8 @@ struct OsrcScratch {
 int64_t osrc_scratch_per_rhs(const bem_mesh *m, int np);
 // work entries of one system of the solves (n + partial sums); state must exist
 int64_t osrc_work_len(const bem_mesh *m);
+// the scratch of `batch` right-hand sides laid out from base
+OsrcScratch osrc_scratch_at(const bem_mesh *m, int np, int batch, double2 *base);
 // R right-hand sides, [R][2N] contiguous each
 void osrc_apply_strong(bem_mesh *m, OsrcState &st, const double2 *x, double2 *y, int R,
                        hipStream_t s, const OsrcScratch *scr = nullptr);

@@ -68,15 +68,11 @@ extern "C" int osrc_apply_noalloc(const bem_mesh *mesh, int pade_terms, double t
         const int64_t cap = (int64_t)(NOALLOC_SCRATCH_BYTES / sizeof(double2));
         if ((int64_t)batch * per > cap)
             bem::fail(BEM_E_INVAL,
-                      "min(n_rhs, 16) * ((pade_terms + 2) (2 n_vertices + P) + "
-                      "(pade_terms + 5) n_vertices) * 16 bytes = " +
+                      "the work vectors of min(n_rhs, 16) right-hand sides need " +
                           std::to_string((int64_t)batch * per * 16) +
-                          " exceeds the no-allocation scratch of " +
+                          " bytes, which exceeds the no-allocation scratch of " +
                           std::to_string(NOALLOC_SCRATCH_BYTES) + " bytes");
-        double2 *base = scratch_ptr();
-        const int64_t wl = bem::osrc_work_len(m);
-        double2 *obuf = base + (int64_t)batch * (pade_terms + 2) * wl;
-        const bem::OsrcScratch scr{base, obuf, obuf + (int64_t)batch * (pade_terms + 3) * n};
+        const bem::OsrcScratch scr = bem::osrc_scratch_at(m, pade_terms, batch, scratch_ptr());
         const bem::NoTimerScope no_events;
         hipStream_t s = (hipStream_t)hip_stream;
         for (int r0 = 0; r0 < n_rhs; r0 += batch)

@@ -54,11 +54,19 @@ int64_t OsrcState::bytes() const {
            wbuf.bytes();
 }
 
+// Both operators' solves in one batch (2 N_p + 2 systems) when the task
+// list holds them, else two stages (N_p + 2, then N_p systems).
+bool osrc_one_stage(int np) { return 2 * np + 2 <= PADE_MAX + 2; }
+int osrc_tasks(int np) { return osrc_one_stage(np) ? 2 * np + 2 : np + 2; }
+// solve outputs per right-hand side: one stage s_0..s_{np-1}, u, s'_0..
+// s'_{np-1}, v; two stages s_0..s_{np-1}, u, v, M v
+int64_t osrc_obuf_len(int np, int64_t n) { return (osrc_one_stage(np) ? 2 * np + 2 : np + 3) * n; }
+
 void OsrcState::ensure_batch(int R) {
     if (R <= batch) return;
     const size_t n = cvert.n;
-    work.alloc((size_t)R * (np + 2) * wlen);
-    obuf.alloc((size_t)R * (np + 3) * n);
+    work.alloc((size_t)R * osrc_tasks(np) * wlen);
+    obuf.alloc((size_t)R * osrc_obuf_len(np, n));
     wbuf.alloc((size_t)R * 2 * n);
     batch = R;
 }
@@ -82,14 +90,14 @@ OsrcStats osrc_stats(const bem_mesh *m, const OsrcState &st) {
                      st.invLT.bytes();
     // one single-vector apply: per block solve the off-block entries of L (rows)
     // and L^T (columns) with their indices, both dense inverses, D^{-1}, the
-    // input and the output; three mass products (8-byte values, column
-    // indices, row pointers, input, output); two Pade sums (np + 1 inputs,
-    // one output)
+    // input and the output; two mass products (three with two stages; 8-byte
+    // values, column indices, row pointers, input, output); two Pade sums
+    // (np + 1 inputs, one output)
     const int64_t c16 = 16, n = o.n;
     const int64_t per_solve = 2 * o.nnz_ext * (c16 + 4) + 2 * o.ndense * c16 + n * c16 + 2 * n * c16;
     const int64_t spmv = o.mass_nnz * 12 + (n + 1) * 4 + 2 * n * c16;
     const int64_t sums = (int64_t)(st.np + 2) * n * c16;
-    o.bytes_per_apply = o.solves * per_solve + 3 * spmv + 2 * sums;
+    o.bytes_per_apply = o.solves * per_solve + (osrc_one_stage(st.np) ? 2 : 3) * spmv + 2 * sums;
     return o;
 }
 int64_t osrc_sym_bytes(const OsrcSymbolicState &st) { return st.bytes(); }
@@ -260,8 +268,9 @@ OsrcSymbolicState &symbolic(bem_mesh *m) {
     };
     // 1 (automatic; measured on the 10 242- and 40 962-vertex meshes): the
     // bottom-subtree schedule with the top levels one launch per level; plans
-    // with subtrees of up to 512 .. 4096 rows, each batch taking the one with
-    // the largest subtrees that still gives OSRC_SUB_MIN_GROUPS workgroups.
+    // with subtrees of up to 512 .. 4096 rows, each batch taking the one of
+    // up to OSRC_SUB_ROWS rows, or a larger one when that still gives
+    // OSRC_SUB_MIN_GROUPS workgroups.
     // 2: the two-part solve with partial sums; 3: one bottom-subtree plan of
     // up to osrc.bottom_rows rows
     const int split_mode = tn.osrc_split.load();
@@ -293,6 +302,7 @@ OsrcSymbolicState &symbolic(bem_mesh *m) {
             SplitSchedule &sc = st->bottom[st->nbottom];
             make_split(sc, rows, true);
             if (!sc.plan.ok) continue;
+            sc.rows = rows;
             // keep only plans that differ from the previous one
             if (st->nbottom > 0 && st->bottom[st->nbottom - 1].plan.H == sc.plan.H) {
                 sc = SplitSchedule();
@@ -318,9 +328,12 @@ LdlSplitDev split_view(const OsrcSymbolicState &sy, int ntasks, int nrhs) {
     if (sy.split_mode == 2 && sy.split.plan.ok) {
         sc = &sy.split;
     } else if (sy.nbottom > 0) {
-        // largest subtrees that still fill the device; else the smallest
+        // subtrees of up to OSRC_SUB_ROWS rows, larger ones while they still
+        // give OSRC_SUB_MIN_GROUPS workgroups
         sc = &sy.bottom[0];
-        for (int i = sy.nbottom - 1; i >= 0; i--)
+        for (int i = 0; i < sy.nbottom; i++)
+            if (sy.bottom[i].rows <= OSRC_SUB_ROWS) sc = &sy.bottom[i];
+        for (int i = sy.nbottom - 1; i >= 0 && sy.bottom[i].rows > sc->rows; i--)
             if ((int64_t)sy.bottom[i].plan.nsub * ntasks * nrhs >= OSRC_SUB_MIN_GROUPS) {
                 sc = &sy.bottom[i];
                 break;
@@ -405,7 +418,7 @@ int64_t osrc_state_bytes(bem_mesh *m, int np, int R) {
     // right-hand side work, outputs and weak vectors; complex128 each
     return (int64_t)sizeof(double2) *
            (n + nf * (n + 2 * nnz + 2 * nd) +
-            (int64_t)R * ((np + 2) * sy.wlen + ((np + 3) + 2) * n));
+            (int64_t)R * (osrc_tasks(np) * sy.wlen + osrc_obuf_len(np, n) + 2 * n));
 }
 
 // Cache key of a state; k_obj with equal entries collapses to k (set to
@@ -447,7 +460,13 @@ int64_t osrc_work_len(const bem_mesh *m) { return m->osrc_sym->wlen; }
 
 int64_t osrc_scratch_per_rhs(const bem_mesh *m, int np) {
     const int64_t n = m->osrc_sym->n, wlen = m->osrc_sym->wlen;
-    return (np + 2) * wlen + ((np + 3) + 2) * n;
+    return osrc_tasks(np) * wlen + osrc_obuf_len(np, n) + 2 * n;
+}
+
+OsrcScratch osrc_scratch_at(const bem_mesh *m, int np, int batch, double2 *base) {
+    const int64_t n = m->osrc_sym->n, wlen = m->osrc_sym->wlen;
+    double2 *obuf = base + (int64_t)batch * osrc_tasks(np) * wlen;
+    return OsrcScratch{base, obuf, obuf + (int64_t)batch * osrc_obuf_len(np, n)};
 }
 
 OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
@@ -488,6 +507,18 @@ OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
         st->pf.A[j] = d2(A[j] / B[j]);
     }
     st->pf.C0 = d2(C0p);
+    // R(X)(I + X)^{-1} in partial fractions over (I + X)^{-1} and the same
+    // shifts (B_j != 1 for b_j < 1):  [C_0 - sum_j A_j/(1 - B_j)] (I + X)^{-1}
+    // + sum_j A_j/(1 - B_j) (I + B_j X)^{-1}; kept as C_0 - sum_j A_j s_j with
+    // the signs of the Pade sum kernel
+    cdd D0 = C0;
+    st->qf.np = np;
+    for (int j = 0; j < np; j++) {
+        const cdd E = A[j] / (1.0 - B[j]);
+        D0 -= E;
+        st->qf.A[j] = d2(-E);
+    }
+    st->qf.C0 = d2(D0);
     st->B.resize(np);
     for (int j = 0; j < np; j++) st->B[j] = d2(B[j]);
     // 1/k_eps^2 per vertex (object)
@@ -563,19 +594,39 @@ OsrcState &osrc_get(bem_mesh *m, int np, double theta, double2 k,
 void osrc_apply_from_weak(bem_mesh *m, OsrcState &st, const double2 *yw, double2 *z, int R,
                           hipStream_t s, const OsrcScratch *scr) {
     OsrcSymbolicState &sy = *m->osrc_sym;
-    const int n = sy.n, np = st.np;
+    const int n = sy.n, np = st.np, nt = osrc_tasks(np);
     if (!scr) st.ensure_batch(R);
     const LdlDev L = ldl_view(sy, st);
     const cdd ik = cdd(0, 1) * cdd(st.k.x, st.k.y);
     const double2 one = make_double2(1.0, 0.0);
-    // right-hand side r: yw + r 2n in, z + r 2n out, obuf + r (np + 3) n,
-    // work + r (np + 2) n
+    // right-hand side r: yw + r 2n in, z + r 2n out, obuf + r os, work + r ws
     const int64_t wl = sy.wlen;
-    const int64_t n2 = 2 * (int64_t)n, os = (int64_t)(np + 3) * n, ws = (int64_t)(np + 2) * wl;
+    const int64_t n2 = 2 * (int64_t)n, os = osrc_obuf_len(np, n), ws = (int64_t)nt * wl;
     double2 *ob = scr ? scr->obuf : st.obuf.p, *wk = scr ? scr->work : st.work.p;
-    const LdlSplitDev P = split_view(sy, np + 2, R);
-    double2 *u1 = ob + (size_t)np * n, *v = ob + (size_t)(np + 1) * n, *m2 = ob + (size_t)(np + 2) * n;
+    const LdlSplitDev P = split_view(sy, nt, R);
+    double2 *u1 = ob + (size_t)np * n;
     Timer tm("osrc_apply", s);
+    if (osrc_one_stage(np)) {
+        // DtN: shifted solves and M^{-1} on y1; NtD: the same shifts and
+        // (M - S/k_eps^2)^{-1} on y2 (R(X)(I + X)^{-1} in partial fractions)
+        double2 *s2 = ob + (size_t)(np + 1) * n, *v = ob + (size_t)(2 * np + 1) * n;
+        TaskList ta{};
+        for (int j = 0; j < np; j++) {
+            ta.t[j] = SolveTask{j, yw, ob + (size_t)j * n, one, wk + j * wl};
+            ta.t[np + 1 + j] = SolveTask{j, yw + n, s2 + (size_t)j * n, one, wk + (np + 1 + j) * wl};
+        }
+        ta.t[np] = SolveTask{np + 1, yw, u1, one, wk + np * wl};
+        ta.t[2 * np + 1] = SolveTask{np, yw + n, v, one, wk + (2 * np + 1) * wl};
+        ta.in_stride = n2;
+        ta.out_stride = os;
+        ta.work_stride = ws;
+        launch_ldl_solve(L, P, ta, nt, R, s);
+        // z1 = ik (C_0' u - sum_j (A_j/B_j) s_j);  z2 = (1/ik) (D_0 v + sum_j E_j s'_j)
+        launch_pade_pair(n, st.pf, d2(ik), st.ikv.p, u1, os, ob, n, os, z, n2, st.qf,
+                         d2(1.0 / ik), st.iikv.p, v, s2, z + n, R, s);
+        return;
+    }
+    double2 *v = ob + (size_t)(np + 1) * n, *m2 = ob + (size_t)(np + 2) * n;
     // stage 1: shifted solves and M^{-1} on y1 (DtN); (M - S/k_eps^2)^{-1} on y2 (NtD)
     TaskList ta{};
     for (int j = 0; j < np; j++) ta.t[j] = SolveTask{j, yw, ob + (size_t)j * n, one, wk + j * wl};

@@ -14,9 +14,11 @@ struct PadeCoef {
     double2 A[PADE_MAX];
 };
 
-// Workgroups (subtrees x systems x vectors) a bottom-subtree plan should
-// give to be chosen for a batch.
-constexpr int OSRC_SUB_MIN_GROUPS = 256;
+// Bottom-subtree plan of a batch: subtrees of up to OSRC_SUB_ROWS rows, or
+// larger ones when they still give OSRC_SUB_MIN_GROUPS workgroups (subtrees
+// x systems x vectors).
+constexpr int OSRC_SUB_ROWS = 2048;
+constexpr int OSRC_SUB_MIN_GROUPS = 1024;
 
 // Largest dissection block (rows) a level workgroup can hold in LDS.
 constexpr int LDL_MAX_BLOCK = 4096;
@@ -109,6 +111,7 @@ struct SplitSchedule {
     DevBuf<LdlRow> sdesc;
     int top_single = 0;
     int top_levels = 0;   // the top part by the level kernels (no partial sums)
+    int rows = 0;         // subtree rows the plan was made for
     int hrows = 0;   // most rows of one (subtree or top part, height)
     int desc_lds = 0;   // row descriptors of a subtree fit in LDS
     int64_t bytes() const;
@@ -148,6 +151,7 @@ struct OsrcState {
     double2 k{0, 0};
     PadeCoef pc{};               // C_0, A_j of the Pade approximant
     PadeCoef pf{};               // partial fractions: C_0', A_j / B_j
+    PadeCoef qf{};               // R(X)(I + X)^{-1} over (I + X)^{-1} and the shifts
     std::vector<double2> B;      // Pade B_j
     int nfactors = 0;            // np shifts, (M - S/k_eps^2), M
     DevBuf<double2> cvert;       // 1/k_eps^2 of each vertex's object
@@ -194,6 +198,14 @@ void launch_pade_sum_spmv(int n, const PadeCoef &pc, double2 alpha, const double
                           const int32_t *gptr, const int32_t *gcol, const double *V,
                           const double2 *in, int64_t istride, double2 *mout, int64_t mstride,
                           int nspmv, hipStream_t s);
+// two Pade sums per right-hand side in one launch: out_r = alpha (C0 u_r -
+// sum_j A_j s_{r,j}) by pc (s_{r,j} = sv + r ostride + j sstride) and out2_r
+// likewise by pc2 from u2, sv2 (same strides)
+void launch_pade_pair(int n, const PadeCoef &pc, double2 alpha, const double2 *alpha_v,
+                      const double2 *u, int64_t ustride, const double2 *sv, int64_t sstride,
+                      int64_t vstride, double2 *out, int64_t ostride, const PadeCoef &pc2,
+                      double2 alpha2, const double2 *alpha2_v, const double2 *u2,
+                      const double2 *sv2, double2 *out2, int nrhs, hipStream_t s);
 // out_b = V in_b for b < nblk, in_b = in + b istride, out_b = out + b ostride
 void launch_spmv_real(int n, int nblk, const int32_t *gptr, const int32_t *gcol,
                       const double *V, const double2 *in, int64_t istride, double2 *out,

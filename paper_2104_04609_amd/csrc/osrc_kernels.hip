@@ -566,6 +566,17 @@ __global__ __launch_bounds__(256) void pade_spmv_kernel(int n, int npade, PadeAr
     else spmv_row(i, y - npade, ma);
 }
 
+// Two Pade sums per right-hand side: by pa for blockIdx.y < nrhs, by pb for
+// right-hand side blockIdx.y - nrhs.
+__global__ __launch_bounds__(256) void pade_pair_kernel(int n, int nrhs, PadeArgs pa,
+                                                        PadeArgs pb) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int y = blockIdx.y;
+    if (y < nrhs) pade_sum_row(i, y, pa);
+    else pade_sum_row(i, y - nrhs, pb);
+}
+
 }   // namespace
 
 int ldl_split_max_lds() {
@@ -693,6 +704,18 @@ void launch_pade_sum_spmv(int n, const PadeCoef &pc, double2 alpha, const double
     const SpmvArgs ma{gptr, gcol, V, in, istride, mout, mstride};
     hipLaunchKernelGGL(pade_spmv_kernel, dim3((n + 255) / 256, npade + nspmv), dim3(256), 0, s, n,
                        npade, pa, ma);
+    BEM_LAUNCH_CHECK();
+}
+
+void launch_pade_pair(int n, const PadeCoef &pc, double2 alpha, const double2 *alpha_v,
+                      const double2 *u, int64_t ustride, const double2 *sv, int64_t sstride,
+                      int64_t vstride, double2 *out, int64_t ostride, const PadeCoef &pc2,
+                      double2 alpha2, const double2 *alpha2_v, const double2 *u2,
+                      const double2 *sv2, double2 *out2, int nrhs, hipStream_t s) {
+    const PadeArgs pa{pc, alpha, alpha_v, u, sv, ustride, sstride, vstride, out, ostride};
+    const PadeArgs pb{pc2, alpha2, alpha2_v, u2, sv2, ustride, sstride, vstride, out2, ostride};
+    hipLaunchKernelGGL(pade_pair_kernel, dim3((n + 255) / 256, 2 * nrhs), dim3(256), 0, s, n,
+                       nrhs, pa, pb);
     BEM_LAUNCH_CHECK();
 }
 

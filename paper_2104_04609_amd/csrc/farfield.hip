@@ -58,6 +58,20 @@ __host__ __device__ constexpr double qw(int i) { return i < 3 ? DUN_W1 : DUN_W2;
 __host__ __device__ constexpr double qb(int i, int a) {
     return (a == i % 3) ? (1.0 - 2.0 * (i < 3 ? DUN_A1 : DUN_A2)) : (i < 3 ? DUN_A1 : DUN_A2);
 }
+// FP32 roundings of the weight products, read with a point index j that is
+// uniform over the wavefront (a loop counter) through the scalar cache, so
+// that no FP64 arithmetic or selects run per point pair:
+// kQW2[6 j + i] = (float)(qw(i) qw(j)), kQWB[3 j + a] = (float)(qw(j) qb(j, a)).
+#define BEM_QW2_ROW(j)                                                                       \
+    (float)(qw(0) * qw(j)), (float)(qw(1) * qw(j)), (float)(qw(2) * qw(j)),                 \
+        (float)(qw(3) * qw(j)), (float)(qw(4) * qw(j)), (float)(qw(5) * qw(j))
+#define BEM_QWB_ROW(j) (float)(qw(j) * qb(j, 0)), (float)(qw(j) * qb(j, 1)), (float)(qw(j) * qb(j, 2))
+__constant__ float kQW2[36] = {BEM_QW2_ROW(0), BEM_QW2_ROW(1), BEM_QW2_ROW(2),
+                               BEM_QW2_ROW(3), BEM_QW2_ROW(4), BEM_QW2_ROW(5)};
+__constant__ float kQWB[18] = {BEM_QWB_ROW(0), BEM_QWB_ROW(1), BEM_QWB_ROW(2),
+                               BEM_QWB_ROW(3), BEM_QWB_ROW(4), BEM_QWB_ROW(5)};
+#undef BEM_QW2_ROW
+#undef BEM_QWB_ROW
 
 // ---------------------------------------------------------------- math
 template <class R> struct Math;
@@ -663,6 +677,8 @@ void farfield_sym_kernel(
                 // slots instead of 9 %), which outweighs the loop overhead
 #pragma unroll 1
                 for (int j = 0; j < 6; j++) {
+                    // j is the same on every lane: the weight selects stay scalar
+                    const int ju = __builtin_amdgcn_readfirstlane(j);
                     const R yx = src[3 * j], yy = src[3 * j + 1], yz = src[3 * j + 2];
                     const R spr = src[GEO_STRIDE + 2 * j], spi = src[GEO_STRIDE + 2 * j + 1];
                     const R sfr = src[GEO_STRIDE + 12 + 2 * j], sfi = src[GEO_STRIDE + 12 + 2 * j + 1];
@@ -743,7 +759,7 @@ void farfield_sym_kernel(
                         a1i[i] = t1i;
                         a2r[i] = t2r;
                         a2i[i] = t2i;
-                        const R ww = (R)(qw(i) * qw(j));
+                        const R ww = kQW2[6 * ju + i];
                         gwr = fmac(ww, GWr, gwr);
                         gwi = fmac(ww, GWi, gwi);
                         // sigma at y_j: sums over i of G_V s_psi(x_i), F s_phi(x_i),
@@ -773,7 +789,7 @@ void farfield_sym_kernel(
                     r2i = fmac(-gni, nr, r2i);
 #pragma unroll
                     for (int a = 0; a < 3; a++) {
-                        const R wb = (R)(qw(j) * qb(j, a));
+                        const R wb = kQWB[3 * ju + a];
                         o[2 * a] = fmac(wb, r1r, o[2 * a]);
                         o[2 * a + 1] = fmac(wb, r1i, o[2 * a + 1]);
                         o[6 + 2 * a] = fmac(wb, r2r, o[6 + 2 * a]);

@@ -2,7 +2,9 @@
 against the FP64 oracle, through the C ABI.
 
 * osrc_apply (strong form, diag(L_DtN, L_NtD)) element by element, <= 1e-10,
-  for N_p = 4 and 8, real and lossy wavenumbers, one and two objects.
+  for N_p = 1, 4, 8, 16 (both operators' solves in one batch; 16 is the
+  largest such batch) and 20 (two stages), real and lossy wavenumbers, one
+  and two objects.
 * pmchwt_solve FP64: the solution agrees with the oracle's GMRES solution to
   the accuracy both solves reach; iteration counts agree within 2 (several
   solutions of the rounding are valid; the discrete solution is unique).
@@ -37,6 +39,8 @@ OSRC_CASES = {
     "ico2_np1_theta0": (lambda: icosphere(2), 2.0, 1, 0.0, 0.5),
     "two_spheres2": (lambda: two_spheres(2, offset=1.5), 4.0, 4, np.pi / 3, 0.1),
     "ico5_np4": (lambda: icosphere(5), 15.0, 4, np.pi / 3, 0.1),
+    "ico3_np16_lossy": (lambda: icosphere(3), 5.0 + 0.2j, 16, np.pi / 3, 0.1),
+    "ico3_np20_two_stages": (lambda: icosphere(3), 5.0, 20, np.pi / 4, 0.1),
 }
 
 

@@ -122,9 +122,9 @@ int64_t bem_mesh::device_bytes() const {
                 dyn64.bytes() + dyn32.bytes() + partial.bytes() + trirows.bytes() +
                 sym_items.bytes() + P_d.bytes();
     for (const auto &kv : near_cache) b += kv.second->vals.bytes();
-    for (const auto &kv : dense_cache) b += kv.second->B.bytes();
-    for (const auto &kv : dense64_cache) b += kv.second->B64.bytes();
-    for (const auto &kv : dense_rounded_cache) b += kv.second->B.bytes();
+    for (const auto &kv : dense_cache) b += kv.second->bytes();
+    for (const auto &kv : dense64_cache) b += kv.second->bytes();
+    for (const auto &kv : dense_rounded_cache) b += kv.second->bytes();
     for (const auto &kv : hmat_cache) b += bem::hmat_bytes(*kv.second);
     b += xs32.bytes();
     for (const auto &kv : osrc_cache) b += bem::osrc_bytes(*kv.second);

@@ -155,6 +155,17 @@ struct DenseOperator {
     bool fp64 = false;         // B64 (complex128) instead of B (complex64)
     DevBuf<float2> B;
     DevBuf<double2> B64;
+    // Split-K workspace of the MFMA product, kept between calls: a freshly
+    // allocated one costs the product 5-10 % (first use of its pages).  One
+    // call at a time holds it (until its kernels have finished); a concurrent
+    // call on the same operator allocates its own.
+    struct GemmWork {
+        std::mutex mu;
+        DevBuf<float> Xp, Yp;
+        std::atomic<int64_t> held{0};
+    };
+    std::unique_ptr<GemmWork> gw = std::make_unique<GemmWork>();
+    int64_t bytes() const { return B.bytes() + B64.bytes() + gw->held.load(); }
 };
 
 // Assembled operators: complex64 from the FP32 assembly, complex128 from the

@@ -916,23 +916,42 @@ void dense_gemm(const DenseOperator &op, const double2 *x, double2 *y, int R, hi
     const int Rp = ((R + 63) / 64) * 64, Np = 2 * Rp;
     const int kchunk = gemm_kchunk(((M + GM - 1) / GM) * (Np / GN), Kp);
     const int nchunks = (int)((Kp + kchunk - 1) / kchunk);
-    DevBuf<float> Xp((size_t)(Kp * Np));
-    DevBuf<float> Yp((size_t)nchunks * M * Np);
+    const size_t nx = (size_t)(Kp * Np), ny = (size_t)nchunks * M * Np;
+    // the operator's workspace when no other call holds it, else our own
+    DenseOperator::GemmWork &w = *op.gw;
+    std::unique_lock<std::mutex> lk(w.mu, std::try_to_lock);
+    DevBuf<float> own_x, own_y;
+    float *Xp, *Yp;
+    if (lk.owns_lock()) {
+        if (w.Xp.n < nx) w.Xp.alloc(nx);
+        if (w.Yp.n < ny) w.Yp.alloc(ny);
+        w.held = w.Xp.bytes() + w.Yp.bytes();
+        Xp = w.Xp.p;
+        Yp = w.Yp.p;
+    } else {
+        own_x.alloc(nx);
+        own_y.alloc(ny);
+        Xp = own_x.p;
+        Yp = own_y.p;
+    }
     const int64_t prep = K * Rp;
     hipLaunchKernelGGL(gemm_xprep_kernel, dim3((unsigned)((prep + 255) / 256)), dim3(256), 0, s, x,
-                       R, K, Np, Xp.p);
+                       R, K, Np, Xp);
     BEM_LAUNCH_CHECK();
     {
         Timer tm("dense_gemm_mfma", s);
         hipLaunchKernelGGL(gemm_mfma_kernel,
                            dim3((unsigned)((M + GM - 1) / GM), Np / GN, nchunks), dim3(256), 0, s,
-                           (const float *)op.B.p, Xp.p, Yp.p, M, Kp, Np, kchunk);
+                           (const float *)op.B.p, Xp, Yp, M, Kp, Np, kchunk);
         BEM_LAUNCH_CHECK();
     }
     const int64_t red = M * R;
     hipLaunchKernelGGL(gemm_reduce_kernel, dim3((unsigned)((red + 255) / 256)), dim3(256), 0, s,
-                       Yp.p, nchunks, M, Np, R, y);
+                       Yp, nchunks, M, Np, R, y);
     BEM_LAUNCH_CHECK();
+    // the workspace is free again once these kernels have finished (an own
+    // one is freed on return, which waits for them as well)
+    if (lk.owns_lock()) BEM_HIP(hipStreamSynchronize(s));
     BEM_HIP(hipStreamSynchronize(s));   // Xp, Yp are released on return
 }
 
@@ -943,7 +962,7 @@ std::atomic<uint64_t> g_share_tick{0};   // last-use stamps comparable across me
 int64_t DenseShare::bytes() {
     std::lock_guard<std::mutex> g(mu);
     int64_t b = 0;
-    for (const auto &kv : ops) b += kv.second.op->B.bytes() + kv.second.op->B64.bytes();
+    for (const auto &kv : ops) b += kv.second.op->bytes();
     return b;
 }
 
@@ -951,7 +970,7 @@ int64_t DenseShare::idle_bytes() {
     std::lock_guard<std::mutex> g(mu);
     int64_t b = 0;
     for (const auto &kv : ops)
-        if (kv.second.op.use_count() == 1) b += kv.second.op->B.bytes() + kv.second.op->B64.bytes();
+        if (kv.second.op.use_count() == 1) b += kv.second.op->bytes();
     return b;
 }
 
@@ -976,7 +995,7 @@ int64_t DenseShare::evict_idle_lru() {
         drop = std::move(victim->second.op);
         ops.erase(victim);
     }
-    return drop->B.bytes() + drop->B64.bytes();
+    return drop->bytes();
 }
 
 namespace {

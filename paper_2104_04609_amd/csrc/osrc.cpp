@@ -43,9 +43,7 @@ int64_t SplitSchedule::bytes() const {
 }
 int64_t OsrcSymbolicState::bytes() const {
     return gptr_d.bytes() + gcol_d.bytes() + perm_d.bytes() + Rj_d.bytes() + Li_d.bytes() +
-           bstart_d.bytes() + lbptr_d.bytes() + lblk_d.bytes() + lptr_d.bytes() + lrow_d.bytes() +
-           frange_d.bytes() + brange_d.bytes() + doff_d.bytes() + blk_d.bytes() + Mv_d.bytes() +
-           Sv_d.bytes() + jrow_d.bytes() + lrowd_d.bytes() + lblkd_d.bytes() + split.bytes() +
+           Mv_d.bytes() + Sv_d.bytes() + jrow_d.bytes() + lrowd_d.bytes() + lblkd_d.bytes() + split.bytes() +
            bottom[0].bytes() + bottom[1].bytes() + bottom[2].bytes() + bottom[3].bytes();
 }
 int64_t OsrcState::bytes() const {
@@ -174,21 +172,6 @@ OsrcSymbolicState &symbolic(bem_mesh *m) {
         st->lbcount[l] = lbptr[l + 1] - lbptr[l];
         st->lrcount[l] = S.lptr[l + 1] - S.lptr[l];
     }
-    st->lptr_d.upload(S.lptr);
-    st->lrow_d.upload(S.lrow);
-    std::vector<int2> fr(n), br(n);
-    for (int j = 0; j < n; j++) {
-        fr[j] = make_int2(S.Rp[j], S.fext[j]);
-        br[j] = make_int2(S.bext[j], S.Lp[j + 1]);
-    }
-    std::vector<int64_t> doff(S.doff.begin(), S.doff.end() - 1);
-    st->bstart_d.upload(S.bstart);
-    st->lbptr_d.upload(lbptr);
-    st->lblk_d.upload(lblk);
-    st->frange_d.upload(fr);
-    st->brange_d.upload(br);
-    st->doff_d.upload(doff);
-    st->blk_d.upload(S.blk);
     // row and block descriptors (one load per row / block in the solve kernels)
     if (S.ndense >= ((int64_t)1 << 31)) fail(BEM_E_UNSUPPORTED, "dense block inverses too large");
     std::vector<LdlRow> jrow(n);
@@ -380,22 +363,13 @@ LdlDev ldl_view(const OsrcSymbolicState &sy, const OsrcState &st) {
     L.Rj = sy.Rj_d.p;
     L.Li = sy.Li_d.p;
     L.nlev = (int)sy.lbcount.size();
-    L.frange = sy.frange_d.p;
-    L.brange = sy.brange_d.p;
-    L.bstart = sy.bstart_d.p;
-    L.doff = sy.doff_d.p;
-    L.lbptr = sy.lbptr_d.p;
-    L.lblk = sy.lblk_d.p;
     L.lbcount = sy.lbcount.data();
-    L.lptr = sy.lptr_d.p;
-    L.lrow = sy.lrow_d.p;
     L.lrcount = sy.lrcount.data();
     L.Dinv = st.Dinv.p;
     L.Lcsr = st.Lcsr.p;
     L.Lcsc = st.Lcsc.p;
     L.invL = st.invL.p;
     L.invLT = st.invLT.p;
-    L.blk = sy.blk_d.p;
     L.wlen = sy.wlen;
     L.jrow = sy.jrow_d.p;
     L.lrowd = sy.lrowd_d.p;

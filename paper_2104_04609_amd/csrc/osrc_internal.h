@@ -43,29 +43,20 @@ struct LdlDev {
     const int32_t *perm;      // perm[new] = old
     const int32_t *Rj;        // CSR column indices of L (forward sweep)
     const int32_t *Li;        // CSC row indices of L (backward sweep with L^T)
-    const int2 *frange;       // row j: external CSR entries [x, y)
-    const int2 *brange;       // column j: external CSC entries [x, y)
-    const int32_t *bstart;    // block b: rows [bstart[b], bstart[b+1])
-    const int64_t *doff;      // block b: dense inverse at doff[b] (w x w, row-major)
     int nlev;                 // levels of the dissection tree
-    const int32_t *lbptr;     // level l: blocks lblk[lbptr[l] .. lbptr[l+1])
-    const int32_t *lblk;
-    const int32_t *lbcount;   // host copy: blocks per level
-    const int32_t *lptr;      // level l: rows lrow[lptr[l] .. lptr[l+1])
-    const int32_t *lrow;
-    const int32_t *lrcount;   // host copy: rows per level
+    const int32_t *lbcount;   // host: blocks per level
+    const int32_t *lrcount;   // host: rows per level
     const double2 *Dinv;      // [factors][n]
     const double2 *Lcsr;      // [factors][nnz]
     const double2 *Lcsc;      // [factors][nnz]
     const double2 *invL;      // [factors][ndense]
     const double2 *invLT;     // [factors][ndense]
-    const int32_t *blk;       // row -> dissection block
     int64_t wlen;             // work length per system: n + partial sums of the split solve
     const LdlRow *jrow;       // row descriptors by row j
-    const LdlRow *lrowd;      // row descriptors in level order (lrow)
-    const int4 *lblkd;        // blocks in level order (lblk): {s0, w, doff, 0}
-    const int32_t *lptr_h;    // host copies of lptr / lbptr (launch arguments)
-    const int32_t *lbptr_h;
+    const LdlRow *lrowd;      // row descriptors in level order (rows of the blocks of height l)
+    const int4 *lblkd;        // blocks in level order: {s0, w, doff, 0}
+    const int32_t *lptr_h;    // host: level l's rows lrowd[lptr_h[l] .. lptr_h[l+1])
+    const int32_t *lbptr_h;   // host: level l's blocks lblkd[lbptr_h[l] .. lbptr_h[l+1])
     const int64_t *lext_f;    // host: external entries of each level, forward / backward
     const int64_t *lext_b;
 };
@@ -124,10 +115,7 @@ struct OsrcSymbolicState {
     std::vector<int32_t> gptr, gcol;
     std::vector<double> Mv, Sv;
     LdlSymbolic sym;
-    DevBuf<int32_t> gptr_d, gcol_d, perm_d, Rj_d, Li_d, bstart_d, lbptr_d, lblk_d, lptr_d, lrow_d;
-    DevBuf<int2> frange_d, brange_d;
-    DevBuf<int64_t> doff_d;
-    DevBuf<int32_t> blk_d;
+    DevBuf<int32_t> gptr_d, gcol_d, perm_d, Rj_d, Li_d;
     std::vector<int32_t> lbcount, lrcount;   // blocks and rows per level (host)
     std::vector<int32_t> lptr_h, lbptr_h;
     std::vector<int64_t> lext_f, lext_b;

@@ -18,7 +18,13 @@
 // M^{-1} S (M - beta S)^{-1} = [(M - beta S)^{-1} - M^{-1}] / beta,
 //   R(X_h) u = C_0' u - sum_j (A_j / B_j) (M - (B_j/k_eps^2) S)^{-1} M u,
 //   C_0' = C_0 + sum_j A_j / B_j,
-// so one application needs two batched solve stages and no stiffness products.
+// and, with (I + B X)^{-1} (I + X)^{-1} = [(I + X)^{-1} - B (I + B X)^{-1}] / (1 - B)
+// (B_j != 1 since b_j < 1), the NtD operator over the same shifts,
+//   R(X_h) (I + X_h)^{-1} = [C_0 - sum_j A_j/(1 - B_j)] (I + X_h)^{-1}
+//                           + sum_j A_j/(1 - B_j) (I + B_j X_h)^{-1},
+// (I + B X_h)^{-1} u = (M - (B/k_eps^2) S)^{-1} M u.  So one application is
+// one batch of 2 N_p + 2 solves on the two weak inputs (two stages above 16
+// Pade terms, where the task list is full) and no stiffness products.
 // All N_p + 2 systems (N_p shifts, M - S/k_eps^2, M) share the vertex-graph
 // pattern, one ordering and one symbolic factorisation; each is factorised
 // once (complex-symmetric LDL^T) and kept on the device (Sec. 2.7: a sparse

@@ -71,9 +71,124 @@ __global__ __launch_bounds__(BT) void axpby_kernel(double2 a, const double2 *x, 
                           a.x * u.y + a.y * u.x + b.x * v.y + b.y * v.x);
 }
 
+// Partial dot products: workgroup (c, i, a) sums conj(V_a[i][k]) w_a[k] over
+// chunk c (fixed order: per-thread strided sums, then an LDS tree) into
+// part[(a m + i) C + c].
+__global__ __launch_bounds__(BT) void dot_partial_kernel(CVecs V, int64_t ld, int m, CVecs w,
+                                                         int64_t n, int C,
+                                                         double2 *__restrict__ part) {
+    __shared__ double sr[BT], si[BT];
+    const int c = blockIdx.x, i = blockIdx.y, a = blockIdx.z;
+    const double2 *v = V.p[a] + (int64_t)i * ld, *x = w.p[a];
+    const int64_t k0 = (int64_t)c * BLAS_DOT_CHUNK;
+    const int64_t k1 = k0 + BLAS_DOT_CHUNK < n ? k0 + BLAS_DOT_CHUNK : n;
+    double ar = 0.0, ai = 0.0;
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += BT) {
+        const double2 p = v[k], q = x[k];
+        ar += p.x * q.x + p.y * q.y;
+        ai += p.x * q.y - p.y * q.x;
+    }
+    sr[threadIdx.x] = ar;
+    si[threadIdx.x] = ai;
+    __syncthreads();
+    for (int o = BT / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            sr[threadIdx.x] += sr[threadIdx.x + o];
+            si[threadIdx.x] += si[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[((int64_t)a * m + i) * C + c] = make_double2(sr[0], si[0]);
+}
+
+// h_a[i] = sum of the chunks in order; thread a m + i
+__global__ __launch_bounds__(BT) void dot_finish_kernel(const double2 *__restrict__ part, int m,
+                                                        int C, int A, Vecs h) {
+    const int t = blockIdx.x * BT + threadIdx.x;
+    if (t >= A * m) return;
+    const int a = t / m, i = t - a * m;
+    const double2 *p = part + (int64_t)t * C;
+    double sx = 0.0, sy = 0.0;
+    for (int c = 0; c < C; c++) {
+        sx += p[c].x;
+        sy += p[c].y;
+    }
+    h.p[a][i] = make_double2(sx, sy);
+}
+
+// w_a[k] += sign * sum_{i < m} V_a[i][k] h_a[i]   (fixed order in i), system blockIdx.y
+__global__ __launch_bounds__(BT) void axpy_batch_kernel(CVecs V, int64_t ld, CVecs h, int m,
+                                                        double sign, Vecs w, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (k >= n) return;
+    const int a = blockIdx.y;
+    const double2 *v = V.p[a], *hh = h.p[a];
+    double ar = 0.0, ai = 0.0;
+    for (int i = 0; i < m; i++) {
+        const double2 p = v[(int64_t)i * ld + k], q = hh[i];
+        ar += p.x * q.x - p.y * q.y;
+        ai += p.x * q.y + p.y * q.x;
+    }
+    double2 o = w.p[a][k];
+    w.p[a][k] = make_double2(o.x + sign * ar, o.y + sign * ai);
+}
+
+__global__ __launch_bounds__(BT) void normalize_batch_kernel(Vecs v, CVecs nrm2, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (k >= n) return;
+    const int a = blockIdx.y;
+    const double q = nrm2.p[a]->x;
+    const double sc = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
+    v.p[a][k] = make_double2(v.p[a][k].x * sc, v.p[a][k].y * sc);
+}
+
+__global__ __launch_bounds__(BT) void copy_batch_kernel(Vecs dst, CVecs src, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (k >= n) return;
+    dst.p[blockIdx.y][k] = src.p[blockIdx.y][k];
+}
+
 unsigned blocks(int64_t n) { return (unsigned)((n + BT - 1) / BT); }
 
+void check_batch(int A) {
+    if (A < 1 || A > BLAS_MAX_BATCH) fail(BEM_E_INVAL, "vector batch out of range");
+}
+
 }   // namespace
+
+void blas_block_dot_batch(const CVecs &V, int64_t ld, int m, const CVecs &w, int64_t n,
+                          const Vecs &h, int A, double2 *part, hipStream_t s) {
+    check_batch(A);
+    const int C = (int)blas_dot_chunks(n);
+    hipLaunchKernelGGL(dot_partial_kernel, dim3((unsigned)C, (unsigned)m, (unsigned)A), dim3(BT),
+                       0, s, V, ld, m, w, n, C, part);
+    BEM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(dot_finish_kernel, dim3(blocks((int64_t)A * m)), dim3(BT), 0, s, part, m,
+                       C, A, h);
+    BEM_LAUNCH_CHECK();
+}
+
+void blas_block_axpy_batch(const CVecs &V, int64_t ld, const CVecs &h, int m, double sign,
+                           const Vecs &w, int64_t n, int A, hipStream_t s) {
+    check_batch(A);
+    hipLaunchKernelGGL(axpy_batch_kernel, dim3(blocks(n), (unsigned)A), dim3(BT), 0, s, V, ld, h,
+                       m, sign, w, n);
+    BEM_LAUNCH_CHECK();
+}
+
+void blas_normalize_batch(const Vecs &v, const CVecs &nrm2, int64_t n, int A, hipStream_t s) {
+    check_batch(A);
+    hipLaunchKernelGGL(normalize_batch_kernel, dim3(blocks(n), (unsigned)A), dim3(BT), 0, s, v,
+                       nrm2, n);
+    BEM_LAUNCH_CHECK();
+}
+
+void blas_copy_batch(const Vecs &dst, const CVecs &src, int64_t n, int A, hipStream_t s) {
+    check_batch(A);
+    hipLaunchKernelGGL(copy_batch_kernel, dim3(blocks(n), (unsigned)A), dim3(BT), 0, s, dst, src,
+                       n);
+    BEM_LAUNCH_CHECK();
+}
 
 void blas_block_dot(const double2 *V, int64_t ld, int m, const double2 *w, int64_t n,
                     double2 *h, hipStream_t s) {

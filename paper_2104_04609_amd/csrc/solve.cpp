@@ -192,7 +192,17 @@ struct Workspace {
 
 // Squared norms of R vectors (stride n) into host nrm[R] (one sync).
 void dev_norms(const double2 *v, int64_t n, int R, double2 *dbuf, double *nrm, hipStream_t s) {
-    for (int r = 0; r < R; r++) blas_block_dot(v + r * n, n, 1, v + r * n, n, dbuf + r, s);
+    DevBuf<double2> part((size_t)std::min(R, BLAS_MAX_BATCH) * blas_dot_chunks(n));
+    for (int r0 = 0; r0 < R; r0 += BLAS_MAX_BATCH) {
+        const int A = std::min(BLAS_MAX_BATCH, R - r0);
+        CVecs x{};
+        Vecs h{};
+        for (int a = 0; a < A; a++) {
+            x.p[a] = v + (r0 + a) * n;
+            h.p[a] = dbuf + r0 + a;
+        }
+        blas_block_dot_batch(x, n, 1, x, n, h, A, part.p, s);
+    }
     std::vector<double2> h(R);
     BEM_HIP(hipMemcpyAsync(h.data(), dbuf, R * sizeof(double2), hipMemcpyDeviceToHost, s));
     BEM_HIP(hipStreamSynchronize(s));
@@ -208,6 +218,7 @@ void copy_vec(double2 *dst, const double2 *src, int64_t n, hipStream_t s) {
 
 // Waves solved together in one lockstep group.
 constexpr int SOLVE_BATCH = 16;
+static_assert(SOLVE_BATCH <= BLAS_MAX_BATCH, "lockstep groups are orthogonalised per launch");
 
 // Bound on |(P64 - P32) v| / |P32 v| for the FP32 preconditioned operator
 // used when a refinement residual is updated with the FP32 product.
@@ -248,36 +259,52 @@ void gmres_batch(Op &op, int prec, const double2 *b, double2 *x, int R, int64_t 
             blas_axpby(make_double2(1.0 / bn[r], 0.0), b + r * n2, make_double2(0, 0), nullptr,
                        ws[r].V.p, n2, s);
     }
-    DevBuf<double2> vin, vout;
+    DevBuf<double2> vin, vout, part;
     std::vector<double2> hh;
+    const int64_t nch = blas_dot_chunks(n2);
     for (int j = 0;; j++) {
         std::vector<int> act;
         for (int r = 0; r < R; r++)
             if (sy[r].run) act.push_back(r);
         if (act.empty()) break;
-        const int A = (int)act.size();
+        const int A = (int)act.size();   // <= SOLVE_BATCH = BLAS_MAX_BATCH
         if (vin.n < (size_t)(A * n2)) {
             vin.alloc((size_t)(A * n2));
             vout.alloc((size_t)(A * n2));
         }
-        for (int a = 0; a < A; a++) {
-            ws[act[a]].ensure(j + 2, s);
-            copy_vec(vin.p + a * n2, ws[act[a]].V.p + (size_t)j * n2, n2, s);
-        }
-        op.apply(vin.p, vout.p, A, prec);
+        if (part.n < (size_t)(A * (j + 1) * nch))   // grows with the basis, doubling
+            part.alloc((size_t)(A * nch) * std::max(2 * (j + 1), 64));
+        for (int a = 0; a < A; a++) ws[act[a]].ensure(j + 2, s);
+        // every active system's newest vector through the operator, then CGS2
+        // of each against its own basis, all systems per launch
+        CVecs V{}, Vn_c{}, h1_c{}, h2_c{}, nr_c{}, vo{};
+        Vecs Vn{}, h1{}, h2{}, nr{}, vi{};
         for (int a = 0; a < A; a++) {
             Workspace &w = ws[act[a]];
-            double2 *Vn = w.V.p + (size_t)(j + 1) * n2;
-            copy_vec(Vn, vout.p + a * n2, n2, s);
-            double2 *h1 = w.h.p, *h2 = w.h.p + (j + 1), *nr = w.h.p + 2 * (j + 1);
-            blas_block_dot(w.V.p, n2, j + 1, Vn, n2, h1, s);
-            blas_block_axpy(w.V.p, n2, h1, j + 1, -1.0, Vn, n2, s);
-            blas_block_dot(w.V.p, n2, j + 1, Vn, n2, h2, s);
-            blas_block_axpy(w.V.p, n2, h2, j + 1, -1.0, Vn, n2, s);
-            blas_block_dot(Vn, n2, 1, Vn, n2, nr, s);
-            blas_normalize(Vn, nr, n2, s);
-            napply[act[a]]++;
+            V.p[a] = w.V.p;
+            Vn.p[a] = w.V.p + (size_t)(j + 1) * n2;
+            Vn_c.p[a] = Vn.p[a];
+            vi.p[a] = vin.p + a * n2;
+            vo.p[a] = vout.p + a * n2;
+            h1.p[a] = w.h.p;
+            h2.p[a] = w.h.p + (j + 1);
+            nr.p[a] = w.h.p + 2 * (j + 1);
+            h1_c.p[a] = h1.p[a];
+            h2_c.p[a] = h2.p[a];
+            nr_c.p[a] = nr.p[a];
         }
+        CVecs vj{};
+        for (int a = 0; a < A; a++) vj.p[a] = V.p[a] + (size_t)j * n2;
+        blas_copy_batch(vi, vj, n2, A, s);
+        op.apply(vin.p, vout.p, A, prec);
+        blas_copy_batch(Vn, vo, n2, A, s);
+        blas_block_dot_batch(V, n2, j + 1, Vn_c, n2, h1, A, part.p, s);
+        blas_block_axpy_batch(V, n2, h1_c, j + 1, -1.0, Vn, n2, A, s);
+        blas_block_dot_batch(V, n2, j + 1, Vn_c, n2, h2, A, part.p, s);
+        blas_block_axpy_batch(V, n2, h2_c, j + 1, -1.0, Vn, n2, A, s);
+        blas_block_dot_batch(Vn_c, n2, 1, Vn_c, n2, nr, A, part.p, s);
+        blas_normalize_batch(Vn, nr_c, n2, A, s);
+        for (int a = 0; a < A; a++) napply[act[a]]++;
         const size_t per = 2 * (size_t)(j + 1) + 1;
         hh.resize(per * A);
         for (int a = 0; a < A; a++)
@@ -443,6 +470,8 @@ int64_t solve_footprint(bem_mesh *m, double2 k0, double2 k1, double rho,
     else if (o.formulation != BEM_FORM_OSRC) b += (int64_t)G * n2 * c16;       // t1
     // the initial Krylov basis; its growth is reported through reserve_bytes
     b += G * ((int64_t)(KRYLOV_CAP0 + 1) * n2 * c16 + (2 * (int64_t)o.maxiter + 8) * c16);
+    // partial dot products of the orthogonalisation
+    b += G * blas_dot_chunks(n2) * (2 * (int64_t)o.maxiter + 64) * c16;
     return b;
 }
 

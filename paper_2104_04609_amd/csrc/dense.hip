@@ -242,24 +242,26 @@ __global__ __launch_bounds__(256) void dense_gemv64_kernel(const double2 *__rest
 }
 
 // y_r = B x_r for NR vectors (2..8); x: [NR][n2] complex64, y_r = y + r ystride.
-// Two rows per wavefront (eight per
-// workgroup); each chunk of the NR vectors (512 entries each) is staged in
-// LDS once per workgroup and read by all eight rows, so x costs the L2 one
-// pass per eight rows instead of one per row.  16-byte loads of B (2N even:
-// rows and vectors 16-byte aligned), non-temporal; FP32 partial sums per
-// chunk added in FP64, fixed-order wave reduction.
-constexpr int GV_RW = 2;     // rows per wavefront
-constexpr int GV_CH = 256;   // float4 (two complex entries) per chunk and vector
+// Two rows per wavefront, GV_WAVES wavefronts per workgroup; each chunk of the
+// NR vectors (512 entries each) is staged in LDS once per workgroup and read by
+// all its rows (each LDS value once per wavefront, for both of its rows), so x
+// costs the L2 one pass per 2 GV_WAVES rows.  16-byte loads of B (2N even:
+// rows and vectors 16-byte aligned), non-temporal; FP32 partial sums per chunk
+// added in FP64, fixed-order wave reduction.
+constexpr int GV_RW = 2;      // rows per wavefront
+constexpr int GV_CH = 256;    // float4 (two complex entries) per chunk and vector
+constexpr int GV_WAVES = 8;   // wavefronts per workgroup
 
 template <int NR>
-__global__ __launch_bounds__(256) void dense_gemv_kernel(const float2 *__restrict__ B,
-                                                         int64_t n2,
-                                                         const float2 *__restrict__ x,
-                                                         double2 *__restrict__ y,
-                                                         int64_t ystride) {
+__global__ __launch_bounds__(64 * GV_WAVES) void dense_gemv_kernel(const float2 *__restrict__ B,
+                                                                   int64_t n2,
+                                                                   const float2 *__restrict__ x,
+                                                                   double2 *__restrict__ y,
+                                                                   int64_t ystride) {
+    constexpr int NT = 64 * GV_WAVES, NU = GV_CH / 64;
     __shared__ fvec4 xs[NR * GV_CH];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * GV_RW;
+    const int64_t row0 = ((int64_t)blockIdx.x * GV_WAVES + wave) * GV_RW;
     const int nrow = row0 >= n2 ? 0 : (n2 - row0 < GV_RW ? (int)(n2 - row0) : GV_RW);
     const fvec4 *b4[GV_RW];
     for (int q = 0; q < GV_RW; q++)
@@ -272,34 +274,41 @@ __global__ __launch_bounds__(256) void dense_gemv_kernel(const float2 *__restric
     for (int64_t c0 = 0; c0 < n4; c0 += GV_CH) {
         const int cnt = n4 - c0 < GV_CH ? (int)(n4 - c0) : GV_CH;
         __syncthreads();   // the previous chunk's readers are done
-        for (int idx = threadIdx.x; idx < NR * GV_CH; idx += 256) {
+        for (int idx = threadIdx.x; idx < NR * GV_CH; idx += NT) {
             const int r = idx / GV_CH, c = idx - r * GV_CH;
             xs[idx] = c < cnt ? x4[r * n4 + c0 + c] : fvec4{0.f, 0.f, 0.f, 0.f};
         }
         __syncthreads();
         if (nrow == 0) continue;   // (the barriers above stay uniform)
+        fvec4 a[GV_RW][NU];
 #pragma unroll
-        for (int q = 0; q < GV_RW; q++) {
-            fvec4 a[GV_CH / 64];
+        for (int q = 0; q < GV_RW; q++)
 #pragma unroll
-            for (int u = 0; u < GV_CH / 64; u++) {
+            for (int u = 0; u < NU; u++) {
                 const int c = u * 64 + lane;
-                a[u] = c < cnt ? __builtin_nontemporal_load(b4[q] + c0 + c)
-                               : fvec4{0.f, 0.f, 0.f, 0.f};
+                a[q][u] = c < cnt ? __builtin_nontemporal_load(b4[q] + c0 + c)
+                                  : fvec4{0.f, 0.f, 0.f, 0.f};
             }
 #pragma unroll
-            for (int r = 0; r < NR; r++) {
-                float pr = 0.f, pi = 0.f;
+        for (int r = 0; r < NR; r++) {
+            float pr[GV_RW], pi[GV_RW];
 #pragma unroll
-                for (int u = 0; u < GV_CH / 64; u++) {
-                    const fvec4 v = xs[r * GV_CH + u * 64 + lane];
-                    pr += a[u].x * v.x - a[u].y * v.y;
-                    pi += a[u].x * v.y + a[u].y * v.x;
-                    pr += a[u].z * v.z - a[u].w * v.w;
-                    pi += a[u].z * v.w + a[u].w * v.z;
+            for (int q = 0; q < GV_RW; q++) pr[q] = pi[q] = 0.f;
+#pragma unroll
+            for (int u = 0; u < NU; u++) {
+                const fvec4 v = xs[r * GV_CH + u * 64 + lane];
+#pragma unroll
+                for (int q = 0; q < GV_RW; q++) {
+                    pr[q] += a[q][u].x * v.x - a[q][u].y * v.y;
+                    pi[q] += a[q][u].x * v.y + a[q][u].y * v.x;
+                    pr[q] += a[q][u].z * v.z - a[q][u].w * v.w;
+                    pi[q] += a[q][u].z * v.w + a[q][u].w * v.z;
                 }
-                sr[q][r] += pr;
-                si[q][r] += pi;
+            }
+#pragma unroll
+            for (int q = 0; q < GV_RW; q++) {
+                sr[q][r] += pr[q];
+                si[q][r] += pi[q];
             }
         }
     }
@@ -795,8 +804,9 @@ std::unique_ptr<DenseOperator> dense_assemble(bem_mesh *m, const NearOperator &n
 
 template <int NR>
 void launch_gemv(const DenseOperator &op, const float2 *xs, double2 *y, hipStream_t s) {
-    hipLaunchKernelGGL(dense_gemv_kernel<NR>, dim3((unsigned)((op.n2 + 4 * GV_RW - 1) / (4 * GV_RW))),
-                       dim3(256), 0, s, op.B.p, op.n2, xs, y, op.n2);
+    const int64_t rows = (int64_t)GV_WAVES * GV_RW;   // per workgroup
+    hipLaunchKernelGGL(dense_gemv_kernel<NR>, dim3((unsigned)((op.n2 + rows - 1) / rows)),
+                       dim3(64 * GV_WAVES), 0, s, op.B.p, op.n2, xs, y, op.n2);
 }
 
 constexpr int GEMV_MAX_RHS = 8;   // right-hand sides per multi-vector GEMV launch

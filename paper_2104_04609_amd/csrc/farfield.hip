@@ -545,8 +545,15 @@ __host__ __device__ inline int64_t sym_sig_off(int64_t b, int64_t T, int64_t blk
     return b * T - blk * (b * (b - 1) / 2);
 }
 
+// Waves per SIMD (measured): 2 for real wavenumbers and one material (256
+// VGPRs, nothing spilled: 2.6 % faster than 3), 3 for the lossy and
+// several-material variants (their extra exp and table lookups: 5 % faster
+// than 2).
+template <bool CK0, bool CK1, bool MULTI>
+constexpr int sym_waves() { return CK0 || CK1 || MULTI ? 3 : 2; }
+
 template <class R, bool CK0, bool CK1, bool MULTI, bool FR>
-__global__ __launch_bounds__(FF_BLOCK) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ __launch_bounds__(FF_BLOCK) __attribute__((amdgpu_waves_per_eu(sym_waves<CK0, CK1, MULTI>())))
 void farfield_sym_kernel(
     const R *__restrict__ geo, const R *__restrict__ dyn,
     const int32_t *__restrict__ tobj, const int32_t *__restrict__ tri, int T,

@@ -180,7 +180,8 @@ __global__ __launch_bounds__(256) void region_kernel(const double *__restrict__ 
 
 // partial single- and double-layer sums of the split's triangles at each
 // point, with the wavenumber and the triangles of the point's region
-__global__ __launch_bounds__(256) void field_kernel(
+// Three waves per SIMD (measured against two: 5 % faster; four: 2.6x slower).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void field_kernel(
     const double *__restrict__ src, const double *__restrict__ geo,
     const int32_t *__restrict__ tobj, int T, int split_len, const double *__restrict__ pts,
     const int32_t *__restrict__ region, int64_t n, double2 k0, const double *__restrict__ omat,

@@ -298,6 +298,24 @@ def test_solve_multiple_waves(P):
         assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-8, w
 
 
+def test_solve_lockstep_groups_fp64(P):
+    """18 waves: a full lockstep group of 16 (every wave orthogonalised in one
+    launch per step) and a group of 2, against waves solved alone."""
+    from bem_inputs import wave_directions
+    mesh = icosphere(2)
+    M = P.Mesh.from_inputs(mesh)
+    d = wave_directions(18, seed=4)
+    sol, info, rc = P.pmchwt_solve(M, 2.5, 3.5, 1.4, d, 1e-10, precision="fp64", path=1)
+    assert rc == 0
+    X = sol.cpu().numpy()
+    for w in (0, 7, 15, 16, 17):
+        one, i1, rc1 = P.pmchwt_solve(M, 2.5, 3.5, 1.4, d[w:w + 1], 1e-10, precision="fp64", path=1)
+        assert rc1 == 0 and info[w]["rel_residual"] <= 1e-10 and i1[0]["rel_residual"] <= 1e-10
+        b = one.cpu().numpy()[0]
+        assert np.linalg.norm(X[w] - b) / np.linalg.norm(b) < 1e-8, w
+        assert abs(info[w]["iterations"] - i1[0]["iterations"]) <= 1, w
+
+
 def test_solve_lockstep_waves_fp32_dense(P):
     """Waves solved in one lockstep group (multi-vector dense product, batched
     OSRC) against each wave solved alone; both to 1e-9."""
